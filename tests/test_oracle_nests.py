@@ -1,0 +1,293 @@
+"""Pins of the oracle's serial nests against facts that do not come from the
+oracle itself: published generator outputs, closed forms, exact special
+cases, symmetries and independent library routines."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from conftest import read_golden
+from oracle import cnests as C
+from oracle.ga import SplitMix64
+
+MASK = 0xFFFFFFFFFFFFFFFF
+
+
+# ------------------------------------------------------------ generators
+def test_splitmix64_published_outputs():
+    want = [int(x, 16) for x in read_golden("splitmix64_seed0.txt")]
+    got_counter = [C.sm64_nth(0, k) for k in range(1, len(want) + 1)]
+    g = SplitMix64(0)
+    got_seq = [g.next() for _ in want]
+    assert got_counter == want
+    assert got_seq == want
+
+
+def test_lcg_published_outputs():
+    want = [int(x) for x in read_golden("lcg_numerical_recipes.txt")]
+    assert [int(v) for v in C.lcg_states(len(want), 0)] == want
+
+
+def test_init_uniform_is_splitmix_stream():
+    seed, stream, n = 1234567, 3, 257
+    x = C.init_uniform(n, seed, stream)
+    key = SplitMix64(seed)
+    for _ in range(stream + 1):
+        k = key.next()
+    g = SplitMix64(k)
+    for idx in range(n):
+        z = g.next()
+        assert x[idx] == np.float32((z >> 40) / 16777216.0)
+
+
+def test_init_uniform_distribution():
+    n = 1 << 18
+    x = C.init_uniform(n, 1, 0).astype(np.float64)
+    assert x.min() >= 0.0 and x.max() < 1.0
+    assert np.all(x * 16777216.0 == np.floor(x * 16777216.0))
+    sigma = math.sqrt(1.0 / 12.0 / n)
+    assert abs(x.mean() - 0.5) < 4 * sigma
+    y = C.init_uniform(n, 1, 1).astype(np.float64)
+    assert abs(np.corrcoef(x, y)[0, 1]) < 4.0 / math.sqrt(n)
+
+
+# ------------------------------------------------------------ GEMM
+@pytest.mark.parametrize("N", [1, 7, 64, 130])
+def test_gemm_identity_exact(N):
+    B = C.init_uniform(N * N, 5, 1).reshape(N, N)
+    A = np.eye(N, dtype=np.float32)
+    assert np.array_equal(C.gemm_f32(A, B), B)
+    assert np.array_equal(C.gemm_f32(B, A), B)
+
+
+def test_gemm_rank1_exact():
+    N = 96
+    u = (np.arange(N) % 7 + 1).astype(np.float32)
+    v = (np.arange(N) % 5 + 1).astype(np.float32)
+    A = np.repeat(u[:, None], N, axis=1)          # A[i][k] = u_i
+    B = np.repeat(v[None, :], N, axis=0)          # B[k][j] = v_j
+    want = (N * np.outer(u, v)).astype(np.float32)
+    assert np.array_equal(C.gemm_f32(A, B), want)
+    assert np.array_equal(C.gemm_f64(A, B), want.astype(np.float64))
+
+
+@pytest.mark.parametrize("M,N,K", [(64, 64, 64), (37, 53, 129), (1, 200, 3)])
+def test_gemm_random_vs_library(M, N, K):
+    A = C.init_uniform(M * K, 9, 0).reshape(M, K)
+    B = C.init_uniform(K * N, 9, 1).reshape(K, N)
+    ref = np.matmul(A.astype(np.float64), B.astype(np.float64))
+    c64 = C.gemm_f64(A, B)
+    assert np.max(np.abs(c64 - ref) / np.abs(ref)) < 1e-13
+    c32 = C.gemm_f32(A, B)
+    assert np.max(np.abs(c32 - ref) / np.abs(ref)) < 1e-5
+
+
+def test_gemm_serial_order():
+    # FP32 accumulation in increasing k: (1e8 + 1) - 1e8 rounds, order matters.
+    A = np.array([[1e8, 1.0, -1e8]], np.float32)
+    B = np.array([[1.0], [1.0], [1.0]], np.float32)
+    assert C.gemm_f32(A, B)[0, 0] == np.float32(0.0)
+
+
+def test_gemm_bf16_vs_library():
+    M = N = K = 48
+    A = C.cast_bf16(C.init_uniform(M * K, 2, 0).reshape(M, K))
+    B = C.cast_bf16(C.init_uniform(K * N, 2, 1).reshape(K, N))
+    fa = (A.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    fb = (B.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    ref = fa @ fb
+    assert np.max(np.abs(C.gemm_bf16_f64(A, B) - ref) / ref) < 1e-13
+    assert np.max(np.abs(C.gemm_bf16(A, B) - ref) / ref) < 1e-5
+
+
+# ------------------------------------------------------------ element-wise
+def test_elementwise_against_ieee_numpy():
+    n = 1000
+    A = C.init_uniform(n, 3, 0)
+    X = C.init_uniform(n, 3, 1)
+    Cm = X.copy()
+    C.add_scaled(Cm, A, 0.5)
+    assert np.array_equal(Cm, X + np.float32(0.5) * A)
+    S = np.empty(n, np.float32)
+    C.avg2(S, X, A)
+    assert np.array_equal(S, np.float32(0.5) * (X + A))
+    D = X.copy()
+    C.scale(D, 2.0)
+    assert np.array_equal(D, X * np.float32(2.0))
+    E = np.empty(n, np.float32)
+    C.copy(E, X)
+    assert np.array_equal(E, X)
+
+
+def test_cast_bf16_against_torch():
+    x = np.concatenate([C.init_uniform(4096, 4, 0) * 1000 - 500,
+                        np.array([1.0, 1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -0.0, 65504.0,
+                                  3.0e38, 1e-40], np.float32)]).astype(np.float32)
+    got = C.cast_bf16(x)
+    want = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    assert np.array_equal(got, want)
+
+
+def test_transpose_involution_and_library():
+    X = C.init_uniform(37 * 53, 8, 0).reshape(37, 53)
+    T = C.transpose(X)
+    assert np.array_equal(T, X.T)
+    assert np.array_equal(C.transpose(T), X)
+
+
+def test_sumsq_closed_forms():
+    s = np.zeros(1)
+    C.sumsq(np.ones(1001, np.float32), s)
+    assert s[0] == 1001.0
+    n = 3000
+    s = np.array([5.0])
+    C.sumsq(np.arange(1, n + 1, dtype=np.float32), s)
+    assert s[0] == 5.0 + n * (n + 1) * (2 * n + 1) / 6
+
+
+def test_recurrences_closed_forms():
+    N = 50
+    S = np.ones((N, 3), np.float32)
+    v = np.zeros(N, np.float32)
+    v[0] = 7.0
+    C.rec_prefix(v, S)
+    assert np.array_equal(v, 7.0 + np.arange(N, dtype=np.float32))
+    K = 20
+    p = np.zeros((3, 3, K), np.float32)
+    p[1, 1, :] = 1.0
+    w = np.zeros(K, np.float32)
+    C.rec_decay(w, p)
+    # w_k = 0.5 w_{k-1} + 1, w_0 = 0  ->  w_k = 2 (1 - 2^-k), exact dyadics
+    assert np.array_equal(w, (2.0 * (1.0 - 2.0 ** -np.arange(K))).astype(np.float32))
+
+
+def test_lcg_fill_scaling():
+    L = np.empty(5, np.float32)
+    C.lcg_fill(L, 0)
+    states = C.lcg_states(5, 0)
+    assert np.array_equal(L, ((states >> 8).astype(np.float64) / 2 ** 24).astype(np.float32))
+
+
+# ------------------------------------------------------------ stencil
+def _sweep(p, twin=False):
+    q = np.zeros_like(p)
+    res = np.zeros(1)
+    if twin:
+        C.stencil19_f64(p, q, res)
+    else:
+        C.stencil19(p, q, res)
+    return q, res[0]
+
+
+@pytest.mark.parametrize("shape", [(5, 6, 7), (19, 23, 71)])
+def test_stencil_fixed_points_exact(shape):
+    I, J, K = shape
+    ii, jj, kk = np.meshgrid(np.arange(I), np.arange(J), np.arange(K), indexing="ij")
+    for field in (np.ones(shape, np.float32) * 3.0,
+                  (ii + 2 * jj + 3 * kk).astype(np.float32),
+                  (1000 + 5 * ii - 7 * jj + 11 * kk).astype(np.float32)):
+        q, r = _sweep(np.ascontiguousarray(field))
+        inner = (slice(1, -1),) * 3
+        assert np.array_equal(q[inner], field[inner])
+        assert r == 0.0
+        # the boundary is never written
+        qb = q.copy()
+        qb[inner] = 0
+        assert not qb.any()
+
+
+def test_stencil_reflection_symmetry_exact():
+    I, J, K = 9, 11, 13
+    p = C.init_uniform(I * J * K, 21, 0).reshape(I, J, K)
+    q, _ = _sweep(p)
+    for ax in range(3):
+        pf = np.ascontiguousarray(np.flip(p, axis=ax))
+        qf, _ = _sweep(pf)
+        assert np.array_equal(qf, np.flip(q, axis=ax))
+
+
+def test_stencil_point_weights():
+    # a unit impulse shows every weight once: centre 1/4, faces 1/16, edges 1/32,
+    # corners 0 -- and nothing outside the 19-point neighbourhood
+    p = np.zeros((7, 7, 7), np.float32)
+    p[3, 3, 3] = 1.0
+    q, _ = _sweep(p)
+    for di in (-1, 0, 1):
+        for dj in (-1, 0, 1):
+            for dk in (-1, 0, 1):
+                nz = abs(di) + abs(dj) + abs(dk)
+                want = {0: 0.25, 1: 1 / 16, 2: 1 / 32, 3: 0.0}[nz]
+                assert q[3 + di, 3 + dj, 3 + dk] == want
+    total = q.sum(dtype=np.float64)
+    assert total == 1.0
+
+
+def _eigen_rows():
+    rows = []
+    for line in read_golden("stencil_eigen.txt"):
+        f = line.split()
+        rows.append((int(f[0]), int(f[1]), int(f[2]), int(f[3]), float(f[4]), float(f[5]), float(f[6])))
+    return rows
+
+
+@pytest.mark.parametrize("row", [r for r in _eigen_rows() if r[0] * r[1] * r[2] < 100000])
+def test_stencil_eigenmode_f64_closed_form(row):
+    I, J, K, m, mu, r1, r10 = row
+    _, p0 = C.sin_field(I, J, K, m, want64=True)
+    p = p0.copy()
+    res = []
+    for n in range(10):
+        q = p.copy()
+        cell = np.zeros(1)
+        C.stencil19_f64(p, q, cell)
+        res.append(cell[0])
+        C.copy_interior(p, q)
+    assert abs(res[0] - r1) <= 1e-10 * r1
+    assert abs(res[9] - r10) <= 1e-10 * r10
+    inner = (slice(1, -1),) * 3
+    assert np.max(np.abs(p[inner] - mu ** 10 * p0[inner])) <= 1e-12
+
+
+@pytest.mark.parametrize("row", [r for r in _eigen_rows() if r[0] * r[1] * r[2] < 100000])
+def test_stencil_eigenmode_f32(row):
+    I, J, K, m, mu, r1, r10 = row
+    p0 = C.sin_field(I, J, K, m)
+    p = p0.copy()
+    q = np.zeros_like(p)
+    res = []
+    for n in range(10):
+        cell = np.zeros(1)
+        C.stencil19(p, q, cell)
+        res.append(cell[0])
+        C.copy_interior(p, q)
+    inner = (slice(1, -1),) * 3
+    want = mu ** 10 * p0[inner].astype(np.float64)
+    # FP32 rounding per sweep: a few ulp of the field's max, times sweeps
+    err = np.max(np.abs(p[inner] - want)) / np.max(np.abs(want))
+    assert err < 10 * 10 * 2.0 ** -24
+    # the FP32 residual differs by about 2^-24/|mu-1| relative (reported bound)
+    bound = 8 * 2.0 ** -24 / abs(mu - 1) + 1e-6
+    assert abs(res[0] - r1) / r1 < bound
+    assert abs(res[9] - r10) / r10 < bound
+
+
+def test_stencil_f32_vs_f64_twin_random():
+    I, J, K = 12, 17, 45
+    p = C.init_uniform(I * J * K, 33, 0).reshape(I, J, K)
+    q32, r32 = _sweep(p)
+    q64, r64 = _sweep(p.astype(np.float64), twin=True)
+    inner = (slice(1, -1),) * 3
+    assert np.max(np.abs(q32[inner] - q64[inner])) <= 4 * 2.0 ** -24
+    assert abs(r32 - r64) / r64 < 1e-5
+
+
+def test_copy_interior():
+    p = C.init_uniform(6 * 7 * 8, 1, 0).reshape(6, 7, 8)
+    q = C.init_uniform(6 * 7 * 8, 1, 1).reshape(6, 7, 8)
+    p0 = p.copy()
+    C.copy_interior(p, q)
+    inner = (slice(1, -1),) * 3
+    assert np.array_equal(p[inner], q[inner])
+    p[inner] = p0[inner]
+    assert np.array_equal(p, p0)
