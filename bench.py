@@ -1,0 +1,203 @@
+"""Benchmark of the offload path on one MI355X.
+
+A step is one run of the medium application (12 loop nests, 2 of them
+loop-carried recurrences that stay on the CPU; GEMM 1024 x 1024, 19-point
+sweep on 129 x 129 x 257 for 100 sweeps with the FP64 residual) under the
+pattern that puts every parallelisable nest on the GPU, through
+ofl_run_pattern: verdicts, plan, kernels, the two host nests and the copies
+they require.  Inputs are resident in HBM when the timed region starts (set-up
+content restored device-side, untimed) and outputs stay there.
+
+Prints one JSON line; `value` is application runs per second.  The dominant
+kernel's roofline comes from HIP events recorded on the run's stream around
+every launch during the timed steps.  `cpu_baseline` times the oracle's serial
+run of the same application on one host core.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "app time & speedup vs 1-core oracle; stencil GB/s, GEMM MFMA % of peak"
+HBM_PEAK_GBS = 8000.0
+FP32_MFMA_PEAK_TFLOPS = 157.3
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def stencil_bytes(I, J, K):
+    # read every element of p once, write every interior element of q once
+    return 4 * I * J * K + 4 * (I - 2) * (J - 2) * (K - 2)
+
+
+def kernel_table(app, ops):
+    out = {}
+    for op in ops:
+        n, ms = app.kernel_stats(op)
+        if n:
+            out[op] = {"launches": n, "total_ms": ms, "avg_us": 1e3 * ms / n}
+    return out
+
+
+def run_medium(args):
+    import torch
+
+    import paper_1806_01430_amd as ofl
+    import workloads
+
+    doc = workloads.app_doc("medium")
+    P = doc["params"]
+    app = ofl.App(json.dumps(doc), seed=1)
+    gene = [1] * app.gene_len
+    bufs = app.alloc_device_buffers("cuda:0")
+    flags = ofl.PRESTAGED | ofl.KEEP_OUTPUTS
+    for _ in range(args.warmup):
+        app.run_pattern(gene, bufs, flags=flags)
+    torch.cuda.synchronize()
+    app.set_kernel_timing(True)
+    internal = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = app.run_pattern(gene, bufs, flags=flags)
+        internal.append(st["t_total_s"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    app.set_kernel_timing(False)
+    ktab = kernel_table(app, ["stencil19", "copy_interior", "gemm", "init_uniform", "add_scaled", "transpose",
+                              "avg2", "sumsq", "copy", "scale"])
+    # paper protocol for context: set-up content copied in, outputs copied out
+    pcie = []
+    for _ in range(3):
+        pcie.append(app.run_pattern(gene, bufs, flags=0)["t_total_s"])
+    internal.sort()
+    pcie.sort()
+    return {"app": app, "params": P, "wall": wall, "internal_median_s": internal[len(internal) // 2],
+            "pcie_median_s": pcie[1], "kernels": ktab, "last": st}
+
+
+def run_kernels_large(args):
+    """Stencil on the largest grid and the FP32 GEMM at 8192 (the sizes where
+    the HBM and MFMA rooflines are meaningful)."""
+    import paper_1806_01430_amd as ofl
+    from workloads import appgen
+
+    out = {}
+    I, J, K = 513, 513, 1025
+    app = ofl.App(json.dumps(appgen.stencil_app(I, J, K, 10)), seed=1)
+    bufs = app.alloc_device_buffers("cuda:0")
+    app.run_pattern([1, 1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
+    app.set_kernel_timing(True)
+    for _ in range(2):
+        app.run_pattern([1, 1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
+    n, ms = app.kernel_stats("stencil19")
+    avg = ms / n * 1e-3
+    gbs = stencil_bytes(I, J, K) / avg / 1e9
+    nc, msc = app.kernel_stats("copy_interior")
+    out["stencil19_513x513x1025"] = {"avg_us": avg * 1e6, "GBps": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
+                                     "copy_interior_GBps": 8 * (I - 2) * (J - 2) * (K - 2) / (msc / nc * 1e-3) / 1e9}
+    del bufs, app
+    N = 8192
+    doc = {"name": "gemm8192", "params": {"N": N},
+           "buffers": [{"name": b, "dims": ["N", "N"], "output": b == "C"} for b in ("A", "B", "C")],
+           "program": [appgen.init_nest(["A", "B"], [0, 1]), appgen.gemm_nest("A", "B", "C")]}
+    app = ofl.App(json.dumps(doc), seed=1)
+    bufs = app.alloc_device_buffers("cuda:0")
+    app.run_pattern([1, 1], bufs, flags=ofl.KEEP_OUTPUTS)
+    app.set_kernel_timing(True)
+    for _ in range(3):
+        app.run_pattern([1, 1], bufs, flags=ofl.KEEP_OUTPUTS)
+    n, ms = app.kernel_stats("gemm")
+    avg = ms / n * 1e-3
+    tf = 2.0 * N ** 3 / avg / 1e12
+    out["gemm_f32_8192"] = {"avg_ms": avg * 1e3, "TFLOPs": tf, "frac_mfma": tf / FP32_MFMA_PEAK_TFLOPS}
+    return out
+
+
+def cpu_baseline():
+    """The oracle's serial run of the medium application (the all-CPU gene),
+    one host core."""
+    import workloads
+    from oracle import ir
+    from oracle import run as orun
+
+    app_o = ir.load(workloads.app_doc("medium"))
+    ts = []
+    for _ in range(3):
+        bufs = orun.setup_buffers(app_o)
+        t0 = time.perf_counter()
+        orun.run_app(app_o, 1, bufs=bufs)
+        ts.append(time.perf_counter() - t0)
+    return sorted(ts)[1]
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-large", action="store_true", help="skip the 513^3-class stencil / 8192 GEMM lines")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+
+    log("bench: medium app, %d warmup + %d timed steps" % (args.warmup, args.steps))
+    r = run_medium(args)
+    P = r["params"]
+    ms_per_step = 1e3 * r["wall"] / args.steps
+    value = args.steps / r["wall"]
+    ks = r["kernels"]
+    # dominant kernel by total time
+    dom = max(ks.items(), key=lambda kv: kv[1]["total_ms"])[0]
+    I, J, K = P["I"], P["J"], P["K"]
+    st = ks["stencil19"]
+    achieved = stencil_bytes(I, J, K) / (st["avg_us"] * 1e-6) / 1e9
+    roofline = {"kernel": "stencil19", "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "bytes_per_launch": stencil_bytes(I, J, K), "avg_launch_us": round(st["avg_us"], 3),
+                "dominant_by_time": dom}
+    g = ks.get("gemm")
+    gemm_tf = 2.0 * 1024 ** 3 / (g["avg_us"] * 1e-6) / 1e12 if g else None
+
+    line = {"metric": METRIC, "value": round(value, 3), "unit": "medium-app runs/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic (seeded SplitMix64 inputs, sine-mode grid)",
+            "config": {"workload": "medium app: 12 loop nests (2 loop-carried recurrences on the CPU), "
+                                   "GEMM 1024x1024, 19-point sweep 129x129x257 x 100 sweeps + FP64 residual",
+                       "gene": "all 10 parallelisable nests on the GPU", "policy": "resident",
+                       "inputs": "resident in HBM at the start of the timed region; outputs left in HBM"},
+            "app_time_ms": round(1e3 * r["internal_median_s"], 4),
+            "app_time_pcie_ms": round(1e3 * r["pcie_median_s"], 4),
+            "gemm1024_TFLOPs": round(gemm_tf, 2) if gemm_tf else None,
+            "roofline": roofline,
+            "kernels_medium": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in ks.items()}}
+    if not args.no_large:
+        log("bench: large-grid stencil and 8192 GEMM")
+        line["kernels_large"] = {k: {kk: round(vv, 4) for kk, vv in v.items()}
+                                 for k, v in run_kernels_large(args).items()}
+    if not args.no_cpu_baseline:
+        log("bench: oracle on one host core (full medium application)")
+        dt = cpu_baseline()
+        line["cpu_baseline"] = {"value": round(1.0 / dt, 5), "unit": "medium-app runs/s", "cores": 1,
+                                "kind": "oracle", "sample": "median of 3 full serial runs of the medium "
+                                                            "application (all 12 nests; %.2f s each)" % dt}
+        line["speedup_vs_1core_oracle"] = round(dt / r["internal_median_s"], 1)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,261 @@
+/*
+ * ofl.h -- C ABI of the GA-driven GPU offload library for AMD MI355X (gfx950).
+ *
+ * The method (Yamato et al., "Study of Automatic GPU Offloading Technology for
+ * Open IoT", Sec. 3.3 and Sec. 4): the for-loop nests of an application are
+ * checked one by one for parallelisability; the ``a`` nests that pass each get
+ * one bit of a gene (1 = run on the GPU, 0 = run on the CPU); a Simple GA
+ * searches the genes, the fitness of each coming from the measured run time
+ * of the application under that pattern (Sec. 5.1.2: fitness = time^-1/2,
+ * roulette selection with one elite, one-point crossover Pc = 0.9, bit-flip
+ * mutation Pm = 0.05), and a pattern measured before is not measured again.
+ *
+ * Here every offloaded nest runs as a hand-written HIP kernel for gfx950 and
+ * every CPU nest as serial host code; host<->device copies follow from the
+ * pattern (Sec. 3.3: transfer overhead is why the combination of individually
+ * parallelisable loops is searched rather than all offloaded).
+ *
+ * Conventions for every function below
+ *  - Return value: OFL_OK (0) or a negative OFL_E_* code; ofl_status_str()
+ *    names a code and ofl_last_error() gives the detail of the calling
+ *    thread's last failure.  No function aborts the process.
+ *  - Ownership: an ofl_app owns the parsed application, the verdicts, the
+ *    pinned host copies of every buffer and a small device scratch area (both
+ *    allocated on first use and released by ofl_app_free).  The caller owns the
+ *    device buffers (one per application buffer, at least ofl_buf_info's
+ *    byte size, 16-byte aligned) and the stream; the library never frees them.
+ *  - Layouts: matrices row-major; grids p[i][j][k] with k contiguous; f32 and
+ *    f64 IEEE, bf16 as raw 16-bit patterns.
+ *  - Genes: uint8 arrays of length a (ofl_app_info's gene_len), each byte 0 or
+ *    1; bit i belongs to the i-th accepted nest in program order.
+ *  - Streams: a hipStream_t passed as void* (NULL = the null stream).  Run
+ *    and evaluation calls synchronise the stream before returning.
+ *  - Threads: one ofl_app must not be used by two threads at once.
+ */
+#ifndef OFL_H
+#define OFL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---------------------------------------------------------------- codes */
+enum {
+    OFL_OK = 0,
+    OFL_E_ARG = -1,          /* null pointer, bad size or enum value */
+    OFL_E_IO = -2,           /* application file cannot be read */
+    OFL_E_PARSE = -3,        /* malformed JSON or expression */
+    OFL_E_IR = -4,           /* invalid application: unknown op, shape or dtype
+                                mismatch, out-of-bounds access, accepted nest
+                                without a device kernel */
+    OFL_E_GENE_LEN = -5,     /* gene length differs from a */
+    OFL_E_GENE_BIT = -6,     /* gene byte not 0 or 1 */
+    OFL_E_NOT_PARALLEL = -7, /* a rejected nest asked to run on the GPU */
+    OFL_E_BUF = -8,          /* device buffer missing, misaligned or n_bufs wrong */
+    OFL_E_HIP = -9,          /* HIP runtime error (detail in ofl_last_error) */
+    OFL_E_TIMEOUT = -10,     /* run exceeded its deadline and was abandoned */
+    OFL_E_MISMATCH = -11,    /* output check failed */
+    OFL_E_STATE = -12,       /* call out of order (e.g. read before any run) */
+    OFL_E_NOMEM = -13,       /* host or device allocation failed */
+    OFL_E_RANGE = -14        /* index out of range */
+};
+
+/* Parallelisability verdict of a nest and the reason of a rejection
+ * (the compile-error kinds listed in Sec. 4 of the paper). */
+enum { OFL_PARALLEL = 0, OFL_PARALLEL_REDUCTION = 1, OFL_REJECT = 2 };
+enum { OFL_R_NONE = 0, OFL_R_DATA_DEP = 1, OFL_R_EXTERNAL_CALL = 2, OFL_R_BREAK = 3 };
+
+/* Transfer policies (see ofl_plan_transfers) and run flags. */
+enum { OFL_POLICY_RESIDENT = 0, OFL_POLICY_PER_REGION = 1 };
+enum {
+    OFL_RUN_PRESTAGED = 1,   /* set-up content already on the device when the
+                                timed region starts (restored device-side,
+                                outside the timed region) */
+    OFL_RUN_KEEP_OUTPUTS = 2 /* leave outputs on the device (no final D2H);
+                                ofl_read_buffer fetches them afterwards */
+};
+
+/* Buffer element types. */
+enum { OFL_F32 = 0, OFL_F64 = 1, OFL_BF16 = 2 };
+
+/* Run status inside evaluation / GA traces. */
+enum { OFL_ST_OK = 0, OFL_ST_TIMEOUT = 1, OFL_ST_FAILED = 2 };
+
+typedef struct ofl_app ofl_app;
+
+typedef struct {
+    int32_t policy;          /* OFL_POLICY_* */
+    int32_t flags;           /* OFL_RUN_* bits */
+    double deadline_s;       /* wall-time limit of the run, 0 = none */
+} ofl_run_opts;
+
+typedef struct {
+    double t_total_s;        /* host wall time of the timed region: first nest
+                                to outputs in place, transfers included */
+    uint64_t bytes_h2d, bytes_d2h;
+    int32_t n_copies;        /* number of host<->device copies */
+    int32_t n_launches;      /* kernel launches */
+    int32_t n_host_nests;    /* nest executions on the CPU */
+    int32_t status;          /* OFL_ST_* */
+} ofl_run_stats;
+
+typedef struct {
+    int32_t reps;            /* timed runs per gene; time = median (>= 1) */
+    int32_t warmup;          /* untimed runs before them (>= 0) */
+    int32_t policy, flags;   /* as ofl_run_opts */
+    double deadline_s;       /* per run, 0 = none */
+} ofl_eval_opts;
+
+typedef struct {
+    int32_t M, T;            /* individuals, evaluated generations (incl. the first) */
+    double Pc, Pm;           /* crossover rate per pair, mutation rate per bit */
+    double p;                /* fitness = time^-p (the paper uses 1/2) */
+    uint64_t seed;           /* SplitMix64 seed of the GA's random stream */
+    int32_t reps, warmup;    /* measurement of one gene, as ofl_eval_opts */
+    int32_t policy, flags;   /* transfer policy and run flags */
+    double deadline_factor;  /* > 0: measure the all-zero gene first and give
+                                every later run the limit
+                                min(t_all0, deadline_factor * t_best); 0 = none */
+} ofl_ga_params;
+
+typedef struct {
+    uint8_t *best_gene;      /* [a] caller-owned, filled */
+    uint8_t *pop_trace;      /* [T*M*a] caller-owned or NULL */
+    double *time_trace;      /* [T*M] or NULL */
+    int32_t *status_trace;   /* [T*M] or NULL */
+    double best_time, best_fitness;
+    double t_all0;           /* all-zero gene time when measured, else -1 */
+    int32_t n_measured;      /* fresh measurements (cache misses) */
+    int32_t n_generations;
+    double search_wall_s;    /* wall time of the whole search */
+    double time_to_best_s;   /* wall time until the final best was measured */
+} ofl_ga_result;
+
+/* ------------------------------------------------------------ application */
+
+/* Parse an application description (JSON: params, buffers, program of loop
+ * nests with affine accesses and repeat blocks), validate it and run the
+ * parallelisability check of every nest (Sec. 4: loops found and counted,
+ * each checked on its own; the accepted ones define the gene).  `seed` drives
+ * the application's random-initialisation nests.  Allocates nothing on the
+ * GPU.  Errors: OFL_E_IO, OFL_E_PARSE, OFL_E_IR, OFL_E_ARG, OFL_E_NOMEM. */
+int ofl_app_load(const char *path, uint64_t seed, ofl_app **out);
+int ofl_app_load_json(const char *json_text, uint64_t seed, ofl_app **out);
+void ofl_app_free(ofl_app *app);
+
+/* Counts: nests in program order, gene length a, buffers. */
+int ofl_app_info(const ofl_app *app, int32_t *n_nests, int32_t *gene_len, int32_t *n_bufs);
+
+/* Verdict of nest `nest` (OFL_PARALLEL / _REDUCTION / OFL_REJECT), reason
+ * (OFL_R_*), and its gene position (-1 when rejected).  OFL_E_RANGE. */
+int ofl_nest_info(const ofl_app *app, int32_t nest, int32_t *verdict, int32_t *reason,
+                  int32_t *gene_pos);
+int ofl_nest_name(const ofl_app *app, int32_t nest, char *out, int32_t cap);
+
+/* Size in bytes, element type (OFL_F32/F64/BF16) and output flag of buffer
+ * `buf`.  OFL_E_RANGE. */
+int ofl_buf_info(const ofl_app *app, int32_t buf, uint64_t *bytes, int32_t *dtype,
+                 int32_t *is_output);
+int ofl_buf_name(const ofl_app *app, int32_t buf, char *out, int32_t cap);
+
+/* Extents of buffer `buf`, outermost first: *ndim set to the rank, the first
+ * min(rank, cap) extents written to dims.  OFL_E_RANGE. */
+int ofl_buf_dims(const ofl_app *app, int32_t buf, int64_t *dims, int32_t cap, int32_t *ndim);
+
+/* Replace the set-up content of buffer `buf` (what its host copy holds when a
+ * run starts) by `bytes` bytes copied from host memory `src`; `bytes` must be
+ * the buffer's size.  The benchmark input of the application, supplied by the
+ * caller.  Errors: OFL_E_RANGE, OFL_E_ARG, OFL_E_NOMEM. */
+int ofl_set_input(ofl_app *app, int32_t buf, const void *src, uint64_t bytes);
+
+/* Convert a per-nest placement mask (n_nests bytes, 1 = GPU) to a gene.
+ * OFL_E_NOT_PARALLEL when a rejected nest is set, OFL_E_GENE_BIT on a byte
+ * other than 0/1. */
+int ofl_mask_to_gene(const ofl_app *app, const uint8_t *mask, int32_t n_nests, uint8_t *gene_out);
+
+/* ---------------------------------------------------------------- planning */
+
+/* Host<->device copies implied by a gene (pure host computation).  Per nest a
+ * buffer is read when any access reads it or when it is written only in part,
+ * written when any access writes it.  Buffer state (host_valid, dev_valid)
+ * starts (1,0) ((1,1) with OFL_RUN_PRESTAGED).
+ *   RESIDENT: before a GPU nest copy in every read buffer not valid on the
+ *     device; before a CPU nest copy out every read buffer not valid on the
+ *     host; after a nest its written buffers are valid only where it ran; at
+ *     the end copy out outputs not valid on the host (unless KEEP_OUTPUTS).
+ *   PER_REGION: the directive compiler's implicit copies (Sec. 2 of the
+ *     paper): every GPU nest copies in all it reads and copies out all it
+ *     writes.
+ * Errors: OFL_E_GENE_LEN, OFL_E_GENE_BIT, OFL_E_ARG. */
+int ofl_plan_transfers(const ofl_app *app, const uint8_t *gene, int32_t gene_len, int32_t policy,
+                       int32_t flags, uint64_t *bytes_h2d, uint64_t *bytes_d2h, int32_t *n_copies);
+
+/* ---------------------------------------------------------------- running */
+
+/* Run the application once under `gene` (Sec. 4: the pattern is built, run and
+ * its time measured): host copies reset to the set-up content (untimed), then
+ * the timed region executes every nest in program order -- GPU nests as HIP
+ * kernels on `stream` into the caller's device buffers `dev_bufs[n_bufs]`
+ * (device pointers, one per application buffer), CPU nests serially on the
+ * host copies -- with the planned copies in between, and ends when the outputs
+ * are in place.  Synchronous.  With a deadline, a run that exceeds it stops at
+ * the next nest boundary (or inside a CPU nest) and returns OFL_E_TIMEOUT with
+ * stats->status = OFL_ST_TIMEOUT.  Errors: gene errors, OFL_E_BUF, OFL_E_HIP,
+ * OFL_E_TIMEOUT, OFL_E_NOMEM. */
+int ofl_run_pattern(ofl_app *app, const uint8_t *gene, int32_t gene_len, void *const *dev_bufs,
+                    int32_t n_bufs, void *stream, const ofl_run_opts *opts, ofl_run_stats *stats);
+
+/* Measure `pop` genes (row-major pop x gene_len): per gene `warmup` untimed
+ * runs and `reps` timed runs, time = median.  Genes that occur more than once
+ * are measured once.  time_out[pop], status_out[pop] (OFL_ST_*); a failed or
+ * timed-out gene gets its status and the time it reached.  Returns OFL_OK
+ * unless the arguments are invalid or a HIP error leaves the device unusable. */
+int ofl_eval_population(ofl_app *app, const uint8_t *genes, int32_t pop, int32_t gene_len,
+                        void *const *dev_bufs, int32_t n_bufs, void *stream,
+                        const ofl_eval_opts *opts, double *time_out, int32_t *status_out);
+
+/* The Simple GA (Sec. 3.3, Sec. 4, Sec. 5.1.2) with measured fitness.
+ * Random stream: SplitMix64(seed); initial bits next()>>63; per generation
+ * M-1 roulette draws (first m whose running fitness sum exceeds u*total,
+ * uniform next()%M when all fitness is 0), pairs in draw order with one u()
+ * against Pc and a point 1 + next()%(a-1), then per non-elite child and bit
+ * one u() against Pm; u() = (next()>>11) * 2^-53.  The elite (highest fitness,
+ * lowest index on ties) is copied unchanged to position 0.  Cached genes are
+ * not re-measured.  Result: best gene over all measurements (earliest on
+ * ties).  Errors: OFL_E_ARG plus those of ofl_run_pattern. */
+int ofl_ga_run(ofl_app *app, const ofl_ga_params *params, void *const *dev_bufs, int32_t n_bufs,
+               void *stream, ofl_ga_result *result);
+
+/* The same GA over an injected time table (host only, no GPU): the time of
+ * gene g is t_table[idx(g)] with idx = sum g_i 2^i, its status
+ * status_table[idx] (NULL = all OK); with deadline_factor > 0 a time above the
+ * limit becomes OFL_ST_TIMEOUT at the limit.  gene_len <= 24. */
+int ofl_ga_run_table(int32_t gene_len, const ofl_ga_params *params, const double *t_table,
+                     const int32_t *status_table, ofl_ga_result *result);
+
+/* Copy the current content of buffer `buf` after a run into host memory
+ * (from the host copy or the device, whichever holds the newest values).
+ * Errors: OFL_E_STATE before any run, OFL_E_RANGE, OFL_E_ARG (bytes too
+ * small), OFL_E_HIP. */
+int ofl_read_buffer(ofl_app *app, int32_t buf, void *host_dst, uint64_t bytes);
+
+/* ---------------------------------------------------------------- profiling */
+
+/* Enable (1) / disable (0) per-kernel timing with HIP events recorded on the
+ * run's stream around every launch; enabling clears the totals. */
+int ofl_set_kernel_timing(ofl_app *app, int32_t enable);
+
+/* Accumulated launches and total kernel time (ms) of op kind `op`
+ * (e.g. "stencil19", "gemm") since timing was enabled.  Unknown op: zeros. */
+int ofl_kernel_stats(const ofl_app *app, const char *op, int64_t *launches, double *total_ms);
+
+/* ---------------------------------------------------------------- status */
+const char *ofl_status_str(int32_t code);
+const char *ofl_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OFL_H */

@@ -1,0 +1,39 @@
+// Simple GA over offload genes (Sec. 3.3, Sec. 4 and Sec. 5.1.2 of the paper).
+#pragma once
+
+#include <cstdint>
+#include <functional>
+#include <vector>
+
+namespace ofl {
+
+struct GaConfig {
+    int M = 12, T = 12;
+    double Pc = 0.9, Pm = 0.05, p = 0.5;
+    uint64_t seed = 1;
+    double deadline_factor = 0.0;
+};
+
+struct Measurement {
+    double t = 0.0;
+    int status = 0;   // OFL_ST_*
+};
+
+// evaluate(gene, limit_seconds_or_negative) -> measurement of an uncached gene
+using Evaluator = std::function<Measurement(const std::vector<uint8_t> &, double)>;
+
+struct GaTrace {
+    std::vector<std::vector<std::vector<uint8_t>>> pops;   // [gen][m] genes
+    std::vector<std::vector<Measurement>> meas;            // [gen][m]
+    std::vector<uint8_t> best_gene;
+    double best_t = -1.0, best_f = -1.0, t_all0 = -1.0;
+    int n_measured = 0;
+    double wall_s = 0.0, time_to_best_s = 0.0;
+};
+
+// Returns false only if `evaluate` requests an abort by throwing.
+void run_ga(int a, const GaConfig &cfg, const Evaluator &evaluate, GaTrace &out);
+
+double ga_fitness(const Measurement &m, double p);
+
+}  // namespace ofl

@@ -1,0 +1,31 @@
+// Serial host execution of a nest (gene bit 0, and the rejected nests that
+// always stay on the CPU).  One thread, the nest's own loop order.
+#pragma once
+
+#include <chrono>
+#include <cstdint>
+#include <vector>
+
+#include "ir.hpp"
+
+namespace ofl {
+
+struct Deadline {
+    bool active = false;
+    std::chrono::steady_clock::time_point until;
+    bool expired() const { return active && std::chrono::steady_clock::now() > until; }
+};
+
+// Runs nest `n` on host arrays `host[b]`; `env` = repeat-variable values;
+// `seed` = application seed.  Returns false if the deadline expired (checked
+// once per outer-loop iteration), leaving the outputs partially written.
+bool run_host_nest(const AppIR &app, const Nest &n, const std::vector<void *> &host, const int64_t *env,
+                   uint64_t seed, const Deadline &dl);
+
+// Host part of the counter-based generator: key of random stream `stream`.
+uint64_t uniform_stream_key(uint64_t seed, uint32_t stream);
+
+// Set-up content of a buffer (sine-mode field), written into `dst`.
+void fill_setup_sin(const Buffer &b, float *dst);
+
+}  // namespace ofl

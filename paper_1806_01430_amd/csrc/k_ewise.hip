@@ -1,0 +1,257 @@
+// Element-wise, copy, cast, transpose, sum-of-squares and initialisation
+// kernels.  All are bound by HBM bandwidth: 16-byte vector accesses where the
+// element count allows, grid-stride loops sized to a few waves per SIMD.
+#include <hip/hip_runtime.h>
+
+#include "dev_common.hpp"
+#include "kernels.hpp"
+
+namespace ofl {
+namespace k {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+inline unsigned grid_for(int64_t work_items, int per_thread = 1) {
+    int64_t blocks = (work_items + (int64_t)kThreads * per_thread - 1) / ((int64_t)kThreads * per_thread);
+    if (blocks < 1) blocks = 1;
+    if (blocks > 8192) blocks = 8192;   // 256 CUs x 32 blocks: grid-stride beyond that
+    return (unsigned)blocks;
+}
+
+__device__ inline uint64_t mix64(uint64_t z) {
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ inline float uniform24(uint64_t key, int64_t e) {
+    return (float)(mix64(key + (uint64_t)(e + 1) * kGolden) >> 40) * (1.0f / 16777216.0f);
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill_zero(uint4 *dst, int64_t n16, unsigned char *tail, int ntail) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n16; i += stride)
+        dst[i] = make_uint4(0, 0, 0, 0);
+    if (blockIdx.x == 0 && (int)threadIdx.x < ntail) tail[threadIdx.x] = 0;
+}
+
+__global__ __launch_bounds__(kThreads) void k_init_uniform(float *x, int64_t n, uint64_t key) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t n4 = n / 4;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n4; g += stride) {
+        const int64_t e = g * 4;
+        float4 v;
+        v.x = uniform24(key, e);
+        v.y = uniform24(key, e + 1);
+        v.z = uniform24(key, e + 2);
+        v.w = uniform24(key, e + 3);
+        reinterpret_cast<float4 *>(x)[g] = v;
+    }
+    if (blockIdx.x == 0 && (int)threadIdx.x < (int)(n - n4 * 4)) {
+        const int64_t e = n4 * 4 + threadIdx.x;
+        x[e] = uniform24(key, e);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_add_scaled(float *C, const float *A, float alpha, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t n4 = n / 4;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n4; g += stride) {
+        float4 c = reinterpret_cast<float4 *>(C)[g];
+        const float4 a = reinterpret_cast<const float4 *>(A)[g];
+        c.x = c.x + alpha * a.x;
+        c.y = c.y + alpha * a.y;
+        c.z = c.z + alpha * a.z;
+        c.w = c.w + alpha * a.w;
+        reinterpret_cast<float4 *>(C)[g] = c;
+    }
+    if (blockIdx.x == 0 && (int)threadIdx.x < (int)(n - n4 * 4)) {
+        const int64_t e = n4 * 4 + threadIdx.x;
+        C[e] = C[e] + alpha * A[e];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_avg2(float *S, const float *X, const float *Y, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t n4 = n / 4;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n4; g += stride) {
+        const float4 x = reinterpret_cast<const float4 *>(X)[g];
+        const float4 y = reinterpret_cast<const float4 *>(Y)[g];
+        float4 s;
+        s.x = 0.5f * (x.x + y.x);
+        s.y = 0.5f * (x.y + y.y);
+        s.z = 0.5f * (x.z + y.z);
+        s.w = 0.5f * (x.w + y.w);
+        reinterpret_cast<float4 *>(S)[g] = s;
+    }
+    if (blockIdx.x == 0 && (int)threadIdx.x < (int)(n - n4 * 4)) {
+        const int64_t e = n4 * 4 + threadIdx.x;
+        S[e] = 0.5f * (X[e] + Y[e]);
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_scale(float *D, float beta, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t n4 = n / 4;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n4; g += stride) {
+        float4 d = reinterpret_cast<float4 *>(D)[g];
+        d.x = beta * d.x;
+        d.y = beta * d.y;
+        d.z = beta * d.z;
+        d.w = beta * d.w;
+        reinterpret_cast<float4 *>(D)[g] = d;
+    }
+    if (blockIdx.x == 0 && (int)threadIdx.x < (int)(n - n4 * 4)) {
+        const int64_t e = n4 * 4 + threadIdx.x;
+        D[e] = beta * D[e];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_copy16(uint4 *dst, const uint4 *src, int64_t n16,
+                                                     unsigned char *dtail, const unsigned char *stail, int ntail) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+    if (blockIdx.x == 0 && (int)threadIdx.x < ntail) dtail[threadIdx.x] = stail[threadIdx.x];
+}
+
+__device__ inline unsigned short bf16_rne(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return (unsigned short)((u >> 16) | 0x40u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+
+__global__ __launch_bounds__(kThreads) void k_cast_bf16(unsigned short *dst, const float *src, int64_t n) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t n4 = n / 4;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n4; g += stride) {
+        const float4 v = reinterpret_cast<const float4 *>(src)[g];
+        uint2 o;
+        o.x = (unsigned)bf16_rne(v.x) | ((unsigned)bf16_rne(v.y) << 16);
+        o.y = (unsigned)bf16_rne(v.z) | ((unsigned)bf16_rne(v.w) << 16);
+        reinterpret_cast<uint2 *>(dst)[g] = o;
+    }
+    if (blockIdx.x == 0 && (int)threadIdx.x < (int)(n - n4 * 4)) {
+        const int64_t e = n4 * 4 + threadIdx.x;
+        dst[e] = bf16_rne(src[e]);
+    }
+}
+
+// T[c][r] = X[r][c]; 64 x 64 tiles through LDS (+1 column of padding so the
+// transposed read hits 64 distinct banks).
+constexpr int kTile = 64;
+__global__ __launch_bounds__(kThreads) void k_transpose(const float *__restrict__ X, float *__restrict__ T,
+                                                        int64_t R, int64_t Cc) {
+    __shared__ float tile[kTile][kTile + 1];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int64_t c0 = (int64_t)blockIdx.x * kTile, r0 = (int64_t)blockIdx.y * kTile;
+#pragma unroll
+    for (int r = ty; r < kTile; r += kThreads / kTile) {
+        const int64_t row = r0 + r, col = c0 + tx;
+        if (row < R && col < Cc) tile[r][tx] = X[row * Cc + col];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = ty; r < kTile; r += kThreads / kTile) {
+        const int64_t orow = c0 + r, ocol = r0 + tx;   // T is Cc x R
+        if (orow < Cc && ocol < R) T[orow * R + ocol] = tile[tx][r];
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_sumsq(const float *x, int64_t n, double *s_out, double *partials,
+                                                    unsigned *counter) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t n4 = n / 4;
+    double acc = 0.0;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n4; g += stride) {
+        const float4 v = reinterpret_cast<const float4 *>(x)[g];
+        const double a = v.x, b = v.y, c = v.z, d = v.w;
+        acc = acc + a * a;
+        acc = acc + b * b;
+        acc = acc + c * c;
+        acc = acc + d * d;
+    }
+    if (blockIdx.x == 0 && (int)threadIdx.x < (int)(n - n4 * 4)) {
+        const double a = x[n4 * 4 + threadIdx.x];
+        acc = acc + a * a;
+    }
+    reduce_finish(acc, partials, counter, s_out);
+}
+
+}  // namespace
+
+hipError_t fill_zero(void *dst, uint64_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    const int64_t n16 = (int64_t)(bytes / 16);
+    const int ntail = (int)(bytes - (uint64_t)n16 * 16);
+    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(n16 > 0 ? n16 : 1, 4)), dim3(kThreads), 0, s,
+                       static_cast<uint4 *>(dst), n16, static_cast<unsigned char *>(dst) + n16 * 16, ntail);
+    return hipGetLastError();
+}
+
+hipError_t init_uniform(float *x, int64_t n, uint64_t key, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_init_uniform, dim3(grid_for(n / 4 + 1, 2)), dim3(kThreads), 0, s, x, n, key);
+    return hipGetLastError();
+}
+
+hipError_t add_scaled(float *C, const float *A, float alpha, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_add_scaled, dim3(grid_for(n / 4 + 1, 4)), dim3(kThreads), 0, s, C, A, alpha, n);
+    return hipGetLastError();
+}
+
+hipError_t avg2(float *S, const float *X, const float *Y, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_avg2, dim3(grid_for(n / 4 + 1, 4)), dim3(kThreads), 0, s, S, X, Y, n);
+    return hipGetLastError();
+}
+
+hipError_t scale(float *D, float beta, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_scale, dim3(grid_for(n / 4 + 1, 4)), dim3(kThreads), 0, s, D, beta, n);
+    return hipGetLastError();
+}
+
+hipError_t copy_bytes(void *dst, const void *src, uint64_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    const int64_t n16 = (int64_t)(bytes / 16);
+    const int ntail = (int)(bytes - (uint64_t)n16 * 16);
+    hipLaunchKernelGGL(k_copy16, dim3(grid_for(n16 > 0 ? n16 : 1, 4)), dim3(kThreads), 0, s,
+                       static_cast<uint4 *>(dst), static_cast<const uint4 *>(src), n16,
+                       static_cast<unsigned char *>(dst) + n16 * 16,
+                       static_cast<const unsigned char *>(src) + n16 * 16, ntail);
+    return hipGetLastError();
+}
+
+hipError_t cast_bf16(uint16_t *dst, const float *src, int64_t n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_cast_bf16, dim3(grid_for(n / 4 + 1, 4)), dim3(kThreads), 0, s,
+                       reinterpret_cast<unsigned short *>(dst), src, n);
+    return hipGetLastError();
+}
+
+hipError_t transpose(const float *X, float *T, int64_t R, int64_t Cc, hipStream_t s) {
+    if (R <= 0 || Cc <= 0) return hipSuccess;
+    dim3 grid((unsigned)((Cc + kTile - 1) / kTile), (unsigned)((R + kTile - 1) / kTile));
+    if (grid.y > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_transpose, grid, dim3(kThreads), 0, s, X, T, R, Cc);
+    return hipGetLastError();
+}
+
+int64_t sumsq_partials(int64_t n) { return grid_for(n / 4 + 1, 8); }
+
+hipError_t sumsq(const float *x, int64_t n, double *s_out, const ReduceScratch &rs, hipStream_t s) {
+    const unsigned blocks = (unsigned)sumsq_partials(n);
+    if ((int64_t)blocks > rs.capacity) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_sumsq, dim3(blocks), dim3(kThreads), 0, s, x, n, s_out, rs.partials, rs.counter);
+    return hipGetLastError();
+}
+
+}  // namespace k
+}  // namespace ofl

@@ -1,0 +1,41 @@
+// Launchers of the gfx950 kernels, one per nest kind.  All launch on the given
+// stream and return the launch status; none synchronises.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ofl {
+namespace k {
+
+// Device scratch used by the reductions: per-block partial sums and a
+// completion counter that the last block returns to zero.
+struct ReduceScratch {
+    double *partials = nullptr;
+    unsigned *counter = nullptr;
+    int64_t capacity = 0;   // number of partials
+};
+
+hipError_t fill_zero(void *dst, uint64_t bytes, hipStream_t s);
+hipError_t init_uniform(float *x, int64_t n, uint64_t key, hipStream_t s);
+hipError_t add_scaled(float *C, const float *A, float alpha, int64_t n, hipStream_t s);
+hipError_t avg2(float *S, const float *X, const float *Y, int64_t n, hipStream_t s);
+hipError_t scale(float *D, float beta, int64_t n, hipStream_t s);
+hipError_t copy_bytes(void *dst, const void *src, uint64_t bytes, hipStream_t s);
+hipError_t cast_bf16(uint16_t *dst, const float *src, int64_t n, hipStream_t s);
+hipError_t transpose(const float *X, float *T, int64_t R, int64_t Cc, hipStream_t s);
+hipError_t sumsq(const float *x, int64_t n, double *s_out, const ReduceScratch &rs, hipStream_t s);
+hipError_t stencil19(const float *p, float *q, int64_t I, int64_t J, int64_t K, double *res_slot,
+                     const ReduceScratch &rs, hipStream_t s);
+hipError_t copy_interior(float *p, const float *q, int64_t I, int64_t J, int64_t K, hipStream_t s);
+hipError_t gemm_f32(const float *A, const float *B, float *C, int64_t M, int64_t N, int64_t K, hipStream_t s);
+hipError_t gemm_bf16(const uint16_t *A, const uint16_t *B, float *C, int64_t M, int64_t N, int64_t K,
+                     hipStream_t s);
+
+// Upper bound on partials the reductions need for a problem size.
+int64_t sumsq_partials(int64_t n);
+int64_t stencil_partials(int64_t I, int64_t J, int64_t K);
+
+}  // namespace k
+}  // namespace ofl

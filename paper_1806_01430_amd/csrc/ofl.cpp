@@ -1,0 +1,783 @@
+// C ABI, application object and pattern executor.
+#include "../../include/ofl.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <new>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "ga.hpp"
+#include "host_nests.hpp"
+#include "ir.hpp"
+#include "kernels.hpp"
+#include "plan.hpp"
+
+using namespace ofl;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string &msg) {
+    g_last_error = msg;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return OFL_E_HIP;
+}
+
+using clk = std::chrono::steady_clock;
+
+}  // namespace
+
+struct ofl_app {
+    AppIR ir;
+    uint64_t seed = 0;
+
+    // pinned host copies of every buffer and the set-up content of sine fields
+    std::vector<void *> host;
+    std::vector<char> host_dirty;            // differs from the set-up content
+    std::vector<std::vector<unsigned char>> setup;   // non-zero set-up content (empty = zeros)
+
+    // device side owned by the library
+    int device = -1;
+    std::vector<void *> dev_setup;           // device copies of sine set-up content
+    double *d_partials = nullptr;
+    unsigned *d_counter = nullptr;
+    int64_t partial_cap = 0;
+
+    // state after the last completed run
+    bool ran = false;
+    std::vector<char> host_valid, dev_valid, host_written;
+    std::vector<void *> last_dev;
+    hipStream_t last_stream = nullptr;
+
+    // per-kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> events;
+    std::map<std::string, std::pair<int64_t, double>> kstats;
+
+    ~ofl_app() {
+        for (void *p : host)
+            if (p) (void)hipHostFree(p);
+        for (void *p : dev_setup)
+            if (p) (void)hipFree(p);
+        if (d_partials) (void)hipFree(d_partials);
+        for (auto e : events) (void)hipEventDestroy(e);
+    }
+};
+
+namespace {
+
+int check_gene(const ofl_app *app, const uint8_t *gene, int32_t gene_len, std::vector<uint8_t> &placement) {
+    if (!gene && gene_len > 0) return fail(OFL_E_ARG, "null gene");
+    if (gene_len != app->ir.gene_len)
+        return fail(OFL_E_GENE_LEN, "gene length " + std::to_string(gene_len) + " != " + std::to_string(app->ir.gene_len));
+    for (int i = 0; i < gene_len; ++i)
+        if (gene[i] > 1) return fail(OFL_E_GENE_BIT, "gene byte " + std::to_string(i) + " is not 0/1");
+    placement.assign(app->ir.nests.size(), 0);
+    for (size_t n = 0; n < app->ir.nests.size(); ++n) {
+        const Nest &ns = app->ir.nests[n];
+        if (ns.gene_pos >= 0) placement[n] = gene[ns.gene_pos];
+    }
+    return OFL_OK;
+}
+
+int ensure_host(ofl_app *app) {
+    if (!app->host.empty()) return OFL_OK;
+    const size_t nb = app->ir.bufs.size();
+    if (app->setup.size() != nb) app->setup.resize(nb);
+    std::vector<void *> host(nb, nullptr);
+    for (size_t b = 0; b < nb; ++b) {
+        const Buffer &buf = app->ir.bufs[b];
+        hipError_t e = hipHostMalloc(&host[b], buf.nbytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            for (void *p : host)
+                if (p) (void)hipHostFree(p);
+            return e == hipErrorOutOfMemory ? fail(OFL_E_NOMEM, "pinned host allocation failed")
+                                            : hip_fail(e, "hipHostMalloc");
+        }
+        if (buf.setup_sin && app->setup[b].empty()) {
+            app->setup[b].resize(buf.nbytes);
+            fill_setup_sin(buf, reinterpret_cast<float *>(app->setup[b].data()));
+        }
+        if (!app->setup[b].empty()) std::memcpy(host[b], app->setup[b].data(), buf.nbytes);
+        else std::memset(host[b], 0, buf.nbytes);
+    }
+    app->host = host;
+    app->host_dirty.assign(nb, 0);
+    app->dev_setup.assign(nb, nullptr);
+    return OFL_OK;
+}
+
+void restore_host(ofl_app *app, int b) {
+    const Buffer &buf = app->ir.bufs[b];
+    if (!app->setup[b].empty()) std::memcpy(app->host[b], app->setup[b].data(), buf.nbytes);
+    else std::memset(app->host[b], 0, buf.nbytes);
+    app->host_dirty[b] = 0;
+}
+
+int ensure_device(ofl_app *app) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (app->device >= 0 && app->device != dev)
+        return fail(OFL_E_STATE, "application already bound to another device");
+    app->device = dev;
+    if (app->d_partials) return OFL_OK;
+    int64_t cap = 1;
+    for (const auto &n : app->ir.nests) {
+        if (n.op == OP_SUMSQ) cap = std::max(cap, k::sumsq_partials(app->ir.bufs[n.b[0]].count));
+        if (n.op == OP_STENCIL19) {
+            const auto &d = app->ir.bufs[n.b[0]].dims;
+            cap = std::max(cap, k::stencil_partials(d[0], d[1], d[2]));
+        }
+    }
+    void *mem = nullptr;
+    const size_t bytes = (size_t)cap * sizeof(double) + 256;
+    e = hipMalloc(&mem, bytes);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(OFL_E_NOMEM, "device scratch") : hip_fail(e, "hipMalloc");
+    e = hipMemset(mem, 0, bytes);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        (void)hipFree(mem);
+        return hip_fail(e, "scratch init");
+    }
+    app->d_partials = static_cast<double *>(mem);
+    app->d_counter = reinterpret_cast<unsigned *>(static_cast<char *>(mem) + (size_t)cap * sizeof(double));
+    app->partial_cap = cap;
+    return OFL_OK;
+}
+
+int ensure_dev_setup(ofl_app *app, int b) {
+    if (app->dev_setup[b]) return OFL_OK;
+    const Buffer &buf = app->ir.bufs[b];
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, buf.nbytes);
+    if (e != hipSuccess) return e == hipErrorOutOfMemory ? fail(OFL_E_NOMEM, "device set-up copy") : hip_fail(e, "hipMalloc");
+    e = hipMemcpy(p, app->setup[b].data(), buf.nbytes, hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(p);
+        return hip_fail(e, "set-up upload");
+    }
+    app->dev_setup[b] = p;
+    return OFL_OK;
+}
+
+int check_bufs(const ofl_app *app, void *const *dev_bufs, int32_t n_bufs) {
+    if (n_bufs != (int32_t)app->ir.bufs.size())
+        return fail(OFL_E_BUF, "n_bufs " + std::to_string(n_bufs) + " != " + std::to_string(app->ir.bufs.size()));
+    if (!dev_bufs) return fail(OFL_E_BUF, "null buffer table");
+    for (int32_t b = 0; b < n_bufs; ++b) {
+        if (!dev_bufs[b]) return fail(OFL_E_BUF, "null device pointer for buffer '" + app->ir.bufs[b].name + "'");
+        if (reinterpret_cast<uintptr_t>(dev_bufs[b]) % 16)
+            return fail(OFL_E_BUF, "device buffer '" + app->ir.bufs[b].name + "' not 16-byte aligned");
+    }
+    return OFL_OK;
+}
+
+hipError_t launch_nest(ofl_app *app, const Nest &n, void *const *dev, const int64_t *env, hipStream_t s) {
+    const AppIR &ir = app->ir;
+    auto F = [&](int i) { return static_cast<float *>(dev[n.b[i]]); };
+    auto cnt = [&](int i) { return ir.bufs[n.b[i]].count; };
+    k::ReduceScratch rs{app->d_partials, app->d_counter, app->partial_cap};
+    hipError_t e = hipSuccess;
+    switch (n.op) {
+    case OP_INIT_UNIFORM:
+        for (size_t t = 0; t < n.b.size() && e == hipSuccess; ++t)
+            e = k::init_uniform(static_cast<float *>(dev[n.b[t]]), ir.bufs[n.b[t]].count,
+                                uniform_stream_key(app->seed, n.streams[t]), s);
+        return e;
+    case OP_GEMM: {
+        const auto &a = ir.bufs[n.b[0]].dims, &bb = ir.bufs[n.b[1]].dims;
+        return k::gemm_f32(F(0), F(1), F(2), a[0], bb[1], a[1], s);
+    }
+    case OP_GEMM_BF16: {
+        const auto &a = ir.bufs[n.b[0]].dims, &bb = ir.bufs[n.b[1]].dims;
+        return k::gemm_bf16(static_cast<const uint16_t *>(dev[n.b[0]]), static_cast<const uint16_t *>(dev[n.b[1]]),
+                            F(2), a[0], bb[1], a[1], s);
+    }
+    case OP_ADD_SCALED: return k::add_scaled(F(0), F(1), (float)n.alpha, cnt(0), s);
+    case OP_AVG2: return k::avg2(F(0), F(1), F(2), cnt(0), s);
+    case OP_SCALE: return k::scale(F(0), (float)n.alpha, cnt(0), s);
+    case OP_COPY: return k::copy_bytes(dev[n.b[0]], dev[n.b[1]], ir.bufs[n.b[0]].nbytes, s);
+    case OP_CAST_BF16:
+        for (size_t t = 0; t + 1 < n.b.size() && e == hipSuccess; t += 2)
+            e = k::cast_bf16(static_cast<uint16_t *>(dev[n.b[t]]), static_cast<const float *>(dev[n.b[t + 1]]),
+                             ir.bufs[n.b[t]].count, s);
+        return e;
+    case OP_TRANSPOSE: {
+        const auto &d = ir.bufs[n.b[0]].dims;
+        return k::transpose(F(0), F(1), d[0], d[1], s);
+    }
+    case OP_SUMSQ: return k::sumsq(F(0), cnt(0), static_cast<double *>(dev[n.b[1]]), rs, s);
+    case OP_STENCIL19: {
+        const auto &d = ir.bufs[n.b[0]].dims;
+        double *slot = static_cast<double *>(dev[n.b[2]]) + env[n.slot_repeat];
+        return k::stencil19(F(0), F(1), d[0], d[1], d[2], slot, rs, s);
+    }
+    case OP_COPY_INTERIOR: {
+        const auto &d = ir.bufs[n.b[0]].dims;
+        return k::copy_interior(F(0), F(1), d[0], d[1], d[2], s);
+    }
+    default:
+        return hipErrorInvalidValue;
+    }
+}
+
+int32_t kernel_launch_count(const Nest &n) {
+    if (n.op == OP_INIT_UNIFORM) return (int32_t)n.b.size();
+    if (n.op == OP_CAST_BF16) return (int32_t)(n.b.size() / 2);
+    return 1;
+}
+
+struct RunResult {
+    int code = OFL_OK;
+    ofl_run_stats st{};
+};
+
+RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *const *dev, hipStream_t stream,
+                   int policy, int flags, double deadline_s) {
+    RunResult rr;
+    ofl_run_stats &st = rr.st;
+    std::memset(&st, 0, sizeof(st));
+    const AppIR &ir = app->ir;
+    const size_t nb = ir.bufs.size();
+    int rc = ensure_host(app);
+    if (rc == OFL_OK) rc = ensure_device(app);
+    if (rc != OFL_OK) {
+        rr.code = rc;
+        st.status = OFL_ST_FAILED;
+        return rr;
+    }
+    Plan plan;
+    build_plan(ir, placement, policy, flags, plan);
+    app->ran = false;
+
+    // ---- untimed reset: restore only set-up content that this run consumes
+    for (size_t b = 0; b < nb; ++b)
+        if (plan.host_init_used[b] && app->host_dirty[b]) restore_host(app, (int)b);
+    if (flags & OFL_RUN_PRESTAGED) {
+        for (size_t b = 0; b < nb; ++b) {
+            if (!plan.dev_init_used[b]) continue;
+            hipError_t e;
+            if (!app->setup[b].empty()) {
+                if ((rc = ensure_dev_setup(app, (int)b)) != OFL_OK) {
+                    rr.code = rc;
+                    st.status = OFL_ST_FAILED;
+                    return rr;
+                }
+                e = k::copy_bytes(dev[b], app->dev_setup[b], ir.bufs[b].nbytes, stream);
+            } else {
+                e = k::fill_zero(dev[b], ir.bufs[b].nbytes, stream);
+            }
+            if (e != hipSuccess) {
+                rr.code = hip_fail(e, "device set-up restore");
+                st.status = OFL_ST_FAILED;
+                return rr;
+            }
+        }
+    }
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        rr.code = hip_fail(e, "hipStreamSynchronize");
+        st.status = OFL_ST_FAILED;
+        return rr;
+    }
+
+    // per-kernel timing events: two per GPU nest step
+    std::vector<std::pair<int, int>> timed;   // (nest, event index)
+    if (app->timing) {
+        const size_t need = 2 * (size_t)plan.launches;
+        while (app->events.size() < need) {
+            hipEvent_t ev;
+            if (hipEventCreate(&ev) != hipSuccess) break;
+            app->events.push_back(ev);
+        }
+    }
+
+    std::vector<char> host_written(nb, 0);
+    Deadline dl;
+    const auto t0 = clk::now();
+    if (deadline_s > 0) {
+        dl.active = true;
+        dl.until = t0 + std::chrono::duration_cast<clk::duration>(std::chrono::duration<double>(deadline_s));
+    }
+    bool pending = false, timed_out = false;
+    size_t ev_next = 0;
+    for (const Step &step : plan.steps) {
+        if (dl.expired()) {
+            timed_out = true;
+            break;
+        }
+        switch (step.kind) {
+        case ST_H2D:
+            e = hipMemcpyAsync(dev[step.idx], app->host[step.idx], ir.bufs[step.idx].nbytes, hipMemcpyHostToDevice,
+                               stream);
+            if (e != hipSuccess) {
+                rr.code = hip_fail(e, "H2D copy");
+                break;
+            }
+            st.bytes_h2d += ir.bufs[step.idx].nbytes;
+            st.n_copies++;
+            pending = true;
+            break;
+        case ST_D2H:
+            e = hipMemcpyAsync(app->host[step.idx], dev[step.idx], ir.bufs[step.idx].nbytes, hipMemcpyDeviceToHost,
+                               stream);
+            if (e != hipSuccess) {
+                rr.code = hip_fail(e, "D2H copy");
+                break;
+            }
+            st.bytes_d2h += ir.bufs[step.idx].nbytes;
+            st.n_copies++;
+            host_written[step.idx] = 1;
+            pending = true;
+            break;
+        case ST_GPU: {
+            const Nest &n = ir.nests[step.idx];
+            const bool tm = app->timing && ev_next + 2 <= app->events.size();
+            if (tm) (void)hipEventRecord(app->events[ev_next], stream);
+            e = launch_nest(app, n, dev, plan.env.data() + step.env, stream);
+            if (e != hipSuccess) {
+                rr.code = hip_fail(e, (std::string("launch of nest ") + n.name).c_str());
+                break;
+            }
+            if (tm) {
+                (void)hipEventRecord(app->events[ev_next + 1], stream);
+                timed.emplace_back(step.idx, (int)ev_next);
+                ev_next += 2;
+            }
+            st.n_launches += kernel_launch_count(n);
+            pending = true;
+            break;
+        }
+        case ST_CPU: {
+            if (pending) {
+                e = hipStreamSynchronize(stream);
+                if (e != hipSuccess) {
+                    rr.code = hip_fail(e, "hipStreamSynchronize");
+                    break;
+                }
+                pending = false;
+            }
+            const Nest &n = ir.nests[step.idx];
+            if (!run_host_nest(ir, n, app->host, plan.env.data() + step.env, app->seed, dl)) timed_out = true;
+            for (int b : n.writes) host_written[b] = 1;
+            st.n_host_nests++;
+            break;
+        }
+        }
+        if (rr.code != OFL_OK || timed_out) break;
+    }
+    e = hipStreamSynchronize(stream);
+    const auto t1 = clk::now();
+    st.t_total_s = std::chrono::duration<double>(t1 - t0).count();
+    for (size_t b = 0; b < nb; ++b)
+        if (host_written[b]) app->host_dirty[b] = 1;
+    if (rr.code == OFL_OK && e != hipSuccess) rr.code = hip_fail(e, "hipStreamSynchronize");
+    if (rr.code != OFL_OK) {
+        st.status = OFL_ST_FAILED;
+        return rr;
+    }
+    if (timed_out || dl.expired()) {
+        st.status = OFL_ST_TIMEOUT;
+        rr.code = fail(OFL_E_TIMEOUT, "run exceeded its deadline");
+        return rr;
+    }
+    for (const auto &te : timed) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, app->events[te.second], app->events[te.second + 1]) == hipSuccess) {
+            auto &ks = app->kstats[op_name(ir.nests[te.first].op)];
+            ks.first += kernel_launch_count(ir.nests[te.first]);
+            ks.second += ms;
+        }
+    }
+    st.status = OFL_ST_OK;
+    app->ran = true;
+    app->host_valid = plan.host_valid;
+    app->dev_valid = plan.dev_valid;
+    app->host_written = host_written;
+    app->last_dev.assign(dev, dev + nb);
+    app->last_stream = stream;
+    return rr;
+}
+
+double median_of(std::vector<double> v) {
+    std::sort(v.begin(), v.end());
+    const size_t n = v.size();
+    return (n % 2) ? v[n / 2] : 0.5 * (v[n / 2 - 1] + v[n / 2]);
+}
+
+// warmup + reps runs of one gene; median time
+Measurement measure(ofl_app *app, const std::vector<uint8_t> &placement, void *const *dev, hipStream_t s,
+                    int reps, int warmup, int policy, int flags, double deadline_s, int *hard_error) {
+    Measurement m;
+    std::vector<double> ts;
+    for (int r = 0; r < warmup + reps; ++r) {
+        RunResult rr = run_once(app, placement, dev, s, policy, flags, deadline_s);
+        if (rr.code == OFL_E_TIMEOUT) {
+            m.status = OFL_ST_TIMEOUT;
+            m.t = rr.st.t_total_s;
+            return m;
+        }
+        if (rr.code != OFL_OK) {
+            m.status = OFL_ST_FAILED;
+            m.t = rr.st.t_total_s;
+            if (rr.code == OFL_E_HIP || rr.code == OFL_E_NOMEM || rr.code == OFL_E_STATE) *hard_error = rr.code;
+            return m;
+        }
+        if (r >= warmup) ts.push_back(rr.st.t_total_s);
+    }
+    m.status = OFL_ST_OK;
+    m.t = median_of(ts);
+    return m;
+}
+
+void copy_name(const std::string &s, char *out, int32_t cap) {
+    if (!out || cap <= 0) return;
+    const size_t n = std::min((size_t)cap - 1, s.size());
+    std::memcpy(out, s.data(), n);
+    out[n] = 0;
+}
+
+void fill_ga_result(const GaTrace &tr, int a, int M, ofl_ga_result *res) {
+    if (res->best_gene && !tr.best_gene.empty()) std::memcpy(res->best_gene, tr.best_gene.data(), a);
+    for (size_t g = 0; g < tr.pops.size(); ++g)
+        for (int m = 0; m < M; ++m) {
+            const size_t o = g * M + m;
+            if (res->pop_trace) std::memcpy(res->pop_trace + o * a, tr.pops[g][m].data(), a);
+            if (res->time_trace) res->time_trace[o] = tr.meas[g][m].t;
+            if (res->status_trace) res->status_trace[o] = tr.meas[g][m].status;
+        }
+    res->best_time = tr.best_t;
+    res->best_fitness = tr.best_f;
+    res->t_all0 = tr.t_all0;
+    res->n_measured = tr.n_measured;
+    res->n_generations = (int32_t)tr.pops.size();
+    res->search_wall_s = tr.wall_s;
+    res->time_to_best_s = tr.time_to_best_s;
+}
+
+int check_ga_params(const ofl_ga_params *p, int a) {
+    if (!p) return fail(OFL_E_ARG, "null GA parameters");
+    if (p->M < 1 || p->T < 1 || a < 1) return fail(OFL_E_ARG, "need M >= 1, T >= 1 and a non-empty gene");
+    if (!(p->Pc >= 0 && p->Pc <= 1 && p->Pm >= 0 && p->Pm <= 1 && p->p > 0))
+        return fail(OFL_E_ARG, "rates must lie in [0,1] and the exponent be > 0");
+    return OFL_OK;
+}
+
+GaConfig ga_config(const ofl_ga_params *p) {
+    GaConfig c;
+    c.M = p->M;
+    c.T = p->T;
+    c.Pc = p->Pc;
+    c.Pm = p->Pm;
+    c.p = p->p;
+    c.seed = p->seed;
+    c.deadline_factor = p->deadline_factor;
+    return c;
+}
+
+int load_common(const std::string &text, uint64_t seed, ofl_app **out) {
+    if (!out) return fail(OFL_E_ARG, "null output pointer");
+    *out = nullptr;
+    ofl_app *app = new (std::nothrow) ofl_app();
+    if (!app) return fail(OFL_E_NOMEM, "out of memory");
+    std::string err;
+    int rc = parse_app(text, app->ir, err);
+    if (rc != OFL_OK) {
+        delete app;
+        return fail(rc, err);
+    }
+    app->seed = seed;
+    *out = app;
+    return OFL_OK;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+extern "C" {
+
+int ofl_app_load_json(const char *json_text, uint64_t seed, ofl_app **out) {
+    if (!json_text) return fail(OFL_E_ARG, "null JSON text");
+    return load_common(json_text, seed, out);
+}
+
+int ofl_app_load(const char *path, uint64_t seed, ofl_app **out) {
+    if (!path) return fail(OFL_E_ARG, "null path");
+    std::ifstream f(path);
+    if (!f) return fail(OFL_E_IO, std::string("cannot open ") + path);
+    std::stringstream ss;
+    ss << f.rdbuf();
+    return load_common(ss.str(), seed, out);
+}
+
+void ofl_app_free(ofl_app *app) { delete app; }
+
+int ofl_app_info(const ofl_app *app, int32_t *n_nests, int32_t *gene_len, int32_t *n_bufs) {
+    if (!app) return fail(OFL_E_ARG, "null app");
+    if (n_nests) *n_nests = (int32_t)app->ir.nests.size();
+    if (gene_len) *gene_len = app->ir.gene_len;
+    if (n_bufs) *n_bufs = (int32_t)app->ir.bufs.size();
+    return OFL_OK;
+}
+
+int ofl_nest_info(const ofl_app *app, int32_t nest, int32_t *verdict, int32_t *reason, int32_t *gene_pos) {
+    if (!app) return fail(OFL_E_ARG, "null app");
+    if (nest < 0 || nest >= (int32_t)app->ir.nests.size()) return fail(OFL_E_RANGE, "nest index out of range");
+    const Nest &n = app->ir.nests[nest];
+    if (verdict) *verdict = n.verdict;
+    if (reason) *reason = n.reason;
+    if (gene_pos) *gene_pos = n.gene_pos;
+    return OFL_OK;
+}
+
+int ofl_nest_name(const ofl_app *app, int32_t nest, char *out, int32_t cap) {
+    if (!app || !out || cap <= 0) return fail(OFL_E_ARG, "bad arguments");
+    if (nest < 0 || nest >= (int32_t)app->ir.nests.size()) return fail(OFL_E_RANGE, "nest index out of range");
+    copy_name(app->ir.nests[nest].name, out, cap);
+    return OFL_OK;
+}
+
+int ofl_buf_info(const ofl_app *app, int32_t buf, uint64_t *bytes, int32_t *dtype, int32_t *is_output) {
+    if (!app) return fail(OFL_E_ARG, "null app");
+    if (buf < 0 || buf >= (int32_t)app->ir.bufs.size()) return fail(OFL_E_RANGE, "buffer index out of range");
+    const Buffer &b = app->ir.bufs[buf];
+    if (bytes) *bytes = b.nbytes;
+    if (dtype) *dtype = b.dtype;
+    if (is_output) *is_output = b.output ? 1 : 0;
+    return OFL_OK;
+}
+
+int ofl_buf_name(const ofl_app *app, int32_t buf, char *out, int32_t cap) {
+    if (!app || !out || cap <= 0) return fail(OFL_E_ARG, "bad arguments");
+    if (buf < 0 || buf >= (int32_t)app->ir.bufs.size()) return fail(OFL_E_RANGE, "buffer index out of range");
+    copy_name(app->ir.bufs[buf].name, out, cap);
+    return OFL_OK;
+}
+
+int ofl_buf_dims(const ofl_app *app, int32_t buf, int64_t *dims, int32_t cap, int32_t *ndim) {
+    if (!app || !ndim || (cap > 0 && !dims)) return fail(OFL_E_ARG, "null argument");
+    if (buf < 0 || buf >= (int32_t)app->ir.bufs.size()) return fail(OFL_E_RANGE, "buffer index out of range");
+    const auto &d = app->ir.bufs[buf].dims;
+    *ndim = (int32_t)d.size();
+    for (int32_t i = 0; i < cap && i < (int32_t)d.size(); ++i) dims[i] = d[i];
+    return OFL_OK;
+}
+
+int ofl_set_input(ofl_app *app, int32_t buf, const void *src, uint64_t bytes) {
+    if (!app || !src) return fail(OFL_E_ARG, "null argument");
+    if (buf < 0 || buf >= (int32_t)app->ir.bufs.size()) return fail(OFL_E_RANGE, "buffer index out of range");
+    const Buffer &b = app->ir.bufs[buf];
+    if (bytes != b.nbytes) return fail(OFL_E_ARG, "input size differs from the buffer size");
+    if (app->setup.size() != app->ir.bufs.size()) app->setup.resize(app->ir.bufs.size());
+    try {
+        app->setup[buf].assign(static_cast<const unsigned char *>(src), static_cast<const unsigned char *>(src) + bytes);
+    } catch (const std::bad_alloc &) {
+        return fail(OFL_E_NOMEM, "out of memory");
+    }
+    if (!app->host.empty()) app->host_dirty[buf] = 1;   // host copy must be refreshed
+    if (!app->dev_setup.empty() && app->dev_setup[buf]) {
+        (void)hipFree(app->dev_setup[buf]);
+        app->dev_setup[buf] = nullptr;
+    }
+    return OFL_OK;
+}
+
+int ofl_mask_to_gene(const ofl_app *app, const uint8_t *mask, int32_t n_nests, uint8_t *gene_out) {
+    if (!app || !mask || (!gene_out && app->ir.gene_len > 0)) return fail(OFL_E_ARG, "null argument");
+    if (n_nests != (int32_t)app->ir.nests.size()) return fail(OFL_E_ARG, "mask length differs from the nest count");
+    for (int32_t n = 0; n < n_nests; ++n) {
+        if (mask[n] > 1) return fail(OFL_E_GENE_BIT, "mask byte is not 0/1");
+        const Nest &ns = app->ir.nests[n];
+        if (ns.gene_pos < 0) {
+            if (mask[n]) return fail(OFL_E_NOT_PARALLEL, "nest " + ns.name + " was rejected and cannot run on the GPU");
+        } else {
+            gene_out[ns.gene_pos] = mask[n];
+        }
+    }
+    return OFL_OK;
+}
+
+int ofl_plan_transfers(const ofl_app *app, const uint8_t *gene, int32_t gene_len, int32_t policy, int32_t flags,
+                       uint64_t *bytes_h2d, uint64_t *bytes_d2h, int32_t *n_copies) {
+    if (!app) return fail(OFL_E_ARG, "null app");
+    if (policy != OFL_POLICY_RESIDENT && policy != OFL_POLICY_PER_REGION) return fail(OFL_E_ARG, "bad policy");
+    if (flags & ~(OFL_RUN_PRESTAGED | OFL_RUN_KEEP_OUTPUTS)) return fail(OFL_E_ARG, "bad flags");
+    std::vector<uint8_t> placement;
+    int rc = check_gene(app, gene, gene_len, placement);
+    if (rc != OFL_OK) return rc;
+    Plan plan;
+    build_plan(app->ir, placement, policy, flags, plan);
+    if (bytes_h2d) *bytes_h2d = plan.h2d;
+    if (bytes_d2h) *bytes_d2h = plan.d2h;
+    if (n_copies) *n_copies = plan.copies;
+    return OFL_OK;
+}
+
+int ofl_run_pattern(ofl_app *app, const uint8_t *gene, int32_t gene_len, void *const *dev_bufs, int32_t n_bufs,
+                    void *stream, const ofl_run_opts *opts, ofl_run_stats *stats) {
+    if (!app) return fail(OFL_E_ARG, "null app");
+    for (const auto &n : app->ir.nests)
+        if (n.op == OP_NONE) return fail(OFL_E_IR, "application has analysis-only nests and cannot run");
+    std::vector<uint8_t> placement;
+    int rc = check_gene(app, gene, gene_len, placement);
+    if (rc != OFL_OK) return rc;
+    if ((rc = check_bufs(app, dev_bufs, n_bufs)) != OFL_OK) return rc;
+    const int policy = opts ? opts->policy : OFL_POLICY_RESIDENT;
+    const int flags = opts ? opts->flags : 0;
+    const double deadline = opts ? opts->deadline_s : 0.0;
+    if (policy != OFL_POLICY_RESIDENT && policy != OFL_POLICY_PER_REGION) return fail(OFL_E_ARG, "bad policy");
+    if (flags & ~(OFL_RUN_PRESTAGED | OFL_RUN_KEEP_OUTPUTS)) return fail(OFL_E_ARG, "bad flags");
+    RunResult rr = run_once(app, placement, dev_bufs, static_cast<hipStream_t>(stream), policy, flags, deadline);
+    if (stats) *stats = rr.st;
+    return rr.code;
+}
+
+int ofl_eval_population(ofl_app *app, const uint8_t *genes, int32_t pop, int32_t gene_len, void *const *dev_bufs,
+                        int32_t n_bufs, void *stream, const ofl_eval_opts *opts, double *time_out,
+                        int32_t *status_out) {
+    if (!app || !genes || !time_out || !status_out || !opts || pop < 0) return fail(OFL_E_ARG, "null argument");
+    if (opts->reps < 1 || opts->warmup < 0) return fail(OFL_E_ARG, "need reps >= 1 and warmup >= 0");
+    int rc = check_bufs(app, dev_bufs, n_bufs);
+    if (rc != OFL_OK) return rc;
+    std::map<std::vector<uint8_t>, Measurement> seen;
+    std::vector<uint8_t> placement;
+    for (int32_t m = 0; m < pop; ++m) {
+        rc = check_gene(app, genes + (size_t)m * gene_len, gene_len, placement);
+        if (rc != OFL_OK) return rc;
+    }
+    for (int32_t m = 0; m < pop; ++m) {
+        std::vector<uint8_t> g(genes + (size_t)m * gene_len, genes + (size_t)(m + 1) * gene_len);
+        auto it = seen.find(g);
+        Measurement meas;
+        if (it != seen.end()) {
+            meas = it->second;
+        } else {
+            check_gene(app, g.data(), gene_len, placement);
+            int hard = OFL_OK;
+            meas = measure(app, placement, dev_bufs, static_cast<hipStream_t>(stream), opts->reps, opts->warmup,
+                           opts->policy, opts->flags, opts->deadline_s, &hard);
+            if (hard != OFL_OK) return hard;
+            seen[g] = meas;
+        }
+        time_out[m] = meas.t;
+        status_out[m] = meas.status;
+    }
+    return OFL_OK;
+}
+
+int ofl_ga_run(ofl_app *app, const ofl_ga_params *params, void *const *dev_bufs, int32_t n_bufs, void *stream,
+               ofl_ga_result *result) {
+    if (!app || !result) return fail(OFL_E_ARG, "null argument");
+    int rc = check_ga_params(params, app->ir.gene_len);
+    if (rc != OFL_OK) return rc;
+    if ((rc = check_bufs(app, dev_bufs, n_bufs)) != OFL_OK) return rc;
+    if (params->reps < 1 || params->warmup < 0) return fail(OFL_E_ARG, "need reps >= 1 and warmup >= 0");
+    int hard = OFL_OK;
+    const int a = app->ir.gene_len;
+    Evaluator ev = [&](const std::vector<uint8_t> &g, double limit) -> Measurement {
+        if (hard != OFL_OK) return Measurement{0.0, OFL_ST_FAILED};
+        std::vector<uint8_t> placement;
+        check_gene(app, g.data(), a, placement);
+        return measure(app, placement, dev_bufs, static_cast<hipStream_t>(stream), params->reps, params->warmup,
+                       params->policy, params->flags, limit > 0 ? limit : 0.0, &hard);
+    };
+    GaTrace tr;
+    run_ga(a, ga_config(params), ev, tr);
+    if (hard != OFL_OK) return hard;
+    fill_ga_result(tr, a, params->M, result);
+    return OFL_OK;
+}
+
+int ofl_ga_run_table(int32_t gene_len, const ofl_ga_params *params, const double *t_table,
+                     const int32_t *status_table, ofl_ga_result *result) {
+    if (!t_table || !result) return fail(OFL_E_ARG, "null argument");
+    if (gene_len < 1 || gene_len > 24) return fail(OFL_E_ARG, "gene_len must be in [1, 24]");
+    int rc = check_ga_params(params, gene_len);
+    if (rc != OFL_OK) return rc;
+    Evaluator ev = [&](const std::vector<uint8_t> &g, double limit) -> Measurement {
+        uint64_t idx = 0;
+        for (int i = 0; i < gene_len; ++i) idx |= (uint64_t)g[i] << i;
+        Measurement m{t_table[idx], status_table ? status_table[idx] : OFL_ST_OK};
+        if (m.status == OFL_ST_OK && limit > 0 && m.t > limit) {
+            m.t = limit;
+            m.status = OFL_ST_TIMEOUT;
+        }
+        return m;
+    };
+    GaTrace tr;
+    run_ga(gene_len, ga_config(params), ev, tr);
+    fill_ga_result(tr, gene_len, params->M, result);
+    return OFL_OK;
+}
+
+int ofl_read_buffer(ofl_app *app, int32_t buf, void *host_dst, uint64_t bytes) {
+    if (!app || !host_dst) return fail(OFL_E_ARG, "null argument");
+    if (buf < 0 || buf >= (int32_t)app->ir.bufs.size()) return fail(OFL_E_RANGE, "buffer index out of range");
+    if (!app->ran) return fail(OFL_E_STATE, "no completed run");
+    const Buffer &b = app->ir.bufs[buf];
+    if (bytes < b.nbytes) return fail(OFL_E_ARG, "destination too small");
+    if (app->host_valid[buf]) {
+        // a host copy this run never touched still holds stale content from an
+        // earlier run when its restore was skipped: its true value is the set-up
+        if (!app->host_written[buf] && app->host_dirty[buf]) restore_host(app, buf);
+        std::memcpy(host_dst, app->host[buf], b.nbytes);
+        return OFL_OK;
+    }
+    hipError_t e = hipMemcpyAsync(host_dst, app->last_dev[buf], b.nbytes, hipMemcpyDeviceToHost, app->last_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(app->last_stream);
+    return e == hipSuccess ? OFL_OK : hip_fail(e, "read_buffer");
+}
+
+int ofl_set_kernel_timing(ofl_app *app, int32_t enable) {
+    if (!app) return fail(OFL_E_ARG, "null app");
+    app->timing = enable != 0;
+    if (app->timing) app->kstats.clear();
+    return OFL_OK;
+}
+
+int ofl_kernel_stats(const ofl_app *app, const char *op, int64_t *launches, double *total_ms) {
+    if (!app || !op) return fail(OFL_E_ARG, "null argument");
+    auto it = app->kstats.find(op);
+    if (launches) *launches = it == app->kstats.end() ? 0 : it->second.first;
+    if (total_ms) *total_ms = it == app->kstats.end() ? 0.0 : it->second.second;
+    return OFL_OK;
+}
+
+const char *ofl_status_str(int32_t code) {
+    switch (code) {
+    case OFL_OK: return "ok";
+    case OFL_E_ARG: return "invalid argument";
+    case OFL_E_IO: return "I/O error";
+    case OFL_E_PARSE: return "parse error";
+    case OFL_E_IR: return "invalid application";
+    case OFL_E_GENE_LEN: return "gene length mismatch";
+    case OFL_E_GENE_BIT: return "gene byte not 0/1";
+    case OFL_E_NOT_PARALLEL: return "nest not parallelisable";
+    case OFL_E_BUF: return "bad device buffer";
+    case OFL_E_HIP: return "HIP runtime error";
+    case OFL_E_TIMEOUT: return "deadline exceeded";
+    case OFL_E_MISMATCH: return "output mismatch";
+    case OFL_E_STATE: return "invalid state";
+    case OFL_E_NOMEM: return "out of memory";
+    case OFL_E_RANGE: return "index out of range";
+    default: return "unknown status";
+    }
+}
+
+const char *ofl_last_error(void) { return g_last_error.c_str(); }
+
+}  // extern "C"

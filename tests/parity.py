@@ -1,0 +1,80 @@
+"""Comparison of GPU-path outputs with the oracle.
+
+The bar, per buffer:
+* untouched by any GEMM (the random initialisation, the sweep field, element-
+  wise results of exact inputs): identical bits to the serial FP32 oracle;
+  FP64 sums (sweep residuals, sums of squares) whose GPU order differs: within
+  1e-12 relative of the oracle's serial sum;
+* downstream of a GEMM (whose MFMA accumulation order differs from the serial
+  one): within 1e-5 relative, element by element, of the oracle's FP64 twin;
+  bf16 results within one bf16 rounding (2^-8 relative) of the twin.
+"""
+import numpy as np
+
+from oracle import run as orun
+from oracle import xfer
+
+REL_GEMM = 1e-5
+REL_SUM = 1e-12
+
+
+def gemm_tainted(app_o):
+    tainted = set()
+    for ni in xfer.executions(app_o):
+        n = app_o.nests[ni]
+        reads, writes = xfer.nest_sets(app_o, n)
+        if n.op in ("gemm", "gemm_bf16") or any(b in tainted for b in reads):
+            tainted |= set(writes)
+    return tainted
+
+
+def oracle_outputs(app_o, seed, inputs=None, twin=True):
+    """(FP32 serial run, FP64 twin run) of the oracle with optional inputs."""
+    b32 = orun.setup_buffers(app_o)
+    b64 = orun.setup_buffers(app_o, twin=True) if twin else None
+    for name, arr in (inputs or {}).items():
+        b32[name][...] = arr
+        if twin:
+            b64[name][...] = arr
+    o32 = orun.run_app(app_o, seed, bufs=b32)
+    o64 = orun.run_app(app_o, seed, twin=True, bufs=b64) if twin else None
+    return o32, o64
+
+
+def _bits(a):
+    a = np.ascontiguousarray(a)
+    return a.view({4: np.uint32, 8: np.uint64, 2: np.uint16}[a.dtype.itemsize])
+
+
+def compare(app_o, got, o32, o64, names=None, rel_gemm=REL_GEMM):
+    """Return a list of failure strings (empty when everything matches)."""
+    bad = []
+    tainted = gemm_tainted(app_o)
+    for b, buf in enumerate(app_o.buffers):
+        if names is not None and buf.name not in names:
+            continue
+        g = np.asarray(got[buf.name])
+        if b not in tainted:
+            y = o32[buf.name]
+            if buf.dtype == "f64":
+                den = np.maximum(np.abs(y), 1e-300)
+                err = np.max(np.abs(g - y) / den) if g.size else 0.0
+                if err > REL_SUM:
+                    bad.append("%s: FP64 sum rel err %.3e > %.0e" % (buf.name, err, REL_SUM))
+            elif not np.array_equal(_bits(g), _bits(y)):
+                n = int(np.sum(_bits(g) != _bits(y)))
+                bad.append("%s: %d of %d elements differ from the serial oracle" % (buf.name, n, g.size))
+        else:
+            y = o64[buf.name]
+            if buf.dtype == "bf16":
+                gv = (g.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+                yv = (y.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+                err = np.max(np.abs(gv - yv) / np.maximum(np.abs(yv), 1e-30)) if g.size else 0.0
+                if err > 2.0 ** -8 + rel_gemm:
+                    bad.append("%s: bf16 rel err %.3e" % (buf.name, err))
+            else:
+                gv = g.astype(np.float64)
+                err = np.max(np.abs(gv - y) / np.maximum(np.abs(y), 1e-30)) if g.size else 0.0
+                if err > rel_gemm:
+                    bad.append("%s: rel err %.3e vs FP64 twin > %.0e" % (buf.name, err, rel_gemm))
+    return bad

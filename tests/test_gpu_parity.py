@@ -1,0 +1,247 @@
+"""GPU path vs the oracle, through the C ABI (needs an MI355X).
+
+Every case runs the application under a gene with ofl_run_pattern, reads the
+buffers back and compares them with the oracle's serial run (bits) or its
+FP64 twin (GEMM-dependent values), see tests/parity.py for the bar."""
+import json
+import random
+import sys
+
+import numpy as np
+import pytest
+
+import paper_1806_01430_amd as ofl
+import workloads
+from workloads import appgen
+from oracle import cnests as OC
+from oracle import ir
+
+import parity
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    yield
+
+
+def _run_and_compare(doc, genes, seed=1, inputs=None, policies=(ofl.RESIDENT,), flags_list=(0,), names=None):
+    app = ofl.App(json.dumps(doc), seed=seed)
+    o = ir.load(doc)
+    for name, arr in (inputs or {}).items():
+        app.set_input(name, arr)
+    o32, o64 = parity.oracle_outputs(o, seed, inputs)
+    bufs = app.alloc_device_buffers()
+    for g in genes:
+        for pol in policies:
+            for fl in flags_list:
+                say("case", doc["name"], doc["params"], "gene", list(g), "policy", pol, "flags", fl)
+                st = app.run_pattern(g, bufs, policy=pol, flags=fl)
+                assert st["status"] == ofl.ST_OK
+                assert (st["bytes_h2d"], st["bytes_d2h"], st["n_copies"]) == app.plan_transfers(g, pol, fl)
+                bad = parity.compare(o, app.read_all(), o32, o64, names=names)
+                assert not bad, (list(g), pol, fl, bad)
+    return app, bufs
+
+
+# ---------------------------------------------------------------- applications
+def test_tiny_all_64_genes():
+    doc = workloads.app_doc("tiny")
+    genes = [[(idx >> i) & 1 for i in range(6)] for idx in range(64)]
+    _run_and_compare(doc, genes)
+
+
+def test_tiny_policies_and_flags():
+    doc = workloads.app_doc("tiny")
+    genes = [[1] * 6, [0, 1, 0, 1, 0, 1], [1, 0, 1, 0, 1, 0]]
+    _run_and_compare(doc, genes, policies=(ofl.RESIDENT, ofl.PER_REGION),
+                     flags_list=(0, ofl.PRESTAGED, ofl.KEEP_OUTPUTS, ofl.PRESTAGED | ofl.KEEP_OUTPUTS))
+
+
+def test_medium_reduced_random_genes():
+    doc = workloads.app_doc("medium", **workloads.SMALL_MEDIUM)
+    rng = random.Random(1)
+    genes = [[1] * 10, [0] * 10] + [[rng.randint(0, 1) for _ in range(10)] for _ in range(10)]
+    _run_and_compare(doc, genes, seed=3, policies=(ofl.RESIDENT, ofl.PER_REGION))
+
+
+def test_large_reduced_random_genes():
+    doc = workloads.app_doc("large", **workloads.SMALL_LARGE)
+    rng = random.Random(2)
+    genes = [[1] * 13] + [[rng.randint(0, 1) for _ in range(13)] for _ in range(5)]
+    _run_and_compare(doc, genes, seed=5, flags_list=(0, ofl.PRESTAGED | ofl.KEEP_OUTPUTS))
+
+
+def test_repeated_runs_restore_inputs():
+    # consecutive runs with different genes must each start from the set-up
+    doc = workloads.app_doc("medium", **workloads.SMALL_MEDIUM)
+    genes = [[1] * 10, [0] * 10, [1] * 10, [1, 0] * 5, [1] * 10]
+    _run_and_compare(doc, genes, seed=2, flags_list=(ofl.PRESTAGED | ofl.KEEP_OUTPUTS, 0))
+
+
+def test_medium_full_size_all_gpu():
+    doc = workloads.app_doc("medium")
+    _run_and_compare(doc, [[1] * 10], seed=1, flags_list=(ofl.PRESTAGED | ofl.KEEP_OUTPUTS,))
+
+
+# ---------------------------------------------------------------- GEMM
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (17, 33, 5), (64, 64, 64), (130, 70, 37), (257, 129, 300),
+                                   (1000, 1000, 1000), (1024, 1024, 1024), (2048, 2048, 128)])
+def test_gemm_f32_shapes(M, N, K):
+    doc = appgen.gemm_app(M, N, K)
+    A = OC.init_uniform(M * K, 11, 0).reshape(M, K)
+    B = OC.init_uniform(K * N, 11, 1).reshape(K, N)
+    _run_and_compare(doc, [[1]], inputs={"A": A, "B": B})
+
+
+def test_gemm_f32_large_sampled():
+    # 4096^3 in the launch configuration of the large products: sampled rows
+    # against the FP64 twin (the full serial oracle would take minutes)
+    import torch
+    M = N = K = 4096
+    doc = appgen.gemm_app(M, N, K)
+    app = ofl.App(json.dumps(doc))
+    A = OC.init_uniform(M * K, 12, 0).reshape(M, K)
+    B = OC.init_uniform(K * N, 12, 1).reshape(K, N)
+    app.set_input("A", A)
+    app.set_input("B", B)
+    bufs = app.alloc_device_buffers()
+    say("case gemm 4096 sampled")
+    app.run_pattern([1], bufs, flags=ofl.KEEP_OUTPUTS)
+    C = app.read_buffer("C")
+    rows = np.random.default_rng(0).choice(M, 24, replace=False)
+    ref = OC.gemm_f64(np.ascontiguousarray(A[rows]), B)
+    err = np.max(np.abs(C[rows] - ref) / ref)
+    assert err < 1e-5, err
+    del torch
+
+
+def test_gemm_identity_and_rank1_exact():
+    for N in (64, 200, 1024):
+        doc = appgen.gemm_app(N, N, N)
+        B = OC.init_uniform(N * N, 3, 1).reshape(N, N)
+        app = ofl.App(json.dumps(doc))
+        app.set_input("A", np.eye(N, dtype=np.float32))
+        app.set_input("B", B)
+        bufs = app.alloc_device_buffers()
+        say("case gemm identity", N)
+        app.run_pattern([1], bufs)
+        assert np.array_equal(app.read_buffer("C"), B)
+        u = (np.arange(N) % 7 + 1).astype(np.float32)
+        v = (np.arange(N) % 5 + 1).astype(np.float32)
+        app.set_input("A", np.repeat(u[:, None], N, axis=1))
+        app.set_input("B", np.repeat(v[None, :], N, axis=0))
+        say("case gemm rank-1", N)
+        app.run_pattern([1], bufs)
+        assert np.array_equal(app.read_buffer("C"), (N * np.outer(u, v)).astype(np.float32))
+
+
+@pytest.mark.parametrize("M,N,K", [(16, 16, 32), (100, 70, 45), (512, 512, 512)])
+def test_gemm_bf16_shapes(M, N, K):
+    doc = appgen.gemm_app(M, N, K, op="gemm_bf16")
+    A = OC.cast_bf16(OC.init_uniform(M * K, 4, 0).reshape(M, K))
+    B = OC.cast_bf16(OC.init_uniform(K * N, 4, 1).reshape(K, N))
+    _run_and_compare(doc, [[1]], inputs={"A": A, "B": B})
+
+
+# ---------------------------------------------------------------- stencil
+@pytest.mark.parametrize("I,J,K,S", [(3, 3, 3, 2), (4, 5, 6, 3), (33, 33, 65, 10), (19, 23, 71, 4),
+                                     (5, 130, 300, 2), (70, 9, 64, 2), (10, 11, 127, 3), (129, 129, 257, 3)])
+def test_stencil_shapes(I, J, K, S):
+    _run_and_compare(appgen.stencil_app(I, J, K, S), [[1, 1], [1, 0], [0, 1]])
+
+
+def test_stencil_fixed_point_exact():
+    I, J, K = 21, 34, 133
+    ii, jj, kk = np.meshgrid(np.arange(I), np.arange(J), np.arange(K), indexing="ij")
+    field = (ii + 2 * jj + 3 * kk).astype(np.float32)
+    doc = appgen.stencil_app(I, J, K, 3)
+    app = ofl.App(json.dumps(doc))
+    app.set_input("p", field)
+    bufs = app.alloc_device_buffers()
+    say("case stencil fixed point")
+    app.run_pattern([1, 1], bufs)
+    inner = (slice(1, -1),) * 3
+    assert np.array_equal(app.read_buffer("p"), field)
+    assert np.array_equal(app.read_buffer("q")[inner], field[inner])
+    assert np.all(app.read_buffer("res") == 0.0)
+
+
+def test_stencil_eigenmode_decay():
+    I, J, K = 33, 33, 65
+    rows = [line.split() for line in open(workloads.ROOT + "/tests/golden/stencil_eigen.txt")
+            if not line.startswith("#")]
+    mu = [float(r[4]) for r in rows if r[:4] == ["33", "33", "65", "1"]][0]
+    doc = appgen.stencil_app(I, J, K, 10)
+    app = ofl.App(json.dumps(doc))
+    bufs = app.alloc_device_buffers()
+    app.run_pattern([1, 1], bufs)
+    _, p0 = OC.sin_field(I, J, K, 1, want64=True)
+    inner = (slice(1, -1),) * 3
+    err = np.max(np.abs(app.read_buffer("p")[inner] - mu ** 10 * p0[inner]))
+    assert err < 100 * 2.0 ** -24
+
+
+@pytest.mark.parametrize("I,J,K", [(257, 257, 513), (513, 513, 1025)])
+def test_stencil_full_size_one_sweep(I, J, K):
+    _run_and_compare(appgen.stencil_app(I, J, K, 1), [[1, 1]], flags_list=(ofl.PRESTAGED | ofl.KEEP_OUTPUTS,))
+
+
+# ---------------------------------------------------------------- element-wise
+@pytest.mark.parametrize("R,C", [(1, 1), (3, 5), (64, 64), (65, 127), (1000, 333), (2048, 2048)])
+def test_ewise_transpose_cast_sumsq(R, C):
+    _run_and_compare(appgen.ewise_app(R, C), [[1] * 8, [1, 0] * 4, [0, 1] * 4])
+
+
+# ---------------------------------------------------------------- runtime
+def test_deadline_abandons_run():
+    doc = workloads.app_doc("medium", **workloads.SMALL_MEDIUM)
+    app = ofl.App(json.dumps(doc))
+    bufs = app.alloc_device_buffers()
+    say("case deadline")
+    st = app.run_pattern([0] * 10, bufs, deadline_s=1e-6, check=False)
+    assert st["rc"] == -10 and st["status"] == ofl.ST_TIMEOUT
+    with pytest.raises(ofl.OflError):
+        app.read_buffer("C")
+    st = app.run_pattern([1] * 10, bufs)
+    assert st["status"] == ofl.ST_OK
+
+
+def test_kernel_timing_and_bad_buffers():
+    doc = workloads.app_doc("tiny")
+    app = ofl.App(json.dumps(doc))
+    bufs = app.alloc_device_buffers()
+    app.set_kernel_timing(True)
+    app.run_pattern([1] * 6, bufs)
+    n, ms = app.kernel_stats("stencil19")
+    assert n == 10 and ms > 0
+    n, ms = app.kernel_stats("gemm")
+    assert n == 1 and ms > 0
+    with pytest.raises(ofl.OflError) as ei:
+        app.run_pattern([1] * 6, bufs[:-1])
+    assert ei.value.code == -8
+
+
+def test_eval_population_and_ga_tiny():
+    doc = workloads.app_doc("tiny")
+    app = ofl.App(json.dumps(doc))
+    bufs = app.alloc_device_buffers()
+    genes = [[(idx >> i) & 1 for i in range(6)] for idx in range(64)]
+    say("case eval population 64")
+    t, s = app.eval_population(genes, bufs, reps=3, warmup=1)
+    assert np.all(s == ofl.ST_OK) and np.all(t > 0)
+    best_idx = int(np.argmin(t))
+    say("case GA tiny 4x3")
+    res = app.ga_run(ofl.ga_params(M=4, T=3, seed=1, reps=3, warmup=1), bufs)
+    assert res["n_generations"] == 3
+    assert len(res["best_gene"]) == 6
+    assert res["best_time"] > 0
+    rank = int(np.sum(t < t[sum(b << i for i, b in enumerate(res["best_gene"]))]))
+    say("GA best gene", res["best_gene"], "exhaustive best", genes[best_idx], "rank", rank)

@@ -1,0 +1,216 @@
+"""The C-ABI library's host logic against the oracle, on the CPU (no GPU call):
+parallelisability verdicts, transfer plans, the GA under an injected time
+table, and the error paths of the boundary."""
+import json
+import os
+import random
+import re
+
+import numpy as np
+import pytest
+
+import paper_1806_01430_amd as ofl
+import workloads
+from oracle import depcheck as D
+from oracle import enum as E
+from oracle import ga as G
+from oracle import ir, xfer
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_library_exports_every_declared_symbol():
+    with open(os.path.join(ROOT, "include", "ofl.h")) as f:
+        text = f.read()
+    declared = set(re.findall(r"\b(ofl_[a-z0-9_]+)\s*\(", text))
+    assert declared == set(ofl.EXPORTS)
+    L = ofl.lib()
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_status_strings():
+    L = ofl.lib()
+    assert L.ofl_status_str(0) == b"ok"
+    for code in ofl.E:
+        assert L.ofl_status_str(code) != b"unknown status"
+
+
+@pytest.mark.parametrize("name", ["tiny", "medium", "precision", "large"])
+def test_verdicts_match_oracle(name):
+    app = ofl.App(workloads.app_path(name))
+    o = ir.load(workloads.app_path(name))
+    assert app.n_nests == len(o.nests)
+    assert app.gene_len == D.gene_length(o)
+    assert app.verdicts() == [tuple(v) for v in D.check_app(o)]
+    assert [app.nest_name(i) for i in range(app.n_nests)] == [n.name for n in o.nests]
+    for b, buf in enumerate(o.buffers):
+        assert app.buf_name(b) == buf.name
+        assert app.buf_dims(b) == tuple(buf.dims)
+        assert app.buf_info(b)[0] == buf.nbytes
+        assert app.buf_info(b)[2] == buf.output
+
+
+def test_random_nests_match_oracle():
+    rng = random.Random(99)
+    seen = set()
+    for _ in range(300):
+        doc = workloads.random_nest_doc(rng)
+        o = ir.load(doc)
+        app = ofl.App(json.dumps(doc))
+        want = tuple(D.check_app(o)[0])
+        assert app.nest_info(0) == want, doc
+        seen.add(want[0])
+    assert seen == {D.PARALLEL, D.REJECT}
+
+
+def test_random_nests_with_flags_and_reductions():
+    rng = random.Random(7)
+    for t in range(100):
+        doc = workloads.random_nest_doc(rng)
+        nest = doc["program"][0]
+        if t % 3 == 0:
+            nest["access"].append(["Y", "sum"] + ["0"] * len(doc["buffers"][1]["dims"]))
+        if t % 5 == 0:
+            nest["flags"] = [rng.choice(["opaque_call", "early_exit"])]
+        if t % 7 == 0:
+            doc["program"] = [{"repeat": "3", "var": "n", "body": [nest]}]
+        o = ir.load(doc)
+        app = ofl.App(json.dumps(doc))
+        assert app.nest_info(0) == tuple(D.check_app(o)[0]), doc
+
+
+def test_plans_tiny_all_genes_match_oracle():
+    app = ofl.App(workloads.app_path("tiny"))
+    o = ir.load(workloads.app_path("tiny"))
+    for flags in (0, ofl.PRESTAGED, ofl.KEEP_OUTPUTS, ofl.PRESTAGED | ofl.KEEP_OUTPUTS):
+        for g, res, per in E.enumerate_plans(o, flags):
+            assert app.plan_transfers(g, ofl.RESIDENT, flags) == res
+            assert app.plan_transfers(g, ofl.PER_REGION, flags) == per
+
+
+@pytest.mark.parametrize("name", ["medium", "large"])
+def test_plans_random_genes_match_oracle(name):
+    app = ofl.App(workloads.app_path(name))
+    o = ir.load(workloads.app_path(name))
+    v = D.check_app(o)
+    rng = random.Random(3)
+    for _ in range(80):
+        g = tuple(rng.randint(0, 1) for _ in range(app.gene_len))
+        pl = xfer.placement_of_gene(o, v, g)
+        for pol in (xfer.RESIDENT, xfer.PER_REGION):
+            for flags in (0, 3):
+                assert app.plan_transfers(g, pol, flags) == xfer.totals(o, pl, pol, flags)
+
+
+def test_mask_to_gene():
+    app = ofl.App(workloads.app_path("medium"))
+    v = app.verdicts()
+    mask = [1 if x[0] != ofl.REJECT else 0 for x in v]
+    assert app.mask_to_gene(mask) == tuple([1] * app.gene_len)
+    bad = [1] * app.n_nests
+    with pytest.raises(ofl.OflError) as ei:
+        app.mask_to_gene(bad)
+    assert ei.value.code == -7
+
+
+def test_gene_errors():
+    app = ofl.App(workloads.app_path("tiny"))
+    with pytest.raises(ofl.OflError) as ei:
+        app.plan_transfers([1] * 5)
+    assert ei.value.code == -5
+    with pytest.raises(ofl.OflError) as ei:
+        app.plan_transfers([1, 0, 2, 0, 0, 0])
+    assert ei.value.code == -6
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda d: d.update(program="x"), -3),
+    (lambda d: d["program"][1].update(op="fft"), -4),
+    (lambda d: d["program"][1]["access"].append(["A", "r", "i+70", "k"]), -4),
+    (lambda d: d["program"][1]["access"].append(["A", "r", "i*2", "k"]), -3),
+    (lambda d: d["buffers"][0].update(dims=["N", "N", "N"]), -4),
+    (lambda d: d["program"][2]["args"].update(A="nope"), -4),
+    (lambda d: d["program"][1]["args"].update(prec="fp4"), -4),
+])
+def test_invalid_applications(mutate, code):
+    doc = workloads.app_doc("tiny")
+    mutate(doc)
+    with pytest.raises(ofl.OflError) as ei:
+        ofl.App(json.dumps(doc))
+    assert ei.value.code == code
+
+
+def test_malformed_json_and_missing_file():
+    with pytest.raises(ofl.OflError) as ei:
+        ofl.App('{"name": "x", "buffers": [ }')
+    assert ei.value.code == -3
+    with pytest.raises(ofl.OflError) as ei:
+        ofl.App("/nonexistent/app.json")
+    assert ei.value.code == -2
+
+
+def test_accepted_host_only_op_is_invalid():
+    # a recurrence body declared with parallel-looking accesses has no kernel
+    doc = workloads.app_doc("medium")
+    for nest in doc["program"]:
+        if nest.get("op") == "rec_prefix":
+            nest["access"] = [["v", "w", "i"], ["S", "r", "i", "0"]]
+    with pytest.raises(ofl.OflError) as ei:
+        ofl.App(json.dumps(doc))
+    assert ei.value.code == -4
+
+
+# ------------------------------------------------------------ GA parity
+def _oracle_ga(a, params, table, status=None):
+    return G.run_ga(a, params.M, params.T, G.table_evaluator(table, status), Pc=params.Pc, Pm=params.Pm,
+                    p=params.p, seed=params.seed, deadline_factor=params.deadline_factor)
+
+
+@pytest.mark.parametrize("a,M,T,Pc,Pm,p,seed,dl", [
+    (6, 4, 3, 0.9, 0.05, 0.5, 1, 0.0),
+    (6, 12, 12, 0.9, 0.05, 0.5, 7, 0.0),
+    (10, 20, 20, 0.9, 0.05, 1.0, 3, 0.0),
+    (13, 30, 20, 0.9, 0.05, 0.5, 11, 3.0),
+    (1, 3, 4, 0.9, 0.5, 0.5, 2, 0.0),
+    (5, 7, 6, 0.0, 0.0, 0.5, 5, 0.0),
+    (5, 8, 6, 1.0, 1.0, 0.5, 6, 2.0),
+    (12, 12, 12, 0.9, 0.05, 0.5, 2018, 0.0),
+])
+def test_ga_trajectory_matches_oracle(a, M, T, Pc, Pm, p, seed, dl):
+    table = workloads.time_table(a, seed * 31 + a, lo=0.01, hi=5.0)
+    params = ofl.ga_params(M=M, T=T, Pc=Pc, Pm=Pm, p=p, seed=seed, deadline_factor=dl)
+    got = ofl.ga_run_table(a, params, table)
+    want = _oracle_ga(a, params, table)
+    assert got["n_generations"] == len(want["generations"])
+    for gi, gen in enumerate(want["generations"]):
+        assert [tuple(int(x) for x in g) for g in got["pops"][gi]] == list(gen["pop"])
+        assert list(got["times"][gi]) == gen["time"]
+        assert list(got["status"][gi]) == gen["status"]
+    assert got["best_gene"] == want["best_gene"]
+    assert got["best_time"] == want["best_time"]
+    assert got["n_measured"] == want["n_measured"]
+    if dl > 0:
+        assert got["t_all0"] == want["t_all0"]
+
+
+def test_ga_with_failed_statuses_matches_oracle():
+    a = 6
+    rng = random.Random(4)
+    table = workloads.time_table(a, 5)
+    status = [G.ST_FAILED if rng.random() < 0.3 else G.ST_OK for _ in range(1 << a)]
+    params = ofl.ga_params(M=8, T=6, seed=9)
+    got = ofl.ga_run_table(a, params, table, status)
+    want = _oracle_ga(a, params, table, status)
+    for gi, gen in enumerate(want["generations"]):
+        assert [tuple(int(x) for x in g) for g in got["pops"][gi]] == list(gen["pop"])
+        assert list(got["status"][gi]) == gen["status"]
+    assert got["best_gene"] == want["best_gene"]
+
+
+def test_ga_table_argument_errors():
+    params = ofl.ga_params(M=0)
+    with pytest.raises(ofl.OflError):
+        ofl.ga_run_table(3, params, np.ones(8))
+    with pytest.raises(ofl.OflError):
+        ofl.ga_run_table(3, ofl.ga_params(Pc=1.5), np.ones(8))

@@ -1,17 +1,19 @@
-"""Writes the application descriptions (tiny / medium / precision / large).
+"""Builders of application descriptions (tiny / medium / precision / large and
+single-nest test applications); ``python -m workloads.appgen`` rewrites the
+JSON files under paper_1806_01430_amd/apps/.
 
 Each application is a program of for-loop nests over arrays, the input the
 offloader works on (Sec. 4 of the paper: the source is parsed and every for
 statement found).  The JSON holds the parsed form: loops with bounds, affine
 array accesses, the body kind (``op``) with its arguments, and ``repeat``
-blocks for the iterated sweep.  Run ``python make_apps.py`` to regenerate.
+blocks for the iterated sweep.
 
 Shapes: matrices are row-major N x N; grids are p[i][j][k] with k contiguous.
 """
 import json
 import os
 
-HERE = os.path.dirname(os.path.abspath(__file__))
+HERE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1806_01430_amd", "apps")
 
 ALL2 = [["i", "0", "N"], ["j", "0", "N"]]
 
@@ -189,6 +191,48 @@ def large():
 
 
 APPS = {"tiny": tiny, "medium": medium, "precision": precision, "large": large}
+
+
+# ---------------------------------------------------------------- test apps
+def gemm_app(M, N, K, op="gemm"):
+    """One GEMM nest C[M][N] = A[M][K] B[K][N] with caller-supplied A, B."""
+    dt = "bf16" if op == "gemm_bf16" else "f32"
+    nest = gemm_nest("A", "B", "C", op=op)
+    nest["loops"] = [["i", "0", "M"], ["j", "0", "NN"], ["k", "0", "KK"]]
+    return {"name": "gemm", "params": {"M": M, "NN": N, "KK": K},
+            "buffers": [{"name": "A", "dtype": dt, "dims": ["M", "KK"]},
+                        {"name": "B", "dtype": dt, "dims": ["KK", "NN"]},
+                        {"name": "C", "dtype": "f32", "dims": ["M", "NN"], "output": True}],
+            "program": [nest]}
+
+
+def stencil_app(I, J, K, sweeps, mode=1):
+    """The iterated sweep alone on an I x J x K grid (sine set-up unless the
+    caller supplies p)."""
+    return {"name": "stencil", "params": {"I": I, "J": J, "K": K, "SWEEPS": sweeps, "MODE": mode},
+            "buffers": [grid("p", "sin", True), grid("q", "zero", True),
+                        {"name": "res", "dtype": "f64", "dims": ["SWEEPS"], "output": True}],
+            "program": [sweep_block()]}
+
+
+def ewise_app(R, Cc):
+    """Element-wise nests, transpose, cast and reduction on R x Cc matrices."""
+    def m(name, dims=("R", "CC"), dtype="f32"):
+        return {"name": name, "dtype": dtype, "dims": list(dims), "output": True}
+    L2 = [["i", "0", "R"], ["j", "0", "CC"]]
+
+    def on(n):
+        n = json.loads(json.dumps(n))
+        n["loops"] = L2
+        return n
+    tr = transpose_nest("C", "T")
+    tr["loops"] = L2
+    return {"name": "ewise", "params": {"R": R, "CC": Cc},
+            "buffers": [m("A"), m("C"), m("T", ("CC", "R")), m("S"), m("D"), m("Cb", dtype="bf16"),
+                        {"name": "s", "dtype": "f64", "dims": ["1"], "output": True}],
+            "program": [on(init_nest(["A", "C"], [0, 1])), on(add_scaled_nest("C", "A", 0.5)), tr,
+                        on(avg2_nest("S", "C", "A")), on(copy_nest("D", "S")), on(scale_nest("D", 2.0)),
+                        on(cast_nest(["Cb"], ["D"])), on(sumsq_nest("S", "s"))]}
 
 
 def main():
