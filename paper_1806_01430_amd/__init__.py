@@ -84,6 +84,10 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise RuntimeError("libofl.so is not built: run `python -m paper_1806_01430_amd.build`")
+        # torch ships its own HIP runtime with the same soname; loading torch
+        # first makes libofl bind to that one, so the process holds a single
+        # runtime whichever module the caller imported first
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         sig = {
             "ofl_app_load": (_I, [ctypes.c_char_p, ctypes.c_uint64, ctypes.POINTER(_P)]),

@@ -12,7 +12,7 @@
 // Mapping (gfx950, wave64): a work item is 64 consecutive k (lanes 1..62
 // produce outputs, lanes 0 and 63 only supply the k-1 / k+1 neighbours), JR
 // consecutive rows j and a run of IC planes along i.  A wave marches along i
-// holding a, x, y of three planes in registers, with the next PD planes
+// holding a, x, y of three planes in registers, with the next three planes
 // already in flight in a register ring: every element of p is loaded once per
 // work item (plus two halo rows and two halo planes), the k neighbours arrive
 // through DPP lane shifts, and no LDS is used.  Waves loop over work items
@@ -23,6 +23,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <mutex>
+#include <type_traits>
 
 #include "dev_common.hpp"
 #include "kernels.hpp"
@@ -50,96 +51,118 @@ struct Geo {
     int IC;                 // planes per work item
     int nkt, njt, nic;      // work items along k, j, i
     int items;              // nkt * njt * nic
+    int bytes;              // size of p (and q) in bytes, < 2^31
 };
 
-template <int JR, int PD>
+constexpr int kBufferConfig = 0x00020000;   // raw buffer resource, gfx9 family
+
+__device__ inline float buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+// One sweep.  Work item w (jt fastest, then kt, then ic) covers rows
+// jb .. jb+JR-1, the 62 output columns of k-tile kt and planes [ib, ie).
+// Plane sets P[0..2] hold a, x, y of planes i-1, i, i+1 with roles rotating
+// every step (the i-loop is unrolled by three, so no register moves); the ring
+// holds the next three raw planes in flight.  Loads are raw buffer loads with
+// the wave-uniform row offset in a scalar register; the loop body has no
+// branches: a load past the end of the array reads 0 and a store whose offset
+// is past the end is dropped (raw buffer range check), so the refills are
+// unconditional (no register copies or full waits at the loop edge) and
+// outputs that must not be written get an out-of-range offset.
+constexpr int kOutOfRange = 0x40000000;
+
+template <int JR>
 __global__ __launch_bounds__(kThreads) void k_stencil19(const float *__restrict__ p, float *__restrict__ q, Geo g,
                                                         double *res_slot, double *partials, unsigned *counter) {
+    constexpr int R = JR + 2;
     const int lane = threadIdx.x & (kWave - 1);
-    const int gwave = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    const int nwaves = gridDim.x * kWavesPerBlock;
+    // blocks are dealt to the 8 XCDs round-robin: renumber them so that one
+    // XCD takes a contiguous run of work items (neighbouring j-runs share
+    // their halo rows in that XCD's L2); gridDim.x is a multiple of 8
+    const int nb = gridDim.x;
+    const int lb = (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8;
+    const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int nwaves = nb * kWavesPerBlock;
     const int J = g.J, K = g.K;
-    const size_t plane = (size_t)J * K;
+    const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, g.bytes, kBufferConfig);
+    const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc((void *)q, (short)0, g.bytes, kBufferConfig);
     double acc = 0.0;
 
-    for (int w = gwave; w < g.items; w += nwaves) {
+    for (int w = lb * kWavesPerBlock + wib; w < g.items; w += nwaves) {
         const int jt = w % g.njt;
         const int rest = w / g.njt;
         const int kt = rest % g.nkt;
         const int ic = rest / g.nkt;
         const int k = kt * kOut + lane;             // lane 0 holds k-1 of the first output
-        const bool kin = k < K;
+        const int voff = k * 4;
         const bool kout = lane >= 1 && lane <= kOut && k <= K - 2;
         const int jb = 1 + jt * JR;                 // first output row
         const int ib = 1 + ic * g.IC;
         const int ie = min(ib + g.IC, g.I - 1);     // exclusive; ib < ie by construction
+        const int jlast = J - 2 - jb;               // rows r <= jlast are interior
 
-        float am[JR], a0[JR], ap[JR], xm[JR], x0[JR], xp[JR], y0[JR], yp[JR];
-        float ring[PD][JR + 2];
+        float Pa[3][JR], Px[3][JR], Py[3][JR];
+        float ring[3][R];
 
-        auto load = [&](int i, float (&v)[JR + 2]) {
-            const float *base = p + (size_t)i * plane + (size_t)(jb - 1) * K + k;
+        auto load = [&](int i, float (&v)[R]) {
+            const int base = ((i * J + jb - 1) * K) * 4;
 #pragma unroll
-            for (int r = 0; r < JR + 2; ++r)
-                v[r] = (kin && jb - 1 + r < J) ? base[(size_t)r * K] : 0.0f;
+            for (int r = 0; r < R; ++r) v[r] = buf_load(rp, voff, base + r * K * 4);
         };
-        auto derive = [&](const float (&v)[JR + 2], float (&a)[JR], float (&x)[JR], float (&y)[JR]) {
-            float vl[JR + 2], vr[JR + 2];
+        auto derive = [&](const float (&v)[R], float (&a)[JR], float (&x)[JR], float (&y)[JR]) {
+            float h[R];                             // p[j][k-1] + p[j][k+1] per row
 #pragma unroll
-            for (int r = 0; r < JR + 2; ++r) {
-                vl[r] = from_left(v[r]);
-                vr[r] = from_right(v[r]);
-            }
+            for (int r = 0; r < R; ++r) h[r] = from_left(v[r]) + from_right(v[r]);
 #pragma unroll
             for (int r = 0; r < JR; ++r) {
                 a[r] = v[r + 1];
-                x[r] = (v[r] + v[r + 2]) + (vl[r + 1] + vr[r + 1]);
-                y[r] = (vl[r] + vr[r]) + (vl[r + 2] + vr[r + 2]);
+                x[r] = (v[r] + v[r + 2]) + h[r + 1];
+                y[r] = h[r] + h[r + 2];
+            }
+        };
+        auto step = [&](auto S, int i) {
+            constexpr int s = decltype(S)::value;
+            constexpr int m = s, c = (s + 1) % 3, n = (s + 2) % 3;
+            // keep each step's use of its ring slot in place: hoisting the
+            // later slots' use to the loop top would wait for the newest loads
+            __builtin_amdgcn_sched_barrier(0);
+            derive(ring[s], Pa[n], Px[n], Py[n]);            // plane i+1
+            // the refill must not start before the slot's old value is consumed,
+            // or old and new value need separate registers (a copy per iteration)
+            __builtin_amdgcn_sched_barrier(0);
+            load(i + 4, ring[s]);
+            const bool plane_ok = i < ie;
+#pragma unroll
+            for (int r = 0; r < JR; ++r) {
+                const float F = (Pa[m][r] + Pa[n][r]) + Px[c][r];
+                const float E = (Px[m][r] + Px[n][r]) + Py[c][r];
+                const float t0 = 0.25f * Pa[c][r];
+                const float t1 = 0.0625f * F;
+                const float t2 = 0.03125f * E;
+                const float v = (t0 + t1) + t2;
+                const bool ok = kout && plane_ok && r <= jlast;
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rq, ok ? voff : kOutOfRange,
+                                                      ((i * J + jb + r) * K) * 4, 0);
+                const double d = (double)v - (double)Pa[c][r];
+                acc = __builtin_fma(ok ? d : 0.0, d, acc);
             }
         };
 
         {
-            float raw[JR + 2], ydummy[JR];
-            load(ib - 1, raw);
-#pragma unroll
-            for (int s = 0; s < PD; ++s)
-                if (ib + 1 + s <= ie) load(ib + 1 + s, ring[s]);
-            derive(raw, am, xm, ydummy);
-            load(ib, raw);
-            derive(raw, a0, x0, y0);
+            float r0[R], r1[R];
+            load(ib - 1, r0);
+            load(ib, r1);
+            load(ib + 1, ring[0]);
+            load(ib + 2, ring[1]);
+            load(ib + 3, ring[2]);
+            derive(r0, Pa[0], Px[0], Py[0]);
+            derive(r1, Pa[1], Px[1], Py[1]);
         }
-        for (int i0 = ib; i0 < ie; i0 += PD) {
-#pragma unroll
-            for (int s = 0; s < PD; ++s) {
-                const int i = i0 + s;
-                if (i < ie) {
-                    derive(ring[s], ap, xp, yp);                    // plane i+1
-                    if (i + 1 + PD <= ie) load(i + 1 + PD, ring[s]);
-                    float *qrow = q + (size_t)i * plane + (size_t)jb * K + k;
-#pragma unroll
-                    for (int r = 0; r < JR; ++r) {
-                        const float F = (am[r] + ap[r]) + x0[r];
-                        const float E = (xm[r] + xp[r]) + y0[r];
-                        const float t0 = 0.25f * a0[r];
-                        const float t1 = 0.0625f * F;
-                        const float t2 = 0.03125f * E;
-                        const float v = (t0 + t1) + t2;
-                        if (kout && jb + r <= J - 2) {
-                            __builtin_nontemporal_store(v, qrow + (size_t)r * K);
-                            const double d = (double)v - (double)a0[r];
-                            acc = acc + d * d;
-                        }
-                    }
-#pragma unroll
-                    for (int r = 0; r < JR; ++r) {
-                        am[r] = a0[r];
-                        a0[r] = ap[r];
-                        xm[r] = x0[r];
-                        x0[r] = xp[r];
-                        y0[r] = yp[r];
-                    }
-                }
-            }
+        for (int i0 = ib; i0 < ie; i0 += 3) {
+            step(std::integral_constant<int, 0>(), i0);
+            step(std::integral_constant<int, 1>(), i0 + 1);
+            step(std::integral_constant<int, 2>(), i0 + 2);
         }
     }
     reduce_finish(acc, partials, counter, res_slot);
@@ -170,12 +193,12 @@ __global__ __launch_bounds__(kThreads) void k_copy_interior(float *__restrict__ 
 }
 
 struct Config {
-    int JR, PD;
+    int JR;
     Geo g;
     unsigned blocks;
 };
 
-int resident_blocks_per_cu(int JR, int PD);
+int resident_blocks_per_cu(int JR);
 
 int cu_count() {
     static std::once_flag once;
@@ -189,88 +212,83 @@ int cu_count() {
     return n;
 }
 
-// Tuning knob: OFL_STENCIL_CFG="JR,PD,IC" overrides the choice (JR in {2,4,8},
-// PD in {1,2,3}); used by the tuning sweeps.
-bool env_override(int &JR, int &PD, int &IC) {
+// Tuning knob: OFL_STENCIL_CFG="JR,IC" overrides the choice (JR in {2,4,8},
+// IC planes per work item, 0 = automatic); used by tuning sweeps.
+bool env_override(int &JR, int &IC) {
     const char *s = std::getenv("OFL_STENCIL_CFG");
     if (!s) return false;
-    int a, b, c;
-    if (std::sscanf(s, "%d,%d,%d", &a, &b, &c) != 3) return false;
-    if (!((a == 2 || a == 4 || a == 8) && b >= 1 && b <= 3 && c >= 1)) return false;
+    int a, b;
+    if (std::sscanf(s, "%d,%d", &a, &b) != 2) return false;
+    if (!((a == 2 || a == 4 || a == 8) && b >= 0)) return false;
     JR = a;
-    PD = b;
-    IC = c;
+    IC = b;
     return true;
 }
 
+// Work items sized so that every resident wave gets one (no tail round):
+// long i-runs on large grids (two halo planes per run are negligible), more
+// and shorter runs on small grids.
 Config choose(int64_t I, int64_t J, int64_t K) {
     Config c;
     const int64_t ni = I - 2, nj = J - 2;
-    int JR, PD, IC;
-    if (!env_override(JR, PD, IC)) {
-        // large grids: long i-runs (halo planes negligible) and deep prefetch;
-        // small grids: short runs so that enough work items exist
+    int JR = 0, IC = 0;
+    if (!env_override(JR, IC)) {
         const int64_t pts = ni * nj * (K - 2);
-        if (pts >= (int64_t)32 << 20) {
-            JR = 8;
-            PD = 2;
-            IC = 32;
-        } else {
-            JR = 4;
-            PD = 2;
-            IC = 8;
-        }
+        JR = pts >= ((int64_t)32 << 20) ? 8 : 4;
+        IC = 0;
     }
-    if (IC > ni) IC = (int)ni;
     c.JR = JR;
-    c.PD = PD;
     c.g.I = (int)I;
     c.g.J = (int)J;
     c.g.K = (int)K;
-    c.g.IC = IC;
+    c.g.bytes = (int)(I * J * K * 4);
     c.g.nkt = (int)((K - 2 + kOut - 1) / kOut);
     c.g.njt = (int)((nj + JR - 1) / JR);
+    const int64_t per_plane_run = (int64_t)c.g.nkt * c.g.njt;
+    const int64_t resident_blocks = (int64_t)cu_count() * resident_blocks_per_cu(JR);
+    const int64_t resident_waves = resident_blocks * kWavesPerBlock;
+    if (IC <= 0) {
+        int64_t nic = resident_waves / per_plane_run;
+        if (nic < 1) nic = 1;
+        if (nic > ni) nic = ni;
+        IC = (int)((ni + nic - 1) / nic);
+        IC = (IC + 2) / 3 * 3;   // the i-loop advances three planes at a time
+    }
+    if (IC > ni) IC = (int)ni;
+    c.g.IC = IC;
     c.g.nic = (int)((ni + IC - 1) / IC);
-    c.g.items = c.g.nkt * c.g.njt * c.g.nic;
-    const int64_t blocks_needed = ((int64_t)c.g.items + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int64_t slots = (int64_t)cu_count() * resident_blocks_per_cu(JR, PD);
-    c.blocks = (unsigned)(blocks_needed < slots ? blocks_needed : slots);
-    if (c.blocks < 1) c.blocks = 1;
+    c.g.items = (int)(per_plane_run * c.g.nic);
+    int64_t blocks = ((int64_t)c.g.items + kWavesPerBlock - 1) / kWavesPerBlock;
+    if (blocks > resident_blocks) blocks = resident_blocks;
+    blocks = (blocks + 7) / 8 * 8;
+    c.blocks = (unsigned)blocks;
     return c;
 }
 
-template <int JR, int PD>
+template <int JR>
 hipError_t launch_t(const Config &c, const float *p, float *q, double *res_slot, const ReduceScratch &rs,
                     hipStream_t s) {
-    hipLaunchKernelGGL((k_stencil19<JR, PD>), dim3(c.blocks), dim3(kThreads), 0, s, p, q, c.g, res_slot,
-                       rs.partials, rs.counter);
+    hipLaunchKernelGGL((k_stencil19<JR>), dim3(c.blocks), dim3(kThreads), 0, s, p, q, c.g, res_slot, rs.partials,
+                       rs.counter);
     return hipGetLastError();
 }
 
-template <int JR, int PD>
+template <int JR>
 int occupancy_t() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_stencil19<JR, PD>, kThreads, 0) != hipSuccess || n < 1)
-        n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_stencil19<JR>, kThreads, 0) != hipSuccess || n < 1) n = 1;
     return n;
 }
 
-int resident_blocks_per_cu(int JR, int PD) {
+int resident_blocks_per_cu(int JR) {
     static std::once_flag once;
-    static int table[3][3];
+    static int table[3];
     std::call_once(once, [] {
-        table[0][0] = occupancy_t<2, 1>();
-        table[0][1] = occupancy_t<2, 2>();
-        table[0][2] = occupancy_t<2, 3>();
-        table[1][0] = occupancy_t<4, 1>();
-        table[1][1] = occupancy_t<4, 2>();
-        table[1][2] = occupancy_t<4, 3>();
-        table[2][0] = occupancy_t<8, 1>();
-        table[2][1] = occupancy_t<8, 2>();
-        table[2][2] = occupancy_t<8, 3>();
+        table[0] = occupancy_t<2>();
+        table[1] = occupancy_t<4>();
+        table[2] = occupancy_t<8>();
     });
-    const int r = JR == 2 ? 0 : JR == 4 ? 1 : 2;
-    return table[r][PD - 1];
+    return table[JR == 2 ? 0 : JR == 4 ? 1 : 2];
 }
 
 }  // namespace
@@ -278,23 +296,21 @@ int resident_blocks_per_cu(int JR, int PD) {
 int64_t stencil_partials(int64_t I, int64_t J, int64_t K) {
     if (I < 3 || J < 3 || K < 3) return 1;
     // upper bound over every configuration the launcher may choose: one block
-    // per resident slot, at most 2048 threads per CU
-    return (int64_t)cu_count() * (2048 / kThreads);
+    // per resident slot (at most 2048 threads per CU), rounded up to 8
+    return (int64_t)cu_count() * (2048 / kThreads) + 8;
 }
 
 hipError_t stencil19(const float *p, float *q, int64_t I, int64_t J, int64_t K, double *res_slot,
                      const ReduceScratch &rs, hipStream_t s) {
     if (I < 3 || J < 3 || K < 3) return hipSuccess;   // no interior: nothing written, residual unchanged
-    if (J * K >= (1ll << 31) || I >= (1ll << 31)) return hipErrorInvalidValue;
+    // byte offsets are 32-bit buffer offsets; the loop reads up to five planes
+    // past the end and marks dropped stores with an extra 2^30
+    if ((I + 6) * J * K * 4 >= (1ll << 31) - (1ll << 30)) return hipErrorInvalidValue;
     const Config c = choose(I, J, K);
     if ((int64_t)c.blocks > rs.capacity) return hipErrorInvalidValue;
-#define OFL_STENCIL_CASE(jr, pd) \
-    if (c.JR == jr && c.PD == pd) return launch_t<jr, pd>(c, p, q, res_slot, rs, s);
-    OFL_STENCIL_CASE(2, 1) OFL_STENCIL_CASE(2, 2) OFL_STENCIL_CASE(2, 3)
-    OFL_STENCIL_CASE(4, 1) OFL_STENCIL_CASE(4, 2) OFL_STENCIL_CASE(4, 3)
-    OFL_STENCIL_CASE(8, 1) OFL_STENCIL_CASE(8, 2) OFL_STENCIL_CASE(8, 3)
-#undef OFL_STENCIL_CASE
-    return hipErrorInvalidValue;
+    if (c.JR == 8) return launch_t<8>(c, p, q, res_slot, rs, s);
+    if (c.JR == 4) return launch_t<4>(c, p, q, res_slot, rs, s);
+    return launch_t<2>(c, p, q, res_slot, rs, s);
 }
 
 hipError_t copy_interior(float *p, const float *q, int64_t I, int64_t J, int64_t K, hipStream_t s) {
