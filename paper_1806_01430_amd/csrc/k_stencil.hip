@@ -56,21 +56,23 @@ struct Geo {
 
 constexpr int kBufferConfig = 0x00020000;   // raw buffer resource, gfx9 family
 
-__device__ inline float buf_load(__amdgpu_buffer_rsrc_t r, int voff, int soff) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+// The whole byte offset goes in the per-lane (VGPR) operand with a zero SGPR
+// offset: the raw-buffer range check covers the VGPR offset, so an access
+// at or past num_records reads 0 / is dropped and never touches memory.
+__device__ inline float buf_load(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
 // One sweep.  Work item w (jt fastest, then kt, then ic) covers rows
 // jb .. jb+JR-1, the 62 output columns of k-tile kt and planes [ib, ie).
 // Plane sets P[0..2] hold a, x, y of planes i-1, i, i+1 with roles rotating
 // every step (the i-loop is unrolled by three, so no register moves); the ring
-// holds the next three raw planes in flight.  Loads are raw buffer loads with
-// the wave-uniform row offset in a scalar register; the loop body has no
-// branches: a load past the end of the array reads 0 and a store whose offset
-// is past the end is dropped (raw buffer range check), so the refills are
-// unconditional (no register copies or full waits at the loop edge) and
-// outputs that must not be written get an out-of-range offset.
-constexpr int kOutOfRange = 0x40000000;
+// holds the next three raw planes in flight.  Loads are raw buffer loads; the
+// loop body has no branches: loads beyond the work item are clamped into the
+// array (their values feed no stored output), so refills are unconditional,
+// and a store that must not happen gets an offset past num_records, which the
+// raw-buffer range check drops.
+constexpr int kOutOfRange = (int)0x80000000u;
 
 template <int JR>
 __global__ __launch_bounds__(kThreads) void k_stencil19(const float *__restrict__ p, float *__restrict__ q, Geo g,
@@ -96,6 +98,7 @@ __global__ __launch_bounds__(kThreads) void k_stencil19(const float *__restrict_
         const int ic = rest / g.nkt;
         const int k = kt * kOut + lane;             // lane 0 holds k-1 of the first output
         const int voff = k * 4;
+        const int kld = min(k, K - 1) * 4;          // loads stay inside the row
         const bool kout = lane >= 1 && lane <= kOut && k <= K - 2;
         const int jb = 1 + jt * JR;                 // first output row
         const int ib = 1 + ic * g.IC;
@@ -105,10 +108,12 @@ __global__ __launch_bounds__(kThreads) void k_stencil19(const float *__restrict_
         float Pa[3][JR], Px[3][JR], Py[3][JR];
         float ring[3][R];
 
+        // every load offset lies inside the array: planes past the last and
+        // rows past the last are clamped (those values feed no stored output)
         auto load = [&](int i, float (&v)[R]) {
-            const int base = ((i * J + jb - 1) * K) * 4;
+            const int ii = min(i, g.I - 1);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[r] = buf_load(rp, voff, base + r * K * 4);
+            for (int r = 0; r < R; ++r) v[r] = buf_load(rp, ((ii * J + min(jb - 1 + r, J - 1)) * K) * 4 + kld);
         };
         auto derive = [&](const float (&v)[R], float (&a)[JR], float (&x)[JR], float (&y)[JR]) {
             float h[R];                             // p[j][k-1] + p[j][k+1] per row
@@ -142,8 +147,8 @@ __global__ __launch_bounds__(kThreads) void k_stencil19(const float *__restrict_
                 const float t2 = 0.03125f * E;
                 const float v = (t0 + t1) + t2;
                 const bool ok = kout && plane_ok && r <= jlast;
-                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rq, ok ? voff : kOutOfRange,
-                                                      ((i * J + jb + r) * K) * 4, 0);
+                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rq,
+                                                      ok ? ((i * J + jb + r) * K) * 4 + voff : kOutOfRange, 0, 0);
                 const double d = (double)v - (double)Pa[c][r];
                 acc = __builtin_fma(ok ? d : 0.0, d, acc);
             }
@@ -303,9 +308,9 @@ int64_t stencil_partials(int64_t I, int64_t J, int64_t K) {
 hipError_t stencil19(const float *p, float *q, int64_t I, int64_t J, int64_t K, double *res_slot,
                      const ReduceScratch &rs, hipStream_t s) {
     if (I < 3 || J < 3 || K < 3) return hipSuccess;   // no interior: nothing written, residual unchanged
-    // byte offsets are 32-bit buffer offsets; the loop reads up to five planes
-    // past the end and marks dropped stores with an extra 2^30
-    if ((I + 6) * J * K * 4 >= (1ll << 31) - (1ll << 30)) return hipErrorInvalidValue;
+    // byte offsets are non-negative 32-bit ints: the loop may form offsets up
+    // to five planes past the end (read as 0); dropped stores use 2^31
+    if ((I + 6) * J * K * 4 >= (1ll << 31)) return hipErrorInvalidValue;
     const Config c = choose(I, J, K);
     if ((int64_t)c.blocks > rs.capacity) return hipErrorInvalidValue;
     if (c.JR == 8) return launch_t<8>(c, p, q, res_slot, rs, s);
