@@ -92,10 +92,13 @@ __global__ __launch_bounds__(kThreads) void k_stencil19(const float *__restrict_
     double acc = 0.0;
 
     for (int w = lb * kWavesPerBlock + wib; w < g.items; w += nwaves) {
-        const int jt = w % g.njt;
-        const int rest = w / g.njt;
-        const int kt = rest % g.nkt;
-        const int ic = rest / g.nkt;
+        // k-tile fastest: the waves of a block take neighbouring k-tiles of
+        // the same rows in lockstep, so the cache lines a tile boundary
+        // straddles are fetched once and hit in L1 for the other wave
+        const int kt = w % g.nkt;
+        const int rest = w / g.nkt;
+        const int jt = rest % g.njt;
+        const int ic = rest / g.njt;
         const int k = kt * kOut + lane;             // lane 0 holds k-1 of the first output
         const int voff = k * 4;
         const int kld = min(k, K - 1) * 4;          // loads stay inside the row
@@ -134,9 +137,10 @@ __global__ __launch_bounds__(kThreads) void k_stencil19(const float *__restrict_
             __builtin_amdgcn_sched_barrier(0);
             derive(ring[s], Pa[n], Px[n], Py[n]);            // plane i+1
             // the refill must not start before the slot's old value is consumed,
-            // or old and new value need separate registers (a copy per iteration)
+            // or old and new value need separate registers (a copy per iteration);
+            // past the run's last plane it re-reads that plane (an L1 hit)
             __builtin_amdgcn_sched_barrier(0);
-            load(i + 4, ring[s]);
+            load(min(i + 4, ie), ring[s]);
             const bool plane_ok = i < ie;
 #pragma unroll
             for (int r = 0; r < JR; ++r) {
@@ -159,8 +163,8 @@ __global__ __launch_bounds__(kThreads) void k_stencil19(const float *__restrict_
             load(ib - 1, r0);
             load(ib, r1);
             load(ib + 1, ring[0]);
-            load(ib + 2, ring[1]);
-            load(ib + 3, ring[2]);
+            load(min(ib + 2, ie), ring[1]);
+            load(min(ib + 3, ie), ring[2]);
             derive(r0, Pa[0], Px[0], Py[0]);
             derive(r1, Pa[1], Px[1], Py[1]);
         }
@@ -173,26 +177,52 @@ __global__ __launch_bounds__(kThreads) void k_stencil19(const float *__restrict_
     reduce_finish(acc, partials, counter, res_slot);
 }
 
-// p[i][j][k] = q[i][j][k] on the interior: one wave per row (i, j), 16-byte
-// accesses on the aligned middle of the row, single elements at its ends.
+// p[i][j][k] = q[i][j][k] on the interior: a wave copies kRows consecutive
+// rows (i, j) at a time, issuing all their loads before any store; 16-byte
+// accesses on the aligned middle of each row, single elements at its ends.
+constexpr int kRows = 4;
+
 __global__ __launch_bounds__(kThreads) void k_copy_interior(float *__restrict__ p, const float *__restrict__ q,
                                                             int I, int J, int K) {
     const int lane = threadIdx.x & (kWave - 1);
     const int gwave = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     const int nwaves = gridDim.x * kWavesPerBlock;
     const int rows = (I - 2) * (J - 2);
-    for (int row = gwave; row < rows; row += nwaves) {
-        const int i = 1 + row / (J - 2), j = 1 + row % (J - 2);
-        const size_t base = ((size_t)i * J + j) * K;
-        const size_t lo = base + 1, hi = base + K - 1;        // [lo, hi)
-        const size_t a0 = (lo + 3) & ~(size_t)3, a1 = hi & ~(size_t)3;
-        if (a0 < a1) {
-            for (size_t e = a0 + 4 * (size_t)lane; e < a1; e += 4 * kWave)
-                *reinterpret_cast<float4 *>(p + e) = *reinterpret_cast<const float4 *>(q + e);
-            if (lo + lane < a0) p[lo + lane] = q[lo + lane];
-            if (a1 + lane < hi) p[a1 + lane] = q[a1 + lane];
-        } else {
-            for (size_t e = lo + lane; e < hi; e += kWave) p[e] = q[e];
+    const int vec_per_row = (K + 3) / 4;       // upper bound of 16-byte groups in a row
+    for (int row0 = gwave * kRows; row0 < rows; row0 += nwaves * kRows) {
+        size_t lo[kRows], a0[kRows], a1[kRows], hi[kRows];
+#pragma unroll
+        for (int t = 0; t < kRows; ++t) {
+            const int row = min(row0 + t, rows - 1);
+            const int i = 1 + row / (J - 2), j = 1 + row % (J - 2);
+            const size_t base = ((size_t)i * J + j) * K;
+            lo[t] = base + 1;
+            hi[t] = base + K - 1;                 // [lo, hi)
+            a0[t] = (lo[t] + 3) & ~(size_t)3;
+            a1[t] = hi[t] & ~(size_t)3;
+            if (a1[t] < a0[t]) a1[t] = a0[t];
+        }
+        for (int v = lane; v < vec_per_row; v += kWave) {
+            float4 buf[kRows];
+#pragma unroll
+            for (int t = 0; t < kRows; ++t) {
+                const size_t e = a0[t] + 4 * (size_t)v;
+                if (row0 + t < rows && e < a1[t]) buf[t] = *reinterpret_cast<const float4 *>(q + e);
+            }
+#pragma unroll
+            for (int t = 0; t < kRows; ++t) {
+                const size_t e = a0[t] + 4 * (size_t)v;
+                if (row0 + t < rows && e < a1[t]) *reinterpret_cast<float4 *>(p + e) = buf[t];
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < kRows; ++t) {
+            if (row0 + t >= rows) continue;
+            // ends of the row: [lo, a0) and [a1, hi), at most 3 elements each,
+            // or the whole row when it holds no aligned group
+            const size_t e0 = lo[t] + lane, e1 = a1[t] + lane;
+            if (e0 < a0[t] && e0 < hi[t]) p[e0] = q[e0];
+            if (e1 < hi[t] && e1 >= a0[t]) p[e1] = q[e1];
         }
     }
 }
@@ -238,8 +268,7 @@ Config choose(int64_t I, int64_t J, int64_t K) {
     const int64_t ni = I - 2, nj = J - 2;
     int JR = 0, IC = 0;
     if (!env_override(JR, IC)) {
-        const int64_t pts = ni * nj * (K - 2);
-        JR = pts >= ((int64_t)32 << 20) ? 8 : 4;
+        JR = 8;
         IC = 0;
     }
     c.JR = JR;
@@ -257,6 +286,9 @@ Config choose(int64_t I, int64_t J, int64_t K) {
         if (nic < 1) nic = 1;
         if (nic > ni) nic = ni;
         IC = (int)((ni + nic - 1) / nic);
+        // runs shorter than 12 planes spend too much on their two halo planes
+        // and their start-up loads
+        if (IC < 12) IC = 12;
         IC = (IC + 2) / 3 * 3;   // the i-loop advances three planes at a time
     }
     if (IC > ni) IC = (int)ni;
@@ -322,7 +354,7 @@ hipError_t copy_interior(float *p, const float *q, int64_t I, int64_t J, int64_t
     if (I < 3 || J < 3 || K < 3) return hipSuccess;
     if ((I - 2) * (J - 2) >= (1ll << 31)) return hipErrorInvalidValue;
     const int64_t rows = (I - 2) * (J - 2);
-    int64_t blocks = (rows + kWavesPerBlock - 1) / kWavesPerBlock;
+    int64_t blocks = (rows + kWavesPerBlock * kRows - 1) / (kWavesPerBlock * kRows);
     if (blocks > (int64_t)cu_count() * 16) blocks = (int64_t)cu_count() * 16;
     hipLaunchKernelGGL(k_copy_interior, dim3((unsigned)blocks), dim3(kThreads), 0, s, p, q, (int)I, (int)J, (int)K);
     return hipGetLastError();
