@@ -178,8 +178,10 @@ __global__ __launch_bounds__(kThreads) void k_stencil19(const float *__restrict_
 }
 
 // p[i][j][k] = q[i][j][k] on the interior: a wave copies kRows consecutive
-// rows (i, j) at a time, issuing all their loads before any store; 16-byte
-// accesses on the aligned middle of each row, single elements at its ends.
+// rows (i, j) at a time.  Each row splits into a head [lo, a0) and a tail
+// [a1, hi) of at most three elements and a 16-byte aligned middle [a0, a1);
+// a pass moves up to 64 middle groups of every row plus the heads and tails,
+// with all loads of the pass issued before its stores.
 constexpr int kRows = 4;
 
 __global__ __launch_bounds__(kThreads) void k_copy_interior(float *__restrict__ p, const float *__restrict__ q,
@@ -188,41 +190,44 @@ __global__ __launch_bounds__(kThreads) void k_copy_interior(float *__restrict__ 
     const int gwave = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     const int nwaves = gridDim.x * kWavesPerBlock;
     const int rows = (I - 2) * (J - 2);
-    const int vec_per_row = (K + 3) / 4;       // upper bound of 16-byte groups in a row
+    const int passes = ((K - 2) / 4 + kWave) / kWave;   // >= ceil(groups / 64), groups <= (K-2)/4
     for (int row0 = gwave * kRows; row0 < rows; row0 += nwaves * kRows) {
         size_t lo[kRows], a0[kRows], a1[kRows], hi[kRows];
+        bool live[kRows];
 #pragma unroll
         for (int t = 0; t < kRows; ++t) {
-            const int row = min(row0 + t, rows - 1);
+            live[t] = row0 + t < rows;
+            const int row = live[t] ? row0 + t : rows - 1;
             const int i = 1 + row / (J - 2), j = 1 + row % (J - 2);
             const size_t base = ((size_t)i * J + j) * K;
             lo[t] = base + 1;
             hi[t] = base + K - 1;                 // [lo, hi)
             a0[t] = (lo[t] + 3) & ~(size_t)3;
             a1[t] = hi[t] & ~(size_t)3;
-            if (a1[t] < a0[t]) a1[t] = a0[t];
+            if (a1[t] < a0[t]) a1[t] = a0[t];     // no aligned group: all in head / tail
         }
-        for (int v = lane; v < vec_per_row; v += kWave) {
-            float4 buf[kRows];
+        for (int pass = 0; pass < passes; ++pass) {
+            float4 mid[kRows];
+            float hd[kRows], tl[kRows];
+            bool mok[kRows], hok[kRows], tok[kRows];
 #pragma unroll
             for (int t = 0; t < kRows; ++t) {
-                const size_t e = a0[t] + 4 * (size_t)v;
-                if (row0 + t < rows && e < a1[t]) buf[t] = *reinterpret_cast<const float4 *>(q + e);
+                const size_t e = a0[t] + 4 * (size_t)(pass * kWave + lane);
+                const size_t eh = lo[t] + lane, et = a1[t] + lane;
+                mok[t] = live[t] && e < a1[t];
+                hok[t] = live[t] && pass == 0 && eh < a0[t] && eh < hi[t];
+                tok[t] = live[t] && pass == 0 && et < hi[t] && et >= a0[t];
+                if (mok[t]) mid[t] = *reinterpret_cast<const float4 *>(q + e);
+                if (hok[t]) hd[t] = q[eh];
+                if (tok[t]) tl[t] = q[et];
             }
 #pragma unroll
             for (int t = 0; t < kRows; ++t) {
-                const size_t e = a0[t] + 4 * (size_t)v;
-                if (row0 + t < rows && e < a1[t]) *reinterpret_cast<float4 *>(p + e) = buf[t];
+                const size_t e = a0[t] + 4 * (size_t)(pass * kWave + lane);
+                if (mok[t]) *reinterpret_cast<float4 *>(p + e) = mid[t];
+                if (hok[t]) p[lo[t] + lane] = hd[t];
+                if (tok[t]) p[a1[t] + lane] = tl[t];
             }
-        }
-#pragma unroll
-        for (int t = 0; t < kRows; ++t) {
-            if (row0 + t >= rows) continue;
-            // ends of the row: [lo, a0) and [a1, hi), at most 3 elements each,
-            // or the whole row when it holds no aligned group
-            const size_t e0 = lo[t] + lane, e1 = a1[t] + lane;
-            if (e0 < a0[t] && e0 < hi[t]) p[e0] = q[e0];
-            if (e1 < hi[t] && e1 >= a0[t]) p[e1] = q[e1];
         }
     }
 }
