@@ -180,8 +180,11 @@ __global__ __launch_bounds__(kThreads) void k_stencil19(const float *__restrict_
 // p[i][j][k] = q[i][j][k] on the interior: a wave copies kRows consecutive
 // rows (i, j) at a time.  Each row splits into a head [lo, a0) and a tail
 // [a1, hi) of at most three elements and a 16-byte aligned middle [a0, a1);
-// a pass moves up to 64 middle groups of every row plus the heads and tails,
-// with all loads of the pass issued before its stores.
+// a pass moves up to 64 middle groups of every row plus the heads and tails.
+// Raw buffer accesses without branches: every load reads a valid element
+// (element 0 when the lane has nothing to move), so all loads of a pass
+// overlap, and a store that must not happen carries an offset past
+// num_records, which the range check drops.
 constexpr int kRows = 4;
 
 __global__ __launch_bounds__(kThreads) void k_copy_interior(float *__restrict__ p, const float *__restrict__ q,
@@ -190,43 +193,45 @@ __global__ __launch_bounds__(kThreads) void k_copy_interior(float *__restrict__ 
     const int gwave = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
     const int nwaves = gridDim.x * kWavesPerBlock;
     const int rows = (I - 2) * (J - 2);
+    const int bytes = I * J * K * 4;
+    const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc((void *)q, (short)0, bytes, kBufferConfig);
+    const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, bytes, kBufferConfig);
     const int passes = ((K - 2) / 4 + kWave) / kWave;   // >= ceil(groups / 64), groups <= (K-2)/4
     for (int row0 = gwave * kRows; row0 < rows; row0 += nwaves * kRows) {
-        size_t lo[kRows], a0[kRows], a1[kRows], hi[kRows];
+        int lo[kRows], a0[kRows], a1[kRows], hi[kRows];
         bool live[kRows];
 #pragma unroll
         for (int t = 0; t < kRows; ++t) {
             live[t] = row0 + t < rows;
             const int row = live[t] ? row0 + t : rows - 1;
             const int i = 1 + row / (J - 2), j = 1 + row % (J - 2);
-            const size_t base = ((size_t)i * J + j) * K;
+            const int base = (i * J + j) * K;
             lo[t] = base + 1;
             hi[t] = base + K - 1;                 // [lo, hi)
-            a0[t] = (lo[t] + 3) & ~(size_t)3;
-            a1[t] = hi[t] & ~(size_t)3;
+            a0[t] = (lo[t] + 3) & ~3;
+            a1[t] = hi[t] & ~3;
             if (a1[t] < a0[t]) a1[t] = a0[t];     // no aligned group: all in head / tail
         }
         for (int pass = 0; pass < passes; ++pass) {
-            float4 mid[kRows];
-            float hd[kRows], tl[kRows];
-            bool mok[kRows], hok[kRows], tok[kRows];
+            __attribute__((ext_vector_type(4))) unsigned mid[kRows];
+            unsigned hd[kRows], tl[kRows];
+            int om[kRows], oh[kRows], ot[kRows];
 #pragma unroll
             for (int t = 0; t < kRows; ++t) {
-                const size_t e = a0[t] + 4 * (size_t)(pass * kWave + lane);
-                const size_t eh = lo[t] + lane, et = a1[t] + lane;
-                mok[t] = live[t] && e < a1[t];
-                hok[t] = live[t] && pass == 0 && eh < a0[t] && eh < hi[t];
-                tok[t] = live[t] && pass == 0 && et < hi[t] && et >= a0[t];
-                if (mok[t]) mid[t] = *reinterpret_cast<const float4 *>(q + e);
-                if (hok[t]) hd[t] = q[eh];
-                if (tok[t]) tl[t] = q[et];
+                const int em = a0[t] + 4 * (pass * kWave + lane);
+                const int eh = lo[t] + lane, et = a1[t] + lane;
+                om[t] = (live[t] && em < a1[t]) ? em * 4 : -1;
+                oh[t] = (live[t] && pass == 0 && eh < a0[t] && eh < hi[t]) ? eh * 4 : -1;
+                ot[t] = (live[t] && pass == 0 && et < hi[t] && et >= a0[t]) ? et * 4 : -1;
+                mid[t] = __builtin_amdgcn_raw_buffer_load_b128(rq, om[t] < 0 ? 0 : om[t], 0, 0);
+                hd[t] = __builtin_amdgcn_raw_buffer_load_b32(rq, oh[t] < 0 ? 0 : oh[t], 0, 0);
+                tl[t] = __builtin_amdgcn_raw_buffer_load_b32(rq, ot[t] < 0 ? 0 : ot[t], 0, 0);
             }
 #pragma unroll
             for (int t = 0; t < kRows; ++t) {
-                const size_t e = a0[t] + 4 * (size_t)(pass * kWave + lane);
-                if (mok[t]) *reinterpret_cast<float4 *>(p + e) = mid[t];
-                if (hok[t]) p[lo[t] + lane] = hd[t];
-                if (tok[t]) p[a1[t] + lane] = tl[t];
+                __builtin_amdgcn_raw_buffer_store_b128(mid[t], rp, om[t] < 0 ? kOutOfRange : om[t], 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b32(hd[t], rp, oh[t] < 0 ? kOutOfRange : oh[t], 0, 0);
+                __builtin_amdgcn_raw_buffer_store_b32(tl[t], rp, ot[t] < 0 ? kOutOfRange : ot[t], 0, 0);
             }
         }
     }
@@ -357,7 +362,7 @@ hipError_t stencil19(const float *p, float *q, int64_t I, int64_t J, int64_t K, 
 
 hipError_t copy_interior(float *p, const float *q, int64_t I, int64_t J, int64_t K, hipStream_t s) {
     if (I < 3 || J < 3 || K < 3) return hipSuccess;
-    if ((I - 2) * (J - 2) >= (1ll << 31)) return hipErrorInvalidValue;
+    if (I * J * K * 4 >= (1ll << 31)) return hipErrorInvalidValue;   // 32-bit buffer offsets
     const int64_t rows = (I - 2) * (J - 2);
     int64_t blocks = (rows + kWavesPerBlock * kRows - 1) / (kWavesPerBlock * kRows);
     if (blocks > (int64_t)cu_count() * 16) blocks = (int64_t)cu_count() * 16;
