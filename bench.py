@@ -125,6 +125,23 @@ def run_kernels_large(args):
     return out
 
 
+def calibration_copy():
+    """A plain copy nest of known size (1 GiB read, 1 GiB written), run once:
+    the reference against which rocprofv3's FETCH_SIZE / WRITE_SIZE readings
+    of the other kernels are scaled."""
+    import paper_1806_01430_amd as ofl
+    from workloads import appgen
+
+    n = 1 << 14
+    doc = {"name": "copy1GiB", "params": {"N": n},
+           "buffers": [{"name": "C", "dims": ["N", "N"]}, {"name": "D", "dims": ["N", "N"], "output": True}],
+           "program": [appgen.copy_nest("D", "C")]}
+    app = ofl.App(json.dumps(doc))
+    bufs = app.alloc_device_buffers("cuda:0")
+    app.run_pattern([1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
+    del app, bufs
+
+
 def cpu_baseline():
     """The oracle's serial run of the medium application (the all-CPU gene),
     one host core."""
@@ -149,6 +166,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the 513^3-class stencil / 8192 GEMM lines")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="first run a plain 1 GiB copy kernel (reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -159,6 +178,10 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
+    if args.calibration_copy:
+        log("bench: calibration copy (1 GiB)")
+        calibration_copy()
+        torch.cuda.empty_cache()
     log("bench: medium app, %d warmup + %d timed steps" % (args.warmup, args.steps))
     r = run_medium(args)
     P = r["params"]

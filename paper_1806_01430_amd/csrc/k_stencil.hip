@@ -270,9 +270,8 @@ bool env_override(int &JR, int &IC) {
     return true;
 }
 
-// Work items sized so that every resident wave gets one (no tail round):
-// long i-runs on large grids (two halo planes per run are negligible), more
-// and shorter runs on small grids.
+// Work items: JR = 8 rows, i-runs of IC planes; the grid holds at most one
+// block per resident slot and waves loop over the items.
 Config choose(int64_t I, int64_t J, int64_t K) {
     Config c;
     const int64_t ni = I - 2, nj = J - 2;
@@ -290,16 +289,11 @@ Config choose(int64_t I, int64_t J, int64_t K) {
     c.g.njt = (int)((nj + JR - 1) / JR);
     const int64_t per_plane_run = (int64_t)c.g.nkt * c.g.njt;
     const int64_t resident_blocks = (int64_t)cu_count() * resident_blocks_per_cu(JR);
-    const int64_t resident_waves = resident_blocks * kWavesPerBlock;
     if (IC <= 0) {
-        int64_t nic = resident_waves / per_plane_run;
-        if (nic < 1) nic = 1;
-        if (nic > ni) nic = ni;
-        IC = (int)((ni + nic - 1) / nic);
-        // runs shorter than 12 planes spend too much on their two halo planes
-        // and their start-up loads
-        if (IC < 12) IC = 12;
-        IC = (IC + 2) / 3 * 3;   // the i-loop advances three planes at a time
+        // measured on gfx950 (129^3-, 257^3- and 513^3-class grids): runs of
+        // 48 planes (a few work items per resident wave) on grids with at
+        // least 192 interior planes, 12 planes below that
+        IC = ni >= 192 ? 48 : 12;
     }
     if (IC > ni) IC = (int)ni;
     c.g.IC = IC;
