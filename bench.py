@@ -166,6 +166,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-large", action="store_true", help="skip the 513^3-class stencil / 8192 GEMM lines")
+    ap.add_argument("--large-only", action="store_true",
+                    help="only the 513x513x1025 stencil and 8192 GEMM kernel lines (for profiling)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first run a plain 1 GiB copy kernel (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -178,6 +180,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
+    if args.large_only:
+        print(json.dumps({"kernels_large": run_kernels_large(args)}), flush=True)
+        return
     if args.calibration_copy:
         log("bench: calibration copy (1 GiB)")
         calibration_copy()

@@ -5,6 +5,7 @@
 
 #include "dev_common.hpp"
 #include "kernels.hpp"
+#include "launch.hpp"
 
 namespace ofl {
 namespace k {
@@ -189,59 +190,51 @@ hipError_t fill_zero(void *dst, uint64_t bytes, hipStream_t s) {
     if (bytes == 0) return hipSuccess;
     const int64_t n16 = (int64_t)(bytes / 16);
     const int ntail = (int)(bytes - (uint64_t)n16 * 16);
-    hipLaunchKernelGGL(k_fill_zero, dim3(grid_for(n16 > 0 ? n16 : 1, 4)), dim3(kThreads), 0, s,
+    return launch(k_fill_zero, dim3(grid_for(n16 > 0 ? n16 : 1, 4)), dim3(kThreads), 0, s,
                        static_cast<uint4 *>(dst), n16, static_cast<unsigned char *>(dst) + n16 * 16, ntail);
-    return hipGetLastError();
 }
 
 hipError_t init_uniform(float *x, int64_t n, uint64_t key, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_init_uniform, dim3(grid_for(n / 4 + 1, 2)), dim3(kThreads), 0, s, x, n, key);
-    return hipGetLastError();
+    return launch(k_init_uniform, dim3(grid_for(n / 4 + 1, 2)), dim3(kThreads), 0, s, x, n, key);
 }
 
 hipError_t add_scaled(float *C, const float *A, float alpha, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_add_scaled, dim3(grid_for(n / 4 + 1, 4)), dim3(kThreads), 0, s, C, A, alpha, n);
-    return hipGetLastError();
+    return launch(k_add_scaled, dim3(grid_for(n / 4 + 1, 4)), dim3(kThreads), 0, s, C, A, alpha, n);
 }
 
 hipError_t avg2(float *S, const float *X, const float *Y, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_avg2, dim3(grid_for(n / 4 + 1, 4)), dim3(kThreads), 0, s, S, X, Y, n);
-    return hipGetLastError();
+    return launch(k_avg2, dim3(grid_for(n / 4 + 1, 4)), dim3(kThreads), 0, s, S, X, Y, n);
 }
 
 hipError_t scale(float *D, float beta, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_scale, dim3(grid_for(n / 4 + 1, 4)), dim3(kThreads), 0, s, D, beta, n);
-    return hipGetLastError();
+    return launch(k_scale, dim3(grid_for(n / 4 + 1, 4)), dim3(kThreads), 0, s, D, beta, n);
 }
 
 hipError_t copy_bytes(void *dst, const void *src, uint64_t bytes, hipStream_t s) {
     if (bytes == 0) return hipSuccess;
     const int64_t n16 = (int64_t)(bytes / 16);
     const int ntail = (int)(bytes - (uint64_t)n16 * 16);
-    hipLaunchKernelGGL(k_copy16, dim3(grid_for(n16 > 0 ? n16 : 1, 4)), dim3(kThreads), 0, s,
+    return launch(k_copy16, dim3(grid_for(n16 > 0 ? n16 : 1, 4)), dim3(kThreads), 0, s,
                        static_cast<uint4 *>(dst), static_cast<const uint4 *>(src), n16,
                        static_cast<unsigned char *>(dst) + n16 * 16,
                        static_cast<const unsigned char *>(src) + n16 * 16, ntail);
-    return hipGetLastError();
 }
 
 hipError_t cast_bf16(uint16_t *dst, const float *src, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_cast_bf16, dim3(grid_for(n / 4 + 1, 4)), dim3(kThreads), 0, s,
+    return launch(k_cast_bf16, dim3(grid_for(n / 4 + 1, 4)), dim3(kThreads), 0, s,
                        reinterpret_cast<unsigned short *>(dst), src, n);
-    return hipGetLastError();
 }
 
 hipError_t transpose(const float *X, float *T, int64_t R, int64_t Cc, hipStream_t s) {
     if (R <= 0 || Cc <= 0) return hipSuccess;
     dim3 grid((unsigned)((Cc + kTile - 1) / kTile), (unsigned)((R + kTile - 1) / kTile));
     if (grid.y > 65535) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_transpose, grid, dim3(kThreads), 0, s, X, T, R, Cc);
-    return hipGetLastError();
+    return launch(k_transpose, grid, dim3(kThreads), 0, s, X, T, R, Cc);
 }
 
 int64_t sumsq_partials(int64_t n) { return grid_for(n / 4 + 1, 8); }
@@ -249,8 +242,7 @@ int64_t sumsq_partials(int64_t n) { return grid_for(n / 4 + 1, 8); }
 hipError_t sumsq(const float *x, int64_t n, double *s_out, const ReduceScratch &rs, hipStream_t s) {
     const unsigned blocks = (unsigned)sumsq_partials(n);
     if ((int64_t)blocks > rs.capacity) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_sumsq, dim3(blocks), dim3(kThreads), 0, s, x, n, s_out, rs.partials, rs.counter);
-    return hipGetLastError();
+    return launch(k_sumsq, dim3(blocks), dim3(kThreads), 0, s, x, n, s_out, rs.partials, rs.counter);
 }
 
 }  // namespace k

@@ -16,6 +16,7 @@
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
+#include "launch.hpp"
 
 namespace ofl {
 namespace k {
@@ -222,10 +223,9 @@ hipError_t launch_f32(const float *A, const float *B, float *C, int M, int N, in
     const unsigned tiles = (unsigned)(((M + BM - 1) / BM) * ((N + BN - 1) / BN));
     const bool vec = (K % 4 == 0) && (N % 4 == 0);
     if (vec)
-        hipLaunchKernelGGL((k_gemm_f32<BM, BN, BK, true>), dim3(tiles), dim3(kThreads), 0, s, A, B, C, M, N, K);
+        return launch((k_gemm_f32<BM, BN, BK, true>), dim3(tiles), dim3(kThreads), 0, s, A, B, C, M, N, K);
     else
-        hipLaunchKernelGGL((k_gemm_f32<BM, BN, BK, false>), dim3(tiles), dim3(kThreads), 0, s, A, B, C, M, N, K);
-    return hipGetLastError();
+        return launch((k_gemm_f32<BM, BN, BK, false>), dim3(tiles), dim3(kThreads), 0, s, A, B, C, M, N, K);
 }
 
 }  // namespace
@@ -245,10 +245,9 @@ hipError_t gemm_bf16(const uint16_t *A, const uint16_t *B, float *C, int64_t M, 
     if (K <= 0) return fill_zero(C, (uint64_t)M * N * sizeof(float), s);
     if (M > (1 << 30) || N > (1 << 30) || K > (1 << 30)) return hipErrorInvalidValue;
     const unsigned tiles = (unsigned)(((M + 63) / 64) * ((N + 63) / 64));
-    hipLaunchKernelGGL((k_gemm_bf16<64, 64>), dim3(tiles), dim3(kThreads), 0, s,
+    return launch((k_gemm_bf16<64, 64>), dim3(tiles), dim3(kThreads), 0, s,
                        reinterpret_cast<const unsigned short *>(A), reinterpret_cast<const unsigned short *>(B), C,
                        (int)M, (int)N, (int)K);
-    return hipGetLastError();
 }
 
 }  // namespace k

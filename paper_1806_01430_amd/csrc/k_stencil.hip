@@ -27,6 +27,7 @@
 
 #include "dev_common.hpp"
 #include "kernels.hpp"
+#include "launch.hpp"
 
 namespace ofl {
 namespace k {
@@ -309,9 +310,8 @@ Config choose(int64_t I, int64_t J, int64_t K) {
 template <int JR>
 hipError_t launch_t(const Config &c, const float *p, float *q, double *res_slot, const ReduceScratch &rs,
                     hipStream_t s) {
-    hipLaunchKernelGGL((k_stencil19<JR>), dim3(c.blocks), dim3(kThreads), 0, s, p, q, c.g, res_slot, rs.partials,
+    return launch((k_stencil19<JR>), dim3(c.blocks), dim3(kThreads), 0, s, p, q, c.g, res_slot, rs.partials,
                        rs.counter);
-    return hipGetLastError();
 }
 
 template <int JR>
@@ -360,8 +360,7 @@ hipError_t copy_interior(float *p, const float *q, int64_t I, int64_t J, int64_t
     const int64_t rows = (I - 2) * (J - 2);
     int64_t blocks = (rows + kWavesPerBlock * kRows - 1) / (kWavesPerBlock * kRows);
     if (blocks > (int64_t)cu_count() * 16) blocks = (int64_t)cu_count() * 16;
-    hipLaunchKernelGGL(k_copy_interior, dim3((unsigned)blocks), dim3(kThreads), 0, s, p, q, (int)I, (int)J, (int)K);
-    return hipGetLastError();
+    return launch(k_copy_interior, dim3((unsigned)blocks), dim3(kThreads), 0, s, p, q, (int)I, (int)J, (int)K);
 }
 
 }  // namespace k

@@ -18,6 +18,7 @@
 #include "host_nests.hpp"
 #include "ir.hpp"
 #include "kernels.hpp"
+#include "launch.hpp"
 #include "plan.hpp"
 
 using namespace ofl;
@@ -347,14 +348,19 @@ RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *co
         case ST_GPU: {
             const Nest &n = ir.nests[step.idx];
             const bool tm = app->timing && ev_next + 2 <= app->events.size();
-            if (tm) (void)hipEventRecord(app->events[ev_next], stream);
+            // a single-launch nest gets its events in the dispatch packet itself
+            // (kernel-only interval); a multi-launch nest is bracketed by events
+            const bool single = kernel_launch_count(n) == 1;
+            if (tm && single) k::arm_launch_events(app->events[ev_next], app->events[ev_next + 1]);
+            if (tm && !single) (void)hipEventRecord(app->events[ev_next], stream);
             e = launch_nest(app, n, dev, plan.env.data() + step.env, stream);
+            k::arm_launch_events(nullptr, nullptr);
             if (e != hipSuccess) {
                 rr.code = hip_fail(e, (std::string("launch of nest ") + n.name).c_str());
                 break;
             }
             if (tm) {
-                (void)hipEventRecord(app->events[ev_next + 1], stream);
+                if (!single) (void)hipEventRecord(app->events[ev_next + 1], stream);
                 timed.emplace_back(step.idx, (int)ev_next);
                 ev_next += 2;
             }
