@@ -23,6 +23,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "app time & speedup vs 1-core oracle; stencil GB/s, GEMM MFMA % of peak"
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled
+# by the readings of a plain 1 GiB copy (reads x2.000, writes x1.000); see
+# profiles/stencil19_medium_129x129x257.md.  Must be re-measured (or dropped)
+# whenever the kernel changes.
+MEASURED_TRAFFIC = {("stencil19", 129, 129, 257): (2.000 * 9501.3 + 16236.8) * 1024}
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
@@ -202,8 +207,10 @@ def main():
     dom = max(ks.items(), key=lambda kv: kv[1]["total_ms"])[0]
     rk = dom if dom in algo else "stencil19"
     achieved = algo[rk] / (ks[rk]["avg_us"] * 1e-6) / 1e9
+    traffic = MEASURED_TRAFFIC.get((rk, I, J, K))
     roofline = {"kernel": rk, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": round(traffic) if traffic else None,
                 "bytes_per_launch": algo[rk], "avg_launch_us": round(ks[rk]["avg_us"], 3),
                 "dominant_by_time": dom}
     g = ks.get("gemm")
