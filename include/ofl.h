@@ -73,8 +73,14 @@ enum {
     OFL_RUN_PRESTAGED = 1,   /* set-up content already on the device when the
                                 timed region starts (restored device-side,
                                 outside the timed region) */
-    OFL_RUN_KEEP_OUTPUTS = 2 /* leave outputs on the device (no final D2H);
+    OFL_RUN_KEEP_OUTPUTS = 2, /* leave outputs on the device (no final D2H);
                                 ofl_read_buffer fetches them afterwards */
+    OFL_RUN_GRAPH = 4        /* replay the run as HIP graphs captured once per
+                                (gene, policy, flags): a reset graph (untimed)
+                                and a run graph holding the copies, kernels and
+                                host nodes for the CPU nests; deadlines are not
+                                applied to graph runs.  Plans and results are
+                                those of the eager run. */
 };
 
 /* Buffer element types. */

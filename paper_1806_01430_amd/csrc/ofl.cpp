@@ -9,6 +9,7 @@
 #include <cstring>
 #include <fstream>
 #include <map>
+#include <memory>
 #include <new>
 #include <sstream>
 #include <string>
@@ -41,6 +42,38 @@ using clk = std::chrono::steady_clock;
 
 }  // namespace
 
+struct ofl_app;
+
+namespace {
+
+// Host work recorded into a graph: one serial nest, or the restore of set-up
+// content into host copies.  They live as long as the graph that calls them.
+struct HostTask {
+    ofl_app *app = nullptr;
+    int nest = -1;
+    std::vector<int64_t> env;
+};
+struct HostRestore {
+    ofl_app *app = nullptr;
+    std::vector<int> bufs;
+};
+
+// Captured graphs of one (placement, policy, flags, device buffers).
+struct GraphEntry {
+    hipGraphExec_t reset = nullptr, run = nullptr;
+    Plan plan;
+    std::vector<char> host_written;
+    std::vector<std::unique_ptr<HostTask>> tasks;
+    std::unique_ptr<HostRestore> restore;
+    int32_t launches = 0, host_nests = 0;
+    ~GraphEntry() {
+        if (reset) (void)hipGraphExecDestroy(reset);
+        if (run) (void)hipGraphExecDestroy(run);
+    }
+};
+
+}  // namespace
+
 struct ofl_app {
     AppIR ir;
     uint64_t seed = 0;
@@ -68,7 +101,13 @@ struct ofl_app {
     std::vector<hipEvent_t> events;
     std::map<std::string, std::pair<int64_t, double>> kstats;
 
+    // captured graphs and the stream they are captured on
+    std::map<std::vector<uint64_t>, std::unique_ptr<GraphEntry>> graphs;
+    hipStream_t capture_stream = nullptr;
+
     ~ofl_app() {
+        graphs.clear();
+        if (capture_stream) (void)hipStreamDestroy(capture_stream);
         for (void *p : host)
             if (p) (void)hipHostFree(p);
         for (void *p : dev_setup)
@@ -419,6 +458,181 @@ RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *co
     return rr;
 }
 
+// ------------------------------------------------------------ graph runs
+void host_task_cb(void *p) {
+    const HostTask *t = static_cast<const HostTask *>(p);
+    Deadline none;
+    (void)run_host_nest(t->app->ir, t->app->ir.nests[t->nest], t->app->host, t->env.data(), t->app->seed, none);
+}
+
+void host_restore_cb(void *p) {
+    const HostRestore *r = static_cast<const HostRestore *>(p);
+    for (int b : r->bufs) {
+        const Buffer &buf = r->app->ir.bufs[b];
+        if (!r->app->setup[b].empty()) std::memcpy(r->app->host[b], r->app->setup[b].data(), buf.nbytes);
+        else std::memset(r->app->host[b], 0, buf.nbytes);
+    }
+}
+
+int capture_begin(ofl_app *app) {
+    if (!app->capture_stream) {
+        hipError_t e = hipStreamCreateWithFlags(&app->capture_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+    }
+    hipError_t e = hipStreamBeginCapture(app->capture_stream, hipStreamCaptureModeThreadLocal);
+    return e == hipSuccess ? OFL_OK : hip_fail(e, "hipStreamBeginCapture");
+}
+
+int capture_end(ofl_app *app, hipGraphExec_t *exec, int status) {
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(app->capture_stream, &g);
+    if (status != OFL_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return status;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    return e == hipSuccess ? OFL_OK : hip_fail(e, "hipGraphInstantiate");
+}
+
+// Capture the reset graph (set-up content consumed by the run, restored on
+// host and -- with PRESTAGED -- on device) and the run graph (the plan's
+// copies and launches; CPU nests as host nodes).  No memset nodes: device
+// zeroing uses the fill kernel.
+int build_graphs(ofl_app *app, const std::vector<uint8_t> &placement, void *const *dev, int policy, int flags,
+                 GraphEntry &ge) {
+    const AppIR &ir = app->ir;
+    const size_t nb = ir.bufs.size();
+    build_plan(ir, placement, policy, flags, ge.plan);
+    const Plan &plan = ge.plan;
+    ge.host_written.assign(nb, 0);
+    for (const Step &st : plan.steps) {
+        if (st.kind == ST_D2H) ge.host_written[st.idx] = 1;
+        if (st.kind == ST_CPU)
+            for (int b : ir.nests[st.idx].writes) ge.host_written[b] = 1;
+    }
+    if (flags & OFL_RUN_PRESTAGED)
+        for (size_t b = 0; b < nb; ++b)
+            if (plan.dev_init_used[b] && !app->setup[b].empty()) {
+                int rc = ensure_dev_setup(app, (int)b);
+                if (rc != OFL_OK) return rc;
+            }
+    ge.restore.reset(new HostRestore());
+    ge.restore->app = app;
+    for (size_t b = 0; b < nb; ++b)
+        if (plan.host_init_used[b]) ge.restore->bufs.push_back((int)b);
+
+    hipStream_t cs;
+    int rc = capture_begin(app);
+    if (rc != OFL_OK) return rc;
+    cs = app->capture_stream;
+    hipError_t e = hipLaunchHostFunc(cs, host_restore_cb, ge.restore.get());
+    if (e == hipSuccess && (flags & OFL_RUN_PRESTAGED))
+        for (size_t b = 0; b < nb && e == hipSuccess; ++b) {
+            if (!plan.dev_init_used[b]) continue;
+            e = !app->setup[b].empty() ? k::copy_bytes(dev[b], app->dev_setup[b], ir.bufs[b].nbytes, cs)
+                                       : k::fill_zero(dev[b], ir.bufs[b].nbytes, cs);
+        }
+    rc = capture_end(app, &ge.reset, e == hipSuccess ? OFL_OK : hip_fail(e, "capture of the reset graph"));
+    if (rc != OFL_OK) return rc;
+
+    if ((rc = capture_begin(app)) != OFL_OK) return rc;
+    e = hipSuccess;
+    for (const Step &st : plan.steps) {
+        const Buffer *buf = (st.kind == ST_H2D || st.kind == ST_D2H) ? &ir.bufs[st.idx] : nullptr;
+        switch (st.kind) {
+        case ST_H2D: e = hipMemcpyAsync(dev[st.idx], app->host[st.idx], buf->nbytes, hipMemcpyHostToDevice, cs); break;
+        case ST_D2H: e = hipMemcpyAsync(app->host[st.idx], dev[st.idx], buf->nbytes, hipMemcpyDeviceToHost, cs); break;
+        case ST_GPU:
+            e = launch_nest(app, ir.nests[st.idx], dev, plan.env.data() + st.env, cs);
+            ge.launches += kernel_launch_count(ir.nests[st.idx]);
+            break;
+        case ST_CPU: {
+            std::unique_ptr<HostTask> t(new HostTask());
+            t->app = app;
+            t->nest = st.idx;
+            t->env.assign(plan.env.begin() + st.env, plan.env.begin() + st.env + ir.repeat_names.size());
+            e = hipLaunchHostFunc(cs, host_task_cb, t.get());
+            ge.tasks.push_back(std::move(t));
+            ge.host_nests++;
+            break;
+        }
+        }
+        if (e != hipSuccess) break;
+    }
+    return capture_end(app, &ge.run, e == hipSuccess ? OFL_OK : hip_fail(e, "capture of the run graph"));
+}
+
+RunResult run_graph(ofl_app *app, const std::vector<uint8_t> &placement, void *const *dev, hipStream_t stream,
+                    int policy, int flags) {
+    RunResult rr;
+    ofl_run_stats &st = rr.st;
+    std::memset(&st, 0, sizeof(st));
+    st.status = OFL_ST_FAILED;
+    const size_t nb = app->ir.bufs.size();
+    int rc = ensure_host(app);
+    if (rc == OFL_OK) rc = ensure_device(app);
+    if (rc != OFL_OK) {
+        rr.code = rc;
+        return rr;
+    }
+    std::vector<uint64_t> key(placement.begin(), placement.end());
+    key.push_back((uint64_t)policy);
+    key.push_back((uint64_t)(flags & ~OFL_RUN_GRAPH));
+    for (size_t b = 0; b < nb; ++b) key.push_back(reinterpret_cast<uint64_t>(dev[b]));
+    auto it = app->graphs.find(key);
+    if (it == app->graphs.end()) {
+        std::unique_ptr<GraphEntry> ge(new GraphEntry());
+        rc = build_graphs(app, placement, dev, policy, flags & ~OFL_RUN_GRAPH, *ge);
+        if (rc != OFL_OK) {
+            rr.code = rc;
+            return rr;
+        }
+        it = app->graphs.emplace(key, std::move(ge)).first;
+    }
+    GraphEntry &ge = *it->second;
+    app->ran = false;
+    hipError_t e = hipGraphLaunch(ge.reset, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) {
+        rr.code = hip_fail(e, "reset graph");
+        return rr;
+    }
+    for (int b : ge.restore->bufs) app->host_dirty[b] = 0;
+    const auto t0 = clk::now();
+    e = hipGraphLaunch(ge.run, stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(stream);
+    const auto t1 = clk::now();
+    for (size_t b = 0; b < nb; ++b)
+        if (ge.host_written[b]) app->host_dirty[b] = 1;
+    if (e != hipSuccess) {
+        rr.code = hip_fail(e, "run graph");
+        return rr;
+    }
+    st.t_total_s = std::chrono::duration<double>(t1 - t0).count();
+    st.bytes_h2d = ge.plan.h2d;
+    st.bytes_d2h = ge.plan.d2h;
+    st.n_copies = ge.plan.copies;
+    st.n_launches = ge.launches;
+    st.n_host_nests = ge.host_nests;
+    st.status = OFL_ST_OK;
+    app->ran = true;
+    app->host_valid = ge.plan.host_valid;
+    app->dev_valid = ge.plan.dev_valid;
+    app->host_written = ge.host_written;
+    app->last_dev.assign(dev, dev + nb);
+    app->last_stream = stream;
+    return rr;
+}
+
+// One run, eager or as graphs.
+RunResult run_any(ofl_app *app, const std::vector<uint8_t> &placement, void *const *dev, hipStream_t stream,
+                  int policy, int flags, double deadline_s) {
+    if (flags & OFL_RUN_GRAPH) return run_graph(app, placement, dev, stream, policy, flags);
+    return run_once(app, placement, dev, stream, policy, flags, deadline_s);
+}
+
 double median_of(std::vector<double> v) {
     std::sort(v.begin(), v.end());
     const size_t n = v.size();
@@ -431,7 +645,7 @@ Measurement measure(ofl_app *app, const std::vector<uint8_t> &placement, void *c
     Measurement m;
     std::vector<double> ts;
     for (int r = 0; r < warmup + reps; ++r) {
-        RunResult rr = run_once(app, placement, dev, s, policy, flags, deadline_s);
+        RunResult rr = run_any(app, placement, dev, s, policy, flags, deadline_s);
         if (rr.code == OFL_E_TIMEOUT) {
             m.status = OFL_ST_TIMEOUT;
             m.t = rr.st.t_total_s;
@@ -595,6 +809,7 @@ int ofl_set_input(ofl_app *app, int32_t buf, const void *src, uint64_t bytes) {
         return fail(OFL_E_NOMEM, "out of memory");
     }
     if (!app->host.empty()) app->host_dirty[buf] = 1;   // host copy must be refreshed
+    app->graphs.clear();   // captured reset graphs refer to the old device copy
     if (!app->dev_setup.empty() && app->dev_setup[buf]) {
         (void)hipFree(app->dev_setup[buf]);
         app->dev_setup[buf] = nullptr;
@@ -621,7 +836,7 @@ int ofl_plan_transfers(const ofl_app *app, const uint8_t *gene, int32_t gene_len
                        uint64_t *bytes_h2d, uint64_t *bytes_d2h, int32_t *n_copies) {
     if (!app) return fail(OFL_E_ARG, "null app");
     if (policy != OFL_POLICY_RESIDENT && policy != OFL_POLICY_PER_REGION) return fail(OFL_E_ARG, "bad policy");
-    if (flags & ~(OFL_RUN_PRESTAGED | OFL_RUN_KEEP_OUTPUTS)) return fail(OFL_E_ARG, "bad flags");
+    if (flags & ~(OFL_RUN_PRESTAGED | OFL_RUN_KEEP_OUTPUTS | OFL_RUN_GRAPH)) return fail(OFL_E_ARG, "bad flags");
     std::vector<uint8_t> placement;
     int rc = check_gene(app, gene, gene_len, placement);
     if (rc != OFL_OK) return rc;
@@ -646,8 +861,8 @@ int ofl_run_pattern(ofl_app *app, const uint8_t *gene, int32_t gene_len, void *c
     const int flags = opts ? opts->flags : 0;
     const double deadline = opts ? opts->deadline_s : 0.0;
     if (policy != OFL_POLICY_RESIDENT && policy != OFL_POLICY_PER_REGION) return fail(OFL_E_ARG, "bad policy");
-    if (flags & ~(OFL_RUN_PRESTAGED | OFL_RUN_KEEP_OUTPUTS)) return fail(OFL_E_ARG, "bad flags");
-    RunResult rr = run_once(app, placement, dev_bufs, static_cast<hipStream_t>(stream), policy, flags, deadline);
+    if (flags & ~(OFL_RUN_PRESTAGED | OFL_RUN_KEEP_OUTPUTS | OFL_RUN_GRAPH)) return fail(OFL_E_ARG, "bad flags");
+    RunResult rr = run_any(app, placement, dev_bufs, static_cast<hipStream_t>(stream), policy, flags, deadline);
     if (stats) *stats = rr.st;
     return rr.code;
 }

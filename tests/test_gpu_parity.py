@@ -245,3 +245,41 @@ def test_eval_population_and_ga_tiny():
     assert res["best_time"] > 0
     rank = int(np.sum(t < t[sum(b << i for i, b in enumerate(res["best_gene"]))]))
     say("GA best gene", res["best_gene"], "exhaustive best", genes[best_idx], "rank", rank)
+
+
+# ---------------------------------------------------------------- graph runs
+@pytest.mark.parametrize("name,params,genes", [
+    ("tiny", {}, [[1] * 6, [0, 1, 0, 1, 1, 0], [1, 0, 1, 1, 0, 1]]),
+    ("medium", workloads.SMALL_MEDIUM, [[1] * 10, [1, 0, 1, 1, 0, 1, 0, 1, 1, 0]]),
+])
+def test_graph_replays_match_oracle(name, params, genes):
+    # every replay of a captured run is checked, with eager runs of other
+    # genes and host synchronisation in between
+    doc = workloads.app_doc(name, **params)
+    app = ofl.App(json.dumps(doc), seed=2)
+    o = ir.load(doc)
+    o32, o64 = parity.oracle_outputs(o, 2)
+    bufs = app.alloc_device_buffers()
+    for g in genes:
+        for flags in (ofl.GRAPH, ofl.GRAPH | ofl.PRESTAGED | ofl.KEEP_OUTPUTS):
+            for rep in range(3):
+                say("case graph", name, list(g), flags, rep)
+                st = app.run_pattern(g, bufs, flags=flags)
+                assert st["status"] == ofl.ST_OK
+                assert (st["bytes_h2d"], st["bytes_d2h"], st["n_copies"]) == app.plan_transfers(g, 0, flags)
+                bad = parity.compare(o, app.read_all(), o32, o64)
+                assert not bad, (list(g), flags, rep, bad)
+                other = [1 - b for b in g]
+                app.run_pattern(other, bufs)                     # eager work in between
+                bad = parity.compare(o, app.read_all(), o32, o64)
+                assert not bad, ("eager", other, bad)
+
+
+def test_eval_population_graph_mode():
+    doc = workloads.app_doc("tiny")
+    app = ofl.App(json.dumps(doc))
+    bufs = app.alloc_device_buffers()
+    genes = [[1] * 6, [1] * 6, [0] * 6, [1, 1, 1, 0, 0, 0]]
+    t, s = app.eval_population(genes, bufs, reps=3, warmup=1, flags=ofl.GRAPH)
+    assert np.all(s == ofl.ST_OK) and np.all(t > 0)
+    assert t[0] == t[1]          # duplicates measured once
