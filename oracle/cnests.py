@@ -42,6 +42,10 @@ _SIGS = {
     "or_gemm_f64": (None, [_f32p, _f32p, _f64p, _i64, _i64, _i64]),
     "or_gemm_bf16": (None, [_u16p, _u16p, _f32p, _i64, _i64, _i64]),
     "or_gemm_bf16_f64": (None, [_u16p, _u16p, _f64p, _i64, _i64, _i64]),
+    "or_gemm_split_f64": (None, [_f32p, _f32p, _f64p, _i64, _i64, _i64, ctypes.c_int]),
+    "or_e4m3_value": (ctypes.c_double, [ctypes.c_uint8]),
+    "or_e4m3_rne": (ctypes.c_uint8, [ctypes.c_double]),
+    "or_e4m3_scale": (ctypes.c_double, [ctypes.c_double]),
     "or_add_scaled": (None, [_f32p, _f32p, ctypes.c_float, _i64]),
     "or_avg2": (None, [_f32p, _f32p, _f32p, _i64]),
     "or_scale": (None, [_f32p, ctypes.c_float, _i64]),
@@ -120,6 +124,31 @@ def gemm_bf16_f64(A16, B16):
     C = np.empty((M, N), np.float64)
     lib().or_gemm_bf16_f64(np.ascontiguousarray(A16), np.ascontiguousarray(B16), C, M, N, Kd)
     return C
+
+
+SPLIT_VARIANTS = {"bf16x3": 1, "fp8x2": 2}
+
+
+def gemm_split_f64(A, B, prec):
+    """Split-precision product (hi/lo split, one refinement pass), FP64 sum."""
+    M, Kd = A.shape
+    N = B.shape[1]
+    C = np.empty((M, N), np.float64)
+    lib().or_gemm_split_f64(np.ascontiguousarray(A, np.float32), np.ascontiguousarray(B, np.float32), C, M, N, Kd,
+                            SPLIT_VARIANTS[prec])
+    return C
+
+
+def e4m3_value(code):
+    return lib().or_e4m3_value(int(code))
+
+
+def e4m3_rne(x):
+    return lib().or_e4m3_rne(float(x))
+
+
+def e4m3_scale(amax):
+    return lib().or_e4m3_scale(float(amax))
 
 
 def add_scaled(C, A, alpha):

@@ -20,6 +20,7 @@
 #include <stdint.h>
 #include <string.h>
 #include <math.h>
+#include <stdlib.h>
 
 #define SM64_GAMMA 0x9E3779B97F4A7C15ULL
 
@@ -125,6 +126,138 @@ void or_gemm_bf16_f64(const uint16_t *A, const uint16_t *B, double *C,
             for (int64_t j = 0; j < N; ++j) c[j] += a * (double)bf16_to_f32(b[j]);
         }
     }
+}
+
+/* ------------------------------------------------------------------
+ * Split-precision GEMM (the mixed-precision product of the precision
+ * configuration): with x = hi + lo, hi = round(x), lo = round(x - hi) in the
+ * narrow format, the product is taken as Ah Bh + Ah Bl + Al Bh, i.e. the
+ * base product plus one refinement pass (the bf16x3 scheme of Henry, Tang &
+ * Heinecke 2019; the split itself goes back to Markidis et al. 2018).
+ * Here every product of narrow values is exact in double and the sum is
+ * taken in double, so the result is the split method's value up to FP64
+ * rounding -- the GPU's only further difference is its FP32 accumulation.
+ *
+ * FP8 is OCP e4m3 ("E4M3FN"): 1 sign bit, 4 exponent bits with bias 7,
+ * 3 fraction bits; normal values (1 + f/8) 2^(e-7) for e = 1..15 (e = 15,
+ * f = 7 is NaN, so the largest finite value is 448); subnormals (f/8) 2^-6.
+ * Rows of A and columns of B are scaled by powers of two into range first.
+ * ------------------------------------------------------------------ */
+
+/* Value of an e4m3 code (NaN code -> NAN). */
+double or_e4m3_value(uint8_t c)
+{
+    const int e = (c >> 3) & 15, f = c & 7;
+    double v;
+    if (e == 15 && f == 7) return NAN;
+    if (e == 0) v = ldexp((double)f, -9);            /* f/8 * 2^-6 */
+    else v = ldexp(8.0 + f, e - 10);                  /* (8+f)/8 * 2^(e-7) */
+    return (c & 0x80) ? -v : v;
+}
+
+/* Nearest e4m3 code to x, ties to even; |x| must not exceed 448. */
+uint8_t or_e4m3_rne(double x)
+{
+    const uint8_t sign = (x < 0.0 || (x == 0.0 && signbit(x))) ? 0x80 : 0x00;
+    const double a = fabs(x);
+    double q;                                         /* spacing of codes around a */
+    if (a < ldexp(1.0, -6)) {
+        q = ldexp(1.0, -9);
+    } else {
+        int E;
+        (void)frexp(a, &E);                           /* a = m 2^E, m in [0.5, 1) */
+        q = ldexp(1.0, E - 4);                        /* 3 fraction bits below 2^(E-1) */
+    }
+    const double n = a / q;                           /* exact: q is a power of two */
+    double r = floor(n);
+    const double d = n - r;
+    if (d > 0.5 || (d == 0.5 && fmod(r, 2.0) != 0.0)) r += 1.0;
+    const double v = r * q;                           /* rounded magnitude */
+    if (v == 0.0) return sign;
+    if (v < ldexp(1.0, -6)) return (uint8_t)(sign | (uint8_t)(v / ldexp(1.0, -9)));
+    int E;
+    const double m = frexp(v, &E);                    /* v = m 2^E */
+    const int ef = E - 1 + 7;
+    const int f = (int)((2.0 * m - 1.0) * 8.0);
+    return (uint8_t)(sign | (uint8_t)(ef << 3) | (uint8_t)f);
+}
+
+/* Largest power of two s with amax * s <= 224 (half the e4m3 maximum of 448,
+ * which leaves room for the rounding of hi); 1 for amax 0 or not finite. */
+double or_e4m3_scale(double amax)
+{
+    if (!(amax > 0.0) || !isfinite(amax)) return 1.0;
+    double s = 1.0;
+    while (amax * s > 224.0) s *= 0.5;
+    while (amax * (2.0 * s) <= 224.0 && s < ldexp(1.0, 126)) s *= 2.0;
+    if (s < ldexp(1.0, -126)) s = ldexp(1.0, -126);
+    return s;
+}
+
+static double bf16_to_f64(uint16_t h) { return (double)bf16_to_f32(h); }
+static uint16_t f32_to_bf16_rne(float f);
+
+/* Split of one FP32 value: hi and lo as doubles, both on the narrow grid.
+ * For fp8, xs is the value already multiplied by its power-of-two scale. */
+static void split_bf16(float x, double *hi, double *lo)
+{
+    const uint16_t h = f32_to_bf16_rne(x);
+    *hi = bf16_to_f64(h);
+    const float r = (float)((double)x - *hi);         /* exact in FP32 */
+    *lo = bf16_to_f64(f32_to_bf16_rne(r));
+}
+
+static void split_e4m3(float xs, double *hi, double *lo)
+{
+    *hi = or_e4m3_value(or_e4m3_rne((double)xs));
+    const double r = (double)xs - *hi;                /* exact */
+    *lo = or_e4m3_value(or_e4m3_rne(r));
+}
+
+/* C = Ah Bh + Ah Bl + Al Bh in double; variant 1 = bf16, 2 = e4m3 with a
+ * power-of-two scale per row of A and per column of B. */
+void or_gemm_split_f64(const float *A, const float *B, double *C,
+                       int64_t M, int64_t N, int64_t Kd, int variant)
+{
+    double *ah = malloc(sizeof(double) * (size_t)(M * Kd + 1));
+    double *al = malloc(sizeof(double) * (size_t)(M * Kd + 1));
+    double *bh = malloc(sizeof(double) * (size_t)(Kd * N + 1));
+    double *bl = malloc(sizeof(double) * (size_t)(Kd * N + 1));
+    double *sa = malloc(sizeof(double) * (size_t)(M + 1));
+    double *sb = malloc(sizeof(double) * (size_t)(N + 1));
+    for (int64_t i = 0; i < M; ++i) {
+        double amax = 0.0;
+        for (int64_t k = 0; k < Kd; ++k) amax = fmax(amax, fabs((double)A[i * Kd + k]));
+        sa[i] = variant == 2 ? or_e4m3_scale(amax) : 1.0;
+    }
+    for (int64_t j = 0; j < N; ++j) {
+        double amax = 0.0;
+        for (int64_t k = 0; k < Kd; ++k) amax = fmax(amax, fabs((double)B[k * N + j]));
+        sb[j] = variant == 2 ? or_e4m3_scale(amax) : 1.0;
+    }
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t k = 0; k < Kd; ++k) {
+            const float x = A[i * Kd + k];
+            if (variant == 2) split_e4m3((float)((double)x * sa[i]), &ah[i * Kd + k], &al[i * Kd + k]);
+            else split_bf16(x, &ah[i * Kd + k], &al[i * Kd + k]);
+        }
+    for (int64_t k = 0; k < Kd; ++k)
+        for (int64_t j = 0; j < N; ++j) {
+            const float x = B[k * N + j];
+            if (variant == 2) split_e4m3((float)((double)x * sb[j]), &bh[k * N + j], &bl[k * N + j]);
+            else split_bf16(x, &bh[k * N + j], &bl[k * N + j]);
+        }
+    for (int64_t i = 0; i < M; ++i)
+        for (int64_t j = 0; j < N; ++j) {
+            double acc = 0.0;
+            for (int64_t k = 0; k < Kd; ++k) {
+                const double a1 = ah[i * Kd + k], a0 = al[i * Kd + k];
+                const double b1 = bh[k * N + j], b0 = bl[k * N + j];
+                acc += a1 * b1 + a1 * b0 + a0 * b1;
+            }
+            C[i * N + j] = acc / (sa[i] * sb[j]);
+        }
+    free(ah); free(al); free(bh); free(bl); free(sa); free(sb);
 }
 
 /* Element-wise nests. */

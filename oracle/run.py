@@ -39,13 +39,19 @@ def _bf16_to_f64(x16):
     return (x16.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
 
 
-def run_nest(app, nest, bufs, seed, repeat_env, twin=False):
+def run_nest(app, nest, bufs, seed, repeat_env, twin=False, offloaded=False):
     op, a = nest.op, nest.args
     if op == "init_uniform":
         for name, stream in zip(a["out"], a["streams"]):
             x = bufs[name]
             v = C.init_uniform(x.size, seed, stream).reshape(x.shape)
             x[...] = v
+    elif op == "gemm" and offloaded and a.get("prec", "f32") != "f32":
+        # the offloaded form of a GEMM nest marked with a split precision: the
+        # split product's own definition, summed in FP64; the FP32 run holds
+        # that value rounded to FP32.  On the CPU the nest is plain FP32.
+        A, B, Cm = bufs[a["A"]], bufs[a["B"]], bufs[a["C"]]
+        Cm[...] = C.gemm_split_f64(np.asarray(A, np.float32), np.asarray(B, np.float32), a["prec"])
     elif op == "gemm":
         A, B, Cm = bufs[a["A"]], bufs[a["B"]], bufs[a["C"]]
         if twin:
@@ -130,15 +136,20 @@ def run_nest(app, nest, bufs, seed, repeat_env, twin=False):
         raise ValueError("unknown op %r" % op)
 
 
-def run_app(app, seed, twin=False, bufs=None):
-    """Serial run of the whole program; returns the final buffers."""
+def run_app(app, seed, twin=False, bufs=None, offloaded=()):
+    """Serial run of the whole program; returns the final buffers.
+
+    ``offloaded`` names the nests (by index) that the gene places on the GPU;
+    it matters only for GEMM nests marked with a split precision, whose GPU
+    form computes a different (documented) value than the FP32 loop."""
     if bufs is None:
         bufs = setup_buffers(app, twin)
+    offloaded = set(offloaded)
 
     def walk(items, env):
         for it in items:
             if it[0] == "nest":
-                run_nest(app, app.nests[it[1]], bufs, seed, env, twin)
+                run_nest(app, app.nests[it[1]], bufs, seed, env, twin, it[1] in offloaded)
             else:
                 _, var, count, body = it
                 for n in range(count):

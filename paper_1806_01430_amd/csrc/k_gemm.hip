@@ -218,6 +218,139 @@ __global__ __launch_bounds__(kThreads) void k_gemm_bf16(const unsigned short *__
             }
 }
 
+// Split-precision / low-precision product on k-contiguous operands:
+// C[i][j] = (sum_k A'[i][k] B'[j][k]) * sa[i] * sb[j]   (scales optional),
+// A' is Mp x Kp, B' is Np x Kp (B stored transposed), both zero-padded to
+// whole tiles, so loads need no bounds checks.  T = bf16 (MFMA 16x16x32 bf16)
+// or fp8 e4m3 (MFMA 16x16x32 fp8).  A slab is 128 bytes of k per row; each
+// lane takes a contiguous 32-byte run of the slab for its lane group.
+typedef long fp8x8;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+template <typename T, int BM, int BN, bool SCALED>
+__global__ __launch_bounds__(kThreads) void k_gemm_nt(const T *__restrict__ A, const T *__restrict__ B,
+                                                      float *__restrict__ C, int M, int N, int Kp,
+                                                      const float *__restrict__ sa, const float *__restrict__ sb) {
+    constexpr int SLAB = 128;                       // bytes of k per row per slab
+    constexpr int LDS_ROW = SLAB + 16;              // padded row: conflict-free 16-byte reads
+    constexpr int EPB = SLAB / sizeof(T);           // elements per slab
+    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int TM = WM / 16, TN = WN / 16;
+    constexpr int A_PER = BM * SLAB / 16 / kThreads;
+    constexpr int B_PER = BN * SLAB / 16 / kThreads;
+    static_assert(A_PER * 16 * kThreads == BM * SLAB && B_PER * 16 * kThreads == BN * SLAB, "tile mismatch");
+    __shared__ __attribute__((aligned(16))) unsigned char As[2][BM * LDS_ROW];
+    __shared__ __attribute__((aligned(16))) unsigned char Bs[2][BN * LDS_ROW];
+
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave >> 1, wn = wave & 1;
+    const int tiles_n = (N + BN - 1) / BN;
+    const int tiles = tiles_n * ((M + BM - 1) / BM);
+    const int t = xcd_swizzle(blockIdx.x, tiles);
+    const int m0 = (t / tiles_n) * BM, n0 = (t % tiles_n) * BN;
+    const size_t row_bytes = (size_t)Kp * sizeof(T);
+    const unsigned char *Ab = reinterpret_cast<const unsigned char *>(A) + (size_t)m0 * row_bytes;
+    const unsigned char *Bb = reinterpret_cast<const unsigned char *>(B) + (size_t)n0 * row_bytes;
+
+    floatx4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    u32x4 ra[A_PER], rb[B_PER];
+    auto gload = [&](int slab) {
+        const size_t kb = (size_t)slab * SLAB;
+#pragma unroll
+        for (int s = 0; s < A_PER; ++s) {
+            const int idx = tid + s * kThreads, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
+            ra[s] = *reinterpret_cast<const u32x4 *>(Ab + (size_t)row * row_bytes + kb + c);
+        }
+#pragma unroll
+        for (int s = 0; s < B_PER; ++s) {
+            const int idx = tid + s * kThreads, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
+            rb[s] = *reinterpret_cast<const u32x4 *>(Bb + (size_t)row * row_bytes + kb + c);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int s = 0; s < A_PER; ++s) {
+            const int idx = tid + s * kThreads, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
+            *reinterpret_cast<u32x4 *>(&As[buf][row * LDS_ROW + c]) = ra[s];
+        }
+#pragma unroll
+        for (int s = 0; s < B_PER; ++s) {
+            const int idx = tid + s * kThreads, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
+            *reinterpret_cast<u32x4 *>(&Bs[buf][row * LDS_ROW + c]) = rb[s];
+        }
+    };
+    const int r = lane & 15, g = lane >> 4;
+    auto compute = [&](int buf) {
+        // lane group g owns bytes [32g, 32g+32) of the slab: two 16-byte reads
+        u32x4 af[TM][2], bfr[TN][2];
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                af[i][h] = *reinterpret_cast<const u32x4 *>(&As[buf][(wm * WM + i * 16 + r) * LDS_ROW + 32 * g + 16 * h]);
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                bfr[j][h] = *reinterpret_cast<const u32x4 *>(&Bs[buf][(wn * WN + j * 16 + r) * LDS_ROW + 32 * g + 16 * h]);
+        if constexpr (sizeof(T) == 2) {
+            // 16 bf16 per lane = two MFMA steps of 8
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[i][h]),
+                                                                            __builtin_bit_cast(bf16x8, bfr[j][h]),
+                                                                            acc[i][j], 0, 0, 0);
+        } else {
+            // 32 fp8 per lane = four MFMA steps of 8
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int i = 0; i < TM; ++i)
+#pragma unroll
+                        for (int j = 0; j < TN; ++j) {
+                            const fp8x8 a8 = (fp8x8)(((unsigned long)af[i][h][2 * q + 1] << 32) | af[i][h][2 * q]);
+                            const fp8x8 b8 = (fp8x8)(((unsigned long)bfr[j][h][2 * q + 1] << 32) | bfr[j][h][2 * q]);
+                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a8, b8, acc[i][j], 0, 0, 0);
+                        }
+        }
+    };
+
+    const int nslab = (int)(row_bytes / SLAB);
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    for (int kt = 0; kt < nslab; ++kt) {
+        const int cur = kt & 1;
+        if (kt + 1 < nslab) gload(kt + 1);
+        compute(cur);
+        if (kt + 1 < nslab) sstore(cur ^ 1);
+        __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = m0 + wm * WM + i * 16 + 4 * g + e, col = n0 + wn * WN + j * 16 + r;
+                if (row < M && col < N) {
+                    float v = acc[i][j][e];
+                    if (SCALED) v = v * (sa[row] * sb[col]);
+                    C[(size_t)row * N + col] = v;
+                }
+            }
+}
+
 template <int BM, int BN, int BK>
 hipError_t launch_f32(const float *A, const float *B, float *C, int M, int N, int K, hipStream_t s) {
     const unsigned tiles = (unsigned)(((M + BM - 1) / BM) * ((N + BN - 1) / BN));
@@ -248,6 +381,89 @@ hipError_t gemm_bf16(const uint16_t *A, const uint16_t *B, float *C, int64_t M, 
     return launch((k_gemm_bf16<64, 64>), dim3(tiles), dim3(kThreads), 0, s,
                        reinterpret_cast<const unsigned short *>(A), reinterpret_cast<const unsigned short *>(B), C,
                        (int)M, (int)N, (int)K);
+}
+
+// ---------------------------------------------------------------- split-precision GEMM
+namespace {
+constexpr int kNT = 128;   // tile of the k-contiguous product (rows of A', rows of B')
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+struct NtShape {
+    int64_t Mp, Np, Kp;    // padded rows of A', rows of B', k extent (elements)
+};
+
+NtShape nt_shape(int64_t M, int64_t N, int64_t Kx, int elem) {
+    return {round_up(M, kNT), round_up(N, kNT), round_up(Kx, 128 / elem)};
+}
+}  // namespace
+
+int64_t gemm_workspace_bytes(int64_t M, int64_t N, int64_t K, int variant) {
+    if (M <= 0 || N <= 0 || K <= 0) return 0;
+    if (variant == 0) return 0;
+    const int elem = variant == 2 ? 1 : 2;
+    const int64_t kx = variant == 3 ? K : 3 * K;
+    const NtShape sh = nt_shape(M, N, kx, elem);
+    int64_t bytes = (sh.Mp + sh.Np) * sh.Kp * elem;
+    bytes = round_up(bytes, 256) + 4 * (sh.Mp + sh.Np) * (int64_t)sizeof(float);
+    return round_up(bytes, 256);
+}
+
+hipError_t gemm_split(const float *A, const float *B, float *C, int64_t M, int64_t N, int64_t K, int variant,
+                      void *ws, int64_t ws_bytes, hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (K <= 0) return fill_zero(C, (uint64_t)M * N * sizeof(float), s);
+    if (variant != 1 && variant != 2) return hipErrorInvalidValue;
+    if (M > (1 << 29) || N > (1 << 29) || K > (1 << 28)) return hipErrorInvalidValue;
+    if (gemm_workspace_bytes(M, N, K, variant) > ws_bytes) return hipErrorInvalidValue;
+    const int elem = variant == 2 ? 1 : 2;
+    const NtShape sh = nt_shape(M, N, 3 * K, elem);
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    void *Ap = w;
+    void *Bp = w + sh.Mp * sh.Kp * elem;
+    float *f = reinterpret_cast<float *>(w + round_up((sh.Mp + sh.Np) * sh.Kp * elem, 256));
+    float *sa = f, *sb = f + sh.Mp, *isa = f + sh.Mp + sh.Np, *isb = isa + sh.Mp;
+    const unsigned tiles = (unsigned)((sh.Mp / kNT) * (sh.Np / kNT));
+    hipError_t e = fill_zero(Bp, (uint64_t)(sh.Np * sh.Kp * elem), s);
+    if (variant == 1) {
+        if (e == hipSuccess) e = split_a_bf16x3(A, static_cast<uint16_t *>(Ap), (int)M, (int)K, (int)sh.Mp, (int)sh.Kp, s);
+        if (e == hipSuccess) e = split_bt(B, Bp, nullptr, (int)K, (int)N, (int)sh.Kp, 0, s);
+        if (e == hipSuccess)
+            e = launch((k_gemm_nt<unsigned short, kNT, kNT, false>), dim3(tiles), dim3(kThreads), 0, s,
+                       static_cast<const unsigned short *>(Ap), static_cast<const unsigned short *>(Bp), C, (int)M,
+                       (int)N, (int)sh.Kp, (const float *)nullptr, (const float *)nullptr);
+        return e;
+    }
+    if (e == hipSuccess) e = row_scales(A, sa, isa, (int)M, (int)K, s);
+    if (e == hipSuccess) e = col_scales(B, sb, isb, (int)K, (int)N, s);
+    if (e == hipSuccess) e = split_a_fp8x2(A, static_cast<uint8_t *>(Ap), sa, (int)M, (int)K, (int)sh.Mp, (int)sh.Kp, s);
+    if (e == hipSuccess) e = split_bt(B, Bp, sb, (int)K, (int)N, (int)sh.Kp, 1, s);
+    if (e == hipSuccess)
+        e = launch((k_gemm_nt<unsigned char, kNT, kNT, true>), dim3(tiles), dim3(kThreads), 0, s,
+                   static_cast<const unsigned char *>(Ap), static_cast<const unsigned char *>(Bp), C, (int)M, (int)N,
+                   (int)sh.Kp, (const float *)isa, (const float *)isb);
+    return e;
+}
+
+hipError_t gemm_bf16_nt(const uint16_t *A, const uint16_t *B, float *C, int64_t M, int64_t N, int64_t K, void *ws,
+                        int64_t ws_bytes, hipStream_t s) {
+    if (M <= 0 || N <= 0) return hipSuccess;
+    if (K <= 0) return fill_zero(C, (uint64_t)M * N * sizeof(float), s);
+    if (M > (1 << 29) || N > (1 << 29) || K > (1 << 28)) return hipErrorInvalidValue;
+    if (gemm_workspace_bytes(M, N, K, 3) > ws_bytes) return hipErrorInvalidValue;
+    const NtShape sh = nt_shape(M, N, K, 2);
+    unsigned char *w = static_cast<unsigned char *>(ws);
+    uint16_t *Ap = reinterpret_cast<uint16_t *>(w);
+    void *Bp = w + sh.Mp * sh.Kp * 2;
+    const unsigned tiles = (unsigned)((sh.Mp / kNT) * (sh.Np / kNT));
+    hipError_t e = fill_zero(Bp, (uint64_t)(sh.Np * sh.Kp * 2), s);
+    if (e == hipSuccess) e = pad_a_bf16(A, Ap, (int)M, (int)K, (int)sh.Mp, (int)sh.Kp, s);
+    if (e == hipSuccess) e = split_bt(B, Bp, nullptr, (int)K, (int)N, (int)sh.Kp, 2, s);
+    if (e == hipSuccess)
+        e = launch((k_gemm_nt<unsigned short, kNT, kNT, false>), dim3(tiles), dim3(kThreads), 0, s,
+                   static_cast<const unsigned short *>(static_cast<void *>(Ap)), static_cast<const unsigned short *>(Bp),
+                   C, (int)M, (int)N, (int)sh.Kp, (const float *)nullptr, (const float *)nullptr);
+    return e;
 }
 
 }  // namespace k

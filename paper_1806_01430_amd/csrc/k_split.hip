@@ -1,0 +1,234 @@
+// Operand preparation for the split-precision GEMM variants.
+//
+// A product in lower precision with one refinement pass: with A = Ah + Al and
+// B = Bh + Bl (hi = rounded value, lo = rounded remainder),
+//   A B  ~  Ah Bh + Ah Bl + Al Bh,
+// which is a single GEMM over K' = 3K of A' = [Ah | Ah | Al] (rows of A) with
+// B' = [Bh ; Bl ; Bh].  Both operands are written k-contiguous (B' stored
+// transposed, one row per column of B) and zero-padded to whole tiles, so the
+// GEMM kernel needs no bounds checks on its loads.
+//
+// FP8 (e4m3): each row of A and each column of B gets a power-of-two scale s
+// with amax * s <= 224 (inside the range of either e4m3 variant); the scale
+// factors out of every dot product and is undone in the GEMM epilogue.
+#include <hip/hip_runtime.h>
+
+#include "dev_common.hpp"
+#include "kernels.hpp"
+#include "launch.hpp"
+
+namespace ofl {
+namespace k {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline unsigned short bf16_rne_bits(float f) {
+    unsigned u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return (unsigned short)((u >> 16) | 0x40u);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return (unsigned short)(u >> 16);
+}
+__device__ inline float bf16_value(unsigned short h) { return __uint_as_float((unsigned)h << 16); }
+
+// hi / lo parts of x in the operand type
+struct Bf16Parts {
+    unsigned short hi, lo;
+};
+__device__ inline Bf16Parts split_bf16(float x) {
+    const unsigned short h = bf16_rne_bits(x);
+    return {h, bf16_rne_bits(x - bf16_value(h))};
+}
+struct Fp8Parts {
+    unsigned char hi, lo;
+};
+__device__ inline unsigned char fp8_bits(float x) {
+    return (unsigned char)(__builtin_amdgcn_cvt_pk_fp8_f32(x, 0.0f, 0, false) & 0xFF);
+}
+__device__ inline float fp8_value(unsigned char b) { return __builtin_amdgcn_cvt_f32_fp8((int)b, 0); }
+__device__ inline Fp8Parts split_fp8(float xs) {
+    const unsigned char h = fp8_bits(xs);
+    return {h, fp8_bits(xs - fp8_value(h))};
+}
+
+// Largest power of two s with amax * s <= 224 (1 when amax is 0 or not
+// finite).  With amax = m 2^E, m in [0.5, 1), and 224 = 0.875 * 2^8:
+// s = 2^(8 - E) when m <= 0.875, else 2^(7 - E); exact, no division.
+__device__ inline float pow2_scale(float amax) {
+    if (!(amax > 0.0f) || !(amax <= 3.4028235e38f)) return 1.0f;
+    int E;
+    const float m = frexpf(amax, &E);
+    int e = (m <= 0.875f ? 8 : 7) - E;
+    e = e < -126 ? -126 : (e > 126 ? 126 : e);
+    return ldexpf(1.0f, e);
+}
+
+// A' for BF16x3: rows i < M: [hi(A[i]) | hi(A[i]) | lo(A[i]) | 0 ...]; padded rows 0.
+__global__ __launch_bounds__(kThreads) void k_split_a_bf16(const float *__restrict__ A, unsigned short *__restrict__ Ap,
+                                                           int M, int K, int Mp, int Kp) {
+    const int64_t total = (int64_t)Mp * Kp;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int i = (int)(e / Kp), kp = (int)(e % Kp);
+        unsigned short v = 0;
+        if (i < M && kp < 3 * K) {
+            const int seg = kp / K, kk = kp - seg * K;
+            const Bf16Parts s = split_bf16(A[(size_t)i * K + kk]);
+            v = seg == 2 ? s.lo : s.hi;
+        }
+        Ap[e] = v;
+    }
+}
+
+// A' for FP8x2 with row scales sa (1/s stored in inv_sa).
+__global__ __launch_bounds__(kThreads) void k_split_a_fp8(const float *__restrict__ A, unsigned char *__restrict__ Ap,
+                                                          const float *__restrict__ sa, int M, int K, int Mp,
+                                                          int Kp) {
+    const int64_t total = (int64_t)Mp * Kp;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int i = (int)(e / Kp), kp = (int)(e % Kp);
+        unsigned char v = 0;
+        if (i < M && kp < 3 * K) {
+            const int seg = kp / K, kk = kp - seg * K;
+            const Fp8Parts s = split_fp8(A[(size_t)i * K + kk] * sa[i]);
+            v = seg == 2 ? s.lo : s.hi;
+        }
+        Ap[e] = v;
+    }
+}
+
+// B'^T: row j (< N) of the output holds column j of B: [hi | lo | hi | 0 ...]
+// (or the plain bf16 column for the bf16-input product).  64 x 64 tiles of B
+// through LDS, so both the read of B and the write of B'^T are coalesced.
+constexpr int kT = 64;
+template <int MODE>   // 0: bf16 hi/lo split of f32, 1: fp8 split of f32 * sb, 2: plain bf16 copy
+__global__ __launch_bounds__(kThreads) void k_split_bt(const void *__restrict__ Bv, void *__restrict__ Btv,
+                                                       const float *__restrict__ sb, int K, int N, int Kp) {
+    __shared__ float tile[kT][kT + 1];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+    const int k0 = blockIdx.x * kT, j0 = blockIdx.y * kT;
+    for (int r = ty; r < kT; r += kThreads / kT) {
+        const int kk = k0 + r, j = j0 + tx;
+        float v = 0.0f;
+        if (kk < K && j < N) {
+            if (MODE == 2) v = bf16_value(static_cast<const unsigned short *>(Bv)[(size_t)kk * N + j]);
+            else v = static_cast<const float *>(Bv)[(size_t)kk * N + j];
+        }
+        tile[r][tx] = v;
+    }
+    __syncthreads();
+    for (int r = ty; r < kT; r += kThreads / kT) {
+        const int j = j0 + r, kk = k0 + tx;
+        if (j >= N || kk >= K) continue;
+        const float x = tile[tx][r];
+        if (MODE == 0) {
+            unsigned short *Bt = static_cast<unsigned short *>(Btv) + (size_t)j * Kp;
+            const Bf16Parts s = split_bf16(x);
+            Bt[kk] = s.hi;
+            Bt[K + kk] = s.lo;
+            Bt[2 * K + kk] = s.hi;
+        } else if (MODE == 1) {
+            unsigned char *Bt = static_cast<unsigned char *>(Btv) + (size_t)j * Kp;
+            const Fp8Parts s = split_fp8(x * sb[j]);
+            Bt[kk] = s.hi;
+            Bt[K + kk] = s.lo;
+            Bt[2 * K + kk] = s.hi;
+        } else {
+            unsigned short *Bt = static_cast<unsigned short *>(Btv) + (size_t)j * Kp;
+            Bt[kk] = bf16_rne_bits(x);
+        }
+    }
+}
+
+// A'' for the bf16-input product: A copied into the padded, tile-aligned layout.
+__global__ __launch_bounds__(kThreads) void k_pad_a_bf16(const unsigned short *__restrict__ A,
+                                                         unsigned short *__restrict__ Ap, int M, int K, int Mp, int Kp) {
+    const int64_t total = (int64_t)Mp * Kp;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += stride) {
+        const int i = (int)(e / Kp), kp = (int)(e % Kp);
+        Ap[e] = (i < M && kp < K) ? A[(size_t)i * K + kp] : (unsigned short)0;
+    }
+}
+
+// Row scales of A: one wave per row, max |A[i][k]| -> s_i; inv_s_i.
+__global__ __launch_bounds__(kThreads) void k_row_scale(const float *__restrict__ A, float *__restrict__ s,
+                                                        float *__restrict__ inv, int M, int K) {
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * (kThreads / kWave) + threadIdx.x / kWave;
+    if (row >= M) return;
+    float m = 0.0f;
+    for (int k = lane; k < K; k += kWave) m = fmaxf(m, fabsf(A[(size_t)row * K + k]));
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if (lane == 0) {
+        const float sc = pow2_scale(m);
+        s[row] = sc;
+        inv[row] = 1.0f / sc;
+    }
+}
+
+// Column scales of B: a block of 256 threads takes 64 columns and 4 slices
+// of k, then combines the slices in LDS.
+__global__ __launch_bounds__(kThreads) void k_col_scale(const float *__restrict__ B, float *__restrict__ s,
+                                                        float *__restrict__ inv, int K, int N) {
+    __shared__ float part[4][64];
+    const int tx = threadIdx.x & 63, slice = threadIdx.x >> 6;
+    const int j = blockIdx.x * 64 + tx;
+    float m = 0.0f;
+    if (j < N)
+        for (int k = slice; k < K; k += 4) m = fmaxf(m, fabsf(B[(size_t)k * N + j]));
+    part[slice][tx] = m;
+    __syncthreads();
+    if (slice == 0 && j < N) {
+        m = fmaxf(fmaxf(part[0][tx], part[1][tx]), fmaxf(part[2][tx], part[3][tx]));
+        const float sc = pow2_scale(m);
+        s[j] = sc;
+        inv[j] = 1.0f / sc;
+    }
+}
+
+unsigned grid_elems(int64_t n) {
+    int64_t b = (n + kThreads * 4 - 1) / (kThreads * 4);
+    if (b < 1) b = 1;
+    if (b > 8192) b = 8192;
+    return (unsigned)b;
+}
+
+}  // namespace
+
+hipError_t split_a_bf16x3(const float *A, uint16_t *Ap, int M, int K, int Mp, int Kp, hipStream_t s) {
+    return launch(k_split_a_bf16, dim3(grid_elems((int64_t)Mp * Kp)), dim3(kThreads), 0, s, A,
+                  reinterpret_cast<unsigned short *>(Ap), M, K, Mp, Kp);
+}
+
+hipError_t split_a_fp8x2(const float *A, uint8_t *Ap, const float *sa, int M, int K, int Mp, int Kp, hipStream_t s) {
+    return launch(k_split_a_fp8, dim3(grid_elems((int64_t)Mp * Kp)), dim3(kThreads), 0, s, A,
+                  reinterpret_cast<unsigned char *>(Ap), sa, M, K, Mp, Kp);
+}
+
+hipError_t pad_a_bf16(const uint16_t *A, uint16_t *Ap, int M, int K, int Mp, int Kp, hipStream_t s) {
+    return launch(k_pad_a_bf16, dim3(grid_elems((int64_t)Mp * Kp)), dim3(kThreads), 0, s,
+                  reinterpret_cast<const unsigned short *>(A), reinterpret_cast<unsigned short *>(Ap), M, K, Mp, Kp);
+}
+
+hipError_t split_bt(const void *B, void *Bt, const float *sb, int K, int N, int Kp, int mode, hipStream_t s) {
+    dim3 grid((unsigned)((K + kT - 1) / kT), (unsigned)((N + kT - 1) / kT));
+    if (grid.y > 65535) return hipErrorInvalidValue;
+    if (mode == 0) return launch((k_split_bt<0>), grid, dim3(kThreads), 0, s, B, Bt, sb, K, N, Kp);
+    if (mode == 1) return launch((k_split_bt<1>), grid, dim3(kThreads), 0, s, B, Bt, sb, K, N, Kp);
+    return launch((k_split_bt<2>), grid, dim3(kThreads), 0, s, B, Bt, sb, K, N, Kp);
+}
+
+hipError_t row_scales(const float *A, float *s_out, float *inv_out, int M, int K, hipStream_t s) {
+    const unsigned blocks = (unsigned)((M + (kThreads / kWave) - 1) / (kThreads / kWave));
+    return launch(k_row_scale, dim3(blocks), dim3(kThreads), 0, s, A, s_out, inv_out, M, K);
+}
+
+hipError_t col_scales(const float *B, float *s_out, float *inv_out, int K, int N, hipStream_t s) {
+    return launch(k_col_scale, dim3((unsigned)((N + 63) / 64)), dim3(kThreads), 0, s, B, s_out, inv_out, K, N);
+}
+
+}  // namespace k
+}  // namespace ofl

@@ -89,6 +89,8 @@ struct ofl_app {
     double *d_partials = nullptr;
     unsigned *d_counter = nullptr;
     int64_t partial_cap = 0;
+    void *d_gemm_ws = nullptr;               // operand workspace of split-precision GEMM nests
+    int64_t gemm_ws_bytes = 0;
 
     // state after the last completed run
     bool ran = false;
@@ -113,6 +115,7 @@ struct ofl_app {
         for (void *p : dev_setup)
             if (p) (void)hipFree(p);
         if (d_partials) (void)hipFree(d_partials);
+        if (d_gemm_ws) (void)hipFree(d_gemm_ws);
         for (auto e : events) (void)hipEventDestroy(e);
     }
 };
@@ -193,6 +196,22 @@ int ensure_device(ofl_app *app) {
         (void)hipFree(mem);
         return hip_fail(e, "scratch init");
     }
+    int64_t ws = 0;
+    for (const auto &n : app->ir.nests) {
+        if (n.op != OP_GEMM || n.prec == PREC_F32) continue;
+        const auto &a = app->ir.bufs[n.b[0]].dims, &bb = app->ir.bufs[n.b[1]].dims;
+        ws = std::max(ws, k::gemm_workspace_bytes(a[0], bb[1], a[1], n.prec == PREC_BF16X3 ? 1 : 2));
+    }
+    if (ws > 0) {
+        void *w = nullptr;
+        e = hipMalloc(&w, (size_t)ws);
+        if (e != hipSuccess) {
+            (void)hipFree(mem);
+            return e == hipErrorOutOfMemory ? fail(OFL_E_NOMEM, "GEMM workspace") : hip_fail(e, "hipMalloc");
+        }
+        app->d_gemm_ws = w;
+        app->gemm_ws_bytes = ws;
+    }
     app->d_partials = static_cast<double *>(mem);
     app->d_counter = reinterpret_cast<unsigned *>(static_cast<char *>(mem) + (size_t)cap * sizeof(double));
     app->partial_cap = cap;
@@ -240,7 +259,9 @@ hipError_t launch_nest(ofl_app *app, const Nest &n, void *const *dev, const int6
         return e;
     case OP_GEMM: {
         const auto &a = ir.bufs[n.b[0]].dims, &bb = ir.bufs[n.b[1]].dims;
-        return k::gemm_f32(F(0), F(1), F(2), a[0], bb[1], a[1], s);
+        if (n.prec == PREC_F32) return k::gemm_f32(F(0), F(1), F(2), a[0], bb[1], a[1], s);
+        return k::gemm_split(F(0), F(1), F(2), a[0], bb[1], a[1], n.prec == PREC_BF16X3 ? 1 : 2, app->d_gemm_ws,
+                             app->gemm_ws_bytes, s);
     }
     case OP_GEMM_BF16: {
         const auto &a = ir.bufs[n.b[0]].dims, &bb = ir.bufs[n.b[1]].dims;
@@ -278,6 +299,8 @@ hipError_t launch_nest(ofl_app *app, const Nest &n, void *const *dev, const int6
 int32_t kernel_launch_count(const Nest &n) {
     if (n.op == OP_INIT_UNIFORM) return (int32_t)n.b.size();
     if (n.op == OP_CAST_BF16) return (int32_t)(n.b.size() / 2);
+    if (n.op == OP_GEMM && n.prec == PREC_BF16X3) return 4;   // zero pad, split A, split B, product
+    if (n.op == OP_GEMM && n.prec == PREC_FP8X2) return 6;    // + row and column scales
     return 1;
 }
 

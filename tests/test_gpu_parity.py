@@ -37,16 +37,21 @@ def _run_and_compare(doc, genes, seed=1, inputs=None, policies=(ofl.RESIDENT,), 
     o = ir.load(doc)
     for name, arr in (inputs or {}).items():
         app.set_input(name, arr)
-    o32, o64 = parity.oracle_outputs(o, seed, inputs)
+    cache = {}
     bufs = app.alloc_device_buffers()
     for g in genes:
+        key = parity.offloaded_split(o, g)
+        if key not in cache:
+            cache[key] = parity.oracle_outputs(o, seed, inputs, offloaded=key)
+        o32, o64 = cache[key]
         for pol in policies:
             for fl in flags_list:
                 say("case", doc["name"], doc["params"], "gene", list(g), "policy", pol, "flags", fl)
                 st = app.run_pattern(g, bufs, policy=pol, flags=fl)
                 assert st["status"] == ofl.ST_OK
                 assert (st["bytes_h2d"], st["bytes_d2h"], st["n_copies"]) == app.plan_transfers(g, pol, fl)
-                bad = parity.compare(o, app.read_all(), o32, o64, names=names)
+                bad = parity.compare(o, app.read_all(), o32, o64, names=names,
+                                     rel_gemm=parity.rel_gemm_for(o, key))
                 assert not bad, (list(g), pol, fl, bad)
     return app, bufs
 
@@ -149,6 +154,119 @@ def test_gemm_bf16_shapes(M, N, K):
     A = OC.cast_bf16(OC.init_uniform(M * K, 4, 0).reshape(M, K))
     B = OC.cast_bf16(OC.init_uniform(K * N, 4, 1).reshape(K, N))
     _run_and_compare(doc, [[1]], inputs={"A": A, "B": B})
+
+
+# ---------------------------------------------------------------- split-precision GEMM
+SPLIT = ["bf16x3", "fp8x2"]
+
+
+def _wide(shape, seed):
+    """Signed values over ~10 decades: many land on e4m3 subnormals after scaling."""
+    r = np.random.default_rng(seed)
+    return (r.standard_normal(shape) * np.exp(r.uniform(-11, 11, shape))).astype(np.float32)
+
+
+@pytest.mark.parametrize("prec", SPLIT)
+@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (17, 33, 5), (130, 70, 37), (257, 129, 300), (384, 256, 200)])
+def test_gemm_split_shapes(prec, M, N, K):
+    # gene 1: the split product (oracle: its definition summed in FP64);
+    # gene 0: the nest as written, plain FP32 on the CPU
+    doc = appgen.gemm_app(M, N, K, prec=prec)
+    A = OC.init_uniform(M * K, 21, 0).reshape(M, K)
+    B = OC.init_uniform(K * N, 21, 1).reshape(K, N)
+    _run_and_compare(doc, [[1], [0]], inputs={"A": A, "B": B})
+
+
+@pytest.mark.parametrize("prec", SPLIT)
+def test_gemm_split_signed_wide_range(prec):
+    M, N, K = 200, 150, 333
+    A, B = _wide((M, K), 1), _wide((K, N), 2)
+    app = ofl.App(json.dumps(appgen.gemm_app(M, N, K, prec=prec)))
+    app.set_input("A", A)
+    app.set_input("B", B)
+    bufs = app.alloc_device_buffers()
+    say("case split wide", prec)
+    app.run_pattern([1], bufs)
+    got = app.read_buffer("C").astype(np.float64)
+    emu = OC.gemm_split_f64(A, B, prec)
+    mag = np.abs(A.astype(np.float64)) @ np.abs(B.astype(np.float64))
+    err = np.max(np.abs(got - emu) / mag)
+    say("split wide", prec, "max err / sum|a||b|", err)
+    assert err < (parity.REL_GEMM if prec == "bf16x3" else parity.REL_FP8_MFMA), err
+
+
+@pytest.mark.parametrize("prec", SPLIT)
+def test_gemm_split_identity_and_rank1_exact(prec):
+    # A = I: every output is hi + lo of one element of B, exact in FP32, so the
+    # GPU must equal the oracle's split bit for bit -- including e4m3
+    # subnormals, as B spans many decades within each column
+    for N in (64, 200):
+        app = ofl.App(json.dumps(appgen.gemm_app(N, N, N, prec=prec)))
+        B = _wide((N, N), N)
+        app.set_input("A", np.eye(N, dtype=np.float32))
+        app.set_input("B", B)
+        bufs = app.alloc_device_buffers()
+        say("case split identity", prec, N)
+        app.run_pattern([1], bufs)
+        want = OC.gemm_split_f64(np.eye(N, dtype=np.float32), B, prec).astype(np.float32)
+        assert np.array_equal(app.read_buffer("C"), want)
+        u = (np.arange(N) % 7 + 1).astype(np.float32)
+        v = (np.arange(N) % 5 + 1).astype(np.float32)
+        app.set_input("A", np.repeat(u[:, None], N, axis=1))
+        app.set_input("B", np.repeat(v[None, :], N, axis=0))
+        say("case split rank-1", prec, N)
+        app.run_pattern([1], bufs)
+        assert np.array_equal(app.read_buffer("C"), (N * np.outer(u, v)).astype(np.float32))
+
+
+@pytest.mark.parametrize("prec", SPLIT)
+def test_gemm_split_4096_sampled(prec):
+    # the GEMM of the precision workload at full size, sampled rows against
+    # the split definition (1e-5) and against the exact product (reported)
+    M = N = K = 4096
+    app = ofl.App(json.dumps(appgen.gemm_app(M, N, K, prec=prec)))
+    A = OC.init_uniform(M * K, 12, 0).reshape(M, K)
+    B = OC.init_uniform(K * N, 12, 1).reshape(K, N)
+    app.set_input("A", A)
+    app.set_input("B", B)
+    bufs = app.alloc_device_buffers()
+    say("case split 4096 sampled", prec)
+    app.run_pattern([1], bufs, flags=ofl.KEEP_OUTPUTS)
+    C = app.read_buffer("C").astype(np.float64)
+    rows = np.random.default_rng(1).choice(M, 8, replace=False)
+    emu = OC.gemm_split_f64(np.ascontiguousarray(A[rows]), B, prec)
+    exact = OC.gemm_f64(np.ascontiguousarray(A[rows]), B)
+    err_emu = np.max(np.abs(C[rows] - emu) / emu)
+    err_exact = np.max(np.abs(C[rows] - exact) / exact)
+    say("split 4096", prec, "max rel err vs split definition", err_emu, "vs exact product", err_exact)
+    assert err_emu < (parity.REL_GEMM if prec == "bf16x3" else parity.REL_FP8_MFMA), err_emu
+    assert err_exact < (1e-5 if prec == "bf16x3" else 1e-3), err_exact
+
+
+def test_gemm_fp8_run_truncation():
+    # the premise of the fp8 tolerance, through the product path: one row
+    # A = [416, 3 * 2^-8], B = [1; 1].  Scales 1/2 and 128 make every split
+    # exact (lo parts 0); the products 26624 and 0.75 share one run of 8, and
+    # 0.75 lies below 2^-14 of 2^14, so the MFMA drops it: C = 416 exactly,
+    # where the split definition gives 416 + 3 * 2^-8.
+    app = ofl.App(json.dumps(appgen.gemm_app(1, 1, 2, prec="fp8x2")))
+    app.set_input("A", np.array([[416.0, 3 * 2.0 ** -8]], np.float32))
+    app.set_input("B", np.ones((2, 1), np.float32))
+    bufs = app.alloc_device_buffers()
+    say("case fp8 run truncation")
+    app.run_pattern([1], bufs)
+    emu = OC.gemm_split_f64(np.array([[416.0, 3 * 2.0 ** -8]], np.float32), np.ones((2, 1), np.float32), "fp8x2")
+    assert emu[0, 0] == 416.0 + 3 * 2.0 ** -8
+    assert app.read_buffer("C")[0, 0] == 416.0
+
+
+def test_precision_app_reduced_all_forms():
+    # the precision workload at reduced size under each GEMM form, all-GPU and
+    # all-CPU genes
+    for prec in ["f32"] + SPLIT:
+        doc = workloads.app_doc("precision", N=160, I=13, J=17, K=67, SWEEPS=3)
+        doc["program"][1]["args"]["prec"] = prec
+        _run_and_compare(doc, [[1] * 4, [0] * 4, [1, 1, 0, 1]])
 
 
 # ---------------------------------------------------------------- stencil

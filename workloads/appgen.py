@@ -194,10 +194,10 @@ APPS = {"tiny": tiny, "medium": medium, "precision": precision, "large": large}
 
 
 # ---------------------------------------------------------------- test apps
-def gemm_app(M, N, K, op="gemm"):
+def gemm_app(M, N, K, op="gemm", prec=None):
     """One GEMM nest C[M][N] = A[M][K] B[K][N] with caller-supplied A, B."""
     dt = "bf16" if op == "gemm_bf16" else "f32"
-    nest = gemm_nest("A", "B", "C", op=op)
+    nest = gemm_nest("A", "B", "C", op=op, prec=prec)
     nest["loops"] = [["i", "0", "M"], ["j", "0", "NN"], ["k", "0", "KK"]]
     return {"name": "gemm", "params": {"M": M, "NN": N, "KK": K},
             "buffers": [{"name": "A", "dtype": dt, "dims": ["M", "KK"]},
