@@ -157,67 +157,6 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(const float *__restrict__
             }
 }
 
-// BF16 inputs: As[m][k] and Bs[n][k] (B transposed on its way into LDS) so
-// that each lane's 8 consecutive k values are one 16-byte LDS read.
-template <int BM, int BN>
-__global__ __launch_bounds__(kThreads) void k_gemm_bf16(const unsigned short *__restrict__ A,
-                                                        const unsigned short *__restrict__ B, float *__restrict__ C,
-                                                        int M, int N, int K) {
-    constexpr int BK = 32;
-    constexpr int WM = BM / 2, WN = BN / 2;
-    constexpr int TM = WM / 16, TN = WN / 16;
-    constexpr int LD = BK + 8;           // in bf16 elements (80 bytes per row)
-    __shared__ unsigned short As[BM * LD];
-    __shared__ unsigned short Bs[BN * LD];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
-    const int tiles_n = (N + BN - 1) / BN;
-    const int tiles = tiles_n * ((M + BM - 1) / BM);
-    const int t = xcd_swizzle(blockIdx.x, tiles);
-    const int m0 = (t / tiles_n) * BM, n0 = (t % tiles_n) * BN;
-    floatx4 acc[TM][TN];
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
-    const int r = lane & 15, g = lane >> 4;
-    for (int k0 = 0; k0 < K; k0 += BK) {
-        // A: BM x 32 elements, element-wise guarded
-        for (int idx = tid; idx < BM * BK; idx += kThreads) {
-            const int row = idx / BK, kk = idx % BK, gm = m0 + row, gk = k0 + kk;
-            As[row * LD + kk] = (gm < M && gk < K) ? A[(size_t)gm * K + gk] : (unsigned short)0;
-        }
-        // B: 32 x BN elements read along n, stored transposed
-        for (int idx = tid; idx < BK * BN; idx += kThreads) {
-            const int kk = idx / BN, col = idx % BN, gk = k0 + kk, gn = n0 + col;
-            Bs[col * LD + kk] = (gk < K && gn < N) ? B[(size_t)gk * N + gn] : (unsigned short)0;
-        }
-        __syncthreads();
-        bf16x8 af[TM], bfr[TN];
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-            af[i] = *reinterpret_cast<const bf16x8 *>(&As[(wm * WM + i * 16 + r) * LD + 8 * g]);
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-            bfr[j] = *reinterpret_cast<const bf16x8 *>(&Bs[(wn * WN + j * 16 + r) * LD + 8 * g]);
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int j = 0; j < TN; ++j)
-                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[i], bfr[j], acc[i][j], 0, 0, 0);
-        __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int row = m0 + wm * WM + i * 16 + 4 * g + e, col = n0 + wn * WN + j * 16 + r;
-                if (row < M && col < N) C[(size_t)row * N + col] = acc[i][j][e];
-            }
-}
-
 // Split-precision / low-precision product on k-contiguous operands:
 // C[i][j] = (sum_k A'[i][k] B'[j][k]) * sa[i] * sb[j]   (scales optional),
 // A' is Mp x Kp, B' is Np x Kp (B stored transposed), both zero-padded to
@@ -232,7 +171,6 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt(const T *__restrict__ A, c
                                                       const float *__restrict__ sa, const float *__restrict__ sb) {
     constexpr int SLAB = 128;                       // bytes of k per row per slab
     constexpr int LDS_ROW = SLAB + 16;              // padded row: conflict-free 16-byte reads
-    constexpr int EPB = SLAB / sizeof(T);           // elements per slab
     constexpr int WM = BM / 2, WN = BN / 2;
     constexpr int TM = WM / 16, TN = WN / 16;
     constexpr int A_PER = BM * SLAB / 16 / kThreads;
@@ -372,97 +310,114 @@ hipError_t gemm_f32(const float *A, const float *B, float *C, int64_t M, int64_t
     return launch_f32<64, 64, 32>(A, B, C, (int)M, (int)N, (int)K, s);
 }
 
-hipError_t gemm_bf16(const uint16_t *A, const uint16_t *B, float *C, int64_t M, int64_t N, int64_t K,
-                     hipStream_t s) {
-    if (M <= 0 || N <= 0) return hipSuccess;
-    if (K <= 0) return fill_zero(C, (uint64_t)M * N * sizeof(float), s);
-    if (M > (1 << 30) || N > (1 << 30) || K > (1 << 30)) return hipErrorInvalidValue;
-    const unsigned tiles = (unsigned)(((M + 63) / 64) * ((N + 63) / 64));
-    return launch((k_gemm_bf16<64, 64>), dim3(tiles), dim3(kThreads), 0, s,
-                       reinterpret_cast<const unsigned short *>(A), reinterpret_cast<const unsigned short *>(B), C,
-                       (int)M, (int)N, (int)K);
-}
-
 // ---------------------------------------------------------------- split-precision GEMM
 namespace {
 constexpr int kNT = 128;   // tile of the k-contiguous product (rows of A', rows of B')
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
-struct NtShape {
-    int64_t Mp, Np, Kp;    // padded rows of A', rows of B', k extent (elements)
+// Workspace layout of one product: [A' | B' | float area], A' omitted when
+// bf16 inputs are already tile-aligned.  float area (fp8 only): row scales,
+// column scales, their inverses, and per-slice column maxima.
+struct NtLayout {
+    int64_t Mp = 0, Np = 0, Kp = 0, kx = 0;
+    int elem = 2;
+    bool a_copy = true;    // A' is written (else A is used in place)
+    bool b_pad = true;     // B' has a padded region that must read as zero
+    int64_t a_bytes = 0, b_bytes = 0, f_off = 0, total = 0;
 };
 
-NtShape nt_shape(int64_t M, int64_t N, int64_t Kx, int elem) {
-    return {round_up(M, kNT), round_up(N, kNT), round_up(Kx, 128 / elem)};
+NtLayout nt_layout(int64_t M, int64_t N, int64_t K, int variant) {
+    NtLayout L;
+    L.elem = variant == 2 ? 1 : 2;
+    L.kx = variant == 3 ? K : 3 * K;
+    L.Mp = round_up(M, kNT);
+    L.Np = round_up(N, kNT);
+    L.Kp = round_up(L.kx, 128 / L.elem);
+    L.a_copy = variant != 3 || L.Mp != M || L.Kp != K;
+    L.b_pad = L.Np != N || L.Kp != L.kx;
+    L.a_bytes = L.a_copy ? L.Mp * L.Kp * L.elem : 0;
+    L.b_bytes = L.Np * L.Kp * L.elem;
+    L.f_off = round_up(L.a_bytes + L.b_bytes, 256);
+    const int64_t nf = variant == 2 ? 2 * (L.Mp + L.Np) + (int64_t)kColSlices * L.Np : 0;
+    L.total = round_up(L.f_off + nf * (int64_t)sizeof(float), 256);
+    return L;
+}
+
+bool nt_sizes_ok(int64_t M, int64_t N, int64_t K) {
+    return M <= (1 << 28) && N <= (1 << 22) && K <= (1 << 26);
 }
 }  // namespace
 
 int64_t gemm_workspace_bytes(int64_t M, int64_t N, int64_t K, int variant) {
-    if (M <= 0 || N <= 0 || K <= 0) return 0;
-    if (variant == 0) return 0;
-    const int elem = variant == 2 ? 1 : 2;
-    const int64_t kx = variant == 3 ? K : 3 * K;
-    const NtShape sh = nt_shape(M, N, kx, elem);
-    int64_t bytes = (sh.Mp + sh.Np) * sh.Kp * elem;
-    bytes = round_up(bytes, 256) + 4 * (sh.Mp + sh.Np) * (int64_t)sizeof(float);
-    return round_up(bytes, 256);
+    if (M <= 0 || N <= 0 || K <= 0 || variant < 1 || variant > 3) return 0;
+    return nt_layout(M, N, K, variant).total;
+}
+
+int gemm_launches(int64_t M, int64_t N, int64_t K, int variant) {
+    if (M <= 0 || N <= 0) return 0;
+    if (K <= 0) return 1;
+    if (variant == 0) return 1;
+    const NtLayout L = nt_layout(M, N, K, variant);
+    int n = (L.b_pad ? 1 : 0) + 2 + (L.a_copy ? 1 : 0);   // [zero B'], B', product, [A']
+    if (variant == 2) n += 3;                               // row scales, column maxima, column scales
+    return n;
 }
 
 hipError_t gemm_split(const float *A, const float *B, float *C, int64_t M, int64_t N, int64_t K, int variant,
                       void *ws, int64_t ws_bytes, hipStream_t s) {
     if (M <= 0 || N <= 0) return hipSuccess;
     if (K <= 0) return fill_zero(C, (uint64_t)M * N * sizeof(float), s);
-    if (variant != 1 && variant != 2) return hipErrorInvalidValue;
-    if (M > (1 << 29) || N > (1 << 29) || K > (1 << 28)) return hipErrorInvalidValue;
-    if (gemm_workspace_bytes(M, N, K, variant) > ws_bytes) return hipErrorInvalidValue;
-    const int elem = variant == 2 ? 1 : 2;
-    const NtShape sh = nt_shape(M, N, 3 * K, elem);
+    if ((variant != 1 && variant != 2) || !nt_sizes_ok(M, N, 3 * K)) return hipErrorInvalidValue;
+    const NtLayout L = nt_layout(M, N, K, variant);
+    if (L.total > ws_bytes || !ws) return hipErrorInvalidValue;
     unsigned char *w = static_cast<unsigned char *>(ws);
-    void *Ap = w;
-    void *Bp = w + sh.Mp * sh.Kp * elem;
-    float *f = reinterpret_cast<float *>(w + round_up((sh.Mp + sh.Np) * sh.Kp * elem, 256));
-    float *sa = f, *sb = f + sh.Mp, *isa = f + sh.Mp + sh.Np, *isb = isa + sh.Mp;
-    const unsigned tiles = (unsigned)((sh.Mp / kNT) * (sh.Np / kNT));
-    hipError_t e = fill_zero(Bp, (uint64_t)(sh.Np * sh.Kp * elem), s);
+    void *Ap = w, *Bp = w + L.a_bytes;
+    float *f = reinterpret_cast<float *>(w + L.f_off);
+    float *sa = f, *sb = f + L.Mp, *isa = sb + L.Np, *isb = isa + L.Mp, *colmax = isb + L.Np;
+    const unsigned tiles = (unsigned)((L.Mp / kNT) * (L.Np / kNT));
+    hipError_t e = L.b_pad ? fill_zero(Bp, (uint64_t)L.b_bytes, s) : hipSuccess;
     if (variant == 1) {
-        if (e == hipSuccess) e = split_a_bf16x3(A, static_cast<uint16_t *>(Ap), (int)M, (int)K, (int)sh.Mp, (int)sh.Kp, s);
-        if (e == hipSuccess) e = split_bt(B, Bp, nullptr, (int)K, (int)N, (int)sh.Kp, 0, s);
+        if (e == hipSuccess) e = prep_a(A, Ap, nullptr, (int)M, (int)K, (int)L.Mp, (int)L.Kp, 0, s);
+        if (e == hipSuccess) e = split_bt(B, Bp, nullptr, (int)K, (int)N, (int)L.Kp, 0, s);
         if (e == hipSuccess)
             e = launch((k_gemm_nt<unsigned short, kNT, kNT, false>), dim3(tiles), dim3(kThreads), 0, s,
                        static_cast<const unsigned short *>(Ap), static_cast<const unsigned short *>(Bp), C, (int)M,
-                       (int)N, (int)sh.Kp, (const float *)nullptr, (const float *)nullptr);
+                       (int)N, (int)L.Kp, (const float *)nullptr, (const float *)nullptr);
         return e;
     }
     if (e == hipSuccess) e = row_scales(A, sa, isa, (int)M, (int)K, s);
-    if (e == hipSuccess) e = col_scales(B, sb, isb, (int)K, (int)N, s);
-    if (e == hipSuccess) e = split_a_fp8x2(A, static_cast<uint8_t *>(Ap), sa, (int)M, (int)K, (int)sh.Mp, (int)sh.Kp, s);
-    if (e == hipSuccess) e = split_bt(B, Bp, sb, (int)K, (int)N, (int)sh.Kp, 1, s);
+    if (e == hipSuccess) e = col_scales(B, sb, isb, colmax, (int)K, (int)N, (int)L.Np, s);
+    if (e == hipSuccess) e = prep_a(A, Ap, sa, (int)M, (int)K, (int)L.Mp, (int)L.Kp, 1, s);
+    if (e == hipSuccess) e = split_bt(B, Bp, sb, (int)K, (int)N, (int)L.Kp, 1, s);
     if (e == hipSuccess)
         e = launch((k_gemm_nt<unsigned char, kNT, kNT, true>), dim3(tiles), dim3(kThreads), 0, s,
                    static_cast<const unsigned char *>(Ap), static_cast<const unsigned char *>(Bp), C, (int)M, (int)N,
-                   (int)sh.Kp, (const float *)isa, (const float *)isb);
+                   (int)L.Kp, (const float *)isa, (const float *)isb);
     return e;
 }
 
-hipError_t gemm_bf16_nt(const uint16_t *A, const uint16_t *B, float *C, int64_t M, int64_t N, int64_t K, void *ws,
-                        int64_t ws_bytes, hipStream_t s) {
+hipError_t gemm_bf16(const uint16_t *A, const uint16_t *B, float *C, int64_t M, int64_t N, int64_t K, void *ws,
+                     int64_t ws_bytes, hipStream_t s) {
     if (M <= 0 || N <= 0) return hipSuccess;
     if (K <= 0) return fill_zero(C, (uint64_t)M * N * sizeof(float), s);
-    if (M > (1 << 29) || N > (1 << 29) || K > (1 << 28)) return hipErrorInvalidValue;
-    if (gemm_workspace_bytes(M, N, K, 3) > ws_bytes) return hipErrorInvalidValue;
-    const NtShape sh = nt_shape(M, N, K, 2);
+    if (!nt_sizes_ok(M, N, K)) return hipErrorInvalidValue;
+    const NtLayout L = nt_layout(M, N, K, 3);
+    if (L.total > ws_bytes || !ws) return hipErrorInvalidValue;
     unsigned char *w = static_cast<unsigned char *>(ws);
-    uint16_t *Ap = reinterpret_cast<uint16_t *>(w);
-    void *Bp = w + sh.Mp * sh.Kp * 2;
-    const unsigned tiles = (unsigned)((sh.Mp / kNT) * (sh.Np / kNT));
-    hipError_t e = fill_zero(Bp, (uint64_t)(sh.Np * sh.Kp * 2), s);
-    if (e == hipSuccess) e = pad_a_bf16(A, Ap, (int)M, (int)K, (int)sh.Mp, (int)sh.Kp, s);
-    if (e == hipSuccess) e = split_bt(B, Bp, nullptr, (int)K, (int)N, (int)sh.Kp, 2, s);
+    void *Bp = w + L.a_bytes;
+    const void *Ause = A;
+    const unsigned tiles = (unsigned)((L.Mp / kNT) * (L.Np / kNT));
+    hipError_t e = L.b_pad ? fill_zero(Bp, (uint64_t)L.b_bytes, s) : hipSuccess;
+    if (L.a_copy) {
+        if (e == hipSuccess) e = prep_a(A, w, nullptr, (int)M, (int)K, (int)L.Mp, (int)L.Kp, 2, s);
+        Ause = w;
+    }
+    if (e == hipSuccess) e = split_bt(B, Bp, nullptr, (int)K, (int)N, (int)L.Kp, 2, s);
     if (e == hipSuccess)
         e = launch((k_gemm_nt<unsigned short, kNT, kNT, false>), dim3(tiles), dim3(kThreads), 0, s,
-                   static_cast<const unsigned short *>(static_cast<void *>(Ap)), static_cast<const unsigned short *>(Bp),
-                   C, (int)M, (int)N, (int)sh.Kp, (const float *)nullptr, (const float *)nullptr);
+                   static_cast<const unsigned short *>(Ause), static_cast<const unsigned short *>(Bp), C, (int)M,
+                   (int)N, (int)L.Kp, (const float *)nullptr, (const float *)nullptr);
     return e;
 }
 

@@ -64,38 +64,58 @@ __device__ inline float pow2_scale(float amax) {
     return ldexpf(1.0f, e);
 }
 
-// A' for BF16x3: rows i < M: [hi(A[i]) | hi(A[i]) | lo(A[i]) | 0 ...]; padded rows 0.
-__global__ __launch_bounds__(kThreads) void k_split_a_bf16(const float *__restrict__ A, unsigned short *__restrict__ Ap,
-                                                           int M, int K, int Mp, int Kp) {
-    const int64_t total = (int64_t)Mp * Kp;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += stride) {
-        const int i = (int)(e / Kp), kp = (int)(e % Kp);
-        unsigned short v = 0;
-        if (i < M && kp < 3 * K) {
-            const int seg = kp / K, kk = kp - seg * K;
-            const Bf16Parts s = split_bf16(A[(size_t)i * K + kk]);
-            v = seg == 2 ? s.lo : s.hi;
+// A' rows.  Each thread reads kPrepV elements of A (lanes on consecutive k,
+// so every load and store instruction is coalesced) and writes each one's
+// parts to all segments of the row: MODE 0 bf16 split [hi | hi | lo],
+// MODE 1 e4m3 split of A * sa[i], MODE 2 plain bf16 copy.  The same threads
+// zero the row's padding k' >= kx; rows i >= M are written as zero.
+constexpr int kPrepV = 4;
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_prep_a(const void *__restrict__ Av, void *__restrict__ Apv,
+                                                     const float *__restrict__ sa, int M, int K, int Kp, int kx) {
+    constexpr int nseg = MODE == 2 ? 1 : 3;
+    const int i = blockIdx.x;
+    const int pad = Kp - kx;                  // zero tail of the row
+    const float scale = (MODE == 1 && i < M) ? sa[i] : 1.0f;
+#pragma unroll
+    for (int e = 0; e < kPrepV; ++e) {
+        const int kk = (blockIdx.y * kPrepV + e) * kThreads + threadIdx.x;
+        if (kk < K) {
+            unsigned hi = 0, lo = 0;
+            if (i < M) {
+                if (MODE == 2) {
+                    hi = static_cast<const unsigned short *>(Av)[(size_t)i * K + kk];
+                } else {
+                    const float a = static_cast<const float *>(Av)[(size_t)i * K + kk];
+                    if (MODE == 0) {
+                        const Bf16Parts p = split_bf16(a);
+                        hi = p.hi;
+                        lo = p.lo;
+                    } else {
+                        const Fp8Parts p = split_fp8(a * scale);
+                        hi = p.hi;
+                        lo = p.lo;
+                    }
+                }
+            }
+            if (MODE == 1) {
+                unsigned char *row = static_cast<unsigned char *>(Apv) + (size_t)i * Kp;
+                row[kk] = (unsigned char)hi;
+                row[K + kk] = (unsigned char)hi;
+                row[2 * K + kk] = (unsigned char)lo;
+            } else {
+                unsigned short *row = static_cast<unsigned short *>(Apv) + (size_t)i * Kp;
+                row[kk] = (unsigned short)hi;
+                if (nseg == 3) {
+                    row[K + kk] = (unsigned short)hi;
+                    row[2 * K + kk] = (unsigned short)lo;
+                }
+            }
         }
-        Ap[e] = v;
-    }
-}
-
-// A' for FP8x2 with row scales sa (1/s stored in inv_sa).
-__global__ __launch_bounds__(kThreads) void k_split_a_fp8(const float *__restrict__ A, unsigned char *__restrict__ Ap,
-                                                          const float *__restrict__ sa, int M, int K, int Mp,
-                                                          int Kp) {
-    const int64_t total = (int64_t)Mp * Kp;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += stride) {
-        const int i = (int)(e / Kp), kp = (int)(e % Kp);
-        unsigned char v = 0;
-        if (i < M && kp < 3 * K) {
-            const int seg = kp / K, kk = kp - seg * K;
-            const Fp8Parts s = split_fp8(A[(size_t)i * K + kk] * sa[i]);
-            v = seg == 2 ? s.lo : s.hi;
+        if (kk < pad) {
+            if (MODE == 1) static_cast<unsigned char *>(Apv)[(size_t)i * Kp + kx + kk] = 0;
+            else static_cast<unsigned short *>(Apv)[(size_t)i * Kp + kx + kk] = 0;
         }
-        Ap[e] = v;
     }
 }
 
@@ -142,17 +162,6 @@ __global__ __launch_bounds__(kThreads) void k_split_bt(const void *__restrict__ 
     }
 }
 
-// A'' for the bf16-input product: A copied into the padded, tile-aligned layout.
-__global__ __launch_bounds__(kThreads) void k_pad_a_bf16(const unsigned short *__restrict__ A,
-                                                         unsigned short *__restrict__ Ap, int M, int K, int Mp, int Kp) {
-    const int64_t total = (int64_t)Mp * Kp;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total; e += stride) {
-        const int i = (int)(e / Kp), kp = (int)(e % Kp);
-        Ap[e] = (i < M && kp < K) ? A[(size_t)i * K + kp] : (unsigned short)0;
-    }
-}
-
 // Row scales of A: one wave per row, max |A[i][k]| -> s_i; inv_s_i.
 __global__ __launch_bounds__(kThreads) void k_row_scale(const float *__restrict__ A, float *__restrict__ s,
                                                         float *__restrict__ inv, int M, int K) {
@@ -169,48 +178,46 @@ __global__ __launch_bounds__(kThreads) void k_row_scale(const float *__restrict_
     }
 }
 
-// Column scales of B: a block of 256 threads takes 64 columns and 4 slices
-// of k, then combines the slices in LDS.
-__global__ __launch_bounds__(kThreads) void k_col_scale(const float *__restrict__ B, float *__restrict__ s,
-                                                        float *__restrict__ inv, int K, int N) {
-    __shared__ float part[4][64];
-    const int tx = threadIdx.x & 63, slice = threadIdx.x >> 6;
+// Column maxima of |B| in two deterministic stages: block (x, y) takes 64
+// columns and slice y of the k range, combining its 4 row lanes in LDS;
+// then one thread per column reduces the kColSlices partial maxima.
+__global__ __launch_bounds__(kThreads) void k_col_max(const float *__restrict__ B, float *__restrict__ part, int K,
+                                                      int N, int ld_part) {
+    __shared__ float red[4][64];
+    const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
     const int j = blockIdx.x * 64 + tx;
+    const int rows = (K + kColSlices - 1) / kColSlices;
+    const int k0 = blockIdx.y * rows, k1 = min(K, k0 + rows);
     float m = 0.0f;
     if (j < N)
-        for (int k = slice; k < K; k += 4) m = fmaxf(m, fabsf(B[(size_t)k * N + j]));
-    part[slice][tx] = m;
+        for (int k = k0 + ty; k < k1; k += 4) m = fmaxf(m, fabsf(B[(size_t)k * N + j]));
+    red[ty][tx] = m;
     __syncthreads();
-    if (slice == 0 && j < N) {
-        m = fmaxf(fmaxf(part[0][tx], part[1][tx]), fmaxf(part[2][tx], part[3][tx]));
-        const float sc = pow2_scale(m);
-        s[j] = sc;
-        inv[j] = 1.0f / sc;
-    }
+    if (ty == 0 && j < N)
+        part[(size_t)blockIdx.y * ld_part + j] = fmaxf(fmaxf(red[0][tx], red[1][tx]), fmaxf(red[2][tx], red[3][tx]));
 }
 
-unsigned grid_elems(int64_t n) {
-    int64_t b = (n + kThreads * 4 - 1) / (kThreads * 4);
-    if (b < 1) b = 1;
-    if (b > 8192) b = 8192;
-    return (unsigned)b;
+__global__ __launch_bounds__(kThreads) void k_col_scale(const float *__restrict__ part, float *__restrict__ s,
+                                                        float *__restrict__ inv, int N, int ld_part) {
+    const int j = blockIdx.x * kThreads + threadIdx.x;
+    if (j >= N) return;
+    float m = 0.0f;
+    for (int y = 0; y < kColSlices; ++y) m = fmaxf(m, part[(size_t)y * ld_part + j]);
+    const float sc = pow2_scale(m);
+    s[j] = sc;
+    inv[j] = 1.0f / sc;
 }
 
 }  // namespace
 
-hipError_t split_a_bf16x3(const float *A, uint16_t *Ap, int M, int K, int Mp, int Kp, hipStream_t s) {
-    return launch(k_split_a_bf16, dim3(grid_elems((int64_t)Mp * Kp)), dim3(kThreads), 0, s, A,
-                  reinterpret_cast<unsigned short *>(Ap), M, K, Mp, Kp);
-}
-
-hipError_t split_a_fp8x2(const float *A, uint8_t *Ap, const float *sa, int M, int K, int Mp, int Kp, hipStream_t s) {
-    return launch(k_split_a_fp8, dim3(grid_elems((int64_t)Mp * Kp)), dim3(kThreads), 0, s, A,
-                  reinterpret_cast<unsigned char *>(Ap), sa, M, K, Mp, Kp);
-}
-
-hipError_t pad_a_bf16(const uint16_t *A, uint16_t *Ap, int M, int K, int Mp, int Kp, hipStream_t s) {
-    return launch(k_pad_a_bf16, dim3(grid_elems((int64_t)Mp * Kp)), dim3(kThreads), 0, s,
-                  reinterpret_cast<const unsigned short *>(A), reinterpret_cast<unsigned short *>(Ap), M, K, Mp, Kp);
+hipError_t prep_a(const void *A, void *Ap, const float *sa, int M, int K, int Mp, int Kp, int mode, hipStream_t s) {
+    const int kx = mode == 2 ? K : 3 * K;
+    const int span = K > Kp - kx ? K : Kp - kx;   // k range the threads of one row cover
+    const dim3 grid((unsigned)Mp, (unsigned)((span + kThreads * kPrepV - 1) / (kThreads * kPrepV)));
+    if (grid.y > 65535 || K <= 0) return hipErrorInvalidValue;
+    if (mode == 0) return launch((k_prep_a<0>), grid, dim3(kThreads), 0, s, A, Ap, sa, M, K, Kp, kx);
+    if (mode == 1) return launch((k_prep_a<1>), grid, dim3(kThreads), 0, s, A, Ap, sa, M, K, Kp, kx);
+    return launch((k_prep_a<2>), grid, dim3(kThreads), 0, s, A, Ap, sa, M, K, Kp, kx);
 }
 
 hipError_t split_bt(const void *B, void *Bt, const float *sb, int K, int N, int Kp, int mode, hipStream_t s) {
@@ -226,8 +233,13 @@ hipError_t row_scales(const float *A, float *s_out, float *inv_out, int M, int K
     return launch(k_row_scale, dim3(blocks), dim3(kThreads), 0, s, A, s_out, inv_out, M, K);
 }
 
-hipError_t col_scales(const float *B, float *s_out, float *inv_out, int K, int N, hipStream_t s) {
-    return launch(k_col_scale, dim3((unsigned)((N + 63) / 64)), dim3(kThreads), 0, s, B, s_out, inv_out, K, N);
+hipError_t col_scales(const float *B, float *s_out, float *inv_out, float *part, int K, int N, int ld_part,
+                      hipStream_t s) {
+    hipError_t e = launch(k_col_max, dim3((unsigned)((N + 63) / 64), (unsigned)kColSlices), dim3(kThreads), 0, s, B,
+                          part, K, N, ld_part);
+    if (e != hipSuccess) return e;
+    return launch(k_col_scale, dim3((unsigned)((N + kThreads - 1) / kThreads)), dim3(kThreads), 0, s,
+                  (const float *)part, s_out, inv_out, N, ld_part);
 }
 
 }  // namespace k

@@ -30,23 +30,22 @@ hipError_t stencil19(const float *p, float *q, int64_t I, int64_t J, int64_t K, 
                      const ReduceScratch &rs, hipStream_t s);
 hipError_t copy_interior(float *p, const float *q, int64_t I, int64_t J, int64_t K, hipStream_t s);
 hipError_t gemm_f32(const float *A, const float *B, float *C, int64_t M, int64_t N, int64_t K, hipStream_t s);
-hipError_t gemm_bf16(const uint16_t *A, const uint16_t *B, float *C, int64_t M, int64_t N, int64_t K,
-                     hipStream_t s);
 
-// Split-precision products (variant 1 = BF16x3, 2 = FP8x2; 3 = bf16 inputs):
-// operands are prepared in the caller-provided workspace, then one MFMA
-// product over k-contiguous, tile-padded operands.
+// Products on MFMA over k-contiguous, tile-padded operands prepared in a
+// caller-provided workspace.  variant 1 = BF16x3 and 2 = FP8x2 (FP32 inputs
+// split into hi/lo parts, one refinement pass), 3 = bf16 inputs.
+constexpr int kColSlices = 32;   // k slices of the column-maximum pass
 int64_t gemm_workspace_bytes(int64_t M, int64_t N, int64_t K, int variant);
+int gemm_launches(int64_t M, int64_t N, int64_t K, int variant);
 hipError_t gemm_split(const float *A, const float *B, float *C, int64_t M, int64_t N, int64_t K, int variant,
                       void *ws, int64_t ws_bytes, hipStream_t s);
-hipError_t gemm_bf16_nt(const uint16_t *A, const uint16_t *B, float *C, int64_t M, int64_t N, int64_t K, void *ws,
-                        int64_t ws_bytes, hipStream_t s);
-hipError_t split_a_bf16x3(const float *A, uint16_t *Ap, int M, int K, int Mp, int Kp, hipStream_t s);
-hipError_t split_a_fp8x2(const float *A, uint8_t *Ap, const float *sa, int M, int K, int Mp, int Kp, hipStream_t s);
-hipError_t pad_a_bf16(const uint16_t *A, uint16_t *Ap, int M, int K, int Mp, int Kp, hipStream_t s);
+hipError_t gemm_bf16(const uint16_t *A, const uint16_t *B, float *C, int64_t M, int64_t N, int64_t K, void *ws,
+                     int64_t ws_bytes, hipStream_t s);
+hipError_t prep_a(const void *A, void *Ap, const float *sa, int M, int K, int Mp, int Kp, int mode, hipStream_t s);
 hipError_t split_bt(const void *B, void *Bt, const float *sb, int K, int N, int Kp, int mode, hipStream_t s);
 hipError_t row_scales(const float *A, float *s_out, float *inv_out, int M, int K, hipStream_t s);
-hipError_t col_scales(const float *B, float *s_out, float *inv_out, int K, int N, hipStream_t s);
+hipError_t col_scales(const float *B, float *s_out, float *inv_out, float *part, int K, int N, int ld_part,
+                      hipStream_t s);
 
 // Upper bound on partials the reductions need for a problem size.
 int64_t sumsq_partials(int64_t n);

@@ -170,6 +170,12 @@ void restore_host(ofl_app *app, int b) {
     app->host_dirty[b] = 0;
 }
 
+// Kernel variant of a GEMM nest (as numbered by the k:: GEMM launchers).
+int gemm_variant(const Nest &n) {
+    if (n.op == OP_GEMM_BF16) return 3;
+    return n.prec == PREC_BF16X3 ? 1 : (n.prec == PREC_FP8X2 ? 2 : 0);
+}
+
 int ensure_device(ofl_app *app) {
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
@@ -198,9 +204,9 @@ int ensure_device(ofl_app *app) {
     }
     int64_t ws = 0;
     for (const auto &n : app->ir.nests) {
-        if (n.op != OP_GEMM || n.prec == PREC_F32) continue;
+        if ((n.op != OP_GEMM && n.op != OP_GEMM_BF16) || gemm_variant(n) == 0) continue;
         const auto &a = app->ir.bufs[n.b[0]].dims, &bb = app->ir.bufs[n.b[1]].dims;
-        ws = std::max(ws, k::gemm_workspace_bytes(a[0], bb[1], a[1], n.prec == PREC_BF16X3 ? 1 : 2));
+        ws = std::max(ws, k::gemm_workspace_bytes(a[0], bb[1], a[1], gemm_variant(n)));
     }
     if (ws > 0) {
         void *w = nullptr;
@@ -260,13 +266,13 @@ hipError_t launch_nest(ofl_app *app, const Nest &n, void *const *dev, const int6
     case OP_GEMM: {
         const auto &a = ir.bufs[n.b[0]].dims, &bb = ir.bufs[n.b[1]].dims;
         if (n.prec == PREC_F32) return k::gemm_f32(F(0), F(1), F(2), a[0], bb[1], a[1], s);
-        return k::gemm_split(F(0), F(1), F(2), a[0], bb[1], a[1], n.prec == PREC_BF16X3 ? 1 : 2, app->d_gemm_ws,
+        return k::gemm_split(F(0), F(1), F(2), a[0], bb[1], a[1], gemm_variant(n), app->d_gemm_ws,
                              app->gemm_ws_bytes, s);
     }
     case OP_GEMM_BF16: {
         const auto &a = ir.bufs[n.b[0]].dims, &bb = ir.bufs[n.b[1]].dims;
         return k::gemm_bf16(static_cast<const uint16_t *>(dev[n.b[0]]), static_cast<const uint16_t *>(dev[n.b[1]]),
-                            F(2), a[0], bb[1], a[1], s);
+                            F(2), a[0], bb[1], a[1], app->d_gemm_ws, app->gemm_ws_bytes, s);
     }
     case OP_ADD_SCALED: return k::add_scaled(F(0), F(1), (float)n.alpha, cnt(0), s);
     case OP_AVG2: return k::avg2(F(0), F(1), F(2), cnt(0), s);
@@ -296,11 +302,13 @@ hipError_t launch_nest(ofl_app *app, const Nest &n, void *const *dev, const int6
     }
 }
 
-int32_t kernel_launch_count(const Nest &n) {
+int32_t kernel_launch_count(const AppIR &ir, const Nest &n) {
     if (n.op == OP_INIT_UNIFORM) return (int32_t)n.b.size();
     if (n.op == OP_CAST_BF16) return (int32_t)(n.b.size() / 2);
-    if (n.op == OP_GEMM && n.prec == PREC_BF16X3) return 4;   // zero pad, split A, split B, product
-    if (n.op == OP_GEMM && n.prec == PREC_FP8X2) return 6;    // + row and column scales
+    if (n.op == OP_GEMM || n.op == OP_GEMM_BF16) {
+        const auto &a = ir.bufs[n.b[0]].dims, &bb = ir.bufs[n.b[1]].dims;
+        return k::gemm_launches(a[0], bb[1], a[1], gemm_variant(n));
+    }
     return 1;
 }
 
@@ -412,7 +420,7 @@ RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *co
             const bool tm = app->timing && ev_next + 2 <= app->events.size();
             // a single-launch nest gets its events in the dispatch packet itself
             // (kernel-only interval); a multi-launch nest is bracketed by events
-            const bool single = kernel_launch_count(n) == 1;
+            const bool single = kernel_launch_count(ir, n) == 1;
             if (tm && single) k::arm_launch_events(app->events[ev_next], app->events[ev_next + 1]);
             if (tm && !single) (void)hipEventRecord(app->events[ev_next], stream);
             e = launch_nest(app, n, dev, plan.env.data() + step.env, stream);
@@ -426,7 +434,7 @@ RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *co
                 timed.emplace_back(step.idx, (int)ev_next);
                 ev_next += 2;
             }
-            st.n_launches += kernel_launch_count(n);
+            st.n_launches += kernel_launch_count(ir, n);
             pending = true;
             break;
         }
@@ -467,7 +475,7 @@ RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *co
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, app->events[te.second], app->events[te.second + 1]) == hipSuccess) {
             auto &ks = app->kstats[op_name(ir.nests[te.first].op)];
-            ks.first += kernel_launch_count(ir.nests[te.first]);
+            ks.first += kernel_launch_count(ir, ir.nests[te.first]);
             ks.second += ms;
         }
     }
@@ -569,7 +577,7 @@ int build_graphs(ofl_app *app, const std::vector<uint8_t> &placement, void *cons
         case ST_D2H: e = hipMemcpyAsync(app->host[st.idx], dev[st.idx], buf->nbytes, hipMemcpyDeviceToHost, cs); break;
         case ST_GPU:
             e = launch_nest(app, ir.nests[st.idx], dev, plan.env.data() + st.env, cs);
-            ge.launches += kernel_launch_count(ir.nests[st.idx]);
+            ge.launches += kernel_launch_count(ir, ir.nests[st.idx]);
             break;
         case ST_CPU: {
             std::unique_ptr<HostTask> t(new HostTask());
