@@ -59,7 +59,9 @@ enum {
     OFL_E_MISMATCH = -11,    /* output check failed */
     OFL_E_STATE = -12,       /* call out of order (e.g. read before any run) */
     OFL_E_NOMEM = -13,       /* host or device allocation failed */
-    OFL_E_RANGE = -14        /* index out of range */
+    OFL_E_RANGE = -14,       /* index out of range */
+    OFL_E_UNSUPPORTED = -15  /* batch: a nest without a grouped kernel, or
+                                instances that differ in structure */
 };
 
 /* Parallelisability verdict of a nest and the reason of a rejection
@@ -256,6 +258,89 @@ int ofl_set_kernel_timing(ofl_app *app, int32_t enable);
 /* Accumulated launches and total kernel time (ms) of op kind `op`
  * (e.g. "stencil19", "gemm") since timing was enabled.  Unknown op: zeros. */
 int ofl_kernel_stats(const ofl_app *app, const char *op, int64_t *launches, double *total_ms);
+
+/* ---------------------------------------------------------------- instance batches */
+
+/* Many instances of one application description that differ only in their
+ * parameter values (sizes) and seeds, run with every nest on the GPU: the
+ * batching configuration (uneven instance sizes in one persistent launch per
+ * nest, the iterated sweeps captured in a HIP graph, tile shapes chosen by the
+ * library's own tuner).  Each nest of the program runs as ONE grouped launch
+ * that covers that nest in all instances; results equal those of running
+ * every instance alone under the all-GPU gene (bit-identical wherever the
+ * arithmetic is fixed; the product within the FP32 GEMM tolerance, as its
+ * tile shape is tuned).  Supported nests: init_uniform, FP32 gemm, stencil19,
+ * copy_interior.  Buffers: bufs[inst * n_bufs + buf], caller-owned device
+ * pointers, 16-byte aligned, sized by ofl_batch_buf_bytes. */
+typedef struct ofl_batch ofl_batch;
+
+enum {
+    OFL_BATCH_LOOP = 0,           /* per-instance launches, instance after instance */
+    OFL_BATCH_GROUPED = 1,        /* one grouped launch per nest execution */
+    OFL_BATCH_GROUPED_GRAPH = 2   /* the grouped launches as one captured HIP graph */
+};
+
+typedef struct {
+    int32_t gemm_cfg;               /* tile shape index: 0..5 = (64,16) (64,32) (64,64)
+                                       (128,16) (128,32) (128,64) as (BM = BN, BK) */
+    int32_t gemm_blocks_per_cu;     /* persistent blocks per CU (1..8, <= occupancy) */
+    int32_t stencil_rows;           /* rows per sweep item: 2, 4 or 8 */
+    int32_t stencil_planes;         /* planes per sweep item (>= 1) */
+    int32_t stencil_blocks_per_cu;  /* persistent blocks per CU */
+} ofl_batch_config;
+
+typedef struct {
+    double t_total_s;        /* wall time from the first launch to completion */
+    int32_t n_launches;      /* kernel launches (inside the graph for mode 2) */
+    int32_t n_submissions;   /* host submissions: launches, or 1 graph launch */
+    int32_t status;          /* OFL_ST_* */
+} ofl_batch_stats;
+
+typedef struct {
+    int32_t phase;           /* 0 = product, 1 = sweep */
+    ofl_batch_config cfg;    /* the candidate */
+    double ms;               /* median launch time */
+} ofl_tune_entry;
+
+/* Parse `app_json` once per instance with its parameter values
+ * param_values[inst * n_params + p] for the names param_names[p] (each must
+ * be a parameter the description declares) and its seed seeds[inst].
+ * Errors: OFL_E_ARG, OFL_E_PARSE, OFL_E_IR, OFL_E_NOT_PARALLEL (a rejected
+ * nest), OFL_E_UNSUPPORTED, OFL_E_NOMEM. */
+int ofl_batch_create(const char *app_json, int32_t n_inst, const char *const *param_names, int32_t n_params,
+                     const int64_t *param_values, const uint64_t *seeds, ofl_batch **out);
+void ofl_batch_free(ofl_batch *batch);
+int ofl_batch_info(const ofl_batch *batch, int32_t *n_inst, int32_t *n_bufs, int32_t *n_nests);
+/* Size in bytes, dtype (OFL_F32 / OFL_F64 / OFL_BF16) and rank of buffer `buf`
+ * of instance `inst`; its extents (min(rank, cap) written); its name (the
+ * same in every instance, NUL-terminated, truncated to cap).  OFL_E_RANGE. */
+int ofl_batch_buf_info(const ofl_batch *batch, int32_t inst, int32_t buf, uint64_t *bytes, int32_t *dtype,
+                       int32_t *rank);
+int ofl_batch_buf_dims(const ofl_batch *batch, int32_t inst, int32_t buf, int64_t *dims, int32_t cap);
+int ofl_batch_buf_name(const ofl_batch *batch, int32_t buf, char *name, int32_t cap);
+
+/* Write every buffer's set-up content (sine fields, zeros) into the device
+ * buffers; synchronous, untimed.  Errors: OFL_E_BUF, OFL_E_HIP, OFL_E_NOMEM. */
+int ofl_batch_setup(ofl_batch *batch, void *const *bufs, int32_t n_ptrs, void *stream);
+
+/* Run the program of every instance once in `mode` on `stream`; synchronous.
+ * Errors: OFL_E_ARG, OFL_E_BUF, OFL_E_HIP, OFL_E_NOMEM. */
+int ofl_batch_run(ofl_batch *batch, void *const *bufs, int32_t n_ptrs, void *stream, int32_t mode,
+                  ofl_batch_stats *stats);
+
+int ofl_batch_get_config(const ofl_batch *batch, ofl_batch_config *cfg);
+/* Errors: OFL_E_ARG for a value outside the ranges above. */
+int ofl_batch_set_config(ofl_batch *batch, const ofl_batch_config *cfg);
+
+/* Autotune the grouped product and sweep: every tile shape x blocks per CU
+ * in {1,2,4,8} within occupancy (product), every rows in {2,4,8} x planes in
+ * {8,16,32} x blocks per CU (sweep), each timed as the median of `reps`
+ * launches after one warm-up on the batch's own buffers (contents change:
+ * call ofl_batch_setup afterwards).  The fastest of each phase becomes the
+ * configuration; min(cap, count) entries are written, *n_entries = count.
+ * Errors: as ofl_batch_run. */
+int ofl_batch_tune(ofl_batch *batch, void *const *bufs, int32_t n_ptrs, void *stream, int32_t reps,
+                   ofl_tune_entry *entries, int32_t cap, int32_t *n_entries);
 
 /* ---------------------------------------------------------------- status */
 const char *ofl_status_str(int32_t code);

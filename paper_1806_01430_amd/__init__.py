@@ -17,12 +17,13 @@ APPS_DIR = os.path.join(HERE, "apps")
 OK = 0
 E = {-1: "E_ARG", -2: "E_IO", -3: "E_PARSE", -4: "E_IR", -5: "E_GENE_LEN", -6: "E_GENE_BIT",
      -7: "E_NOT_PARALLEL", -8: "E_BUF", -9: "E_HIP", -10: "E_TIMEOUT", -11: "E_MISMATCH",
-     -12: "E_STATE", -13: "E_NOMEM", -14: "E_RANGE"}
+     -12: "E_STATE", -13: "E_NOMEM", -14: "E_RANGE", -15: "E_UNSUPPORTED"}
 PARALLEL, PARALLEL_REDUCTION, REJECT = 0, 1, 2
 R_NONE, R_DATA_DEP, R_EXTERNAL_CALL, R_BREAK = 0, 1, 2, 3
 RESIDENT, PER_REGION = 0, 1
 PRESTAGED, KEEP_OUTPUTS, GRAPH = 1, 2, 4
 ST_OK, ST_TIMEOUT, ST_FAILED = 0, 1, 2
+BATCH_LOOP, BATCH_GROUPED, BATCH_GROUPED_GRAPH = 0, 1, 2
 _NP_DTYPE = {0: np.float32, 1: np.float64, 2: np.uint16}
 
 # names declared in include/ofl.h (checked by the ABI test)
@@ -30,7 +31,9 @@ EXPORTS = ["ofl_app_load", "ofl_app_load_json", "ofl_app_free", "ofl_app_info", 
            "ofl_nest_name", "ofl_buf_info", "ofl_buf_name", "ofl_buf_dims", "ofl_set_input", "ofl_mask_to_gene",
            "ofl_plan_transfers", "ofl_run_pattern", "ofl_eval_population", "ofl_ga_run",
            "ofl_ga_run_table", "ofl_read_buffer", "ofl_set_kernel_timing", "ofl_kernel_stats",
-           "ofl_status_str", "ofl_last_error"]
+           "ofl_batch_create", "ofl_batch_free", "ofl_batch_info", "ofl_batch_buf_info", "ofl_batch_buf_dims",
+           "ofl_batch_buf_name", "ofl_batch_setup", "ofl_batch_run", "ofl_batch_get_config",
+           "ofl_batch_set_config", "ofl_batch_tune", "ofl_status_str", "ofl_last_error"]
 
 
 class OflError(RuntimeError):
@@ -70,6 +73,27 @@ class GaResult(ctypes.Structure):
                 ("best_time", ctypes.c_double), ("best_fitness", ctypes.c_double), ("t_all0", ctypes.c_double),
                 ("n_measured", ctypes.c_int32), ("n_generations", ctypes.c_int32),
                 ("search_wall_s", ctypes.c_double), ("time_to_best_s", ctypes.c_double)]
+
+
+class BatchConfig(ctypes.Structure):
+    _fields_ = [("gemm_cfg", ctypes.c_int32), ("gemm_blocks_per_cu", ctypes.c_int32),
+                ("stencil_rows", ctypes.c_int32), ("stencil_planes", ctypes.c_int32),
+                ("stencil_blocks_per_cu", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class BatchStats(ctypes.Structure):
+    _fields_ = [("t_total_s", ctypes.c_double), ("n_launches", ctypes.c_int32), ("n_submissions", ctypes.c_int32),
+                ("status", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class TuneEntry(ctypes.Structure):
+    _fields_ = [("phase", ctypes.c_int32), ("cfg", BatchConfig), ("ms", ctypes.c_double)]
 
 
 _lib = None
@@ -115,6 +139,21 @@ def lib():
             "ofl_set_kernel_timing": (_I, [_P, _I]),
             "ofl_kernel_stats": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(ctypes.c_double)]),
+            "ofl_batch_create": (_I, [ctypes.c_char_p, _I, ctypes.POINTER(ctypes.c_char_p), _I,
+                                      ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_uint64),
+                                      ctypes.POINTER(_P)]),
+            "ofl_batch_free": (None, [_P]),
+            "ofl_batch_info": (_I, [_P, ctypes.POINTER(_I), ctypes.POINTER(_I), ctypes.POINTER(_I)]),
+            "ofl_batch_buf_info": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(_I),
+                                        ctypes.POINTER(_I)]),
+            "ofl_batch_buf_dims": (_I, [_P, _I, _I, ctypes.POINTER(ctypes.c_int64), _I]),
+            "ofl_batch_buf_name": (_I, [_P, _I, ctypes.c_char_p, _I]),
+            "ofl_batch_setup": (_I, [_P, ctypes.POINTER(_P), _I, _P]),
+            "ofl_batch_run": (_I, [_P, ctypes.POINTER(_P), _I, _P, _I, ctypes.POINTER(BatchStats)]),
+            "ofl_batch_get_config": (_I, [_P, ctypes.POINTER(BatchConfig)]),
+            "ofl_batch_set_config": (_I, [_P, ctypes.POINTER(BatchConfig)]),
+            "ofl_batch_tune": (_I, [_P, ctypes.POINTER(_P), _I, _P, _I, ctypes.POINTER(TuneEntry), _I,
+                                    ctypes.POINTER(_I)]),
             "ofl_status_str": (ctypes.c_char_p, [_I]),
             "ofl_last_error": (ctypes.c_char_p, []),
         }
@@ -337,3 +376,102 @@ class App:
         n, ms = ctypes.c_int64(), ctypes.c_double()
         _check(lib().ofl_kernel_stats(self._h, op.encode(), ctypes.byref(n), ctypes.byref(ms)), "ofl_kernel_stats")
         return n.value, ms.value
+
+
+class Batch:
+    """Instances of one application description with per-instance parameter
+    values and seeds, every nest on the GPU (owns an ofl_batch handle)."""
+
+    def __init__(self, src, params, seeds):
+        """src: description (dict or JSON text); params: list of dicts (one per
+        instance, same keys); seeds: one integer per instance."""
+        import json
+        if isinstance(src, dict):
+            src = json.dumps(src)
+        n = len(params)
+        names = sorted(params[0]) if n else []
+        for p in params:
+            if sorted(p) != names:
+                raise ValueError("every instance must set the same parameters")
+        cn = (ctypes.c_char_p * max(1, len(names)))(*[x.encode() for x in names])
+        vals = np.ascontiguousarray([[int(p[k]) for k in names] for p in params], np.int64).reshape(-1)
+        sd = np.ascontiguousarray(seeds, np.uint64)
+        if sd.size != n:
+            raise ValueError("one seed per instance")
+        h = _P()
+        _check(lib().ofl_batch_create(src.encode(), n, cn, len(names), vals.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      sd.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), ctypes.byref(h)),
+               "ofl_batch_create")
+        self._h = h
+        ni, nb, nn = _I(), _I(), _I()
+        _check(lib().ofl_batch_info(h, ctypes.byref(ni), ctypes.byref(nb), ctypes.byref(nn)), "ofl_batch_info")
+        self.n_inst, self.n_bufs, self.n_nests = ni.value, nb.value, nn.value
+        buf = ctypes.create_string_buffer(256)
+        self.buf_names = []
+        for b in range(self.n_bufs):
+            _check(lib().ofl_batch_buf_name(h, b, buf, 256), "ofl_batch_buf_name")
+            self.buf_names.append(buf.value.decode())
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.ofl_batch_free(h)
+            self._h = None
+
+    def buf_info(self, inst, b):
+        nbytes, dt, rank = ctypes.c_uint64(), _I(), _I()
+        _check(lib().ofl_batch_buf_info(self._h, inst, b, ctypes.byref(nbytes), ctypes.byref(dt), ctypes.byref(rank)),
+               "ofl_batch_buf_info")
+        dims = (ctypes.c_int64 * max(1, rank.value))()
+        _check(lib().ofl_batch_buf_dims(self._h, inst, b, dims, rank.value), "ofl_batch_buf_dims")
+        return nbytes.value, _NP_DTYPE[dt.value], tuple(dims[i] for i in range(rank.value))
+
+    def alloc_device_buffers(self, device="cuda"):
+        """Per instance, one torch uint8 tensor per buffer (caller-owned)."""
+        import torch
+        return [[torch.empty(max(self.buf_info(i, b)[0], 16), dtype=torch.uint8, device=device)
+                 for b in range(self.n_bufs)] for i in range(self.n_inst)]
+
+    @staticmethod
+    def _ptrs(bufs):
+        flat = [t for row in bufs for t in row]
+        return (_P * len(flat))(*[ctypes.c_void_p(t.data_ptr()) for t in flat]), len(flat)
+
+    def setup(self, bufs, stream=None):
+        p, n = self._ptrs(bufs)
+        _check(lib().ofl_batch_setup(self._h, p, n, App._stream(stream)), "ofl_batch_setup")
+
+    def run(self, bufs, mode=BATCH_GROUPED_GRAPH, stream=None):
+        p, n = self._ptrs(bufs)
+        st = BatchStats()
+        _check(lib().ofl_batch_run(self._h, p, n, App._stream(stream), mode, ctypes.byref(st)), "ofl_batch_run")
+        return st.as_dict()
+
+    @property
+    def config(self):
+        c = BatchConfig()
+        _check(lib().ofl_batch_get_config(self._h, ctypes.byref(c)), "ofl_batch_get_config")
+        return c.as_dict()
+
+    def set_config(self, **kw):
+        c = BatchConfig(**{**self.config, **kw})
+        _check(lib().ofl_batch_set_config(self._h, ctypes.byref(c)), "ofl_batch_set_config")
+
+    def tune(self, bufs, reps=3, stream=None):
+        p, n = self._ptrs(bufs)
+        cap = 512
+        ents = (TuneEntry * cap)()
+        cnt = _I()
+        _check(lib().ofl_batch_tune(self._h, p, n, App._stream(stream), reps, ents, cap, ctypes.byref(cnt)),
+               "ofl_batch_tune")
+        return [{"phase": ("gemm", "stencil")[e.phase], **e.cfg.as_dict(), "ms": e.ms}
+                for e in ents[:min(cap, cnt.value)]]
+
+    def read(self, bufs, inst, name):
+        """Host copy of buffer `name` of instance `inst` (synchronises)."""
+        import torch
+        b = self.buf_names.index(name) if isinstance(name, str) else name
+        nbytes, dt, dims = self.buf_info(inst, b)
+        torch.cuda.synchronize()
+        raw = bufs[inst][b][:nbytes].cpu().numpy()
+        return raw.view(dt).reshape(dims).copy()

@@ -11,6 +11,23 @@ namespace k {
 
 constexpr int kWave = 64;
 
+// SplitMix64 (Steele, Lea & Flood 2014) output function and the
+// counter-based U[0,1) value of element e under a stream key: the top 24 bits
+// of mix64(key + (e + 1) * golden), scaled by 2^-24.
+constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+
+__device__ inline uint64_t mix64(uint64_t z) {
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ inline float uniform24(uint64_t key, int64_t e) {
+    return (float)(mix64(key + (uint64_t)(e + 1) * kGolden) >> 40) * (1.0f / 16777216.0f);
+}
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
     for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off);

@@ -452,7 +452,8 @@ bool parse_program(Ctx &cx, const Json &arr, std::vector<std::pair<int, int64_t>
 
 }  // namespace
 
-int parse_app(const std::string &text, AppIR &app, std::string &err) {
+int parse_app(const std::string &text, AppIR &app, std::string &err,
+              const std::map<std::string, int64_t> *overrides) {
     Json doc;
     JsonParser jp(text);
     if (!jp.parse(doc, err)) return OFL_E_PARSE;
@@ -472,6 +473,16 @@ int parse_app(const std::string &text, AppIR &app, std::string &err) {
                 return cx.status;
             }
             app.params[kv.first] = kv.second.inum;
+        }
+    }
+    if (overrides) {
+        for (const auto &kv : *overrides) {
+            auto it = app.params.find(kv.first);
+            if (it == app.params.end()) {
+                cx.fail(OFL_E_ARG, "unknown parameter '" + kv.first + "'");
+                return cx.status;
+            }
+            it->second = kv.second;
         }
     }
     const Json *bufs = doc.get("buffers");

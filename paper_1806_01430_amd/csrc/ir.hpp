@@ -118,7 +118,9 @@ struct AppIR {
 };
 
 // Parse + validate; returns an OFL_* status and fills `err` on failure.
-int parse_app(const std::string &text, AppIR &app, std::string &err);
+// `overrides` replaces the values of parameters the description declares.
+int parse_app(const std::string &text, AppIR &app, std::string &err,
+              const std::map<std::string, int64_t> *overrides = nullptr);
 
 // Parallelisability verdict of every nest and gene positions.
 void analyse(AppIR &app);

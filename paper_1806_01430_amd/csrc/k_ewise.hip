@@ -13,25 +13,12 @@ namespace k {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
 
 inline unsigned grid_for(int64_t work_items, int per_thread = 1) {
     int64_t blocks = (work_items + (int64_t)kThreads * per_thread - 1) / ((int64_t)kThreads * per_thread);
     if (blocks < 1) blocks = 1;
     if (blocks > 8192) blocks = 8192;   // 256 CUs x 32 blocks: grid-stride beyond that
     return (unsigned)blocks;
-}
-
-__device__ inline uint64_t mix64(uint64_t z) {
-    z ^= z >> 30;
-    z *= 0xBF58476D1CE4E5B9ull;
-    z ^= z >> 27;
-    z *= 0x94D049BB133111EBull;
-    return z ^ (z >> 31);
-}
-
-__device__ inline float uniform24(uint64_t key, int64_t e) {
-    return (float)(mix64(key + (uint64_t)(e + 1) * kGolden) >> 40) * (1.0f / 16777216.0f);
 }
 
 __global__ __launch_bounds__(kThreads) void k_fill_zero(uint4 *dst, int64_t n16, unsigned char *tail, int ntail) {

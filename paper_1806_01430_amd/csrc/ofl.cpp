@@ -21,22 +21,25 @@
 #include "kernels.hpp"
 #include "launch.hpp"
 #include "plan.hpp"
+#include "status.hpp"
 
 using namespace ofl;
 
 namespace {
-
 thread_local std::string g_last_error;
+}  // namespace
 
-int fail(int code, const std::string &msg) {
+int ofl::fail(int code, const std::string &msg) {
     g_last_error = msg;
     return code;
 }
 
-int hip_fail(hipError_t e, const char *what) {
+int ofl::hip_fail(hipError_t e, const char *what) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
     return OFL_E_HIP;
 }
+
+namespace {
 
 using clk = std::chrono::steady_clock;
 
@@ -1026,6 +1029,7 @@ const char *ofl_status_str(int32_t code) {
     case OFL_E_STATE: return "invalid state";
     case OFL_E_NOMEM: return "out of memory";
     case OFL_E_RANGE: return "index out of range";
+    case OFL_E_UNSUPPORTED: return "not supported in a batch";
     default: return "unknown status";
     }
 }

@@ -214,3 +214,79 @@ def test_ga_table_argument_errors():
         ofl.ga_run_table(3, params, np.ones(8))
     with pytest.raises(ofl.OflError):
         ofl.ga_run_table(3, ofl.ga_params(Pc=1.5), np.ones(8))
+
+
+# ---------------------------------------------------------------- instance batches (host side)
+def _batch_doc():
+    return workloads.app_doc("batch")
+
+
+def test_batch_create_and_buffer_shapes():
+    params, seeds = workloads.batch_instances(7, seed=3)
+    for p in params:
+        p["SWEEPS"] = 4
+    b = ofl.Batch(_batch_doc(), params, seeds)
+    assert (b.n_inst, b.n_bufs, b.n_nests) == (7, 6, 4)
+    assert b.buf_names == ["A", "B", "C", "p", "q", "res"]
+    for i, p in enumerate(params):
+        assert b.buf_info(i, 0)[2] == (p["N"], p["N"])
+        assert b.buf_info(i, 3)[2] == (p["I"], p["J"], p["K"])
+        assert b.buf_info(i, 3)[0] == 4 * p["I"] * p["J"] * p["K"]
+        assert b.buf_info(i, 5)[1] == np.float64 and b.buf_info(i, 5)[2] == (4,)
+
+
+def test_batch_instance_generator_matches_recipe():
+    params, seeds = workloads.batch_instances(256, seed=1)
+    Ns = np.array([p["N"] for p in params])
+    assert Ns.min() >= 32 and Ns.max() <= 511 and len(set(seeds)) == 256
+    assert all(p["I"] == p["J"] and p["K"] == 2 * p["I"] - 1 and 17 <= p["I"] <= 65 for p in params)
+    # log-uniform: about half the orders below the geometric midpoint 128
+    assert 0.35 < np.mean(Ns < 128) < 0.65
+
+
+def test_batch_errors():
+    doc = _batch_doc()
+    with pytest.raises(ofl.OflError) as e:
+        ofl.Batch(doc, [{"NOPE": 3}], [1])
+    assert e.value.code == -1                                    # unknown parameter
+    with pytest.raises(ofl.OflError) as e:
+        ofl.Batch(doc, [{"SWEEPS": 3}, {"SWEEPS": 4}], [1, 2])
+    assert e.value.code == -15                                   # repeat counts differ
+    with pytest.raises(ofl.OflError) as e:
+        ofl.Batch(workloads.app_doc("medium"), [{"N": 64}], [1])
+    assert e.value.code == -7                                    # rejected recurrences
+    with pytest.raises(ofl.OflError) as e:
+        ofl.Batch(workloads.app_doc("tiny"), [{"N": 64}], [1])
+    assert e.value.code == -15                                   # element-wise nests have no grouped form
+    d = _batch_doc()
+    d["program"][1]["args"]["prec"] = "bf16x3"
+    with pytest.raises(ofl.OflError) as e:
+        ofl.Batch(d, [{"N": 64}], [1])
+    assert e.value.code == -15
+    with pytest.raises(ValueError):
+        ofl.Batch(doc, [{"N": 64}, {"I": 20}], [1, 2])
+
+
+def test_batch_config_roundtrip_and_range():
+    b = ofl.Batch(_batch_doc(), [{"N": 40}, {"N": 50}], [1, 2])
+    c = b.config
+    assert c["stencil_rows"] in (2, 4, 8) and 0 <= c["gemm_cfg"] < 6
+    b.set_config(gemm_cfg=5, gemm_blocks_per_cu=1, stencil_rows=8, stencil_planes=16, stencil_blocks_per_cu=4)
+    assert b.config == {"gemm_cfg": 5, "gemm_blocks_per_cu": 1, "stencil_rows": 8, "stencil_planes": 16,
+                        "stencil_blocks_per_cu": 4}
+    for bad in [dict(gemm_cfg=6), dict(gemm_blocks_per_cu=0), dict(stencil_rows=3), dict(stencil_blocks_per_cu=9),
+                dict(stencil_planes=-1)]:
+        with pytest.raises(ofl.OflError) as e:
+            b.set_config(**bad)
+        assert e.value.code == -1
+
+
+def test_batch_run_checks_pointer_table():
+    import ctypes
+    b = ofl.Batch(_batch_doc(), [{"N": 40}, {"N": 50}], [1, 2])
+    st = ofl.BatchStats()
+    ptrs = (ctypes.c_void_p * 3)()
+    assert ofl.lib().ofl_batch_run(b._h, ptrs, 3, None, ofl.BATCH_GROUPED, ctypes.byref(st)) == -8
+    ptrs = (ctypes.c_void_p * 12)()
+    assert ofl.lib().ofl_batch_run(b._h, ptrs, 12, None, ofl.BATCH_GROUPED, ctypes.byref(st)) == -8
+    assert ofl.lib().ofl_batch_run(b._h, ptrs, 12, None, 7, ctypes.byref(st)) == -1

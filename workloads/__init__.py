@@ -73,6 +73,20 @@ def random_nest_doc(rng, max_loops=3, max_dims=3, max_extent=6, n_access=3):
             "program": [{"nest": "rand", "op": "none", "loops": loops, "access": acc}]}
 
 
+def batch_instances(n=256, seed=1, n_lo=32, n_hi=512, g_lo=17, g_hi=65):
+    """Per-instance sizes of the batching configuration: product order
+    N = floor(exp(U[ln n_lo, ln n_hi])) (not rounded to any tile), grid
+    I = J ~ U{g_lo..g_hi}, K = 2I - 1; instance seeds seed*1000 + i."""
+    rng = random.Random(seed)
+    out = []
+    for _ in range(n):
+        N = int(math.floor(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
+        I = rng.randint(g_lo, g_hi)
+        out.append({"N": min(N, n_hi - 1), "I": I, "J": I, "K": 2 * I - 1})
+    seeds = [seed * 1000 + i for i in range(n)]
+    return out, seeds
+
+
 def time_table(a, seed, lo=0.001, hi=1.0):
     """A seeded table of 2^a positive 'run times' (log-uniform in [lo, hi])."""
     rng = random.Random(seed)

@@ -190,7 +190,18 @@ def large():
             "buffers": bufs, "program": prog}
 
 
-APPS = {"tiny": tiny, "medium": medium, "precision": precision, "large": large}
+def batch():
+    """One instance of the batching configuration: product, then the iterated
+    sweep on the instance's own grid (sizes set per instance)."""
+    return {"name": "batch",
+            "params": {"N": 64, "I": 17, "J": 17, "K": 33, "SWEEPS": 10, "MODE": 1},
+            "buffers": [mat("A"), mat("B"), mat("C", True), grid("p", "sin", True), grid("q"),
+                        {"name": "res", "dtype": "f64", "dims": ["SWEEPS"], "setup": "zero",
+                         "output": True}],
+            "program": [init_nest(["A", "B"], [0, 1]), gemm_nest("A", "B", "C"), sweep_block()]}
+
+
+APPS = {"tiny": tiny, "medium": medium, "precision": precision, "large": large, "batch": batch}
 
 
 # ---------------------------------------------------------------- test apps
