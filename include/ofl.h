@@ -77,12 +77,27 @@ enum {
                                 outside the timed region) */
     OFL_RUN_KEEP_OUTPUTS = 2, /* leave outputs on the device (no final D2H);
                                 ofl_read_buffer fetches them afterwards */
-    OFL_RUN_GRAPH = 4        /* replay the run as HIP graphs captured once per
+    OFL_RUN_GRAPH = 4,       /* replay the run as HIP graphs captured once per
                                 (gene, policy, flags): a reset graph (untimed)
                                 and a run graph holding the copies, kernels and
                                 host nodes for the CPU nests; deadlines are not
                                 applied to graph runs.  Plans and results are
                                 those of the eager run. */
+    OFL_RUN_BATCHED = 8      /* population evaluation (ofl_eval_population,
+                                ofl_ga_run, ofl_ga_run_table) only: all
+                                uncached genes of a population / generation are
+                                measured in ONE submission -- per repetition
+                                the reset and run graphs of every gene queued
+                                back to back with an event pair around each run
+                                graph, one synchronisation at the end; a gene's
+                                time is the median of its event intervals (GPU
+                                timeline, host nodes included).  Implies
+                                OFL_RUN_GRAPH.  Deadlines are applied to the
+                                measured times (a run over the limit gets
+                                OFL_ST_TIMEOUT at the limit) instead of cutting
+                                runs short; in the GA every gene of a
+                                generation gets the limit taken at the start of
+                                that generation. */
 };
 
 /* Buffer element types. */

@@ -60,12 +60,16 @@ def fitness(t, status, p):
 
 
 def run_ga(a, M, T, evaluate, Pc=0.9, Pm=0.05, p=0.5, seed=1,
-           deadline_factor=0.0):
+           deadline_factor=0.0, batched=False):
     """Run the GA.  ``evaluate(gene_tuple, deadline) -> (time, status)``
     measures an uncached pattern; ``deadline`` is None or a time limit.
     When deadline_factor > 0 the all-zero gene is measured first (baseline,
     also entered in the cache and the best-so-far), and every later
     measurement gets the limit min(t_all0, deadline_factor * t_best).
+
+    ``batched``: all uncached genes of a generation are measured together (in
+    order of first appearance), so they share the limit taken at the start
+    of the generation; everything else is unchanged.
 
     Returns a dict with the per-generation populations, times, statuses,
     fitness values, the evaluation log and the best gene."""
@@ -90,20 +94,31 @@ def run_ga(a, M, T, evaluate, Pc=0.9, Pm=0.05, p=0.5, seed=1,
         consider(g0, t0, s0)
         t_all0 = t0 if s0 == ST_OK else None
 
+    def current_limit():
+        if deadline_factor > 0 and best["t"] is not None:
+            cands = [deadline_factor * best["t"]]
+            if t_all0 is not None:
+                cands.append(t_all0)
+            return min(cands)
+        return None
+
     pop = [tuple(rng.next() >> 63 for _ in range(a)) for _ in range(M)]
     gens = []
     for gen in range(1, T + 1):
+        if batched:
+            limit = current_limit()
+            for g in pop:
+                if g not in cache:
+                    t, st = evaluate(g, limit)
+                    cache[g] = (t, st)
+                    log.append((g, t, st))
+                    consider(g, t, st)
         times, stats, fits = [], [], []
         for g in pop:
             if g in cache:
                 t, st = cache[g]
             else:
-                limit = None
-                if deadline_factor > 0 and best["t"] is not None:
-                    cands = [deadline_factor * best["t"]]
-                    if t_all0 is not None:
-                        cands.append(t_all0)
-                    limit = min(cands)
+                limit = current_limit()
                 t, st = evaluate(g, limit)
                 cache[g] = (t, st)
                 log.append((g, t, st))

@@ -19,6 +19,7 @@
 // seed, u = (next >> 11) * 2^-53, draws in the order listed above.
 #include "ga.hpp"
 
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <map>
@@ -51,7 +52,7 @@ double ga_fitness(const Measurement &m, double p) {
     return std::pow(m.t, -p);
 }
 
-void run_ga(int a, const GaConfig &cfg, const Evaluator &evaluate, GaTrace &out) {
+void run_ga(int a, const GaConfig &cfg, const Evaluator &evaluate, GaTrace &out, const BatchEvaluator *batch) {
     using clk = std::chrono::steady_clock;
     const auto t_start = clk::now();
     out = GaTrace();
@@ -82,7 +83,30 @@ void run_ga(int a, const GaConfig &cfg, const Evaluator &evaluate, GaTrace &out)
     for (auto &g : pop)
         for (auto &bit : g) bit = (uint8_t)(rng.next() >> 63);
 
+    auto current_limit = [&]() {
+        double limit = -1.0;
+        if (cfg.deadline_factor > 0.0 && out.best_t > 0.0) {
+            limit = cfg.deadline_factor * out.best_t;
+            if (out.t_all0 > 0.0 && out.t_all0 < limit) limit = out.t_all0;
+        }
+        return limit;
+    };
+
     for (int gen = 1; gen <= cfg.T; ++gen) {
+        if (batch) {
+            std::vector<std::vector<uint8_t>> todo;
+            for (int m = 0; m < cfg.M; ++m)
+                if (!cache.count(pop[m]) && std::find(todo.begin(), todo.end(), pop[m]) == todo.end())
+                    todo.push_back(pop[m]);
+            if (!todo.empty()) {
+                const std::vector<Measurement> got = (*batch)(todo, current_limit());
+                for (size_t i = 0; i < todo.size(); ++i) {
+                    const Measurement mi = i < got.size() ? got[i] : Measurement{0.0, OFL_ST_FAILED};
+                    cache[todo[i]] = mi;
+                    record(todo[i], mi);
+                }
+            }
+        }
         std::vector<Measurement> meas(cfg.M);
         std::vector<double> fit(cfg.M);
         for (int m = 0; m < cfg.M; ++m) {
@@ -90,12 +114,7 @@ void run_ga(int a, const GaConfig &cfg, const Evaluator &evaluate, GaTrace &out)
             if (it != cache.end()) {
                 meas[m] = it->second;
             } else {
-                double limit = -1.0;
-                if (cfg.deadline_factor > 0.0 && out.best_t > 0.0) {
-                    limit = cfg.deadline_factor * out.best_t;
-                    if (out.t_all0 > 0.0 && out.t_all0 < limit) limit = out.t_all0;
-                }
-                meas[m] = evaluate(pop[m], limit);
+                meas[m] = evaluate(pop[m], current_limit());
                 cache[pop[m]] = meas[m];
                 record(pop[m], meas[m]);
             }

@@ -21,6 +21,10 @@ struct Measurement {
 
 // evaluate(gene, limit_seconds_or_negative) -> measurement of an uncached gene
 using Evaluator = std::function<Measurement(const std::vector<uint8_t> &, double)>;
+// evaluate_all(genes, limit) -> measurements of a generation's uncached genes
+// (first-appearance order), all under the limit taken at the generation start
+using BatchEvaluator =
+    std::function<std::vector<Measurement>(const std::vector<std::vector<uint8_t>> &, double)>;
 
 struct GaTrace {
     std::vector<std::vector<std::vector<uint8_t>>> pops;   // [gen][m] genes
@@ -31,8 +35,10 @@ struct GaTrace {
     double wall_s = 0.0, time_to_best_s = 0.0;
 };
 
-// Returns false only if `evaluate` requests an abort by throwing.
-void run_ga(int a, const GaConfig &cfg, const Evaluator &evaluate, GaTrace &out);
+// With `batch`, every generation's uncached genes are measured by one call of
+// it (the baseline all-zero gene still by `evaluate`).
+void run_ga(int a, const GaConfig &cfg, const Evaluator &evaluate, GaTrace &out,
+            const BatchEvaluator *batch = nullptr);
 
 double ga_fitness(const Measurement &m, double p);
 

@@ -106,6 +106,9 @@ struct ofl_app {
     std::vector<hipEvent_t> events;
     std::map<std::string, std::pair<int64_t, double>> kstats;
 
+    // event pairs of batched population evaluation
+    std::vector<hipEvent_t> chain_events;
+
     // captured graphs and the stream they are captured on
     std::map<std::vector<uint64_t>, std::unique_ptr<GraphEntry>> graphs;
     hipStream_t capture_stream = nullptr;
@@ -120,6 +123,7 @@ struct ofl_app {
         if (d_partials) (void)hipFree(d_partials);
         if (d_gemm_ws) (void)hipFree(d_gemm_ws);
         for (auto e : events) (void)hipEventDestroy(e);
+        for (auto e : chain_events) (void)hipEventDestroy(e);
     }
 };
 
@@ -598,6 +602,40 @@ int build_graphs(ofl_app *app, const std::vector<uint8_t> &placement, void *cons
     return capture_end(app, &ge.run, e == hipSuccess ? OFL_OK : hip_fail(e, "capture of the run graph"));
 }
 
+int get_graph(ofl_app *app, const std::vector<uint8_t> &placement, void *const *dev, int policy, int flags,
+              GraphEntry **out) {
+    const size_t nb = app->ir.bufs.size();
+    const int gflags = flags & ~(OFL_RUN_GRAPH | OFL_RUN_BATCHED);
+    std::vector<uint64_t> key(placement.begin(), placement.end());
+    key.push_back((uint64_t)policy);
+    key.push_back((uint64_t)gflags);
+    for (size_t b = 0; b < nb; ++b) key.push_back(reinterpret_cast<uint64_t>(dev[b]));
+    auto it = app->graphs.find(key);
+    if (it == app->graphs.end()) {
+        std::unique_ptr<GraphEntry> ge(new GraphEntry());
+        int rc = build_graphs(app, placement, dev, policy, gflags, *ge);
+        if (rc != OFL_OK) return rc;
+        it = app->graphs.emplace(key, std::move(ge)).first;
+    }
+    *out = it->second.get();
+    return OFL_OK;
+}
+
+// Host-side state after a run of `ge` (its reset restored the host copies it
+// lists, its run wrote the ones it marks).
+void note_graph_run(ofl_app *app, const GraphEntry &ge, void *const *dev, hipStream_t stream) {
+    const size_t nb = app->ir.bufs.size();
+    for (int b : ge.restore->bufs) app->host_dirty[b] = 0;
+    for (size_t b = 0; b < nb; ++b)
+        if (ge.host_written[b]) app->host_dirty[b] = 1;
+    app->ran = true;
+    app->host_valid = ge.plan.host_valid;
+    app->dev_valid = ge.plan.dev_valid;
+    app->host_written = ge.host_written;
+    app->last_dev.assign(dev, dev + nb);
+    app->last_stream = stream;
+}
+
 RunResult run_graph(ofl_app *app, const std::vector<uint8_t> &placement, void *const *dev, hipStream_t stream,
                     int policy, int flags) {
     RunResult rr;
@@ -607,25 +645,13 @@ RunResult run_graph(ofl_app *app, const std::vector<uint8_t> &placement, void *c
     const size_t nb = app->ir.bufs.size();
     int rc = ensure_host(app);
     if (rc == OFL_OK) rc = ensure_device(app);
+    GraphEntry *gep = nullptr;
+    if (rc == OFL_OK) rc = get_graph(app, placement, dev, policy, flags, &gep);
     if (rc != OFL_OK) {
         rr.code = rc;
         return rr;
     }
-    std::vector<uint64_t> key(placement.begin(), placement.end());
-    key.push_back((uint64_t)policy);
-    key.push_back((uint64_t)(flags & ~OFL_RUN_GRAPH));
-    for (size_t b = 0; b < nb; ++b) key.push_back(reinterpret_cast<uint64_t>(dev[b]));
-    auto it = app->graphs.find(key);
-    if (it == app->graphs.end()) {
-        std::unique_ptr<GraphEntry> ge(new GraphEntry());
-        rc = build_graphs(app, placement, dev, policy, flags & ~OFL_RUN_GRAPH, *ge);
-        if (rc != OFL_OK) {
-            rr.code = rc;
-            return rr;
-        }
-        it = app->graphs.emplace(key, std::move(ge)).first;
-    }
-    GraphEntry &ge = *it->second;
+    GraphEntry &ge = *gep;
     app->ran = false;
     hipError_t e = hipGraphLaunch(ge.reset, stream);
     if (e == hipSuccess) e = hipStreamSynchronize(stream);
@@ -696,6 +722,62 @@ Measurement measure(ofl_app *app, const std::vector<uint8_t> &placement, void *c
     m.status = OFL_ST_OK;
     m.t = median_of(ts);
     return m;
+}
+
+// All genes in one submission: per repetition, each gene's reset graph and
+// run graph back to back on the stream, an event pair around every run
+// graph; one synchronisation; per gene the median of its timed intervals.
+// limit > 0: a time over it becomes OFL_ST_TIMEOUT at the limit.
+int measure_batched(ofl_app *app, const std::vector<std::vector<uint8_t>> &placements, void *const *dev,
+                    hipStream_t s, int reps, int warmup, int policy, int flags, double limit,
+                    std::vector<Measurement> &out) {
+    const size_t n = placements.size();
+    out.assign(n, Measurement{0.0, OFL_ST_FAILED});
+    if (n == 0) return OFL_OK;
+    int rc = ensure_host(app);
+    if (rc == OFL_OK) rc = ensure_device(app);
+    if (rc != OFL_OK) return rc;
+    std::vector<GraphEntry *> ge(n);
+    for (size_t g = 0; g < n; ++g)
+        if ((rc = get_graph(app, placements[g], dev, policy, flags, &ge[g])) != OFL_OK) return rc;
+    const size_t need = 2 * n * (size_t)reps;
+    while (app->chain_events.size() < need) {
+        hipEvent_t e = nullptr;
+        hipError_t he = hipEventCreate(&e);
+        if (he != hipSuccess) return hip_fail(he, "hipEventCreate");
+        app->chain_events.push_back(e);
+    }
+    app->ran = false;
+    hipError_t e = hipSuccess;
+    for (int r = 0; r < warmup + reps && e == hipSuccess; ++r)
+        for (size_t g = 0; g < n && e == hipSuccess; ++g) {
+            const bool timed = r >= warmup;
+            const size_t ev = 2 * ((size_t)(r - warmup) * n + g);
+            e = hipGraphLaunch(ge[g]->reset, s);
+            if (e == hipSuccess && timed) e = hipEventRecord(app->chain_events[ev], s);
+            if (e == hipSuccess) e = hipGraphLaunch(ge[g]->run, s);
+            if (e == hipSuccess && timed) e = hipEventRecord(app->chain_events[ev + 1], s);
+        }
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "batched evaluation");
+    for (size_t g = 0; g < n; ++g) {
+        std::vector<double> ts;
+        for (int r = 0; r < reps; ++r) {
+            const size_t ev = 2 * ((size_t)r * n + g);
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, app->chain_events[ev], app->chain_events[ev + 1]);
+            if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+            ts.push_back(1e-3 * ms);
+        }
+        Measurement m{median_of(ts), OFL_ST_OK};
+        if (limit > 0 && m.t > limit) {
+            m.t = limit;
+            m.status = OFL_ST_TIMEOUT;
+        }
+        out[g] = m;
+        note_graph_run(app, *ge[g], dev, s);
+    }
+    return OFL_OK;
 }
 
 void copy_name(const std::string &s, char *out, int32_t cap) {
@@ -908,11 +990,34 @@ int ofl_eval_population(ofl_app *app, const uint8_t *genes, int32_t pop, int32_t
     if (opts->reps < 1 || opts->warmup < 0) return fail(OFL_E_ARG, "need reps >= 1 and warmup >= 0");
     int rc = check_bufs(app, dev_bufs, n_bufs);
     if (rc != OFL_OK) return rc;
+    if (opts->flags & ~(OFL_RUN_PRESTAGED | OFL_RUN_KEEP_OUTPUTS | OFL_RUN_GRAPH | OFL_RUN_BATCHED))
+        return fail(OFL_E_ARG, "bad flags");
     std::map<std::vector<uint8_t>, Measurement> seen;
     std::vector<uint8_t> placement;
     for (int32_t m = 0; m < pop; ++m) {
         rc = check_gene(app, genes + (size_t)m * gene_len, gene_len, placement);
         if (rc != OFL_OK) return rc;
+    }
+    if (opts->flags & OFL_RUN_BATCHED) {
+        std::vector<std::vector<uint8_t>> uniq, places;
+        for (int32_t m = 0; m < pop; ++m) {
+            std::vector<uint8_t> g(genes + (size_t)m * gene_len, genes + (size_t)(m + 1) * gene_len);
+            if (std::find(uniq.begin(), uniq.end(), g) != uniq.end()) continue;
+            check_gene(app, g.data(), gene_len, placement);
+            uniq.push_back(g);
+            places.push_back(placement);
+        }
+        std::vector<Measurement> got;
+        rc = measure_batched(app, places, dev_bufs, static_cast<hipStream_t>(stream), opts->reps, opts->warmup,
+                             opts->policy, opts->flags, opts->deadline_s, got);
+        if (rc != OFL_OK) return rc;
+        for (int32_t m = 0; m < pop; ++m) {
+            std::vector<uint8_t> g(genes + (size_t)m * gene_len, genes + (size_t)(m + 1) * gene_len);
+            const size_t k = std::find(uniq.begin(), uniq.end(), g) - uniq.begin();
+            time_out[m] = got[k].t;
+            status_out[m] = got[k].status;
+        }
+        return OFL_OK;
     }
     for (int32_t m = 0; m < pop; ++m) {
         std::vector<uint8_t> g(genes + (size_t)m * gene_len, genes + (size_t)(m + 1) * gene_len);
@@ -950,8 +1055,18 @@ int ofl_ga_run(ofl_app *app, const ofl_ga_params *params, void *const *dev_bufs,
         return measure(app, placement, dev_bufs, static_cast<hipStream_t>(stream), params->reps, params->warmup,
                        params->policy, params->flags, limit > 0 ? limit : 0.0, &hard);
     };
+    BatchEvaluator bev = [&](const std::vector<std::vector<uint8_t>> &gs, double limit) {
+        std::vector<Measurement> out(gs.size(), Measurement{0.0, OFL_ST_FAILED});
+        if (hard != OFL_OK) return out;
+        std::vector<std::vector<uint8_t>> places(gs.size());
+        for (size_t i = 0; i < gs.size(); ++i) check_gene(app, gs[i].data(), a, places[i]);
+        const int rc2 = measure_batched(app, places, dev_bufs, static_cast<hipStream_t>(stream), params->reps,
+                                        params->warmup, params->policy, params->flags, limit, out);
+        if (rc2 != OFL_OK) hard = rc2;
+        return out;
+    };
     GaTrace tr;
-    run_ga(a, ga_config(params), ev, tr);
+    run_ga(a, ga_config(params), ev, tr, (params->flags & OFL_RUN_BATCHED) ? &bev : nullptr);
     if (hard != OFL_OK) return hard;
     fill_ga_result(tr, a, params->M, result);
     return OFL_OK;
@@ -973,8 +1088,13 @@ int ofl_ga_run_table(int32_t gene_len, const ofl_ga_params *params, const double
         }
         return m;
     };
+    BatchEvaluator bev = [&](const std::vector<std::vector<uint8_t>> &gs, double limit) {
+        std::vector<Measurement> out;
+        for (const auto &g : gs) out.push_back(ev(g, limit));
+        return out;
+    };
     GaTrace tr;
-    run_ga(gene_len, ga_config(params), ev, tr);
+    run_ga(gene_len, ga_config(params), ev, tr, (params->flags & OFL_RUN_BATCHED) ? &bev : nullptr);
     fill_ga_result(tr, gene_len, params->M, result);
     return OFL_OK;
 }

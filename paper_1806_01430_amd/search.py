@@ -15,7 +15,7 @@ import time
 
 import numpy as np
 
-from . import App, app_path, ga_params, RESIDENT, PER_REGION, PRESTAGED, KEEP_OUTPUTS, GRAPH
+from . import App, app_path, ga_params, RESIDENT, PER_REGION, PRESTAGED, KEEP_OUTPUTS, GRAPH, BATCHED
 
 
 def main(argv=None):
@@ -32,6 +32,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--policy", choices=["resident", "per_region"], default="resident")
     ap.add_argument("--graph", action="store_true", help="measure graph replays")
+    ap.add_argument("--batched", action="store_true",
+                    help="measure each generation's new genes in one submission (graph chain)")
     ap.add_argument("--deadline-factor", type=float, default=0.0)
     ap.add_argument("--baseline", action="store_true", help="also measure the all-CPU gene")
     ap.add_argument("--exhaustive", action="store_true",
@@ -46,7 +48,7 @@ def main(argv=None):
     app = App(src, seed=args.seed)
     bufs = app.alloc_device_buffers("cuda:0")
     policy = RESIDENT if args.policy == "resident" else PER_REGION
-    flags = GRAPH if args.graph else 0
+    flags = (GRAPH if args.graph else 0) | (BATCHED if args.batched else 0)
     params = ga_params(M=args.M, T=args.T, Pc=args.Pc, Pm=args.Pm, p=args.p, seed=args.ga_seed, reps=args.reps,
                        warmup=args.warmup, policy=policy, flags=flags, deadline_factor=args.deadline_factor)
     t0 = time.perf_counter()
@@ -55,7 +57,7 @@ def main(argv=None):
     out = {"app": args.app, "nests": [{"name": app.nest_name(i), "verdict": v, "reason": r, "gene_pos": g}
                                       for i, (v, r, g) in enumerate(app.verdicts())],
            "gene_len": app.gene_len, "M": args.M, "T": args.T, "Pc": args.Pc, "Pm": args.Pm, "p": args.p,
-           "reps": args.reps, "policy": args.policy, "graph": args.graph,
+           "reps": args.reps, "policy": args.policy, "graph": args.graph, "batched": args.batched,
            "best_gene": res["best_gene"], "best_time_s": res["best_time"], "n_measured": res["n_measured"],
            "search_wall_s": res["search_wall_s"], "time_to_best_s": res["time_to_best_s"],
            "per_generation_best_s": [float(np.min(np.where(res["status"][g] == 0, res["times"][g], np.inf)))

@@ -401,3 +401,45 @@ def test_eval_population_graph_mode():
     t, s = app.eval_population(genes, bufs, reps=3, warmup=1, flags=ofl.GRAPH)
     assert np.all(s == ofl.ST_OK) and np.all(t > 0)
     assert t[0] == t[1]          # duplicates measured once
+
+
+def test_eval_population_batched_one_submission():
+    # all 64 genes of the tiny application in one submission: every gene
+    # measured, duplicates once, and afterwards the device / host state is
+    # that of the last gene's run (its outputs match the oracle)
+    doc = workloads.app_doc("tiny")
+    app = ofl.App(json.dumps(doc))
+    o = ir.load(doc)
+    o32, o64 = parity.oracle_outputs(o, 1)
+    bufs = app.alloc_device_buffers()
+    genes = [[(idx >> i) & 1 for i in range(6)] for idx in range(64)] + [[1] * 6]
+    say("case eval batched tiny 64")
+    t, s = app.eval_population(genes, bufs, reps=3, warmup=1, flags=ofl.BATCHED)
+    assert np.all(s == ofl.ST_OK) and np.all(t > 0)
+    assert t[63] == t[64]
+    assert t[0] > t[63]                       # the all-CPU gene is the slowest kind here
+    bad = parity.compare(o, app.read_all(), o32, o64)
+    assert not bad, bad
+    # with a limit below the slowest genes: those become timeouts at the limit
+    lim = float(np.median(t))
+    t2, s2 = app.eval_population(genes[:64], bufs, reps=1, warmup=0, flags=ofl.BATCHED, deadline_s=lim)
+    assert np.all((s2 == ofl.ST_OK) | (s2 == ofl.ST_TIMEOUT)) and np.any(s2 == ofl.ST_TIMEOUT)
+    assert np.all(t2[s2 == ofl.ST_TIMEOUT] == lim)
+    # a following eager run is unaffected
+    st = app.run_pattern([1, 0, 1, 1, 0, 1], bufs)
+    assert st["status"] == ofl.ST_OK
+    assert not parity.compare(o, app.read_all(), o32, o64)
+
+
+def test_ga_batched_generations_medium_reduced():
+    doc = workloads.app_doc("medium", **workloads.SMALL_MEDIUM)
+    app = ofl.App(json.dumps(doc))
+    bufs = app.alloc_device_buffers()
+    params = ofl.ga_params(M=8, T=4, p=1.0, seed=5, reps=2, warmup=1, flags=ofl.BATCHED)
+    say("case GA batched medium reduced")
+    res = app.ga_run(params, bufs)
+    assert res["n_generations"] == 4
+    uniq = {tuple(int(x) for x in g) for gen in res["pops"] for g in gen}
+    assert res["n_measured"] == len(uniq)
+    assert np.all(res["status"] == ofl.ST_OK)
+    assert res["best_time"] == float(np.min(res["times"]))

@@ -164,7 +164,8 @@ def test_accepted_host_only_op_is_invalid():
 # ------------------------------------------------------------ GA parity
 def _oracle_ga(a, params, table, status=None):
     return G.run_ga(a, params.M, params.T, G.table_evaluator(table, status), Pc=params.Pc, Pm=params.Pm,
-                    p=params.p, seed=params.seed, deadline_factor=params.deadline_factor)
+                    p=params.p, seed=params.seed, deadline_factor=params.deadline_factor,
+                    batched=bool(params.flags & ofl.BATCHED))
 
 
 @pytest.mark.parametrize("a,M,T,Pc,Pm,p,seed,dl", [
@@ -177,9 +178,11 @@ def _oracle_ga(a, params, table, status=None):
     (5, 8, 6, 1.0, 1.0, 0.5, 6, 2.0),
     (12, 12, 12, 0.9, 0.05, 0.5, 2018, 0.0),
 ])
-def test_ga_trajectory_matches_oracle(a, M, T, Pc, Pm, p, seed, dl):
+@pytest.mark.parametrize("batched", [False, True])
+def test_ga_trajectory_matches_oracle(a, M, T, Pc, Pm, p, seed, dl, batched):
     table = workloads.time_table(a, seed * 31 + a, lo=0.01, hi=5.0)
-    params = ofl.ga_params(M=M, T=T, Pc=Pc, Pm=Pm, p=p, seed=seed, deadline_factor=dl)
+    params = ofl.ga_params(M=M, T=T, Pc=Pc, Pm=Pm, p=p, seed=seed, deadline_factor=dl,
+                           flags=ofl.BATCHED if batched else 0)
     got = ofl.ga_run_table(a, params, table)
     want = _oracle_ga(a, params, table)
     assert got["n_generations"] == len(want["generations"])
@@ -192,6 +195,26 @@ def test_ga_trajectory_matches_oracle(a, M, T, Pc, Pm, p, seed, dl):
     assert got["n_measured"] == want["n_measured"]
     if dl > 0:
         assert got["t_all0"] == want["t_all0"]
+
+
+def test_batched_generations_change_only_the_deadline():
+    # without deadlines, measuring a generation's genes together leaves the
+    # trajectory unchanged; with deadlines the limits differ, and the batched
+    # run gives every fresh gene of a generation the limit at its start
+    for seed in range(1, 6):
+        table = workloads.time_table(8, seed, lo=0.01, hi=5.0)
+        ev = G.table_evaluator(table)
+        seq = G.run_ga(8, 10, 8, ev, seed=seed)
+        bat = G.run_ga(8, 10, 8, ev, seed=seed, batched=True)
+        assert [g["pop"] for g in seq["generations"]] == [g["pop"] for g in bat["generations"]]
+        assert seq["best_gene"] == bat["best_gene"]
+    limits = []
+
+    def spy(g, limit):
+        limits.append(limit)
+        return ev(g, limit)
+    G.run_ga(8, 10, 3, spy, seed=3, deadline_factor=2.0, batched=True)
+    assert len(set(limits[1:11])) == 1 and limits[0] is None
 
 
 def test_ga_with_failed_statuses_matches_oracle():
