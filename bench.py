@@ -143,6 +143,88 @@ def run_kernels_large(args):
     return out
 
 
+def run_precision(args):
+    """The precision workload (GEMM 4096, sweep 257 x 257 x 513 x 200, FP64
+    residual) under each GEMM form, all nests on the GPU: application time and
+    the product nest's kernel time per form."""
+    import paper_1806_01430_amd as ofl
+    import workloads
+
+    out = {}
+    N = None
+    for prec in ("f32", "bf16x3", "fp8x2"):
+        doc = workloads.app_doc("precision")
+        doc["program"][1]["args"]["prec"] = prec
+        N = doc["params"]["N"]
+        app = ofl.App(json.dumps(doc), seed=1)
+        bufs = app.alloc_device_buffers("cuda:0")
+        gene = [1] * app.gene_len
+        flags = ofl.PRESTAGED | ofl.KEEP_OUTPUTS
+        app.run_pattern(gene, bufs, flags=flags)
+        app.set_kernel_timing(True)
+        ts = sorted(app.run_pattern(gene, bufs, flags=flags)["t_total_s"] for _ in range(3))
+        n, ms = app.kernel_stats("gemm")
+        gemm_ms = ms / n
+        out[prec] = {"app_time_ms": round(1e3 * ts[1], 3), "gemm_ms": round(gemm_ms, 4),
+                     "gemm_TFLOPs_fp32_equiv": round(2.0 * N ** 3 / (gemm_ms * 1e-3) / 1e12, 1)}
+        del app, bufs
+    return out
+
+
+def run_batch(args):
+    """The batching workload: 256 instances (product order log-uniform in
+    [32, 512), grids 17..65 x same x 2I-1, 10 sweeps), all nests on the GPU,
+    as per-instance launches, as grouped launches, and as one graph; then the
+    tuner's choice."""
+    import paper_1806_01430_amd as ofl
+    import workloads
+
+    params, seeds = workloads.batch_instances(256, seed=1)
+    for p in params:
+        p["SWEEPS"] = 10
+    b = ofl.Batch(workloads.app_doc("batch"), params, seeds)
+    bufs = b.alloc_device_buffers("cuda:0")
+    b.setup(bufs)
+
+    def timed(mode, reps=5):
+        b.run(bufs, mode)
+        ts = sorted(b.run(bufs, mode)["t_total_s"] for _ in range(reps))
+        return ts[reps // 2]
+
+    out = {"instances": 256, "per_instance_launches_ms": round(1e3 * timed(ofl.BATCH_LOOP), 3),
+           "grouped_ms": round(1e3 * timed(ofl.BATCH_GROUPED), 3),
+           "graph_ms": round(1e3 * timed(ofl.BATCH_GROUPED_GRAPH), 3)}
+    t0 = time.perf_counter()
+    b.tune(bufs, reps=3)
+    out["tune_s"] = round(time.perf_counter() - t0, 3)
+    out["tuned_config"] = b.config
+    b.setup(bufs)
+    out["graph_tuned_ms"] = round(1e3 * timed(ofl.BATCH_GROUPED_GRAPH), 3)
+    out["speedup_vs_per_instance"] = round(out["per_instance_launches_ms"] / out["graph_tuned_ms"], 2)
+    return out
+
+
+def run_population(args):
+    """Population evaluation on the tiny application: all 64 genes, measured
+    gene by gene as graph replays vs in one submission (graph chain)."""
+    import torch
+
+    import paper_1806_01430_amd as ofl
+    import workloads
+
+    app = ofl.App(json.dumps(workloads.app_doc("tiny")), seed=1)
+    bufs = app.alloc_device_buffers("cuda:0")
+    genes = [[(i >> k) & 1 for k in range(6)] for i in range(64)]
+    out = {"genes": 64, "reps": 3, "warmup": 1}
+    for name, flags in (("per_gene_graph", ofl.GRAPH), ("one_submission", ofl.BATCHED)):
+        app.eval_population(genes, bufs, reps=1, warmup=0, flags=flags)   # capture the graphs
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        app.eval_population(genes, bufs, reps=3, warmup=1, flags=flags)
+        out[name + "_s"] = round(time.perf_counter() - t0, 4)
+    return out
+
+
 def calibration_copy():
     """A plain copy nest of known size (1 GiB read, 1 GiB written), run once:
     the reference against which rocprofv3's FETCH_SIZE / WRITE_SIZE readings
@@ -186,6 +268,8 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 513^3-class stencil / 8192 GEMM lines")
     ap.add_argument("--large-only", action="store_true",
                     help="only the 513x513x1025 stencil and 8192 GEMM kernel lines (for profiling)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the precision, batching and population-evaluation lines")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first run a plain 1 GiB copy kernel (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -248,6 +332,15 @@ def main():
         log("bench: large-grid stencil and 8192 GEMM")
         line["kernels_large"] = {k: {kk: round(vv, 4) for kk, vv in v.items()}
                                  for k, v in run_kernels_large(args).items()}
+    if not args.no_extras:
+        log("bench: precision workload under each GEMM form")
+        line["precision"] = run_precision(args)
+        torch.cuda.empty_cache()
+        log("bench: batching workload (256 instances)")
+        line["batch"] = run_batch(args)
+        torch.cuda.empty_cache()
+        log("bench: population evaluation (tiny, 64 genes)")
+        line["population_eval"] = run_population(args)
     if not args.no_cpu_baseline:
         log("bench: oracle on one host core (full medium application)")
         dt = cpu_baseline()
