@@ -67,33 +67,36 @@ def run_medium(args):
     gene = [1] * app.gene_len
     bufs = app.alloc_device_buffers("cuda:0")
     flags = ofl.PRESTAGED | ofl.KEEP_OUTPUTS
-    for _ in range(args.warmup):
-        app.run_pattern(gene, bufs, flags=flags)
-    torch.cuda.synchronize()
+    gflags = flags | ofl.GRAPH
+    # timing on before the warm-up: the graphs are captured with an event
+    # record node around every GPU nest, so the timed steps replay exactly
+    # the graphs whose kernels they time
     app.set_kernel_timing(True)
-    internal = []
+    for _ in range(args.warmup):
+        app.run_pattern(gene, bufs, flags=gflags)
     torch.cuda.synchronize()
+    app.set_kernel_timing(True)          # clears the warm-up's totals
+    internal = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        st = app.run_pattern(gene, bufs, flags=flags)
+        st = app.run_pattern(gene, bufs, flags=gflags)
         internal.append(st["t_total_s"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     app.set_kernel_timing(False)
     ktab = kernel_table(app, ["stencil19", "copy_interior", "gemm", "init_uniform", "add_scaled", "transpose",
                               "avg2", "sumsq", "copy", "scale"])
-    # the same steps replayed as captured HIP graphs (reset graph untimed)
-    gflags = flags | ofl.GRAPH
+    # context: the same steps run eagerly (one launch at a time, no graphs)
     for _ in range(2):
-        app.run_pattern(gene, bufs, flags=gflags)
+        app.run_pattern(gene, bufs, flags=flags)
     torch.cuda.synchronize()
-    tg0 = time.perf_counter()
-    ginternal = []
+    te0 = time.perf_counter()
+    einternal = []
     for _ in range(args.steps):
-        ginternal.append(app.run_pattern(gene, bufs, flags=gflags)["t_total_s"])
+        einternal.append(app.run_pattern(gene, bufs, flags=flags)["t_total_s"])
     torch.cuda.synchronize()
-    gwall = time.perf_counter() - tg0
-    ginternal.sort()
+    ewall = time.perf_counter() - te0
+    einternal.sort()
     # paper protocol for context: set-up content copied in, outputs copied out
     pcie = []
     for _ in range(3):
@@ -101,46 +104,8 @@ def run_medium(args):
     internal.sort()
     pcie.sort()
     return {"app": app, "params": P, "wall": wall, "internal_median_s": internal[len(internal) // 2],
-            "pcie_median_s": pcie[1], "kernels": ktab, "last": st, "graph_wall": gwall,
-            "graph_internal_median_s": ginternal[len(ginternal) // 2]}
-
-
-def run_kernels_large(args):
-    """Stencil on the largest grid and the FP32 GEMM at 8192 (the sizes where
-    the HBM and MFMA rooflines are meaningful)."""
-    import paper_1806_01430_amd as ofl
-    from workloads import appgen
-
-    out = {}
-    I, J, K = 513, 513, 1025
-    app = ofl.App(json.dumps(appgen.stencil_app(I, J, K, 10)), seed=1)
-    bufs = app.alloc_device_buffers("cuda:0")
-    app.run_pattern([1, 1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
-    app.set_kernel_timing(True)
-    for _ in range(2):
-        app.run_pattern([1, 1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
-    n, ms = app.kernel_stats("stencil19")
-    avg = ms / n * 1e-3
-    gbs = stencil_bytes(I, J, K) / avg / 1e9
-    nc, msc = app.kernel_stats("copy_interior")
-    out["stencil19_513x513x1025"] = {"avg_us": avg * 1e6, "GBps": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
-                                     "copy_interior_GBps": 8 * (I - 2) * (J - 2) * (K - 2) / (msc / nc * 1e-3) / 1e9}
-    del bufs, app
-    N = 8192
-    doc = {"name": "gemm8192", "params": {"N": N},
-           "buffers": [{"name": b, "dims": ["N", "N"], "output": b == "C"} for b in ("A", "B", "C")],
-           "program": [appgen.init_nest(["A", "B"], [0, 1]), appgen.gemm_nest("A", "B", "C")]}
-    app = ofl.App(json.dumps(doc), seed=1)
-    bufs = app.alloc_device_buffers("cuda:0")
-    app.run_pattern([1, 1], bufs, flags=ofl.KEEP_OUTPUTS)
-    app.set_kernel_timing(True)
-    for _ in range(3):
-        app.run_pattern([1, 1], bufs, flags=ofl.KEEP_OUTPUTS)
-    n, ms = app.kernel_stats("gemm")
-    avg = ms / n * 1e-3
-    tf = 2.0 * N ** 3 / avg / 1e12
-    out["gemm_f32_8192"] = {"avg_ms": avg * 1e3, "TFLOPs": tf, "frac_mfma": tf / FP32_MFMA_PEAK_TFLOPS}
-    return out
+            "pcie_median_s": pcie[1], "kernels": ktab, "last": st, "eager_wall": ewall,
+            "eager_internal_median_s": einternal[len(einternal) // 2]}
 
 
 def run_precision(args):
@@ -270,6 +235,8 @@ def main():
                     help="only the 513x513x1025 stencil and 8192 GEMM kernel lines (for profiling)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the precision, batching and population-evaluation lines")
+    ap.add_argument("--extras-only", action="store_true",
+                    help="only the precision, batching and population-evaluation lines (for profiling)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first run a plain 1 GiB copy kernel (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -282,13 +249,21 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
 
-    if args.large_only:
-        print(json.dumps({"kernels_large": run_kernels_large(args)}), flush=True)
-        return
     if args.calibration_copy:
         log("bench: calibration copy (1 GiB)")
         calibration_copy()
         torch.cuda.empty_cache()
+    if args.large_only:
+        print(json.dumps({"kernels_large": run_kernels_large(args)}), flush=True)
+        return
+    if args.extras_only:
+        out = {"precision": run_precision(args)}
+        torch.cuda.empty_cache()
+        out["batch"] = run_batch(args)
+        torch.cuda.empty_cache()
+        out["population_eval"] = run_population(args)
+        print(json.dumps(out), flush=True)
+        return
     log("bench: medium app, %d warmup + %d timed steps" % (args.warmup, args.steps))
     r = run_medium(args)
     P = r["params"]
@@ -320,11 +295,13 @@ def main():
             "config": {"workload": "medium app: 12 loop nests (2 loop-carried recurrences on the CPU), "
                                    "GEMM 1024x1024, 19-point sweep 129x129x257 x 100 sweeps + FP64 residual",
                        "gene": "all 10 parallelisable nests on the GPU", "policy": "resident",
+                       "execution": "each step one ofl_run_pattern replaying the pattern's captured HIP graphs "
+                                    "(reset graph untimed inside the call, run graph timed)",
                        "inputs": "resident in HBM at the start of the timed region; outputs left in HBM"},
             "app_time_ms": round(1e3 * r["internal_median_s"], 4),
             "app_time_pcie_ms": round(1e3 * r["pcie_median_s"], 4),
-            "graph_runs_per_s": round(args.steps / r["graph_wall"], 3),
-            "graph_app_time_ms": round(1e3 * r["graph_internal_median_s"], 4),
+            "eager_runs_per_s": round(args.steps / r["eager_wall"], 3),
+            "eager_app_time_ms": round(1e3 * r["eager_internal_median_s"], 4),
             "gemm1024_TFLOPs": round(gemm_tf, 2) if gemm_tf else None,
             "roofline": roofline,
             "kernels_medium": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in ks.items()}}

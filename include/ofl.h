@@ -70,7 +70,7 @@ enum { OFL_PARALLEL = 0, OFL_PARALLEL_REDUCTION = 1, OFL_REJECT = 2 };
 enum { OFL_R_NONE = 0, OFL_R_DATA_DEP = 1, OFL_R_EXTERNAL_CALL = 2, OFL_R_BREAK = 3 };
 
 /* Transfer policies (see ofl_plan_transfers) and run flags. */
-enum { OFL_POLICY_RESIDENT = 0, OFL_POLICY_PER_REGION = 1 };
+enum { OFL_POLICY_RESIDENT = 0, OFL_POLICY_PER_REGION = 1, OFL_POLICY_SECTIONS = 2 };
 enum {
     OFL_RUN_PRESTAGED = 1,   /* set-up content already on the device when the
                                 timed region starts (restored device-side,
@@ -211,6 +211,12 @@ int ofl_mask_to_gene(const ofl_app *app, const uint8_t *mask, int32_t n_nests, u
  *   PER_REGION: the directive compiler's implicit copies (Sec. 2 of the
  *     paper): every GPU nest copies in all it reads and copies out all it
  *     writes.
+ *   SECTIONS: RESIDENT, but a CPU nest that only reads a buffer stale on the
+ *     host copies out just the bounding box of the elements its plain reads
+ *     touch (the array section a data clause would name), unless a box of
+ *     that buffer copied out earlier and still current contains it; a box
+ *     equal to the whole buffer is a whole copy; any write drops the boxes.
+ *     Each box copy counts as one copy of its bytes.
  * Errors: OFL_E_GENE_LEN, OFL_E_GENE_BIT, OFL_E_ARG. */
 int ofl_plan_transfers(const ofl_app *app, const uint8_t *gene, int32_t gene_len, int32_t policy,
                        int32_t flags, uint64_t *bytes_h2d, uint64_t *bytes_d2h, int32_t *n_copies);
@@ -267,7 +273,10 @@ int ofl_read_buffer(ofl_app *app, int32_t buf, void *host_dst, uint64_t bytes);
 /* ---------------------------------------------------------------- profiling */
 
 /* Enable (1) / disable (0) per-kernel timing with HIP events recorded on the
- * run's stream around every launch; enabling clears the totals. */
+ * run's stream around every launch; enabling clears the totals.  Graph runs
+ * (OFL_RUN_GRAPH) use graphs captured while timing is on, which hold an event
+ * record node before and after every GPU nest; their intervals are added
+ * after each replay. */
 int ofl_set_kernel_timing(ofl_app *app, int32_t enable);
 
 /* Accumulated launches and total kernel time (ms) of op kind `op`

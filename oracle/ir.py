@@ -90,7 +90,8 @@ class Buffer:
         for x in self.dims:
             n *= x
         self.count = n
-        self.nbytes = n * DTYPE_BYTES[self.dtype]
+        self.elem_bytes = DTYPE_BYTES[self.dtype]
+        self.nbytes = n * self.elem_bytes
 
 
 class Access:

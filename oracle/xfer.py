@@ -22,12 +22,19 @@ PER_REGION policy (the compiler-managed copies around each offloaded region
     that the paper's directive-based toolchain performs, Sec. 2)
     GPU nest: H2D every read buffer, then D2H every written buffer; CPU nests
     copy nothing; the host copy is always current.
+SECTIONS policy (RESIDENT with array sections, as a directive's data clause
+    may name them): a CPU nest that only reads a buffer stale on the host
+    copies out just the bounding box of the elements it reads (per dimension
+    the range its subscripts take over the loop and repeat ranges), unless a
+    box copied out earlier and still current contains it; a box equal to the
+    whole buffer is a whole copy.  Every other copy is RESIDENT's; a write
+    anywhere invalidates the host boxes of that buffer.
 
 Flags (both policies): PRESTAGED -- every buffer starts (1, 1), i.e. the
 set-up content is already resident on the device; KEEP_OUTPUTS -- no final
 D2H (results stay on the device).
 """
-RESIDENT, PER_REGION = 0, 1
+RESIDENT, PER_REGION, SECTIONS = 0, 1, 2
 FLAG_PRESTAGED, FLAG_KEEP_OUTPUTS = 1, 2
 
 
@@ -68,6 +75,40 @@ def nest_sets(app, nest):
     return sorted(reads), sorted(writes)
 
 
+def read_box(app, nest, b):
+    """Bounding box [(lo, hi), ...] of the elements of buffer b that the nest's
+    plain reads touch, or None when they touch nothing."""
+    ranges = {v: (lo, hi) for v, lo, hi in nest.loops}
+    box = None
+    for a in nest.access:
+        if app.buf_index[a.buf] != b or a.mode != "r":
+            continue
+        cur = []
+        for v, c in a.subs:
+            if v is None:
+                cur.append((c, c + 1))
+            elif v in ranges:
+                lo, hi = ranges[v]
+                cur.append((lo + c, hi + c))
+            else:
+                cur.append((c, nest.repeat_vars[v] + c))
+        if any(lo >= hi for lo, hi in cur):
+            continue
+        box = cur if box is None else [(min(p[0], q[0]), max(p[1], q[1])) for p, q in zip(box, cur)]
+    return box
+
+
+def box_bytes(app, b, box):
+    n = 1
+    for lo, hi in box:
+        n *= hi - lo
+    return n * app.buffers[b].elem_bytes
+
+
+def _contains(outer, inner):
+    return all(o[0] <= i[0] and i[1] <= o[1] for o, i in zip(outer, inner))
+
+
 def executions(app):
     """Nest indices in execution order, repeats expanded."""
     out = []
@@ -90,18 +131,20 @@ def plan(app, placement, policy=RESIDENT, flags=0):
     init = 1 if flags & FLAG_PRESTAGED else 0
     host = [1] * nb
     dev = [init] * nb
+    boxes = [[] for _ in range(nb)]
     copies = []
     sets = [nest_sets(app, n) for n in app.nests]
     for ni in executions(app):
         reads, writes = sets[ni]
         if placement[ni]:
-            if policy == RESIDENT:
+            if policy in (RESIDENT, SECTIONS):
                 for b in reads:
                     if not dev[b]:
                         copies.append(("H2D", b, app.buffers[b].nbytes))
                         dev[b] = 1
                 for b in writes:
                     host[b], dev[b] = 0, 1
+                    boxes[b] = []
             else:
                 for b in reads:
                     copies.append(("H2D", b, app.buffers[b].nbytes))
@@ -110,13 +153,25 @@ def plan(app, placement, policy=RESIDENT, flags=0):
                     copies.append(("D2H", b, app.buffers[b].nbytes))
                     host[b], dev[b] = 1, 1
         else:
-            if policy == RESIDENT:
+            if policy in (RESIDENT, SECTIONS):
                 for b in reads:
-                    if not host[b]:
-                        copies.append(("D2H", b, app.buffers[b].nbytes))
-                        host[b] = 1
+                    if host[b]:
+                        continue
+                    if policy == SECTIONS and b not in writes:
+                        box = read_box(app, app.nests[ni], b)
+                        if box is None:
+                            continue
+                        whole = all(lo == 0 and hi == d for (lo, hi), d in zip(box, app.buffers[b].dims))
+                        if not whole:
+                            if not any(_contains(o, box) for o in boxes[b]):
+                                copies.append(("D2H", b, box_bytes(app, b, box)))
+                                boxes[b].append(box)
+                            continue
+                    copies.append(("D2H", b, app.buffers[b].nbytes))
+                    host[b] = 1
             for b in writes:
                 host[b], dev[b] = 1, 0
+                boxes[b] = []
     if not flags & FLAG_KEEP_OUTPUTS:
         for b, buf in enumerate(app.buffers):
             if buf.output and not host[b]:

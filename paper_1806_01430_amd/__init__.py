@@ -20,7 +20,7 @@ E = {-1: "E_ARG", -2: "E_IO", -3: "E_PARSE", -4: "E_IR", -5: "E_GENE_LEN", -6: "
      -12: "E_STATE", -13: "E_NOMEM", -14: "E_RANGE", -15: "E_UNSUPPORTED"}
 PARALLEL, PARALLEL_REDUCTION, REJECT = 0, 1, 2
 R_NONE, R_DATA_DEP, R_EXTERNAL_CALL, R_BREAK = 0, 1, 2, 3
-RESIDENT, PER_REGION = 0, 1
+RESIDENT, PER_REGION, SECTIONS = 0, 1, 2
 PRESTAGED, KEEP_OUTPUTS, GRAPH, BATCHED = 1, 2, 4, 8
 ST_OK, ST_TIMEOUT, ST_FAILED = 0, 1, 2
 BATCH_LOOP, BATCH_GROUPED, BATCH_GROUPED_GRAPH = 0, 1, 2

@@ -69,9 +69,16 @@ struct GraphEntry {
     std::vector<std::unique_ptr<HostTask>> tasks;
     std::unique_ptr<HostRestore> restore;
     int32_t launches = 0, host_nests = 0;
+    // with kernel timing: an event record node before and after every GPU
+    // nest (nest index, start event, stop event)
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> timed;
     ~GraphEntry() {
         if (reset) (void)hipGraphExecDestroy(reset);
         if (run) (void)hipGraphExecDestroy(run);
+        for (auto &t : timed) {
+            (void)hipEventDestroy(t.second.first);
+            (void)hipEventDestroy(t.second.second);
+        }
     }
 };
 
@@ -324,6 +331,42 @@ struct RunResult {
     ofl_run_stats st{};
 };
 
+// Copy box `bx` of buffer b from the device to the same place in its host
+// copy: the trailing dimensions the box covers whole and the first partial
+// one form contiguous runs; the next dimension out becomes the rows of one
+// 2-D copy, and any further dimensions are looped over.
+hipError_t copy_box_d2h(const Buffer &buf, void *host, const void *dev, const Box &bx, hipStream_t s) {
+    const int r = (int)buf.dims.size();
+    const size_t elem = buf.nbytes / (size_t)std::max<int64_t>(1, buf.count);
+    std::vector<size_t> stride(r, 1);   // elements per step of each dimension
+    for (int d = r - 2; d >= 0; --d) stride[d] = stride[d + 1] * (size_t)buf.dims[d + 1];
+    int t = r - 1;                      // innermost dimension not covered whole
+    while (t > 0 && bx.lo[t] == 0 && bx.hi[t] == buf.dims[t]) --t;
+    const size_t width = (size_t)(bx.hi[t] - bx.lo[t]) * stride[t] * elem;
+    const int rd = t - 1;               // dimension of the rows (-1: none)
+    const size_t rows = rd >= 0 ? (size_t)(bx.hi[rd] - bx.lo[rd]) : 1;
+    const size_t pitch = rd >= 0 ? stride[rd] * elem : width;
+    // loop over the dimensions outside the rows
+    std::vector<int64_t> idx(r, 0);
+    for (int d = 0; d < r; ++d) idx[d] = bx.lo[d];
+    while (true) {
+        size_t off = 0;
+        for (int d = 0; d < r; ++d) off += (size_t)idx[d] * stride[d];
+        off *= elem;
+        hipError_t e = hipMemcpy2DAsync(static_cast<char *>(host) + off, pitch,
+                                        static_cast<const char *>(dev) + off, pitch, width, rows,
+                                        hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess) return e;
+        int d = rd - 1;
+        while (d >= 0 && ++idx[d] == bx.hi[d]) {
+            idx[d] = bx.lo[d];
+            --d;
+        }
+        if (d < 0) break;
+    }
+    return hipSuccess;
+}
+
 RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *const *dev, hipStream_t stream,
                    int policy, int flags, double deadline_s) {
     RunResult rr;
@@ -411,8 +454,10 @@ RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *co
             pending = true;
             break;
         case ST_D2H:
-            e = hipMemcpyAsync(app->host[step.idx], dev[step.idx], ir.bufs[step.idx].nbytes, hipMemcpyDeviceToHost,
-                               stream);
+            e = step.box < 0 ? hipMemcpyAsync(app->host[step.idx], dev[step.idx], ir.bufs[step.idx].nbytes,
+                                              hipMemcpyDeviceToHost, stream)
+                             : copy_box_d2h(ir.bufs[step.idx], app->host[step.idx], dev[step.idx],
+                                            plan.boxes[step.box], stream);
             if (e != hipSuccess) {
                 rr.code = hip_fail(e, "D2H copy");
                 break;
@@ -581,11 +626,27 @@ int build_graphs(ofl_app *app, const std::vector<uint8_t> &placement, void *cons
         const Buffer *buf = (st.kind == ST_H2D || st.kind == ST_D2H) ? &ir.bufs[st.idx] : nullptr;
         switch (st.kind) {
         case ST_H2D: e = hipMemcpyAsync(dev[st.idx], app->host[st.idx], buf->nbytes, hipMemcpyHostToDevice, cs); break;
-        case ST_D2H: e = hipMemcpyAsync(app->host[st.idx], dev[st.idx], buf->nbytes, hipMemcpyDeviceToHost, cs); break;
-        case ST_GPU:
-            e = launch_nest(app, ir.nests[st.idx], dev, plan.env.data() + st.env, cs);
+        case ST_D2H:
+            e = st.box < 0 ? hipMemcpyAsync(app->host[st.idx], dev[st.idx], buf->nbytes, hipMemcpyDeviceToHost, cs)
+                           : copy_box_d2h(*buf, app->host[st.idx], dev[st.idx], plan.boxes[st.box], cs);
+            break;
+        case ST_GPU: {
+            hipEvent_t ev0 = nullptr, ev1 = nullptr;
+            if (app->timing) {
+                e = hipEventCreate(&ev0);
+                if (e == hipSuccess) e = hipEventCreate(&ev1);
+                if (e == hipSuccess) ge.timed.push_back({st.idx, {ev0, ev1}});
+                else {
+                    if (ev0) (void)hipEventDestroy(ev0);
+                    break;
+                }
+                e = hipEventRecord(ev0, cs);
+            }
+            if (e == hipSuccess) e = launch_nest(app, ir.nests[st.idx], dev, plan.env.data() + st.env, cs);
+            if (e == hipSuccess && app->timing) e = hipEventRecord(ev1, cs);
             ge.launches += kernel_launch_count(ir, ir.nests[st.idx]);
             break;
+        }
         case ST_CPU: {
             std::unique_ptr<HostTask> t(new HostTask());
             t->app = app;
@@ -609,6 +670,7 @@ int get_graph(ofl_app *app, const std::vector<uint8_t> &placement, void *const *
     std::vector<uint64_t> key(placement.begin(), placement.end());
     key.push_back((uint64_t)policy);
     key.push_back((uint64_t)gflags);
+    key.push_back(app->timing ? 1u : 0u);
     for (size_t b = 0; b < nb; ++b) key.push_back(reinterpret_cast<uint64_t>(dev[b]));
     auto it = app->graphs.find(key);
     if (it == app->graphs.end()) {
@@ -671,6 +733,14 @@ RunResult run_graph(ofl_app *app, const std::vector<uint8_t> &placement, void *c
         return rr;
     }
     st.t_total_s = std::chrono::duration<double>(t1 - t0).count();
+    for (const auto &te : ge.timed) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, te.second.first, te.second.second) == hipSuccess) {
+            auto &ks = app->kstats[op_name(app->ir.nests[te.first].op)];
+            ks.first += kernel_launch_count(app->ir, app->ir.nests[te.first]);
+            ks.second += ms;
+        }
+    }
     st.bytes_h2d = ge.plan.h2d;
     st.bytes_d2h = ge.plan.d2h;
     st.n_copies = ge.plan.copies;
@@ -951,7 +1021,7 @@ int ofl_mask_to_gene(const ofl_app *app, const uint8_t *mask, int32_t n_nests, u
 int ofl_plan_transfers(const ofl_app *app, const uint8_t *gene, int32_t gene_len, int32_t policy, int32_t flags,
                        uint64_t *bytes_h2d, uint64_t *bytes_d2h, int32_t *n_copies) {
     if (!app) return fail(OFL_E_ARG, "null app");
-    if (policy != OFL_POLICY_RESIDENT && policy != OFL_POLICY_PER_REGION) return fail(OFL_E_ARG, "bad policy");
+    if (policy < OFL_POLICY_RESIDENT || policy > OFL_POLICY_SECTIONS) return fail(OFL_E_ARG, "bad policy");
     if (flags & ~(OFL_RUN_PRESTAGED | OFL_RUN_KEEP_OUTPUTS | OFL_RUN_GRAPH)) return fail(OFL_E_ARG, "bad flags");
     std::vector<uint8_t> placement;
     int rc = check_gene(app, gene, gene_len, placement);
@@ -976,7 +1046,7 @@ int ofl_run_pattern(ofl_app *app, const uint8_t *gene, int32_t gene_len, void *c
     const int policy = opts ? opts->policy : OFL_POLICY_RESIDENT;
     const int flags = opts ? opts->flags : 0;
     const double deadline = opts ? opts->deadline_s : 0.0;
-    if (policy != OFL_POLICY_RESIDENT && policy != OFL_POLICY_PER_REGION) return fail(OFL_E_ARG, "bad policy");
+    if (policy < OFL_POLICY_RESIDENT || policy > OFL_POLICY_SECTIONS) return fail(OFL_E_ARG, "bad policy");
     if (flags & ~(OFL_RUN_PRESTAGED | OFL_RUN_KEEP_OUTPUTS | OFL_RUN_GRAPH)) return fail(OFL_E_ARG, "bad flags");
     RunResult rr = run_any(app, placement, dev_bufs, static_cast<hipStream_t>(stream), policy, flags, deadline);
     if (stats) *stats = rr.st;

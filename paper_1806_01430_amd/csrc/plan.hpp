@@ -15,11 +15,18 @@ struct Step {
     StepKind kind;
     int idx;            // buffer (copies) or nest (executions)
     int env;            // offset into Plan::env (values of the repeat variables)
+    int box = -1;       // copies: index into Plan::boxes, -1 = the whole buffer
+};
+
+// A box of a buffer: per dimension the index range [lo, hi).
+struct Box {
+    std::vector<int64_t> lo, hi;
 };
 
 struct Plan {
     std::vector<Step> steps;
     std::vector<int64_t> env;        // repeat-variable values, one block per nest step
+    std::vector<Box> boxes;          // sections copied by SECTIONS-policy steps
     uint64_t h2d = 0, d2h = 0;
     int32_t copies = 0, launches = 0, host_nests = 0;
     // Whether the set-up content of a buffer's host / device copy is consumed
@@ -29,7 +36,7 @@ struct Plan {
     std::vector<char> host_valid, dev_valid;
 };
 
-// placement[nest] = 1 for GPU.  policy: 0 RESIDENT, 1 PER_REGION; flags: OFL_RUN_*.
+// placement[nest] = 1 for GPU.  policy: OFL_POLICY_*; flags: OFL_RUN_*.
 void build_plan(const AppIR &app, const std::vector<uint8_t> &placement, int policy, int flags, Plan &out);
 
 }  // namespace ofl

@@ -15,7 +15,7 @@ import time
 
 import numpy as np
 
-from . import App, app_path, ga_params, RESIDENT, PER_REGION, PRESTAGED, KEEP_OUTPUTS, GRAPH, BATCHED
+from . import App, app_path, ga_params, RESIDENT, PER_REGION, SECTIONS, PRESTAGED, KEEP_OUTPUTS, GRAPH, BATCHED
 
 
 def main(argv=None):
@@ -30,7 +30,7 @@ def main(argv=None):
     ap.add_argument("--ga-seed", type=int, default=1)
     ap.add_argument("--reps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--policy", choices=["resident", "per_region"], default="resident")
+    ap.add_argument("--policy", choices=["resident", "per_region", "sections"], default="resident")
     ap.add_argument("--graph", action="store_true", help="measure graph replays")
     ap.add_argument("--batched", action="store_true",
                     help="measure each generation's new genes in one submission (graph chain)")
@@ -47,7 +47,7 @@ def main(argv=None):
     src = args.app if args.app.endswith(".json") else app_path(args.app)
     app = App(src, seed=args.seed)
     bufs = app.alloc_device_buffers("cuda:0")
-    policy = RESIDENT if args.policy == "resident" else PER_REGION
+    policy = {"resident": RESIDENT, "per_region": PER_REGION, "sections": SECTIONS}[args.policy]
     flags = (GRAPH if args.graph else 0) | (BATCHED if args.batched else 0)
     params = ga_params(M=args.M, T=args.T, Pc=args.Pc, Pm=args.Pm, p=args.p, seed=args.ga_seed, reps=args.reps,
                        warmup=args.warmup, policy=policy, flags=flags, deadline_factor=args.deadline_factor)

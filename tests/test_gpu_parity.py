@@ -443,3 +443,38 @@ def test_ga_batched_generations_medium_reduced():
     assert res["n_measured"] == len(uniq)
     assert np.all(res["status"] == ofl.ST_OK)
     assert res["best_time"] == float(np.min(res["times"]))
+
+
+def test_kernel_timing_in_graph_replays():
+    doc = workloads.app_doc("medium", **workloads.SMALL_MEDIUM)
+    app = ofl.App(json.dumps(doc))
+    o = ir.load(doc)
+    o32, o64 = parity.oracle_outputs(o, 1)
+    bufs = app.alloc_device_buffers()
+    gene = [1] * app.gene_len
+    app.set_kernel_timing(True)
+    say("case graph replays with timing nodes")
+    for _ in range(3):
+        st = app.run_pattern(gene, bufs, flags=ofl.GRAPH | ofl.PRESTAGED)
+        assert st["status"] == ofl.ST_OK
+        assert not parity.compare(o, app.read_all(), o32, o64)
+    n, ms = app.kernel_stats("stencil19")
+    assert n == 3 * doc["params"]["SWEEPS"] and ms > 0
+    n, ms = app.kernel_stats("gemm")
+    assert n == 3 and ms > 0
+    app.set_kernel_timing(False)
+    app.run_pattern(gene, bufs, flags=ofl.GRAPH | ofl.PRESTAGED)
+    assert not parity.compare(o, app.read_all(), o32, o64)
+
+
+@pytest.mark.parametrize("name,params", [("medium", workloads.SMALL_MEDIUM), ("large", workloads.SMALL_LARGE)])
+def test_sections_policy_random_genes(name, params):
+    # the SECTIONS policy copies boxes (columns, rows, sub-blocks) out for the
+    # CPU nests; every gene must still give the oracle's values, eager and as
+    # graph replays
+    doc = workloads.app_doc(name, **params)
+    rng = random.Random(17)
+    a = ofl.App(json.dumps(doc)).gene_len
+    genes = [[1] * a] + [[rng.randint(0, 1) for _ in range(a)] for _ in range(5)]
+    _run_and_compare(doc, genes, policies=(ofl.SECTIONS,),
+                     flags_list=(0, ofl.PRESTAGED | ofl.KEEP_OUTPUTS, ofl.GRAPH | ofl.PRESTAGED))

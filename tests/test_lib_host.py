@@ -103,6 +103,23 @@ def test_plans_random_genes_match_oracle(name):
                 assert app.plan_transfers(g, pol, flags) == xfer.totals(o, pl, pol, flags)
 
 
+@pytest.mark.parametrize("name", ["tiny", "medium", "large"])
+def test_sections_plans_match_oracle(name):
+    app = ofl.App(workloads.app_path(name))
+    o = ir.load(workloads.app_path(name))
+    v = D.check_app(o)
+    rng = random.Random(5)
+    genes = [tuple([1] * app.gene_len), tuple([0] * app.gene_len)]
+    genes += [tuple(rng.randint(0, 1) for _ in range(app.gene_len)) for _ in range(60)]
+    for g in genes:
+        pl = xfer.placement_of_gene(o, v, g)
+        for flags in (0, 1, 2, 3):
+            want = xfer.totals(o, pl, xfer.SECTIONS, flags)
+            assert app.plan_transfers(g, ofl.SECTIONS, flags) == want, (g, flags)
+            # device-side copies do not depend on how much the host copies out
+            assert want[0] == xfer.totals(o, pl, xfer.RESIDENT, flags)[0]
+
+
 def test_mask_to_gene():
     app = ofl.App(workloads.app_path("medium"))
     v = app.verdicts()

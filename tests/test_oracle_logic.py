@@ -268,3 +268,37 @@ def test_run_medium_small_closed_forms():
     assert np.max(np.abs(out["w"] - w_ref)) < 1e-6
     A, B = out["A"].astype(np.float64), out["B"].astype(np.float64)
     assert np.max(np.abs(Cm - (A @ B + 0.5 * A)) / Cm) < 1e-5
+
+
+def test_sections_plan_medium_by_hand():
+    # all parallel nests on the GPU: the two CPU recurrences read one column
+    # of S (rows 1..N-1 of column 0) and one row of p (p[1][1][1..K-1]); with
+    # sections only those boxes cross PCIe instead of the whole arrays
+    o = ir.load(workloads.app_doc("medium"))
+    v = D.check_app(o)
+    pl = xfer.placement_of_gene(o, v, [1] * 10)
+    N, K = o.params["N"], o.params["K"]
+    cs = xfer.plan(o, pl, xfer.SECTIONS, xfer.FLAG_PRESTAGED | xfer.FLAG_KEEP_OUTPUTS)
+    assert [(c[0], o.buffers[c[1]].name, c[2]) for c in cs] == [("D2H", "S", 4 * (N - 1)), ("D2H", "p", 4 * (K - 1))]
+    rs = xfer.plan(o, pl, xfer.RESIDENT, xfer.FLAG_PRESTAGED | xfer.FLAG_KEEP_OUTPUTS)
+    assert [c[2] for c in rs] == [4 * N * N, 4 * o.params["I"] * o.params["J"] * K]
+
+
+def test_sections_boxes_reused_and_dropped():
+    # two CPU readers of the same stale buffer: the second reads inside the
+    # first one's box (no copy); a GPU write in between drops the box
+    doc = {"name": "t", "params": {"N": 16},
+           "buffers": [{"name": "X", "dims": ["N", "N"]}, {"name": "Y", "dims": ["N"]}],
+           "program": [
+               {"nest": "w", "op": "none", "loops": [["i", "0", "N"], ["j", "0", "N"]], "access": [["X", "w", "i", "j"]]},
+               {"nest": "r1", "op": "none", "loops": [["i", "2", "10"]], "access": [["Y", "w", "i"], ["X", "r", "i", "3"], ["X", "r", "i", "5"]]},
+               {"nest": "r2", "op": "none", "loops": [["i", "4", "6"]], "access": [["Y", "w", "i"], ["X", "r", "i", "4"]]},
+               {"nest": "w2", "op": "none", "loops": [["i", "0", "N"], ["j", "0", "N"]], "access": [["X", "w", "i", "j"]]},
+               {"nest": "r3", "op": "none", "loops": [["i", "4", "6"]], "access": [["Y", "w", "i"], ["X", "r", "i", "4"]]},
+               {"nest": "r4", "op": "none", "loops": [["i", "0", "N"], ["j", "0", "N"]], "access": [["Y", "w", "i"], ["X", "r", "i", "j"]]}]}
+    o = ir.load(doc)
+    cs = xfer.plan(o, [1, 0, 0, 1, 0, 0], xfer.SECTIONS, xfer.FLAG_KEEP_OUTPUTS)
+    got = [(c[0], o.buffers[c[1]].name, c[2]) for c in cs]
+    # r1: rows 2..9, columns 3..5 -> 8 x 3 floats; r2 inside it; w2 drops the
+    # box; r3 copies rows 4..5 column 4; r4 reads the whole array: whole copy
+    assert got == [("D2H", "X", 4 * 8 * 3), ("D2H", "X", 4 * 2 * 1), ("D2H", "X", 4 * 16 * 16)]
