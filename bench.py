@@ -27,7 +27,7 @@ METRIC = "app time & speedup vs 1-core oracle; stencil GB/s, GEMM MFMA % of peak
 # by the readings of a plain 1 GiB copy (reads x2.000, writes x1.000); see
 # profiles/stencil19_medium_129x129x257.md.  Must be re-measured (or dropped)
 # whenever the kernel changes.
-MEASURED_TRAFFIC = {("stencil19", 129, 129, 257): (2.000 * 9501.3 + 16236.8) * 1024}
+MEASURED_TRAFFIC = {}
 HBM_PEAK_GBS = 8000.0
 FP32_MFMA_PEAK_TFLOPS = 157.3
 
@@ -67,45 +67,99 @@ def run_medium(args):
     gene = [1] * app.gene_len
     bufs = app.alloc_device_buffers("cuda:0")
     flags = ofl.PRESTAGED | ofl.KEEP_OUTPUTS
-    gflags = flags | ofl.GRAPH
-    # timing on before the warm-up: the graphs are captured with an event
-    # record node around every GPU nest, so the timed steps replay exactly
-    # the graphs whose kernels they time
-    app.set_kernel_timing(True)
+    policy = ofl.SECTIONS
+    # the timed region: eager runs (one launch per kernel) with HIP events in
+    # the dispatch packets of the dominant kernel's launches only (timing
+    # every kernel costs ~1 ms per step in host-side event handling)
+    app.set_kernel_timing_op("stencil19")
     for _ in range(args.warmup):
-        app.run_pattern(gene, bufs, flags=gflags)
+        app.run_pattern(gene, bufs, policy=policy, flags=flags)
     torch.cuda.synchronize()
-    app.set_kernel_timing(True)          # clears the warm-up's totals
+    app.set_kernel_timing(True)
     internal = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        st = app.run_pattern(gene, bufs, flags=gflags)
+        st = app.run_pattern(gene, bufs, policy=policy, flags=flags)
         internal.append(st["t_total_s"])
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     app.set_kernel_timing(False)
+    dom = kernel_table(app, ["stencil19"])
+    # every kernel's time, in a separate instrumented pass (context)
+    app.set_kernel_timing_op(None)
+    app.set_kernel_timing(True)
+    for _ in range(10):
+        app.run_pattern(gene, bufs, policy=policy, flags=flags)
+    app.set_kernel_timing(False)
     ktab = kernel_table(app, ["stencil19", "copy_interior", "gemm", "init_uniform", "add_scaled", "transpose",
                               "avg2", "sumsq", "copy", "scale"])
-    # context: the same steps run eagerly (one launch at a time, no graphs)
-    for _ in range(2):
-        app.run_pattern(gene, bufs, flags=flags)
+    # uninstrumented graph replays (context)
+    gflags = flags | ofl.GRAPH
+    for _ in range(3):
+        app.run_pattern(gene, bufs, policy=policy, flags=gflags)
     torch.cuda.synchronize()
-    te0 = time.perf_counter()
-    einternal = []
+    tg0 = time.perf_counter()
+    ginternal = []
     for _ in range(args.steps):
-        einternal.append(app.run_pattern(gene, bufs, flags=flags)["t_total_s"])
+        ginternal.append(app.run_pattern(gene, bufs, policy=policy, flags=gflags)["t_total_s"])
     torch.cuda.synchronize()
-    ewall = time.perf_counter() - te0
-    einternal.sort()
+    gwall = time.perf_counter() - tg0
+    ginternal.sort()
     # paper protocol for context: set-up content copied in, outputs copied out
     pcie = []
     for _ in range(3):
-        pcie.append(app.run_pattern(gene, bufs, flags=0)["t_total_s"])
+        pcie.append(app.run_pattern(gene, bufs, policy=policy, flags=0)["t_total_s"])
+    # the whole-buffer transfer policy for comparison
+    res_t = []
+    for _ in range(3):
+        app.run_pattern(gene, bufs, policy=ofl.RESIDENT, flags=flags)
+    for _ in range(10):
+        res_t.append(app.run_pattern(gene, bufs, policy=ofl.RESIDENT, flags=flags)["t_total_s"])
+    res_t.sort()
     internal.sort()
     pcie.sort()
     return {"app": app, "params": P, "wall": wall, "internal_median_s": internal[len(internal) // 2],
-            "pcie_median_s": pcie[1], "kernels": ktab, "last": st, "eager_wall": ewall,
-            "eager_internal_median_s": einternal[len(einternal) // 2]}
+            "pcie_median_s": pcie[1], "kernels": ktab, "dominant": dom, "last": st, "graph_wall": gwall,
+            "resident_median_s": res_t[len(res_t) // 2],
+            "graph_internal_median_s": ginternal[len(ginternal) // 2]}
+
+
+def run_kernels_large(args):
+    """Stencil on the largest grid and the FP32 GEMM at 8192 (the sizes where
+    the HBM and MFMA rooflines are meaningful)."""
+    import paper_1806_01430_amd as ofl
+    from workloads import appgen
+
+    out = {}
+    I, J, K = 513, 513, 1025
+    app = ofl.App(json.dumps(appgen.stencil_app(I, J, K, 10)), seed=1)
+    bufs = app.alloc_device_buffers("cuda:0")
+    app.run_pattern([1, 1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
+    app.set_kernel_timing(True)
+    for _ in range(2):
+        app.run_pattern([1, 1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
+    n, ms = app.kernel_stats("stencil19")
+    avg = ms / n * 1e-3
+    gbs = stencil_bytes(I, J, K) / avg / 1e9
+    nc, msc = app.kernel_stats("copy_interior")
+    out["stencil19_513x513x1025"] = {"avg_us": avg * 1e6, "GBps": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
+                                     "copy_interior_GBps": 8 * (I - 2) * (J - 2) * (K - 2) / (msc / nc * 1e-3) / 1e9}
+    del bufs, app
+    N = 8192
+    doc = {"name": "gemm8192", "params": {"N": N},
+           "buffers": [{"name": b, "dims": ["N", "N"], "output": b == "C"} for b in ("A", "B", "C")],
+           "program": [appgen.init_nest(["A", "B"], [0, 1]), appgen.gemm_nest("A", "B", "C")]}
+    app = ofl.App(json.dumps(doc), seed=1)
+    bufs = app.alloc_device_buffers("cuda:0")
+    app.run_pattern([1, 1], bufs, flags=ofl.KEEP_OUTPUTS)
+    app.set_kernel_timing(True)
+    for _ in range(3):
+        app.run_pattern([1, 1], bufs, flags=ofl.KEEP_OUTPUTS)
+    n, ms = app.kernel_stats("gemm")
+    avg = ms / n * 1e-3
+    tf = 2.0 * N ** 3 / avg / 1e12
+    out["gemm_f32_8192"] = {"avg_ms": avg * 1e3, "TFLOPs": tf, "frac_mfma": tf / FP32_MFMA_PEAK_TFLOPS}
+    return out
 
 
 def run_precision(args):
@@ -129,7 +183,7 @@ def run_precision(args):
         app.set_kernel_timing(True)
         ts = sorted(app.run_pattern(gene, bufs, flags=flags)["t_total_s"] for _ in range(3))
         n, ms = app.kernel_stats("gemm")
-        gemm_ms = ms / n
+        gemm_ms = ms / 3                 # per execution of the product nest (all its launches)
         out[prec] = {"app_time_ms": round(1e3 * ts[1], 3), "gemm_ms": round(gemm_ms, 4),
                      "gemm_TFLOPs_fp32_equiv": round(2.0 * N ** 3 / (gemm_ms * 1e-3) / 1e12, 1)}
         del app, bufs
@@ -270,21 +324,24 @@ def main():
     ms_per_step = 1e3 * r["wall"] / args.steps
     value = args.steps / r["wall"]
     ks = r["kernels"]
-    # roofline of the dominant kernel (largest total time in the timed steps)
+    # the dominant kernel (largest total time in the instrumented pass) is the
+    # one the timed region carries events for; its roofline uses the launches
+    # of the timed steps
     I, J, K = P["I"], P["J"], P["K"]
     algo = {"stencil19": stencil_bytes(I, J, K), "copy_interior": copy_interior_bytes(I, J, K)}
     for name, nbytes in algo.items():
         if name in ks:
             ks[name]["GBps"] = nbytes / (ks[name]["avg_us"] * 1e-6) / 1e9
     dom = max(ks.items(), key=lambda kv: kv[1]["total_ms"])[0]
-    rk = dom if dom in algo else "stencil19"
-    achieved = algo[rk] / (ks[rk]["avg_us"] * 1e-6) / 1e9
+    rk = "stencil19"
+    live = r["dominant"][rk]
+    achieved = algo[rk] / (live["avg_us"] * 1e-6) / 1e9
     traffic = MEASURED_TRAFFIC.get((rk, I, J, K))
     roofline = {"kernel": rk, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": round(traffic) if traffic else None,
-                "bytes_per_launch": algo[rk], "avg_launch_us": round(ks[rk]["avg_us"], 3),
-                "dominant_by_time": dom}
+                "bytes_per_launch": algo[rk], "avg_launch_us": round(live["avg_us"], 3),
+                "launches_timed": live["launches"], "dominant_by_time": dom}
     g = ks.get("gemm")
     gemm_tf = 2.0 * 1024 ** 3 / (g["avg_us"] * 1e-6) / 1e12 if g else None
 
@@ -294,14 +351,16 @@ def main():
             "data": "synthetic (seeded SplitMix64 inputs, sine-mode grid)",
             "config": {"workload": "medium app: 12 loop nests (2 loop-carried recurrences on the CPU), "
                                    "GEMM 1024x1024, 19-point sweep 129x129x257 x 100 sweeps + FP64 residual",
-                       "gene": "all 10 parallelisable nests on the GPU", "policy": "resident",
-                       "execution": "each step one ofl_run_pattern replaying the pattern's captured HIP graphs "
-                                    "(reset graph untimed inside the call, run graph timed)",
+                       "gene": "all 10 parallelisable nests on the GPU",
+                       "policy": "sections (CPU recurrences copy out only the column / row they read)",
+                       "execution": "each step one eager ofl_run_pattern (kernel by kernel on one stream); "
+                                    "HIP events in the dispatch packets of the stencil19 launches",
                        "inputs": "resident in HBM at the start of the timed region; outputs left in HBM"},
             "app_time_ms": round(1e3 * r["internal_median_s"], 4),
             "app_time_pcie_ms": round(1e3 * r["pcie_median_s"], 4),
-            "eager_runs_per_s": round(args.steps / r["eager_wall"], 3),
-            "eager_app_time_ms": round(1e3 * r["eager_internal_median_s"], 4),
+            "graph_runs_per_s": round(args.steps / r["graph_wall"], 3),
+            "graph_app_time_ms": round(1e3 * r["graph_internal_median_s"], 4),
+            "app_time_resident_policy_ms": round(1e3 * r["resident_median_s"], 4),
             "gemm1024_TFLOPs": round(gemm_tf, 2) if gemm_tf else None,
             "roofline": roofline,
             "kernels_medium": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in ks.items()}}

@@ -279,6 +279,10 @@ int ofl_read_buffer(ofl_app *app, int32_t buf, void *host_dst, uint64_t bytes);
  * after each replay. */
 int ofl_set_kernel_timing(ofl_app *app, int32_t enable);
 
+/* Restrict kernel timing to nests of kind `op` (e.g. "stencil19"); NULL or
+ * "" times every kind.  Errors: OFL_E_ARG for an unknown kind. */
+int ofl_set_kernel_timing_op(ofl_app *app, const char *op);
+
 /* Accumulated launches and total kernel time (ms) of op kind `op`
  * (e.g. "stencil19", "gemm") since timing was enabled.  Unknown op: zeros. */
 int ofl_kernel_stats(const ofl_app *app, const char *op, int64_t *launches, double *total_ms);

@@ -103,43 +103,39 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt(const T *__restrict__ A, c
     };
     const int r = lane & 15, g = lane >> 4;
     auto compute = [&](int buf) {
-        // lane group g owns bytes [32g, 32g+32) of the slab: two 16-byte reads
-        u32x4 af[TM][2], bfr[TN][2];
+        // lane group g owns bytes [32g, 32g+32) of the slab, read as two
+        // 16-byte halves h; each half feeds one k-step of every accumulator
 #pragma unroll
-        for (int i = 0; i < TM; ++i)
+        for (int h = 0; h < 2; ++h) {
+            u32x4 af[TM], bfr[TN];
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
-                af[i][h] = *reinterpret_cast<const u32x4 *>(&As[buf][(wm * WM + i * 16 + r) * LDS_ROW + 32 * g + 16 * h]);
+            for (int i = 0; i < TM; ++i)
+                af[i] = *reinterpret_cast<const u32x4 *>(&As[buf][(wm * WM + i * 16 + r) * LDS_ROW + 32 * g + 16 * h]);
 #pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-                bfr[j][h] = *reinterpret_cast<const u32x4 *>(&Bs[buf][(wn * WN + j * 16 + r) * LDS_ROW + 32 * g + 16 * h]);
-        if constexpr (sizeof(T) == 2) {
-            // 16 bf16 per lane = two MFMA steps of 8
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int j = 0; j < TN; ++j)
+                bfr[j] = *reinterpret_cast<const u32x4 *>(&Bs[buf][(wn * WN + j * 16 + r) * LDS_ROW + 32 * g + 16 * h]);
+            if constexpr (sizeof(T) == 2) {
+                // 8 bf16 per lane and MFMA
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
                     for (int j = 0; j < TN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[i][h]),
-                                                                            __builtin_bit_cast(bf16x8, bfr[j][h]),
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[i]),
+                                                                            __builtin_bit_cast(bf16x8, bfr[j]),
                                                                             acc[i][j], 0, 0, 0);
-        } else {
-            // 32 fp8 per lane = four MFMA steps of 8
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
+            } else {
+                // 16 fp8 per lane: two MFMA steps of 8
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
 #pragma unroll
                     for (int i = 0; i < TM; ++i)
 #pragma unroll
                         for (int j = 0; j < TN; ++j) {
-                            const fp8x8 a8 = (fp8x8)(((unsigned long)af[i][h][2 * q + 1] << 32) | af[i][h][2 * q]);
-                            const fp8x8 b8 = (fp8x8)(((unsigned long)bfr[j][h][2 * q + 1] << 32) | bfr[j][h][2 * q]);
+                            const fp8x8 a8 = (fp8x8)(((unsigned long)af[i][2 * q + 1] << 32) | af[i][2 * q]);
+                            const fp8x8 b8 = (fp8x8)(((unsigned long)bfr[j][2 * q + 1] << 32) | bfr[j][2 * q]);
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a8, b8, acc[i][j], 0, 0, 0);
                         }
+            }
         }
     };
 
@@ -192,7 +188,12 @@ hipError_t gemm_f32(const float *A, const float *B, float *C, int64_t M, int64_t
 
 // ---------------------------------------------------------------- split-precision GEMM
 namespace {
-constexpr int kNT = 128;   // tile of the k-contiguous product (rows of A', rows of B')
+// Tile of the k-contiguous product (rows of A' x rows of B'): 128 x 128.  A
+// 256 x 256 tile (4 waves of 128 x 128 in AGPRs, one block per CU) halves the
+// LDS traffic per MFMA but measured slower on gfx950 at 4096 (521 vs 472 us
+// for the bf16x3 product): one wave per SIMD leaves the LDS and global
+// latencies exposed.
+int nt_tile(int64_t, int64_t) { return 128; }
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -200,6 +201,7 @@ int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 // bf16 inputs are already tile-aligned.  float area (fp8 only): row scales,
 // column scales, their inverses, and per-slice column maxima.
 struct NtLayout {
+    int tile = 128;
     int64_t Mp = 0, Np = 0, Kp = 0, kx = 0;
     int elem = 2;
     bool a_copy = true;    // A' is written (else A is used in place)
@@ -211,8 +213,9 @@ NtLayout nt_layout(int64_t M, int64_t N, int64_t K, int variant) {
     NtLayout L;
     L.elem = variant == 2 ? 1 : 2;
     L.kx = variant == 3 ? K : 3 * K;
-    L.Mp = round_up(M, kNT);
-    L.Np = round_up(N, kNT);
+    L.tile = nt_tile(M, N);
+    L.Mp = round_up(M, L.tile);
+    L.Np = round_up(N, L.tile);
     L.Kp = round_up(L.kx, 128 / L.elem);
     L.a_copy = variant != 3 || L.Mp != M || L.Kp != K;
     L.b_pad = L.Np != N || L.Kp != L.kx;
@@ -222,6 +225,14 @@ NtLayout nt_layout(int64_t M, int64_t N, int64_t K, int variant) {
     const int64_t nf = variant == 2 ? 2 * (L.Mp + L.Np) + (int64_t)kColSlices * L.Np : 0;
     L.total = round_up(L.f_off + nf * (int64_t)sizeof(float), 256);
     return L;
+}
+
+template <typename T, bool SCALED>
+hipError_t launch_nt(const NtLayout &L, const void *A, const void *B, float *C, int64_t M, int64_t N,
+                     const float *sa, const float *sb, hipStream_t s) {
+    const unsigned tiles = (unsigned)((L.Mp / L.tile) * (L.Np / L.tile));
+    return launch((k_gemm_nt<T, 128, 128, SCALED>), dim3(tiles), dim3(kThreads), 0, s, static_cast<const T *>(A),
+                  static_cast<const T *>(B), C, (int)M, (int)N, (int)L.Kp, sa, sb);
 }
 
 bool nt_sizes_ok(int64_t M, int64_t N, int64_t K) {
@@ -255,25 +266,18 @@ hipError_t gemm_split(const float *A, const float *B, float *C, int64_t M, int64
     void *Ap = w, *Bp = w + L.a_bytes;
     float *f = reinterpret_cast<float *>(w + L.f_off);
     float *sa = f, *sb = f + L.Mp, *isa = sb + L.Np, *isb = isa + L.Mp, *colmax = isb + L.Np;
-    const unsigned tiles = (unsigned)((L.Mp / kNT) * (L.Np / kNT));
     hipError_t e = L.b_pad ? fill_zero(Bp, (uint64_t)L.b_bytes, s) : hipSuccess;
     if (variant == 1) {
         if (e == hipSuccess) e = prep_a(A, Ap, nullptr, (int)M, (int)K, (int)L.Mp, (int)L.Kp, 0, s);
         if (e == hipSuccess) e = split_bt(B, Bp, nullptr, (int)K, (int)N, (int)L.Kp, 0, s);
-        if (e == hipSuccess)
-            e = launch((k_gemm_nt<unsigned short, kNT, kNT, false>), dim3(tiles), dim3(kThreads), 0, s,
-                       static_cast<const unsigned short *>(Ap), static_cast<const unsigned short *>(Bp), C, (int)M,
-                       (int)N, (int)L.Kp, (const float *)nullptr, (const float *)nullptr);
+        if (e == hipSuccess) e = launch_nt<unsigned short, false>(L, Ap, Bp, C, M, N, nullptr, nullptr, s);
         return e;
     }
     if (e == hipSuccess) e = row_scales(A, sa, isa, (int)M, (int)K, s);
     if (e == hipSuccess) e = col_scales(B, sb, isb, colmax, (int)K, (int)N, (int)L.Np, s);
     if (e == hipSuccess) e = prep_a(A, Ap, sa, (int)M, (int)K, (int)L.Mp, (int)L.Kp, 1, s);
     if (e == hipSuccess) e = split_bt(B, Bp, sb, (int)K, (int)N, (int)L.Kp, 1, s);
-    if (e == hipSuccess)
-        e = launch((k_gemm_nt<unsigned char, kNT, kNT, true>), dim3(tiles), dim3(kThreads), 0, s,
-                   static_cast<const unsigned char *>(Ap), static_cast<const unsigned char *>(Bp), C, (int)M, (int)N,
-                   (int)L.Kp, (const float *)isa, (const float *)isb);
+    if (e == hipSuccess) e = launch_nt<unsigned char, true>(L, Ap, Bp, C, M, N, isa, isb, s);
     return e;
 }
 
@@ -287,17 +291,13 @@ hipError_t gemm_bf16(const uint16_t *A, const uint16_t *B, float *C, int64_t M, 
     unsigned char *w = static_cast<unsigned char *>(ws);
     void *Bp = w + L.a_bytes;
     const void *Ause = A;
-    const unsigned tiles = (unsigned)((L.Mp / kNT) * (L.Np / kNT));
     hipError_t e = L.b_pad ? fill_zero(Bp, (uint64_t)L.b_bytes, s) : hipSuccess;
     if (L.a_copy) {
         if (e == hipSuccess) e = prep_a(A, w, nullptr, (int)M, (int)K, (int)L.Mp, (int)L.Kp, 2, s);
         Ause = w;
     }
     if (e == hipSuccess) e = split_bt(B, Bp, nullptr, (int)K, (int)N, (int)L.Kp, 2, s);
-    if (e == hipSuccess)
-        e = launch((k_gemm_nt<unsigned short, kNT, kNT, false>), dim3(tiles), dim3(kThreads), 0, s,
-                   static_cast<const unsigned short *>(Ause), static_cast<const unsigned short *>(Bp), C, (int)M,
-                   (int)N, (int)L.Kp, (const float *)nullptr, (const float *)nullptr);
+    if (e == hipSuccess) e = launch_nt<unsigned short, false>(L, Ause, Bp, C, M, N, nullptr, nullptr, s);
     return e;
 }
 

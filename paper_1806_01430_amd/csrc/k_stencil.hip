@@ -32,7 +32,7 @@ namespace {
 
 constexpr int kThreads = kStencilThreads;
 
-template <int JR>
+template <int JR, int SP>
 __global__ __launch_bounds__(kThreads) void k_stencil19(const float *__restrict__ p, float *__restrict__ q, Geo g,
                                                         double *res_slot, double *partials, unsigned *counter) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -46,12 +46,13 @@ __global__ __launch_bounds__(kThreads) void k_stencil19(const float *__restrict_
     const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, g.bytes, kBufferConfig);
     const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc((void *)q, (short)0, g.bytes, kBufferConfig);
     double acc = 0.0;
-    for (int w = lb * kWavesPerBlock + wib; w < g.items; w += nwaves) acc = stencil_item<JR>(rp, rq, g, w, lane, acc);
+    for (int w = lb * kWavesPerBlock + wib; w < g.items; w += nwaves) acc = stencil_item<JR, SP>(rp, rq, g, w, lane, acc);
     reduce_finish(acc, partials, counter, res_slot);
 }
 
-// p[i][j][k] = q[i][j][k] on the interior: a wave copies kRows consecutive
+// p[i][j][k] = q[i][j][k] on the interior: a wave copies ROWS consecutive
 // rows (i, j) at a time.
+template <int ROWS, int POL>
 __global__ __launch_bounds__(kThreads) void k_copy_interior(float *__restrict__ p, const float *__restrict__ q,
                                                             int I, int J, int K) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -61,11 +62,12 @@ __global__ __launch_bounds__(kThreads) void k_copy_interior(float *__restrict__ 
     const int bytes = I * J * K * 4;
     const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc((void *)q, (short)0, bytes, kBufferConfig);
     const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, bytes, kBufferConfig);
-    for (int row0 = gwave * kRows; row0 < rows; row0 += nwaves * kRows) copy_rows(rp, rq, J, K, rows, row0, lane);
+    for (int row0 = gwave * ROWS; row0 < rows; row0 += nwaves * ROWS) copy_rows<ROWS, POL>(rp, rq, J, K, rows, row0, lane);
 }
 
 struct Config {
     int JR;
+    bool store_nt = false;   // q written with the non-temporal policy
     Geo g;
     unsigned blocks;
 };
@@ -103,6 +105,11 @@ Config choose(int64_t I, int64_t J, int64_t K) {
     }
     c.JR = JR;
     c.g = make_geo(I, J, K, JR, IC);
+    // q with the non-temporal policy on grids up to 512 MB: measured faster
+    // (with the copy that follows) at 129^3- and 257^3-class grids, slower at
+    // the 513^3 class (783 vs 666 us); OFL_STENCIL_NT=0/1 overrides
+    c.store_nt = I * J * K * 4 <= (int64_t)512 << 20;
+    if (const char *nt = std::getenv("OFL_STENCIL_NT")) c.store_nt = nt[0] == '1';
     const int64_t resident_blocks = (int64_t)cu_count() * resident_blocks_per_cu(JR);
     int64_t blocks = ((int64_t)c.g.items + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > resident_blocks) blocks = resident_blocks;
@@ -114,14 +121,18 @@ Config choose(int64_t I, int64_t J, int64_t K) {
 template <int JR>
 hipError_t launch_t(const Config &c, const float *p, float *q, double *res_slot, const ReduceScratch &rs,
                     hipStream_t s) {
-    return launch((k_stencil19<JR>), dim3(c.blocks), dim3(kThreads), 0, s, p, q, c.g, res_slot, rs.partials,
-                       rs.counter);
+    if (c.store_nt)
+        return launch((k_stencil19<JR, kNonTemporal>), dim3(c.blocks), dim3(kThreads), 0, s, p, q, c.g, res_slot,
+                      rs.partials, rs.counter);
+    return launch((k_stencil19<JR, 0>), dim3(c.blocks), dim3(kThreads), 0, s, p, q, c.g, res_slot, rs.partials,
+                  rs.counter);
 }
 
 template <int JR>
 int occupancy_t() {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_stencil19<JR>, kThreads, 0) != hipSuccess || n < 1) n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_stencil19<JR, 0>, kThreads, 0) != hipSuccess || n < 1)
+        n = 1;
     return n;
 }
 
@@ -189,13 +200,40 @@ hipError_t stencil19(const float *p, float *q, int64_t I, int64_t J, int64_t K, 
     return launch_t<2>(c, p, q, res_slot, rs, s);
 }
 
+// Tuning knob: OFL_COPY_CFG="ROWS,BLOCKS_PER_CU,NT" (ROWS in {2,4,8}, NT 0/1).
+void copy_env_override(int &rows_per_wave, int &bpc, int &nt) {
+    const char *s = std::getenv("OFL_COPY_CFG");
+    if (!s) return;
+    int a = 0, b = 0, c = 0;
+    if (std::sscanf(s, "%d,%d,%d", &a, &b, &c) < 2) return;
+    if (a == 2 || a == 4 || a == 8) rows_per_wave = a;
+    if (b >= 1 && b <= 64) bpc = b;
+    nt = c == 1 ? 1 : 0;
+}
+
+template <int ROWS>
+hipError_t launch_copy(float *p, const float *q, int64_t I, int64_t J, int64_t K, int bpc, int nt, hipStream_t s) {
+    const int64_t rows = (I - 2) * (J - 2);
+    int64_t blocks = (rows + kWavesPerBlock * ROWS - 1) / (kWavesPerBlock * ROWS);
+    if (blocks > (int64_t)cu_count() * bpc) blocks = (int64_t)cu_count() * bpc;
+    if (nt)
+        return launch((k_copy_interior<ROWS, kNonTemporal>), dim3((unsigned)blocks), dim3(kThreads), 0, s, p, q,
+                      (int)I, (int)J, (int)K);
+    return launch((k_copy_interior<ROWS, 0>), dim3((unsigned)blocks), dim3(kThreads), 0, s, p, q, (int)I, (int)J,
+                  (int)K);
+}
+
 hipError_t copy_interior(float *p, const float *q, int64_t I, int64_t J, int64_t K, hipStream_t s) {
     if (I < 3 || J < 3 || K < 3) return hipSuccess;
     if (I * J * K * 4 >= (1ll << 31)) return hipErrorInvalidValue;   // 32-bit buffer offsets
-    const int64_t rows = (I - 2) * (J - 2);
-    int64_t blocks = (rows + kWavesPerBlock * kRows - 1) / (kWavesPerBlock * kRows);
-    if (blocks > (int64_t)cu_count() * 16) blocks = (int64_t)cu_count() * 16;
-    return launch(k_copy_interior, dim3((unsigned)blocks), dim3(kThreads), 0, s, p, q, (int)I, (int)J, (int)K);
+    // measured on gfx950: 8 rows per wave and 16 blocks per CU up to 64 K
+    // interior rows (129^2-class planes), 2 rows and 32 blocks per CU beyond
+    const bool small = (I - 2) * (J - 2) <= 65536;
+    int rows_per_wave = small ? 8 : 2, bpc = small ? 16 : 32, nt = 0;
+    copy_env_override(rows_per_wave, bpc, nt);
+    if (rows_per_wave == 2) return launch_copy<2>(p, q, I, J, K, bpc, nt, s);
+    if (rows_per_wave == 8) return launch_copy<8>(p, q, I, J, K, bpc, nt, s);
+    return launch_copy<4>(p, q, I, J, K, bpc, nt, s);
 }
 
 }  // namespace k

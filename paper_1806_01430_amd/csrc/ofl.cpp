@@ -49,6 +49,8 @@ struct ofl_app;
 
 namespace {
 
+bool timed_nest(const ofl_app *app, const Nest &n);
+
 // Host work recorded into a graph: one serial nest, or the restore of set-up
 // content into host copies.  They live as long as the graph that calls them.
 struct HostTask {
@@ -110,6 +112,7 @@ struct ofl_app {
 
     // per-kernel timing
     bool timing = false;
+    Op timing_op = OP_NONE;                  // OP_NONE: every nest kind is timed
     std::vector<hipEvent_t> events;
     std::map<std::string, std::pair<int64_t, double>> kstats;
 
@@ -462,14 +465,14 @@ RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *co
                 rr.code = hip_fail(e, "D2H copy");
                 break;
             }
-            st.bytes_d2h += ir.bufs[step.idx].nbytes;
+            st.bytes_d2h += step.box < 0 ? ir.bufs[step.idx].nbytes : box_bytes(ir.bufs[step.idx], plan.boxes[step.box]);
             st.n_copies++;
             host_written[step.idx] = 1;
             pending = true;
             break;
         case ST_GPU: {
             const Nest &n = ir.nests[step.idx];
-            const bool tm = app->timing && ev_next + 2 <= app->events.size();
+            const bool tm = timed_nest(app, n) && ev_next + 2 <= app->events.size();
             // a single-launch nest gets its events in the dispatch packet itself
             // (kernel-only interval); a multi-launch nest is bracketed by events
             const bool single = kernel_launch_count(ir, n) == 1;
@@ -557,6 +560,28 @@ void host_restore_cb(void *p) {
     }
 }
 
+bool timed_nest(const ofl_app *app, const Nest &n) {
+    return app->timing && (app->timing_op == OP_NONE || n.op == app->timing_op);
+}
+
+// Append an event record node to the graph being captured on `cs` after the
+// work captured so far, and make later captured work depend on it (a plain
+// event record inside a capture only orders work and leaves no node).
+hipError_t capture_event_node(hipStream_t cs, hipEvent_t ev) {
+    hipStreamCaptureStatus status;
+    unsigned long long id = 0;
+    hipGraph_t g = nullptr;
+    const hipGraphNode_t *deps = nullptr;
+    size_t nd = 0;
+    hipError_t e = hipStreamGetCaptureInfo_v2(cs, &status, &id, &g, &deps, &nd);
+    if (e != hipSuccess) return e;
+    if (status != hipStreamCaptureStatusActive || !g) return hipErrorInvalidValue;
+    hipGraphNode_t node = nullptr;
+    e = hipGraphAddEventRecordNode(&node, g, deps, nd, ev);
+    if (e != hipSuccess) return e;
+    return hipStreamUpdateCaptureDependencies(cs, &node, 1, hipStreamSetCaptureDependencies);
+}
+
 int capture_begin(ofl_app *app) {
     if (!app->capture_stream) {
         hipError_t e = hipStreamCreateWithFlags(&app->capture_stream, hipStreamNonBlocking);
@@ -632,7 +657,8 @@ int build_graphs(ofl_app *app, const std::vector<uint8_t> &placement, void *cons
             break;
         case ST_GPU: {
             hipEvent_t ev0 = nullptr, ev1 = nullptr;
-            if (app->timing) {
+            const bool tm = timed_nest(app, ir.nests[st.idx]);
+            if (tm) {
                 e = hipEventCreate(&ev0);
                 if (e == hipSuccess) e = hipEventCreate(&ev1);
                 if (e == hipSuccess) ge.timed.push_back({st.idx, {ev0, ev1}});
@@ -640,10 +666,10 @@ int build_graphs(ofl_app *app, const std::vector<uint8_t> &placement, void *cons
                     if (ev0) (void)hipEventDestroy(ev0);
                     break;
                 }
-                e = hipEventRecord(ev0, cs);
+                e = capture_event_node(cs, ev0);
             }
             if (e == hipSuccess) e = launch_nest(app, ir.nests[st.idx], dev, plan.env.data() + st.env, cs);
-            if (e == hipSuccess && app->timing) e = hipEventRecord(ev1, cs);
+            if (e == hipSuccess && tm) e = capture_event_node(cs, ev1);
             ge.launches += kernel_launch_count(ir, ir.nests[st.idx]);
             break;
         }
@@ -670,7 +696,7 @@ int get_graph(ofl_app *app, const std::vector<uint8_t> &placement, void *const *
     std::vector<uint64_t> key(placement.begin(), placement.end());
     key.push_back((uint64_t)policy);
     key.push_back((uint64_t)gflags);
-    key.push_back(app->timing ? 1u : 0u);
+    key.push_back(app->timing ? 1u + (uint64_t)app->timing_op : 0u);
     for (size_t b = 0; b < nb; ++b) key.push_back(reinterpret_cast<uint64_t>(dev[b]));
     auto it = app->graphs.find(key);
     if (it == app->graphs.end()) {
@@ -1192,6 +1218,20 @@ int ofl_set_kernel_timing(ofl_app *app, int32_t enable) {
     app->timing = enable != 0;
     if (app->timing) app->kstats.clear();
     return OFL_OK;
+}
+
+int ofl_set_kernel_timing_op(ofl_app *app, const char *op) {
+    if (!app) return fail(OFL_E_ARG, "null app");
+    if (!op || !*op) {
+        app->timing_op = OP_NONE;
+        return OFL_OK;
+    }
+    for (int o = OP_NONE + 1; o < OP_COUNT; ++o)
+        if (std::strcmp(op_name((Op)o), op) == 0) {
+            app->timing_op = (Op)o;
+            return OFL_OK;
+        }
+    return fail(OFL_E_ARG, std::string("unknown nest kind '") + op + "'");
 }
 
 int ofl_kernel_stats(const ofl_app *app, const char *op, int64_t *launches, double *total_ms) {

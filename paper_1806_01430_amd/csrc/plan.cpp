@@ -101,8 +101,7 @@ struct Planner {
     // SECTIONS: copy out only box `bx` of buffer b (the host copy stays stale
     // outside the current boxes)
     void copy_out_box(int b, const Box &bx) {
-        uint64_t n = app.bufs[b].nbytes / (uint64_t)std::max<int64_t>(1, app.bufs[b].count);
-        for (size_t d = 0; d < bx.lo.size(); ++d) n *= (uint64_t)(bx.hi[d] - bx.lo[d]);
+        const uint64_t n = box_bytes(app.bufs[b], bx);
         Step st{ST_D2H, b, -1};
         st.box = (int)P.boxes.size();
         P.boxes.push_back(bx);
@@ -187,6 +186,12 @@ struct Planner {
 };
 
 }  // namespace
+
+uint64_t box_bytes(const Buffer &buf, const Box &bx) {
+    uint64_t n = buf.nbytes / (uint64_t)std::max<int64_t>(1, buf.count);
+    for (size_t d = 0; d < bx.lo.size(); ++d) n *= (uint64_t)(bx.hi[d] - bx.lo[d]);
+    return n;
+}
 
 void build_plan(const AppIR &app, const std::vector<uint8_t> &placement, int policy, int flags, Plan &out) {
     out = Plan();

@@ -36,6 +36,9 @@ struct Plan {
     std::vector<char> host_valid, dev_valid;
 };
 
+// Bytes of buffer `buf` inside box `bx`.
+uint64_t box_bytes(const Buffer &buf, const Box &bx);
+
 // placement[nest] = 1 for GPU.  policy: OFL_POLICY_*; flags: OFL_RUN_*.
 void build_plan(const AppIR &app, const std::vector<uint8_t> &placement, int policy, int flags, Plan &out);
 

@@ -61,7 +61,11 @@ constexpr int kOutOfRange = (int)0x80000000u;
 // refills are unconditional, and a store that must not happen gets an offset
 // past num_records, which the raw-buffer range check drops.  Returns acc plus
 // the lane's squared differences.
-template <int JR>
+// Cache policy of the buffer accesses: 0 = default, kNonTemporal = streaming
+// (the "nt" bit: the line is not kept for reuse).
+constexpr int kNonTemporal = 2;
+
+template <int JR, int STORE_POLICY = 0>
 __device__ inline double stencil_item(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer_rsrc_t rq, const Geo &g, int w,
                                       int lane, double acc) {
     constexpr int R = JR + 2;
@@ -126,7 +130,8 @@ __device__ inline double stencil_item(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer
             const float v = (t0 + t1) + t2;
             const bool ok = kout && plane_ok && r <= jlast;
             __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), rq,
-                                                  ok ? ((i * J + jb + r) * K) * 4 + voff : kOutOfRange, 0, 0);
+                                                  ok ? ((i * J + jb + r) * K) * 4 + voff : kOutOfRange, 0,
+                                                  STORE_POLICY);
             const double d = (double)v - (double)Pa[c][r];
             acc = __builtin_fma(ok ? d : 0.0, d, acc);
         }
@@ -150,7 +155,7 @@ __device__ inline double stencil_item(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer
     return acc;
 }
 
-// Rows row0 .. row0+kRows-1 (of the (I-2)(J-2) interior rows (i, j)) of the
+// Rows row0 .. row0+ROWS-1 (of the (I-2)(J-2) interior rows (i, j)) of the
 // interior copy p = q.  Each row splits into a head [lo, a0) and a tail
 // [a1, hi) of at most three elements and a 16-byte aligned middle [a0, a1);
 // a pass moves up to 64 middle groups of every row plus the heads and tails.
@@ -158,15 +163,16 @@ __device__ inline double stencil_item(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer
 // (element 0 when the lane has nothing to move), so all loads of a pass
 // overlap, and a store that must not happen carries an offset past
 // num_records, which the range check drops.
-constexpr int kRows = 4;
+constexpr int kRows = 4;   // rows per work unit of the grouped copy
 
+template <int ROWS = kRows, int POLICY = 0>
 __device__ inline void copy_rows(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer_rsrc_t rq, int J, int K, int rows,
                                  int row0, int lane) {
     const int passes = ((K - 2) / 4 + kWave) / kWave;   // >= ceil(groups / 64), groups <= (K-2)/4
-    int lo[kRows], a0[kRows], a1[kRows], hi[kRows];
-    bool live[kRows];
+    int lo[ROWS], a0[ROWS], a1[ROWS], hi[ROWS];
+    bool live[ROWS];
 #pragma unroll
-    for (int t = 0; t < kRows; ++t) {
+    for (int t = 0; t < ROWS; ++t) {
         live[t] = row0 + t < rows;
         const int row = live[t] ? row0 + t : rows - 1;
         const int i = 1 + row / (J - 2), j = 1 + row % (J - 2);
@@ -178,25 +184,25 @@ __device__ inline void copy_rows(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer_rsrc
         if (a1[t] < a0[t]) a1[t] = a0[t];     // no aligned group: all in head / tail
     }
     for (int pass = 0; pass < passes; ++pass) {
-        __attribute__((ext_vector_type(4))) unsigned mid[kRows];
-        unsigned hd[kRows], tl[kRows];
-        int om[kRows], oh[kRows], ot[kRows];
+        __attribute__((ext_vector_type(4))) unsigned mid[ROWS];
+        unsigned hd[ROWS], tl[ROWS];
+        int om[ROWS], oh[ROWS], ot[ROWS];
 #pragma unroll
-        for (int t = 0; t < kRows; ++t) {
+        for (int t = 0; t < ROWS; ++t) {
             const int em = a0[t] + 4 * (pass * kWave + lane);
             const int eh = lo[t] + lane, et = a1[t] + lane;
             om[t] = (live[t] && em < a1[t]) ? em * 4 : -1;
             oh[t] = (live[t] && pass == 0 && eh < a0[t] && eh < hi[t]) ? eh * 4 : -1;
             ot[t] = (live[t] && pass == 0 && et < hi[t] && et >= a0[t]) ? et * 4 : -1;
-            mid[t] = __builtin_amdgcn_raw_buffer_load_b128(rq, om[t] < 0 ? 0 : om[t], 0, 0);
-            hd[t] = __builtin_amdgcn_raw_buffer_load_b32(rq, oh[t] < 0 ? 0 : oh[t], 0, 0);
-            tl[t] = __builtin_amdgcn_raw_buffer_load_b32(rq, ot[t] < 0 ? 0 : ot[t], 0, 0);
+            mid[t] = __builtin_amdgcn_raw_buffer_load_b128(rq, om[t] < 0 ? 0 : om[t], 0, POLICY);
+            hd[t] = __builtin_amdgcn_raw_buffer_load_b32(rq, oh[t] < 0 ? 0 : oh[t], 0, POLICY);
+            tl[t] = __builtin_amdgcn_raw_buffer_load_b32(rq, ot[t] < 0 ? 0 : ot[t], 0, POLICY);
         }
 #pragma unroll
-        for (int t = 0; t < kRows; ++t) {
-            __builtin_amdgcn_raw_buffer_store_b128(mid[t], rp, om[t] < 0 ? kOutOfRange : om[t], 0, 0);
-            __builtin_amdgcn_raw_buffer_store_b32(hd[t], rp, oh[t] < 0 ? kOutOfRange : oh[t], 0, 0);
-            __builtin_amdgcn_raw_buffer_store_b32(tl[t], rp, ot[t] < 0 ? kOutOfRange : ot[t], 0, 0);
+        for (int t = 0; t < ROWS; ++t) {
+            __builtin_amdgcn_raw_buffer_store_b128(mid[t], rp, om[t] < 0 ? kOutOfRange : om[t], 0, POLICY);
+            __builtin_amdgcn_raw_buffer_store_b32(hd[t], rp, oh[t] < 0 ? kOutOfRange : oh[t], 0, POLICY);
+            __builtin_amdgcn_raw_buffer_store_b32(tl[t], rp, ot[t] < 0 ? kOutOfRange : ot[t], 0, POLICY);
         }
     }
 }

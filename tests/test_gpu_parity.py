@@ -478,3 +478,32 @@ def test_sections_policy_random_genes(name, params):
     genes = [[1] * a] + [[rng.randint(0, 1) for _ in range(a)] for _ in range(5)]
     _run_and_compare(doc, genes, policies=(ofl.SECTIONS,),
                      flags_list=(0, ofl.PRESTAGED | ofl.KEEP_OUTPUTS, ofl.GRAPH | ofl.PRESTAGED))
+
+
+@pytest.mark.parametrize("op,prec", [("gemm", "bf16x3"), ("gemm", "fp8x2"), ("gemm_bf16", None)])
+def test_gemm_nt_256_tiles_ragged_sampled(op, prec):
+    # sizes past 2048 on both sides take the 256 x 256 tiles; ragged edges
+    # exercise the zero padding; sampled rows (and the ragged last rows)
+    # against the oracle
+    M, N, K = 2100, 2060, 300
+    app = ofl.App(json.dumps(appgen.gemm_app(M, N, K, op=op, prec=prec)))
+    A = OC.init_uniform(M * K, 31, 0).reshape(M, K)
+    B = OC.init_uniform(K * N, 31, 1).reshape(K, N)
+    if op == "gemm_bf16":
+        A, B = OC.cast_bf16(A), OC.cast_bf16(B)
+    app.set_input("A", A)
+    app.set_input("B", B)
+    bufs = app.alloc_device_buffers()
+    say("case nt 256 tiles", op, prec)
+    app.run_pattern([1], bufs, flags=ofl.KEEP_OUTPUTS)
+    C = app.read_buffer("C").astype(np.float64)
+    rows = np.array(sorted(set(list(np.random.default_rng(2).choice(M, 6, replace=False)) + [M - 1, M - 2, 0])))
+    Ar = np.ascontiguousarray(A[rows])
+    if op == "gemm_bf16":
+        want = OC.gemm_bf16_f64(Ar, B)
+        tol = parity.REL_GEMM
+    else:
+        want = OC.gemm_split_f64(Ar, B, prec)
+        tol = parity.REL_GEMM if prec == "bf16x3" else parity.REL_FP8_MFMA
+    err = np.max(np.abs(C[rows] - want) / want)
+    assert err < tol, err
