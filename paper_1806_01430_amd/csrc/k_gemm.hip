@@ -103,39 +103,45 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt(const T *__restrict__ A, c
     };
     const int r = lane & 15, g = lane >> 4;
     auto compute = [&](int buf) {
-        // lane group g owns bytes [32g, 32g+32) of the slab, read as two
-        // 16-byte halves h; each half feeds one k-step of every accumulator
+        // lane group g owns bytes [32g, 32g+32) of the slab: two 16-byte
+        // halves h, each feeding one k-step of every accumulator; all reads
+        // of the slab are issued before the first MFMA
+        u32x4 af[TM][2], bfr[TN][2];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            u32x4 af[TM], bfr[TN];
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-            for (int i = 0; i < TM; ++i)
-                af[i] = *reinterpret_cast<const u32x4 *>(&As[buf][(wm * WM + i * 16 + r) * LDS_ROW + 32 * g + 16 * h]);
+            for (int h = 0; h < 2; ++h)
+                af[i][h] = *reinterpret_cast<const u32x4 *>(&As[buf][(wm * WM + i * 16 + r) * LDS_ROW + 32 * g + 16 * h]);
 #pragma unroll
-            for (int j = 0; j < TN; ++j)
-                bfr[j] = *reinterpret_cast<const u32x4 *>(&Bs[buf][(wn * WN + j * 16 + r) * LDS_ROW + 32 * g + 16 * h]);
-            if constexpr (sizeof(T) == 2) {
-                // 8 bf16 per lane and MFMA
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
+                bfr[j][h] = *reinterpret_cast<const u32x4 *>(&Bs[buf][(wn * WN + j * 16 + r) * LDS_ROW + 32 * g + 16 * h]);
+        if constexpr (sizeof(T) == 2) {
+            // 8 bf16 per lane and MFMA
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
                     for (int j = 0; j < TN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[i]),
-                                                                            __builtin_bit_cast(bf16x8, bfr[j]),
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[i][h]),
+                                                                            __builtin_bit_cast(bf16x8, bfr[j][h]),
                                                                             acc[i][j], 0, 0, 0);
-            } else {
-                // 16 fp8 per lane: two MFMA steps of 8
+        } else {
+            // 16 fp8 per lane and half: two MFMA steps of 8
+#pragma unroll
+            for (int h = 0; h < 2; ++h)
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
 #pragma unroll
                     for (int i = 0; i < TM; ++i)
 #pragma unroll
                         for (int j = 0; j < TN; ++j) {
-                            const fp8x8 a8 = (fp8x8)(((unsigned long)af[i][2 * q + 1] << 32) | af[i][2 * q]);
-                            const fp8x8 b8 = (fp8x8)(((unsigned long)bfr[j][2 * q + 1] << 32) | bfr[j][2 * q]);
+                            const fp8x8 a8 = (fp8x8)(((unsigned long)af[i][h][2 * q + 1] << 32) | af[i][h][2 * q]);
+                            const fp8x8 b8 = (fp8x8)(((unsigned long)bfr[j][h][2 * q + 1] << 32) | bfr[j][h][2 * q]);
                             acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a8, b8, acc[i][j], 0, 0, 0);
                         }
-            }
         }
     };
 
@@ -189,10 +195,10 @@ hipError_t gemm_f32(const float *A, const float *B, float *C, int64_t M, int64_t
 // ---------------------------------------------------------------- split-precision GEMM
 namespace {
 // Tile of the k-contiguous product (rows of A' x rows of B'): 128 x 128.  A
-// 256 x 256 tile (4 waves of 128 x 128 in AGPRs, one block per CU) halves the
-// LDS traffic per MFMA but measured slower on gfx950 at 4096 (521 vs 472 us
-// for the bf16x3 product): one wave per SIMD leaves the LDS and global
-// latencies exposed.
+// 256 x 256 tile (4 waves of 128 x 128, accumulators in AGPRs, one block per
+// CU) halves the LDS traffic per MFMA but measured slower on gfx950 at 4096
+// (521 vs 472 us for the bf16x3 product): with one wave per SIMD the LDS and
+// global latencies stay exposed.
 int nt_tile(int64_t, int64_t) { return 128; }
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
