@@ -507,3 +507,50 @@ def test_gemm_nt_256_tiles_ragged_sampled(op, prec):
         tol = parity.REL_GEMM if prec == "bf16x3" else parity.REL_FP8_MFMA
     err = np.max(np.abs(C[rows] - want) / want)
     assert err < tol, err
+
+
+def test_precision_workload_error_report():
+    # the precision configuration at full size under each GEMM form: max
+    # relative error of each output against FP64 references -- C against the
+    # exact product on sampled rows; the sweep field p and the residuals r_S
+    # against the closed form of the sine mode (p_n = mu^n p_0,
+    # r_n = (mu - 1)^2 mu^(2n-2) (I-1)(J-1)(K-1) / 8), which the sweep follows
+    # exactly in exact arithmetic
+    import torch
+    doc0 = workloads.app_doc("precision")
+    P = doc0["params"]
+    N, I, J, K, S = P["N"], P["I"], P["J"], P["K"], P["SWEEPS"]
+    rows = [line.split() for line in open(workloads.ROOT + "/tests/golden/stencil_eigen.txt")
+            if not line.startswith("#")]
+    mu = [float(r[4]) for r in rows if r[:4] == [str(I), str(J), str(K), "1"]][0]
+    _, p0 = OC.sin_field(I, J, K, 1, want64=True)
+    inner = (slice(1, -1),) * 3
+    p_exact = mu ** S * p0[inner]
+    n = np.arange(1, S + 1)
+    r_exact = (mu - 1) ** 2 * mu ** (2 * n - 2) * (I - 1) * (J - 1) * (K - 1) / 8
+    A = OC.init_uniform(N * N, 1, 0).reshape(N, N)
+    B = OC.init_uniform(N * N, 1, 1).reshape(N, N)
+    sample = np.random.default_rng(4).choice(N, 6, replace=False)
+    exact_C = OC.gemm_f64(np.ascontiguousarray(A[sample]), B)
+    report = {}
+    for prec in ("f32", "bf16x3", "fp8x2"):
+        doc = workloads.app_doc("precision")
+        doc["program"][1]["args"]["prec"] = prec
+        app = ofl.App(json.dumps(doc), seed=1)
+        bufs = app.alloc_device_buffers()
+        say("case precision workload", prec)
+        app.run_pattern([1] * app.gene_len, bufs, policy=ofl.SECTIONS, flags=ofl.KEEP_OUTPUTS)
+        C = app.read_buffer("C")[sample].astype(np.float64)
+        p = app.read_buffer("p")[inner].astype(np.float64)
+        r = app.read_buffer("res")
+        report[prec] = {"C": float(np.max(np.abs(C - exact_C) / exact_C)),
+                        "p": float(np.max(np.abs(p - p_exact)) / np.max(np.abs(p_exact))),
+                        "r_S": float(np.max(np.abs(r - r_exact) / r_exact))}
+        say("precision errors", prec, report[prec])
+        del app, bufs
+        torch.cuda.empty_cache()
+    assert report["f32"]["C"] < 1e-5 and report["bf16x3"]["C"] < 1e-5 and report["fp8x2"]["C"] < 1e-3
+    for prec in report:
+        # the sweep does not depend on the product: the same field in every form
+        assert report[prec]["p"] == report["f32"]["p"] and report[prec]["p"] < S * 8 * 2.0 ** -24
+        assert report[prec]["r_S"] < 1e-2   # FP32 field: ~2^-24 / |mu - 1| relative (reported, not tight)
