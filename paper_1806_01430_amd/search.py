@@ -22,6 +22,8 @@ def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--app", default="tiny", help="application name or JSON path")
     ap.add_argument("--seed", type=int, default=1, help="application seed")
+    ap.add_argument("--set", action="append", default=[], metavar="NAME=VALUE",
+                    help="override an application parameter (repeatable)")
     ap.add_argument("--M", type=int, default=12)
     ap.add_argument("--T", type=int, default=12)
     ap.add_argument("--Pc", type=float, default=0.9)
@@ -45,6 +47,13 @@ def main(argv=None):
         print("search needs a GPU", file=sys.stderr)
         return 2
     src = args.app if args.app.endswith(".json") else app_path(args.app)
+    if args.set:
+        with open(src) as f:
+            doc = json.load(f)
+        for kv in args.set:
+            k, v = kv.split("=", 1)
+            doc["params"][k] = int(v)
+        src = doc
     app = App(src, seed=args.seed)
     bufs = app.alloc_device_buffers("cuda:0")
     policy = {"resident": RESIDENT, "per_region": PER_REGION, "sections": SECTIONS}[args.policy]
