@@ -5,6 +5,8 @@
 // (k_gemm_nt) after preparation passes (k_split.hip).
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "gemm_tile.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
@@ -46,7 +48,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(const float *__restrict__
 typedef long fp8x8;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 template <typename T, int BM, int BN, bool SCALED>
-__global__ __launch_bounds__(kThreads) void k_gemm_nt(const T *__restrict__ A, const T *__restrict__ B,
+__global__ __launch_bounds__(kThreads, 2) void k_gemm_nt(const T *__restrict__ A, const T *__restrict__ B,
                                                       float *__restrict__ C, int M, int N, int Kp,
                                                       const float *__restrict__ sa, const float *__restrict__ sb) {
     constexpr int SLAB = 128;                       // bytes of k per row per slab
@@ -75,30 +77,33 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt(const T *__restrict__ A, c
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    u32x4 ra[A_PER], rb[B_PER];
-    auto gload = [&](int slab) {
+    // two register sets of staged slabs: the slab two ahead is in flight
+    // from global memory while the current one is computed, so each load has
+    // two compute periods to arrive before it is written to LDS
+    u32x4 ra[2][A_PER], rb[2][B_PER];
+    auto gload = [&](int slab, int set) {
         const size_t kb = (size_t)slab * SLAB;
 #pragma unroll
         for (int s = 0; s < A_PER; ++s) {
             const int idx = tid + s * kThreads, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
-            ra[s] = *reinterpret_cast<const u32x4 *>(Ab + (size_t)row * row_bytes + kb + c);
+            ra[set][s] = *reinterpret_cast<const u32x4 *>(Ab + (size_t)row * row_bytes + kb + c);
         }
 #pragma unroll
         for (int s = 0; s < B_PER; ++s) {
             const int idx = tid + s * kThreads, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
-            rb[s] = *reinterpret_cast<const u32x4 *>(Bb + (size_t)row * row_bytes + kb + c);
+            rb[set][s] = *reinterpret_cast<const u32x4 *>(Bb + (size_t)row * row_bytes + kb + c);
         }
     };
-    auto sstore = [&](int buf) {
+    auto sstore = [&](int buf, int set) {
 #pragma unroll
         for (int s = 0; s < A_PER; ++s) {
             const int idx = tid + s * kThreads, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
-            *reinterpret_cast<u32x4 *>(&As[buf][row * LDS_ROW + c]) = ra[s];
+            *reinterpret_cast<u32x4 *>(&As[buf][row * LDS_ROW + c]) = ra[set][s];
         }
 #pragma unroll
         for (int s = 0; s < B_PER; ++s) {
             const int idx = tid + s * kThreads, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
-            *reinterpret_cast<u32x4 *>(&Bs[buf][row * LDS_ROW + c]) = rb[s];
+            *reinterpret_cast<u32x4 *>(&Bs[buf][row * LDS_ROW + c]) = rb[set][s];
         }
     };
     const int r = lane & 15, g = lane >> 4;
@@ -145,16 +150,24 @@ __global__ __launch_bounds__(kThreads) void k_gemm_nt(const T *__restrict__ A, c
         }
     };
 
+    // slab kt lives in LDS buffer kt & 1 and, before that, in register set
+    // kt & 1; iteration kt loads slab kt + 2 into the set slab kt left,
+    // computes slab kt and writes slab kt + 1 to the other LDS buffer
     const int nslab = (int)(row_bytes / SLAB);
-    gload(0);
-    sstore(0);
+    gload(0, 0);
+    sstore(0, 0);
+    if (nslab > 1) gload(1, 1);
     __syncthreads();
-    for (int kt = 0; kt < nslab; ++kt) {
-        const int cur = kt & 1;
-        if (kt + 1 < nslab) gload(kt + 1);
-        compute(cur);
-        if (kt + 1 < nslab) sstore(cur ^ 1);
+    auto iteration = [&](int kt, auto SET) {
+        constexpr int set = decltype(SET)::value;      // = kt & 1
+        if (kt + 2 < nslab) gload(kt + 2, set);
+        compute(set);
+        if (kt + 1 < nslab) sstore(set ^ 1, set ^ 1);
         __syncthreads();
+    };
+    for (int kt = 0; kt < nslab; kt += 2) {
+        iteration(kt, std::integral_constant<int, 0>());
+        if (kt + 1 < nslab) iteration(kt + 1, std::integral_constant<int, 1>());
     }
 #pragma unroll
     for (int i = 0; i < TM; ++i)
