@@ -279,13 +279,20 @@ int ofl_read_buffer(ofl_app *app, int32_t buf, void *host_dst, uint64_t bytes);
  * after each replay. */
 int ofl_set_kernel_timing(ofl_app *app, int32_t enable);
 
-/* Restrict kernel timing to nests of kind `op` (e.g. "stencil19"); NULL or
- * "" times every kind.  Errors: OFL_E_ARG for an unknown kind. */
+/* Restrict kernel timing to nests of the kinds listed in `op`, names
+ * separated by commas (e.g. "stencil19" or "stencil19,copy_interior"); NULL
+ * or "" times every kind.  Errors: OFL_E_ARG for an unknown kind (the
+ * previous selection stays). */
 int ofl_set_kernel_timing_op(ofl_app *app, const char *op);
 
-/* Accumulated launches and total kernel time (ms) of op kind `op`
- * (e.g. "stencil19", "gemm") since timing was enabled.  Unknown op: zeros. */
-int ofl_kernel_stats(const ofl_app *app, const char *op, int64_t *launches, double *total_ms);
+/* Timed executions of nests of kind `op` (e.g. "stencil19", "gemm") and
+ * their total kernel time (ms) since timing was enabled.  Unknown op: zeros.
+ * The time of an execution covers all of the nest's launches, except for
+ * "stencil19" outside graph runs: that nest is two launches (the sweep, then
+ * a one-block kernel that adds the per-wave residual partials) and its time
+ * is that of the sweep kernel alone; in graph runs it is the interval of
+ * both. */
+int ofl_kernel_stats(const ofl_app *app, const char *op, int64_t *executions, double *total_ms);
 
 /* ---------------------------------------------------------------- instance batches */
 

@@ -378,6 +378,7 @@ class App:
         _check(lib().ofl_set_kernel_timing_op(self._h, op.encode() if op else None), "ofl_set_kernel_timing_op")
 
     def kernel_stats(self, op):
+        """(timed executions of nests of kind `op`, their total kernel ms)."""
         n, ms = ctypes.c_int64(), ctypes.c_double()
         _check(lib().ofl_kernel_stats(self._h, op.encode(), ctypes.byref(n), ctypes.byref(ms)), "ofl_kernel_stats")
         return n.value, ms.value

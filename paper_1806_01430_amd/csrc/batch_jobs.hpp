@@ -52,7 +52,7 @@ struct CopyJob {
 constexpr int kGemmCfgs = 6;
 void gemm_cfg_shape(int cfg, int *bm, int *bk);
 
-Geo make_geo(int64_t I, int64_t J, int64_t K, int JR, int IC);
+Geo make_geo(int64_t I, int64_t J, int64_t K, int JR, int IC, int kout = kOut);
 int cu_count();
 int grouped_gemm_occupancy(int cfg);
 int grouped_stencil_occupancy(int JR);

@@ -38,6 +38,12 @@ __device__ inline double wave_sum(double v) {
 // block publishes the block's sum; the block that completes last adds all
 // partials, in block order, to target[0] and returns the counter to zero.  The
 // combination order depends only on the grid, so results are reproducible.
+// Ordering: each block's counter increment is a release (its partial is
+// written back before the increment), and only the reading lanes of the last
+// block acquire, each with an acquire load of the counter (it reads the final
+// increment, which continues every block's release sequence).  An acquire in
+// every block would invalidate the L2 of its XCD once per block, evicting
+// lines that the blocks still running there are about to read.
 __device__ inline void reduce_finish(double v, double *partials, unsigned *counter, double *target) {
     __shared__ double wsum[16];
     __shared__ int last;
@@ -52,12 +58,12 @@ __device__ inline void reduce_finish(double v, double *partials, unsigned *count
         for (int i = 0; i < nw; ++i) t += wsum[i];
         const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
         __hip_atomic_store(&partials[bid], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
         last = (prev == nb - 1) ? 1 : 0;
     }
     __syncthreads();
     if (last && w == 0) {
-        __threadfence();
+        (void)__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
         double s = 0.0;
         for (unsigned i = lane; i < nb; i += kWave)
             s += __hip_atomic_load(&partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

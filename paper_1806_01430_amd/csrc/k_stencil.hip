@@ -32,9 +32,14 @@ namespace {
 
 constexpr int kThreads = kStencilThreads;
 
+// The residual: every wave stores the sum of its squared differences in
+// partials[wave] (a plain store: no atomics and no fences in the sweep, whose
+// blocks would otherwise serialise on one counter and write back or
+// invalidate their XCD's L2 once per block), and k_residual_finish, launched
+// after the sweep on the same stream, adds the partials in wave order.
 template <int JR, int SP>
 __global__ __launch_bounds__(kThreads) void k_stencil19(const float *__restrict__ p, float *__restrict__ q, Geo g,
-                                                        double *res_slot, double *partials, unsigned *counter) {
+                                                        double *partials) {
     const int lane = threadIdx.x & (kWave - 1);
     // blocks are dealt to the 8 XCDs round-robin: renumber them so that one
     // XCD takes a contiguous run of work items (neighbouring j-runs share
@@ -47,7 +52,55 @@ __global__ __launch_bounds__(kThreads) void k_stencil19(const float *__restrict_
     const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc((void *)q, (short)0, g.bytes, kBufferConfig);
     double acc = 0.0;
     for (int w = lb * kWavesPerBlock + wib; w < g.items; w += nwaves) acc = stencil_item<JR, SP>(rp, rq, g, w, lane, acc);
-    reduce_finish(acc, partials, counter, res_slot);
+    acc = wave_sum(acc);
+    if (lane == 0) partials[lb * kWavesPerBlock + wib] = acc;
+}
+
+// The sweep with two columns per lane (stencil_item_w); same grid logic.
+template <int JR, int SP>
+__global__ __launch_bounds__(kThreads) void k_stencil19w(const float *__restrict__ p, float *__restrict__ q, Geo g,
+                                                         double *partials) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nb = gridDim.x;
+    const int lb = (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8;
+    const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int nwaves = nb * kWavesPerBlock;
+    const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, g.bytes, kBufferConfig);
+    const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc((void *)q, (short)0, g.bytes, kBufferConfig);
+    double acc = 0.0;
+    for (int w = lb * kWavesPerBlock + wib; w < g.items; w += nwaves) acc = stencil_item_w<JR, SP>(rp, rq, g, w, lane, acc);
+    acc = wave_sum(acc);
+    if (lane == 0) partials[lb * kWavesPerBlock + wib] = acc;
+}
+
+// res_slot[0] += the n wave partials of the sweep, in a fixed order: thread t
+// sums partials t, t + 256, ... (loads unrolled so that they overlap), then a
+// tree over the threads in LDS.  One block.
+constexpr int kFinishThreads = 256;
+
+__global__ __launch_bounds__(kFinishThreads) void k_residual_finish(const double *__restrict__ partials, int n,
+                                                                    double *res_slot) {
+    __shared__ double t[kFinishThreads];
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    int i = tid;
+    for (; i + 3 * kFinishThreads < n; i += 4 * kFinishThreads) {
+        const double a = partials[i], b = partials[i + kFinishThreads];
+        const double c = partials[i + 2 * kFinishThreads], d = partials[i + 3 * kFinishThreads];
+        s += a;
+        s += b;
+        s += c;
+        s += d;
+    }
+    for (; i < n; i += kFinishThreads) s += partials[i];
+    t[tid] = s;
+    __syncthreads();
+#pragma unroll
+    for (int h = kFinishThreads / 2; h > 0; h >>= 1) {
+        if (tid < h) t[tid] += t[tid + h];
+        __syncthreads();
+    }
+    if (tid == 0) res_slot[0] = res_slot[0] + t[0];
 }
 
 // p[i][j][k] = q[i][j][k] on the interior: a wave copies ROWS consecutive
@@ -67,15 +120,18 @@ __global__ __launch_bounds__(kThreads) void k_copy_interior(float *__restrict__ 
 
 struct Config {
     int JR;
+    bool wide = false;       // two columns per lane
     bool store_nt = false;   // q written with the non-temporal policy
     Geo g;
     unsigned blocks;
 };
 
-int resident_blocks_per_cu(int JR);
+int resident_blocks_per_cu(int JR, bool wide);
 
-// Tuning knob: OFL_STENCIL_CFG="JR,IC" overrides the choice (JR in {2,4,8},
-// IC planes per work item, 0 = automatic); used by tuning sweeps.
+// Tuning knobs, used by tuning sweeps: OFL_STENCIL_CFG="JR,IC" overrides the
+// choice (JR in {2,4,8}, IC planes per work item, 0 = automatic) and then
+// selects one column per lane unless OFL_STENCIL_WIDE=1 (two columns per
+// lane; OFL_STENCIL_WIDE=0/1 also overrides the default choice).
 bool env_override(int &JR, int &IC) {
     const char *s = std::getenv("OFL_STENCIL_CFG");
     if (!s) return false;
@@ -87,30 +143,35 @@ bool env_override(int &JR, int &IC) {
     return true;
 }
 
-// Work items: JR = 8 rows, i-runs of IC planes; the grid holds at most one
-// block per resident slot and waves loop over the items.
+// Work items: JR rows, i-runs of IC planes; the grid holds at most one block
+// per resident slot and waves loop over the items.  Defaults measured on
+// gfx950 (sweep kernel time, median of interleaved runs):
+//   fewer than 192 interior planes: JR = 4, IC = 6 (3 below 96 planes):
+//     129x129x257 10.2 us (JR 8: 10.8; IC 4 / 8: 11.8 / 10.9), 65x65x129 5.6 us
+//   192 .. 383 planes: JR = 8, IC = 12: 257x257x513 54.5 us (IC 24: 55.5,
+//     IC 48: 61.8, two columns per lane: 57.5)
+//   384 and more: two columns per lane, JR = 8, IC = 16: 513x513x1025 574 us
+//     (one column per lane, IC 48: 599)
 Config choose(int64_t I, int64_t J, int64_t K) {
     Config c;
     const int64_t ni = I - 2;
     int JR = 0, IC = 0;
-    if (!env_override(JR, IC)) {
-        JR = 8;
-        IC = 0;
-    }
-    if (IC <= 0) {
-        // measured on gfx950 (129^3-, 257^3- and 513^3-class grids): runs of
-        // 48 planes (a few work items per resident wave) on grids with at
-        // least 192 interior planes, 12 planes below that
-        IC = ni >= 192 ? 48 : 12;
-    }
+    const bool forced = env_override(JR, IC);
+    if (!forced) JR = ni >= 192 ? 8 : 4;
+    if (IC <= 0) IC = ni >= 384 ? 16 : ni >= 192 ? 12 : ni >= 96 ? 6 : 3;
+    c.wide = !forced && ni >= 384;
     c.JR = JR;
     c.g = make_geo(I, J, K, JR, IC);
-    // q with the non-temporal policy on grids up to 512 MB: measured faster
-    // (with the copy that follows) at 129^3- and 257^3-class grids, slower at
-    // the 513^3 class (783 vs 666 us); OFL_STENCIL_NT=0/1 overrides
-    c.store_nt = I * J * K * 4 <= (int64_t)512 << 20;
+    // q with the non-temporal policy on grids of 4 MB to 512 MB: measured
+    // faster at 129x129x257 (9.9 vs 12.3 us) and 257x257x513 (54.4 vs 61.1),
+    // slower at 513x513x1025 (654 vs 573) and 65x65x129 (6.4 vs 5.6);
+    // OFL_STENCIL_NT=0/1 overrides
+    const int64_t grid_bytes = I * J * K * 4;
+    c.store_nt = grid_bytes >= ((int64_t)4 << 20) && grid_bytes <= ((int64_t)512 << 20);
     if (const char *nt = std::getenv("OFL_STENCIL_NT")) c.store_nt = nt[0] == '1';
-    const int64_t resident_blocks = (int64_t)cu_count() * resident_blocks_per_cu(JR);
+    if (const char *wd = std::getenv("OFL_STENCIL_WIDE")) c.wide = wd[0] == '1';
+    if (c.wide) c.g = make_geo(I, J, K, JR, IC, kOutW);
+    const int64_t resident_blocks = (int64_t)cu_count() * resident_blocks_per_cu(JR, c.wide);
     int64_t blocks = ((int64_t)c.g.items + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > resident_blocks) blocks = resident_blocks;
     blocks = (blocks + 7) / 8 * 8;
@@ -119,32 +180,36 @@ Config choose(int64_t I, int64_t J, int64_t K) {
 }
 
 template <int JR>
-hipError_t launch_t(const Config &c, const float *p, float *q, double *res_slot, const ReduceScratch &rs,
-                    hipStream_t s) {
+hipError_t launch_t(const Config &c, const float *p, float *q, double *partials, hipStream_t s) {
+    if (c.wide) {
+        if (c.store_nt)
+            return launch((k_stencil19w<JR, kNonTemporal>), dim3(c.blocks), dim3(kThreads), 0, s, p, q, c.g, partials);
+        return launch((k_stencil19w<JR, 0>), dim3(c.blocks), dim3(kThreads), 0, s, p, q, c.g, partials);
+    }
     if (c.store_nt)
-        return launch((k_stencil19<JR, kNonTemporal>), dim3(c.blocks), dim3(kThreads), 0, s, p, q, c.g, res_slot,
-                      rs.partials, rs.counter);
-    return launch((k_stencil19<JR, 0>), dim3(c.blocks), dim3(kThreads), 0, s, p, q, c.g, res_slot, rs.partials,
-                  rs.counter);
+        return launch((k_stencil19<JR, kNonTemporal>), dim3(c.blocks), dim3(kThreads), 0, s, p, q, c.g, partials);
+    return launch((k_stencil19<JR, 0>), dim3(c.blocks), dim3(kThreads), 0, s, p, q, c.g, partials);
 }
 
-template <int JR>
-int occupancy_t() {
+template <typename Kern>
+int occupancy_of(Kern kern) {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_stencil19<JR, 0>, kThreads, 0) != hipSuccess || n < 1)
-        n = 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, kThreads, 0) != hipSuccess || n < 1) n = 1;
     return n;
 }
 
-int resident_blocks_per_cu(int JR) {
+int resident_blocks_per_cu(int JR, bool wide) {
     static std::once_flag once;
-    static int table[3];
+    static int table[2][3];
     std::call_once(once, [] {
-        table[0] = occupancy_t<2>();
-        table[1] = occupancy_t<4>();
-        table[2] = occupancy_t<8>();
+        table[0][0] = occupancy_of(k_stencil19<2, 0>);
+        table[0][1] = occupancy_of(k_stencil19<4, 0>);
+        table[0][2] = occupancy_of(k_stencil19<8, 0>);
+        table[1][0] = occupancy_of(k_stencil19w<2, 0>);
+        table[1][1] = occupancy_of(k_stencil19w<4, 0>);
+        table[1][2] = occupancy_of(k_stencil19w<8, 0>);
     });
-    return table[JR == 2 ? 0 : JR == 4 ? 1 : 2];
+    return table[wide ? 1 : 0][JR == 2 ? 0 : JR == 4 ? 1 : 2];
 }
 
 }  // namespace
@@ -163,14 +228,14 @@ int cu_count() {
 
 // Work-item geometry of a sweep over an I x J x K grid with JR-row items and
 // i-runs of IC planes (IC clamped to the interior).
-Geo make_geo(int64_t I, int64_t J, int64_t K, int JR, int IC) {
+Geo make_geo(int64_t I, int64_t J, int64_t K, int JR, int IC, int kout) {
     Geo g;
     const int64_t ni = I - 2, nj = J - 2;
     g.I = (int)I;
     g.J = (int)J;
     g.K = (int)K;
     g.bytes = (int)(I * J * K * 4);
-    g.nkt = (int)((K - 2 + kOut - 1) / kOut);
+    g.nkt = (int)((K - 2 + kout - 1) / kout);
     g.njt = (int)((nj + JR - 1) / JR);
     if (IC > ni) IC = (int)ni;
     if (IC < 1) IC = 1;
@@ -182,9 +247,10 @@ Geo make_geo(int64_t I, int64_t J, int64_t K, int JR, int IC) {
 
 int64_t stencil_partials(int64_t I, int64_t J, int64_t K) {
     if (I < 3 || J < 3 || K < 3) return 1;
-    // upper bound over every configuration the launcher may choose: one block
-    // per resident slot (at most 2048 threads per CU), rounded up to 8
-    return (int64_t)cu_count() * (2048 / kThreads) + 8;
+    // upper bound over every configuration the launcher may choose: one
+    // partial per wave, one block per resident slot (at most 2048 threads
+    // per CU), blocks rounded up to 8
+    return ((int64_t)cu_count() * (2048 / kThreads) + 8) * kWavesPerBlock;
 }
 
 hipError_t stencil19(const float *p, float *q, int64_t I, int64_t J, int64_t K, double *res_slot,
@@ -194,10 +260,14 @@ hipError_t stencil19(const float *p, float *q, int64_t I, int64_t J, int64_t K, 
     // to five planes past the end (read as 0); dropped stores use 2^31
     if ((I + 6) * J * K * 4 >= (1ll << 31)) return hipErrorInvalidValue;
     const Config c = choose(I, J, K);
-    if ((int64_t)c.blocks > rs.capacity) return hipErrorInvalidValue;
-    if (c.JR == 8) return launch_t<8>(c, p, q, res_slot, rs, s);
-    if (c.JR == 4) return launch_t<4>(c, p, q, res_slot, rs, s);
-    return launch_t<2>(c, p, q, res_slot, rs, s);
+    const int waves = (int)c.blocks * kWavesPerBlock;
+    if ((int64_t)waves > rs.capacity) return hipErrorInvalidValue;
+    const hipError_t e = c.JR == 8   ? launch_t<8>(c, p, q, rs.partials, s)
+                         : c.JR == 4 ? launch_t<4>(c, p, q, rs.partials, s)
+                                     : launch_t<2>(c, p, q, rs.partials, s);
+    if (e != hipSuccess) return e;
+    return launch(k_residual_finish, dim3(1), dim3(kFinishThreads), 0, s, (const double *)rs.partials, waves,
+                  res_slot);
 }
 
 // Tuning knob: OFL_COPY_CFG="ROWS,BLOCKS_PER_CU,NT" (ROWS in {2,4,8}, NT 0/1).

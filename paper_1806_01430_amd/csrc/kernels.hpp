@@ -26,8 +26,11 @@ hipError_t copy_bytes(void *dst, const void *src, uint64_t bytes, hipStream_t s)
 hipError_t cast_bf16(uint16_t *dst, const float *src, int64_t n, hipStream_t s);
 hipError_t transpose(const float *X, float *T, int64_t R, int64_t Cc, hipStream_t s);
 hipError_t sumsq(const float *x, int64_t n, double *s_out, const ReduceScratch &rs, hipStream_t s);
+// Two launches: the sweep (q and per-wave residual partials), then a
+// one-block kernel that adds the partials to res_slot[0].
 hipError_t stencil19(const float *p, float *q, int64_t I, int64_t J, int64_t K, double *res_slot,
                      const ReduceScratch &rs, hipStream_t s);
+constexpr int kStencilLaunches = 2;
 hipError_t copy_interior(float *p, const float *q, int64_t I, int64_t J, int64_t K, hipStream_t s);
 hipError_t gemm_f32(const float *A, const float *B, float *C, int64_t M, int64_t N, int64_t K, hipStream_t s);
 

@@ -112,7 +112,7 @@ struct ofl_app {
 
     // per-kernel timing
     bool timing = false;
-    Op timing_op = OP_NONE;                  // OP_NONE: every nest kind is timed
+    uint64_t timing_ops = 0;                 // bit per Op of the timed kinds; 0: every kind
     std::vector<hipEvent_t> events;
     std::map<std::string, std::pair<int64_t, double>> kstats;
 
@@ -326,7 +326,14 @@ int32_t kernel_launch_count(const AppIR &ir, const Nest &n) {
         const auto &a = ir.bufs[n.b[0]].dims, &bb = ir.bufs[n.b[1]].dims;
         return k::gemm_launches(a[0], bb[1], a[1], gemm_variant(n));
     }
+    if (n.op == OP_STENCIL19) return k::kStencilLaunches;
     return 1;
+}
+
+// Whether the kernel timing of a nest is its first launch alone: single-launch
+// nests, and the sweep, whose second launch only adds up the residual.
+bool first_launch_timed(const AppIR &ir, const Nest &n) {
+    return n.op == OP_STENCIL19 || kernel_launch_count(ir, n) == 1;
 }
 
 struct RunResult {
@@ -473,9 +480,10 @@ RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *co
         case ST_GPU: {
             const Nest &n = ir.nests[step.idx];
             const bool tm = timed_nest(app, n) && ev_next + 2 <= app->events.size();
-            // a single-launch nest gets its events in the dispatch packet itself
-            // (kernel-only interval); a multi-launch nest is bracketed by events
-            const bool single = kernel_launch_count(ir, n) == 1;
+            // a single-launch nest (and the sweep's main kernel) gets its events
+            // in the dispatch packet itself (kernel-only interval); another
+            // multi-launch nest is bracketed by events
+            const bool single = first_launch_timed(ir, n);
             if (tm && single) k::arm_launch_events(app->events[ev_next], app->events[ev_next + 1]);
             if (tm && !single) (void)hipEventRecord(app->events[ev_next], stream);
             e = launch_nest(app, n, dev, plan.env.data() + step.env, stream);
@@ -530,7 +538,7 @@ RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *co
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, app->events[te.second], app->events[te.second + 1]) == hipSuccess) {
             auto &ks = app->kstats[op_name(ir.nests[te.first].op)];
-            ks.first += kernel_launch_count(ir, ir.nests[te.first]);
+            ks.first += 1;
             ks.second += ms;
         }
     }
@@ -561,7 +569,7 @@ void host_restore_cb(void *p) {
 }
 
 bool timed_nest(const ofl_app *app, const Nest &n) {
-    return app->timing && (app->timing_op == OP_NONE || n.op == app->timing_op);
+    return app->timing && (app->timing_ops == 0 || ((app->timing_ops >> n.op) & 1u));
 }
 
 // Append an event record node to the graph being captured on `cs` after the
@@ -696,7 +704,8 @@ int get_graph(ofl_app *app, const std::vector<uint8_t> &placement, void *const *
     std::vector<uint64_t> key(placement.begin(), placement.end());
     key.push_back((uint64_t)policy);
     key.push_back((uint64_t)gflags);
-    key.push_back(app->timing ? 1u + (uint64_t)app->timing_op : 0u);
+    key.push_back(app->timing ? 1u : 0u);
+    key.push_back(app->timing ? app->timing_ops : 0u);
     for (size_t b = 0; b < nb; ++b) key.push_back(reinterpret_cast<uint64_t>(dev[b]));
     auto it = app->graphs.find(key);
     if (it == app->graphs.end()) {
@@ -763,7 +772,7 @@ RunResult run_graph(ofl_app *app, const std::vector<uint8_t> &placement, void *c
         float ms = 0.f;
         if (hipEventElapsedTime(&ms, te.second.first, te.second.second) == hipSuccess) {
             auto &ks = app->kstats[op_name(app->ir.nests[te.first].op)];
-            ks.first += kernel_launch_count(app->ir, app->ir.nests[te.first]);
+            ks.first += 1;
             ks.second += ms;
         }
     }
@@ -1220,24 +1229,32 @@ int ofl_set_kernel_timing(ofl_app *app, int32_t enable) {
     return OFL_OK;
 }
 
+static_assert(OP_COUNT <= 64, "timed kinds are a 64-bit mask");
+
 int ofl_set_kernel_timing_op(ofl_app *app, const char *op) {
     if (!app) return fail(OFL_E_ARG, "null app");
-    if (!op || !*op) {
-        app->timing_op = OP_NONE;
-        return OFL_OK;
+    uint64_t ops = 0;
+    const std::string list = op ? op : "";
+    // every comma-separated piece must name a kind (an empty piece does not)
+    for (size_t at = 0; !list.empty() && at <= list.size();) {
+        size_t end = list.find(',', at);
+        if (end == std::string::npos) end = list.size();
+        const std::string name = list.substr(at, end - at);
+        int found = OP_NONE;
+        for (int o = OP_NONE + 1; o < OP_COUNT; ++o)
+            if (name == op_name((Op)o)) found = o;
+        if (found == OP_NONE) return fail(OFL_E_ARG, "unknown nest kind '" + name + "'");
+        ops |= 1ull << found;
+        at = end + 1;
     }
-    for (int o = OP_NONE + 1; o < OP_COUNT; ++o)
-        if (std::strcmp(op_name((Op)o), op) == 0) {
-            app->timing_op = (Op)o;
-            return OFL_OK;
-        }
-    return fail(OFL_E_ARG, std::string("unknown nest kind '") + op + "'");
+    app->timing_ops = ops;
+    return OFL_OK;
 }
 
-int ofl_kernel_stats(const ofl_app *app, const char *op, int64_t *launches, double *total_ms) {
+int ofl_kernel_stats(const ofl_app *app, const char *op, int64_t *executions, double *total_ms) {
     if (!app || !op) return fail(OFL_E_ARG, "null argument");
     auto it = app->kstats.find(op);
-    if (launches) *launches = it == app->kstats.end() ? 0 : it->second.first;
+    if (executions) *executions = it == app->kstats.end() ? 0 : it->second.first;
     if (total_ms) *total_ms = it == app->kstats.end() ? 0.0 : it->second.second;
     return OFL_OK;
 }

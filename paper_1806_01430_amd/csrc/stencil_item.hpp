@@ -48,7 +48,8 @@ __device__ inline float buf_load(__amdgpu_buffer_rsrc_t r, int off) {
     return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
 }
 
-// Store offset that the raw-buffer range check always drops.
+// Offset that the raw-buffer range check always drops (stores are not made,
+// loads return zero without a memory access).
 constexpr int kOutOfRange = (int)0x80000000u;
 
 // One work item of the sweep.  Item w (k-tile fastest, then j-run, then
@@ -56,10 +57,11 @@ constexpr int kOutOfRange = (int)0x80000000u;
 // planes [ib, ie).  Plane sets P[0..2] hold a, x, y of planes i-1, i, i+1
 // with roles rotating every step (the i-loop is unrolled by three, so no
 // register moves); the ring holds the next three raw planes in flight.  Loads
-// are raw buffer loads; the loop body has no branches: loads beyond the work
-// item are clamped into the array (their values feed no stored output), so
-// refills are unconditional, and a store that must not happen gets an offset
-// past num_records, which the raw-buffer range check drops.  Returns acc plus
+// are raw buffer loads; the loop body branches only on wave-uniform values:
+// loads of rows beyond the work item are clamped into the array (their values
+// feed no stored output), and a refill past the run's last plane or a store
+// that must not happen gets an offset past num_records, which the raw-buffer
+// range check drops (a load so dropped returns zeros).  Returns acc plus
 // the lane's squared differences.
 // Cache policy of the buffer accesses: 0 = default, kNonTemporal = streaming
 // (the "nt" bit: the line is not kept for reuse).
@@ -94,7 +96,8 @@ __device__ inline double stencil_item(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer
     auto load = [&](int i, float (&v)[R]) {
         const int ii = min(i, g.I - 1);
 #pragma unroll
-        for (int r = 0; r < R; ++r) v[r] = buf_load(rp, ((ii * J + min(jb - 1 + r, J - 1)) * K) * 4 + kld);
+        for (int r = 0; r < R; ++r)
+            v[r] = buf_load(rp, i < 0 ? kOutOfRange : ((ii * J + min(jb - 1 + r, J - 1)) * K) * 4 + kld);
     };
     auto derive = [&](const float (&v)[R], float (&a)[JR], float (&x)[JR], float (&y)[JR]) {
         float h[R];                             // p[j][k-1] + p[j][k+1] per row
@@ -116,9 +119,10 @@ __device__ inline double stencil_item(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer
         derive(ring[s], Pa[n], Px[n], Py[n]);            // plane i+1
         // the refill must not start before the slot's old value is consumed,
         // or old and new value need separate registers (a copy per iteration);
-        // past the run's last plane it re-reads that plane (an L1 hit)
+        // past the run's last plane there is nothing left to fetch: the
+        // refill then reads past num_records (no memory access, zeros)
         __builtin_amdgcn_sched_barrier(0);
-        load(min(i + 4, ie), ring[s]);
+        load(i + 4 <= ie ? i + 4 : -1, ring[s]);
         const bool plane_ok = i < ie;
 #pragma unroll
         for (int r = 0; r < JR; ++r) {
@@ -139,6 +143,123 @@ __device__ inline double stencil_item(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer
 
     {
         float r0[R], r1[R];
+        load(ib - 1, r0);
+        load(ib, r1);
+        load(ib + 1, ring[0]);
+        load(min(ib + 2, ie), ring[1]);
+        load(min(ib + 3, ie), ring[2]);
+        derive(r0, Pa[0], Px[0], Py[0]);
+        derive(r1, Pa[1], Px[1], Py[1]);
+    }
+    for (int i0 = ib; i0 < ie; i0 += 3) {
+        step(std::integral_constant<int, 0>(), i0);
+        step(std::integral_constant<int, 1>(), i0 + 1);
+        step(std::integral_constant<int, 2>(), i0 + 2);
+    }
+    return acc;
+}
+
+// The same sweep with two consecutive k per lane: a wave covers 128 k of
+// each row with one 8-byte load (the lines a row window straddles are
+// fetched once per 126 outputs instead of once per 62) and produces the 126
+// columns k0+1 .. k0+126 (lane 0's first and lane 63's second value only
+// supply neighbours).  Per point the arithmetic is that of stencil_item, in
+// the same order, so the field is bit-identical; only the order in which the
+// residual terms are summed differs.
+constexpr int kOutW = 126;
+
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+__device__ inline f32x2 buf_load2(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+
+template <int JR, int STORE_POLICY = 0>
+__device__ inline double stencil_item_w(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer_rsrc_t rq, const Geo &g, int w,
+                                        int lane, double acc) {
+    constexpr int R = JR + 2;
+    const int J = g.J, K = g.K;
+    const int kt = w % g.nkt;
+    const int rest = w / g.nkt;
+    const int jt = rest % g.njt;
+    const int ic = rest / g.njt;
+    const int k = kt * kOutW + 2 * lane;        // this lane's first column
+    // the 8-byte window stays inside the row: a lane whose first column is
+    // the row's last reads the window one column earlier and takes its second
+    // value; lanes past the row read anything (their values feed no output)
+    const bool shifted = k > K - 2;
+    const int kld = min(k, K - 2) * 4;
+    const bool out0 = lane >= 1 && k <= K - 2;
+    const bool out1 = lane <= 62 && k + 1 <= K - 2;
+    const int voff0 = k * 4, voff1 = voff0 + 4;
+    const int jb = 1 + jt * JR;
+    const int ib = 1 + ic * g.IC;
+    const int ie = min(ib + g.IC, g.I - 1);
+    const int jlast = J - 2 - jb;
+
+    f32x2 Pa[3][JR], Px[3][JR], Py[3][JR];
+    f32x2 ring[3][R];
+
+    auto load = [&](int i, f32x2 (&v)[R]) {
+        const int ii = min(i, g.I - 1);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const f32x2 t = buf_load2(rp, ((ii * J + min(jb - 1 + r, J - 1)) * K) * 4 + kld);
+            v[r] = shifted ? f32x2{t.y, t.y} : t;
+        }
+    };
+    auto derive = [&](const f32x2 (&v)[R], f32x2 (&a)[JR], f32x2 (&x)[JR], f32x2 (&y)[JR]) {
+        f32x2 h[R];                             // p[j][k-1] + p[j][k+1] per row and column
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            h[r].x = from_left(v[r].y) + v[r].y;
+            h[r].y = v[r].x + from_right(v[r].x);
+        }
+#pragma unroll
+        for (int r = 0; r < JR; ++r) {
+            a[r] = v[r + 1];
+            x[r].x = (v[r].x + v[r + 2].x) + h[r + 1].x;
+            x[r].y = (v[r].y + v[r + 2].y) + h[r + 1].y;
+            y[r].x = h[r].x + h[r + 2].x;
+            y[r].y = h[r].y + h[r + 2].y;
+        }
+    };
+    auto point = [&](float am, float an, float ac, float xm, float xn, float xc, float yc) {
+        const float F = (am + an) + xc;
+        const float E = (xm + xn) + yc;
+        const float t0 = 0.25f * ac;
+        const float t1 = 0.0625f * F;
+        const float t2 = 0.03125f * E;
+        return (t0 + t1) + t2;
+    };
+    auto step = [&](auto S, int i) {
+        constexpr int s = decltype(S)::value;
+        constexpr int m = s, c = (s + 1) % 3, n = (s + 2) % 3;
+        __builtin_amdgcn_sched_barrier(0);
+        derive(ring[s], Pa[n], Px[n], Py[n]);
+        __builtin_amdgcn_sched_barrier(0);
+        load(min(i + 4, ie), ring[s]);
+        const bool plane_ok = i < ie;
+#pragma unroll
+        for (int r = 0; r < JR; ++r) {
+            const float v0 = point(Pa[m][r].x, Pa[n][r].x, Pa[c][r].x, Px[m][r].x, Px[n][r].x, Px[c][r].x, Py[c][r].x);
+            const float v1 = point(Pa[m][r].y, Pa[n][r].y, Pa[c][r].y, Px[m][r].y, Px[n][r].y, Px[c][r].y, Py[c][r].y);
+            const bool row_ok = plane_ok && r <= jlast;
+            const bool ok0 = out0 && row_ok, ok1 = out1 && row_ok;
+            const int base = ((i * J + jb + r) * K) * 4;
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v0), rq,
+                                                  ok0 ? base + voff0 : kOutOfRange, 0, STORE_POLICY);
+            __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v1), rq,
+                                                  ok1 ? base + voff1 : kOutOfRange, 0, STORE_POLICY);
+            const double d0 = (double)v0 - (double)Pa[c][r].x;
+            const double d1 = (double)v1 - (double)Pa[c][r].y;
+            acc = __builtin_fma(ok0 ? d0 : 0.0, d0, acc);
+            acc = __builtin_fma(ok1 ? d1 : 0.0, d1, acc);
+        }
+    };
+
+    {
+        f32x2 r0[R], r1[R];
         load(ib - 1, r0);
         load(ib, r1);
         load(ib + 1, ring[0]);

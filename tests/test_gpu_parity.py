@@ -276,6 +276,21 @@ def test_stencil_shapes(I, J, K, S):
     _run_and_compare(appgen.stencil_app(I, J, K, S), [[1, 1], [1, 0], [0, 1]])
 
 
+# every sweep kernel form (rows per item, planes per item, one or two columns
+# per lane, store policy), forced through the library's tuning knobs, on
+# ragged shapes: k-tiles with a partial last tile, j-runs past the last row,
+# i-runs shorter than the item
+@pytest.mark.parametrize("cfg,wide,nt", [("2,1", "0", "0"), ("4,3", "0", "1"), ("8,5", "0", "0"), ("2,2", "1", "1"),
+                                         ("4,6", "1", "0"), ("8,4", "1", "1"), ("8,16", "1", "0")])
+def test_stencil_kernel_forms(cfg, wide, nt, monkeypatch):
+    monkeypatch.setenv("OFL_STENCIL_CFG", cfg)
+    monkeypatch.setenv("OFL_STENCIL_WIDE", wide)
+    monkeypatch.setenv("OFL_STENCIL_NT", nt)
+    for I, J, K in [(4, 5, 6), (19, 23, 71), (5, 130, 300), (10, 11, 129), (6, 9, 254), (7, 6, 128)]:
+        say("case stencil form %s wide=%s nt=%s grid %dx%dx%d" % (cfg, wide, nt, I, J, K))
+        _run_and_compare(appgen.stencil_app(I, J, K, 2), [[1, 1]])
+
+
 def test_stencil_fixed_point_exact():
     I, J, K = 21, 34, 133
     ii, jj, kk = np.meshgrid(np.arange(I), np.arange(J), np.arange(K), indexing="ij")

@@ -141,6 +141,16 @@ def test_gene_errors():
     assert ei.value.code == -6
 
 
+def test_kernel_timing_kind_lists():
+    app = ofl.App(workloads.app_path("tiny"))
+    for ok in (None, "", "stencil19", "stencil19,copy_interior", "gemm,stencil19,copy_interior"):
+        app.set_kernel_timing_op(ok)
+    for bad in ("fft", "stencil19,", "stencil19,,gemm", ",gemm", "stencil19 ,gemm"):
+        with pytest.raises(ofl.OflError) as ei:
+            app.set_kernel_timing_op(bad)
+        assert ei.value.code == -1
+
+
 @pytest.mark.parametrize("mutate,code", [
     (lambda d: d.update(program="x"), -3),
     (lambda d: d["program"][1].update(op="fft"), -4),
