@@ -285,13 +285,19 @@ int ofl_set_kernel_timing(ofl_app *app, int32_t enable);
  * previous selection stays). */
 int ofl_set_kernel_timing_op(ofl_app *app, const char *op);
 
+/* Time only every stride-th execution of each timed kind in a run: the
+ * executions i = phase, phase + stride, ... (counted per kind from 0 in each
+ * run).  Default 1, 0 (all).  Errors: OFL_E_ARG unless stride >= 1 and
+ * 0 <= phase < stride. */
+int ofl_set_kernel_timing_sample(ofl_app *app, int32_t stride, int32_t phase);
+
 /* Timed executions of nests of kind `op` (e.g. "stencil19", "gemm") and
  * their total kernel time (ms) since timing was enabled.  Unknown op: zeros.
- * The time of an execution covers all of the nest's launches, except for
- * "stencil19" outside graph runs: that nest is two launches (the sweep, then
- * a one-block kernel that adds the per-wave residual partials) and its time
- * is that of the sweep kernel alone; in graph runs it is the interval of
- * both. */
+ * The time of an execution covers all of the nest's launches.  A "stencil19"
+ * nest launches the sweep; the sum of its per-wave residual partials runs
+ * as one extra block of the "copy_interior" launch when that nest follows on
+ * the GPU, else as a one-block kernel before the next step (counted in the
+ * run's launches, timed with neither nest). */
 int ofl_kernel_stats(const ofl_app *app, const char *op, int64_t *executions, double *total_ms);
 
 /* ---------------------------------------------------------------- instance batches */

@@ -30,7 +30,8 @@ _NP_DTYPE = {0: np.float32, 1: np.float64, 2: np.uint16}
 EXPORTS = ["ofl_app_load", "ofl_app_load_json", "ofl_app_free", "ofl_app_info", "ofl_nest_info",
            "ofl_nest_name", "ofl_buf_info", "ofl_buf_name", "ofl_buf_dims", "ofl_set_input", "ofl_mask_to_gene",
            "ofl_plan_transfers", "ofl_run_pattern", "ofl_eval_population", "ofl_ga_run",
-           "ofl_ga_run_table", "ofl_read_buffer", "ofl_set_kernel_timing", "ofl_set_kernel_timing_op", "ofl_kernel_stats",
+           "ofl_ga_run_table", "ofl_read_buffer", "ofl_set_kernel_timing", "ofl_set_kernel_timing_op",
+           "ofl_set_kernel_timing_sample", "ofl_kernel_stats",
            "ofl_batch_create", "ofl_batch_free", "ofl_batch_info", "ofl_batch_buf_info", "ofl_batch_buf_dims",
            "ofl_batch_buf_name", "ofl_batch_setup", "ofl_batch_run", "ofl_batch_get_config",
            "ofl_batch_set_config", "ofl_batch_tune", "ofl_status_str", "ofl_last_error"]
@@ -138,6 +139,7 @@ def lib():
             "ofl_read_buffer": (_I, [_P, _I, _P, ctypes.c_uint64]),
             "ofl_set_kernel_timing": (_I, [_P, _I]),
             "ofl_set_kernel_timing_op": (_I, [_P, ctypes.c_char_p]),
+            "ofl_set_kernel_timing_sample": (_I, [_P, ctypes.c_int32, ctypes.c_int32]),
             "ofl_kernel_stats": (_I, [_P, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int64),
                                       ctypes.POINTER(ctypes.c_double)]),
             "ofl_batch_create": (_I, [ctypes.c_char_p, _I, ctypes.POINTER(ctypes.c_char_p), _I,
@@ -374,8 +376,12 @@ class App:
         _check(lib().ofl_set_kernel_timing(self._h, 1 if enable else 0), "ofl_set_kernel_timing")
 
     def set_kernel_timing_op(self, op=None):
-        """Time only nests of kind `op` (None: every kind)."""
+        """Time only nests of the kinds in `op` (comma-separated; None: every kind)."""
         _check(lib().ofl_set_kernel_timing_op(self._h, op.encode() if op else None), "ofl_set_kernel_timing_op")
+
+    def set_kernel_timing_sample(self, stride=1, phase=0):
+        """Time only executions phase, phase + stride, ... of each timed kind in a run."""
+        _check(lib().ofl_set_kernel_timing_sample(self._h, stride, phase), "ofl_set_kernel_timing_sample")
 
     def kernel_stats(self, op):
         """(timed executions of nests of kind `op`, their total kernel ms)."""

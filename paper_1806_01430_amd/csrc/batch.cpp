@@ -408,7 +408,7 @@ hipError_t launch_single(ofl_batch *b, int i, int ni, const std::vector<int64_t>
     case OP_STENCIL19: {
         const auto &d = ir.bufs[n.b[0]].dims;
         k::ReduceScratch rs{b->d_partials, b->d_counter, b->partial_cap};
-        *launches += k::kStencilLaunches;
+        *launches += 2;   // sweep + residual finish
         return k::stencil19(F(0), F(1), d[0], d[1], d[2],
                             reinterpret_cast<double *>(F(2)) + env[n.slot_repeat], rs, s);
     }

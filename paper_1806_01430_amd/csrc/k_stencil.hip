@@ -73,13 +73,14 @@ __global__ __launch_bounds__(kThreads) void k_stencil19w(const float *__restrict
     if (lane == 0) partials[lb * kWavesPerBlock + wib] = acc;
 }
 
-// res_slot[0] += the n wave partials of the sweep, in a fixed order: thread t
+// res_slot[0] += the n wave partials of a sweep, in a fixed order: thread t
 // sums partials t, t + 256, ... (loads unrolled so that they overlap), then a
-// tree over the threads in LDS.  One block.
+// tree over the threads in LDS.  Executed by one whole block of 256 threads:
+// k_residual_finish, or the extra block of an interior copy launched next.
 constexpr int kFinishThreads = 256;
+static_assert(kFinishThreads == kThreads, "the copy's extra block runs the finish");
 
-__global__ __launch_bounds__(kFinishThreads) void k_residual_finish(const double *__restrict__ partials, int n,
-                                                                    double *res_slot) {
+__device__ inline void finish_block(const double *__restrict__ partials, int n, double *res_slot) {
     __shared__ double t[kFinishThreads];
     const int tid = threadIdx.x;
     double s = 0.0;
@@ -103,14 +104,27 @@ __global__ __launch_bounds__(kFinishThreads) void k_residual_finish(const double
     if (tid == 0) res_slot[0] = res_slot[0] + t[0];
 }
 
+__global__ __launch_bounds__(kFinishThreads) void k_residual_finish(const double *__restrict__ partials, int n,
+                                                                    double *res_slot) {
+    finish_block(partials, n, res_slot);
+}
+
 // p[i][j][k] = q[i][j][k] on the interior: a wave copies ROWS consecutive
 // rows (i, j) at a time.
+// With fin_n > 0 the grid has one extra (last) block, which adds up the
+// residual partials of the sweep launched before instead of copying.
 template <int ROWS, int POL>
 __global__ __launch_bounds__(kThreads) void k_copy_interior(float *__restrict__ p, const float *__restrict__ q,
-                                                            int I, int J, int K) {
+                                                            int I, int J, int K, const double *fin_partials,
+                                                            int fin_n, double *fin_slot) {
+    const int copy_blocks = (int)gridDim.x - (fin_n > 0 ? 1 : 0);
+    if ((int)blockIdx.x >= copy_blocks) {
+        finish_block(fin_partials, fin_n, fin_slot);
+        return;
+    }
     const int lane = threadIdx.x & (kWave - 1);
     const int gwave = blockIdx.x * kWavesPerBlock + threadIdx.x / kWave;
-    const int nwaves = gridDim.x * kWavesPerBlock;
+    const int nwaves = copy_blocks * kWavesPerBlock;
     const int rows = (I - 2) * (J - 2);
     const int bytes = I * J * K * 4;
     const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc((void *)q, (short)0, bytes, kBufferConfig);
@@ -253,8 +267,20 @@ int64_t stencil_partials(int64_t I, int64_t J, int64_t K) {
     return ((int64_t)cu_count() * (2048 / kThreads) + 8) * kWavesPerBlock;
 }
 
-hipError_t stencil19(const float *p, float *q, int64_t I, int64_t J, int64_t K, double *res_slot,
-                     const ReduceScratch &rs, hipStream_t s) {
+hipError_t residual_finish(ResidualFinish &fin, hipStream_t s) {
+    const ResidualFinish f = fin;
+    fin = ResidualFinish{};
+    if (f.n <= 0) return hipSuccess;
+    return launch(k_residual_finish, dim3(1), dim3(kFinishThreads), 0, s, f.partials, f.n, f.target);
+}
+
+hipError_t stencil19_sweep(const float *p, float *q, int64_t I, int64_t J, int64_t K, double *res_slot,
+                           const ReduceScratch &rs, hipStream_t s, ResidualFinish &fin) {
+    // a finish still owed reads the partials this sweep overwrites: do it first
+    if (fin.n > 0) {
+        const hipError_t e = residual_finish(fin, s);
+        if (e != hipSuccess) return e;
+    }
     if (I < 3 || J < 3 || K < 3) return hipSuccess;   // no interior: nothing written, residual unchanged
     // byte offsets are non-negative 32-bit ints: the loop may form offsets up
     // to five planes past the end (read as 0); dropped stores use 2^31
@@ -266,8 +292,16 @@ hipError_t stencil19(const float *p, float *q, int64_t I, int64_t J, int64_t K, 
                          : c.JR == 4 ? launch_t<4>(c, p, q, rs.partials, s)
                                      : launch_t<2>(c, p, q, rs.partials, s);
     if (e != hipSuccess) return e;
-    return launch(k_residual_finish, dim3(1), dim3(kFinishThreads), 0, s, (const double *)rs.partials, waves,
-                  res_slot);
+    fin = ResidualFinish{rs.partials, waves, res_slot};
+    return hipSuccess;
+}
+
+hipError_t stencil19(const float *p, float *q, int64_t I, int64_t J, int64_t K, double *res_slot,
+                     const ReduceScratch &rs, hipStream_t s) {
+    ResidualFinish fin;
+    const hipError_t e = stencil19_sweep(p, q, I, J, K, res_slot, rs, s, fin);
+    if (e != hipSuccess) return e;
+    return residual_finish(fin, s);
 }
 
 // Tuning knob: OFL_COPY_CFG="ROWS,BLOCKS_PER_CU,NT" (ROWS in {2,4,8}, NT 0/1).
@@ -282,28 +316,36 @@ void copy_env_override(int &rows_per_wave, int &bpc, int &nt) {
 }
 
 template <int ROWS>
-hipError_t launch_copy(float *p, const float *q, int64_t I, int64_t J, int64_t K, int bpc, int nt, hipStream_t s) {
+hipError_t launch_copy(float *p, const float *q, int64_t I, int64_t J, int64_t K, int bpc, int nt,
+                       const ResidualFinish &f, hipStream_t s) {
     const int64_t rows = (I - 2) * (J - 2);
     int64_t blocks = (rows + kWavesPerBlock * ROWS - 1) / (kWavesPerBlock * ROWS);
     if (blocks > (int64_t)cu_count() * bpc) blocks = (int64_t)cu_count() * bpc;
+    if (f.n > 0) ++blocks;   // the finish block
     if (nt)
         return launch((k_copy_interior<ROWS, kNonTemporal>), dim3((unsigned)blocks), dim3(kThreads), 0, s, p, q,
-                      (int)I, (int)J, (int)K);
+                      (int)I, (int)J, (int)K, f.partials, f.n, f.target);
     return launch((k_copy_interior<ROWS, 0>), dim3((unsigned)blocks), dim3(kThreads), 0, s, p, q, (int)I, (int)J,
-                  (int)K);
+                  (int)K, f.partials, f.n, f.target);
 }
 
-hipError_t copy_interior(float *p, const float *q, int64_t I, int64_t J, int64_t K, hipStream_t s) {
-    if (I < 3 || J < 3 || K < 3) return hipSuccess;
+hipError_t copy_interior(float *p, const float *q, int64_t I, int64_t J, int64_t K, hipStream_t s,
+                         ResidualFinish *fin) {
+    const ResidualFinish f = fin ? *fin : ResidualFinish{};
+    if (fin) *fin = ResidualFinish{};
+    if (I < 3 || J < 3 || K < 3) {   // nothing to copy: the finish still runs
+        ResidualFinish g = f;
+        return residual_finish(g, s);
+    }
     if (I * J * K * 4 >= (1ll << 31)) return hipErrorInvalidValue;   // 32-bit buffer offsets
     // measured on gfx950: 8 rows per wave and 16 blocks per CU up to 64 K
     // interior rows (129^2-class planes), 2 rows and 32 blocks per CU beyond
     const bool small = (I - 2) * (J - 2) <= 65536;
     int rows_per_wave = small ? 8 : 2, bpc = small ? 16 : 32, nt = 0;
     copy_env_override(rows_per_wave, bpc, nt);
-    if (rows_per_wave == 2) return launch_copy<2>(p, q, I, J, K, bpc, nt, s);
-    if (rows_per_wave == 8) return launch_copy<8>(p, q, I, J, K, bpc, nt, s);
-    return launch_copy<4>(p, q, I, J, K, bpc, nt, s);
+    if (rows_per_wave == 2) return launch_copy<2>(p, q, I, J, K, bpc, nt, f, s);
+    if (rows_per_wave == 8) return launch_copy<8>(p, q, I, J, K, bpc, nt, f, s);
+    return launch_copy<4>(p, q, I, J, K, bpc, nt, f, s);
 }
 
 }  // namespace k

@@ -26,12 +26,29 @@ hipError_t copy_bytes(void *dst, const void *src, uint64_t bytes, hipStream_t s)
 hipError_t cast_bf16(uint16_t *dst, const float *src, int64_t n, hipStream_t s);
 hipError_t transpose(const float *X, float *T, int64_t R, int64_t Cc, hipStream_t s);
 hipError_t sumsq(const float *x, int64_t n, double *s_out, const ReduceScratch &rs, hipStream_t s);
-// Two launches: the sweep (q and per-wave residual partials), then a
-// one-block kernel that adds the partials to res_slot[0].
+// The sweep writes q and one residual partial per wave; adding the partials
+// to the sweep's residual slot is a separate step (ResidualFinish) that runs
+// as a one-block kernel or as the extra block of an interior copy launched
+// next on the same stream.  The partials live in the ReduceScratch area, so a
+// finish must run before the next launch that writes partials.
+struct ResidualFinish {
+    const double *partials = nullptr;
+    int n = 0;                 // 0: nothing owed
+    double *target = nullptr;  // the sweep's residual slot
+};
+// Launch the sweep; a finish still owed in `fin` is launched first; on
+// return `fin` holds the sweep's own finish.
+hipError_t stencil19_sweep(const float *p, float *q, int64_t I, int64_t J, int64_t K, double *res_slot,
+                           const ReduceScratch &rs, hipStream_t s, ResidualFinish &fin);
+// Launch the finish owed in `fin` (if any) as one block; clears `fin`.
+hipError_t residual_finish(ResidualFinish &fin, hipStream_t s);
+// Sweep and finish (two launches).
 hipError_t stencil19(const float *p, float *q, int64_t I, int64_t J, int64_t K, double *res_slot,
                      const ReduceScratch &rs, hipStream_t s);
-constexpr int kStencilLaunches = 2;
-hipError_t copy_interior(float *p, const float *q, int64_t I, int64_t J, int64_t K, hipStream_t s);
+// p = q on the interior; a finish owed in *fin runs as one extra block of
+// the same launch (and *fin is cleared).
+hipError_t copy_interior(float *p, const float *q, int64_t I, int64_t J, int64_t K, hipStream_t s,
+                         ResidualFinish *fin = nullptr);
 hipError_t gemm_f32(const float *A, const float *B, float *C, int64_t M, int64_t N, int64_t K, hipStream_t s);
 
 // Products on MFMA over k-contiguous, tile-padded operands prepared in a

@@ -49,7 +49,7 @@ struct ofl_app;
 
 namespace {
 
-bool timed_nest(const ofl_app *app, const Nest &n);
+bool timed_nest(const ofl_app *app, const Nest &n, int32_t *exec_count);
 
 // Host work recorded into a graph: one serial nest, or the restore of set-up
 // content into host copies.  They live as long as the graph that calls them.
@@ -113,6 +113,7 @@ struct ofl_app {
     // per-kernel timing
     bool timing = false;
     uint64_t timing_ops = 0;                 // bit per Op of the timed kinds; 0: every kind
+    int32_t timing_stride = 1, timing_phase = 0;   // time executions i of a kind with i % stride == phase
     std::vector<hipEvent_t> events;
     std::map<std::string, std::pair<int64_t, double>> kstats;
 
@@ -268,7 +269,11 @@ int check_bufs(const ofl_app *app, void *const *dev_bufs, int32_t n_bufs) {
     return OFL_OK;
 }
 
-hipError_t launch_nest(ofl_app *app, const Nest &n, void *const *dev, const int64_t *env, hipStream_t s) {
+// `fin`: the residual finish owed by the last sweep launched on `s`; a sweep
+// sets it, an interior copy runs it as its extra block.  The callers run it
+// by itself (k::residual_finish) before any other step.
+hipError_t launch_nest(ofl_app *app, const Nest &n, void *const *dev, const int64_t *env, hipStream_t s,
+                       k::ResidualFinish &fin) {
     const AppIR &ir = app->ir;
     auto F = [&](int i) { return static_cast<float *>(dev[n.b[i]]); };
     auto cnt = [&](int i) { return ir.bufs[n.b[i]].count; };
@@ -308,11 +313,11 @@ hipError_t launch_nest(ofl_app *app, const Nest &n, void *const *dev, const int6
     case OP_STENCIL19: {
         const auto &d = ir.bufs[n.b[0]].dims;
         double *slot = static_cast<double *>(dev[n.b[2]]) + env[n.slot_repeat];
-        return k::stencil19(F(0), F(1), d[0], d[1], d[2], slot, rs, s);
+        return k::stencil19_sweep(F(0), F(1), d[0], d[1], d[2], slot, rs, s, fin);
     }
     case OP_COPY_INTERIOR: {
         const auto &d = ir.bufs[n.b[0]].dims;
-        return k::copy_interior(F(0), F(1), d[0], d[1], d[2], s);
+        return k::copy_interior(F(0), F(1), d[0], d[1], d[2], s, &fin);
     }
     default:
         return hipErrorInvalidValue;
@@ -326,14 +331,14 @@ int32_t kernel_launch_count(const AppIR &ir, const Nest &n) {
         const auto &a = ir.bufs[n.b[0]].dims, &bb = ir.bufs[n.b[1]].dims;
         return k::gemm_launches(a[0], bb[1], a[1], gemm_variant(n));
     }
-    if (n.op == OP_STENCIL19) return k::kStencilLaunches;
-    return 1;
+    return 1;   // a sweep's residual finish is counted where it is launched
 }
 
-// Whether the kernel timing of a nest is its first launch alone: single-launch
-// nests, and the sweep, whose second launch only adds up the residual.
-bool first_launch_timed(const AppIR &ir, const Nest &n) {
-    return n.op == OP_STENCIL19 || kernel_launch_count(ir, n) == 1;
+// Whether `step` takes the residual finish still owed by the last sweep: an
+// interior copy on the GPU runs it as an extra block of its launch; before
+// any other step (and at the end of the run) it runs by itself.
+bool takes_finish(const Step &step, const AppIR &ir) {
+    return step.kind == ST_GPU && ir.nests[step.idx].op == OP_COPY_INTERIOR;
 }
 
 struct RunResult {
@@ -446,10 +451,20 @@ RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *co
     }
     bool pending = false, timed_out = false;
     size_t ev_next = 0;
+    k::ResidualFinish fin;
+    int32_t exec_count[OP_COUNT] = {};
     for (const Step &step : plan.steps) {
         if (dl.expired()) {
             timed_out = true;
             break;
+        }
+        if (fin.n > 0 && !takes_finish(step, ir)) {
+            e = k::residual_finish(fin, stream);
+            if (e != hipSuccess) {
+                rr.code = hip_fail(e, "launch of a residual finish");
+                break;
+            }
+            st.n_launches++;
         }
         switch (step.kind) {
         case ST_H2D:
@@ -479,14 +494,13 @@ RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *co
             break;
         case ST_GPU: {
             const Nest &n = ir.nests[step.idx];
-            const bool tm = timed_nest(app, n) && ev_next + 2 <= app->events.size();
-            // a single-launch nest (and the sweep's main kernel) gets its events
-            // in the dispatch packet itself (kernel-only interval); another
-            // multi-launch nest is bracketed by events
-            const bool single = first_launch_timed(ir, n);
+            const bool tm = timed_nest(app, n, exec_count) && ev_next + 2 <= app->events.size();
+            // a single-launch nest gets its events in the dispatch packet itself
+            // (kernel-only interval); a multi-launch nest is bracketed by events
+            const bool single = kernel_launch_count(ir, n) == 1;
             if (tm && single) k::arm_launch_events(app->events[ev_next], app->events[ev_next + 1]);
             if (tm && !single) (void)hipEventRecord(app->events[ev_next], stream);
-            e = launch_nest(app, n, dev, plan.env.data() + step.env, stream);
+            e = launch_nest(app, n, dev, plan.env.data() + step.env, stream, fin);
             k::arm_launch_events(nullptr, nullptr);
             if (e != hipSuccess) {
                 rr.code = hip_fail(e, (std::string("launch of nest ") + n.name).c_str());
@@ -518,6 +532,11 @@ RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *co
         }
         }
         if (rr.code != OFL_OK || timed_out) break;
+    }
+    if (rr.code == OFL_OK && !timed_out && fin.n > 0) {
+        e = k::residual_finish(fin, stream);
+        if (e != hipSuccess) rr.code = hip_fail(e, "launch of a residual finish");
+        else st.n_launches++;
     }
     e = hipStreamSynchronize(stream);
     const auto t1 = clk::now();
@@ -568,8 +587,12 @@ void host_restore_cb(void *p) {
     }
 }
 
-bool timed_nest(const ofl_app *app, const Nest &n) {
-    return app->timing && (app->timing_ops == 0 || ((app->timing_ops >> n.op) & 1u));
+// Whether this execution of nest n is timed; exec_count[op] counts the
+// executions of each kind in the run (or the captured graph) so far.
+bool timed_nest(const ofl_app *app, const Nest &n, int32_t *exec_count) {
+    const int32_t i = exec_count[n.op]++;
+    if (!app->timing || !(app->timing_ops == 0 || ((app->timing_ops >> n.op) & 1u))) return false;
+    return i % app->timing_stride == app->timing_phase;
 }
 
 // Append an event record node to the graph being captured on `cs` after the
@@ -655,8 +678,15 @@ int build_graphs(ofl_app *app, const std::vector<uint8_t> &placement, void *cons
 
     if ((rc = capture_begin(app)) != OFL_OK) return rc;
     e = hipSuccess;
+    k::ResidualFinish fin;
+    int32_t exec_count[OP_COUNT] = {};
     for (const Step &st : plan.steps) {
         const Buffer *buf = (st.kind == ST_H2D || st.kind == ST_D2H) ? &ir.bufs[st.idx] : nullptr;
+        if (fin.n > 0 && !takes_finish(st, ir)) {
+            e = k::residual_finish(fin, cs);
+            if (e != hipSuccess) break;
+            ge.launches++;
+        }
         switch (st.kind) {
         case ST_H2D: e = hipMemcpyAsync(dev[st.idx], app->host[st.idx], buf->nbytes, hipMemcpyHostToDevice, cs); break;
         case ST_D2H:
@@ -665,7 +695,7 @@ int build_graphs(ofl_app *app, const std::vector<uint8_t> &placement, void *cons
             break;
         case ST_GPU: {
             hipEvent_t ev0 = nullptr, ev1 = nullptr;
-            const bool tm = timed_nest(app, ir.nests[st.idx]);
+            const bool tm = timed_nest(app, ir.nests[st.idx], exec_count);
             if (tm) {
                 e = hipEventCreate(&ev0);
                 if (e == hipSuccess) e = hipEventCreate(&ev1);
@@ -676,7 +706,7 @@ int build_graphs(ofl_app *app, const std::vector<uint8_t> &placement, void *cons
                 }
                 e = capture_event_node(cs, ev0);
             }
-            if (e == hipSuccess) e = launch_nest(app, ir.nests[st.idx], dev, plan.env.data() + st.env, cs);
+            if (e == hipSuccess) e = launch_nest(app, ir.nests[st.idx], dev, plan.env.data() + st.env, cs, fin);
             if (e == hipSuccess && tm) e = capture_event_node(cs, ev1);
             ge.launches += kernel_launch_count(ir, ir.nests[st.idx]);
             break;
@@ -694,6 +724,10 @@ int build_graphs(ofl_app *app, const std::vector<uint8_t> &placement, void *cons
         }
         if (e != hipSuccess) break;
     }
+    if (e == hipSuccess && fin.n > 0) {
+        e = k::residual_finish(fin, cs);
+        if (e == hipSuccess) ge.launches++;
+    }
     return capture_end(app, &ge.run, e == hipSuccess ? OFL_OK : hip_fail(e, "capture of the run graph"));
 }
 
@@ -706,6 +740,7 @@ int get_graph(ofl_app *app, const std::vector<uint8_t> &placement, void *const *
     key.push_back((uint64_t)gflags);
     key.push_back(app->timing ? 1u : 0u);
     key.push_back(app->timing ? app->timing_ops : 0u);
+    key.push_back(app->timing ? ((uint64_t)app->timing_stride << 32 | (uint32_t)app->timing_phase) : 0u);
     for (size_t b = 0; b < nb; ++b) key.push_back(reinterpret_cast<uint64_t>(dev[b]));
     auto it = app->graphs.find(key);
     if (it == app->graphs.end()) {
@@ -1226,6 +1261,14 @@ int ofl_set_kernel_timing(ofl_app *app, int32_t enable) {
     if (!app) return fail(OFL_E_ARG, "null app");
     app->timing = enable != 0;
     if (app->timing) app->kstats.clear();
+    return OFL_OK;
+}
+
+int ofl_set_kernel_timing_sample(ofl_app *app, int32_t stride, int32_t phase) {
+    if (!app) return fail(OFL_E_ARG, "null app");
+    if (stride < 1 || phase < 0 || phase >= stride) return fail(OFL_E_ARG, "need stride >= 1 and 0 <= phase < stride");
+    app->timing_stride = stride;
+    app->timing_phase = phase;
     return OFL_OK;
 }
 

@@ -291,6 +291,35 @@ def test_stencil_kernel_forms(cfg, wide, nt, monkeypatch):
         _run_and_compare(appgen.stencil_app(I, J, K, 2), [[1, 1]])
 
 
+def _two_sweep_app(I, J, K, S):
+    # two sweeps back to back (the second reads the first one's output), then
+    # the interior copy; a single sweep as the program's last nest
+    doc = appgen.stencil_app(I, J, K, S)
+    doc["name"] = "two_sweeps"
+    doc["buffers"] += [appgen.grid("r", "zero", True), {"name": "res2", "dtype": "f64", "dims": ["SWEEPS"],
+                                                        "output": True},
+                       {"name": "res3", "dtype": "f64", "dims": ["LAST"], "output": True}]
+    doc["params"]["LAST"] = 2
+    second = appgen.stencil_nest("q", "r", "res2", "n")
+    second["nest"] = "stencil19_b"
+    doc["program"] = [{"repeat": "SWEEPS", "var": "n",
+                       "body": [appgen.stencil_nest("p", "q", "res", "n"), second,
+                                appgen.copy_interior_nest("p", "r")]},
+                      {"repeat": "LAST", "var": "m",
+                       "body": [dict(appgen.stencil_nest("p", "q", "res3", "m"), nest="stencil19_last")]}]
+    return doc
+
+
+def test_stencil_residual_finish_placement():
+    # the residual finish a sweep owes runs in the next interior copy's extra
+    # block, or by itself before any other step / at the end of the run: every
+    # placement of the four nests (the last sweep repeated twice: a sweep
+    # directly after a sweep), eager and as graph replays
+    doc = _two_sweep_app(9, 12, 131, 3)
+    genes = [[(g >> b) & 1 for b in range(4)] for g in range(16)]
+    _run_and_compare(doc, genes, flags_list=(0, ofl.GRAPH | ofl.PRESTAGED | ofl.KEEP_OUTPUTS))
+
+
 def test_stencil_fixed_point_exact():
     I, J, K = 21, 34, 133
     ii, jj, kk = np.meshgrid(np.arange(I), np.arange(J), np.arange(K), indexing="ij")
@@ -357,6 +386,18 @@ def test_kernel_timing_and_bad_buffers():
     assert n == 10 and ms > 0
     n, ms = app.kernel_stats("gemm")
     assert n == 1 and ms > 0
+    # sampled timing of two kinds: executions 1, 5, 9 of the 10 sweeps and
+    # copies, eager and in a graph replay
+    app.set_kernel_timing_op("stencil19,copy_interior")
+    app.set_kernel_timing_sample(4, 1)
+    for flags in (0, ofl.GRAPH):
+        app.set_kernel_timing(True)
+        app.run_pattern([1] * 6, bufs, flags=flags)
+        assert [app.kernel_stats(k)[0] for k in ("stencil19", "copy_interior", "gemm")] == [3, 3, 0]
+        assert min(app.kernel_stats(k)[1] for k in ("stencil19", "copy_interior")) > 0
+    app.set_kernel_timing(False)
+    app.set_kernel_timing_sample(1, 0)
+    app.set_kernel_timing_op(None)
     with pytest.raises(ofl.OflError) as ei:
         app.run_pattern([1] * 6, bufs[:-1])
     assert ei.value.code == -8

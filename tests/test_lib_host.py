@@ -149,6 +149,12 @@ def test_kernel_timing_kind_lists():
         with pytest.raises(ofl.OflError) as ei:
             app.set_kernel_timing_op(bad)
         assert ei.value.code == -1
+    for stride, phase in ((1, 0), (25, 12), (100, 99)):
+        app.set_kernel_timing_sample(stride, phase)
+    for stride, phase in ((0, 0), (-1, 0), (10, 10), (10, -1)):
+        with pytest.raises(ofl.OflError) as ei:
+            app.set_kernel_timing_sample(stride, phase)
+        assert ei.value.code == -1
 
 
 @pytest.mark.parametrize("mutate,code", [
