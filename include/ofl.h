@@ -141,6 +141,11 @@ typedef struct {
     double deadline_factor;  /* > 0: measure the all-zero gene first and give
                                 every later run the limit
                                 min(t_all0, deadline_factor * t_best); 0 = none */
+    double timeout_s;        /* > 0: no run (the all-zero one included) goes on
+                                past this wall time; one that would is a
+                                TIMEOUT with fitness 0, like a trial cut off
+                                by a timeout (Sec. 5.2); 0 = none.  With
+                                deadline_factor the limit is the smaller one */
 } ofl_ga_params;
 
 typedef struct {

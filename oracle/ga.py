@@ -60,12 +60,15 @@ def fitness(t, status, p):
 
 
 def run_ga(a, M, T, evaluate, Pc=0.9, Pm=0.05, p=0.5, seed=1,
-           deadline_factor=0.0, batched=False):
+           deadline_factor=0.0, batched=False, timeout=None):
     """Run the GA.  ``evaluate(gene_tuple, deadline) -> (time, status)``
     measures an uncached pattern; ``deadline`` is None or a time limit.
     When deadline_factor > 0 the all-zero gene is measured first (baseline,
     also entered in the cache and the best-so-far), and every later
     measurement gets the limit min(t_all0, deadline_factor * t_best).
+    ``timeout`` (seconds, None = none) caps every measurement, the baseline
+    included: the paper's trials that ran too long were cut off (Sec. 5.2);
+    the limit is the smaller of the two.
 
     ``batched``: all uncached genes of a generation are measured together (in
     order of first appearance), so they share the limit taken at the start
@@ -88,19 +91,21 @@ def run_ga(a, M, T, evaluate, Pc=0.9, Pm=0.05, p=0.5, seed=1,
     t_all0 = None
     if deadline_factor > 0:
         g0 = tuple([0] * a)
-        t0, s0 = evaluate(g0, None)
+        t0, s0 = evaluate(g0, timeout)
         cache[g0] = (t0, s0)
         log.append((g0, t0, s0))
         consider(g0, t0, s0)
         t_all0 = t0 if s0 == ST_OK else None
 
     def current_limit():
+        cands = []
         if deadline_factor > 0 and best["t"] is not None:
-            cands = [deadline_factor * best["t"]]
+            cands.append(deadline_factor * best["t"])
             if t_all0 is not None:
                 cands.append(t_all0)
-            return min(cands)
-        return None
+        if timeout is not None:
+            cands.append(timeout)
+        return min(cands) if cands else None
 
     pop = [tuple(rng.next() >> 63 for _ in range(a)) for _ in range(M)]
     gens = []

@@ -73,7 +73,7 @@ void run_ga(int a, const GaConfig &cfg, const Evaluator &evaluate, GaTrace &out,
 
     if (cfg.deadline_factor > 0.0) {
         std::vector<uint8_t> zero(a, 0);
-        Measurement m0 = evaluate(zero, -1.0);
+        Measurement m0 = evaluate(zero, cfg.timeout_s > 0.0 ? cfg.timeout_s : -1.0);
         cache[zero] = m0;
         record(zero, m0);
         if (m0.status == OFL_ST_OK) out.t_all0 = m0.t;
@@ -89,6 +89,7 @@ void run_ga(int a, const GaConfig &cfg, const Evaluator &evaluate, GaTrace &out,
             limit = cfg.deadline_factor * out.best_t;
             if (out.t_all0 > 0.0 && out.t_all0 < limit) limit = out.t_all0;
         }
+        if (cfg.timeout_s > 0.0 && (limit < 0.0 || cfg.timeout_s < limit)) limit = cfg.timeout_s;
         return limit;
     };
 

@@ -12,6 +12,7 @@ struct GaConfig {
     double Pc = 0.9, Pm = 0.05, p = 0.5;
     uint64_t seed = 1;
     double deadline_factor = 0.0;
+    double timeout_s = 0.0;      // > 0: absolute limit on every run
 };
 
 struct Measurement {

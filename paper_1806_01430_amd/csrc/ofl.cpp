@@ -962,6 +962,7 @@ GaConfig ga_config(const ofl_ga_params *p) {
     c.p = p->p;
     c.seed = p->seed;
     c.deadline_factor = p->deadline_factor;
+    c.timeout_s = p->timeout_s;
     return c;
 }
 

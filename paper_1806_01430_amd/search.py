@@ -37,6 +37,7 @@ def main(argv=None):
     ap.add_argument("--batched", action="store_true",
                     help="measure each generation's new genes in one submission (graph chain)")
     ap.add_argument("--deadline-factor", type=float, default=0.0)
+    ap.add_argument("--timeout", type=float, default=0.0, help="seconds; cut off any run longer than this (0 = none)")
     ap.add_argument("--baseline", action="store_true", help="also measure the all-CPU gene")
     ap.add_argument("--exhaustive", action="store_true",
                     help="also measure every gene (gene length <= 12) and rank the GA's answer")
@@ -59,7 +60,8 @@ def main(argv=None):
     policy = {"resident": RESIDENT, "per_region": PER_REGION, "sections": SECTIONS}[args.policy]
     flags = (GRAPH if args.graph else 0) | (BATCHED if args.batched else 0)
     params = ga_params(M=args.M, T=args.T, Pc=args.Pc, Pm=args.Pm, p=args.p, seed=args.ga_seed, reps=args.reps,
-                       warmup=args.warmup, policy=policy, flags=flags, deadline_factor=args.deadline_factor)
+                       warmup=args.warmup, policy=policy, flags=flags, deadline_factor=args.deadline_factor,
+                       timeout_s=args.timeout)
     t0 = time.perf_counter()
     res = app.ga_run(params, bufs)
     wall = time.perf_counter() - t0

@@ -198,23 +198,26 @@ def test_accepted_host_only_op_is_invalid():
 def _oracle_ga(a, params, table, status=None):
     return G.run_ga(a, params.M, params.T, G.table_evaluator(table, status), Pc=params.Pc, Pm=params.Pm,
                     p=params.p, seed=params.seed, deadline_factor=params.deadline_factor,
-                    batched=bool(params.flags & ofl.BATCHED))
+                    batched=bool(params.flags & ofl.BATCHED),
+                    timeout=params.timeout_s if params.timeout_s > 0 else None)
 
 
-@pytest.mark.parametrize("a,M,T,Pc,Pm,p,seed,dl", [
-    (6, 4, 3, 0.9, 0.05, 0.5, 1, 0.0),
-    (6, 12, 12, 0.9, 0.05, 0.5, 7, 0.0),
-    (10, 20, 20, 0.9, 0.05, 1.0, 3, 0.0),
-    (13, 30, 20, 0.9, 0.05, 0.5, 11, 3.0),
-    (1, 3, 4, 0.9, 0.5, 0.5, 2, 0.0),
-    (5, 7, 6, 0.0, 0.0, 0.5, 5, 0.0),
-    (5, 8, 6, 1.0, 1.0, 0.5, 6, 2.0),
-    (12, 12, 12, 0.9, 0.05, 0.5, 2018, 0.0),
+@pytest.mark.parametrize("a,M,T,Pc,Pm,p,seed,dl,tmo", [
+    (6, 4, 3, 0.9, 0.05, 0.5, 1, 0.0, 0.0),
+    (6, 12, 12, 0.9, 0.05, 0.5, 7, 0.0, 0.0),
+    (10, 20, 20, 0.9, 0.05, 1.0, 3, 0.0, 0.0),
+    (13, 30, 20, 0.9, 0.05, 0.5, 11, 3.0, 0.0),
+    (1, 3, 4, 0.9, 0.5, 0.5, 2, 0.0, 0.0),
+    (5, 7, 6, 0.0, 0.0, 0.5, 5, 0.0, 0.0),
+    (5, 8, 6, 1.0, 1.0, 0.5, 6, 2.0, 0.0),
+    (12, 12, 12, 0.9, 0.05, 0.5, 2018, 0.0, 0.0),
+    (8, 10, 8, 0.9, 0.05, 0.5, 4, 0.0, 2.5),
+    (10, 12, 10, 0.9, 0.05, 0.5, 9, 3.0, 1.0),
 ])
 @pytest.mark.parametrize("batched", [False, True])
-def test_ga_trajectory_matches_oracle(a, M, T, Pc, Pm, p, seed, dl, batched):
+def test_ga_trajectory_matches_oracle(a, M, T, Pc, Pm, p, seed, dl, tmo, batched):
     table = workloads.time_table(a, seed * 31 + a, lo=0.01, hi=5.0)
-    params = ofl.ga_params(M=M, T=T, Pc=Pc, Pm=Pm, p=p, seed=seed, deadline_factor=dl,
+    params = ofl.ga_params(M=M, T=T, Pc=Pc, Pm=Pm, p=p, seed=seed, deadline_factor=dl, timeout_s=tmo,
                            flags=ofl.BATCHED if batched else 0)
     got = ofl.ga_run_table(a, params, table)
     want = _oracle_ga(a, params, table)
@@ -227,7 +230,8 @@ def test_ga_trajectory_matches_oracle(a, M, T, Pc, Pm, p, seed, dl, batched):
     assert got["best_time"] == want["best_time"]
     assert got["n_measured"] == want["n_measured"]
     if dl > 0:
-        assert got["t_all0"] == want["t_all0"]
+        # the library reports a baseline that did not finish as -1
+        assert got["t_all0"] == (want["t_all0"] if want["t_all0"] is not None else -1.0)
 
 
 def test_batched_generations_change_only_the_deadline():

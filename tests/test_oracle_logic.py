@@ -224,6 +224,19 @@ def test_ga_deadline_marks_slow_genes():
             assert table[G.gene_index(g)] > t
 
 
+def test_ga_timeout_caps_every_run():
+    # a fixed timeout cuts off every run above it, the all-zero baseline included
+    a = 6
+    table = workloads.time_table(a, 8, lo=0.01, hi=10.0)
+    table[0] = 9.0
+    out = G.run_ga(a, 8, 4, G.table_evaluator(table), seed=2, deadline_factor=2.0, timeout=3.0)
+    assert out["log"][0] == (tuple([0] * a), 3.0, G.ST_TIMEOUT)
+    assert out["t_all0"] is None
+    for g, t, st in out["log"]:
+        assert t <= 3.0
+        assert (st == G.ST_TIMEOUT) == (table[G.gene_index(g)] > t)
+
+
 def test_ga_all_failed_uniform_selection():
     a = 4
     out = G.run_ga(a, 5, 3, G.table_evaluator([1.0] * 16, [G.ST_FAILED] * 16), seed=1)
