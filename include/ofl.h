@@ -83,7 +83,7 @@ enum {
                                 host nodes for the CPU nests; deadlines are not
                                 applied to graph runs.  Plans and results are
                                 those of the eager run. */
-    OFL_RUN_BATCHED = 8      /* population evaluation (ofl_eval_population,
+    OFL_RUN_BATCHED = 8,     /* population evaluation (ofl_eval_population,
                                 ofl_ga_run, ofl_ga_run_table) only: all
                                 uncached genes of a population / generation are
                                 measured in ONE submission -- per repetition
@@ -98,6 +98,9 @@ enum {
                                 runs short; in the GA every gene of a
                                 generation gets the limit taken at the start of
                                 that generation. */
+    OFL_RUN_PROGRESS = 16    /* ofl_ga_run only: one line per generation on
+                                stderr (generation, best time so far, genes
+                                measured, wall time), for long searches */
 };
 
 /* Buffer element types. */

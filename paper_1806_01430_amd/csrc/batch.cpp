@@ -242,7 +242,7 @@ int build_tables(ofl_batch *b, void *const *bufs) {
             std::vector<int64_t> work(b->inst.size());
             for (size_t i = 0; i < b->inst.size(); ++i) {
                 const Nest &n = b->inst[i].nests[ni];
-                const auto &a = b->inst[i].bufs[n.b[0]].dims, &bb = b->inst[i].bufs[n.b[1]].dims;
+                const auto &a = b->inst[i].bufs[n.b[0]].dims;
                 work[i] = a[1];   // per-tile cost grows with K
             }
             std::vector<k::GemmJob> jobs;

@@ -52,7 +52,8 @@ double ga_fitness(const Measurement &m, double p) {
     return std::pow(m.t, -p);
 }
 
-void run_ga(int a, const GaConfig &cfg, const Evaluator &evaluate, GaTrace &out, const BatchEvaluator *batch) {
+void run_ga(int a, const GaConfig &cfg, const Evaluator &evaluate, GaTrace &out, const BatchEvaluator *batch,
+            const GaProgress *progress) {
     using clk = std::chrono::steady_clock;
     const auto t_start = clk::now();
     out = GaTrace();
@@ -123,6 +124,7 @@ void run_ga(int a, const GaConfig &cfg, const Evaluator &evaluate, GaTrace &out,
         }
         out.pops.push_back(pop);
         out.meas.push_back(meas);
+        if (progress) (*progress)(gen, out, elapsed());
         if (gen == cfg.T) break;
 
         int elite = 0;

@@ -15,6 +15,11 @@ struct GaConfig {
     double timeout_s = 0.0;      // > 0: absolute limit on every run
 };
 
+struct GaTrace;
+// called after each generation is measured: (generation 1..T, trace so far,
+// wall seconds since the search started)
+using GaProgress = std::function<void(int, const GaTrace &, double)>;
+
 struct Measurement {
     double t = 0.0;
     int status = 0;   // OFL_ST_*
@@ -39,7 +44,7 @@ struct GaTrace {
 // With `batch`, every generation's uncached genes are measured by one call of
 // it (the baseline all-zero gene still by `evaluate`).
 void run_ga(int a, const GaConfig &cfg, const Evaluator &evaluate, GaTrace &out,
-            const BatchEvaluator *batch = nullptr);
+            const BatchEvaluator *batch = nullptr, const GaProgress *progress = nullptr);
 
 double ga_fitness(const Measurement &m, double p);
 

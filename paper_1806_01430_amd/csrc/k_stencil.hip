@@ -73,6 +73,31 @@ __global__ __launch_bounds__(kThreads) void k_stencil19w(const float *__restrict
     if (lane == 0) partials[lb * kWavesPerBlock + wib] = acc;
 }
 
+// The sweep with 128 output columns per wave (stencil_item_v): items whose
+// tile lies wholly inside the interior take the mask-free path.
+template <int JR, int SP>
+__global__ __launch_bounds__(kThreads) void k_stencil19v(const float *__restrict__ p, float *__restrict__ q, Geo g,
+                                                         double *partials) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int nb = gridDim.x;
+    const int lb = (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8;
+    const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int nwaves = nb * kWavesPerBlock;
+    const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, g.bytes, kBufferConfig);
+    const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc((void *)q, (short)0, g.bytes, kBufferConfig);
+    const int nkt_full = (g.K - 2) / kOutV, njt_full = (g.J - 2) / JR;
+    double acc = 0.0;
+    for (int w = lb * kWavesPerBlock + wib; w < g.items; w += nwaves) {
+        const int kt = w % g.nkt, jt = (w / g.nkt) % g.njt;
+        if (kt < nkt_full && jt < njt_full)
+            acc = stencil_item_v<JR, true, SP>(rp, rq, g, w, lane, acc);
+        else
+            acc = stencil_item_v<JR, false, SP>(rp, rq, g, w, lane, acc);
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) partials[lb * kWavesPerBlock + wib] = acc;
+}
+
 // res_slot[0] += the n wave partials of a sweep, in a fixed order: thread t
 // sums partials t, t + 256, ... (loads unrolled so that they overlap), then a
 // tree over the threads in LDS.  Executed by one whole block of 256 threads:
@@ -132,26 +157,37 @@ __global__ __launch_bounds__(kThreads) void k_copy_interior(float *__restrict__ 
     for (int row0 = gwave * ROWS; row0 < rows; row0 += nwaves * ROWS) copy_rows<ROWS, POL>(rp, rq, J, K, rows, row0, lane);
 }
 
+// Sweep forms: one column per lane (62 outputs per wave), two columns per
+// lane (126 outputs), two columns per lane with scalar-loaded halo columns
+// (128 outputs, 8-byte stores on interior tiles).
+enum Form { kFormOne = 0, kFormWide = 1, kFormV = 2 };
+
 struct Config {
     int JR;
-    bool wide = false;       // two columns per lane
+    int form = kFormOne;
     bool store_nt = false;   // q written with the non-temporal policy
     Geo g;
     unsigned blocks;
 };
 
-int resident_blocks_per_cu(int JR, bool wide);
+int resident_blocks_per_cu(int JR, int form);
+
+bool valid_jr(int JR, int form) {
+    return form == kFormV ? (JR == 4 || JR == 6 || JR == 8) : (JR == 2 || JR == 4 || JR == 8);
+}
 
 // Tuning knobs, used by tuning sweeps: OFL_STENCIL_CFG="JR,IC" overrides the
-// choice (JR in {2,4,8}, IC planes per work item, 0 = automatic) and then
-// selects one column per lane unless OFL_STENCIL_WIDE=1 (two columns per
-// lane; OFL_STENCIL_WIDE=0/1 also overrides the default choice).
+// choice (JR rows per item, IC planes per work item, 0 = automatic) and then
+// selects one column per lane unless a form is named: OFL_STENCIL_WIDE=0/1
+// (one / two columns per lane) or OFL_STENCIL_FORM=1/w/v (one column, two
+// columns, two columns with 128 outputs per wave), the latter taking
+// precedence.  JR is one of 2, 4, 8 (forms 1 and w) or 4, 6, 8 (form v).
 bool env_override(int &JR, int &IC) {
     const char *s = std::getenv("OFL_STENCIL_CFG");
     if (!s) return false;
     int a, b;
     if (std::sscanf(s, "%d,%d", &a, &b) != 2) return false;
-    if (!((a == 2 || a == 4 || a == 8) && b >= 0)) return false;
+    if (!((a == 2 || a == 4 || a == 6 || a == 8) && b >= 0)) return false;
     JR = a;
     IC = b;
     return true;
@@ -173,9 +209,7 @@ Config choose(int64_t I, int64_t J, int64_t K) {
     const bool forced = env_override(JR, IC);
     if (!forced) JR = ni >= 192 ? 8 : 4;
     if (IC <= 0) IC = ni >= 384 ? 16 : ni >= 192 ? 12 : ni >= 96 ? 6 : 3;
-    c.wide = !forced && ni >= 384;
-    c.JR = JR;
-    c.g = make_geo(I, J, K, JR, IC);
+    c.form = !forced && ni >= 384 ? kFormWide : kFormOne;
     // q with the non-temporal policy on grids of 4 MB to 512 MB: measured
     // faster at 129x129x257 (9.9 vs 12.3 us) and 257x257x513 (54.4 vs 61.1),
     // slower at 513x513x1025 (654 vs 573) and 65x65x129 (6.4 vs 5.6);
@@ -183,9 +217,13 @@ Config choose(int64_t I, int64_t J, int64_t K) {
     const int64_t grid_bytes = I * J * K * 4;
     c.store_nt = grid_bytes >= ((int64_t)4 << 20) && grid_bytes <= ((int64_t)512 << 20);
     if (const char *nt = std::getenv("OFL_STENCIL_NT")) c.store_nt = nt[0] == '1';
-    if (const char *wd = std::getenv("OFL_STENCIL_WIDE")) c.wide = wd[0] == '1';
-    if (c.wide) c.g = make_geo(I, J, K, JR, IC, kOutW);
-    const int64_t resident_blocks = (int64_t)cu_count() * resident_blocks_per_cu(JR, c.wide);
+    if (const char *wd = std::getenv("OFL_STENCIL_WIDE")) c.form = wd[0] == '1' ? kFormWide : kFormOne;
+    if (const char *fm = std::getenv("OFL_STENCIL_FORM"))
+        c.form = fm[0] == 'v' ? kFormV : fm[0] == 'w' ? kFormWide : kFormOne;
+    if (!valid_jr(JR, c.form)) JR = 8;
+    c.JR = JR;
+    c.g = make_geo(I, J, K, JR, IC, c.form == kFormV ? kOutV : c.form == kFormWide ? kOutW : kOut);
+    const int64_t resident_blocks = (int64_t)cu_count() * resident_blocks_per_cu(JR, c.form);
     int64_t blocks = ((int64_t)c.g.items + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > resident_blocks) blocks = resident_blocks;
     blocks = (blocks + 7) / 8 * 8;
@@ -195,14 +233,25 @@ Config choose(int64_t I, int64_t J, int64_t K) {
 
 template <int JR>
 hipError_t launch_t(const Config &c, const float *p, float *q, double *partials, hipStream_t s) {
-    if (c.wide) {
-        if (c.store_nt)
-            return launch((k_stencil19w<JR, kNonTemporal>), dim3(c.blocks), dim3(kThreads), 0, s, p, q, c.g, partials);
-        return launch((k_stencil19w<JR, 0>), dim3(c.blocks), dim3(kThreads), 0, s, p, q, c.g, partials);
+    const dim3 grid(c.blocks), block(kThreads);
+    if (c.form == kFormV) {
+        if constexpr (JR == 2) {
+            return hipErrorInvalidValue;
+        } else {
+            if (c.store_nt) return launch((k_stencil19v<JR, kNonTemporal>), grid, block, 0, s, p, q, c.g, partials);
+            return launch((k_stencil19v<JR, 0>), grid, block, 0, s, p, q, c.g, partials);
+        }
     }
-    if (c.store_nt)
-        return launch((k_stencil19<JR, kNonTemporal>), dim3(c.blocks), dim3(kThreads), 0, s, p, q, c.g, partials);
-    return launch((k_stencil19<JR, 0>), dim3(c.blocks), dim3(kThreads), 0, s, p, q, c.g, partials);
+    if constexpr (JR == 6) {
+        return hipErrorInvalidValue;
+    } else {
+        if (c.form == kFormWide) {
+            if (c.store_nt) return launch((k_stencil19w<JR, kNonTemporal>), grid, block, 0, s, p, q, c.g, partials);
+            return launch((k_stencil19w<JR, 0>), grid, block, 0, s, p, q, c.g, partials);
+        }
+        if (c.store_nt) return launch((k_stencil19<JR, kNonTemporal>), grid, block, 0, s, p, q, c.g, partials);
+        return launch((k_stencil19<JR, 0>), grid, block, 0, s, p, q, c.g, partials);
+    }
 }
 
 template <typename Kern>
@@ -212,18 +261,22 @@ int occupancy_of(Kern kern) {
     return n;
 }
 
-int resident_blocks_per_cu(int JR, bool wide) {
+int resident_blocks_per_cu(int JR, int form) {
     static std::once_flag once;
-    static int table[2][3];
+    static int table[3][4];   // [form][JR 2, 4, 6, 8]
     std::call_once(once, [] {
         table[0][0] = occupancy_of(k_stencil19<2, 0>);
         table[0][1] = occupancy_of(k_stencil19<4, 0>);
-        table[0][2] = occupancy_of(k_stencil19<8, 0>);
+        table[0][3] = occupancy_of(k_stencil19<8, 0>);
         table[1][0] = occupancy_of(k_stencil19w<2, 0>);
         table[1][1] = occupancy_of(k_stencil19w<4, 0>);
-        table[1][2] = occupancy_of(k_stencil19w<8, 0>);
+        table[1][3] = occupancy_of(k_stencil19w<8, 0>);
+        table[2][1] = occupancy_of(k_stencil19v<4, 0>);
+        table[2][2] = occupancy_of(k_stencil19v<6, 0>);
+        table[2][3] = occupancy_of(k_stencil19v<8, 0>);
+        table[0][2] = table[1][2] = table[2][0] = 1;
     });
-    return table[wide ? 1 : 0][JR == 2 ? 0 : JR == 4 ? 1 : 2];
+    return table[form][JR / 2 - 1];
 }
 
 }  // namespace
@@ -289,6 +342,7 @@ hipError_t stencil19_sweep(const float *p, float *q, int64_t I, int64_t J, int64
     const int waves = (int)c.blocks * kWavesPerBlock;
     if ((int64_t)waves > rs.capacity) return hipErrorInvalidValue;
     const hipError_t e = c.JR == 8   ? launch_t<8>(c, p, q, rs.partials, s)
+                         : c.JR == 6 ? launch_t<6>(c, p, q, rs.partials, s)
                          : c.JR == 4 ? launch_t<4>(c, p, q, rs.partials, s)
                                      : launch_t<2>(c, p, q, rs.partials, s);
     if (e != hipSuccess) return e;

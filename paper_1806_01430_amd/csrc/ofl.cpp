@@ -1206,8 +1206,14 @@ int ofl_ga_run(ofl_app *app, const ofl_ga_params *params, void *const *dev_bufs,
         if (rc2 != OFL_OK) hard = rc2;
         return out;
     };
+    GaProgress prog = [&](int gen, const GaTrace &t, double wall) {
+        std::fprintf(stderr, "ga generation %d/%d: best %.6f s, %d genes measured, %.1f s\n", gen, params->T,
+                     t.best_t, t.n_measured, wall);
+        std::fflush(stderr);
+    };
     GaTrace tr;
-    run_ga(a, ga_config(params), ev, tr, (params->flags & OFL_RUN_BATCHED) ? &bev : nullptr);
+    run_ga(a, ga_config(params), ev, tr, (params->flags & OFL_RUN_BATCHED) ? &bev : nullptr,
+           (params->flags & OFL_RUN_PROGRESS) ? &prog : nullptr);
     if (hard != OFL_OK) return hard;
     fill_ga_result(tr, a, params->M, result);
     return OFL_OK;

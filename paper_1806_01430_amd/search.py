@@ -15,7 +15,7 @@ import time
 
 import numpy as np
 
-from . import App, app_path, ga_params, RESIDENT, PER_REGION, SECTIONS, PRESTAGED, KEEP_OUTPUTS, GRAPH, BATCHED
+from . import App, app_path, ga_params, RESIDENT, PER_REGION, SECTIONS, PRESTAGED, KEEP_OUTPUTS, GRAPH, BATCHED, PROGRESS
 
 
 def main(argv=None):
@@ -38,6 +38,7 @@ def main(argv=None):
                     help="measure each generation's new genes in one submission (graph chain)")
     ap.add_argument("--deadline-factor", type=float, default=0.0)
     ap.add_argument("--timeout", type=float, default=0.0, help="seconds; cut off any run longer than this (0 = none)")
+    ap.add_argument("--progress", action="store_true", help="one line per generation on stderr")
     ap.add_argument("--baseline", action="store_true", help="also measure the all-CPU gene")
     ap.add_argument("--exhaustive", action="store_true",
                     help="also measure every gene (gene length <= 12) and rank the GA's answer")
@@ -58,7 +59,7 @@ def main(argv=None):
     app = App(src, seed=args.seed)
     bufs = app.alloc_device_buffers("cuda:0")
     policy = {"resident": RESIDENT, "per_region": PER_REGION, "sections": SECTIONS}[args.policy]
-    flags = (GRAPH if args.graph else 0) | (BATCHED if args.batched else 0)
+    flags = (GRAPH if args.graph else 0) | (BATCHED if args.batched else 0) | (PROGRESS if args.progress else 0)
     params = ga_params(M=args.M, T=args.T, Pc=args.Pc, Pm=args.Pm, p=args.p, seed=args.ga_seed, reps=args.reps,
                        warmup=args.warmup, policy=policy, flags=flags, deadline_factor=args.deadline_factor,
                        timeout_s=args.timeout)

@@ -276,18 +276,24 @@ def test_stencil_shapes(I, J, K, S):
     _run_and_compare(appgen.stencil_app(I, J, K, S), [[1, 1], [1, 0], [0, 1]])
 
 
-# every sweep kernel form (rows per item, planes per item, one or two columns
-# per lane, store policy), forced through the library's tuning knobs, on
-# ragged shapes: k-tiles with a partial last tile, j-runs past the last row,
-# i-runs shorter than the item
-@pytest.mark.parametrize("cfg,wide,nt", [("2,1", "0", "0"), ("4,3", "0", "1"), ("8,5", "0", "0"), ("2,2", "1", "1"),
-                                         ("4,6", "1", "0"), ("8,4", "1", "1"), ("8,16", "1", "0")])
-def test_stencil_kernel_forms(cfg, wide, nt, monkeypatch):
+# every sweep kernel form (rows per item, planes per item; one column per
+# lane, two columns per lane with 126 or with 128 outputs per wave; store
+# policy), forced through the library's tuning knobs, on ragged shapes:
+# k-tiles with a partial last tile, j-runs past the last row, i-runs shorter
+# than the item; the 128-output form also on shapes whose tiles are all
+# interior (K - 2 a multiple of 128, J - 2 of the rows per item)
+@pytest.mark.parametrize("cfg,form,nt", [("2,1", "1", "0"), ("4,3", "1", "1"), ("8,5", "1", "0"), ("2,2", "w", "1"),
+                                         ("4,6", "w", "0"), ("8,4", "w", "1"), ("8,16", "w", "0"),
+                                         ("4,2", "v", "0"), ("6,5", "v", "1"), ("8,4", "v", "0"), ("8,16", "v", "1")])
+def test_stencil_kernel_forms(cfg, form, nt, monkeypatch):
     monkeypatch.setenv("OFL_STENCIL_CFG", cfg)
-    monkeypatch.setenv("OFL_STENCIL_WIDE", wide)
+    monkeypatch.setenv("OFL_STENCIL_FORM", form)
     monkeypatch.setenv("OFL_STENCIL_NT", nt)
-    for I, J, K in [(4, 5, 6), (19, 23, 71), (5, 130, 300), (10, 11, 129), (6, 9, 254), (7, 6, 128)]:
-        say("case stencil form %s wide=%s nt=%s grid %dx%dx%d" % (cfg, wide, nt, I, J, K))
+    shapes = [(4, 5, 6), (19, 23, 71), (5, 130, 300), (10, 11, 129), (6, 9, 254), (7, 6, 128)]
+    if form == "v":
+        shapes += [(9, 26, 258), (8, 18, 130), (11, 34, 386)]
+    for I, J, K in shapes:
+        say("case stencil form %s %s nt=%s grid %dx%dx%d" % (cfg, form, nt, I, J, K))
         _run_and_compare(appgen.stencil_app(I, J, K, 2), [[1, 1]])
 
 
@@ -419,6 +425,27 @@ def test_eval_population_and_ga_tiny():
     assert res["best_time"] > 0
     rank = int(np.sum(t < t[sum(b << i for i, b in enumerate(res["best_gene"]))]))
     say("GA best gene", res["best_gene"], "exhaustive best", genes[best_idx], "rank", rank)
+
+
+def test_ga_timeout_and_progress_lines(capfd):
+    # an absolute timeout below the all-CPU gene's time cuts that run off
+    # (TIMEOUT, fitness 0); the progress flag prints one line per generation
+    doc = workloads.app_doc("tiny")
+    app = ofl.App(json.dumps(doc))
+    bufs = app.alloc_device_buffers()
+    t0, s0 = app.eval_population([[0] * 6], bufs, reps=3, warmup=1)
+    assert s0[0] == ofl.ST_OK
+    tmo = float(t0[0]) / 4
+    say("case GA tiny with timeout %.6f s and progress" % tmo)
+    res = app.ga_run(ofl.ga_params(M=4, T=3, seed=1, reps=3, warmup=1, deadline_factor=2.0, timeout_s=tmo,
+                                   flags=ofl.PROGRESS), bufs)
+    err = capfd.readouterr().err
+    lines = [ln for ln in err.splitlines() if ln.startswith("ga generation ")]
+    assert [ln.split()[2].rstrip(":") for ln in lines] == ["1/3", "2/3", "3/3"]
+    assert res["t_all0"] == -1.0            # the all-CPU baseline was cut off
+    for g in range(res["n_generations"]):
+        for t, st in zip(res["times"][g], res["status"][g]):
+            assert st == ofl.ST_TIMEOUT or (st == ofl.ST_OK and t <= tmo)
 
 
 # ---------------------------------------------------------------- graph runs
