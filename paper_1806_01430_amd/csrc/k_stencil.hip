@@ -98,6 +98,183 @@ __global__ __launch_bounds__(kThreads) void k_stencil19v(const float *__restrict
     if (lane == 0) partials[lb * kWavesPerBlock + wib] = acc;
 }
 
+// Band sweep for grids whose interior row spans at most 8 k-tiles of 128
+// columns.  A block of 16 waves owns a band of TB = 64 / NKT rows covering
+// every column of the interior (NKT waves across a row, each 128 columns with
+// two columns per lane; 16 / NKT row groups of 4 rows) and a run of planes.
+// Per plane the block stages the TB + 2 rows it reads -- one contiguous range
+// of the plane -- in LDS through 16-byte loads and stores (the loads of a plane
+// go out one step before it is staged), then
+// every wave derives a, x, y of its 4 rows x 128 columns from LDS (lanes 0 and
+// 63 read the tile's halo columns) and marches along i with a, x, y of three
+// planes in registers, as stencil_item does.  Per point the arithmetic is that
+// of stencil_item, in the same order.  One barrier per plane: a plane's staging
+// buffer (two buffers, alternating) is written only after every wave has
+// passed the barrier of the step after the one that last read it.
+constexpr int kBandThreads = 1024;
+constexpr int kBandChunks = 3;                               // 16-byte pieces per thread per plane
+constexpr int kBandCap = kBandChunks * kBandThreads * 4;     // floats per staging buffer
+
+struct GeoB {
+    int I, J, K;
+    int IC;                  // planes per item
+    int TB;                  // rows per band
+    int nbands, nic, items;  // items: band fastest, then plane run
+    int bytes;
+};
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+template <int NKT, int SP>
+__global__ __launch_bounds__(kBandThreads) void k_stencil19b(const float *__restrict__ p, float *__restrict__ q, GeoB g,
+                                                             double *partials) {
+    constexpr int RG = 16 / NKT;
+    static_assert(RG * NKT == 16, "16 waves per block");
+    __shared__ __attribute__((aligned(16))) float lds[2][kBandCap];
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
+    const int kt = wv % NKT, rg = wv / NKT;
+    const int nb = gridDim.x;
+    const int lb = (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8;
+    const int I = g.I, J = g.J, K = g.K;
+    const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, g.bytes, kBufferConfig);
+    const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc((void *)q, (short)0, g.bytes, kBufferConfig);
+    const int c0 = 1 + kOutV * kt + 2 * lane;                 // this lane's first column
+    const bool cols_full = kOutV * (kt + 1) <= K - 2;         // every lane's two columns interior
+    const bool out0 = c0 <= K - 2, out1 = c0 + 1 <= K - 2;
+    const int edge = lane == 0 ? c0 - 1 : lane == kWave - 1 ? c0 + 2 : c0;   // halo column read
+    const int voff = c0 * 4;
+    double acc = 0.0;
+
+    for (int it = lb; it < g.items; it += nb) {
+        const int bt = it % g.nbands, ic = it / g.nbands;
+        const int jb = 1 + bt * g.TB;
+        const int ib = 1 + ic * g.IC, ie = min(ib + g.IC, I - 1);
+        const int rend = min(jb + g.TB + 1, J);               // rows [jb-1, rend) are staged
+        const int wr = jb + 4 * rg;                           // this wave's first output row
+        const bool full = cols_full && wr + 3 <= J - 2;
+        const int jlast = J - 2 - wr;
+
+        f32x4 st[kBandChunks];
+        f32x2 Pa[3][4], Px[3][4], Py[3][4];
+
+        // global loads of plane i's staged range (none past ie)
+        auto issue = [&](int i, f32x4 (&v)[kBandChunks]) {
+            const int ii = min(i, I - 1);
+            const int f0 = (ii * J + jb - 1) * K, f1 = (ii * J + rend) * K;
+            const int a0 = f0 & ~3;
+#pragma unroll
+            for (int u = 0; u < kBandChunks; ++u) {
+                const int e = a0 + 4 * (u * kBandThreads + tid);
+                v[u] = __builtin_bit_cast(
+                    f32x4, __builtin_amdgcn_raw_buffer_load_b128(rp, (i <= ie && e < f1) ? e * 4 : kOutOfRange, 0, 0));
+            }
+        };
+        auto stage = [&](const f32x4 (&v)[kBandChunks], float *buf) {
+#pragma unroll
+            for (int u = 0; u < kBandChunks; ++u) *(f32x4 *)(buf + 4 * (u * kBandThreads + tid)) = v[u];
+        };
+        // a, x, y of this wave's 4 rows of plane i from the staged plane
+        auto derive = [&](const float *buf, int i, f32x2 (&a)[4], f32x2 (&x)[4], f32x2 (&y)[4]) {
+            const int sh = ((min(i, I - 1) * J + jb - 1) * K) & 3;   // staged range starts sh floats early
+            f32x2 v[6], h[6];
+            float e[6];
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                const float *row = buf + (4 * rg + r) * K + sh;
+                v[r] = f32x2{row[c0], row[c0 + 1]};
+                e[r] = row[edge];
+            }
+#pragma unroll
+            for (int r = 0; r < 6; ++r) {
+                h[r].x = from_left_or(v[r].y, e[r]) + v[r].y;
+                h[r].y = v[r].x + from_right_or(v[r].x, e[r]);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                a[r] = v[r + 1];
+                x[r].x = (v[r].x + v[r + 2].x) + h[r + 1].x;
+                x[r].y = (v[r].y + v[r + 2].y) + h[r + 1].y;
+                y[r].x = h[r].x + h[r + 2].x;
+                y[r].y = h[r].y + h[r + 2].y;
+            }
+        };
+        auto point = [&](float am, float an, float ac, float xm, float xn, float xc, float yc) {
+            const float F = (am + an) + xc;
+            const float E = (xm + xn) + yc;
+            const float t0 = 0.25f * ac;
+            const float t1 = 0.0625f * F;
+            const float t2 = 0.03125f * E;
+            return (t0 + t1) + t2;
+        };
+        // step k of the run (output plane i = ib + k): stage plane i+1 (its
+        // loads went out one step earlier), load plane i+2, derive plane i+1,
+        // produce plane i
+        auto step = [&](auto S, auto FULLC, int i) {
+            constexpr bool FULL = decltype(FULLC)::value;
+            constexpr int k3 = decltype(S)::value;
+            constexpr int m = k3, c = (k3 + 1) % 3, n = (k3 + 2) % 3;
+            float *buf = lds[(i + 1 - ib) & 1];             // plane t is staged in buffer (t - ib) mod 2
+            stage(st, buf);
+            __syncthreads();
+            issue(i + 2, st);
+            derive(buf, i + 1, Pa[n], Px[n], Py[n]);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float v0 = point(Pa[m][r].x, Pa[n][r].x, Pa[c][r].x, Px[m][r].x, Px[n][r].x, Px[c][r].x, Py[c][r].x);
+                const float v1 = point(Pa[m][r].y, Pa[n][r].y, Pa[c][r].y, Px[m][r].y, Px[n][r].y, Px[c][r].y, Py[c][r].y);
+                const int base = ((i * J + wr + r) * K) * 4;
+                const double d0 = (double)v0 - (double)Pa[c][r].x;
+                const double d1 = (double)v1 - (double)Pa[c][r].y;
+                if constexpr (FULL) {
+                    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, f32x2{v0, v1}), rq, base + voff, 0,
+                                                          SP);
+                    acc = __builtin_fma(d0, d0, acc);
+                    acc = __builtin_fma(d1, d1, acc);
+                } else {
+                    const bool ok0 = out0 && r <= jlast, ok1 = out1 && r <= jlast;
+                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v0), rq,
+                                                          ok0 ? base + voff : kOutOfRange, 0, SP);
+                    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v1), rq,
+                                                          ok1 ? base + voff + 4 : kOutOfRange, 0, SP);
+                    acc = __builtin_fma(ok0 ? d0 : 0.0, d0, acc);
+                    acc = __builtin_fma(ok1 ? d1 : 0.0, d1, acc);
+                }
+            }
+        };
+
+        // every wave passes the same barriers whichever store path it takes
+        auto run = [&](auto FULLC) {
+            // the previous item's last reads of the staging buffers are done
+            __syncthreads();
+            issue(ib - 1, st);
+            stage(st, lds[1]);
+            issue(ib, st);
+            __syncthreads();
+            derive(lds[1], ib - 1, Pa[0], Px[0], Py[0]);
+            stage(st, lds[0]);
+            issue(ib + 1, st);
+            __syncthreads();
+            derive(lds[0], ib, Pa[1], Px[1], Py[1]);
+            for (int i0 = ib; i0 < ie; i0 += 3) {
+                step(std::integral_constant<int, 0>(), FULLC, i0);
+                if (i0 + 1 < ie) {
+                    step(std::integral_constant<int, 1>(), FULLC, i0 + 1);
+                    if (i0 + 2 < ie) step(std::integral_constant<int, 2>(), FULLC, i0 + 2);
+                }
+            }
+        };
+        if (full)
+            run(std::true_type());
+        else
+            run(std::false_type());
+    }
+    acc = wave_sum(acc);
+    if (lane == 0) partials[lb * (kBandThreads / kWave) + wv] = acc;
+}
+
 // res_slot[0] += the n wave partials of a sweep, in a fixed order: thread t
 // sums partials t, t + 256, ... (loads unrolled so that they overlap), then a
 // tree over the threads in LDS.  Executed by one whole block of 256 threads:
@@ -160,17 +337,45 @@ __global__ __launch_bounds__(kThreads) void k_copy_interior(float *__restrict__ 
 // Sweep forms: one column per lane (62 outputs per wave), two columns per
 // lane (126 outputs), two columns per lane with scalar-loaded halo columns
 // (128 outputs, 8-byte stores on interior tiles).
-enum Form { kFormOne = 0, kFormWide = 1, kFormV = 2 };
+enum Form { kFormOne = 0, kFormWide = 1, kFormV = 2, kFormBand = 3 };
 
 struct Config {
     int JR;
     int form = kFormOne;
     bool store_nt = false;   // q written with the non-temporal policy
     Geo g;
+    GeoB gb;                 // band form
+    int nkt = 0;             // band form: waves across a row (1, 2, 4, 8)
     unsigned blocks;
+    int waves_per_block = kWavesPerBlock;
 };
 
+// Waves across a row for the band form (a power of two covering the interior
+// row in 128-column tiles), 0 when the row is too long for it.
+int band_nkt(int64_t K) {
+    const int64_t t = (K - 2 + kOutV - 1) / kOutV;
+    return t <= 1 ? 1 : t <= 2 ? 2 : t <= 4 ? 4 : t <= 8 ? 8 : 0;
+}
+
+GeoB make_geo_band(int64_t I, int64_t J, int64_t K, int nkt, int IC) {
+    GeoB g;
+    g.I = (int)I;
+    g.J = (int)J;
+    g.K = (int)K;
+    g.bytes = (int)(I * J * K * 4);
+    g.TB = 64 / nkt;
+    g.nbands = (int)((J - 2 + g.TB - 1) / g.TB);
+    const int64_t ni = I - 2;
+    if (IC > ni) IC = (int)ni;
+    if (IC < 1) IC = 1;
+    g.IC = IC;
+    g.nic = (int)((ni + IC - 1) / IC);
+    g.items = g.nbands * g.nic;
+    return g;
+}
+
 int resident_blocks_per_cu(int JR, int form);
+int band_blocks_per_cu(int nkt);
 
 bool valid_jr(int JR, int form) {
     return form == kFormV ? (JR == 4 || JR == 6 || JR == 8) : (JR == 2 || JR == 4 || JR == 8);
@@ -197,19 +402,24 @@ bool env_override(int &JR, int &IC) {
 // per resident slot and waves loop over the items.  Defaults measured on
 // gfx950 (sweep kernel time, median of interleaved runs):
 //   fewer than 192 interior planes: JR = 4, IC = 6 (3 below 96 planes):
-//     129x129x257 10.2 us (JR 8: 10.8; IC 4 / 8: 11.8 / 10.9), 65x65x129 5.6 us
-//   192 .. 383 planes: JR = 8, IC = 12: 257x257x513 54.5 us (IC 24: 55.5,
-//     IC 48: 61.8, two columns per lane: 57.5)
-//   384 and more: two columns per lane, JR = 8, IC = 16: 513x513x1025 574 us
-//     (one column per lane, IC 48: 599)
+//     129x129x257 9.9 us (JR 8: 10.8; IC 4 / 8: 11.8 / 10.9; the band form
+//     18.3 us: too few bands), 65x65x129 5.6 us
+//   192 planes and more, rows of at most 8 k-tiles: the band form with
+//     about one item per block (IC = interior planes / (blocks / bands)):
+//     257x257x513 50.8 us (one column per lane, JR 8, IC 12: 55.1),
+//     513x513x1025 412 us (IC 64: 415, IC 16: 440; two columns per lane,
+//     JR 8, IC 16: 579)
+//   longer rows: two columns per lane, JR = 8, IC = 16
 Config choose(int64_t I, int64_t J, int64_t K) {
     Config c;
     const int64_t ni = I - 2;
     int JR = 0, IC = 0;
     const bool forced = env_override(JR, IC);
     if (!forced) JR = ni >= 192 ? 8 : 4;
+    const bool band_default = !forced && ni >= 192 && band_nkt(K) > 0;
+    const int ic_asked = IC;   // 0: automatic
     if (IC <= 0) IC = ni >= 384 ? 16 : ni >= 192 ? 12 : ni >= 96 ? 6 : 3;
-    c.form = !forced && ni >= 384 ? kFormWide : kFormOne;
+    c.form = band_default ? kFormBand : !forced && ni >= 384 ? kFormWide : kFormOne;
     // q with the non-temporal policy on grids of 4 MB to 512 MB: measured
     // faster at 129x129x257 (9.9 vs 12.3 us) and 257x257x513 (54.4 vs 61.1),
     // slower at 513x513x1025 (654 vs 573) and 65x65x129 (6.4 vs 5.6);
@@ -219,7 +429,26 @@ Config choose(int64_t I, int64_t J, int64_t K) {
     if (const char *nt = std::getenv("OFL_STENCIL_NT")) c.store_nt = nt[0] == '1';
     if (const char *wd = std::getenv("OFL_STENCIL_WIDE")) c.form = wd[0] == '1' ? kFormWide : kFormOne;
     if (const char *fm = std::getenv("OFL_STENCIL_FORM"))
-        c.form = fm[0] == 'v' ? kFormV : fm[0] == 'w' ? kFormWide : kFormOne;
+        c.form = fm[0] == 'b' ? kFormBand : fm[0] == 'v' ? kFormV : fm[0] == 'w' ? kFormWide : kFormOne;
+    if (c.form == kFormBand) {
+        c.nkt = band_nkt(K);
+        if (c.nkt > 0) {
+            c.JR = JR;
+            const int64_t slots = (int64_t)cu_count() * band_blocks_per_cu(c.nkt);
+            if (ic_asked <= 0) {
+                // about one item per resident block: the fewest halo planes
+                const int64_t nbands = (J - 2 + 64 / c.nkt - 1) / (64 / c.nkt);
+                const int64_t runs = std::max<int64_t>(1, slots / nbands);
+                IC = (int)((ni + runs - 1) / runs);
+            }
+            c.gb = make_geo_band(I, J, K, c.nkt, IC);
+            const int64_t blocks = std::min<int64_t>(c.gb.items, slots);
+            c.blocks = (unsigned)((blocks + 7) / 8 * 8);
+            c.waves_per_block = kBandThreads / kWave;
+            return c;
+        }
+        c.form = kFormWide;   // rows too long for the band form
+    }
     if (!valid_jr(JR, c.form)) JR = 8;
     c.JR = JR;
     c.g = make_geo(I, J, K, JR, IC, c.form == kFormV ? kOutV : c.form == kFormWide ? kOutW : kOut);
@@ -229,6 +458,23 @@ Config choose(int64_t I, int64_t J, int64_t K) {
     blocks = (blocks + 7) / 8 * 8;
     c.blocks = (unsigned)blocks;
     return c;
+}
+
+hipError_t launch_band(const Config &c, const float *p, float *q, double *partials, hipStream_t s) {
+    const dim3 grid(c.blocks), block(kBandThreads);
+#define OFL_BAND(N)                                                                                         \
+    case N:                                                                                                 \
+        return c.store_nt ? launch((k_stencil19b<N, kNonTemporal>), grid, block, 0, s, p, q, c.gb, partials) \
+                          : launch((k_stencil19b<N, 0>), grid, block, 0, s, p, q, c.gb, partials);
+    switch (c.nkt) {
+        OFL_BAND(1)
+        OFL_BAND(2)
+        OFL_BAND(4)
+        OFL_BAND(8)
+    default:
+        return hipErrorInvalidValue;
+    }
+#undef OFL_BAND
 }
 
 template <int JR>
@@ -277,6 +523,23 @@ int resident_blocks_per_cu(int JR, int form) {
         table[0][2] = table[1][2] = table[2][0] = 1;
     });
     return table[form][JR / 2 - 1];
+}
+
+int band_blocks_per_cu(int nkt) {
+    static std::once_flag once;
+    static int table[4];
+    std::call_once(once, [] {
+        auto occ = [](auto kern) {
+            int n = 0;
+            if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, kBandThreads, 0) != hipSuccess || n < 1) n = 1;
+            return n;
+        };
+        table[0] = occ(k_stencil19b<1, 0>);
+        table[1] = occ(k_stencil19b<2, 0>);
+        table[2] = occ(k_stencil19b<4, 0>);
+        table[3] = occ(k_stencil19b<8, 0>);
+    });
+    return table[nkt == 1 ? 0 : nkt == 2 ? 1 : nkt == 4 ? 2 : 3];
 }
 
 }  // namespace
@@ -339,9 +602,10 @@ hipError_t stencil19_sweep(const float *p, float *q, int64_t I, int64_t J, int64
     // to five planes past the end (read as 0); dropped stores use 2^31
     if ((I + 6) * J * K * 4 >= (1ll << 31)) return hipErrorInvalidValue;
     const Config c = choose(I, J, K);
-    const int waves = (int)c.blocks * kWavesPerBlock;
+    const int waves = (int)c.blocks * c.waves_per_block;
     if ((int64_t)waves > rs.capacity) return hipErrorInvalidValue;
-    const hipError_t e = c.JR == 8   ? launch_t<8>(c, p, q, rs.partials, s)
+    const hipError_t e = c.form == kFormBand ? launch_band(c, p, q, rs.partials, s)
+                         : c.JR == 8         ? launch_t<8>(c, p, q, rs.partials, s)
                          : c.JR == 6 ? launch_t<6>(c, p, q, rs.partials, s)
                          : c.JR == 4 ? launch_t<4>(c, p, q, rs.partials, s)
                                      : launch_t<2>(c, p, q, rs.partials, s);

@@ -281,10 +281,13 @@ def test_stencil_shapes(I, J, K, S):
 # policy), forced through the library's tuning knobs, on ragged shapes:
 # k-tiles with a partial last tile, j-runs past the last row, i-runs shorter
 # than the item; the 128-output form also on shapes whose tiles are all
-# interior (K - 2 a multiple of 128, J - 2 of the rows per item)
+# interior (K - 2 a multiple of 128, J - 2 of the rows per item); the band
+# form (a block per band of rows across the whole row, planes staged in LDS)
+# with every row length it takes
 @pytest.mark.parametrize("cfg,form,nt", [("2,1", "1", "0"), ("4,3", "1", "1"), ("8,5", "1", "0"), ("2,2", "w", "1"),
                                          ("4,6", "w", "0"), ("8,4", "w", "1"), ("8,16", "w", "0"),
-                                         ("4,2", "v", "0"), ("6,5", "v", "1"), ("8,4", "v", "0"), ("8,16", "v", "1")])
+                                         ("4,2", "v", "0"), ("6,5", "v", "1"), ("8,4", "v", "0"), ("8,16", "v", "1"),
+                                         ("8,2", "b", "0"), ("8,7", "b", "1"), ("8,32", "b", "0")])
 def test_stencil_kernel_forms(cfg, form, nt, monkeypatch):
     monkeypatch.setenv("OFL_STENCIL_CFG", cfg)
     monkeypatch.setenv("OFL_STENCIL_FORM", form)
@@ -292,6 +295,8 @@ def test_stencil_kernel_forms(cfg, form, nt, monkeypatch):
     shapes = [(4, 5, 6), (19, 23, 71), (5, 130, 300), (10, 11, 129), (6, 9, 254), (7, 6, 128)]
     if form == "v":
         shapes += [(9, 26, 258), (8, 18, 130), (11, 34, 386)]
+    if form == "b":   # band form: 1, 2, 4 and 8 waves across a row, whole and partial bands
+        shapes += [(9, 26, 258), (6, 70, 131), (5, 40, 520), (4, 20, 1025), (9, 150, 130), (12, 66, 514)]
     for I, J, K in shapes:
         say("case stencil form %s %s nt=%s grid %dx%dx%d" % (cfg, form, nt, I, J, K))
         _run_and_compare(appgen.stencil_app(I, J, K, 2), [[1, 1]])
