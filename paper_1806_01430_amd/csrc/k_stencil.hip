@@ -3,15 +3,22 @@
 // and y are formed once per loaded plane and reused by the three output
 // planes that need them.
 //
-// Mapping (gfx950, wave64): a work item is 64 consecutive k (lanes 1..62
-// produce outputs, lanes 0 and 63 only supply the k-1 / k+1 neighbours), JR
-// consecutive rows j and a run of IC planes along i.  A wave marches along i
-// holding a, x, y of three planes in registers, with the next three planes
-// already in flight in a register ring: every element of p is loaded once per
-// work item (plus two halo rows and two halo planes), the k neighbours arrive
-// through DPP lane shifts, and no LDS is used.  Waves loop over work items
-// (grid sized to the resident wave slots, so there is no tail round); the
-// four waves of a block take neighbouring j-runs, sharing halo rows in L1.
+// Per-wave forms (gfx950, wave64): a work item is 64 consecutive k (lanes
+// 1..62 produce outputs, lanes 0 and 63 only supply the k-1 / k+1
+// neighbours; or two columns per lane), JR consecutive rows j and a run of IC
+// planes along i.  A wave marches along i holding a, x, y of three planes in
+// registers, with the next three planes already in flight in a register
+// ring: every element of p is loaded once per work item (plus two halo rows
+// and two halo planes), the k neighbours arrive through DPP lane shifts, and
+// no LDS is used.  Waves loop over work items (grid sized to the resident
+// wave slots, so there is no tail round).  These serve grids below 192
+// interior planes, where launches and latency, not bandwidth, set the time.
+//
+// Band form (k_stencil19b, grids of 192 and more interior planes): a block
+// owns a band of rows across the whole row; each plane's rows are staged in
+// LDS as one contiguous range with aligned 16-byte loads, which is what the
+// memory system serves near copy speed on rows of arbitrary alignment, and
+// the waves march along i as above.
 #include <hip/hip_runtime.h>
 
 #include <cstdio>
