@@ -295,8 +295,10 @@ def test_stencil_kernel_forms(cfg, form, nt, monkeypatch):
     shapes = [(4, 5, 6), (19, 23, 71), (5, 130, 300), (10, 11, 129), (6, 9, 254), (7, 6, 128)]
     if form == "v":
         shapes += [(9, 26, 258), (8, 18, 130), (11, 34, 386)]
-    if form == "b":   # band form: 1, 2, 4 and 8 waves across a row, whole and partial bands
-        shapes += [(9, 26, 258), (6, 70, 131), (5, 40, 520), (4, 20, 1025), (9, 150, 130), (12, 66, 514)]
+    if form == "b":   # band form: 1, 2, 4 and 8 waves across a row, whole and partial bands;
+        # rows longer than 8 tiles fall back to the two-columns form
+        shapes += [(9, 26, 258), (6, 70, 131), (5, 40, 520), (4, 20, 1025), (9, 150, 130), (12, 66, 514),
+                   (5, 9, 1100)]
     for I, J, K in shapes:
         say("case stencil form %s %s nt=%s grid %dx%dx%d" % (cfg, form, nt, I, J, K))
         _run_and_compare(appgen.stencil_app(I, J, K, 2), [[1, 1]])

@@ -350,3 +350,31 @@ def test_batch_run_checks_pointer_table():
     ptrs = (ctypes.c_void_p * 12)()
     assert ofl.lib().ofl_batch_run(b._h, ptrs, 12, None, ofl.BATCH_GROUPED, ctypes.byref(st)) == -8
     assert ofl.lib().ofl_batch_run(b._h, ptrs, 12, None, 7, ctypes.byref(st)) == -1
+
+
+def test_ga_study_statistics_on_a_table():
+    # the study's statistics on an injected landscape equal those recomputed
+    # from the oracle GA's trajectories (same seeds, same table)
+    from paper_1806_01430_amd import ga_study
+    a, seeds, runs = 5, 12, 4
+    table = workloads.time_table(a, 91, lo=0.01, hi=1.0)
+    status = [G.ST_OK] * (1 << a)
+    settings = [(16, 8, 0.9, 0.05, 0.5, 0.0), (4, 3, 0.9, 0.1, 1.0, 3.0)]
+    res = ga_study.study(a, table, status, settings, seeds, runs)
+    order = sorted(range(1 << a), key=lambda i: (table[i], i))
+    assert res["best_gene"] == [(order[0] >> i) & 1 for i in range(a)]
+    assert abs(res["exhaustive_search_s"] - runs * sum(table)) < 1e-9
+    for (M, T, Pc, Pm, p, dl), got in zip(settings, res["settings"]):
+        hits, ranks, measured, cost = 0, [], [], []
+        for seed in range(1, seeds + 1):
+            o = G.run_ga(a, M, T, G.table_evaluator(table), Pc=Pc, Pm=Pm, p=p, seed=seed, deadline_factor=dl)
+            g = G.gene_index(o["best_gene"])
+            hits += g == order[0]
+            ranks.append(order.index(g))
+            measured.append(o["n_measured"])
+            cost.append(sum(t if st == G.ST_TIMEOUT else runs * t for _, t, st in o["log"]))
+        assert got["p_best"] == hits / seeds
+        assert got["median_rank"] == float(np.median(ranks))
+        assert got["mean_measured"] == float(np.mean(measured))
+        assert abs(got["mean_search_s"] - float(np.mean(cost))) < 1e-9
+    assert "| 16 | 8 |" in ga_study.table(res)
