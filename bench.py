@@ -173,6 +173,26 @@ def run_kernels_large(args):
     avg = ms / n * 1e-3
     tf = 2.0 * N ** 3 / avg / 1e12
     out["gemm_f32_8192"] = {"avg_ms": avg * 1e3, "TFLOPs": tf, "frac_mfma": tf / FP32_MFMA_PEAK_TFLOPS}
+    del bufs, app
+    # element-wise nests, transpose, cast and sum of squares on 8192 x 8192
+    # (256 MB per FP32 matrix: HBM-bound); algorithmic bytes per element
+    R = C = 8192
+    app = ofl.App(json.dumps(appgen.ewise_app(R, C)), seed=1)
+    bufs = app.alloc_device_buffers("cuda:0")
+    gene = [1] * app.gene_len
+    app.run_pattern(gene, bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
+    app.set_kernel_timing(True)
+    for _ in range(3):
+        app.run_pattern(gene, bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
+    per_elem = {"init_uniform": 8, "add_scaled": 12, "transpose": 8, "avg2": 12, "copy": 8, "scale": 8,
+                "cast_bf16": 6, "sumsq": 4}
+    for op, b in per_elem.items():
+        n, ms = app.kernel_stats(op)
+        runs = 3
+        if n:
+            gbs = b * R * C * runs / (ms * 1e-3) / 1e9
+            out["ewise_8192_" + op] = {"launches_per_run": n // runs, "ms_per_run": ms / runs, "GBps": gbs,
+                                       "frac_hbm": gbs / HBM_PEAK_GBS}
     return out
 
 

@@ -71,9 +71,8 @@ struct ofl_batch {
     void *d_tables = nullptr;
     size_t tables_cap = 0;
     double *d_partials = nullptr;     // per sweep item (grouped) / per block (per-instance launches)
-    unsigned *d_counter = nullptr;
     int64_t partial_cap = 0;
-    void *d_scratch = nullptr;        // one allocation: partials + counter
+    void *d_scratch = nullptr;        // the reduction partials
     std::unique_ptr<BatchGraph> graph;
     hipStream_t capture_stream = nullptr;
     hipEvent_t ev[2] = {nullptr, nullptr};
@@ -336,7 +335,6 @@ int build_tables(ofl_batch *b, void *const *bufs) {
         if (e == hipSuccess) e = hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(e, "batch scratch init");
         b->d_partials = static_cast<double *>(b->d_scratch);
-        b->d_counter = reinterpret_cast<unsigned *>(static_cast<char *>(b->d_scratch) + (size_t)need * sizeof(double));
         b->partial_cap = need;
     }
     b->tab_bufs.assign(bufs, bufs + (size_t)b->inst.size() * nb);
@@ -407,7 +405,7 @@ hipError_t launch_single(ofl_batch *b, int i, int ni, const std::vector<int64_t>
     }
     case OP_STENCIL19: {
         const auto &d = ir.bufs[n.b[0]].dims;
-        k::ReduceScratch rs{b->d_partials, b->d_counter, b->partial_cap};
+        k::ReduceScratch rs{b->d_partials, b->partial_cap};
         *launches += 2;   // sweep + residual finish
         return k::stencil19(F(0), F(1), d[0], d[1], d[2],
                             reinterpret_cast<double *>(F(2)) + env[n.slot_repeat], rs, s);

@@ -1,5 +1,5 @@
-// Device helpers shared by the kernels: FP64 wave / block sums and the
-// deterministic "last block finishes" reduction.
+// Device helpers shared by the kernels: the counter-based uniform values, the
+// FP64 wave sum and the fixed-order sum of per-block partials.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,45 +34,35 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// Called by every thread of the block with its own partial.  Thread 0 of each
-// block publishes the block's sum; the block that completes last adds all
-// partials, in block order, to target[0] and returns the counter to zero.  The
-// combination order depends only on the grid, so results are reproducible.
-// Ordering: each block's counter increment is a release (its partial is
-// written back before the increment), and only the reading lanes of the last
-// block acquire, each with an acquire load of the counter (it reads the final
-// increment, which continues every block's release sequence).  An acquire in
-// every block would invalidate the L2 of its XCD once per block, evicting
-// lines that the blocks still running there are about to read.
-__device__ inline void reduce_finish(double v, double *partials, unsigned *counter, double *target) {
-    __shared__ double wsum[16];
-    __shared__ int last;
-    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
-    const int nw = (blockDim.x + kWave - 1) / kWave;
-    v = wave_sum(v);
-    if (lane == 0) wsum[w] = v;
-    __syncthreads();
-    const unsigned nb = gridDim.x * gridDim.y * gridDim.z;
-    if (threadIdx.x == 0) {
-        double t = 0.0;
-        for (int i = 0; i < nw; ++i) t += wsum[i];
-        const unsigned bid = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-        __hip_atomic_store(&partials[bid], t, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        last = (prev == nb - 1) ? 1 : 0;
+// slot[0] += partials[0] + ... + partials[n-1], summed in a fixed order by
+// one whole block of kOrderedSumThreads threads: thread t adds partials t,
+// t + 256, ... (loads unrolled so that they overlap), then a tree over the
+// threads in LDS.  The order depends only on n, so the result is
+// reproducible run to run.
+constexpr int kOrderedSumThreads = 256;
+
+__device__ inline void ordered_sum_into(const double *__restrict__ partials, int n, double *slot) {
+    __shared__ double t[kOrderedSumThreads];
+    const int tid = threadIdx.x;
+    double s = 0.0;
+    int i = tid;
+    for (; i + 3 * kOrderedSumThreads < n; i += 4 * kOrderedSumThreads) {
+        const double a = partials[i], b = partials[i + kOrderedSumThreads];
+        const double c = partials[i + 2 * kOrderedSumThreads], d = partials[i + 3 * kOrderedSumThreads];
+        s += a;
+        s += b;
+        s += c;
+        s += d;
     }
+    for (; i < n; i += kOrderedSumThreads) s += partials[i];
+    t[tid] = s;
     __syncthreads();
-    if (last && w == 0) {
-        (void)__hip_atomic_load(counter, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-        double s = 0.0;
-        for (unsigned i = lane; i < nb; i += kWave)
-            s += __hip_atomic_load(&partials[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        s = wave_sum(s);
-        if (lane == 0) {
-            target[0] = target[0] + s;
-            __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
+#pragma unroll
+    for (int h = kOrderedSumThreads / 2; h > 0; h >>= 1) {
+        if (tid < h) t[tid] += t[tid + h];
+        __syncthreads();
     }
+    if (tid == 0) slot[0] = slot[0] + t[0];
 }
 
 }  // namespace k

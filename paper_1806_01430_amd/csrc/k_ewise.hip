@@ -151,24 +151,50 @@ __global__ __launch_bounds__(kThreads) void k_transpose(const float *__restrict_
     }
 }
 
-__global__ __launch_bounds__(kThreads) void k_sumsq(const float *x, int64_t n, double *s_out, double *partials,
-                                                    unsigned *counter) {
+// s[0] += sum of x[e]^2 in FP64 (the FP32 values widened exactly).  The sum
+// kernel leaves one partial per block with a plain store (per thread in
+// element order, U loads of 16 bytes in flight; the waves of a block then in
+// wave order); k_sumsq_finish, launched next on the same stream, adds the
+// partials in a fixed order.  No atomics and no grid-wide release: a release
+// per block would write back the L2 of its XCD once per block.
+template <int U>
+__global__ __launch_bounds__(kThreads) void k_sumsq(const float *__restrict__ x, int64_t n, double *partials) {
+    __shared__ double wsum[kThreads / kWave];
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t n4 = n / 4;
+    const float4 *x4 = reinterpret_cast<const float4 *>(x);
     double acc = 0.0;
-    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n4; g += stride) {
-        const float4 v = reinterpret_cast<const float4 *>(x)[g];
-        const double a = v.x, b = v.y, c = v.z, d = v.w;
-        acc = acc + a * a;
-        acc = acc + b * b;
-        acc = acc + c * c;
-        acc = acc + d * d;
+    for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < n4; g += U * stride) {
+        float4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) v[u] = g + u * stride < n4 ? x4[g + u * stride] : float4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const double a = v[u].x, b = v[u].y, c = v[u].z, d = v[u].w;
+            acc = acc + a * a;
+            acc = acc + b * b;
+            acc = acc + c * c;
+            acc = acc + d * d;
+        }
     }
     if (blockIdx.x == 0 && (int)threadIdx.x < (int)(n - n4 * 4)) {
         const double a = x[n4 * 4 + threadIdx.x];
         acc = acc + a * a;
     }
-    reduce_finish(acc, partials, counter, s_out);
+    acc = wave_sum(acc);
+    const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+    if (lane == 0) wsum[w] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < kThreads / kWave; ++i) t += wsum[i];
+        partials[blockIdx.x] = t;
+    }
+}
+
+__global__ __launch_bounds__(kOrderedSumThreads) void k_sumsq_finish(const double *__restrict__ partials, int n,
+                                                                     double *s_out) {
+    ordered_sum_into(partials, n, s_out);
 }
 
 }  // namespace
@@ -224,12 +250,17 @@ hipError_t transpose(const float *X, float *T, int64_t R, int64_t Cc, hipStream_
     return launch(k_transpose, grid, dim3(kThreads), 0, s, X, T, R, Cc);
 }
 
-int64_t sumsq_partials(int64_t n) { return grid_for(n / 4 + 1, 8); }
+constexpr int kSumsqUnroll = 4;
+
+int64_t sumsq_partials(int64_t n) { return grid_for(n / 4 + 1, 2 * kSumsqUnroll); }
 
 hipError_t sumsq(const float *x, int64_t n, double *s_out, const ReduceScratch &rs, hipStream_t s) {
     const unsigned blocks = (unsigned)sumsq_partials(n);
     if ((int64_t)blocks > rs.capacity) return hipErrorInvalidValue;
-    return launch(k_sumsq, dim3(blocks), dim3(kThreads), 0, s, x, n, s_out, rs.partials, rs.counter);
+    const hipError_t e = launch(k_sumsq<kSumsqUnroll>, dim3(blocks), dim3(kThreads), 0, s, x, n, rs.partials);
+    if (e != hipSuccess) return e;
+    return launch(k_sumsq_finish, dim3(1), dim3(kOrderedSumThreads), 0, s, (const double *)rs.partials,
+                  (int)blocks, s_out);
 }
 
 }  // namespace k

@@ -282,40 +282,15 @@ __global__ __launch_bounds__(kBandThreads) void k_stencil19b(const float *__rest
     if (lane == 0) partials[lb * (kBandThreads / kWave) + wv] = acc;
 }
 
-// res_slot[0] += the n wave partials of a sweep, in a fixed order: thread t
-// sums partials t, t + 256, ... (loads unrolled so that they overlap), then a
-// tree over the threads in LDS.  Executed by one whole block of 256 threads:
-// k_residual_finish, or the extra block of an interior copy launched next.
-constexpr int kFinishThreads = 256;
+// res_slot[0] += the n wave partials of a sweep, in a fixed order
+// (ordered_sum_into), by one whole block of 256 threads: k_residual_finish,
+// or the extra block of an interior copy launched next.
+constexpr int kFinishThreads = kOrderedSumThreads;
 static_assert(kFinishThreads == kThreads, "the copy's extra block runs the finish");
-
-__device__ inline void finish_block(const double *__restrict__ partials, int n, double *res_slot) {
-    __shared__ double t[kFinishThreads];
-    const int tid = threadIdx.x;
-    double s = 0.0;
-    int i = tid;
-    for (; i + 3 * kFinishThreads < n; i += 4 * kFinishThreads) {
-        const double a = partials[i], b = partials[i + kFinishThreads];
-        const double c = partials[i + 2 * kFinishThreads], d = partials[i + 3 * kFinishThreads];
-        s += a;
-        s += b;
-        s += c;
-        s += d;
-    }
-    for (; i < n; i += kFinishThreads) s += partials[i];
-    t[tid] = s;
-    __syncthreads();
-#pragma unroll
-    for (int h = kFinishThreads / 2; h > 0; h >>= 1) {
-        if (tid < h) t[tid] += t[tid + h];
-        __syncthreads();
-    }
-    if (tid == 0) res_slot[0] = res_slot[0] + t[0];
-}
 
 __global__ __launch_bounds__(kFinishThreads) void k_residual_finish(const double *__restrict__ partials, int n,
                                                                     double *res_slot) {
-    finish_block(partials, n, res_slot);
+    ordered_sum_into(partials, n, res_slot);
 }
 
 // p[i][j][k] = q[i][j][k] on the interior: a wave copies ROWS consecutive
@@ -328,7 +303,7 @@ __global__ __launch_bounds__(kThreads) void k_copy_interior(float *__restrict__ 
                                                             int fin_n, double *fin_slot) {
     const int copy_blocks = (int)gridDim.x - (fin_n > 0 ? 1 : 0);
     if ((int)blockIdx.x >= copy_blocks) {
-        finish_block(fin_partials, fin_n, fin_slot);
+        ordered_sum_into(fin_partials, fin_n, fin_slot);
         return;
     }
     const int lane = threadIdx.x & (kWave - 1);

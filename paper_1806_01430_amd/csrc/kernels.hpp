@@ -9,11 +9,10 @@
 namespace ofl {
 namespace k {
 
-// Device scratch used by the reductions: per-block partial sums and a
-// completion counter that the last block returns to zero.
+// Device scratch used by the reductions: the per-block (or per-wave) partial
+// sums a reduction kernel leaves for the ordered finish launched after it.
 struct ReduceScratch {
     double *partials = nullptr;
-    unsigned *counter = nullptr;
     int64_t capacity = 0;   // number of partials
 };
 

@@ -99,7 +99,6 @@ struct ofl_app {
     int device = -1;
     std::vector<void *> dev_setup;           // device copies of sine set-up content
     double *d_partials = nullptr;
-    unsigned *d_counter = nullptr;
     int64_t partial_cap = 0;
     void *d_gemm_ws = nullptr;               // operand workspace of split-precision GEMM nests
     int64_t gemm_ws_bytes = 0;
@@ -237,7 +236,6 @@ int ensure_device(ofl_app *app) {
         app->gemm_ws_bytes = ws;
     }
     app->d_partials = static_cast<double *>(mem);
-    app->d_counter = reinterpret_cast<unsigned *>(static_cast<char *>(mem) + (size_t)cap * sizeof(double));
     app->partial_cap = cap;
     return OFL_OK;
 }
@@ -277,7 +275,7 @@ hipError_t launch_nest(ofl_app *app, const Nest &n, void *const *dev, const int6
     const AppIR &ir = app->ir;
     auto F = [&](int i) { return static_cast<float *>(dev[n.b[i]]); };
     auto cnt = [&](int i) { return ir.bufs[n.b[i]].count; };
-    k::ReduceScratch rs{app->d_partials, app->d_counter, app->partial_cap};
+    k::ReduceScratch rs{app->d_partials, app->partial_cap};
     hipError_t e = hipSuccess;
     switch (n.op) {
     case OP_INIT_UNIFORM:
@@ -327,6 +325,7 @@ hipError_t launch_nest(ofl_app *app, const Nest &n, void *const *dev, const int6
 int32_t kernel_launch_count(const AppIR &ir, const Nest &n) {
     if (n.op == OP_INIT_UNIFORM) return (int32_t)n.b.size();
     if (n.op == OP_CAST_BF16) return (int32_t)(n.b.size() / 2);
+    if (n.op == OP_SUMSQ) return 2;   // block partials + ordered finish
     if (n.op == OP_GEMM || n.op == OP_GEMM_BF16) {
         const auto &a = ir.bufs[n.b[0]].dims, &bb = ir.bufs[n.b[1]].dims;
         return k::gemm_launches(a[0], bb[1], a[1], gemm_variant(n));
