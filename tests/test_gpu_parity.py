@@ -370,7 +370,9 @@ def test_stencil_full_size_one_sweep(I, J, K):
 
 
 # ---------------------------------------------------------------- element-wise
-@pytest.mark.parametrize("R,C", [(1, 1), (3, 5), (64, 64), (65, 127), (1000, 333), (2048, 2048)])
+# (the transpose takes 16-byte accesses when both sides are multiples of 4)
+@pytest.mark.parametrize("R,C", [(1, 1), (3, 5), (4, 8), (64, 64), (65, 127), (68, 132), (1000, 333), (1000, 332),
+                                 (2048, 2048)])
 def test_ewise_transpose_cast_sumsq(R, C):
     _run_and_compare(appgen.ewise_app(R, C), [[1] * 8, [1, 0] * 4, [0, 1] * 4])
 
