@@ -80,9 +80,10 @@ enum {
     OFL_RUN_GRAPH = 4,       /* replay the run as HIP graphs captured once per
                                 (gene, policy, flags): a reset graph (untimed)
                                 and a run graph holding the copies, kernels and
-                                host nodes for the CPU nests; deadlines are not
-                                applied to graph runs.  Plans and results are
-                                those of the eager run. */
+                                host nodes for the CPU nests (led by one more
+                                host node that stamps the run's start);
+                                deadlines are not applied to single graph runs.
+                                Plans and results are those of the eager run. */
     OFL_RUN_BATCHED = 8,     /* population evaluation (ofl_eval_population,
                                 ofl_ga_run, ofl_ga_run_table) only: all
                                 uncached genes of a population / generation are
@@ -92,12 +93,17 @@ enum {
                                 graph, one synchronisation at the end; a gene's
                                 time is the median of its event intervals (GPU
                                 timeline, host nodes included).  Implies
-                                OFL_RUN_GRAPH.  Deadlines are applied to the
-                                measured times (a run over the limit gets
-                                OFL_ST_TIMEOUT at the limit) instead of cutting
-                                runs short; in the GA every gene of a
-                                generation gets the limit taken at the start of
-                                that generation. */
+                                OFL_RUN_GRAPH.  A deadline applies to the
+                                measured times (a median over the limit gets
+                                OFL_ST_TIMEOUT at the limit) and to the host
+                                nests: each run's graph stamps its start, and a
+                                host nest still running at start + limit stops
+                                (checked between its rows or planes, as in an
+                                eager run), which also makes that gene
+                                OFL_ST_TIMEOUT and skips the host nests of its
+                                remaining runs; GPU work is not cut.  In the GA
+                                every gene of a generation gets the limit taken
+                                at the start of that generation. */
     OFL_RUN_PROGRESS = 16    /* ofl_ga_run only: one line per generation on
                                 stderr (generation, best time so far, genes
                                 measured, wall time), for long searches */

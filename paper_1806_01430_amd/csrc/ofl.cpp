@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdio>
 #include <cstring>
@@ -53,10 +54,21 @@ bool timed_nest(const ofl_app *app, const Nest &n, int32_t *exec_count);
 
 // Host work recorded into a graph: one serial nest, or the restore of set-up
 // content into host copies.  They live as long as the graph that calls them.
+// Time limit of a captured run's host nests: the run graph's first node
+// stamps the start, every host nest of the run checks start + limit_s as an
+// eager run checks its deadline, and a nest that runs out sets `cut`.
+// limit_s <= 0: no limit.  Written by host callbacks, read by the thread that
+// submitted the graphs after it synchronised the stream.
+struct GraphClock {
+    std::chrono::steady_clock::time_point start;
+    double limit_s = 0.0;
+    std::atomic<bool> cut{false};
+};
 struct HostTask {
     ofl_app *app = nullptr;
     int nest = -1;
     std::vector<int64_t> env;
+    GraphClock *clock = nullptr;
 };
 struct HostRestore {
     ofl_app *app = nullptr;
@@ -70,6 +82,7 @@ struct GraphEntry {
     std::vector<char> host_written;
     std::vector<std::unique_ptr<HostTask>> tasks;
     std::unique_ptr<HostRestore> restore;
+    std::unique_ptr<GraphClock> clock;
     int32_t launches = 0, host_nests = 0;
     // with kernel timing: an event record node before and after every GPU
     // nest (nest index, start event, stop event)
@@ -573,9 +586,21 @@ RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *co
 // ------------------------------------------------------------ graph runs
 void host_task_cb(void *p) {
     const HostTask *t = static_cast<const HostTask *>(p);
-    Deadline none;
-    (void)run_host_nest(t->app->ir, t->app->ir.nests[t->nest], t->app->host, t->env.data(), t->app->seed, none);
+    // a gene already cut is a TIMEOUT whatever its later runs do: skip the
+    // host work of its remaining runs (their results are not used)
+    if (t->clock && t->clock->limit_s > 0.0 && t->clock->cut) return;
+    Deadline dl;
+    if (t->clock && t->clock->limit_s > 0.0) {
+        dl.active = true;
+        dl.until = t->clock->start + std::chrono::duration_cast<std::chrono::steady_clock::duration>(
+                                         std::chrono::duration<double>(t->clock->limit_s));
+    }
+    if (!run_host_nest(t->app->ir, t->app->ir.nests[t->nest], t->app->host, t->env.data(), t->app->seed, dl) &&
+        t->clock)
+        t->clock->cut = true;
 }
+
+void clock_start_cb(void *p) { static_cast<GraphClock *>(p)->start = std::chrono::steady_clock::now(); }
 
 void host_restore_cb(void *p) {
     const HostRestore *r = static_cast<const HostRestore *>(p);
@@ -677,6 +702,12 @@ int build_graphs(ofl_app *app, const std::vector<uint8_t> &placement, void *cons
 
     if ((rc = capture_begin(app)) != OFL_OK) return rc;
     e = hipSuccess;
+    // a run with host nests starts with a host node that stamps its start
+    // (the limit of a batched measurement applies to its host nests)
+    ge.clock.reset(new GraphClock());
+    const bool has_host = std::any_of(plan.steps.begin(), plan.steps.end(),
+                                      [](const Step &st) { return st.kind == ST_CPU; });
+    if (has_host) e = hipLaunchHostFunc(cs, clock_start_cb, ge.clock.get());
     k::ResidualFinish fin;
     int32_t exec_count[OP_COUNT] = {};
     for (const Step &st : plan.steps) {
@@ -715,6 +746,7 @@ int build_graphs(ofl_app *app, const std::vector<uint8_t> &placement, void *cons
             t->app = app;
             t->nest = st.idx;
             t->env.assign(plan.env.begin() + st.env, plan.env.begin() + st.env + ir.repeat_names.size());
+            t->clock = ge.clock.get();
             e = hipLaunchHostFunc(cs, host_task_cb, t.get());
             ge.tasks.push_back(std::move(t));
             ge.host_nests++;
@@ -887,6 +919,11 @@ int measure_batched(ofl_app *app, const std::vector<std::vector<uint8_t>> &place
         app->chain_events.push_back(e);
     }
     app->ran = false;
+    // the limit also cuts host nests short (counted from each run's start)
+    for (size_t g = 0; g < n; ++g) {
+        ge[g]->clock->limit_s = limit > 0 ? limit : 0.0;
+        ge[g]->clock->cut = false;
+    }
     hipError_t e = hipSuccess;
     for (int r = 0; r < warmup + reps && e == hipSuccess; ++r)
         for (size_t g = 0; g < n && e == hipSuccess; ++g) {
@@ -898,6 +935,11 @@ int measure_batched(ofl_app *app, const std::vector<std::vector<uint8_t>> &place
             if (e == hipSuccess && timed) e = hipEventRecord(app->chain_events[ev + 1], s);
         }
     if (e == hipSuccess) e = hipStreamSynchronize(s);
+    std::vector<char> cut(n);
+    for (size_t g = 0; g < n; ++g) {
+        cut[g] = ge[g]->clock->cut ? 1 : 0;
+        ge[g]->clock->limit_s = 0.0;   // later graph runs are not limited
+    }
     if (e != hipSuccess) return hip_fail(e, "batched evaluation");
     for (size_t g = 0; g < n; ++g) {
         std::vector<double> ts;
@@ -909,7 +951,7 @@ int measure_batched(ofl_app *app, const std::vector<std::vector<uint8_t>> &place
             ts.push_back(1e-3 * ms);
         }
         Measurement m{median_of(ts), OFL_ST_OK};
-        if (limit > 0 && m.t > limit) {
+        if (limit > 0 && (m.t > limit || cut[g])) {   // over the limit, or host work cut short
             m.t = limit;
             m.status = OFL_ST_TIMEOUT;
         }

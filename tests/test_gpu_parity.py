@@ -436,6 +436,30 @@ def test_eval_population_and_ga_tiny():
     say("GA best gene", res["best_gene"], "exhaustive best", genes[best_idx], "rank", rank)
 
 
+def test_batched_deadline_cuts_host_nests():
+    # in one batched submission the limit stops host nests at the limit: the
+    # all-CPU gene of the medium application (seconds of serial work) ends as
+    # a TIMEOUT after about the limit per run, not after its full run time
+    import time
+    doc = workloads.app_doc("medium")
+    app = ofl.App(json.dumps(doc))
+    bufs = app.alloc_device_buffers()
+    say("case batched deadline, medium all-CPU and all-GPU genes")
+    app.eval_population([[1] * 10], bufs, reps=1, warmup=0, flags=ofl.BATCHED)   # capture, warm
+    t0 = time.perf_counter()
+    t, s = app.eval_population([[0] * 10, [1] * 10], bufs, reps=3, warmup=1, flags=ofl.BATCHED, deadline_s=0.05)
+    wall = time.perf_counter() - t0
+    assert list(s) == [ofl.ST_TIMEOUT, ofl.ST_OK]
+    assert t[0] == 0.05 and 0 < t[1] < 0.05
+    assert wall < 2.0, wall   # four runs of ~1.5 s each without the cut
+    # later runs are not limited: the all-CPU gene completes and matches the oracle
+    o = ir.load(doc)
+    o32, o64 = parity.oracle_outputs(o, 1)
+    st = app.run_pattern([0] * 10, bufs, flags=ofl.GRAPH)
+    assert st["status"] == ofl.ST_OK
+    assert not parity.compare(o, app.read_all(), o32, o64, rel_gemm=parity.rel_gemm_for(o, ()))
+
+
 def test_ga_timeout_and_progress_lines(capfd):
     # an absolute timeout below the all-CPU gene's time cuts that run off
     # (TIMEOUT, fitness 0); the progress flag prints one line per generation
