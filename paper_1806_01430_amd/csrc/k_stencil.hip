@@ -80,31 +80,6 @@ __global__ __launch_bounds__(kThreads) void k_stencil19w(const float *__restrict
     if (lane == 0) partials[lb * kWavesPerBlock + wib] = acc;
 }
 
-// The sweep with 128 output columns per wave (stencil_item_v): items whose
-// tile lies wholly inside the interior take the mask-free path.
-template <int JR, int SP>
-__global__ __launch_bounds__(kThreads) void k_stencil19v(const float *__restrict__ p, float *__restrict__ q, Geo g,
-                                                         double *partials) {
-    const int lane = threadIdx.x & (kWave - 1);
-    const int nb = gridDim.x;
-    const int lb = (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8;
-    const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
-    const int nwaves = nb * kWavesPerBlock;
-    const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, g.bytes, kBufferConfig);
-    const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc((void *)q, (short)0, g.bytes, kBufferConfig);
-    const int nkt_full = (g.K - 2) / kOutV, njt_full = (g.J - 2) / JR;
-    double acc = 0.0;
-    for (int w = lb * kWavesPerBlock + wib; w < g.items; w += nwaves) {
-        const int kt = w % g.nkt, jt = (w / g.nkt) % g.njt;
-        if (kt < nkt_full && jt < njt_full)
-            acc = stencil_item_v<JR, true, SP>(rp, rq, g, w, lane, acc);
-        else
-            acc = stencil_item_v<JR, false, SP>(rp, rq, g, w, lane, acc);
-    }
-    acc = wave_sum(acc);
-    if (lane == 0) partials[lb * kWavesPerBlock + wib] = acc;
-}
-
 // Band sweep for grids whose interior row spans at most 8 k-tiles of 128
 // columns.  A block of 16 waves owns a band of TB = 64 / NKT rows covering
 // every column of the interior (NKT waves across a row, each 128 columns with
@@ -319,7 +294,7 @@ __global__ __launch_bounds__(kThreads) void k_copy_interior(float *__restrict__ 
 // Sweep forms: one column per lane (62 outputs per wave), two columns per
 // lane (126 outputs), two columns per lane with scalar-loaded halo columns
 // (128 outputs, 8-byte stores on interior tiles).
-enum Form { kFormOne = 0, kFormWide = 1, kFormV = 2, kFormBand = 3 };
+enum Form { kFormOne = 0, kFormWide = 1, kFormBand = 2 };
 
 struct Config {
     int JR;
@@ -359,22 +334,20 @@ GeoB make_geo_band(int64_t I, int64_t J, int64_t K, int nkt, int IC) {
 int resident_blocks_per_cu(int JR, int form);
 int band_blocks_per_cu(int nkt);
 
-bool valid_jr(int JR, int form) {
-    return form == kFormV ? (JR == 4 || JR == 6 || JR == 8) : (JR == 2 || JR == 4 || JR == 8);
-}
+bool valid_jr(int JR) { return JR == 2 || JR == 4 || JR == 8; }
 
 // Tuning knobs, used by tuning sweeps: OFL_STENCIL_CFG="JR,IC" overrides the
 // choice (JR rows per item, IC planes per work item, 0 = automatic) and then
 // selects one column per lane unless a form is named: OFL_STENCIL_WIDE=0/1
-// (one / two columns per lane) or OFL_STENCIL_FORM=1/w/v (one column, two
-// columns, two columns with 128 outputs per wave), the latter taking
-// precedence.  JR is one of 2, 4, 8 (forms 1 and w) or 4, 6, 8 (form v).
+// (one / two columns per lane) or OFL_STENCIL_FORM=1/w/b (one column, two
+// columns, band), the latter taking precedence.  JR is one of 2, 4, 8 (the
+// band form ignores it); IC = 0 keeps the automatic choice.
 bool env_override(int &JR, int &IC) {
     const char *s = std::getenv("OFL_STENCIL_CFG");
     if (!s) return false;
     int a, b;
     if (std::sscanf(s, "%d,%d", &a, &b) != 2) return false;
-    if (!((a == 2 || a == 4 || a == 6 || a == 8) && b >= 0)) return false;
+    if (!((a == 2 || a == 4 || a == 8) && b >= 0)) return false;
     JR = a;
     IC = b;
     return true;
@@ -411,7 +384,7 @@ Config choose(int64_t I, int64_t J, int64_t K) {
     if (const char *nt = std::getenv("OFL_STENCIL_NT")) c.store_nt = nt[0] == '1';
     if (const char *wd = std::getenv("OFL_STENCIL_WIDE")) c.form = wd[0] == '1' ? kFormWide : kFormOne;
     if (const char *fm = std::getenv("OFL_STENCIL_FORM"))
-        c.form = fm[0] == 'b' ? kFormBand : fm[0] == 'v' ? kFormV : fm[0] == 'w' ? kFormWide : kFormOne;
+        c.form = fm[0] == 'b' ? kFormBand : fm[0] == 'w' ? kFormWide : kFormOne;
     if (c.form == kFormBand) {
         c.nkt = band_nkt(K);
         if (c.nkt > 0) {
@@ -431,9 +404,9 @@ Config choose(int64_t I, int64_t J, int64_t K) {
         }
         c.form = kFormWide;   // rows too long for the band form
     }
-    if (!valid_jr(JR, c.form)) JR = 8;
+    if (!valid_jr(JR)) JR = 8;
     c.JR = JR;
-    c.g = make_geo(I, J, K, JR, IC, c.form == kFormV ? kOutV : c.form == kFormWide ? kOutW : kOut);
+    c.g = make_geo(I, J, K, JR, IC, c.form == kFormWide ? kOutW : kOut);
     const int64_t resident_blocks = (int64_t)cu_count() * resident_blocks_per_cu(JR, c.form);
     int64_t blocks = ((int64_t)c.g.items + kWavesPerBlock - 1) / kWavesPerBlock;
     if (blocks > resident_blocks) blocks = resident_blocks;
@@ -462,24 +435,12 @@ hipError_t launch_band(const Config &c, const float *p, float *q, double *partia
 template <int JR>
 hipError_t launch_t(const Config &c, const float *p, float *q, double *partials, hipStream_t s) {
     const dim3 grid(c.blocks), block(kThreads);
-    if (c.form == kFormV) {
-        if constexpr (JR == 2) {
-            return hipErrorInvalidValue;
-        } else {
-            if (c.store_nt) return launch((k_stencil19v<JR, kNonTemporal>), grid, block, 0, s, p, q, c.g, partials);
-            return launch((k_stencil19v<JR, 0>), grid, block, 0, s, p, q, c.g, partials);
-        }
+    if (c.form == kFormWide) {
+        if (c.store_nt) return launch((k_stencil19w<JR, kNonTemporal>), grid, block, 0, s, p, q, c.g, partials);
+        return launch((k_stencil19w<JR, 0>), grid, block, 0, s, p, q, c.g, partials);
     }
-    if constexpr (JR == 6) {
-        return hipErrorInvalidValue;
-    } else {
-        if (c.form == kFormWide) {
-            if (c.store_nt) return launch((k_stencil19w<JR, kNonTemporal>), grid, block, 0, s, p, q, c.g, partials);
-            return launch((k_stencil19w<JR, 0>), grid, block, 0, s, p, q, c.g, partials);
-        }
-        if (c.store_nt) return launch((k_stencil19<JR, kNonTemporal>), grid, block, 0, s, p, q, c.g, partials);
-        return launch((k_stencil19<JR, 0>), grid, block, 0, s, p, q, c.g, partials);
-    }
+    if (c.store_nt) return launch((k_stencil19<JR, kNonTemporal>), grid, block, 0, s, p, q, c.g, partials);
+    return launch((k_stencil19<JR, 0>), grid, block, 0, s, p, q, c.g, partials);
 }
 
 template <typename Kern>
@@ -491,20 +452,16 @@ int occupancy_of(Kern kern) {
 
 int resident_blocks_per_cu(int JR, int form) {
     static std::once_flag once;
-    static int table[3][4];   // [form][JR 2, 4, 6, 8]
+    static int table[2][3];   // [one column, two columns][JR 2, 4, 8]
     std::call_once(once, [] {
         table[0][0] = occupancy_of(k_stencil19<2, 0>);
         table[0][1] = occupancy_of(k_stencil19<4, 0>);
-        table[0][3] = occupancy_of(k_stencil19<8, 0>);
+        table[0][2] = occupancy_of(k_stencil19<8, 0>);
         table[1][0] = occupancy_of(k_stencil19w<2, 0>);
         table[1][1] = occupancy_of(k_stencil19w<4, 0>);
-        table[1][3] = occupancy_of(k_stencil19w<8, 0>);
-        table[2][1] = occupancy_of(k_stencil19v<4, 0>);
-        table[2][2] = occupancy_of(k_stencil19v<6, 0>);
-        table[2][3] = occupancy_of(k_stencil19v<8, 0>);
-        table[0][2] = table[1][2] = table[2][0] = 1;
+        table[1][2] = occupancy_of(k_stencil19w<8, 0>);
     });
-    return table[form][JR / 2 - 1];
+    return table[form == kFormWide ? 1 : 0][JR == 2 ? 0 : JR == 4 ? 1 : 2];
 }
 
 int band_blocks_per_cu(int nkt) {
@@ -588,8 +545,7 @@ hipError_t stencil19_sweep(const float *p, float *q, int64_t I, int64_t J, int64
     if ((int64_t)waves > rs.capacity) return hipErrorInvalidValue;
     const hipError_t e = c.form == kFormBand ? launch_band(c, p, q, rs.partials, s)
                          : c.JR == 8         ? launch_t<8>(c, p, q, rs.partials, s)
-                         : c.JR == 6 ? launch_t<6>(c, p, q, rs.partials, s)
-                         : c.JR == 4 ? launch_t<4>(c, p, q, rs.partials, s)
+                         : c.JR == 4         ? launch_t<4>(c, p, q, rs.partials, s)
                                      : launch_t<2>(c, p, q, rs.partials, s);
     if (e != hipSuccess) return e;
     fin = ResidualFinish{rs.partials, waves, res_slot};

@@ -276,154 +276,18 @@ __device__ inline double stencil_item_w(__amdgpu_buffer_rsrc_t rp, __amdgpu_buff
     return acc;
 }
 
-// The sweep with two consecutive k per lane and all 128 columns of a wave
-// producing output: the tile of k-tile kt is columns k0 .. k0+127 with
-// k0 = 1 + 128 kt.  The two halo columns k0-1 and k0+128 of the R loaded rows
-// of a plane arrive with one extra 4-byte load per plane (lane r < R holds row
-// r's left halo, lane 32 + r its right halo) and enter lane 0 / lane 63 as
-// the value a DPP shift leaves in the lane that has no source.  A row of
-// K = 1025 is thus 8 tiles (the 126-column form needs 9).  FULL items (every
-// column and row of the tile interior) store each lane's two results with one
-// 8-byte store and carry no per-lane masks; other items mask per lane and
-// store 4 bytes at a time.  Plane runs end with up to two steps behind
-// wave-uniform branches, so no step is masked.  Per point the arithmetic is
-// that of stencil_item, in the same order.
+// Columns per wave in the band form (two per lane), and DPP wave shifts
+// whose lane without a source keeps `edge` (the band form's halo columns).
 constexpr int kOutV = 128;
 
-// DPP wave shifts whose lane without a source keeps `edge`.
 __device__ inline float from_left_or(float v, float edge) {
     return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x138, 0xF, 0xF, false));
 }
 __device__ inline float from_right_or(float v, float edge) {
     return __int_as_float(__builtin_amdgcn_update_dpp(__float_as_int(edge), __float_as_int(v), 0x130, 0xF, 0xF, false));
 }
-__device__ inline float lane_value(float v, int l) {
-    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
-}
 
 typedef unsigned u32x2 __attribute__((ext_vector_type(2)));
-
-template <int JR, bool FULL, int STORE_POLICY = 0>
-__device__ inline double stencil_item_v(__amdgpu_buffer_rsrc_t rp, __amdgpu_buffer_rsrc_t rq, const Geo &g, int w,
-                                        int lane, double acc) {
-    constexpr int R = JR + 2;
-    static_assert(R <= 32, "halo lanes");
-    const int I = g.I, J = g.J, K = g.K;
-    const int kt = w % g.nkt;
-    const int rest = w / g.nkt;
-    const int jt = rest % g.njt;
-    const int ic = rest / g.njt;
-    const int k0 = 1 + kt * kOutV;              // first output column of the tile
-    const int c0 = k0 + 2 * lane;               // this lane's first column
-    // general items: the 8-byte window stays inside the row (see
-    // stencil_item_w); FULL items have c0 + 1 <= K - 2 in every lane
-    const bool shifted = !FULL && c0 > K - 2;
-    const int kld = (FULL ? c0 : min(c0, K - 2)) * 4;
-    const bool out0 = FULL || c0 <= K - 2;
-    const bool out1 = FULL || c0 + 1 <= K - 2;
-    const int voff = c0 * 4;
-    const int jb = 1 + jt * JR;
-    const int ib = 1 + ic * g.IC;
-    const int ie = min(ib + g.IC, I - 1);
-    const int jlast = J - 2 - jb;
-    // the halo load of a plane: lane r < R reads column k0-1 of row r, lane
-    // 32 + r column min(k0+128, K-1) (inside the row) of row r; other lanes
-    // read nothing (offset past num_records)
-    const int hrow = lane & 31;
-    const bool hlive = hrow < R;
-    const int hoff = ((min(jb - 1 + hrow, J - 1)) * K + (lane < 32 ? k0 - 1 : min(k0 + kOutV, K - 1))) * 4;
-
-    f32x2 Pa[3][JR], Px[3][JR], Py[3][JR];
-    f32x2 ring[3][R];
-    float ringh[3];
-
-    // i < 0: no refill (every load dropped by the range check)
-    auto load = [&](int i, f32x2 (&v)[R], float &vh) {
-        const int ii = min(i, I - 1);
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            const int row = (ii * J + min(jb - 1 + r, J - 1)) * K;
-            const f32x2 t = buf_load2(rp, i < 0 ? kOutOfRange : row * 4 + kld);
-            v[r] = shifted ? f32x2{t.y, t.y} : t;
-        }
-        vh = buf_load(rp, (i < 0 || !hlive) ? kOutOfRange : ii * J * K * 4 + hoff);
-    };
-    auto derive = [&](const f32x2 (&v)[R], float vh, f32x2 (&a)[JR], f32x2 (&x)[JR], f32x2 (&y)[JR]) {
-        f32x2 h[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-            h[r].x = from_left_or(v[r].y, lane_value(vh, r)) + v[r].y;
-            h[r].y = v[r].x + from_right_or(v[r].x, lane_value(vh, 32 + r));
-        }
-#pragma unroll
-        for (int r = 0; r < JR; ++r) {
-            a[r] = v[r + 1];
-            x[r].x = (v[r].x + v[r + 2].x) + h[r + 1].x;
-            x[r].y = (v[r].y + v[r + 2].y) + h[r + 1].y;
-            y[r].x = h[r].x + h[r + 2].x;
-            y[r].y = h[r].y + h[r + 2].y;
-        }
-    };
-    auto point = [&](float am, float an, float ac, float xm, float xn, float xc, float yc) {
-        const float F = (am + an) + xc;
-        const float E = (xm + xn) + yc;
-        const float t0 = 0.25f * ac;
-        const float t1 = 0.0625f * F;
-        const float t2 = 0.03125f * E;
-        return (t0 + t1) + t2;
-    };
-    auto step = [&](auto S, int i) {
-        constexpr int s = decltype(S)::value;
-        constexpr int m = s, c = (s + 1) % 3, n = (s + 2) % 3;
-        __builtin_amdgcn_sched_barrier(0);
-        derive(ring[s], ringh[s], Pa[n], Px[n], Py[n]);
-        __builtin_amdgcn_sched_barrier(0);
-        load(i + 4 <= ie ? i + 4 : -1, ring[s], ringh[s]);
-#pragma unroll
-        for (int r = 0; r < JR; ++r) {
-            const float v0 = point(Pa[m][r].x, Pa[n][r].x, Pa[c][r].x, Px[m][r].x, Px[n][r].x, Px[c][r].x, Py[c][r].x);
-            const float v1 = point(Pa[m][r].y, Pa[n][r].y, Pa[c][r].y, Px[m][r].y, Px[n][r].y, Px[c][r].y, Py[c][r].y);
-            const int base = ((i * J + jb + r) * K) * 4;
-            const double d0 = (double)v0 - (double)Pa[c][r].x;
-            const double d1 = (double)v1 - (double)Pa[c][r].y;
-            if constexpr (FULL) {
-                __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, f32x2{v0, v1}), rq, base + voff, 0,
-                                                      STORE_POLICY);
-                acc = __builtin_fma(d0, d0, acc);
-                acc = __builtin_fma(d1, d1, acc);
-            } else {
-                const bool row_ok = r <= jlast;
-                const bool ok0 = out0 && row_ok, ok1 = out1 && row_ok;
-                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v0), rq,
-                                                      ok0 ? base + voff : kOutOfRange, 0, STORE_POLICY);
-                __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v1), rq,
-                                                      ok1 ? base + voff + 4 : kOutOfRange, 0, STORE_POLICY);
-                acc = __builtin_fma(ok0 ? d0 : 0.0, d0, acc);
-                acc = __builtin_fma(ok1 ? d1 : 0.0, d1, acc);
-            }
-        }
-    };
-
-    {
-        f32x2 r0[R], r1[R];
-        float h0, h1;
-        load(ib - 1, r0, h0);
-        load(ib, r1, h1);
-        load(ib + 1, ring[0], ringh[0]);
-        load(ib + 2 <= ie ? ib + 2 : -1, ring[1], ringh[1]);
-        load(ib + 3 <= ie ? ib + 3 : -1, ring[2], ringh[2]);
-        derive(r0, h0, Pa[0], Px[0], Py[0]);
-        derive(r1, h1, Pa[1], Px[1], Py[1]);
-    }
-    for (int i0 = ib; i0 < ie; i0 += 3) {
-        step(std::integral_constant<int, 0>(), i0);
-        if (i0 + 1 < ie) {
-            step(std::integral_constant<int, 1>(), i0 + 1);
-            if (i0 + 2 < ie) step(std::integral_constant<int, 2>(), i0 + 2);
-        }
-    }
-    return acc;
-}
 
 // Rows row0 .. row0+ROWS-1 (of the (I-2)(J-2) interior rows (i, j)) of the
 // interior copy p = q.  Each row splits into a head [lo, a0) and a tail

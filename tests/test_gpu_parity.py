@@ -276,25 +276,20 @@ def test_stencil_shapes(I, J, K, S):
     _run_and_compare(appgen.stencil_app(I, J, K, S), [[1, 1], [1, 0], [0, 1]])
 
 
-# every sweep kernel form (rows per item, planes per item; one column per
-# lane, two columns per lane with 126 or with 128 outputs per wave; store
-# policy), forced through the library's tuning knobs, on ragged shapes:
-# k-tiles with a partial last tile, j-runs past the last row, i-runs shorter
-# than the item; the 128-output form also on shapes whose tiles are all
-# interior (K - 2 a multiple of 128, J - 2 of the rows per item); the band
-# form (a block per band of rows across the whole row, planes staged in LDS)
-# with every row length it takes
+# every sweep kernel form (rows per item, planes per item; one or two columns
+# per lane; store policy), forced through the library's tuning knobs, on
+# ragged shapes: k-tiles with a partial last tile, j-runs past the last row,
+# i-runs shorter than the item; the band form (a block per band of rows
+# across the whole row, planes staged in LDS) with every row length it takes,
+# whole and partial bands, and its automatic plane runs (IC = 0)
 @pytest.mark.parametrize("cfg,form,nt", [("2,1", "1", "0"), ("4,3", "1", "1"), ("8,5", "1", "0"), ("2,2", "w", "1"),
                                          ("4,6", "w", "0"), ("8,4", "w", "1"), ("8,16", "w", "0"),
-                                         ("4,2", "v", "0"), ("6,5", "v", "1"), ("8,4", "v", "0"), ("8,16", "v", "1"),
-                                         ("8,2", "b", "0"), ("8,7", "b", "1"), ("8,32", "b", "0")])
+                                         ("8,2", "b", "0"), ("8,7", "b", "1"), ("8,32", "b", "0"), ("8,0", "b", "0")])
 def test_stencil_kernel_forms(cfg, form, nt, monkeypatch):
     monkeypatch.setenv("OFL_STENCIL_CFG", cfg)
     monkeypatch.setenv("OFL_STENCIL_FORM", form)
     monkeypatch.setenv("OFL_STENCIL_NT", nt)
     shapes = [(4, 5, 6), (19, 23, 71), (5, 130, 300), (10, 11, 129), (6, 9, 254), (7, 6, 128)]
-    if form == "v":
-        shapes += [(9, 26, 258), (8, 18, 130), (11, 34, 386)]
     if form == "b":   # band form: 1, 2, 4 and 8 waves across a row, whole and partial bands;
         # rows longer than 8 tiles fall back to the two-columns form
         shapes += [(9, 26, 258), (6, 70, 131), (5, 40, 520), (4, 20, 1025), (9, 150, 130), (12, 66, 514),
