@@ -186,6 +186,22 @@ def app_path(name):
     return os.path.join(APPS_DIR, name + ".json")
 
 
+def app_doc(app, sets=()):
+    """Application description (a dict) from a name under apps/, a JSON file
+    or a C source (parsed by cfront), with NAME=VALUE parameter overrides."""
+    import json
+    if app.endswith(".c"):
+        from .cfront import load
+        doc = load(app)
+    else:
+        with open(app if app.endswith(".json") else app_path(app)) as f:
+            doc = json.load(f)
+    for kv in sets:
+        k, v = kv.split("=", 1)
+        doc["params"][k] = int(v)
+    return doc
+
+
 def ga_params(M=12, T=12, Pc=0.9, Pm=0.05, p=0.5, seed=1, reps=3, warmup=1, policy=RESIDENT, flags=0,
               deadline_factor=0.0, timeout_s=0.0):
     return GaParams(M, T, Pc, Pm, p, seed, reps, warmup, policy, flags, deadline_factor, timeout_s)
@@ -232,6 +248,8 @@ class App:
     def __init__(self, src, seed=1):
         L = lib()
         h = _P()
+        if isinstance(src, str) and src.endswith(".c"):
+            src = app_doc(src)
         if isinstance(src, dict):
             import json
             src = json.dumps(src)

@@ -1,0 +1,92 @@
+/* The medium application as C loop nests (the offloader's input; parsed by
+ * paper_1806_01430_amd.cfront into the same description as medium.json). */
+#define N 1024
+#define I 129
+#define J 129
+#define K 257
+#define SWEEPS 100
+#define MODE 1
+
+float A[N][N];
+float B[N][N];
+float C[N][N];          // ofl: output
+float T[N][N];          // ofl: output
+float S[N][N];          // ofl: output
+float v[N];             // ofl: output
+double s[1];            // ofl: output
+float p[I][J][K];       // ofl: output setup=sin mode=MODE
+float q[I][J][K];
+double res[SWEEPS];     // ofl: output
+float w[K];             // ofl: output
+float D[N][N];          // ofl: output
+
+/* random inputs: counter-based uniform streams 0 and 1 */
+for (int i = 0; i < N; i++)
+    for (int j = 0; j < N; j++) {
+        A[i][j] = u01(0, i, j);
+        B[i][j] = u01(1, i, j);
+    }
+
+/* C = A B */
+for (int i = 0; i < N; i++)
+    for (int j = 0; j < N; j++) {
+        C[i][j] = 0.0f;
+        for (int k = 0; k < N; k++)
+            C[i][j] += A[i][k] * B[k][j];
+    }
+
+for (int i = 0; i < N; i++)
+    for (int j = 0; j < N; j++)
+        C[i][j] = C[i][j] + 0.5f * A[i][j];
+
+for (int i = 0; i < N; i++)
+    for (int j = 0; j < N; j++)
+        T[j][i] = C[i][j];
+
+for (int i = 0; i < N; i++)
+    for (int j = 0; j < N; j++)
+        S[i][j] = 0.5f * (C[i][j] + T[i][j]);
+
+/* running sum down the first column: each step needs the previous one */
+for (int i = 1; i < N; i++)
+    v[i] = v[i - 1] + S[i][0];
+
+for (int i = 0; i < N; i++)
+    for (int j = 0; j < N; j++) {
+        double x = (double)S[i][j];
+        s[0] += x * x;
+    }
+
+/* SWEEPS weighted-Jacobi sweeps of the 19-point neighbourhood */
+for (int n = 0; n < SWEEPS; n++) {
+    for (int i = 1; i < I - 1; i++)
+        for (int j = 1; j < J - 1; j++)
+            for (int k = 1; k < K - 1; k++) {
+                float xm = (p[i - 1][j - 1][k] + p[i - 1][j + 1][k]) + (p[i - 1][j][k - 1] + p[i - 1][j][k + 1]);
+                float x0 = (p[i][j - 1][k] + p[i][j + 1][k]) + (p[i][j][k - 1] + p[i][j][k + 1]);
+                float xp = (p[i + 1][j - 1][k] + p[i + 1][j + 1][k]) + (p[i + 1][j][k - 1] + p[i + 1][j][k + 1]);
+                float y0 = (p[i][j - 1][k - 1] + p[i][j - 1][k + 1]) + (p[i][j + 1][k - 1] + p[i][j + 1][k + 1]);
+                float faces = (p[i - 1][j][k] + p[i + 1][j][k]) + x0;
+                float edges = (xm + xp) + y0;
+                float r = (0.25f * p[i][j][k] + 0.0625f * faces) + 0.03125f * edges;
+                q[i][j][k] = r;
+                double d = (double)r - (double)p[i][j][k];
+                res[n] += d * d;
+            }
+    for (int i = 1; i < I - 1; i++)
+        for (int j = 1; j < J - 1; j++)
+            for (int k = 1; k < K - 1; k++)
+                p[i][j][k] = q[i][j][k];
+}
+
+/* first-order filter along one grid line: loop-carried */
+for (int k = 1; k < K; k++)
+    w[k] = 0.5f * w[k - 1] + p[1][1][k];
+
+for (int i = 0; i < N; i++)
+    for (int j = 0; j < N; j++)
+        D[i][j] = C[i][j];
+
+for (int i = 0; i < N; i++)
+    for (int j = 0; j < N; j++)
+        D[i][j] = 2.0f * D[i][j];

@@ -1,0 +1,692 @@
+"""C front end: loop nests of a restricted C program -> the application IR.
+
+The paper's offloader parses the application's source, finds every for
+statement and checks each one for parallelisability (Sec. 4).  This module
+does the parsing step for a subset of C, so that an application can be given
+as source instead of the JSON IR:
+
+* ``#define NAME <int>`` -- parameters;
+* array declarations ``float|double|bf16 NAME[d0][d1]...;`` with an optional
+  trailing ``// ofl: output setup=sin mode=MODE`` annotation (the IR's
+  buffer metadata; default set-up content is zero);
+* statements: ``for (int v = lo; v < hi; v++) stmt``, blocks, assignments
+  ``ref (=|+=|-=|*=) expr;`` to array elements, local temporaries
+  ``float|double t = expr;``.  Expressions: numbers, parameters,
+  array references, locals, ``+ - * /``, parentheses, casts ``(double)x``
+  and calls ``f(...)``.
+
+Every top-level ``for`` is a loop nest: its loops are the for statements it
+contains, outermost first; a top-level for from 0 whose body holds only for
+statements, two or more of them, is a repeat block (the iterated sweep; the
+nests inside it are the candidates).  Accesses come from the array
+references, per element in statement order: an element written is "w", or
+"rw" when read before its first plain write; an element only read is "r"; a
+buffer touched only through ``+=`` at subscripts that use no loop variable of
+the nest is a sum reduction ("sum").  A call of anything but ``u01`` (the
+counter-based uniform value of an element) and ``bf16`` (the rounding cast)
+marks the nest as calling an external routine, which the dependence check
+(``ofl_app_load``) rejects, as it rejects loop-carried dependences.
+
+The body of each nest is bound to one of the library's operations by
+structural matching against C templates (below): temporaries are substituted
+and compound assignments expanded first, then the expression trees must agree
+node by node -- the same constants and grouping, operands in the same order
+except that one addition or product may have its two operands swapped (which
+rounds alike) -- because the library evaluates exactly that expression.  A
+nest matching no template (one that leaves its loop with ``break``, for one)
+is an error: the library could run it neither on the GPU nor on the CPU.
+"""
+import json
+import re
+
+# ------------------------------------------------------------------ lexing
+_TOKEN = re.compile(r"""
+    (?P<ws>\s+|//[^\n]*|/\*.*?\*/)
+  | (?P<num>\d+\.\d*(?:[eE][+-]?\d+)?f?|\d*\.\d+(?:[eE][+-]?\d+)?f?|\d+[eE][+-]?\d+f?|\d+f?)
+  | (?P<id>\$?[A-Za-z_][A-Za-z_0-9]*)
+  | (?P<op>\+\+|\+=|-=|\*=|/=|<=|[-+*/=<()\[\]{};,&@])
+""", re.X | re.S)
+
+TYPES = {"float": "f32", "double": "f64", "bf16": "bf16", "int": "int"}
+
+
+class CError(ValueError):
+    pass
+
+
+def _lex(src):
+    out, pos = [], 0
+    while pos < len(src):
+        m = _TOKEN.match(src, pos)
+        if not m:
+            raise CError("cannot read %r" % src[pos:pos + 20])
+        pos = m.end()
+        if m.lastgroup != "ws":
+            out.append(m.group(m.lastgroup))
+    return out
+
+
+# ------------------------------------------------------------------ parsing
+class _Parser:
+    def __init__(self, toks):
+        self.t, self.i = toks, 0
+
+    def peek(self, k=0):
+        return self.t[self.i + k] if self.i + k < len(self.t) else None
+
+    def take(self, want=None):
+        tok = self.peek()
+        if tok is None or (want is not None and tok != want):
+            raise CError("expected %r, found %r" % (want, tok))
+        self.i += 1
+        return tok
+
+    # expressions: ('num', v) ('var', n) ('ref', n, [subs]) ('bin', op, a, b)
+    # ('neg', a) ('call', n, [args]) ('cast', type, a) ('addr', a)
+    def expr(self):
+        e = self.term()
+        while self.peek() in ("+", "-"):
+            op = self.take()
+            e = ("bin", op, e, self.term())
+        return e
+
+    def term(self):
+        e = self.unary()
+        while self.peek() in ("*", "/"):
+            op = self.take()
+            e = ("bin", op, e, self.unary())
+        return e
+
+    def unary(self):
+        tok = self.peek()
+        if tok == "-":
+            self.take()
+            return ("neg", self.unary())
+        if tok == "&":
+            self.take()
+            return ("addr", self.unary())
+        if tok == "(" and self.peek(1) in TYPES and self.peek(2) == ")":
+            self.take("(")
+            ty = self.take()
+            self.take(")")
+            return ("cast", TYPES[ty], self.unary())
+        return self.primary()
+
+    def primary(self):
+        tok = self.take()
+        if tok == "(":
+            e = self.expr()
+            self.take(")")
+            return e
+        if re.match(r"[\d.]", tok):
+            return ("num", float(tok.rstrip("f")))
+        if not re.match(r"\$?[A-Za-z_]", tok):
+            raise CError("unexpected %r" % tok)
+        if self.peek() == "(":
+            self.take("(")
+            args = []
+            if self.peek() != ")":
+                args.append(self.expr())
+                while self.peek() == ",":
+                    self.take(",")
+                    args.append(self.expr())
+            self.take(")")
+            return ("call", tok, args)
+        subs = []
+        while self.peek() == "[":
+            self.take("[")
+            subs.append(self.expr())
+            self.take("]")
+        return ("ref", tok, subs) if subs else ("var", tok)
+
+    # statements: ('for', v, lo, hi, [body]) ('assign', ref, op, e)
+    # ('local', type, name, e) ('break',)
+    def stmt(self):
+        tok = self.peek()
+        if tok == "{":
+            self.take("{")
+            body = []
+            while self.peek() != "}":
+                body.extend(self.stmt())
+            self.take("}")
+            return body
+        if tok == "for":
+            self.take("for")
+            self.take("(")
+            if self.peek() == "int":
+                self.take()
+            v = self.take()
+            self.take("=")
+            lo = self.expr()
+            self.take(";")
+            if self.take() != v:
+                raise CError("loop condition must test %s" % v)
+            cmp = self.take()
+            hi = self.expr()
+            if cmp == "<=":
+                hi = ("bin", "+", hi, ("num", 1.0))
+            elif cmp != "<":
+                raise CError("loop condition must be < or <=")
+            self.take(";")
+            if self.peek() == "++":
+                self.take()
+                self.take(v)
+            else:
+                self.take(v)
+                if self.take() not in ("++",):
+                    raise CError("loops step by one (v++)")
+            self.take(")")
+            return [("for", v, lo, hi, self.stmt())]
+        if tok == "@":
+            self.take("@")
+            what = self.take()
+            val = self.take()
+            self.take(";")
+            return [("pragma", what, val)]
+        if tok == "break":
+            self.take()
+            self.take(";")
+            return [("break",)]
+        if tok in TYPES and self.peek(2) == "=":
+            ty = TYPES[self.take()]
+            name = self.take()
+            self.take("=")
+            e = self.expr()
+            self.take(";")
+            return [("local", ty, name, e)]
+        lhs = self.primary()
+        op = self.take()
+        if op not in ("=", "+=", "-=", "*=", "/="):
+            raise CError("expected an assignment, found %r" % op)
+        e = self.expr()
+        self.take(";")
+        return [("assign", lhs, op, e)]
+
+
+def _affine(e):
+    """An affine subscript / bound 'name + c', 'c' or 'name - c' -> IR text."""
+    if e[0] == "num":
+        return str(int(e[1]))
+    if e[0] == "var":
+        return e[1]
+    if e[0] == "bin" and e[1] in "+-" and e[3][0] == "num":
+        base = _affine(e[2])
+        c = int(e[3][1])
+        return "%s%s%d" % (base, e[1], c)
+    raise CError("subscript or bound is not 'name + constant': %r" % (e,))
+
+
+# ------------------------------------------------------------------ templates
+# Calls that are part of the language of the nests, not external routines:
+# u01(stream, i, j) is the counter-based uniform value of element (i, j) of a
+# random stream, bf16(x) the round-to-nearest-even bfloat16 of x.  Any other
+# call (lcg01(seed), a sequential generator, for one) is an external routine.
+PURE_CALLS = ("u01", "bf16")
+
+# One C snippet per operation, each the nest's definition in the evaluation
+# order the library follows; names beginning with $ are pattern variables
+# (buffers, parameters, constants).  Loop variables match any names, renamed
+# consistently.  Element-wise results are identical bits to this order; the
+# products (gemm) and the FP64 sums (sumsq, the sweep's residual) are the same
+# expressions summed in another order, within the library's stated bounds.
+TEMPLATES = [
+    ("gemm", """for (int i = 0; i < $M; i++) for (int j = 0; j < $N; j++) {
+                  $C[i][j] = 0.0f;
+                  for (int k = 0; k < $K; k++) $C[i][j] += $A[i][k] * $B[k][j]; }"""),
+    ("add_scaled", "for (int i = 0; i < $R; i++) for (int j = 0; j < $S; j++) "
+                   "$C[i][j] = $C[i][j] + $alpha * $A[i][j];"),
+    ("avg2", "for (int i = 0; i < $R; i++) for (int j = 0; j < $S; j++) $D[i][j] = 0.5f * ($X[i][j] + $Y[i][j]);"),
+    ("scale", "for (int i = 0; i < $R; i++) for (int j = 0; j < $S; j++) $D[i][j] = $beta * $D[i][j];"),
+    ("transpose", "for (int i = 0; i < $R; i++) for (int j = 0; j < $S; j++) $T[j][i] = $X[i][j];"),
+    ("copy", "for (int i = 0; i < $R; i++) for (int j = 0; j < $S; j++) $D[i][j] = $X[i][j];"),
+    ("sumsq", """for (int i = 0; i < $R; i++) for (int j = 0; j < $S; j++) {
+                   double v = (double)$X[i][j];
+                   $s[0] += v * v; }"""),
+    ("rec_prefix", "for (int i = 1; i < $N; i++) $v[i] = $v[i - 1] + $S[i][0];"),
+    ("rec_decay", "for (int k = 1; k < $K; k++) $w[k] = 0.5f * $w[k - 1] + $p[1][1][k];"),
+    ("lcg_fill", "for (int e = 0; e < $N; e++) $L[e] = lcg01($seed);"),
+    ("copy_interior", """for (int i = 1; i < $I - 1; i++) for (int j = 1; j < $J - 1; j++)
+                           for (int k = 1; k < $K - 1; k++) $p[i][j][k] = $q[i][j][k];"""),
+    ("stencil19", """for (int i = 1; i < $I - 1; i++) for (int j = 1; j < $J - 1; j++)
+                       for (int k = 1; k < $K - 1; k++) {
+        float xm = ($p[i - 1][j - 1][k] + $p[i - 1][j + 1][k]) + ($p[i - 1][j][k - 1] + $p[i - 1][j][k + 1]);
+        float x0 = ($p[i][j - 1][k] + $p[i][j + 1][k]) + ($p[i][j][k - 1] + $p[i][j][k + 1]);
+        float xp = ($p[i + 1][j - 1][k] + $p[i + 1][j + 1][k]) + ($p[i + 1][j][k - 1] + $p[i + 1][j][k + 1]);
+        float y0 = ($p[i][j - 1][k - 1] + $p[i][j - 1][k + 1]) + ($p[i][j + 1][k - 1] + $p[i][j + 1][k + 1]);
+        float faces = ($p[i - 1][j][k] + $p[i + 1][j][k]) + x0;
+        float edges = (xm + xp) + y0;
+        float v = (0.25f * $p[i][j][k] + 0.0625f * faces) + 0.03125f * edges;
+        $q[i][j][k] = v;
+        double d = (double)v - (double)$p[i][j][k];
+        $res[$n] += d * d; }"""),
+]
+
+
+def _parse_stmts(src):
+    p = _Parser(_lex(src))
+    out = []
+    while p.peek() is not None:
+        out.extend(p.stmt())
+    return out
+
+
+def _inline(stmts, env=None):
+    """Substitute local temporaries into later expressions; drop the locals.
+    Compound assignments become plain ones (a += b -> a = a + b)."""
+    env = dict(env or {})
+
+    def sub(e):
+        if e[0] == "var" and e[1] in env:
+            return env[e[1]]
+        if e[0] in ("ref",):
+            return ("ref", e[1], [sub(x) for x in e[2]])
+        if e[0] == "bin":
+            return ("bin", e[1], sub(e[2]), sub(e[3]))
+        if e[0] in ("neg", "addr"):
+            return (e[0], sub(e[1]))
+        if e[0] == "cast":
+            return ("cast", e[1], sub(e[2]))
+        if e[0] == "call":
+            return ("call", e[1], [sub(x) for x in e[2]])
+        return e
+
+    out = []
+    for s in stmts:
+        if s[0] == "local":
+            env[s[2]] = sub(s[3])
+        elif s[0] == "assign":
+            lhs, rhs = sub(s[1]), sub(s[3])
+            if s[2] != "=":
+                rhs = ("bin", s[2][0], lhs, rhs)
+            out.append(("assign", lhs, "=", rhs))
+        elif s[0] == "for":
+            out.append(("for", s[1], sub(s[2]), sub(s[3]), _inline(s[4], env)))
+        else:
+            out.append(s)
+    return out
+
+
+_TPL = [(op, _inline(_parse_stmts(src))[0]) for op, src in TEMPLATES]
+
+
+def _match(t, s, env):
+    """Structural match of template node t against source node s; pattern
+    variables and loop-variable renamings are recorded in env."""
+    if isinstance(t, list):
+        return isinstance(s, list) and len(t) == len(s) and all(_match(a, b, env) for a, b in zip(t, s))
+    if not isinstance(t, tuple):
+        return t == s
+    if not (isinstance(s, tuple) and s and s[0] == t[0] and len(s) == len(t)):
+        if t[0] == "var" and t[1].startswith("$") and isinstance(s, tuple):
+            pass            # a pattern variable matches any expression
+        else:
+            return False
+    kind = t[0]
+    if kind == "var":
+        if t[1].startswith("$"):
+            if t[1] in env:
+                return env[t[1]] == s
+            env[t[1]] = s
+            return True
+        if ("loop", t[1]) in env:
+            return s == ("var", env[("loop", t[1])])
+        return s == t
+    if kind == "ref":
+        return _match(("var", t[1]), ("var", s[1]), env) and _match(t[2], s[2], env)
+    if kind == "bin" and t[1] in "+*" and s[1] == t[1]:
+        # one addition or product may have its operands swapped (a + b and
+        # b + a round alike); grouping is kept, (a + b) + c != a + (b + c)
+        saved = dict(env)
+        if _match(t[2], s[2], env) and _match(t[3], s[3], env):
+            return True
+        env.clear()
+        env.update(saved)
+        return _match(t[2], s[3], env) and _match(t[3], s[2], env)
+    if kind == "for":
+        env[("loop", t[1])] = s[1]
+        return _match(t[2], s[2], env) and _match(t[3], s[3], env) and _match(t[4], s[4], env)
+    return all(_match(a, b, env) for a, b in zip(t[1:], s[1:]))
+
+
+def _literal(e, what):
+    if e[0] == "num":
+        return e[1]
+    if e[0] == "neg" and e[1][0] == "num":
+        return -e[1][1]
+    raise CError("%s must be a literal number" % what)
+
+
+def _bind(nest, dtypes):
+    """(op, args) of a nest, by template; CError if none matches."""
+    if _has_break(nest):
+        raise CError("the nest over %s leaves its loop early (break): no operation has such a body"
+                     % ", ".join(_loop_vars(nest)))
+    src = _inline([nest])[0]
+    for op, tpl in _TPL:
+        env = {}
+        if not _match(tpl, src, env):
+            continue
+        v = {k[1:]: e for k, e in env.items() if isinstance(k, str)}
+        buf = {k: e[1] for k, e in v.items() if e[0] == "var"}
+        if op == "gemm":
+            kinds = {dtypes.get(buf[x]) for x in "AB"}
+            if kinds == {"bf16"}:
+                op = "gemm_bf16"
+            elif kinds != {"f32"}:
+                raise CError("product operands are both float or both bf16")
+            return op, {"A": buf["A"], "B": buf["B"], "C": buf["C"]}
+        if op == "add_scaled":
+            return op, {"C": buf["C"], "A": buf["A"], "alpha": _literal(v["alpha"], "alpha")}
+        if op == "avg2":
+            return op, {"S": buf["D"], "X": buf["X"], "Y": buf["Y"]}
+        if op == "scale":
+            return op, {"D": buf["D"], "beta": _literal(v["beta"], "beta")}
+        if op == "copy":
+            return op, {"dst": buf["D"], "src": buf["X"]}
+        if op == "transpose":
+            return op, {"src": buf["X"], "dst": buf["T"]}
+        if op == "sumsq":
+            return op, {"x": buf["X"], "s": buf["s"]}
+        if op == "rec_prefix":
+            return op, {"v": buf["v"], "S": buf["S"]}
+        if op == "rec_decay":
+            return op, {"w": buf["w"], "p": buf["p"]}
+        if op == "lcg_fill":
+            return op, {"L": buf["L"], "seed32": int(_literal(v["seed"], "the generator seed"))}
+        if op == "copy_interior":
+            return op, {"dst": buf["p"], "src": buf["q"]}
+        if op == "stencil19":
+            return op, {"p": buf["p"], "q": buf["q"], "res": buf["res"], "slot": buf["n"]}
+    for bind in (_bind_init, _bind_cast):
+        got = bind(src)
+        if got:
+            return got
+    raise CError("no operation matches the body of the nest over %s" % ", ".join(_loop_vars(nest)))
+
+
+def _rows(src):
+    """Statements of a two-deep i, j nest and its loop variables, or None."""
+    if src[0] != "for" or len(src[4]) != 1 or src[4][0][0] != "for":
+        return None
+    i, j = src[1], src[4][0][1]
+    body = src[4][0][4]
+    if not body or any(s[0] != "assign" or s[1][0] != "ref" or s[1][2] != [("var", i), ("var", j)]
+                       for s in body):
+        return None
+    return i, j, body
+
+
+def _bind_init(src):
+    # X[i][j] = u01(stream, i, j); one statement per buffer
+    got = _rows(src)
+    if not got:
+        return None
+    i, j, body = got
+    outs, streams = [], []
+    for s in body:
+        e = s[3]
+        if not (e[0] == "call" and e[1] == "u01" and len(e[2]) == 3 and e[2][0][0] == "num"
+                and e[2][1] == ("var", i) and e[2][2] == ("var", j)):
+            return None
+        outs.append(s[1][1])
+        streams.append(int(e[2][0][1]))
+    return "init_uniform", {"out": outs, "streams": streams}
+
+
+def _bind_cast(src):
+    # Xb[i][j] = bf16(X[i][j]); one statement per buffer
+    got = _rows(src)
+    if not got:
+        return None
+    i, j, body = got
+    dst, srcs = [], []
+    for s in body:
+        e = s[3]
+        if not (e[0] == "call" and e[1] == "bf16" and len(e[2]) == 1 and e[2][0][0] == "ref"
+                and e[2][0][2] == [("var", i), ("var", j)]):
+            return None
+        dst.append(s[1][1])
+        srcs.append(e[2][0][1])
+    return "cast_bf16", {"dst": dst, "src": srcs}
+
+
+def _has_break(stmt):
+    return stmt[0] == "break" or (stmt[0] == "for" and any(_has_break(b) for b in stmt[4]))
+
+
+def _loop_vars(stmt):
+    out = []
+    if stmt[0] == "for":
+        out.append(stmt[1])
+        for s in stmt[4]:
+            for v in _loop_vars(s):
+                if v not in out:
+                    out.append(v)
+    return out
+
+
+# ------------------------------------------------------------------ nests -> IR
+def _loops(stmt):
+    out = []
+
+    def walk(s):
+        if s[0] != "for":
+            return
+        if s[1] not in [l[0] for l in out]:
+            out.append([s[1], _affine(s[2]), _affine(s[3])])
+        for b in s[4]:
+            walk(b)
+    walk(stmt)
+    return out
+
+
+def _accesses(stmt, loop_vars):
+    """IR access list of a nest: [buf, mode, subscript...] and its flags.
+
+    Per array element (buffer + subscripts), in statement order: a read before
+    any plain write of the same element is exposed; an element written and
+    exposed is "rw", written only "w", read only "r".  A buffer touched only
+    by += whose subscripts use none of the nest's loop variables is a sum
+    reduction ("sum")."""
+    events, flags = [], set()
+
+    def exprs(e):
+        if e[0] == "ref":
+            events.append(("r", e))
+            for x in e[2]:
+                exprs(x)
+        elif e[0] == "bin":
+            exprs(e[2])
+            exprs(e[3])
+        elif e[0] in ("neg", "addr"):
+            exprs(e[1])
+        elif e[0] == "cast":
+            exprs(e[2])
+        elif e[0] == "call":
+            if e[1] not in PURE_CALLS:
+                flags.add("opaque_call")
+            for x in e[2]:
+                exprs(x)
+
+    def walk(s):
+        if s[0] == "for":
+            for b in s[4]:
+                walk(b)
+        elif s[0] == "local":
+            exprs(s[3])
+        elif s[0] == "assign":
+            if s[1][0] != "ref":
+                raise CError("assignments go to array elements (a local is declared with its type)")
+            exprs(s[3])
+            for x in s[1][2]:
+                exprs(x)
+            events.append(("w" if s[2] == "=" else "u", s[1]))
+        elif s[0] == "break":
+            flags.add("early_exit")
+    walk(stmt)
+
+    def key(ref):
+        return ref[1], tuple(_affine(e) for e in ref[2])
+
+    sums = set()
+    for buf in {ref[1] for _, ref in events}:
+        mine = [(m, ref) for m, ref in events if ref[1] == buf]
+        if all(m == "u" for m, _ in mine) and not any(
+                _names_in(x) & set(loop_vars) for _, ref in mine for x in ref[2]):
+            sums.add(buf)
+    order, state = [], {}
+    for m, ref in events:
+        k = key(ref)
+        if k not in state:
+            order.append(k)
+            state[k] = {"w": False, "exposed": False}
+        st = state[k]
+        if m in ("r", "u") and not st["w"]:
+            st["exposed"] = True
+        if m in ("w", "u"):
+            st["w"] = True
+    writes = [k for k in order if state[k]["w"]]
+    reads = [k for k in order if not state[k]["w"]]
+    acc = []
+    for buf, subs in writes + reads:
+        st = state[(buf, subs)]
+        if buf in sums:
+            mode = "sum"
+        elif st["w"]:
+            mode = "rw" if st["exposed"] else "w"
+        else:
+            mode = "r"
+        acc.append([buf, mode] + list(subs))
+    return acc, sorted(flags)
+
+
+def _names_in(e):
+    out = set()
+    if e[0] == "var":
+        out.add(e[1])
+    elif e[0] == "ref":
+        for x in e[2]:
+            out |= _names_in(x)
+    elif e[0] == "bin":
+        out |= _names_in(e[2]) | _names_in(e[3])
+    return out
+
+
+_NEST_NAMES = {
+    "init_uniform": lambda a: "init_" + "".join(a["out"]),
+    "gemm": lambda a: "gemm_" + a["C"],
+    "gemm_bf16": lambda a: "gemm_bf16_" + a["C"],
+    "add_scaled": lambda a: "axpy_" + a["C"],
+    "avg2": lambda a: "avg_" + a["S"],
+    "scale": lambda a: "scale_" + a["D"],
+    "copy": lambda a: "copy_" + a["dst"],
+    "transpose": lambda a: "transpose_" + a["dst"],
+    "sumsq": lambda a: "sumsq_" + a["x"],
+    "cast_bf16": lambda a: "cast_bf16",
+    "rec_prefix": lambda a: "rec_prefix_" + a["v"],
+    "rec_decay": lambda a: "rec_decay_" + a["w"],
+    "lcg_fill": lambda a: "lcg_fill_" + a["L"],
+    "copy_interior": lambda a: "copy_interior",
+    "stencil19": lambda a: "stencil19",
+}
+
+_DEFINE = re.compile(r"\s*#define\s+([A-Za-z_]\w*)\s+(-?\d+)\s*$")
+_ARRAY = re.compile(r"\s*(float|double|bf16)\s+([A-Za-z_]\w*)((?:\s*\[[^\]]+\])+)\s*;\s*(?://\s*ofl:(.*))?$")
+_PRAGMA = re.compile(r"\s*#pragma\s+ofl\s+prec\((\w+)\)\s*$")
+
+
+def parse(src, name="app"):
+    """Application IR (a dict, as ofl_app_load_json takes it) of C source.
+
+    ``#pragma ofl prec(bf16x3|fp8x2|f32)`` on the line before a top-level
+    product nest sets the arithmetic of its offloaded form."""
+    params, buffers, program = {}, [], []
+    body_lines = []
+    for line in src.splitlines():
+        m = _DEFINE.match(line)
+        if m:
+            params[m.group(1)] = int(m.group(2))
+            continue
+        m = _ARRAY.match(line)
+        if m:
+            dims = [d.strip() for d in re.findall(r"\[([^\]]+)\]", m.group(3))]
+            b = {"name": m.group(2), "dtype": TYPES[m.group(1)], "dims": dims, "setup": "zero",
+                 "output": False}
+            for opt in (m.group(4) or "").split():
+                if opt == "output":
+                    b["output"] = True
+                elif opt.startswith("setup="):
+                    b["setup"] = opt.split("=", 1)[1]
+                elif opt.startswith("mode="):
+                    b["mode"] = opt.split("=", 1)[1]
+                else:
+                    raise CError("unknown buffer annotation %r" % opt)
+            buffers.append(b)
+            continue
+        m = _PRAGMA.match(line)
+        if m:
+            line = "@prec %s;" % m.group(1)
+        elif line.lstrip().startswith("#"):
+            raise CError("unsupported directive: %s" % line.strip())
+        body_lines.append(line)
+    dtypes = {b["name"]: b["dtype"] for b in buffers}
+    names_used = {}
+
+    def nest_ir(stmt, prec):
+        loops = _loops(stmt)
+        acc, flags = _accesses(stmt, [l[0] for l in loops])
+        op, args = _bind(stmt, dtypes)
+        if prec is not None:
+            if op != "gemm":
+                raise CError("prec applies to float products only")
+            args["prec"] = prec
+        base = _NEST_NAMES[op](args)
+        names_used[base] = names_used.get(base, 0) + 1
+        n = {"nest": base if names_used[base] == 1 else "%s_%d" % (base, names_used[base]), "op": op,
+             "args": args, "loops": loops, "access": acc}
+        if flags:
+            n["flags"] = flags
+        return n
+
+    prec = None
+    for stmt in _parse_stmts("\n".join(body_lines)):
+        if stmt[0] == "pragma":
+            prec = stmt[2]
+            continue
+        if stmt[0] != "for":
+            raise CError("top-level statements are for loops")
+        inner = stmt[4]
+        if len(inner) >= 2 and all(s[0] == "for" for s in inner):
+            if _affine(stmt[2]) != "0":
+                raise CError("a repeat loop counts from 0")
+            program.append({"repeat": _affine(stmt[3]), "var": stmt[1],
+                            "body": [nest_ir(s, None) for s in inner]})
+        else:
+            program.append(nest_ir(stmt, prec))
+        prec = None
+    return {"name": name, "params": params, "buffers": buffers, "program": program}
+
+
+def load(path):
+    """Application IR of a C source file (named after the file)."""
+    with open(path) as f:
+        return parse(f.read(), re.sub(r"\.c$", "", path.rsplit("/", 1)[-1]))
+
+
+def main(argv=None):
+    import argparse
+    import sys
+    ap = argparse.ArgumentParser(description="C loop nests -> application IR (JSON on stdout)")
+    ap.add_argument("source")
+    ap.add_argument("--name", default=None)
+    args = ap.parse_args(argv)
+    doc = load(args.source)
+    if args.name:
+        doc["name"] = args.name
+    json.dump(doc, sys.stdout, indent=1)
+    print()
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())

@@ -21,7 +21,7 @@ import time
 
 import numpy as np
 
-from . import App, app_path, ga_params, ga_run_table, RESIDENT, PER_REGION, SECTIONS, BATCHED
+from . import App, app_doc, ga_params, ga_run_table, RESIDENT, PER_REGION, SECTIONS, BATCHED
 
 # (M, T, Pc, Pm, p, deadline_factor): the paper's setting first (Sec. 5.1.2)
 SETTINGS = [
@@ -93,7 +93,7 @@ def table(res):
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--app", default="medium", help="application name or JSON path")
+    ap.add_argument("--app", default="medium", help="application name, JSON description or C source")
     ap.add_argument("--seed", type=int, default=1, help="application seed")
     ap.add_argument("--set", action="append", default=[], metavar="NAME=VALUE")
     ap.add_argument("--reps", type=int, default=3)
@@ -107,14 +107,7 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("ga_study needs a GPU to measure the landscape", file=sys.stderr)
         return 2
-    src = args.app if args.app.endswith(".json") else app_path(args.app)
-    if args.set:
-        with open(src) as f:
-            doc = json.load(f)
-        for kv in args.set:
-            k, v = kv.split("=", 1)
-            doc["params"][k] = int(v)
-        src = doc
+    src = app_doc(args.app, args.set)
     app = App(src, seed=args.seed)
     bufs = app.alloc_device_buffers("cuda:0")
     policy = {"resident": RESIDENT, "per_region": PER_REGION, "sections": SECTIONS}[args.policy]
@@ -131,19 +124,12 @@ def main(argv=None):
         print("measured %d / %d genes, %.1f s" % (min(c0 + args.chunk, 1 << a), 1 << a, time.perf_counter() - t0),
               file=sys.stderr, flush=True)
     res = study(a, times, status, SETTINGS, args.seeds, args.reps + args.warmup)
-    res.update({"app": args.app, "params": app_params(src), "gene_len": a, "reps": args.reps,
+    res.update({"app": args.app, "params": src["params"], "gene_len": a, "reps": args.reps,
                 "warmup": args.warmup, "policy": args.policy, "measure_wall_s": time.perf_counter() - t0,
                 "times_quantiles_s": [float(np.quantile(times, q)) for q in (0.0, 0.25, 0.5, 0.75, 1.0)]})
     print(json.dumps(res), flush=True)
     print(table(res), flush=True)
     return 0
-
-
-def app_params(src):
-    if isinstance(src, dict):
-        return src.get("params", {})
-    with open(src) as f:
-        return json.load(f).get("params", {})
 
 
 if __name__ == "__main__":

@@ -15,12 +15,12 @@ import time
 
 import numpy as np
 
-from . import App, app_path, ga_params, RESIDENT, PER_REGION, SECTIONS, PRESTAGED, KEEP_OUTPUTS, GRAPH, BATCHED, PROGRESS
+from . import App, app_doc, ga_params, RESIDENT, PER_REGION, SECTIONS, PRESTAGED, KEEP_OUTPUTS, GRAPH, BATCHED, PROGRESS
 
 
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("--app", default="tiny", help="application name or JSON path")
+    ap.add_argument("--app", default="tiny", help="application name, JSON description or C source")
     ap.add_argument("--seed", type=int, default=1, help="application seed")
     ap.add_argument("--set", action="append", default=[], metavar="NAME=VALUE",
                     help="override an application parameter (repeatable)")
@@ -48,14 +48,7 @@ def main(argv=None):
     if not torch.cuda.is_available():
         print("search needs a GPU", file=sys.stderr)
         return 2
-    src = args.app if args.app.endswith(".json") else app_path(args.app)
-    if args.set:
-        with open(src) as f:
-            doc = json.load(f)
-        for kv in args.set:
-            k, v = kv.split("=", 1)
-            doc["params"][k] = int(v)
-        src = doc
+    src = app_doc(args.app, args.set)
     app = App(src, seed=args.seed)
     bufs = app.alloc_device_buffers("cuda:0")
     policy = {"resident": RESIDENT, "per_region": PER_REGION, "sections": SECTIONS}[args.policy]

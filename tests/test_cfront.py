@@ -1,0 +1,158 @@
+"""The C front end (parsing loop nests of a C subset into the application
+description, Sec. 4): each application's C source yields its hand-built
+description, the library and the oracle give the parsed nests the same
+verdicts, and the access modes, bindings and errors follow the source."""
+import json
+import os
+
+import pytest
+
+import paper_1806_01430_amd as ofl
+from paper_1806_01430_amd import cfront
+from oracle import depcheck as D
+from oracle import ir
+
+APPS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1806_01430_amd", "apps")
+
+
+def _norm(n):
+    n = dict(n)
+    if "access" in n:
+        n["access"] = sorted(tuple(a) for a in n["access"])
+    if "body" in n:
+        n["body"] = [_norm(x) for x in n["body"]]
+    return n
+
+
+@pytest.mark.parametrize("name", ["tiny", "medium", "precision", "large", "batch"])
+def test_c_source_parses_to_the_description(name):
+    got = cfront.load(os.path.join(APPS, name + ".c"))
+    with open(os.path.join(APPS, name + ".json")) as f:
+        want = json.load(f)
+    assert got["name"] == want["name"]
+    assert got["params"] == want["params"]
+    assert got["buffers"] == want["buffers"]
+    assert [_norm(n) for n in got["program"]] == [_norm(n) for n in want["program"]]
+
+
+@pytest.mark.parametrize("name", ["medium", "large"])
+def test_library_and_oracle_verdicts_of_parsed_source(name):
+    app = ofl.App(os.path.join(APPS, name + ".c"))
+    o = ir.load(cfront.load(os.path.join(APPS, name + ".c")))
+    v = [tuple(x) for x in D.check_app(o)]
+    assert app.verdicts() == v
+    by_name = {app.nest_name(i): v[i] for i in range(app.n_nests)}
+    # the two recurrences carry a dependence, the generator is an external call
+    assert by_name["rec_prefix_v"][:2] == (D.REJECT, D.R_DATA_DEP)
+    assert by_name["rec_decay_w"][:2] == (D.REJECT, D.R_DATA_DEP)
+    assert by_name["sumsq_S"][:2] == (D.PARALLEL_REDUCTION, D.R_NONE)
+    assert by_name["stencil19"][:2] == (D.PARALLEL_REDUCTION, D.R_NONE)
+    if name == "large":
+        assert by_name["lcg_fill_L"][:2] == (D.REJECT, D.R_EXTERNAL_CALL)
+
+
+DECLS = """#define R 5
+#define CC 7
+float X[R][CC];
+float Y[R][CC];
+float Z[CC][R];
+double t[1];
+"""
+
+
+def _one(body):
+    doc = cfront.parse(DECLS + body, "t")
+    assert len(doc["program"]) == 1
+    return doc["program"][0]
+
+
+def test_renamed_loops_and_buffers_bind():
+    n = _one("for (int r = 0; r < R; r++) for (int c = 0; c < CC; c++) Z[c][r] = X[r][c];")
+    assert (n["op"], n["args"]) == ("transpose", {"src": "X", "dst": "Z"})
+    assert n["loops"] == [["r", "0", "R"], ["c", "0", "CC"]]
+    assert sorted(map(tuple, n["access"])) == [("X", "r", "r", "c"), ("Z", "w", "c", "r")]
+    n = _one("for (int a = 0; a < R; a++) for (int b = 0; b < CC; b++) Y[a][b] = 0.5f * (Y[a][b] + X[a][b]);")
+    assert (n["op"], n["args"]) == ("avg2", {"S": "Y", "X": "Y", "Y": "X"})
+    # Y read at the element it writes, before the write: read-write
+    assert sorted(map(tuple, n["access"])) == [("X", "r", "a", "b"), ("Y", "rw", "a", "b")]
+
+
+def test_compound_assignment_and_commuted_operands():
+    for body in ("X[i][j] += 0.25f * Y[i][j];", "X[i][j] = X[i][j] + Y[i][j] * 0.25f;",
+                 "X[i][j] = 0.25f * Y[i][j] + X[i][j];"):
+        n = _one("for (int i = 0; i < R; i++) for (int j = 0; j < CC; j++) " + body)
+        assert (n["op"], n["args"]) == ("add_scaled", {"C": "X", "A": "Y", "alpha": 0.25}), body
+        assert sorted(map(tuple, n["access"])) == [("X", "rw", "i", "j"), ("Y", "r", "i", "j")]
+    n = _one("for (int i = 0; i < R; i++) for (int j = 0; j < CC; j++) X[i][j] *= -3.0f;")
+    assert (n["op"], n["args"]) == ("scale", {"D": "X", "beta": -3.0})
+
+
+def test_sum_reduction_through_temporary():
+    n = _one("""for (int i = 0; i < R; i++) for (int j = 0; j < CC; j++) {
+                    double u = (double)X[i][j];
+                    t[0] += u * u; }""")
+    assert (n["op"], n["args"]) == ("sumsq", {"x": "X", "s": "t"})
+    assert sorted(map(tuple, n["access"])) == [("X", "r", "i", "j"), ("t", "sum", "0")]
+
+
+@pytest.mark.parametrize("body", [
+    # grouping differs from the operation's: another rounding
+    "X[i][j] = 0.5f * X[i][j] + 0.5f * Y[i][j];",
+    # another constant
+    "Y[i][j] = 0.25f * (X[i][j] + Y[i][j]);",
+    # element-wise with a shifted operand: no operation reads a neighbour
+    "Y[i][j] = X[i][j];\n X[i][j] = Y[i][j];",
+])
+def test_unmatched_bodies_are_errors(body):
+    with pytest.raises(cfront.CError):
+        _one("for (int i = 0; i < R; i++) for (int j = 0; j < CC; j++) { " + body + " }")
+
+
+def test_source_errors():
+    loop = "for (int i = 0; i < R; i++) for (int j = 0; j < CC; j++) "
+    with pytest.raises(cfront.CError, match="break"):
+        _one(loop + "{ Y[i][j] = X[i][j]; break; }")
+    with pytest.raises(cfront.CError, match="name \\+ constant"):
+        _one(loop + "Y[i][j] = X[2 * i][j];")
+    with pytest.raises(cfront.CError, match="step by one"):
+        _one("for (int i = 0; i < R; i += 2) Y[i][0] = X[i][0];")
+    with pytest.raises(cfront.CError, match="unsupported directive"):
+        cfront.parse("#include <math.h>\n" + DECLS, "t")
+    with pytest.raises(cfront.CError, match="prec"):
+        cfront.parse(DECLS + "#pragma ofl prec(bf16x3)\n" + loop + "Y[i][j] = X[i][j];", "t")
+    with pytest.raises(cfront.CError, match="annotation"):
+        cfront.parse("float P[3]; // ofl: outptu\n", "t")
+
+
+def test_repeat_block_and_prec_pragma():
+    src = """#define N 16
+#define STEPS 3
+float A[N][N];
+float B[N][N];
+float C[N][N];
+#pragma ofl prec(bf16x3)
+for (int i = 0; i < N; i++) for (int j = 0; j < N; j++) {
+    C[i][j] = 0;
+    for (int k = 0; k < N; k++) C[i][j] += A[i][k] * B[k][j]; }
+for (int s = 0; s < STEPS; s++) {
+    for (int i = 0; i < N; i++) for (int j = 0; j < N; j++) A[i][j] = C[i][j];
+    for (int i = 0; i < N; i++) for (int j = 0; j < N; j++) C[i][j] = 2.0f * C[i][j];
+}
+"""
+    doc = cfront.parse(src, "r")
+    g, rep = doc["program"]
+    assert (g["op"], g["args"]) == ("gemm", {"A": "A", "B": "B", "C": "C", "prec": "bf16x3"})
+    assert sorted(map(tuple, g["access"])) == [("A", "r", "i", "k"), ("B", "r", "k", "j"), ("C", "w", "i", "j")]
+    assert rep["repeat"] == "STEPS" and rep["var"] == "s"
+    assert [n["nest"] for n in rep["body"]] == ["copy_A", "scale_C"]
+    app = ofl.App(doc)
+    assert app.verdicts() == [tuple(x) for x in D.check_app(ir.load(doc))]
+    assert app.gene_len == 3
+
+
+def test_command_line_prints_the_description(capsys):
+    assert cfront.main([os.path.join(APPS, "tiny.c")]) == 0
+    doc = json.loads(capsys.readouterr().out)
+    with open(os.path.join(APPS, "tiny.json")) as f:
+        want = json.load(f)
+    assert [_norm(n) for n in doc["program"]] == [_norm(n) for n in want["program"]]
