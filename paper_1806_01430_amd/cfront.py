@@ -55,21 +55,28 @@ class CError(ValueError):
 
 
 def _lex(src):
-    out, pos = [], 0
+    """Tokens, with the 1-based source line of each and whether it is the
+    first token on its line."""
+    out, pos, line, last_line = [], 0, 1, 0
     while pos < len(src):
         m = _TOKEN.match(src, pos)
         if not m:
-            raise CError("cannot read %r" % src[pos:pos + 20])
-        pos = m.end()
+            raise CError("line %d: cannot read %r" % (line, src[pos:pos + 20]))
         if m.lastgroup != "ws":
-            out.append(m.group(m.lastgroup))
+            out.append((m.group(m.lastgroup), line, line != last_line))
+            last_line = line
+        line += src.count("\n", pos, m.end())
+        pos = m.end()
     return out
 
 
 # ------------------------------------------------------------------ parsing
 class _Parser:
     def __init__(self, toks):
-        self.t, self.i = toks, 0
+        self.t = [t[0] for t in toks]
+        self.where = [(t[1], t[2]) for t in toks]
+        self.i = 0
+        self.for_at = {}          # id of a parsed for statement -> (line, first on its line)
 
     def peek(self, k=0):
         return self.t[self.i + k] if self.i + k < len(self.t) else None
@@ -151,6 +158,7 @@ class _Parser:
             self.take("}")
             return body
         if tok == "for":
+            at = self.where[self.i]
             self.take("for")
             self.take("(")
             if self.peek() == "int":
@@ -176,7 +184,9 @@ class _Parser:
                 if self.take() not in ("++",):
                     raise CError("loops step by one (v++)")
             self.take(")")
-            return [("for", v, lo, hi, self.stmt())]
+            node = ("for", v, lo, hi, self.stmt())
+            self.for_at[id(node)] = at
+            return [node]
         if tok == "@":
             self.take("@")
             what = self.take()
@@ -262,11 +272,13 @@ TEMPLATES = [
 ]
 
 
-def _parse_stmts(src):
+def _parse_stmts(src, where=None):
     p = _Parser(_lex(src))
     out = []
     while p.peek() is not None:
         out.extend(p.stmt())
+    if where is not None:
+        where.update(p.for_at)
     return out
 
 
@@ -599,13 +611,20 @@ def parse(src, name="app"):
     """Application IR (a dict, as ofl_app_load_json takes it) of C source.
 
     ``#pragma ofl prec(bf16x3|fp8x2|f32)`` on the line before a top-level
-    product nest sets the arithmetic of its offloaded form."""
-    params, buffers, program = {}, [], []
+    product nest sets the arithmetic of its offloaded form; ``#pragma acc``
+    lines (as ``offloaded_source`` writes them) are ignored."""
+    return _parse(src, name)[0]
+
+
+def _parse(src, name):
+    """(IR, [(line, first on its line)] of each nest's outer for, in program order)."""
+    params, buffers, program, at = {}, [], [], []
     body_lines = []
     for line in src.splitlines():
         m = _DEFINE.match(line)
         if m:
             params[m.group(1)] = int(m.group(2))
+            body_lines.append("")
             continue
         m = _ARRAY.match(line)
         if m:
@@ -622,10 +641,13 @@ def parse(src, name="app"):
                 else:
                     raise CError("unknown buffer annotation %r" % opt)
             buffers.append(b)
+            body_lines.append("")
             continue
         m = _PRAGMA.match(line)
         if m:
             line = "@prec %s;" % m.group(1)
+        elif re.match(r"\s*#pragma\s+acc\b", line):
+            line = ""
         elif line.lstrip().startswith("#"):
             raise CError("unsupported directive: %s" % line.strip())
         body_lines.append(line)
@@ -633,6 +655,7 @@ def parse(src, name="app"):
     names_used = {}
 
     def nest_ir(stmt, prec):
+        at.append(where[id(stmt)])
         loops = _loops(stmt)
         acc, flags = _accesses(stmt, [l[0] for l in loops])
         op, args = _bind(stmt, dtypes)
@@ -648,8 +671,8 @@ def parse(src, name="app"):
             n["flags"] = flags
         return n
 
-    prec = None
-    for stmt in _parse_stmts("\n".join(body_lines)):
+    prec, where = None, {}
+    for stmt in _parse_stmts("\n".join(body_lines), where):
         if stmt[0] == "pragma":
             prec = stmt[2]
             continue
@@ -664,7 +687,43 @@ def parse(src, name="app"):
         else:
             program.append(nest_ir(stmt, prec))
         prec = None
-    return {"name": name, "params": params, "buffers": buffers, "program": program}
+    return {"name": name, "params": params, "buffers": buffers, "program": program}, at
+
+
+_REASONS = {1: "a data dependence between iterations", 2: "a call of an external routine",
+            3: "a break out of the loop"}
+
+
+def offloaded_source(src, verdicts, gene):
+    """The program with the offload pattern written in: ``#pragma acc
+    kernels`` before each nest whose gene bit is 1 (Sec. 4: the directive
+    goes on the loops the gene selects; a 0 bit leaves the loop on the CPU),
+    and a comment before each nest the dependence check excluded.
+
+    verdicts: (verdict, reason, gene position) per nest in program order, as
+    App.verdicts() gives them; gene: one 0/1 per accepted nest."""
+    _, at = _parse(src, "app")
+    if len(verdicts) != len(at):
+        raise ValueError("%d verdicts for %d nests" % (len(verdicts), len(at)))
+    if len(gene) != sum(1 for v in verdicts if v[2] >= 0):
+        raise ValueError("gene length does not match the accepted nests")
+    lines = src.split("\n")
+    insert = {}
+    for (verdict, reason, pos), (line, first) in zip(verdicts, at):
+        if not first:
+            raise CError("line %d: a nest's for must begin its line to take a directive" % line)
+        text = lines[line - 1]
+        indent = text[:len(text) - len(text.lstrip())]
+        if pos < 0:
+            insert[line] = indent + "/* not offloadable: %s */" % _REASONS.get(reason, "rejected")
+        elif gene[pos]:
+            insert[line] = indent + "#pragma acc kernels"
+    out = []
+    for n, text in enumerate(lines, 1):
+        if n in insert:
+            out.append(insert[n])
+        out.append(text)
+    return "\n".join(out)
 
 
 def load(path):

@@ -6,7 +6,10 @@ times, same-pattern skip).
 
 Prints one JSON line: the nests and their verdicts, the best gene, its time,
 the all-CPU time when measured, the speedup, search wall time, time to the
-final best, measurements made, and per-generation best times.
+final best, measurements made, and per-generation best times.  Given a C
+source (``--app paper_1806_01430_amd/apps/medium.c``), ``--emit PATH`` writes
+the program with ``#pragma acc kernels`` before each nest the best gene
+offloads.
 """
 import argparse
 import json
@@ -40,6 +43,8 @@ def main(argv=None):
     ap.add_argument("--timeout", type=float, default=0.0, help="seconds; cut off any run longer than this (0 = none)")
     ap.add_argument("--progress", action="store_true", help="one line per generation on stderr")
     ap.add_argument("--baseline", action="store_true", help="also measure the all-CPU gene")
+    ap.add_argument("--emit", metavar="PATH", default=None,
+                    help="with a C source as --app: write the program with the best gene's directives to PATH")
     ap.add_argument("--exhaustive", action="store_true",
                     help="also measure every gene (gene length <= 12) and rank the GA's answer")
     args = ap.parse_args(argv)
@@ -92,6 +97,16 @@ def main(argv=None):
             t_all0 = float(t[0])
     out["all_cpu_time_s"] = t_all0
     out["speedup_vs_all_cpu"] = (t_all0 / res["best_time"]) if t_all0 else None
+    if args.emit:
+        if not args.app.endswith(".c"):
+            print("--emit needs a C source as --app", file=sys.stderr)
+            return 2
+        from .cfront import offloaded_source
+        with open(args.app) as f:
+            text = offloaded_source(f.read(), app.verdicts(), res["best_gene"])
+        with open(args.emit, "w") as f:
+            f.write(text)
+        out["emitted"] = args.emit
     print(json.dumps(out), flush=True)
     return 0
 

@@ -156,3 +156,31 @@ def test_command_line_prints_the_description(capsys):
     with open(os.path.join(APPS, "tiny.json")) as f:
         want = json.load(f)
     assert [_norm(n) for n in doc["program"]] == [_norm(n) for n in want["program"]]
+
+
+def test_offloaded_source_marks_the_gene():
+    path = os.path.join(APPS, "medium.c")
+    with open(path) as f:
+        src = f.read()
+    app = ofl.App(path)
+    v = app.verdicts()
+    for gene in ([1] * app.gene_len, [0] * app.gene_len, [(i * 7) % 3 % 2 for i in range(app.gene_len)]):
+        text = cfront.offloaded_source(src, v, gene)
+        lines = text.split("\n")
+        assert len(lines) == len(src.split("\n")) + sum(gene) + sum(1 for x in v if x[2] < 0)
+        # the directive sits right before the outer for of each offloaded nest
+        fors = [i for i, t in enumerate(lines) if t.strip() == "#pragma acc kernels"]
+        assert len(fors) == sum(gene)
+        assert all(lines[i + 1].lstrip().startswith("for (") for i in fors)
+        assert text.count("not offloadable: a data dependence") == 2
+        # the written program parses to the same description
+        assert cfront.parse(text, "medium") == cfront.parse(src, "medium")
+    # nests marked in program order: the product is the first accepted nest after init
+    text = cfront.offloaded_source(src, v, [0, 1] + [0] * (app.gene_len - 2))
+    i = text.index("#pragma acc kernels")
+    assert text[i:].split("\n")[3].strip() == "C[i][j] = 0.0f;"
+    with pytest.raises(ValueError):
+        cfront.offloaded_source(src, v, [1] * (app.gene_len + 1))
+    with pytest.raises(cfront.CError, match="begin its line"):
+        cfront.offloaded_source(DECLS + "{ } for (int i = 0; i < R; i++) for (int j = 0; j < CC; j++) Y[i][j] = X[i][j];",
+                                [(0, 0, 0)], [1])

@@ -431,6 +431,30 @@ def test_eval_population_and_ga_tiny():
     say("GA best gene", res["best_gene"], "exhaustive best", genes[best_idx], "rank", rank)
 
 
+def test_search_from_c_source(tmp_path, capsys):
+    # the whole flow from C source: parse, check, GA over measured runs,
+    # the program written back with the best gene's directives; the parsed
+    # application's all-GPU run matches the oracle
+    import os
+    from paper_1806_01430_amd import cfront, search
+    src = os.path.join(os.path.dirname(ofl.__file__), "apps", "tiny.c")
+    out = str(tmp_path / "tiny_offloaded.c")
+    say("case search from tiny.c with --emit")
+    assert search.main(["--app", src, "--M", "4", "--T", "3", "--emit", out]) == 0
+    res = json.loads(capsys.readouterr().out.strip().splitlines()[-1])
+    with open(out) as f:
+        text = f.read()
+    assert text.count("#pragma acc kernels") == sum(res["best_gene"])
+    doc = cfront.load(src)
+    assert cfront.parse(text, "tiny") == doc
+    app = ofl.App(src)
+    bufs = app.alloc_device_buffers()
+    assert app.run_pattern([1] * app.gene_len, bufs)["status"] == ofl.ST_OK
+    o = ir.load(doc)
+    o32, o64 = parity.oracle_outputs(o, 1)
+    assert not parity.compare(o, app.read_all(), o32, o64, rel_gemm=parity.rel_gemm_for(o, ()))
+
+
 def test_batched_deadline_cuts_host_nests():
     # in one batched submission the limit stops host nests at the limit: the
     # all-CPU gene of the medium application (seconds of serial work) ends as
