@@ -193,6 +193,23 @@ def run_kernels_large(args):
             gbs = b * R * C * runs / (ms * 1e-3) / 1e9
             out["ewise_8192_" + op] = {"launches_per_run": n // runs, "ms_per_run": ms / runs, "GBps": gbs,
                                        "frac_hbm": gbs / HBM_PEAK_GBS}
+    del bufs, app
+    # the FFT call on 8192 rows of 1024 complex points (64 MB): each row read
+    # and written once, 16 algorithmic bytes per point; 5 n log2 n flops a row
+    import numpy as np
+    R, n = 8192, 1024
+    app = ofl.App(json.dumps(appgen.fft_app(R, n)), seed=1)
+    app.set_input("X", np.random.default_rng(5).standard_normal((R, 2 * n)).astype(np.float32))
+    bufs = app.alloc_device_buffers("cuda:0")
+    app.run_pattern([1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
+    app.set_kernel_timing(True)
+    for _ in range(5):
+        app.run_pattern([1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
+    nl, ms = app.kernel_stats("fft_rows")
+    avg = ms / nl * 1e-3
+    gbs = 16.0 * R * n / avg / 1e9
+    out["fft_rows_8192x1024"] = {"avg_us": avg * 1e6, "GBps": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
+                                 "GFLOPs": 5.0 * n * 10 * R / avg / 1e9}
     return out
 
 

@@ -76,7 +76,7 @@ class _Parser:
         self.t = [t[0] for t in toks]
         self.where = [(t[1], t[2]) for t in toks]
         self.i = 0
-        self.for_at = {}          # id of a parsed for statement -> (line, first on its line)
+        self.for_at = {}          # id of a parsed for or call statement -> (line, first on its line)
 
     def peek(self, k=0):
         return self.t[self.i + k] if self.i + k < len(self.t) else None
@@ -204,7 +204,13 @@ class _Parser:
             e = self.expr()
             self.take(";")
             return [("local", ty, name, e)]
+        at = self.where[self.i]
         lhs = self.primary()
+        if lhs[0] == "call" and self.peek() == ";":
+            self.take(";")
+            node = ("callstmt", lhs[1], lhs[2])
+            self.for_at[id(node)] = at
+            return [node]
         op = self.take()
         if op not in ("=", "+=", "-=", "*=", "/="):
             raise CError("expected an assignment, found %r" % op)
@@ -232,6 +238,12 @@ def _affine(e):
 # random stream, bf16(x) the round-to-nearest-even bfloat16 of x.  Any other
 # call (lcg01(seed), a sequential generator, for one) is an external routine.
 PURE_CALLS = ("u01", "bf16")
+
+# Library routines called as statements of their own, outside any loop, that
+# the library implements on the CPU and on the GPU: each call becomes a
+# function block (one nest, one gene bit).  fft_rows(X): the forward DFT of
+# every row of X[R][2n] (n complex values per row, interleaved).
+FUNCTION_BLOCKS = {"fft_rows": "fft_rows"}
 
 # One C snippet per operation, each the nest's definition in the evaluation
 # order the library follows; names beginning with $ are pattern variables
@@ -654,8 +666,27 @@ def _parse(src, name):
     dtypes = {b["name"]: b["dtype"] for b in buffers}
     names_used = {}
 
+    def block_ir(stmt):
+        # a call of a library routine the library implements on both sides
+        # becomes a function block: one nest, one gene bit
+        name, args = stmt[1], stmt[2]
+        if name not in FUNCTION_BLOCKS:
+            raise CError("call of %s: not a known library routine (only %s)" % (name, ", ".join(FUNCTION_BLOCKS)))
+        if len(args) != 1 or args[0][0] != "var" or args[0][1] not in dtypes:
+            raise CError("%s takes one declared array" % name)
+        x = args[0][1]
+        b = next(b for b in buffers if b["name"] == x)
+        if b["dtype"] != "f32" or len(b["dims"]) != 2:
+            raise CError("%s needs a 2-D float array (rows of interleaved complex values)" % name)
+        at.append(where[id(stmt)] + ("call",))
+        base = "fft_" + x
+        names_used[base] = names_used.get(base, 0) + 1
+        return {"nest": base if names_used[base] == 1 else "%s_%d" % (base, names_used[base]),
+                "op": FUNCTION_BLOCKS[name], "args": {"x": x},
+                "loops": [["r", "0", b["dims"][0]], ["e", "0", b["dims"][1]]], "access": [[x, "rw", "r", "e"]]}
+
     def nest_ir(stmt, prec):
-        at.append(where[id(stmt)])
+        at.append(where[id(stmt)] + ("loop",))
         loops = _loops(stmt)
         acc, flags = _accesses(stmt, [l[0] for l in loops])
         op, args = _bind(stmt, dtypes)
@@ -676,8 +707,12 @@ def _parse(src, name):
         if stmt[0] == "pragma":
             prec = stmt[2]
             continue
+        if stmt[0] == "callstmt":
+            program.append(block_ir(stmt))
+            prec = None
+            continue
         if stmt[0] != "for":
-            raise CError("top-level statements are for loops")
+            raise CError("top-level statements are for loops and library calls")
         inner = stmt[4]
         if len(inner) >= 2 and all(s[0] == "for" for s in inner):
             if _affine(stmt[2]) != "0":
@@ -709,13 +744,15 @@ def offloaded_source(src, verdicts, gene):
         raise ValueError("gene length does not match the accepted nests")
     lines = src.split("\n")
     insert = {}
-    for (verdict, reason, pos), (line, first) in zip(verdicts, at):
+    for (verdict, reason, pos), (line, first, kind) in zip(verdicts, at):
         if not first:
-            raise CError("line %d: a nest's for must begin its line to take a directive" % line)
+            raise CError("line %d: a nest must begin its line to take a directive" % line)
         text = lines[line - 1]
         indent = text[:len(text) - len(text.lstrip())]
         if pos < 0:
             insert[line] = indent + "/* not offloadable: %s */" % _REASONS.get(reason, "rejected")
+        elif gene[pos] and kind == "call":
+            insert[line] = indent + "/* function block: the GPU implementation replaces this call */"
         elif gene[pos]:
             insert[line] = indent + "#pragma acc kernels"
     out = []

@@ -6,12 +6,14 @@
 
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 namespace ofl {
 
 namespace {
 
 constexpr uint64_t kGolden = 0x9E3779B97F4A7C15ull;
+constexpr double kTwoPi = 6.283185307179586;   // 2 pi rounded to double
 
 // SplitMix64 output mix (Steele, Lea & Flood 2014).
 inline uint64_t mix64(uint64_t z) {
@@ -231,6 +233,41 @@ bool run_host_nest(const AppIR &app, const Nest &n, const std::vector<void *> &h
             L[e] = (float)(x >> 8) * (1.0f / 16777216.0f);
         }
         return !dl.expired();
+    }
+    case OP_FFT_ROWS: {
+        // the CPU form of the FFT call: the same radix-2 self-sorting
+        // (Stockham) passes as the GPU kernel, per row
+        const Buffer &x = app.bufs[n.b[0]];
+        const int64_t rows = x.dims[0], pts = x.dims[1] / 2, half = pts / 2;
+        std::vector<float> w(2 * half), a(2 * pts), b(2 * pts);
+        for (int64_t m = 0; m < half; ++m) {
+            const double th = kTwoPi * (double)m / (double)pts;
+            w[2 * m] = (float)std::cos(th);
+            w[2 * m + 1] = (float)-std::sin(th);
+        }
+        float *X = F(0);
+        for (int64_t r = 0; r < rows; ++r) {
+            if ((r & 15) == 0 && dl.expired()) return false;
+            float *xr = X + r * 2 * pts;
+            std::memcpy(a.data(), xr, 2 * pts * sizeof(float));
+            for (int64_t ns = 1, st = half; ns < pts; ns <<= 1, st >>= 1) {
+                for (int64_t j = 0; j < half; ++j) {
+                    const int64_t k = j & (ns - 1), o = ((j - k) << 1) + k;
+                    const float ur = a[2 * j], ui = a[2 * j + 1];
+                    const float vr0 = a[2 * (j + half)], vi0 = a[2 * (j + half) + 1];
+                    const float tr = w[2 * k * st], ti = w[2 * k * st + 1];
+                    const float vr = vr0 * tr - vi0 * ti;
+                    const float vi = vr0 * ti + vi0 * tr;
+                    b[2 * o] = ur + vr;
+                    b[2 * o + 1] = ui + vi;
+                    b[2 * (o + ns)] = ur - vr;
+                    b[2 * (o + ns) + 1] = ui - vi;
+                }
+                a.swap(b);
+            }
+            std::memcpy(xr, a.data(), 2 * pts * sizeof(float));
+        }
+        return true;
     }
     default:
         return true;

@@ -11,7 +11,7 @@ namespace ofl {
 static const char *kOpNames[OP_COUNT] = {
     "none",       "init_uniform", "gemm",       "gemm_bf16",     "add_scaled", "avg2",
     "scale",      "copy",         "cast_bf16",  "transpose",     "sumsq",      "stencil19",
-    "copy_interior", "rec_prefix", "rec_decay", "lcg_fill"};
+    "copy_interior", "rec_prefix", "rec_decay", "lcg_fill", "fft_rows"};
 
 const char *op_name(Op op) { return (op >= 0 && op < OP_COUNT) ? kOpNames[op] : "?"; }
 
@@ -19,7 +19,7 @@ bool op_has_device_kernel(Op op) {
     switch (op) {
     case OP_INIT_UNIFORM: case OP_GEMM: case OP_GEMM_BF16: case OP_ADD_SCALED: case OP_AVG2:
     case OP_SCALE: case OP_COPY: case OP_CAST_BF16: case OP_TRANSPOSE: case OP_SUMSQ:
-    case OP_STENCIL19: case OP_COPY_INTERIOR:
+    case OP_STENCIL19: case OP_COPY_INTERIOR: case OP_FFT_ROWS:
         return true;
     default:
         return false;
@@ -286,6 +286,17 @@ bool resolve_op(Ctx &cx, Nest &n, const Json *args, const std::vector<int64_t> &
         return need(cx, n, is(0, DT_F32) && is(1, DT_F32) && B(0).dims.size() == 1 && B(1).dims.size() == 3 &&
                                B(1).dims[2] == B(0).dims[0] && B(1).dims[0] >= 2 && B(1).dims[1] >= 2,
                     "needs w[K] and p[I][J][K] f32");
+    case OP_FFT_ROWS: {
+        // x[R][2n]: R rows of n complex values, real and imaginary parts
+        // interleaved; n a power of two up to kFftMaxPoints
+        if (!arg_buf(cx, n, args, "x", x)) return false;
+        n.b.push_back(x);
+        if (!need(cx, n, is(0, DT_F32) && B(0).dims.size() == 2, "needs a 2-D f32 buffer")) return false;
+        const int64_t pts = B(0).dims[1] / 2;
+        return need(cx, n, B(0).dims[1] % 2 == 0 && pts >= 1 && pts <= kFftMaxPoints && (pts & (pts - 1)) == 0 &&
+                               B(0).dims[0] < (1ll << 31),
+                    "row length must be 2 n floats, n a power of two up to " + std::to_string(kFftMaxPoints));
+    }
     case OP_LCG_FILL: {
         if (!arg_buf(cx, n, args, "L", x)) return false;
         n.b.push_back(x);

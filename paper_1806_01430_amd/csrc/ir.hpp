@@ -40,8 +40,12 @@ enum Op {
     OP_REC_PREFIX,
     OP_REC_DECAY,
     OP_LCG_FILL,
+    OP_FFT_ROWS,        // function block: forward complex DFT of each row
     OP_COUNT
 };
+
+// Largest row of the FFT function block, in complex points.
+constexpr int64_t kFftMaxPoints = 2048;
 
 const char *op_name(Op op);
 bool op_has_device_kernel(Op op);

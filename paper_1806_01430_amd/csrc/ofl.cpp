@@ -330,6 +330,10 @@ hipError_t launch_nest(ofl_app *app, const Nest &n, void *const *dev, const int6
         const auto &d = ir.bufs[n.b[0]].dims;
         return k::copy_interior(F(0), F(1), d[0], d[1], d[2], s, &fin);
     }
+    case OP_FFT_ROWS: {
+        const auto &d = ir.bufs[n.b[0]].dims;
+        return k::fft_rows(F(0), d[0], d[1] / 2, s);
+    }
     default:
         return hipErrorInvalidValue;
     }

@@ -10,7 +10,12 @@ The bar, per buffer:
   differ by less than n * 2^-52;
 * downstream of a GEMM (whose MFMA accumulation order differs from the serial
   one): within 1e-5 relative, element by element, of the oracle's FP64 twin;
-  bf16 results within one bf16 rounding (2^-8 relative) of the twin.
+  bf16 results within one bf16 rounding (2^-8 relative) of the twin;
+* downstream of the FFT call (an FP32 radix-2 FFT against the exact
+  transform): row by row, ||got - exact||_2 <= rel_fft(n) ||exact||_2 (the
+  bound below) plus two roundings; FP64 sums of squares of such values within
+  2 rel_fft(n) + the sum bound.  Element-wise relative error means nothing for
+  spectra (bins near zero), the norm-wise bound is what the analysis gives.
 """
 import numpy as np
 
@@ -28,6 +33,37 @@ REL_SUM = 1e-12
 # products satisfy sum|products| <= (1 + u)^2 (1 + 2u) sum|a||b| <= 1.25
 # sum|a||b| for u = 2^-4.  On top comes the FP32 accumulation of the GEMM.
 REL_FP8_MFMA = 7 * 2.0 ** -14 * 1.25 + REL_GEMM
+
+
+def rel_fft(n):
+    """Norm-wise relative error bound of an FP32 radix-2 FFT of length n with
+    twiddles each within mu of exact (Higham, Accuracy and Stability of
+    Numerical Algorithms, 2nd ed., Thm. 24.2):
+        ||y_hat - y|| / ||y|| <= L eta / (1 - L eta),  L = log2 n,
+        eta = mu + gamma_4 (sqrt 2 + mu),  gamma_4 = 4u / (1 - 4u),
+    u = 2^-24; the twiddles are the double values rounded once to FP32, so
+    mu <= u (1 + 2^-20) covers the double evaluation as well."""
+    u = 2.0 ** -24
+    L = max(0, int(n).bit_length() - 1)
+    mu = u * (1 + 2.0 ** -20)
+    eta = mu + 4 * u / (1 - 4 * u) * (np.sqrt(2.0) + mu)
+    return L * eta / (1 - L * eta)
+
+
+def fft_points(app_o):
+    """Largest row length (complex points) of the FFT calls, 0 if none."""
+    return max([app_o.buffers[app_o.buf_index[n.args["x"]]].dims[1] // 2 for n in app_o.nests
+                if n.op == "fft_rows"] or [0])
+
+
+def fft_tainted(app_o):
+    tainted = set()
+    for ni in xfer.executions(app_o):
+        n = app_o.nests[ni]
+        reads, writes = xfer.nest_sets(app_o, n)
+        if n.op == "fft_rows" or any(b in tainted for b in reads):
+            tainted |= set(writes)
+    return tainted
 
 
 def sum_terms(app_o):
@@ -95,11 +131,29 @@ def compare(app_o, got, o32, o64, names=None, rel_gemm=REL_GEMM):
     """Return a list of failure strings (empty when everything matches)."""
     bad = []
     tainted = gemm_tainted(app_o)
+    spectral = fft_tainted(app_o)
+    rf = rel_fft(fft_points(app_o))
     terms = sum_terms(app_o)
     for b, buf in enumerate(app_o.buffers):
         if names is not None and buf.name not in names:
             continue
         g = np.asarray(got[buf.name])
+        if b in spectral and b not in tainted:
+            y = o64[buf.name]
+            gv = g.astype(np.float64)
+            if buf.dtype == "f64":
+                tol = 2 * rf + rf * rf + REL_SUM + terms.get(buf.name, 1) * 2.0 ** -52
+                err = np.max(np.abs(gv - y) / np.maximum(np.abs(y), 1e-300)) if g.size else 0.0
+            else:
+                tol = rf + 2.0 ** -23
+                rows_g = gv.reshape(gv.shape[0], -1) if gv.ndim > 1 else gv.reshape(1, -1)
+                rows_y = y.reshape(rows_g.shape)
+                num = np.sqrt(np.sum((rows_g - rows_y) ** 2, axis=1))
+                den = np.maximum(np.sqrt(np.sum(rows_y ** 2, axis=1)), 1e-300)
+                err = float(np.max(num / den)) if g.size else 0.0
+            if err > tol:
+                bad.append("%s: spectral rel err %.3e > %.3e" % (buf.name, err, tol))
+            continue
         if b not in tainted:
             y = o32[buf.name]
             if buf.dtype == "f64":

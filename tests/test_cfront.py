@@ -24,7 +24,7 @@ def _norm(n):
     return n
 
 
-@pytest.mark.parametrize("name", ["tiny", "medium", "precision", "large", "batch"])
+@pytest.mark.parametrize("name", ["tiny", "medium", "precision", "large", "batch", "spectral"])
 def test_c_source_parses_to_the_description(name):
     got = cfront.load(os.path.join(APPS, name + ".c"))
     with open(os.path.join(APPS, name + ".json")) as f:
@@ -184,3 +184,26 @@ def test_offloaded_source_marks_the_gene():
     with pytest.raises(cfront.CError, match="begin its line"):
         cfront.offloaded_source(DECLS + "{ } for (int i = 0; i < R; i++) for (int j = 0; j < CC; j++) Y[i][j] = X[i][j];",
                                 [(0, 0, 0)], [1])
+
+
+def test_library_call_is_a_function_block():
+    path = os.path.join(APPS, "spectral.c")
+    doc = cfront.load(path)
+    fft = doc["program"][1]
+    assert (fft["nest"], fft["op"], fft["args"]) == ("fft_X", "fft_rows", {"x": "X"})
+    app = ofl.App(path)
+    v = app.verdicts()
+    assert v == [tuple(x) for x in D.check_app(ir.load(doc))]
+    assert v[1] == (D.PARALLEL, D.R_NONE, 1)          # the call holds gene bit 1
+    with open(path) as f:
+        src = f.read()
+    text = cfront.offloaded_source(src, v, [1, 1, 0, 1])
+    lines = text.split("\n")
+    i = lines.index("/* function block: the GPU implementation replaces this call */")
+    assert lines[i + 1] == "fft_rows(X);"
+    assert text.count("#pragma acc kernels") == 2
+    assert cfront.parse(text, "spectral") == doc
+    with pytest.raises(cfront.CError, match="not a known library routine"):
+        cfront.parse(DECLS + "qsort(X);", "t")
+    with pytest.raises(cfront.CError, match="2-D float"):
+        cfront.parse(DECLS + "fft_rows(t);", "t")

@@ -431,6 +431,51 @@ def test_eval_population_and_ga_tiny():
     say("GA best gene", res["best_gene"], "exhaustive best", genes[best_idx], "rank", rank)
 
 
+# ---------------------------------------------------------------- FFT call
+@pytest.mark.parametrize("R,n", [(1, 1), (3, 2), (5, 4), (7, 8), (37, 64), (16, 128), (9, 256), (33, 512),
+                                 (64, 1024), (20, 2048)])
+def test_fft_rows_shapes(R, n):
+    # the function block on the GPU (gene 1) and its CPU form (gene 0),
+    # each row within the FFT error bound of the exact transform
+    from oracle.dft import dft_rows
+    X = np.random.default_rng(R * 4099 + n).standard_normal((R, 2 * n)).astype(np.float32)
+    doc = appgen.fft_app(R, n)
+    app, bufs = _run_and_compare(doc, [[0], [1]], inputs={"X": X})
+    ref = dft_rows(X)
+    outs = {}
+    for g in (0, 1):
+        app.run_pattern([g], bufs, flags=ofl.KEEP_OUTPUTS)
+        outs[g] = app.read_buffer("X").copy()
+        err = np.max(np.linalg.norm(outs[g] - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-300))
+        assert err <= parity.rel_fft(n) + 2.0 ** -23, (g, err)
+    say("fft", R, n, "GPU and CPU forms identical bits:", bool(np.array_equal(outs[0].view(np.uint32),
+                                                                           outs[1].view(np.uint32))))
+
+
+def test_fft_rows_full_size_sampled():
+    # 8192 rows of 1024 points (64 MB), the launch the kernel benchmark times:
+    # sampled rows against the exact transform
+    from oracle.dft import dft_rows
+    R, n = 8192, 1024
+    X = np.random.default_rng(5).standard_normal((R, 2 * n)).astype(np.float32)
+    app = ofl.App(json.dumps(appgen.fft_app(R, n)))
+    app.set_input("X", X)
+    bufs = app.alloc_device_buffers()
+    say("case fft 8192 x 1024 sampled")
+    assert app.run_pattern([1], bufs, flags=ofl.KEEP_OUTPUTS)["status"] == ofl.ST_OK
+    Y = app.read_buffer("X")
+    rows = np.concatenate([[0, R - 1], np.random.default_rng(1).choice(R, 30, replace=False)])
+    ref = dft_rows(X[rows])
+    err = np.max(np.linalg.norm(Y[rows] - ref, axis=1) / np.linalg.norm(ref, axis=1))
+    assert err <= parity.rel_fft(n) + 2.0 ** -23, err
+
+
+def test_spectral_all_genes():
+    doc = workloads.app_doc("spectral", R=37, M=512)
+    genes = [[(idx >> i) & 1 for i in range(4)] for idx in range(16)]
+    _run_and_compare(doc, genes)
+
+
 def test_search_from_c_source(tmp_path, capsys):
     # the whole flow from C source: parse, check, GA over measured runs,
     # the program written back with the best gene's directives; the parsed

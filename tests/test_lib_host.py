@@ -36,7 +36,7 @@ def test_status_strings():
         assert L.ofl_status_str(code) != b"unknown status"
 
 
-@pytest.mark.parametrize("name", ["tiny", "medium", "precision", "large"])
+@pytest.mark.parametrize("name", ["tiny", "medium", "precision", "large", "spectral"])
 def test_verdicts_match_oracle(name):
     app = ofl.App(workloads.app_path(name))
     o = ir.load(workloads.app_path(name))
@@ -103,7 +103,7 @@ def test_plans_random_genes_match_oracle(name):
                 assert app.plan_transfers(g, pol, flags) == xfer.totals(o, pl, pol, flags)
 
 
-@pytest.mark.parametrize("name", ["tiny", "medium", "large"])
+@pytest.mark.parametrize("name", ["tiny", "medium", "large", "spectral"])
 def test_sections_plans_match_oracle(name):
     app = ofl.App(workloads.app_path(name))
     o = ir.load(workloads.app_path(name))
@@ -378,3 +378,17 @@ def test_ga_study_statistics_on_a_table():
         assert got["mean_measured"] == float(np.mean(measured))
         assert abs(got["mean_search_s"] - float(np.mean(cost))) < 1e-9
     assert "| 16 | 8 |" in ga_study.table(res)
+
+
+@pytest.mark.parametrize("R,n,ok", [(4, 1, True), (4, 2048, True), (3, 3, False), (2, 4096, False), (2, 12, False)])
+def test_fft_call_shapes(R, n, ok):
+    # the FFT function block takes rows of n complex values, n a power of two
+    # up to 2048; anything else is an invalid application
+    from workloads import appgen
+    doc = appgen.fft_app(R, n)
+    if ok:
+        app = ofl.App(json.dumps(doc))
+        assert app.verdicts() == [(D.PARALLEL, D.R_NONE, 0)]
+    else:
+        with pytest.raises(ofl.OflError):
+            ofl.App(json.dumps(doc))

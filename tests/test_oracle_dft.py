@@ -1,0 +1,97 @@
+"""Pins of the FFT function block's oracle (the DFT by its definition):
+closed forms that catch a wrong sign of the exponent, swapped real and
+imaginary parts or a transposed index, Parseval's identity, the shift
+theorem, and the library FFT (numpy.fft) as an independent special case."""
+import numpy as np
+import pytest
+
+from oracle.dft import dft_rows
+
+import parity
+
+
+def _interleave(z):
+    z = np.atleast_2d(z)
+    out = np.empty((z.shape[0], 2 * z.shape[1]))
+    out[:, 0::2] = z.real
+    out[:, 1::2] = z.imag
+    return out
+
+
+def _complex(x):
+    return x[:, 0::2] + 1j * x[:, 1::2]
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 64, 1024])
+def test_delta_gives_ones(n):
+    z = np.zeros(n, complex)
+    z[0] = 1
+    assert np.array_equal(_complex(dft_rows(_interleave(z))), np.ones((1, n), complex))
+
+
+@pytest.mark.parametrize("n", [4, 16, 256])
+def test_tone_lands_in_its_bin(n):
+    j = np.arange(n)
+    for m in (1, 3 % n, n // 2, n - 1):
+        z = np.exp(2j * np.pi * m * j / n)        # exp(+2 pi i m j / n)
+        Z = _complex(dft_rows(_interleave(z)))[0]
+        want = np.zeros(n, complex)
+        want[m] = n                               # forward transform: peak at +m, not n - m
+        assert np.max(np.abs(Z - want)) < 1e-9 * n, (n, m)
+
+
+def test_imaginary_delta_and_constant():
+    n = 4
+    z = np.zeros(n, complex)
+    z[1] = 1j                                      # x = i delta_1: X[k] = i exp(-2 pi i k / 4) = i (-i)^k
+    Z = _complex(dft_rows(_interleave(z)))[0]
+    assert np.allclose(Z, [1j, 1, -1j, -1], atol=1e-15)
+    c = 0.75 - 2.5j
+    Z = _complex(dft_rows(_interleave(np.full(8, c))))[0]
+    assert abs(Z[0] - 8 * c) < 1e-13 and np.max(np.abs(Z[1:])) < 1e-13
+    # n = 2: sum and difference; n = 1: identity
+    Z = _complex(dft_rows(_interleave(np.array([2 + 1j, -3 + 0.5j]))))[0]
+    assert np.allclose(Z, [-1 + 1.5j, 5 + 0.5j], rtol=0, atol=1e-15)
+    assert np.array_equal(dft_rows(np.array([[1.5, -2.0]])), [[1.5, -2.0]])
+
+
+def test_parseval_shift_and_library_fft():
+    rng = np.random.default_rng(4)
+    for n in (2, 8, 128, 512):
+        z = rng.standard_normal((5, n)) + 1j * rng.standard_normal((5, n))
+        Z = _complex(dft_rows(_interleave(z)))
+        assert np.allclose(np.sum(np.abs(Z) ** 2, axis=1), n * np.sum(np.abs(z) ** 2, axis=1), rtol=1e-12)
+        ref = np.fft.fft(z, axis=1)
+        assert np.max(np.linalg.norm(Z - ref, axis=1) / np.linalg.norm(ref, axis=1)) < 1e-12
+        s = 3 % n                                  # circular shift by s multiplies bin k by exp(-2 pi i k s / n)
+        Zs = _complex(dft_rows(_interleave(np.roll(z, s, axis=1))))
+        k = np.arange(n)
+        assert np.allclose(Zs, Z * np.exp(-2j * np.pi * k * s / n), atol=1e-9 * n)
+
+
+def test_fft_bound_values():
+    # the parity bound grows with log2 n and stays at a few u per pass
+    u = 2.0 ** -24
+    assert parity.rel_fft(1) == 0.0
+    assert 6.6 * u < parity.rel_fft(2) < 6.7 * u
+    assert 11 * 6.6 * u < parity.rel_fft(2048) < 11 * 6.7 * u
+    # a plain FP32 radix-2 FFT (numpy in float32 arithmetic, exact twiddles
+    # rounded once) stays inside it
+    rng = np.random.default_rng(9)
+    for n in (8, 256, 2048):
+        z = (rng.standard_normal((4, n)) + 1j * rng.standard_normal((4, n))).astype(np.complex64)
+        y = z.copy()
+        w = np.exp(-2j * np.pi * np.arange(n // 2) / n).astype(np.complex64)
+        ns = 1
+        while ns < n:
+            j = np.arange(n // 2)
+            k = j % ns
+            a, b = y[:, j], y[:, j + n // 2] * w[k * (n // (2 * ns))]
+            out = np.empty_like(y)
+            o = (j - k) * 2 + k
+            out[:, o] = a + b
+            out[:, o + ns] = a - b
+            y, ns = out, ns * 2
+        ref = _complex(dft_rows(_interleave(z.astype(complex))))
+        err = np.max(np.linalg.norm(y - ref, axis=1) / np.linalg.norm(ref, axis=1))
+        assert err < parity.rel_fft(n), (n, err)

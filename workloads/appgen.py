@@ -116,6 +116,15 @@ def lcg_nest(L, seed32):
             "loops": [["e", "0", "N"]], "access": [[L, "w", "e"]], "flags": ["opaque_call"]}
 
 
+def fft_nest(x, rows="R", width="M"):
+    """The FFT library call on x[rows][width] (width = 2n floats per row: n
+    complex values, interleaved) as a function block: one gene bit; its
+    iteration space is the rows and the floats of a row, all read and written
+    in place."""
+    return {"nest": "fft_" + x, "op": "fft_rows", "args": {"x": x},
+            "loops": [["r", "0", rows], ["e", "0", width]], "access": [[x, "rw", "r", "e"]]}
+
+
 def mat(name, output=False, dtype="f32"):
     return {"name": name, "dtype": dtype, "dims": ["N", "N"], "setup": "zero", "output": output}
 
@@ -201,7 +210,25 @@ def batch():
             "program": [init_nest(["A", "B"], [0, 1]), gemm_nest("A", "B", "C"), sweep_block()]}
 
 
-APPS = {"tiny": tiny, "medium": medium, "precision": precision, "large": large, "batch": batch}
+def spectral():
+    """Spectra of R rows of n = M/2 complex samples: random samples, the FFT
+    call, the total energy (Parseval: n times the samples' energy), the
+    spectra scaled by 1/n."""
+    rows = [["i", "0", "R"], ["j", "0", "M"]]
+
+    def on(n):
+        n["loops"] = rows
+        return n
+    return {"name": "spectral",
+            "params": {"R": 4096, "M": 2048},
+            "buffers": [{"name": "X", "dtype": "f32", "dims": ["R", "M"], "setup": "zero", "output": True},
+                        {"name": "s", "dtype": "f64", "dims": ["1"], "setup": "zero", "output": True}],
+            "program": [on(init_nest(["X"], [0])), fft_nest("X"), on(sumsq_nest("X", "s")),
+                        on(scale_nest("X", 1.0 / 1024))]}
+
+
+APPS = {"tiny": tiny, "medium": medium, "precision": precision, "large": large, "batch": batch,
+        "spectral": spectral}
 
 
 # ---------------------------------------------------------------- test apps
@@ -224,6 +251,13 @@ def stencil_app(I, J, K, sweeps, mode=1):
             "buffers": [grid("p", "sin", True), grid("q", "zero", True),
                         {"name": "res", "dtype": "f64", "dims": ["SWEEPS"], "output": True}],
             "program": [sweep_block()]}
+
+
+def fft_app(R, n):
+    """The FFT call alone on R rows of n complex values (caller-supplied)."""
+    return {"name": "fft", "params": {"R": R, "M": 2 * n},
+            "buffers": [{"name": "X", "dtype": "f32", "dims": ["R", "M"], "output": True}],
+            "program": [fft_nest("X")]}
 
 
 def ewise_app(R, Cc):
