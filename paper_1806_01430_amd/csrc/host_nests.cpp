@@ -4,6 +4,7 @@
 // the same per-element order (everything except the GEMM and the FP64 sums).
 #include "host_nests.hpp"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -58,6 +59,14 @@ void fill_setup_sin(const Buffer &b, float *dst) {
             float *row = dst + (i * J + j) * K;
             for (int64_t k = 0; k < K; ++k) row[k] = (float)(sij * sk[k]);
         }
+    }
+}
+
+void fft_twiddle_table(float *w) {
+    for (int64_t m = 0; m < kFftMaxPoints / 2; ++m) {
+        const double th = kTwoPi * (double)m / (double)kFftMaxPoints;
+        w[2 * m] = (float)std::cos(th);
+        w[2 * m + 1] = (float)-std::sin(th);
     }
 }
 
@@ -238,13 +247,9 @@ bool run_host_nest(const AppIR &app, const Nest &n, const std::vector<void *> &h
         // the CPU form of the FFT call: the same radix-2 self-sorting
         // (Stockham) passes as the GPU kernel, per row
         const Buffer &x = app.bufs[n.b[0]];
-        const int64_t rows = x.dims[0], pts = x.dims[1] / 2, half = pts / 2;
-        std::vector<float> w(2 * half), a(2 * pts), b(2 * pts);
-        for (int64_t m = 0; m < half; ++m) {
-            const double th = kTwoPi * (double)m / (double)pts;
-            w[2 * m] = (float)std::cos(th);
-            w[2 * m + 1] = (float)-std::sin(th);
-        }
+        const int64_t rows = x.dims[0], pts = x.dims[1] / 2, half = pts / 2, ws = kFftMaxPoints / std::max<int64_t>(pts, 1);
+        std::vector<float> w(kFftMaxPoints), a(2 * pts), b(2 * pts);
+        fft_twiddle_table(w.data());
         float *X = F(0);
         for (int64_t r = 0; r < rows; ++r) {
             if ((r & 15) == 0 && dl.expired()) return false;
@@ -255,7 +260,7 @@ bool run_host_nest(const AppIR &app, const Nest &n, const std::vector<void *> &h
                     const int64_t k = j & (ns - 1), o = ((j - k) << 1) + k;
                     const float ur = a[2 * j], ui = a[2 * j + 1];
                     const float vr0 = a[2 * (j + half)], vi0 = a[2 * (j + half) + 1];
-                    const float tr = w[2 * k * st], ti = w[2 * k * st + 1];
+                    const float tr = w[2 * k * st * ws], ti = w[2 * k * st * ws + 1];
                     const float vr = vr0 * tr - vi0 * ti;
                     const float vi = vr0 * ti + vi0 * tr;
                     b[2 * o] = ur + vr;

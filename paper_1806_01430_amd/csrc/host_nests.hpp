@@ -28,4 +28,12 @@ uint64_t uniform_stream_key(uint64_t seed, uint32_t stream);
 // Set-up content of a buffer (sine-mode field), written into `dst`.
 void fill_setup_sin(const Buffer &b, float *dst);
 
+// Twiddles of the FFT function block: w[2m], w[2m+1] = cos, -sin of
+// 2 pi m / kFftMaxPoints (computed in double, rounded once), m <
+// kFftMaxPoints / 2.  A row of n points uses entries m * (kFftMaxPoints / n):
+// the angle 2 pi (m s) / (n s) is the same double for a power-of-two s.  The
+// CPU form and the GPU kernel read this one table, so both multiply by the
+// same values.
+void fft_twiddle_table(float *w);
+
 }  // namespace ofl

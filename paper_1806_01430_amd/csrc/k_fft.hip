@@ -1,17 +1,26 @@
 // The FFT function block: the GPU implementation swapped in for an FFT
 // library call (the analysis of Sec. 3.2, steps 1-2 and 1-3, finds FFT
-// library calls beside loop statements as offloadable parts).  Each row of n complex values (real and imaginary
-// parts interleaved, n a power of two) is replaced by its forward DFT
+// library calls beside loop statements as offloadable parts).  Each row of n
+// complex values (real and imaginary parts interleaved, n a power of two) is
+// replaced by its forward DFT
 //   X[k] = sum_j x[j] exp(-2 pi i j k / n),
 // computed by radix-2 self-sorting (Stockham) passes: in pass s (half-size
-// ns = 2^s) butterfly j pairs a[j] and a[j + n/2], scales the second by the
-// twiddle exp(-2 pi i k / (2 ns)) with k = j mod ns, and writes the sum and
-// difference to positions (j - k) * 2 + k and that + ns of the other buffer;
-// after log2 n passes the spectrum is in natural order.
+// ns = 2^s) butterfly j pairs a[j] and a[j + n/2], multiplies the second by
+// the twiddle w(k n / (2 ns)) = exp(-2 pi i k / (2 ns)) with k = j mod ns,
+// and writes the sum to position 2 (j - k) + k and the difference ns further
+// on; after log2 n passes the spectrum is in natural order.
 //
-// One block per row: the row, a second buffer and the n/2 twiddles
-// exp(-2 pi i m / n) (computed in double, rounded once) live in LDS, so a row
-// is read from HBM once and written once; 40 KB of LDS at n = 2048.
+// Two passes run back to back in registers: pass s's butterflies g and
+// g + n/4 produce exactly the four inputs of pass s+1's butterflies
+// (g div ns) 2 ns + k and that + ns, so one thread takes a[g + m n/4],
+// m = 0..3, does the four butterflies and stores four outputs at
+// (g div ns) 4 ns + k + m ns.  The butterflies and their operands are those
+// of the plain radix-2 passes, so the result has the same bits as the CPU
+// form (host_nests.cpp), at half the LDS round trips and barriers.  The
+// first pair reads the row from HBM, the last writes it back; odd log2 n
+// begins with one plain pass.  One block per row; the row, a second buffer
+// and the n/2 twiddles live in LDS.  Rows of 1024 and 2048 points take the
+// register form below.
 #include "kernels.hpp"
 #include "launch.hpp"
 
@@ -21,45 +30,157 @@ namespace k {
 namespace {
 
 constexpr int kFftMaxPoints = 2048;
-constexpr double kTwoPi = 6.283185307179586;   // 2 pi rounded to double
+constexpr int kFftThreads = 256;
 
-__global__ __launch_bounds__(256) void k_fft_rows(float2 *__restrict__ x, int n) {
-    extern __shared__ float2 lds[];
+__device__ inline float2 cmul(float2 v, float2 t) {
+    return make_float2(v.x * t.x - v.y * t.y, v.x * t.y + v.y * t.x);
+}
+
+// One plain radix-2 pass (half-size ns): src -> dst.
+__device__ inline void pass1(const float2 *__restrict__ src, float2 *__restrict__ dst, const float2 *w, int n,
+                             int ns, int st) {
     const int half = n >> 1;
+    for (int j = threadIdx.x; j < half; j += blockDim.x) {
+        const int k = j & (ns - 1), o = ((j - k) << 1) + k;
+        const float2 u = src[j], v = cmul(src[j + half], w[k * st]);
+        dst[o] = make_float2(u.x + v.x, u.y + v.y);
+        dst[o + ns] = make_float2(u.x - v.x, u.y - v.y);
+    }
+}
+
+// Passes s and s + 1 (half-sizes ns and 2 ns): src -> dst.
+__device__ inline void pass2(const float2 *__restrict__ src, float2 *__restrict__ dst, const float2 *w, int n,
+                             int ns) {
+    const int q4 = n >> 2, st = n / (2 * ns), st2 = st >> 1;
+    for (int g = threadIdx.x; g < q4; g += blockDim.x) {
+        const int k = g & (ns - 1), base = ((g - k) << 2) + k;
+        const float2 x0 = src[g], x1 = src[g + q4], x2 = src[g + 2 * q4], x3 = src[g + 3 * q4];
+        const float2 t = w[k * st];
+        const float2 m2 = cmul(x2, t), m3 = cmul(x3, t);
+        const float2 u0 = make_float2(x0.x + m2.x, x0.y + m2.y), v0 = make_float2(x0.x - m2.x, x0.y - m2.y);
+        const float2 u1 = make_float2(x1.x + m3.x, x1.y + m3.y), v1 = make_float2(x1.x - m3.x, x1.y - m3.y);
+        const float2 p = cmul(u1, w[k * st2]), r = cmul(v1, w[(k + ns) * st2]);
+        dst[base] = make_float2(u0.x + p.x, u0.y + p.y);
+        dst[base + 2 * ns] = make_float2(u0.x - p.x, u0.y - p.y);
+        dst[base + ns] = make_float2(v0.x + r.x, v0.y + r.y);
+        dst[base + 3 * ns] = make_float2(v0.x - r.x, v0.y - r.y);
+    }
+}
+
+__global__ __launch_bounds__(kFftThreads) void k_fft_rows(float2 *__restrict__ x, const float2 *__restrict__ tw,
+                                                          int n, int logn) {
+    extern __shared__ float2 lds[];
     float2 *a = lds, *b = lds + n, *w = lds + 2 * n;
     float2 *xr = x + (int64_t)blockIdx.x * n;
-    for (int m = threadIdx.x; m < half; m += blockDim.x) {
-        const double th = kTwoPi * (double)m / (double)n;
-        w[m] = make_float2((float)cos(th), (float)-sin(th));
-    }
-    for (int e = threadIdx.x; e < n; e += blockDim.x) a[e] = xr[e];
+    const int half = n >> 1, tws = kFftMaxPoints / n;
+    for (int m = threadIdx.x; m < half; m += blockDim.x) w[m] = tw[m * tws];
     __syncthreads();
-    for (int ns = 1, st = half; ns < n; ns <<= 1, st >>= 1) {
-        for (int j = threadIdx.x; j < half; j += blockDim.x) {
-            const int k = j & (ns - 1), o = ((j - k) << 1) + k;
-            const float2 u = a[j], v = a[j + half], t = w[k * st];
-            const float vr = v.x * t.x - v.y * t.y;
-            const float vi = v.x * t.y + v.y * t.x;
-            b[o] = make_float2(u.x + vr, u.y + vi);
-            b[o + ns] = make_float2(u.x - vr, u.y - vi);
-        }
+    int s = 0;
+    const float2 *src = xr;
+    if (logn & 1) {
+        // one plain pass first; with n = 2 it is the whole transform
+        pass1(xr, logn == 1 ? xr : a, w, n, 1, half);
+        if (logn == 1) return;
         __syncthreads();
-        float2 *tmp = a;
-        a = b;
-        b = tmp;
+        src = a;
+        s = 1;
     }
-    for (int e = threadIdx.x; e < n; e += blockDim.x) xr[e] = a[e];
+    float2 *spare = (src == a) ? b : a;
+    for (; s < logn; s += 2) {
+        const bool last = s + 2 >= logn;
+        float2 *dst = last ? xr : spare;
+        pass2(src, dst, w, n, 1 << s);
+        if (last) break;
+        __syncthreads();
+        spare = const_cast<float2 *>(src == xr ? b : src);
+        src = dst;
+    }
+}
+
+// Rows of 1024 and 2048 points: sixteen points per thread in registers, so
+// four passes run per register stage (passes s..s+3 on the group a[g + m n/16],
+// m = 0..15); stages at s = 0, 4 and 8 (the last of 2 or 3 passes), the
+// first reading the row from HBM, the last writing it, with two LDS
+// exchanges between them.  Within a stage the element at register index
+// i = (m' << t) | d after t passes pairs with the one whose top bit differs;
+// the pass's twiddle index is ((d << s) | k) n / 2^(s+t+1) with k = g mod 2^s,
+// the d bits being the sum/difference choices of the passes done so far
+// (latest highest).  After the stage register D goes to position
+// (g - k) 2^r + k + D 2^s: the same butterflies on the same values as the
+// plain passes.  LDS positions are padded by one slot per sixteen, which
+// keeps the strided stores of the first two stages at two lanes per bank.
+__device__ inline int fft_pad(int p) { return p + (p >> 4); }
+
+template <int R, int S, int LOGN>
+__device__ inline void fft_stage(float2 (&v)[1 << R], const float2 *__restrict__ tw, int k) {
+    constexpr int R2 = 1 << R, H = R2 >> 1, N = 1 << LOGN, TWS = kFftMaxPoints >> LOGN;
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+        float2 nv[R2];
+#pragma unroll
+        for (int rest = 0; rest < H; ++rest) {
+            const int dbits = rest & ((1 << t) - 1), mlow = rest >> t;
+            const float2 w = tw[(((dbits << S) | k) * (N >> (S + t + 1))) * TWS];
+            const float2 a = v[rest], b = cmul(v[rest + H], w);
+            nv[(mlow << (t + 1)) | dbits] = make_float2(a.x + b.x, a.y + b.y);
+            nv[(mlow << (t + 1)) | (1 << t) | dbits] = make_float2(a.x - b.x, a.y - b.y);
+        }
+#pragma unroll
+        for (int i = 0; i < R2; ++i) v[i] = nv[i];
+    }
+}
+
+template <int LOGN>
+__global__ __launch_bounds__((1 << LOGN) / 16) void k_fft_rows16(float2 *__restrict__ x,
+                                                                   const float2 *__restrict__ tw) {
+    constexpr int N = 1 << LOGN, G16 = N / 16, R3 = LOGN - 8, G3 = N >> R3;
+    __shared__ float2 lds[N + N / 16];
+    float2 *xr = x + (int64_t)blockIdx.x * N;
+    const int tid = threadIdx.x;   // one 16-point group per thread in the first two stages
+    {
+        float2 v[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v[m] = xr[tid + m * G16];
+        fft_stage<4, 0, LOGN>(v, tw, 0);
+#pragma unroll
+        for (int d = 0; d < 16; ++d) lds[fft_pad((tid << 4) + d)] = v[d];
+    }
+    __syncthreads();
+    {
+        float2 v[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v[m] = lds[fft_pad(tid + m * G16)];
+        __syncthreads();   // every read of this stage before its stores
+        const int k = tid & 15;
+        fft_stage<4, 4, LOGN>(v, tw, k);
+#pragma unroll
+        for (int d = 0; d < 16; ++d) lds[fft_pad(((tid - k) << 4) + k + (d << 4))] = v[d];
+    }
+    __syncthreads();
+    for (int g = tid; g < G3; g += G16) {   // G3 = 256 groups of 2^R3 points; k = g
+        float2 v[1 << R3];
+#pragma unroll
+        for (int m = 0; m < (1 << R3); ++m) v[m] = lds[fft_pad(g + m * G3)];
+        fft_stage<R3, 8, LOGN>(v, tw, g);
+#pragma unroll
+        for (int d = 0; d < (1 << R3); ++d) xr[g + (d << 8)] = v[d];
+    }
 }
 
 }  // namespace
 
-hipError_t fft_rows(float *x, int64_t rows, int64_t n, hipStream_t s) {
-    if (rows <= 0 || n <= 0) return hipSuccess;
-    if (n > kFftMaxPoints || (n & (n - 1)) != 0 || rows > 0x7FFFFFFF) return hipErrorInvalidValue;
-    const int threads = n >= 512 ? 256 : (n >= 128 ? (int)(n / 2) : 64);
+hipError_t fft_rows(float *x, int64_t rows, int64_t n, const float *tw, hipStream_t s) {
+    if (rows <= 0 || n <= 1) return hipSuccess;   // a 1-point transform is the identity
+    if (n > kFftMaxPoints || (n & (n - 1)) != 0 || rows > 0x7FFFFFFF || tw == nullptr) return hipErrorInvalidValue;
+    const float2 *t2 = reinterpret_cast<const float2 *>(tw);
+    float2 *x2 = reinterpret_cast<float2 *>(x);
+    if (n == 1024) return launch(k_fft_rows16<10>, dim3((unsigned)rows), dim3(64), 0, s, x2, t2);
+    if (n == 2048) return launch(k_fft_rows16<11>, dim3((unsigned)rows), dim3(128), 0, s, x2, t2);
+    int logn = 0;
+    while ((1ll << logn) < n) ++logn;
+    const int threads = n >= 4 * kFftThreads ? kFftThreads : (n >= 256 ? (int)(n / 4) : 64);
     const uint32_t lds_bytes = (uint32_t)((2 * n + n / 2) * sizeof(float2));
-    return launch(k_fft_rows, dim3((unsigned)rows), dim3(threads), lds_bytes, s, reinterpret_cast<float2 *>(x),
-                  (int)n);
+    return launch(k_fft_rows, dim3((unsigned)rows), dim3(threads), lds_bytes, s, x2, t2, (int)n, logn);
 }
 
 }  // namespace k

@@ -115,6 +115,7 @@ struct ofl_app {
     int64_t partial_cap = 0;
     void *d_gemm_ws = nullptr;               // operand workspace of split-precision GEMM nests
     int64_t gemm_ws_bytes = 0;
+    float *d_twiddles = nullptr;             // FFT twiddle table (fft_twiddle_table), if any FFT call
 
     // state after the last completed run
     bool ran = false;
@@ -145,6 +146,7 @@ struct ofl_app {
             if (p) (void)hipFree(p);
         if (d_partials) (void)hipFree(d_partials);
         if (d_gemm_ws) (void)hipFree(d_gemm_ws);
+        if (d_twiddles) (void)hipFree(d_twiddles);
         for (auto e : events) (void)hipEventDestroy(e);
         for (auto e : chain_events) (void)hipEventDestroy(e);
     }
@@ -248,6 +250,21 @@ int ensure_device(ofl_app *app) {
         app->d_gemm_ws = w;
         app->gemm_ws_bytes = ws;
     }
+    bool fft = false;
+    for (const auto &n : app->ir.nests) fft = fft || n.op == OP_FFT_ROWS;
+    if (fft) {
+        std::vector<float> tw(kFftMaxPoints);
+        fft_twiddle_table(tw.data());
+        void *t = nullptr;
+        e = hipMalloc(&t, tw.size() * sizeof(float));
+        if (e == hipSuccess) e = hipMemcpy(t, tw.data(), tw.size() * sizeof(float), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            if (t) (void)hipFree(t);
+            (void)hipFree(mem);
+            return e == hipErrorOutOfMemory ? fail(OFL_E_NOMEM, "FFT twiddles") : hip_fail(e, "twiddle table");
+        }
+        app->d_twiddles = static_cast<float *>(t);
+    }
     app->d_partials = static_cast<double *>(mem);
     app->partial_cap = cap;
     return OFL_OK;
@@ -332,7 +349,7 @@ hipError_t launch_nest(ofl_app *app, const Nest &n, void *const *dev, const int6
     }
     case OP_FFT_ROWS: {
         const auto &d = ir.bufs[n.b[0]].dims;
-        return k::fft_rows(F(0), d[0], d[1] / 2, s);
+        return k::fft_rows(F(0), d[0], d[1] / 2, app->d_twiddles, s);
     }
     default:
         return hipErrorInvalidValue;
