@@ -130,40 +130,59 @@ __device__ inline void fft_stage(float2 (&v)[1 << R], const float2 *__restrict__
     }
 }
 
+// The transform of one row whose sixteen first-stage points per thread are
+// already in registers; ends with the row written back.
 template <int LOGN>
-__global__ __launch_bounds__((1 << LOGN) / 16) void k_fft_rows16(float2 *__restrict__ x,
-                                                                   const float2 *__restrict__ tw) {
+__device__ inline void fft_row16(float2 (&v)[16], float2 *__restrict__ xr, float2 *lds,
+                                 const float2 *__restrict__ tw) {
     constexpr int N = 1 << LOGN, G16 = N / 16, R3 = LOGN - 8, G3 = N >> R3;
-    __shared__ float2 lds[N + N / 16];
-    float2 *xr = x + (int64_t)blockIdx.x * N;
     const int tid = threadIdx.x;   // one 16-point group per thread in the first two stages
-    {
-        float2 v[16];
+    fft_stage<4, 0, LOGN>(v, tw, 0);
 #pragma unroll
-        for (int m = 0; m < 16; ++m) v[m] = xr[tid + m * G16];
-        fft_stage<4, 0, LOGN>(v, tw, 0);
-#pragma unroll
-        for (int d = 0; d < 16; ++d) lds[fft_pad((tid << 4) + d)] = v[d];
-    }
+    for (int d = 0; d < 16; ++d) lds[fft_pad((tid << 4) + d)] = v[d];
     __syncthreads();
-    {
-        float2 v[16];
 #pragma unroll
-        for (int m = 0; m < 16; ++m) v[m] = lds[fft_pad(tid + m * G16)];
-        __syncthreads();   // every read of this stage before its stores
-        const int k = tid & 15;
-        fft_stage<4, 4, LOGN>(v, tw, k);
+    for (int m = 0; m < 16; ++m) v[m] = lds[fft_pad(tid + m * G16)];
+    __syncthreads();   // every read of this stage before its stores
+    const int k = tid & 15;
+    fft_stage<4, 4, LOGN>(v, tw, k);
 #pragma unroll
-        for (int d = 0; d < 16; ++d) lds[fft_pad(((tid - k) << 4) + k + (d << 4))] = v[d];
-    }
+    for (int d = 0; d < 16; ++d) lds[fft_pad(((tid - k) << 4) + k + (d << 4))] = v[d];
     __syncthreads();
     for (int g = tid; g < G3; g += G16) {   // G3 = 256 groups of 2^R3 points; k = g
-        float2 v[1 << R3];
+        float2 w[1 << R3];
 #pragma unroll
-        for (int m = 0; m < (1 << R3); ++m) v[m] = lds[fft_pad(g + m * G3)];
-        fft_stage<R3, 8, LOGN>(v, tw, g);
+        for (int m = 0; m < (1 << R3); ++m) w[m] = lds[fft_pad(g + m * G3)];
+        fft_stage<R3, 8, LOGN>(w, tw, g);
 #pragma unroll
-        for (int d = 0; d < (1 << R3); ++d) xr[g + (d << 8)] = v[d];
+        for (int d = 0; d < (1 << R3); ++d) xr[g + (d << 8)] = w[d];
+    }
+}
+
+// Two rows per block: both rows' loads are issued first, so the second row
+// streams in from HBM while the first is transformed.
+constexpr int kFftRowsPerBlock = 2;
+
+template <int LOGN>
+__global__ __launch_bounds__((1 << LOGN) / 16) void k_fft_rows16(float2 *__restrict__ x,
+                                                                   const float2 *__restrict__ tw, int64_t rows) {
+    constexpr int N = 1 << LOGN, G16 = N / 16;
+    __shared__ float2 lds[N + N / 16];
+    const int64_t r0 = (int64_t)blockIdx.x * kFftRowsPerBlock;
+    const bool two = r0 + 1 < rows;
+    float2 *x0 = x + r0 * N, *x1 = x0 + N;
+    const int tid = threadIdx.x;
+    float2 v0[16], v1[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) v0[m] = x0[tid + m * G16];
+    if (two) {
+#pragma unroll
+        for (int m = 0; m < 16; ++m) v1[m] = x1[tid + m * G16];
+    }
+    fft_row16<LOGN>(v0, x0, lds, tw);
+    if (two) {
+        __syncthreads();   // the first row's last LDS reads before the second row's stores
+        fft_row16<LOGN>(v1, x1, lds, tw);
     }
 }
 
@@ -174,8 +193,9 @@ hipError_t fft_rows(float *x, int64_t rows, int64_t n, const float *tw, hipStrea
     if (n > kFftMaxPoints || (n & (n - 1)) != 0 || rows > 0x7FFFFFFF || tw == nullptr) return hipErrorInvalidValue;
     const float2 *t2 = reinterpret_cast<const float2 *>(tw);
     float2 *x2 = reinterpret_cast<float2 *>(x);
-    if (n == 1024) return launch(k_fft_rows16<10>, dim3((unsigned)rows), dim3(64), 0, s, x2, t2);
-    if (n == 2048) return launch(k_fft_rows16<11>, dim3((unsigned)rows), dim3(128), 0, s, x2, t2);
+    const dim3 pairs((unsigned)((rows + kFftRowsPerBlock - 1) / kFftRowsPerBlock));
+    if (n == 1024) return launch(k_fft_rows16<10>, pairs, dim3(64), 0, s, x2, t2, rows);
+    if (n == 2048) return launch(k_fft_rows16<11>, pairs, dim3(128), 0, s, x2, t2, rows);
     int logn = 0;
     while ((1ll << logn) < n) ++logn;
     const int threads = n >= 4 * kFftThreads ? kFftThreads : (n >= 256 ? (int)(n / 4) : 64);
