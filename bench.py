@@ -194,9 +194,18 @@ def run_kernels_large(args):
             out["ewise_8192_" + op] = {"launches_per_run": n // runs, "ms_per_run": ms / runs, "GBps": gbs,
                                        "frac_hbm": gbs / HBM_PEAK_GBS}
     del bufs, app
-    # the FFT call on 8192 rows of 1024 complex points (64 MB): each row read
-    # and written once, 16 algorithmic bytes per point; 5 n log2 n flops a row
+    out.update(run_fft_kernel(args))
+    return out
+
+
+def run_fft_kernel(args):
+    """The FFT call on 8192 rows of 1024 complex points (64 MB): each row read
+    and written once, 16 algorithmic bytes per point; 5 n log2 n flops a row."""
     import numpy as np
+    import paper_1806_01430_amd as ofl
+    from workloads import appgen
+
+    out = {}
     R, n = 8192, 1024
     app = ofl.App(json.dumps(appgen.fft_app(R, n)), seed=1)
     app.set_input("X", np.random.default_rng(5).standard_normal((R, 2 * n)).astype(np.float32))
@@ -338,6 +347,7 @@ def main():
     ap.add_argument("--no-large", action="store_true", help="skip the 513^3-class stencil / 8192 GEMM lines")
     ap.add_argument("--large-only", action="store_true",
                     help="only the 513x513x1025 stencil and 8192 GEMM kernel lines (for profiling)")
+    ap.add_argument("--fft-only", action="store_true", help="only the FFT kernel line (for profiling)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the precision, batching and population-evaluation lines")
     ap.add_argument("--extras-only", action="store_true",
@@ -358,6 +368,9 @@ def main():
         log("bench: calibration copy (1 GiB)")
         calibration_copy()
         torch.cuda.empty_cache()
+    if args.fft_only:
+        print(json.dumps({"kernels_large": run_fft_kernel(args)}), flush=True)
+        return
     if args.large_only:
         print(json.dumps({"kernels_large": run_kernels_large(args)}), flush=True)
         return
