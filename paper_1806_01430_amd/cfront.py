@@ -15,6 +15,11 @@ as source instead of the JSON IR:
   array references, locals, ``+ - * /``, parentheses, casts ``(double)x``
   and calls ``f(...)``.
 
+A call statement of its own outside any loop, ``fft_rows(X);``, is a
+function block (the FFT library calls Sec. 3.2 names beside loop statements
+as offloadable parts): one nest with one gene bit, whose GPU and CPU forms
+are the library's own.
+
 Every top-level ``for`` is a loop nest: its loops are the for statements it
 contains, outermost first; a top-level for from 0 whose body holds only for
 statements, two or more of them, is a repeat block (the iterated sweep; the
