@@ -15,8 +15,8 @@ as source instead of the JSON IR:
   array references, locals, ``+ - * /``, parentheses, casts ``(double)x``
   and calls ``f(...)``.
 
-A call statement of its own outside any loop, ``fft_rows(X);``, is a
-function block (the FFT library calls Sec. 3.2 names beside loop statements
+A call statement of its own outside any loop, ``fft_rows(X);`` or
+``sgemm(A, B, C);``, is a function block (the FFT library calls Sec. 3.2 names beside loop statements
 as offloadable parts): one nest with one gene bit, whose GPU and CPU forms
 are the library's own.
 
@@ -247,8 +247,10 @@ PURE_CALLS = ("u01", "bf16")
 # Library routines called as statements of their own, outside any loop, that
 # the library implements on the CPU and on the GPU: each call becomes a
 # function block (one nest, one gene bit).  fft_rows(X): the forward DFT of
-# every row of X[R][2n] (n complex values per row, interleaved).
-FUNCTION_BLOCKS = {"fft_rows": "fft_rows"}
+# every row of X[R][2n] (n complex values per row, interleaved);
+# sgemm(A, B, C): C = A B (FP32 or bf16 operands by their declarations),
+# the same nest as the loop form of the product.
+FUNCTION_BLOCKS = {"fft_rows": "fft_rows", "sgemm": "gemm"}
 
 # One C snippet per operation, each the nest's definition in the evaluation
 # order the library follows; names beginning with $ are pattern variables
@@ -677,6 +679,8 @@ def _parse(src, name):
         name, args = stmt[1], stmt[2]
         if name not in FUNCTION_BLOCKS:
             raise CError("call of %s: not a known library routine (only %s)" % (name, ", ".join(FUNCTION_BLOCKS)))
+        if name == "sgemm":
+            return gemm_block_ir(stmt)
         if len(args) != 1 or args[0][0] != "var" or args[0][1] not in dtypes:
             raise CError("%s takes one declared array" % name)
         x = args[0][1]
@@ -689,6 +693,27 @@ def _parse(src, name):
         return {"nest": base if names_used[base] == 1 else "%s_%d" % (base, names_used[base]),
                 "op": FUNCTION_BLOCKS[name], "args": {"x": x},
                 "loops": [["r", "0", b["dims"][0]], ["e", "0", b["dims"][1]]], "access": [[x, "rw", "r", "e"]]}
+
+    def gemm_block_ir(stmt):
+        args = stmt[2]
+        if len(args) != 3 or any(a[0] != "var" or a[1] not in dtypes for a in args):
+            raise CError("sgemm takes three declared arrays: A, B, C")
+        A, B, Cm = (next(b for b in buffers if b["name"] == a[1]) for a in args)
+        if any(len(b["dims"]) != 2 for b in (A, B, Cm)):
+            raise CError("sgemm needs 2-D arrays")
+        if A["dims"][1] != B["dims"][0] or Cm["dims"] != [A["dims"][0], B["dims"][1]]:
+            raise CError("sgemm: C[M][N] = A[M][K] B[K][N] needs matching extents")
+        kinds = {A["dtype"], B["dtype"]}
+        if kinds not in ({"f32"}, {"bf16"}) or Cm["dtype"] != "f32":
+            raise CError("sgemm: float or bf16 operands and a float result")
+        op = "gemm_bf16" if kinds == {"bf16"} else "gemm"
+        at.append(where[id(stmt)] + ("call",))
+        a = {"A": A["name"], "B": B["name"], "C": Cm["name"]}
+        base = _NEST_NAMES[op](a)
+        names_used[base] = names_used.get(base, 0) + 1
+        return {"nest": base if names_used[base] == 1 else "%s_%d" % (base, names_used[base]), "op": op, "args": a,
+                "loops": [["i", "0", A["dims"][0]], ["j", "0", B["dims"][1]], ["k", "0", A["dims"][1]]],
+                "access": [[Cm["name"], "w", "i", "j"], [A["name"], "r", "i", "k"], [B["name"], "r", "k", "j"]]}
 
     def nest_ir(stmt, prec):
         at.append(where[id(stmt)] + ("loop",))
@@ -713,7 +738,12 @@ def _parse(src, name):
             prec = stmt[2]
             continue
         if stmt[0] == "callstmt":
-            program.append(block_ir(stmt))
+            nest = block_ir(stmt)
+            if prec is not None:
+                if nest["op"] != "gemm":
+                    raise CError("prec applies to float products only")
+                nest["args"]["prec"] = prec
+            program.append(nest)
             prec = None
             continue
         if stmt[0] != "for":

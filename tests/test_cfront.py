@@ -207,3 +207,18 @@ def test_library_call_is_a_function_block():
         cfront.parse(DECLS + "qsort(X);", "t")
     with pytest.raises(cfront.CError, match="2-D float"):
         cfront.parse(DECLS + "fft_rows(t);", "t")
+
+
+def test_matrix_product_call_is_the_product_nest():
+    # sgemm(A, B, C) as a function block gives the same nest as the loop form
+    loop = cfront.load(os.path.join(APPS, "tiny.c"))
+    with open(os.path.join(APPS, "tiny.c")) as f:
+        src = f.read()
+    i = src.index("/* C = A B */")
+    j = src.index("for (int i = 0; i < N; i++)\n    for (int j = 0; j < N; j++)\n        C[i][j] = C[i][j]")
+    call = cfront.parse(src[:i] + "#pragma ofl prec(bf16x3)\nsgemm(A, B, C);\n\n" + src[j:], "tiny")
+    want = json.loads(json.dumps(loop))
+    want["program"][1]["args"]["prec"] = "bf16x3"
+    assert [_norm(n) for n in call["program"]] == [_norm(n) for n in want["program"]]
+    with pytest.raises(cfront.CError, match="matching extents"):
+        cfront.parse(DECLS + "sgemm(X, Y, Z);", "t")
