@@ -471,9 +471,25 @@ def test_fft_rows_full_size_sampled():
 
 
 def test_spectral_all_genes():
+    # every gene under both transfer policies, eager and as graph replays
     doc = workloads.app_doc("spectral", R=37, M=512)
     genes = [[(idx >> i) & 1 for i in range(4)] for idx in range(16)]
-    _run_and_compare(doc, genes)
+    _run_and_compare(doc, genes, policies=(ofl.RESIDENT, ofl.SECTIONS), flags_list=(0, ofl.GRAPH))
+
+
+def test_spectral_population_batched():
+    # the FFT call inside one batched submission of a whole population
+    doc = workloads.app_doc("spectral", R=64, M=2048)
+    app = ofl.App(json.dumps(doc))
+    bufs = app.alloc_device_buffers()
+    genes = [[(idx >> i) & 1 for i in range(4)] for idx in range(16)]
+    say("case spectral population batched")
+    t, s = app.eval_population(genes, bufs, reps=2, warmup=1, flags=ofl.BATCHED)
+    assert np.all(s == ofl.ST_OK) and np.all(t > 0)
+    o = ir.load(doc)
+    o32, o64 = parity.oracle_outputs(o, 1)
+    assert app.run_pattern([1, 1, 1, 1], bufs, flags=ofl.GRAPH)["status"] == ofl.ST_OK
+    assert not parity.compare(o, app.read_all(), o32, o64)
 
 
 def test_search_from_c_source(tmp_path, capsys):
