@@ -8,6 +8,8 @@
 // kind (`op`) that selects the GPU kernel and the serial host code.
 #pragma once
 
+#include "fft_limits.hpp"
+
 #include <cstdint>
 #include <map>
 #include <string>
@@ -43,9 +45,6 @@ enum Op {
     OP_FFT_ROWS,        // function block: forward complex DFT of each row
     OP_COUNT
 };
-
-// Largest row of the FFT function block, in complex points.
-constexpr int64_t kFftMaxPoints = 2048;
 
 const char *op_name(Op op);
 bool op_has_device_kernel(Op op);

@@ -21,6 +21,7 @@
 // begins with one plain pass.  One block per row; the row, a second buffer
 // and the n/2 twiddles live in LDS.  Rows of 1024 and 2048 points take the
 // register form below.
+#include "fft_limits.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
 
@@ -29,7 +30,6 @@ namespace k {
 
 namespace {
 
-constexpr int kFftMaxPoints = 2048;
 constexpr int kFftThreads = 256;
 
 __device__ inline float2 cmul(float2 v, float2 t) {
