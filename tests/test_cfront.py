@@ -222,3 +222,57 @@ def test_matrix_product_call_is_the_product_nest():
     assert [_norm(n) for n in call["program"]] == [_norm(n) for n in want["program"]]
     with pytest.raises(cfront.CError, match="matching extents"):
         cfront.parse(DECLS + "sgemm(X, Y, Z);", "t")
+
+
+def _rename_nest(nest, loop_map, buf_map):
+    """A description nest with its loop variables and buffers renamed."""
+    import re as _re
+
+    def sub(text):
+        return _re.sub(r"[A-Za-z_]\w*", lambda m: loop_map.get(m.group(0), m.group(0)), text)
+    out = json.loads(json.dumps(nest))
+    out["loops"] = [[loop_map[v], lo, hi] for v, lo, hi in out["loops"]]
+    out["access"] = [[buf_map[a[0]], a[1]] + [sub(x) for x in a[2:]] for a in out["access"]]
+    out["args"] = {k: (buf_map.get(v, v) if isinstance(v, str) else v) for k, v in out["args"].items()}
+    return out
+
+
+def test_random_renamings_and_commutations_bind():
+    # each element-wise operation written with random loop and array names
+    # and randomly swapped operands of single additions and products parses
+    # to the generator's nest for the same operation, renamed
+    import random
+    from workloads import appgen
+    rng = random.Random(11)
+    names = ["P", "Q", "U", "V", "W"]
+    for trial in range(60):
+        i, j = rng.sample(["i", "j", "r", "c", "ii", "jj"], 2)
+        X, Y, Z = rng.sample(names, 3)
+
+        def sw(a, b, op):
+            return "%s %s %s" % ((a, op, b) if rng.random() < 0.5 else (b, op, a))
+        xi, yi, zi = "%s[%s][%s]" % (X, i, j), "%s[%s][%s]" % (Y, i, j), "%s[%s][%s]" % (Z, i, j)
+        kind = trial % 5
+        if kind == 0:
+            body, want = "%s = %s;" % (zi, sw(zi, sw("0.5f", xi, "*"), "+")), appgen.add_scaled_nest("C", "A", 0.5)
+            bm = {"C": Z, "A": X}
+        elif kind == 1:
+            body, want = "%s = %s;" % (zi, sw("0.5f", "(%s)" % sw(xi, yi, "+"), "*")), appgen.avg2_nest("S", "C", "T")
+            bm = {"S": Z, "C": X, "T": Y}
+            if body.count(yi) and body.index(yi) < body.index(xi):
+                bm = {"S": Z, "C": Y, "T": X}
+        elif kind == 2:
+            body, want = "%s = %s;" % (zi, sw("2.0f", zi, "*")), appgen.scale_nest("D", 2.0)
+            bm = {"D": Z}
+        elif kind == 3:
+            body, want = "%s = %s;" % (zi, xi), appgen.copy_nest("D", "C")
+            bm = {"D": Z, "C": X}
+        else:
+            body = "%s[%s][%s] = %s;" % (Z, j, i, xi)
+            want, bm = appgen.transpose_nest("C", "T"), {"C": X, "T": Z}
+        decl = "#define N 6\n" + "".join("float %s[N][N];\n" % b for b in names)
+        src = decl + "for (int %s = 0; %s < N; %s++) for (int %s = 0; %s < N; %s++) %s" % (i, i, i, j, j, j, body)
+        got = cfront.parse(src, "t")["program"][0]
+        exp = _rename_nest(want, {"i": i, "j": j}, bm)
+        assert (got["op"], got["args"], got["loops"]) == (exp["op"], exp["args"], exp["loops"]), (src, got)
+        assert sorted(map(tuple, got["access"])) == sorted(map(tuple, exp["access"])), src
