@@ -6,6 +6,6 @@
 
 namespace ofl {
 
-constexpr int kFftMaxPoints = 2048;
+constexpr int kFftMaxPoints = 4096;
 
 }  // namespace ofl

@@ -70,6 +70,17 @@ void fft_twiddle_table(float *w) {
     }
 }
 
+void fft_twiddle_packed(float *w) {
+    std::vector<float> t(kFftMaxPoints);
+    fft_twiddle_table(t.data());
+    for (int64_t n = 2; n <= kFftMaxPoints; n <<= 1)
+        for (int64_t m = 0; m < n / 2; ++m) {
+            const int64_t at = n / 2 - 1 + m, from = m * (kFftMaxPoints / n);
+            w[2 * at] = t[2 * from];
+            w[2 * at + 1] = t[2 * from + 1];
+        }
+}
+
 bool run_host_nest(const AppIR &app, const Nest &n, const std::vector<void *> &host, const int64_t *env,
                    uint64_t seed, const Deadline &dl) {
     auto F = [&](int i) { return static_cast<float *>(host[n.b[i]]); };

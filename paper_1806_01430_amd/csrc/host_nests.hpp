@@ -36,4 +36,11 @@ void fill_setup_sin(const Buffer &b, float *dst);
 // same values.
 void fft_twiddle_table(float *w);
 
+// The tables of every row length n = 2, 4, ..., kFftMaxPoints packed back to
+// back, each contiguous: the n/2 twiddles of n points start at complex
+// offset n/2 - 1 and are fft_twiddle_table's entries m * (kFftMaxPoints / n)
+// (the same values; 2 (kFftMaxPoints - 1) floats in all).  The GPU kernel
+// reads these, so its gathers stay dense at every row length.
+void fft_twiddle_packed(float *w);
+
 }  // namespace ofl

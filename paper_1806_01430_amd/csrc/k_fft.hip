@@ -19,7 +19,7 @@
 // form (host_nests.cpp), at half the LDS round trips and barriers.  The
 // first pair reads the row from HBM, the last writes it back; odd log2 n
 // begins with one plain pass.  One block per row; the row, a second buffer
-// and the n/2 twiddles live in LDS.  Rows of 1024 and 2048 points take the
+// and the n/2 twiddles live in LDS.  Rows of 1024 to 4096 points take the
 // register form below.
 #include "fft_limits.hpp"
 #include "kernels.hpp"
@@ -72,8 +72,8 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows(float2 *__restrict__ x
     extern __shared__ float2 lds[];
     float2 *a = lds, *b = lds + n, *w = lds + 2 * n;
     float2 *xr = x + (int64_t)blockIdx.x * n;
-    const int half = n >> 1, tws = kFftMaxPoints / n;
-    for (int m = threadIdx.x; m < half; m += blockDim.x) w[m] = tw[m * tws];
+    const int half = n >> 1;
+    for (int m = threadIdx.x; m < half; m += blockDim.x) w[m] = tw[m];
     __syncthreads();
     int s = 0;
     const float2 *src = xr;
@@ -97,9 +97,10 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows(float2 *__restrict__ x
     }
 }
 
-// Rows of 1024 and 2048 points: sixteen points per thread in registers, so
-// four passes run per register stage (passes s..s+3 on the group a[g + m n/16],
-// m = 0..15); stages at s = 0, 4 and 8 (the last of 2 or 3 passes), the
+// Rows of 1024, 2048 and 4096 points: sixteen points per thread in registers,
+// so four passes run per register stage (passes s..s+3 on the group
+// a[g + m n/16], m = 0..15); stages at s = 0, 4 and 8 (the last of 2, 3 or 4
+// passes), the
 // first reading the row from HBM, the last writing it, with two LDS
 // exchanges between them.  Within a stage the element at register index
 // i = (m' << t) | d after t passes pairs with the one whose top bit differs;
@@ -113,14 +114,14 @@ __device__ inline int fft_pad(int p) { return p + (p >> 4); }
 
 template <int R, int S, int LOGN>
 __device__ inline void fft_stage(float2 (&v)[1 << R], const float2 *__restrict__ tw, int k) {
-    constexpr int R2 = 1 << R, H = R2 >> 1, N = 1 << LOGN, TWS = kFftMaxPoints >> LOGN;
+    constexpr int R2 = 1 << R, H = R2 >> 1, N = 1 << LOGN;
 #pragma unroll
     for (int t = 0; t < R; ++t) {
         float2 nv[R2];
 #pragma unroll
         for (int rest = 0; rest < H; ++rest) {
             const int dbits = rest & ((1 << t) - 1), mlow = rest >> t;
-            const float2 w = tw[(((dbits << S) | k) * (N >> (S + t + 1))) * TWS];
+            const float2 w = tw[((dbits << S) | k) * (N >> (S + t + 1))];
             const float2 a = v[rest], b = cmul(v[rest + H], w);
             nv[(mlow << (t + 1)) | dbits] = make_float2(a.x + b.x, a.y + b.y);
             nv[(mlow << (t + 1)) | (1 << t) | dbits] = make_float2(a.x - b.x, a.y - b.y);
@@ -149,7 +150,7 @@ __device__ inline void fft_row16(float2 (&v)[16], float2 *__restrict__ xr, float
 #pragma unroll
     for (int d = 0; d < 16; ++d) lds[fft_pad(((tid - k) << 4) + k + (d << 4))] = v[d];
     __syncthreads();
-    for (int g = tid; g < G3; g += G16) {   // G3 = 256 groups of 2^R3 points; k = g
+    for (int g = tid; g < G3; g += G16) {   // G3 = 256 groups of 2^R3 points (16 at n = 4096); k = g
         float2 w[1 << R3];
 #pragma unroll
         for (int m = 0; m < (1 << R3); ++m) w[m] = lds[fft_pad(g + m * G3)];
@@ -191,11 +192,12 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void k_fft_rows16(float2 *__restr
 hipError_t fft_rows(float *x, int64_t rows, int64_t n, const float *tw, hipStream_t s) {
     if (rows <= 0 || n <= 1) return hipSuccess;   // a 1-point transform is the identity
     if (n > kFftMaxPoints || (n & (n - 1)) != 0 || rows > 0x7FFFFFFF || tw == nullptr) return hipErrorInvalidValue;
-    const float2 *t2 = reinterpret_cast<const float2 *>(tw);
+    const float2 *t2 = reinterpret_cast<const float2 *>(tw) + (n / 2 - 1);   // this length's table
     float2 *x2 = reinterpret_cast<float2 *>(x);
     const dim3 pairs((unsigned)((rows + kFftRowsPerBlock - 1) / kFftRowsPerBlock));
     if (n == 1024) return launch(k_fft_rows16<10>, pairs, dim3(64), 0, s, x2, t2, rows);
     if (n == 2048) return launch(k_fft_rows16<11>, pairs, dim3(128), 0, s, x2, t2, rows);
+    if (n == 4096) return launch(k_fft_rows16<12>, pairs, dim3(256), 0, s, x2, t2, rows);
     int logn = 0;
     while ((1ll << logn) < n) ++logn;
     const int threads = n >= 4 * kFftThreads ? kFftThreads : (n >= 256 ? (int)(n / 4) : 64);

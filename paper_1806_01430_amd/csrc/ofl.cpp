@@ -115,7 +115,7 @@ struct ofl_app {
     int64_t partial_cap = 0;
     void *d_gemm_ws = nullptr;               // operand workspace of split-precision GEMM nests
     int64_t gemm_ws_bytes = 0;
-    float *d_twiddles = nullptr;             // FFT twiddle table (fft_twiddle_table), if any FFT call
+    float *d_twiddles = nullptr;             // FFT twiddle tables (fft_twiddle_packed), if any FFT call
 
     // state after the last completed run
     bool ran = false;
@@ -253,8 +253,8 @@ int ensure_device(ofl_app *app) {
     bool fft = false;
     for (const auto &n : app->ir.nests) fft = fft || n.op == OP_FFT_ROWS;
     if (fft) {
-        std::vector<float> tw(kFftMaxPoints);
-        fft_twiddle_table(tw.data());
+        std::vector<float> tw(2 * (kFftMaxPoints - 1));
+        fft_twiddle_packed(tw.data());
         void *t = nullptr;
         e = hipMalloc(&t, tw.size() * sizeof(float));
         if (e == hipSuccess) e = hipMemcpy(t, tw.data(), tw.size() * sizeof(float), hipMemcpyHostToDevice);

@@ -433,7 +433,7 @@ def test_eval_population_and_ga_tiny():
 
 # ---------------------------------------------------------------- FFT call
 @pytest.mark.parametrize("R,n", [(1, 1), (3, 2), (5, 4), (7, 8), (37, 64), (16, 128), (9, 256), (33, 512),
-                                 (64, 1024), (7, 1024), (1, 1024), (20, 2048), (3, 2048)])
+                                 (64, 1024), (7, 1024), (1, 1024), (20, 2048), (3, 2048), (6, 4096), (3, 4096)])
 def test_fft_rows_shapes(R, n):
     # the function block on the GPU (gene 1) and its CPU form (gene 0),
     # each row within the FFT error bound of the exact transform

@@ -380,10 +380,10 @@ def test_ga_study_statistics_on_a_table():
     assert "| 16 | 8 |" in ga_study.table(res)
 
 
-@pytest.mark.parametrize("R,n,ok", [(4, 1, True), (4, 2048, True), (3, 3, False), (2, 4096, False), (2, 12, False)])
+@pytest.mark.parametrize("R,n,ok", [(4, 1, True), (4, 4096, True), (3, 3, False), (2, 8192, False), (2, 12, False)])
 def test_fft_call_shapes(R, n, ok):
     # the FFT function block takes rows of n complex values, n a power of two
-    # up to 2048; anything else is an invalid application
+    # up to 4096; anything else is an invalid application
     from workloads import appgen
     doc = appgen.fft_app(R, n)
     if ok:
