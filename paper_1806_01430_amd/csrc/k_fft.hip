@@ -18,9 +18,8 @@
 // of the plain radix-2 passes, so the result has the same bits as the CPU
 // form (host_nests.cpp), at half the LDS round trips and barriers.  The
 // first pair reads the row from HBM, the last writes it back; odd log2 n
-// begins with one plain pass.  One block per row; the row, a second buffer
-// and the n/2 twiddles live in LDS.  Rows of 1024 to 4096 points take the
-// register form below.
+// begins with one plain pass.  Short rows share a block (below); rows of
+// 1024 to 4096 points take the register form further down.
 #include "fft_limits.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
@@ -36,42 +35,56 @@ __device__ inline float2 cmul(float2 v, float2 t) {
     return make_float2(v.x * t.x - v.y * t.y, v.x * t.y + v.y * t.x);
 }
 
-// One plain radix-2 pass (half-size ns): src -> dst.
+// One plain radix-2 pass (half-size ns): src -> dst, by threads t of T.
+// `put` = false skips the stores (a row past the end of the array).
 __device__ inline void pass1(const float2 *__restrict__ src, float2 *__restrict__ dst, const float2 *w, int n,
-                             int ns, int st) {
+                             int ns, int st, int t, int T, bool put) {
     const int half = n >> 1;
-    for (int j = threadIdx.x; j < half; j += blockDim.x) {
+    for (int j = t; j < half; j += T) {
         const int k = j & (ns - 1), o = ((j - k) << 1) + k;
         const float2 u = src[j], v = cmul(src[j + half], w[k * st]);
-        dst[o] = make_float2(u.x + v.x, u.y + v.y);
-        dst[o + ns] = make_float2(u.x - v.x, u.y - v.y);
+        if (put) {
+            dst[o] = make_float2(u.x + v.x, u.y + v.y);
+            dst[o + ns] = make_float2(u.x - v.x, u.y - v.y);
+        }
     }
 }
 
-// Passes s and s + 1 (half-sizes ns and 2 ns): src -> dst.
+// Passes s and s + 1 (half-sizes ns and 2 ns): src -> dst, by threads t of T.
 __device__ inline void pass2(const float2 *__restrict__ src, float2 *__restrict__ dst, const float2 *w, int n,
-                             int ns) {
+                             int ns, int t, int T, bool put) {
     const int q4 = n >> 2, st = n / (2 * ns), st2 = st >> 1;
-    for (int g = threadIdx.x; g < q4; g += blockDim.x) {
+    for (int g = t; g < q4; g += T) {
         const int k = g & (ns - 1), base = ((g - k) << 2) + k;
         const float2 x0 = src[g], x1 = src[g + q4], x2 = src[g + 2 * q4], x3 = src[g + 3 * q4];
-        const float2 t = w[k * st];
-        const float2 m2 = cmul(x2, t), m3 = cmul(x3, t);
+        const float2 tw1 = w[k * st];
+        const float2 m2 = cmul(x2, tw1), m3 = cmul(x3, tw1);
         const float2 u0 = make_float2(x0.x + m2.x, x0.y + m2.y), v0 = make_float2(x0.x - m2.x, x0.y - m2.y);
         const float2 u1 = make_float2(x1.x + m3.x, x1.y + m3.y), v1 = make_float2(x1.x - m3.x, x1.y - m3.y);
         const float2 p = cmul(u1, w[k * st2]), r = cmul(v1, w[(k + ns) * st2]);
-        dst[base] = make_float2(u0.x + p.x, u0.y + p.y);
-        dst[base + 2 * ns] = make_float2(u0.x - p.x, u0.y - p.y);
-        dst[base + ns] = make_float2(v0.x + r.x, v0.y + r.y);
-        dst[base + 3 * ns] = make_float2(v0.x - r.x, v0.y - r.y);
+        if (put) {
+            dst[base] = make_float2(u0.x + p.x, u0.y + p.y);
+            dst[base + 2 * ns] = make_float2(u0.x - p.x, u0.y - p.y);
+            dst[base + ns] = make_float2(v0.x + r.x, v0.y + r.y);
+            dst[base + 3 * ns] = make_float2(v0.x - r.x, v0.y - r.y);
+        }
     }
 }
 
+// Rows of 2 to 512 points: a 256-thread block takes 256 / T rows, T =
+// max(1, n/4) threads per row (one pass-pair group each), with two LDS
+// buffers per row and one twiddle table for the block.  Threads of a row
+// past the end read row 0 and store nothing; every thread reaches every
+// barrier.
 __global__ __launch_bounds__(kFftThreads) void k_fft_rows(float2 *__restrict__ x, const float2 *__restrict__ tw,
-                                                          int n, int logn) {
+                                                          int64_t rows, int n, int logn) {
     extern __shared__ float2 lds[];
-    float2 *a = lds, *b = lds + n, *w = lds + 2 * n;
-    float2 *xr = x + (int64_t)blockIdx.x * n;
+    const int T = n >= 4 ? n >> 2 : 1, rb = kFftThreads / T;
+    const int sub = threadIdx.x / T, t = threadIdx.x - sub * T;
+    const int64_t row = (int64_t)blockIdx.x * rb + sub;
+    const bool valid = row < rows;
+    float2 *w = lds, *a = lds + (n >> 1) + 2 * sub * n, *b = a + n;
+    float2 *xr = x + (valid ? row : 0) * n;
     const int half = n >> 1;
     for (int m = threadIdx.x; m < half; m += blockDim.x) w[m] = tw[m];
     __syncthreads();
@@ -79,7 +92,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows(float2 *__restrict__ x
     const float2 *src = xr;
     if (logn & 1) {
         // one plain pass first; with n = 2 it is the whole transform
-        pass1(xr, logn == 1 ? xr : a, w, n, 1, half);
+        pass1(xr, logn == 1 ? xr : a, w, n, 1, half, t, T, logn != 1 || valid);
         if (logn == 1) return;
         __syncthreads();
         src = a;
@@ -89,7 +102,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows(float2 *__restrict__ x
     for (; s < logn; s += 2) {
         const bool last = s + 2 >= logn;
         float2 *dst = last ? xr : spare;
-        pass2(src, dst, w, n, 1 << s);
+        pass2(src, dst, w, n, 1 << s, t, T, !last || valid);
         if (last) break;
         __syncthreads();
         spare = const_cast<float2 *>(src == xr ? b : src);
@@ -198,11 +211,13 @@ hipError_t fft_rows(float *x, int64_t rows, int64_t n, const float *tw, hipStrea
     if (n == 1024) return launch(k_fft_rows16<10>, pairs, dim3(64), 0, s, x2, t2, rows);
     if (n == 2048) return launch(k_fft_rows16<11>, pairs, dim3(128), 0, s, x2, t2, rows);
     if (n == 4096) return launch(k_fft_rows16<12>, pairs, dim3(256), 0, s, x2, t2, rows);
+    if (n > 512) return hipErrorInvalidValue;
     int logn = 0;
     while ((1ll << logn) < n) ++logn;
-    const int threads = n >= 4 * kFftThreads ? kFftThreads : (n >= 256 ? (int)(n / 4) : 64);
-    const uint32_t lds_bytes = (uint32_t)((2 * n + n / 2) * sizeof(float2));
-    return launch(k_fft_rows, dim3((unsigned)rows), dim3(threads), lds_bytes, s, x2, t2, (int)n, logn);
+    const int64_t rb = kFftThreads / (n >= 4 ? n / 4 : 1);
+    const uint32_t lds_bytes = (uint32_t)((rb * 2 * n + n / 2) * sizeof(float2));
+    return launch(k_fft_rows, dim3((unsigned)((rows + rb - 1) / rb)), dim3(kFftThreads), lds_bytes, s, x2, t2, rows,
+                  (int)n, logn);
 }
 
 }  // namespace k
