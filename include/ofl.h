@@ -175,9 +175,15 @@ typedef struct {
 /* Parse an application description (JSON: params, buffers, program of loop
  * nests with affine accesses and repeat blocks), validate it and run the
  * parallelisability check of every nest (Sec. 4: loops found and counted,
- * each checked on its own; the accepted ones define the gene).  `seed` drives
- * the application's random-initialisation nests.  Allocates nothing on the
- * GPU.  Errors: OFL_E_IO, OFL_E_PARSE, OFL_E_IR, OFL_E_ARG, OFL_E_NOMEM. */
+ * each checked on its own; the accepted ones define the gene).  A nest may
+ * also be a function block, a library call given one gene bit (Sec. 3.2,
+ * steps 1-2 and 1-3, name FFT library calls beside loops): op "fft_rows",
+ * the forward DFT of every row of an f32 buffer [R][2n] (n complex values per
+ * row, interleaved; n a power of two up to 4096).  `seed` drives the
+ * application's random-initialisation nests.  Allocates nothing on the GPU
+ * (the device scratch, and for an FFT call its twiddle tables, come with the
+ * first run).  Errors: OFL_E_IO, OFL_E_PARSE, OFL_E_IR, OFL_E_ARG,
+ * OFL_E_NOMEM. */
 int ofl_app_load(const char *path, uint64_t seed, ofl_app **out);
 int ofl_app_load_json(const char *json_text, uint64_t seed, ofl_app **out);
 void ofl_app_free(ofl_app *app);
