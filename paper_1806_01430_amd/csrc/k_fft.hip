@@ -19,7 +19,7 @@
 // form (host_nests.cpp), at half the LDS round trips and barriers.  The
 // first pair reads the row from HBM, the last writes it back; odd log2 n
 // begins with one plain pass.  Short rows share a block (below); rows of
-// 1024 to 4096 points take the register form further down.
+// 256 to 4096 points take the register form further down.
 #include "fft_limits.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
@@ -71,7 +71,7 @@ __device__ inline void pass2(const float2 *__restrict__ src, float2 *__restrict_
     }
 }
 
-// Rows of 2 to 512 points: a 256-thread block takes 256 / T rows, T =
+// Rows of 2 to 128 points: a 256-thread block takes 256 / T rows, T =
 // max(1, n/4) threads per row (one pass-pair group each), with two LDS
 // buffers per row and one twiddle table for the block.  Threads of a row
 // past the end read row 0 and store nothing; every thread reaches every
@@ -200,6 +200,55 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void k_fft_rows16(float2 *__restr
     }
 }
 
+// Rows of 256 and 512 points: the same register form with T = n/16 threads
+// per row and 64 / T rows per one-wave block, each row in its own LDS area;
+// at 256 points the second stage is the last and writes the row back.
+// Threads of a row past the end read row 0 and store nothing.
+template <int LOGN>
+__global__ __launch_bounds__(64) void k_fft_rows16s(float2 *__restrict__ x, const float2 *__restrict__ tw,
+                                                     int64_t rows) {
+    constexpr int N = 1 << LOGN, T = N / 16, RW = 64 / T, R3 = LOGN - 8, P = N + N / 16;
+    __shared__ float2 lds_all[RW * P];
+    const int sub = threadIdx.x / T, tid = threadIdx.x - sub * T;
+    const int64_t row = (int64_t)blockIdx.x * RW + sub;
+    const bool valid = row < rows;
+    float2 *xr = x + (valid ? row : 0) * N;
+    float2 *lds = lds_all + sub * P;
+    float2 v[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) v[m] = xr[tid + m * T];
+    fft_stage<4, 0, LOGN>(v, tw, 0);
+#pragma unroll
+    for (int d = 0; d < 16; ++d) lds[fft_pad((tid << 4) + d)] = v[d];
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 16; ++m) v[m] = lds[fft_pad(tid + m * T)];
+    const int k = tid & 15;
+    fft_stage<4, 4, LOGN>(v, tw, k);
+    if constexpr (R3 == 0) {
+        if (valid) {
+#pragma unroll
+            for (int d = 0; d < 16; ++d) xr[((tid - k) << 4) + k + (d << 4)] = v[d];
+        }
+    } else {
+        __syncthreads();   // every read of this stage before its stores
+#pragma unroll
+        for (int d = 0; d < 16; ++d) lds[fft_pad(((tid - k) << 4) + k + (d << 4))] = v[d];
+        __syncthreads();
+        constexpr int G3 = N >> R3;   // 256 groups of 2^R3 points; k = g
+        for (int g = tid; g < G3; g += T) {
+            float2 w[1 << R3];
+#pragma unroll
+            for (int m = 0; m < (1 << R3); ++m) w[m] = lds[fft_pad(g + m * G3)];
+            fft_stage<R3, 8, LOGN>(w, tw, g);
+            if (valid) {
+#pragma unroll
+                for (int d = 0; d < (1 << R3); ++d) xr[g + (d << 8)] = w[d];
+            }
+        }
+    }
+}
+
 }  // namespace
 
 hipError_t fft_rows(float *x, int64_t rows, int64_t n, const float *tw, hipStream_t s) {
@@ -211,7 +260,9 @@ hipError_t fft_rows(float *x, int64_t rows, int64_t n, const float *tw, hipStrea
     if (n == 1024) return launch(k_fft_rows16<10>, pairs, dim3(64), 0, s, x2, t2, rows);
     if (n == 2048) return launch(k_fft_rows16<11>, pairs, dim3(128), 0, s, x2, t2, rows);
     if (n == 4096) return launch(k_fft_rows16<12>, pairs, dim3(256), 0, s, x2, t2, rows);
-    if (n > 512) return hipErrorInvalidValue;
+    if (n == 256) return launch(k_fft_rows16s<8>, dim3((unsigned)((rows + 3) / 4)), dim3(64), 0, s, x2, t2, rows);
+    if (n == 512) return launch(k_fft_rows16s<9>, dim3((unsigned)((rows + 1) / 2)), dim3(64), 0, s, x2, t2, rows);
+    if (n > 128) return hipErrorInvalidValue;
     int logn = 0;
     while ((1ll << logn) < n) ++logn;
     const int64_t rb = kFftThreads / (n >= 4 ? n / 4 : 1);
