@@ -234,6 +234,16 @@ def test_ga_trajectory_matches_oracle(a, M, T, Pc, Pm, p, seed, dl, tmo, batched
         assert got["t_all0"] == (want["t_all0"] if want["t_all0"] is not None else -1.0)
 
 
+def test_ga_worked_generation_by_hand():
+    # the generation worked out by hand from the SplitMix64 draws of state 29
+    # (tests/test_oracle_logic.py): the library's GA takes the same steps
+    from test_oracle_logic import WORKED_NEXT, worked_generation_table
+    params = ofl.ga_params(M=3, T=2, Pc=0.9, Pm=0.3, p=0.5, seed=29)
+    got = ofl.ga_run_table(4, params, worked_generation_table())
+    assert [tuple(int(x) for x in g) for g in got["pops"][0]] == [(1, 1, 1, 0), (0, 1, 1, 0), (1, 0, 1, 1)]
+    assert [tuple(int(x) for x in g) for g in got["pops"][1]] == WORKED_NEXT
+
+
 def test_batched_generations_change_only_the_deadline():
     # without deadlines, measuring a generation's genes together leaves the
     # trajectory unchanged; with deadlines the limits differ, and the batched

@@ -315,3 +315,114 @@ def test_sections_boxes_reused_and_dropped():
     # r1: rows 2..9, columns 3..5 -> 8 x 3 floats; r2 inside it; w2 drops the
     # box; r3 copies rows 4..5 column 4; r4 reads the whole array: whole copy
     assert got == [("D2H", "X", 4 * 8 * 3), ("D2H", "X", 4 * 2 * 1), ("D2H", "X", 4 * 16 * 16)]
+
+
+# ------------------------------------------------------------ GA operators
+# Pins of the GA's operators against the paper's definitions (Sec. 3.3,
+# Sec. 5.1.2: roulette selection in proportion to fitness, one elite kept
+# unchanged, one-point crossover, per-value mutation), independent of the
+# library's GA (which is compared with this oracle elsewhere).
+
+# SplitMix64 with state 29 (the generator is pinned to the published outputs
+# from state 0 above); the draws the worked generation below consumes
+_STREAM29 = [0xbb7b49ab8801cf70, 0xba57b7db607f9d1a, 0xe1b9ae67265f7887, 0x5330404c13ee7598,
+             0x14527c80ce1ad689, 0x868c79fa78c0d7ff, 0xc6b9305886e78606, 0x52042190b08a9d24,
+             0xea18a3744e5c0d78, 0x330743f27ac6ddee, 0xd8dc1ac9a40cbb0c, 0xc087f4e359a1e03c,
+             0xc18278c01db3075a, 0x950e8017dc3ab596, 0x2885f7c664c239ff, 0x15d19423ee5387c5,
+             0x9493fee70e8c82bc, 0xffe028b40f65d177, 0x69ef7462eed1a5a8, 0x8892364d1ec21082,
+             0xe9f707722d38e5e1, 0x10a553fb9e99492d, 0x4a101b61e826fb26, 0x845cb7606cf7929c]
+
+
+def worked_generation_table():
+    """Time table of the worked generation (a = 4): genes 7, 6, 13 take
+    0.25, 16 and 1 time units (fitness t^-1/2 = 2, 1/4, 1); every other gene 100."""
+    t = [100.0] * 16
+    t[7], t[6], t[13] = 0.25, 16.0, 1.0
+    return t
+
+
+# One generation of a = 4, M = 3, Pc = 0.9, Pm = 0.3, p = 1/2, seed 29,
+# worked by hand from the draws above:
+#  initial bits (draw >> 63): draws 0-3 -> (1,1,1,0), gene 7; draws 4-7 ->
+#    (0,1,1,0), gene 6; draws 8-11 -> (1,0,1,1), gene 13
+#  fitness (2, 1/4, 1), total 13/4; elite = individual 0 (1,1,1,0)
+#  roulette draw 1: u(draw 12) = 0.7559, u * total = 2.457; running sums
+#    2, 2.25, 3.25 -> the first above it is individual 2 (1,0,1,1)
+#  roulette draw 2: u(draw 13) = 0.5823, u * total = 1.892 < 2 -> individual 0
+#  pair (individual 2, individual 0): u(draw 14) = 0.1583 < Pc -> crossover
+#    at 1 + draw 15 mod 3 = 2; the tails from position 2 on are exchanged:
+#    (1,0 | 1,1) x (1,1 | 1,0) -> (1,0,1,0) and (1,1,1,1)
+#  mutation, one u per bit of each child: child 1 draws 16-19 (0.580, 0.9995,
+#    0.414, 0.533) none below 0.3; child 2 draws 20-23 (0.914, 0.065, 0.289,
+#    0.517): bits 1 and 2 flip -> (1,0,0,1)
+WORKED_NEXT = [(1, 1, 1, 0), (1, 0, 1, 0), (1, 0, 0, 1)]
+
+
+def test_ga_worked_generation_by_hand():
+    rng = G.SplitMix64(29)
+    assert [rng.next() for _ in range(len(_STREAM29))] == _STREAM29
+    out = G.run_ga(4, 3, 2, G.table_evaluator(worked_generation_table()), Pc=0.9, Pm=0.3, p=0.5, seed=29)
+    g0, g1 = out["generations"]
+    assert g0["pop"] == [(1, 1, 1, 0), (0, 1, 1, 0), (1, 0, 1, 1)]
+    assert g0["fitness"] == [2.0, 0.25, 1.0]
+    assert g1["pop"] == WORKED_NEXT
+
+
+def test_ga_roulette_follows_fitness_shares():
+    # Pc = Pm = 0: the M-1 children are the roulette's picks in draw order;
+    # over 10^5 draws each gene's count is within 4 sigma of the binomial
+    # mean sum over runs of (M-1) * n_g f_g / sum_h n_h f_h (n_g its copies in
+    # the population, f_g = t_g^-1/2 = 1 + g here)
+    a, M, runs = 4, 201, 500
+    table = [1.0 / (1.0 + g) ** 2 for g in range(16)]
+    obs = np.zeros(16)
+    mean = np.zeros(16)
+    var = np.zeros(16)
+    for seed in range(runs):
+        out = G.run_ga(a, M, 2, G.table_evaluator(table), Pc=0.0, Pm=0.0, p=0.5, seed=seed)
+        g0, g1 = out["generations"]
+        w = np.zeros(16)
+        for g in g0["pop"]:
+            w[G.gene_index(g)] += 1.0 + G.gene_index(g)
+        share = w / w.sum()
+        mean += (M - 1) * share
+        var += (M - 1) * share * (1.0 - share)
+        for g in g1["pop"][1:]:
+            obs[G.gene_index(g)] += 1
+    assert obs.sum() == runs * (M - 1)
+    assert np.all(np.abs(obs - mean) <= 4.0 * np.sqrt(var) + 1e-9), (obs, mean)
+
+
+def test_ga_one_point_crossover_cuts():
+    # only the all-zero gene Z and the all-one gene O run (every other gene
+    # fails, fitness 0), so every parent is Z or O; with Pc = 1 and Pm = 0 a
+    # pair of one Z and one O must give the two complementary step genes
+    # 0^c 1^(a-c) and 1^c 0^(a-c) with the cut c in [1, a-1] -- never the
+    # parents themselves -- and the cuts are uniform over [1, a-1]
+    a, M = 6, 257
+    Z, O = (0,) * a, (1,) * a
+    table = [1.0] * (1 << a)
+    status = [G.ST_FAILED] * (1 << a)
+    status[0] = status[(1 << a) - 1] = G.ST_OK
+    cuts = np.zeros(a + 1)
+    runs = 0
+    for seed in range(120):
+        out = G.run_ga(a, M, 2, G.table_evaluator(table, status), Pc=1.0, Pm=0.0, p=0.5, seed=seed)
+        g0, g1 = out["generations"]
+        if Z not in g0["pop"] or O not in g0["pop"]:
+            continue
+        runs += 1
+        kids = g1["pop"][1:]
+        for c1, c2 in zip(kids[0::2], kids[1::2]):
+            if (c1, c2) in ((Z, Z), (O, O)):
+                continue
+            assert (c1, c2) not in ((Z, O), (O, Z))
+            c = next(i for i in range(1, a) if c1[i] != c1[0])
+            step = tuple([c1[0]] * c + [1 - c1[0]] * (a - c))
+            assert c1 == step and c2 == tuple(1 - b for b in step), (c1, c2)
+            cuts[c] += 1
+    assert runs >= 40
+    n = cuts.sum()
+    assert cuts[0] == 0 and cuts[a] == 0 and n > 2000
+    p = 1.0 / (a - 1)
+    assert np.all(np.abs(cuts[1:a] - n * p) <= 4.0 * np.sqrt(n * p * (1 - p))), cuts
