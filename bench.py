@@ -1,24 +1,30 @@
 """Benchmark of the offload path on one MI355X.
 
-A step is one run of the medium application (12 loop nests, 2 of them
-loop-carried recurrences that stay on the CPU; GEMM 1024 x 1024, 19-point
-sweep on 129 x 129 x 257 for 100 sweeps with the FP64 residual) under the
-pattern that puts every parallelisable nest on the GPU, through
-ofl_run_pattern: verdicts, plan, kernels, the two host nests and the copies
-they require.  Inputs are resident in HBM when the timed region starts (set-up
-content restored device-side, untimed) and outputs stay there.
+A step is one run of the large application (16 loop nests, 3 of them --
+two loop-carried recurrences and a sequential generator -- on the CPU; FP32
+product 8192 x 8192, element-wise nests on 8192 x 8192, a BF16 product
+8192 x 8192, the 19-point sweep on 513 x 513 x 1025 for 50 sweeps with the
+FP64 residual) under the pattern that puts all 13 parallelisable nests on
+the GPU, through ofl_run_pattern: verdicts, plan, kernels, the three host
+nests and the copies they need.  Inputs are resident in HBM when the timed
+region starts (set-up content restored device-side, untimed) and outputs stay
+there; the rate with set-up content copied in and outputs copied out over
+PCIe is reported beside it.
 
-Prints one JSON line; `value` is application runs per second.  The rooflines
-of the two grid kernels (the sweep and the interior copy) come from HIP events
-in the dispatch packets of a sample of their launches on the run's stream
-during the timed steps (each kernel in every second step, every 25th launch);
-`roofline` is that of the one with the larger total time in a pass where
-every kernel is timed.  `cpu_baseline` times the oracle's serial run of the
-same application on one host core.
+Prints one JSON line; `value` is application runs per second.  `roofline` is
+that of the kernel with the largest total time in a pass where every launch
+is timed; its live figure comes from HIP events in the dispatch packets of a
+sample of its launches on the run's stream during the timed steps.
+`cpu_baseline` is the oracle's serial run of the same application (the
+all-CPU gene) timed on one pinned host core on a bounded sample: every nest
+once at full size (the sweep and the interior copy once each, counted 50
+times), the two products at N = 1024 and 2048 extrapolated as N^3.
 """
 import argparse
+import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -26,16 +32,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "app time & speedup vs 1-core oracle; stencil GB/s, GEMM MFMA % of peak"
-# HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE, scaled
-# by the readings of a plain 1 GiB copy (reads x2.000, writes x1.000); see
-# profiles/stencil19_medium_129x129x257.md.  Must be re-measured (or dropped)
-# whenever the kernel changes.
-MEASURED_TRAFFIC = {("stencil19", 129, 129, 257): (2.000 * 9356.3 + 19094.7) * 1024,
-                    ("copy_interior", 129, 129, 257): (2.000 * 8207.3 + 16288.3) * 1024}
-LIVE_KERNELS = ("stencil19", "copy_interior")
-TIMING_STRIDE = 25
 HBM_PEAK_GBS = 8000.0
-FP32_MFMA_PEAK_TFLOPS = 157.3
+MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}
+LIVE_STRIDE = 5
+CSRC = os.path.join(ROOT, "paper_1806_01430_amd", "csrc")
+# sources each kernel kind is compiled from: a profile's byte counts hold only
+# while these are unchanged
+KERNEL_SOURCES = {
+    "stencil19": ["k_stencil.hip", "stencil_item.hpp", "dev_common.hpp", "launch.hpp"],
+    "copy_interior": ["k_stencil.hip", "stencil_item.hpp", "dev_common.hpp", "launch.hpp"],
+    "gemm": ["k_gemm.hip", "gemm_tile.hpp", "launch.hpp"],
+}
+# every kernel kind of the large application
+LARGE_OPS = ["init_uniform", "gemm", "add_scaled", "transpose", "avg2", "sumsq", "stencil19", "copy_interior",
+             "copy", "scale", "cast_bf16", "gemm_bf16"]
 
 
 def log(*a):
@@ -52,6 +62,31 @@ def copy_interior_bytes(I, J, K):
     return 8 * (I - 2) * (J - 2) * (K - 2)
 
 
+def sources_sha(kind):
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES.get(kind, []):
+        with open(os.path.join(CSRC, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kind, workload):
+    """HBM bytes per launch of `kind` on `workload` from the byte-counter
+    summary under profiles/ (a line `traffic: KIND WORKLOAD BYTES sources SHA`),
+    or None when there is none or the kernel's sources changed since."""
+    pat = re.compile(r"^traffic: (\S+) (\S+) (\d+) sources ([0-9a-f]{16})\s*$")
+    pdir = os.path.join(ROOT, "profiles")
+    for name in sorted(os.listdir(pdir)):
+        if not name.endswith(".md"):
+            continue
+        with open(os.path.join(pdir, name)) as f:
+            for line in f:
+                m = pat.match(line.strip())
+                if m and m.group(1) == kind and m.group(2) == workload:
+                    return int(m.group(3)) if m.group(4) == sources_sha(kind) else None
+    return None
+
+
 def kernel_table(app, ops):
     out = {}
     for op in ops:
@@ -61,7 +96,87 @@ def kernel_table(app, ops):
     return out
 
 
+def large_work(P):
+    """Algorithmic work per launch of the large application's dominant
+    kernels: (bytes or flops, unit, bound, peak)."""
+    I, J, K, N = P["I"], P["J"], P["K"], P["N"]
+    return {"stencil19": (stencil_bytes(I, J, K), "GB/s", "hbm", HBM_PEAK_GBS),
+            "copy_interior": (copy_interior_bytes(I, J, K), "GB/s", "hbm", HBM_PEAK_GBS),
+            "gemm": (2.0 * N ** 3, "TFLOP/s", "mfma", MFMA_PEAK_TFLOPS["f32"]),
+            "gemm_bf16": (2.0 * N ** 3, "TFLOP/s", "mfma", MFMA_PEAK_TFLOPS["bf16"])}
+
+
+def roof_entry(kind, work, live, workload):
+    amount, unit, bound, peak = work
+    secs = live["avg_us"] * 1e-6
+    achieved = amount / secs / (1e9 if unit == "GB/s" else 1e12)
+    traffic = measured_traffic(kind, workload) if unit == "GB/s" else None
+    out = {"kernel": kind, "bound": bound, "achieved": round(achieved, 1), "peak": peak, "unit": unit,
+           "frac": round(achieved / peak, 4), "traffic": traffic,
+           ("bytes_per_launch" if unit == "GB/s" else "flops_per_launch"): amount,
+           "avg_launch_us": round(live["avg_us"], 3), "launches_timed": live["launches"],
+           "total_ms_timed": round(live["total_ms"], 3)}
+    return out
+
+
+def run_large(args):
+    """The headline: the large application, all parallelisable nests on the
+    GPU, inputs resident in HBM."""
+    import torch
+
+    import paper_1806_01430_amd as ofl
+    import workloads
+
+    doc = workloads.app_doc("large")
+    P = doc["params"]
+    app = ofl.App(json.dumps(doc), seed=1)
+    gene = [1] * app.gene_len
+    bufs = app.alloc_device_buffers("cuda:0")
+    flags = ofl.PRESTAGED | ofl.KEEP_OUTPUTS
+    policy = ofl.SECTIONS
+    for _ in range(max(1, args.warmup)):
+        app.run_pattern(gene, bufs, policy=policy, flags=flags)
+    # every kernel's time in an instrumented pass (events around every
+    # launch): which kernel dominates the step
+    app.set_kernel_timing_sample(1, 0)
+    app.set_kernel_timing_op(None)
+    app.set_kernel_timing(True)
+    for _ in range(2):
+        app.run_pattern(gene, bufs, policy=policy, flags=flags)
+    app.set_kernel_timing(False)
+    ktab = kernel_table(app, LARGE_OPS)
+    work = large_work(P)
+    dom = max(work, key=lambda k: ktab.get(k, {"total_ms": 0.0})["total_ms"])
+    # the timed region: eager runs, events in the dispatch packets of every
+    # LIVE_STRIDE-th sweep and interior copy and of each product (a launch
+    # carrying events starts on a drained queue, ~10 us idle once per
+    # sampled launch)
+    app.set_kernel_timing_sample(LIVE_STRIDE, 0)
+    app.set_kernel_timing_op(",".join(work))
+    app.set_kernel_timing(True)
+    torch.cuda.synchronize()
+    internal = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        st = app.run_pattern(gene, bufs, policy=policy, flags=flags)
+        internal.append(st["t_total_s"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    app.set_kernel_timing(False)
+    live = kernel_table(app, list(work))
+    # the paper's protocol (context): set-up content copied in over PCIe and
+    # outputs copied out, inside the timed region
+    pcie = sorted(app.run_pattern(gene, bufs, policy=policy, flags=0)["t_total_s"] for _ in range(3))
+    internal.sort()
+    return {"params": P, "wall": wall, "internal_median_s": internal[len(internal) // 2], "pcie_median_s": pcie[1],
+            "kernels": ktab, "live": live, "dominant": dom, "work": work, "last": st,
+            "plan_pcie": app.plan_transfers(gene, policy, 0), "plan_resident": app.plan_transfers(gene, policy, flags)}
+
+
 def run_medium(args):
+    """The medium application (GEMM 1024, 129 x 129 x 257 x 100 sweeps, 12
+    nests), all 10 parallelisable nests on the GPU, inputs resident (context:
+    its grids sit in the 256 MB last-level cache)."""
     import torch
 
     import paper_1806_01430_amd as ofl
@@ -73,142 +188,62 @@ def run_medium(args):
     gene = [1] * app.gene_len
     bufs = app.alloc_device_buffers("cuda:0")
     flags = ofl.PRESTAGED | ofl.KEEP_OUTPUTS
-    policy = ofl.SECTIONS
-    # the timed region: eager runs (one launch per kernel) with HIP events in
-    # the dispatch packets of a sample of the launches of the two grid
-    # kernels, the sweep and the interior copy (together nearly all of the
-    # kernel time): the kernels take turns step by step, and in a step every
-    # TIMING_STRIDE-th execution of the kernel is timed.  A launch carrying
-    # events leaves the queue idle for a few microseconds around it (the
-    # launches are no longer back to back), so timing every launch would slow
-    # the step by ~0.3 ms per kernel kind
-    app.set_kernel_timing_sample(TIMING_STRIDE, TIMING_STRIDE // 2)
-    app.set_kernel_timing_op(LIVE_KERNELS[0])
-    for _ in range(args.warmup):
-        app.run_pattern(gene, bufs, policy=policy, flags=flags)
-    torch.cuda.synchronize()
+    for _ in range(3):
+        app.run_pattern(gene, bufs, policy=ofl.SECTIONS, flags=flags)
+    app.set_kernel_timing_sample(25, 12)
+    app.set_kernel_timing_op("stencil19,copy_interior")
     app.set_kernel_timing(True)
-    internal = []
+    torch.cuda.synchronize()
+    steps = 20
     t0 = time.perf_counter()
-    for step in range(args.steps):
-        app.set_kernel_timing_op(LIVE_KERNELS[step % len(LIVE_KERNELS)])
-        st = app.run_pattern(gene, bufs, policy=policy, flags=flags)
-        internal.append(st["t_total_s"])
+    ts = [app.run_pattern(gene, bufs, policy=ofl.SECTIONS, flags=flags)["t_total_s"] for _ in range(steps)]
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     app.set_kernel_timing(False)
-    dom = kernel_table(app, LIVE_KERNELS)
-    # every kernel's time, in a separate instrumented pass (context)
-    app.set_kernel_timing_sample(1, 0)
-    app.set_kernel_timing_op(None)
-    app.set_kernel_timing(True)
-    for _ in range(10):
-        app.run_pattern(gene, bufs, policy=policy, flags=flags)
-    app.set_kernel_timing(False)
-    ktab = kernel_table(app, ["stencil19", "copy_interior", "gemm", "init_uniform", "add_scaled", "transpose",
-                              "avg2", "sumsq", "copy", "scale"])
-    # uninstrumented graph replays (context)
-    gflags = flags | ofl.GRAPH
-    for _ in range(3):
-        app.run_pattern(gene, bufs, policy=policy, flags=gflags)
-    torch.cuda.synchronize()
-    tg0 = time.perf_counter()
-    ginternal = []
-    for _ in range(args.steps):
-        ginternal.append(app.run_pattern(gene, bufs, policy=policy, flags=gflags)["t_total_s"])
-    torch.cuda.synchronize()
-    gwall = time.perf_counter() - tg0
-    ginternal.sort()
-    # paper protocol for context: set-up content copied in, outputs copied out
-    pcie = []
-    for _ in range(3):
-        pcie.append(app.run_pattern(gene, bufs, policy=policy, flags=0)["t_total_s"])
-    # the whole-buffer transfer policy for comparison
-    res_t = []
-    for _ in range(3):
-        app.run_pattern(gene, bufs, policy=ofl.RESIDENT, flags=flags)
-    for _ in range(10):
-        res_t.append(app.run_pattern(gene, bufs, policy=ofl.RESIDENT, flags=flags)["t_total_s"])
-    res_t.sort()
-    internal.sort()
-    pcie.sort()
-    return {"app": app, "params": P, "wall": wall, "internal_median_s": internal[len(internal) // 2],
-            "pcie_median_s": pcie[1], "kernels": ktab, "live": dom, "last": st, "graph_wall": gwall,
-            "resident_median_s": res_t[len(res_t) // 2],
-            "graph_internal_median_s": ginternal[len(ginternal) // 2]}
+    live = kernel_table(app, ["stencil19", "copy_interior"])
+    I, J, K = P["I"], P["J"], P["K"]
+    ts.sort()
+    out = {"runs_per_s": round(steps / wall, 2), "app_time_ms": round(1e3 * ts[steps // 2], 4),
+           "app_time_pcie_ms": round(1e3 * sorted(app.run_pattern(gene, bufs, policy=ofl.SECTIONS)["t_total_s"]
+                                                  for _ in range(3))[1], 4)}
+    for kind, nbytes in (("stencil19", stencil_bytes(I, J, K)), ("copy_interior", copy_interior_bytes(I, J, K))):
+        if kind in live:
+            gbs = nbytes / (live[kind]["avg_us"] * 1e-6) / 1e9
+            out[kind] = {"avg_us": round(live[kind]["avg_us"], 3), "GBps": round(gbs, 1),
+                         "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    return out
 
 
 def run_kernels_large(args):
-    """Stencil on the largest grid and the FP32 GEMM at 8192 (the sizes where
-    the HBM and MFMA rooflines are meaningful)."""
+    """Element-wise nests on 8192 x 8192 (HBM-bound) and the FFT call: one
+    line per kernel kind."""
+    import numpy as np
+
     import paper_1806_01430_amd as ofl
     from workloads import appgen
 
     out = {}
-    I, J, K = 513, 513, 1025
-    app = ofl.App(json.dumps(appgen.stencil_app(I, J, K, 10)), seed=1)
-    bufs = app.alloc_device_buffers("cuda:0")
-    app.run_pattern([1, 1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
-    app.set_kernel_timing(True)
-    for _ in range(2):
-        app.run_pattern([1, 1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
-    n, ms = app.kernel_stats("stencil19")
-    avg = ms / n * 1e-3
-    gbs = stencil_bytes(I, J, K) / avg / 1e9
-    nc, msc = app.kernel_stats("copy_interior")
-    out["stencil19_513x513x1025"] = {"avg_us": avg * 1e6, "GBps": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
-                                     "copy_interior_GBps": 8 * (I - 2) * (J - 2) * (K - 2) / (msc / nc * 1e-3) / 1e9}
-    del bufs, app
-    N = 8192
-    doc = {"name": "gemm8192", "params": {"N": N},
-           "buffers": [{"name": b, "dims": ["N", "N"], "output": b == "C"} for b in ("A", "B", "C")],
-           "program": [appgen.init_nest(["A", "B"], [0, 1]), appgen.gemm_nest("A", "B", "C")]}
-    app = ofl.App(json.dumps(doc), seed=1)
-    bufs = app.alloc_device_buffers("cuda:0")
-    app.run_pattern([1, 1], bufs, flags=ofl.KEEP_OUTPUTS)
-    app.set_kernel_timing(True)
-    for _ in range(3):
-        app.run_pattern([1, 1], bufs, flags=ofl.KEEP_OUTPUTS)
-    n, ms = app.kernel_stats("gemm")
-    avg = ms / n * 1e-3
-    tf = 2.0 * N ** 3 / avg / 1e12
-    out["gemm_f32_8192"] = {"avg_ms": avg * 1e3, "TFLOPs": tf, "frac_mfma": tf / FP32_MFMA_PEAK_TFLOPS}
-    del bufs, app
-    # element-wise nests, transpose, cast and sum of squares on 8192 x 8192
-    # (256 MB per FP32 matrix: HBM-bound); algorithmic bytes per element
     R = C = 8192
     app = ofl.App(json.dumps(appgen.ewise_app(R, C)), seed=1)
     bufs = app.alloc_device_buffers("cuda:0")
     gene = [1] * app.gene_len
     app.run_pattern(gene, bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
     app.set_kernel_timing(True)
-    for _ in range(3):
+    runs = 3
+    for _ in range(runs):
         app.run_pattern(gene, bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
     per_elem = {"init_uniform": 8, "add_scaled": 12, "transpose": 8, "avg2": 12, "copy": 8, "scale": 8,
                 "cast_bf16": 6, "sumsq": 4}
     for op, b in per_elem.items():
         n, ms = app.kernel_stats(op)
-        runs = 3
         if n:
             gbs = b * R * C * runs / (ms * 1e-3) / 1e9
-            out["ewise_8192_" + op] = {"launches_per_run": n // runs, "ms_per_run": ms / runs, "GBps": gbs,
-                                       "frac_hbm": gbs / HBM_PEAK_GBS}
+            out["ewise_8192_" + op] = {"launches_per_run": n // runs, "ms_per_run": round(ms / runs, 4),
+                                       "GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
     del bufs, app
-    out.update(run_fft_kernel(args))
-    return out
-
-
-def run_fft_kernel(args):
-    """The FFT call on 8192 rows of 1024 complex points (64 MB): each row read
-    and written once, 16 algorithmic bytes per point; 5 n log2 n flops a row."""
-    import numpy as np
-    import paper_1806_01430_amd as ofl
-    from workloads import appgen
-
-    out = {}
-    R, n = 8192, 1024
-    app = ofl.App(json.dumps(appgen.fft_app(R, n)), seed=1)
-    app.set_input("X", np.random.default_rng(5).standard_normal((R, 2 * n)).astype(np.float32))
+    Rf, n = 8192, 1024
+    app = ofl.App(json.dumps(appgen.fft_app(Rf, n)), seed=1)
+    app.set_input("X", np.random.default_rng(5).standard_normal((Rf, 2 * n)).astype(np.float32))
     bufs = app.alloc_device_buffers("cuda:0")
     app.run_pattern([1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
     app.set_kernel_timing(True)
@@ -216,9 +251,9 @@ def run_fft_kernel(args):
         app.run_pattern([1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
     nl, ms = app.kernel_stats("fft_rows")
     avg = ms / nl * 1e-3
-    gbs = 16.0 * R * n / avg / 1e9
-    out["fft_rows_8192x1024"] = {"avg_us": avg * 1e6, "GBps": gbs, "frac_hbm": gbs / HBM_PEAK_GBS,
-                                 "GFLOPs": 5.0 * n * 10 * R / avg / 1e9}
+    gbs = 16.0 * Rf * n / avg / 1e9
+    out["fft_rows_8192x1024"] = {"avg_us": round(avg * 1e6, 3), "GBps": round(gbs, 1),
+                                 "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
     return out
 
 
@@ -230,7 +265,6 @@ def run_precision(args):
     import workloads
 
     out = {}
-    N = None
     for prec in ("f32", "bf16x3", "fp8x2"):
         doc = workloads.app_doc("precision")
         doc["program"][1]["args"]["prec"] = prec
@@ -321,37 +355,104 @@ def calibration_copy():
     del app, bufs
 
 
-def cpu_baseline():
-    """The oracle's serial run of the medium application (the all-CPU gene),
-    one host core."""
+def host_cpu():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count(), len(os.sched_getaffinity(0))
+
+
+def cpu_baseline_large():
+    """The oracle's serial run of the large application (all 16 nests on the
+    CPU: the all-zero gene), on one pinned host core, from a bounded sample:
+    every nest once at full size in program order (the sweep and the interior
+    copy once each, counted SWEEPS times); the two products at N = 1024 and
+    2048 on leading blocks of their real operands, extrapolated as
+    t(2048) (N / 2048)^3."""
+    import numpy as np
+
     import workloads
+    from oracle import cnests as C
     from oracle import ir
     from oracle import run as orun
 
-    app_o = ir.load(workloads.app_doc("medium"))
-    ts = []
-    for _ in range(3):
-        bufs = orun.setup_buffers(app_o)
+    core = max(os.sched_getaffinity(0))
+    os.sched_setaffinity(0, {core})
+    doc = workloads.app_doc("large")
+    P = doc["params"]
+    app = ir.load(doc)
+    # set-up content (untimed): zeros, and the sine field for the grid; every
+    # page touched once here so that no timed nest pays first-touch faults
+    bufs = {}
+    for b in app.buffers:
+        if b.setup == "sin":
+            bufs[b.name] = C.sin_field(*b.dims, b.mode)
+        else:
+            bufs[b.name] = np.zeros(b.dims, {"f32": np.float32, "f64": np.float64, "bf16": np.uint16}[b.dtype])
+            bufs[b.name].fill(0)
+    per = []
+    gemm_fit = {}
+
+    def timed_nest(nest, env):
         t0 = time.perf_counter()
-        orun.run_app(app_o, 1, bufs=bufs)
-        ts.append(time.perf_counter() - t0)
-    return sorted(ts)[1]
+        orun.run_nest(app, nest, bufs, 1, env)
+        return time.perf_counter() - t0
+
+    def sample_product(nest):
+        a = nest.args
+        A, B = bufs[a["A"]], bufs[a["B"]]
+        fn = C.gemm_f32 if nest.op == "gemm" else C.gemm_bf16
+        ts = {}
+        for n in (1024, 2048):
+            As, Bs = np.ascontiguousarray(A[:n, :n]), np.ascontiguousarray(B[:n, :n])
+            t0 = time.perf_counter()
+            fn(As, Bs)
+            ts[n] = time.perf_counter() - t0
+        est = ts[2048] * (A.shape[0] / 2048.0) ** 3
+        gemm_fit[nest.name] = {"t1024_s": round(ts[1024], 3), "t2048_s": round(ts[2048], 3),
+                               "ratio_2048_1024": round(ts[2048] / ts[1024], 2), "extrapolated_s": round(est, 1)}
+        return est
+
+    def walk(items, env, mult):
+        for it in items:
+            if it[0] == "nest":
+                nest = app.nests[it[1]]
+                if nest.op in ("gemm", "gemm_bf16"):
+                    per.append((nest.name, mult * sample_product(nest)))
+                else:
+                    per.append((nest.name, mult * timed_nest(nest, env)))
+            else:
+                _, var, count, body = it
+                e2 = dict(env)
+                e2[var] = 0
+                walk(body, e2, mult * count)
+    t_all = time.perf_counter()
+    walk(app.program, {}, 1)
+    sample_s = time.perf_counter() - t_all
+    total = sum(t for _, t in per)
+    model, n_cpu, n_aff = host_cpu()
+    return {"total_s": total, "per_nest_s": {n: round(t, 3) for n, t in per}, "gemm_fit": gemm_fit,
+            "sample_s": sample_s, "core": core, "model": model, "n_cpu": n_cpu, "n_affinity": n_aff,
+            "params": P}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
-    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-large", action="store_true", help="skip the 513^3-class stencil / 8192 GEMM lines")
-    ap.add_argument("--large-only", action="store_true",
-                    help="only the 513x513x1025 stencil and 8192 GEMM kernel lines (for profiling)")
-    ap.add_argument("--fft-only", action="store_true", help="only the FFT kernel line (for profiling)")
     ap.add_argument("--no-extras", action="store_true",
-                    help="skip the precision, batching and population-evaluation lines")
-    ap.add_argument("--extras-only", action="store_true",
-                    help="only the precision, batching and population-evaluation lines (for profiling)")
+                    help="skip the medium, element-wise, precision, batching and population lines")
+    ap.add_argument("--large-only", action="store_true",
+                    help="only the large application's timed steps (for profiling)")
+    ap.add_argument("--extras-only", action="store_true", help="only the extra lines (for profiling)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first run a plain 1 GiB copy kernel (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -368,79 +469,56 @@ def main():
         log("bench: calibration copy (1 GiB)")
         calibration_copy()
         torch.cuda.empty_cache()
-    if args.fft_only:
-        print(json.dumps({"kernels_large": run_fft_kernel(args)}), flush=True)
-        return
-    if args.large_only:
-        print(json.dumps({"kernels_large": run_kernels_large(args)}), flush=True)
-        return
     if args.extras_only:
-        out = {"precision": run_precision(args)}
+        out = {"medium": run_medium(args), "kernels_large": run_kernels_large(args)}
+        torch.cuda.empty_cache()
+        out["precision"] = run_precision(args)
         torch.cuda.empty_cache()
         out["batch"] = run_batch(args)
         torch.cuda.empty_cache()
         out["population_eval"] = run_population(args)
         print(json.dumps(out), flush=True)
         return
-    log("bench: medium app, %d warmup + %d timed steps" % (args.warmup, args.steps))
-    r = run_medium(args)
+    log("bench: large app, %d warmup + %d timed steps" % (args.warmup, args.steps))
+    r = run_large(args)
     P = r["params"]
+    workload = "large_%dx%dx%d_N%d" % (P["I"], P["J"], P["K"], P["N"])
     ms_per_step = 1e3 * r["wall"] / args.steps
     value = args.steps / r["wall"]
-    ks = r["kernels"]
-    # the dominant kernel is the one of the two with the larger total time in
-    # the instrumented pass where every launch carries events (the live
-    # figure of a kernel depends a little on which neighbouring launches
-    # carry events); "roofline" is its roofline from the live timing of the
-    # timed steps, "roofline_kernels" has both
-    I, J, K = P["I"], P["J"], P["K"]
-    algo = {"stencil19": stencil_bytes(I, J, K), "copy_interior": copy_interior_bytes(I, J, K)}
-    for name, nbytes in algo.items():
-        if name in ks:
-            ks[name]["GBps"] = nbytes / (ks[name]["avg_us"] * 1e-6) / 1e9
-
-    def roof(rk):
-        live = r["live"][rk]
-        achieved = algo[rk] / (live["avg_us"] * 1e-6) / 1e9
-        traffic = MEASURED_TRAFFIC.get((rk, I, J, K))
-        return {"kernel": rk, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": round(traffic) if traffic else None,
-                "bytes_per_launch": algo[rk], "avg_launch_us": round(live["avg_us"], 3),
-                "launches_timed": live["launches"], "total_ms_timed": round(live["total_ms"], 3)}
-
-    roofs = {rk: roof(rk) for rk in LIVE_KERNELS}
-    dom = max(LIVE_KERNELS, key=lambda rk: ks[rk]["total_ms"])
-    roofline = dict(roofs[dom])
-    g = ks.get("gemm")
-    gemm_tf = 2.0 * 1024 ** 3 / (g["avg_us"] * 1e-6) / 1e12 if g else None
-
-    line = {"metric": METRIC, "value": round(value, 3), "unit": "medium-app runs/s", "n_gpus": 1,
-            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
-            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-            "data": "synthetic (seeded SplitMix64 inputs, sine-mode grid)",
-            "config": {"workload": "medium app: 12 loop nests (2 loop-carried recurrences on the CPU), "
-                                   "GEMM 1024x1024, 19-point sweep 129x129x257 x 100 sweeps + FP64 residual",
-                       "gene": "all 10 parallelisable nests on the GPU",
-                       "policy": "sections (CPU recurrences copy out only the column / row they read)",
+    roofs = {k: roof_entry(k, r["work"][k], r["live"][k], workload) for k in r["work"] if k in r["live"]}
+    roofline = dict(roofs[r["dominant"]])
+    line = {"metric": METRIC, "value": round(value, 4), "unit": "large-app runs/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32+bf16",
+            "data": "synthetic (seeded SplitMix64 matrices, sine-mode grid)",
+            "config": {"workload": "large app: 16 loop nests (2 loop-carried recurrences and a sequential "
+                                   "generator on the CPU), FP32 GEMM 8192x8192, element-wise nests on "
+                                   "8192x8192, BF16 GEMM 8192x8192, 19-point sweep 513x513x1025 x 50 + FP64 "
+                                   "residual",
+                       "gene": "all 13 parallelisable nests on the GPU",
+                       "policy": "sections (CPU nests copy out only the column / row they read)",
                        "execution": "each step one eager ofl_run_pattern (kernel by kernel on one stream); "
-                                    "HIP events in the dispatch packets of every 25th stencil19 sweep "
-                                    "launch (even steps) or copy_interior launch (odd steps)",
+                                    "HIP events in the dispatch packets of every %d-th sweep and interior "
+                                    "copy and of each product" % LIVE_STRIDE,
                        "inputs": "resident in HBM at the start of the timed region; outputs left in HBM"},
-            "app_time_ms": round(1e3 * r["internal_median_s"], 4),
-            "app_time_pcie_ms": round(1e3 * r["pcie_median_s"], 4),
-            "graph_runs_per_s": round(args.steps / r["graph_wall"], 3),
-            "graph_app_time_ms": round(1e3 * r["graph_internal_median_s"], 4),
-            "app_time_resident_policy_ms": round(1e3 * r["resident_median_s"], 4),
-            "gemm1024_TFLOPs": round(gemm_tf, 2) if gemm_tf else None,
+            "app_time_ms": round(1e3 * r["internal_median_s"], 3),
+            "app_time_pcie_ms": round(1e3 * r["pcie_median_s"], 3),
+            "pcie_runs_per_s": round(1.0 / r["pcie_median_s"], 3),
+            "plan_bytes": {"pcie_h2d_d2h_copies": r["plan_pcie"], "resident_h2d_d2h_copies": r["plan_resident"]},
             "roofline": roofline,
             "roofline_kernels": roofs,
-            "kernels_medium": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in ks.items()}}
-    if not args.no_large:
-        log("bench: large-grid stencil and 8192 GEMM")
-        line["kernels_large"] = {k: {kk: round(vv, 4) for kk, vv in v.items()}
-                                 for k, v in run_kernels_large(args).items()}
+            "kernels_large_app": {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in r["kernels"].items()}}
+    if args.large_only:
+        print(json.dumps(line), flush=True)
+        return
+    torch.cuda.empty_cache()
     if not args.no_extras:
+        log("bench: medium app")
+        line["medium"] = run_medium(args)
+        torch.cuda.empty_cache()
+        log("bench: element-wise kernels and FFT call")
+        line["kernels_large"] = run_kernels_large(args)
+        torch.cuda.empty_cache()
         log("bench: precision workload under each GEMM form")
         line["precision"] = run_precision(args)
         torch.cuda.empty_cache()
@@ -450,12 +528,21 @@ def main():
         log("bench: population evaluation (tiny, 64 genes)")
         line["population_eval"] = run_population(args)
     if not args.no_cpu_baseline:
-        log("bench: oracle on one host core (full medium application)")
-        dt = cpu_baseline()
-        line["cpu_baseline"] = {"value": round(1.0 / dt, 5), "unit": "medium-app runs/s", "cores": 1,
-                                "kind": "oracle", "sample": "median of 3 full serial runs of the medium "
-                                                            "application (all 12 nests; %.2f s each)" % dt}
-        line["speedup_vs_1core_oracle"] = round(dt / r["internal_median_s"], 1)
+        log("bench: oracle on one pinned host core (large application, bounded sample)")
+        cb = cpu_baseline_large()
+        fit = "; ".join("%s %.2f s at 1024, %.2f s at 2048 (ratio %.2f) -> %.0f s at %d" % (
+            n, f["t1024_s"], f["t2048_s"], f["ratio_2048_1024"], f["extrapolated_s"], P["N"])
+            for n, f in cb["gemm_fit"].items())
+        line["cpu_baseline"] = {
+            "value": round(1.0 / cb["total_s"], 6), "unit": "large-app runs/s", "cores": 1, "kind": "oracle",
+            "sample": "serial oracle of the large application on host core %d: every non-product nest once at "
+                      "full size (the sweep and interior copy once each, x%d), the two 8192 products "
+                      "extrapolated as t(2048) (N/2048)^3 [%s]; estimated all-CPU run %.1f s from %.1f s of "
+                      "CPU work" % (cb["core"], P["SWEEPS"], fit, cb["total_s"], cb["sample_s"]),
+            "host_cpu": cb["model"], "host_logical_cpus": cb["n_cpu"], "cpus_available": cb["n_affinity"],
+            "per_nest_s": cb["per_nest_s"]}
+        line["speedup_vs_1core_oracle"] = round(cb["total_s"] / r["internal_median_s"], 1)
+        line["speedup_vs_1core_oracle_pcie"] = round(cb["total_s"] / r["pcie_median_s"], 1)
     print(json.dumps(line), flush=True)
 
 

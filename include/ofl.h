@@ -67,7 +67,9 @@ enum {
 /* Parallelisability verdict of a nest and the reason of a rejection
  * (the compile-error kinds listed in Sec. 4 of the paper). */
 enum { OFL_PARALLEL = 0, OFL_PARALLEL_REDUCTION = 1, OFL_REJECT = 2 };
-enum { OFL_R_NONE = 0, OFL_R_DATA_DEP = 1, OFL_R_EXTERNAL_CALL = 2, OFL_R_BREAK = 3 };
+enum { OFL_R_NONE = 0, OFL_R_DATA_DEP = 1, OFL_R_EXTERNAL_CALL = 2, OFL_R_BREAK = 3,
+       OFL_R_NO_KERNEL = 4   /* a host_code nest: no GPU form (Sec. 4's compile
+                                that fails for other reasons) */ };
 
 /* Transfer policies (see ofl_plan_transfers) and run flags. */
 enum { OFL_POLICY_RESIDENT = 0, OFL_POLICY_PER_REGION = 1, OFL_POLICY_SECTIONS = 2 };
@@ -182,8 +184,18 @@ typedef struct {
  * row, interleaved; n a power of two up to 4096).  `seed` drives the
  * application's random-initialisation nests.  Allocates nothing on the GPU
  * (the device scratch, and for an FFT call its twiddle tables, come with the
- * first run).  Errors: OFL_E_IO, OFL_E_PARSE, OFL_E_IR, OFL_E_ARG,
- * OFL_E_NOMEM. */
+ * first run).  A nest of op "host_code" (args {"symbol": name}) is a loop
+ * nest whose body no library operation matches, compiled from its own source
+ * text into the shared object the description names as "host_object" (its
+ * entry point void name(void *const *host_bufs, const int64_t *repeat_env)
+ * gets the host copy of every buffer, in declaration order, and the values
+ * of the repeat variables, by repeat id); such a nest always runs on the CPU
+ * (verdict OFL_REJECT, its own reason or OFL_R_NO_KERNEL) and its transfers
+ * follow from its declared accesses.  Every nest's loops must span exactly
+ * the index space of its operation (the whole arrays; the interior of the
+ * grid for the sweep and the interior copy).  A grid of the sweep or the
+ * interior copy must hold under 2 GiB.  Errors: OFL_E_IO (file or host
+ * object cannot be read), OFL_E_PARSE, OFL_E_IR, OFL_E_ARG, OFL_E_NOMEM. */
 int ofl_app_load(const char *path, uint64_t seed, ofl_app **out);
 int ofl_app_load_json(const char *json_text, uint64_t seed, ofl_app **out);
 void ofl_app_free(ofl_app *app);

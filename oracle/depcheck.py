@@ -18,7 +18,11 @@ Reading used here (the paper does not spell the test out):
   counts as an ordinary read-write);
 * otherwise a write W and any access X of the same buffer conflict when two
   iterations with different outer-loop values reach the same element:
-  REJECT(DATA_DEP).
+  REJECT(DATA_DEP);
+* a nest whose body no library operation implements (op ``host_code``: the
+  loop kept as source text, compiled for the CPU) cannot be offloaded even
+  when its loop is parallel -- the paper's "other" compile errors:
+  REJECT(NO_KERNEL), after the reasons above.
 
 The conflict question is answered exactly for subscripts of the form
 ``var + c`` / ``c``: each subscript equation links two variables by a fixed
@@ -27,7 +31,7 @@ of a graph of offsets, each component free to slide over the intersection of
 its members' ranges.
 """
 PARALLEL, PARALLEL_REDUCTION, REJECT = 0, 1, 2
-R_NONE, R_DATA_DEP, R_EXTERNAL_CALL, R_BREAK = 0, 1, 2, 3
+R_NONE, R_DATA_DEP, R_EXTERNAL_CALL, R_BREAK, R_NO_KERNEL = 0, 1, 2, 3, 4
 
 
 class _Offsets:
@@ -146,6 +150,8 @@ def check_nest(nest):
             for x in accs:
                 if carried(nest, w, x):
                     return REJECT, R_DATA_DEP
+    if nest.op == "host_code":
+        return REJECT, R_NO_KERNEL
     return (PARALLEL_REDUCTION if reduction else PARALLEL), R_NONE
 
 

@@ -41,15 +41,18 @@ rounds alike) -- because the library evaluates exactly that expression.  A
 nest matching no template (one that leaves its loop with ``break``, for one)
 is an error: the library could run it neither on the GPU nor on the CPU.
 """
+import hashlib
 import json
+import os
 import re
+import subprocess
 
 # ------------------------------------------------------------------ lexing
 _TOKEN = re.compile(r"""
     (?P<ws>\s+|//[^\n]*|/\*.*?\*/)
   | (?P<num>\d+\.\d*(?:[eE][+-]?\d+)?f?|\d*\.\d+(?:[eE][+-]?\d+)?f?|\d+[eE][+-]?\d+f?|\d+f?)
   | (?P<id>\$?[A-Za-z_][A-Za-z_0-9]*)
-  | (?P<op>\+\+|\+=|-=|\*=|/=|<=|[-+*/=<()\[\]{};,&@])
+  | (?P<op>\+\+|\+=|-=|\*=|/=|<=|>=|==|!=|&&|\|\||[-+*/%=<>!()\[\]{};,&@?:])
 """, re.X | re.S)
 
 TYPES = {"float": "f32", "double": "f64", "bf16": "bf16", "int": "int"}
@@ -60,15 +63,15 @@ class CError(ValueError):
 
 
 def _lex(src):
-    """Tokens, with the 1-based source line of each and whether it is the
-    first token on its line."""
+    """Tokens, with the 1-based source line of each, whether it is the first
+    token on its line, and its start and end offsets in the text."""
     out, pos, line, last_line = [], 0, 1, 0
     while pos < len(src):
         m = _TOKEN.match(src, pos)
         if not m:
             raise CError("line %d: cannot read %r" % (line, src[pos:pos + 20]))
         if m.lastgroup != "ws":
-            out.append((m.group(m.lastgroup), line, line != last_line))
+            out.append((m.group(m.lastgroup), line, line != last_line, m.start(), m.end()))
             last_line = line
         line += src.count("\n", pos, m.end())
         pos = m.end()
@@ -80,8 +83,10 @@ class _Parser:
     def __init__(self, toks):
         self.t = [t[0] for t in toks]
         self.where = [(t[1], t[2]) for t in toks]
+        self.span = [(t[3], t[4]) for t in toks]
         self.i = 0
         self.for_at = {}          # id of a parsed for or call statement -> (line, first on its line)
+        self.text_at = {}         # id of a parsed for statement -> (start, end) offsets of its text
 
     def peek(self, k=0):
         return self.t[self.i + k] if self.i + k < len(self.t) else None
@@ -93,8 +98,31 @@ class _Parser:
         self.i += 1
         return tok
 
-    # expressions: ('num', v) ('var', n) ('ref', n, [subs]) ('bin', op, a, b)
-    # ('neg', a) ('call', n, [args]) ('cast', type, a) ('addr', a)
+    # expressions: ('num', v, kind) ('var', n) ('ref', n, [subs]) ('bin', op, a, b)
+    # ('neg', a) ('call', n, [args]) ('cast', type, a) ('addr', a) ('not', a)
+    # ('sel', c, a, b); a number's kind is 'i' (integer literal), 'f' (float
+    # literal, suffix f) or 'd' (double literal)
+    def cond(self):
+        e = self.conj()
+        while self.peek() == "||":
+            self.take()
+            e = ("bin", "||", e, self.conj())
+        return e
+
+    def conj(self):
+        e = self.rel()
+        while self.peek() == "&&":
+            self.take()
+            e = ("bin", "&&", e, self.rel())
+        return e
+
+    def rel(self):
+        e = self.expr()
+        while self.peek() in ("<", "<=", ">", ">=", "==", "!="):
+            op = self.take()
+            e = ("bin", op, e, self.expr())
+        return e
+
     def expr(self):
         e = self.term()
         while self.peek() in ("+", "-"):
@@ -104,7 +132,7 @@ class _Parser:
 
     def term(self):
         e = self.unary()
-        while self.peek() in ("*", "/"):
+        while self.peek() in ("*", "/", "%"):
             op = self.take()
             e = ("bin", op, e, self.unary())
         return e
@@ -117,6 +145,9 @@ class _Parser:
         if tok == "&":
             self.take()
             return ("addr", self.unary())
+        if tok == "!":
+            self.take()
+            return ("not", self.unary())
         if tok == "(" and self.peek(1) in TYPES and self.peek(2) == ")":
             self.take("(")
             ty = self.take()
@@ -127,11 +158,12 @@ class _Parser:
     def primary(self):
         tok = self.take()
         if tok == "(":
-            e = self.expr()
+            e = self.cond()
             self.take(")")
             return e
         if re.match(r"[\d.]", tok):
-            return ("num", float(tok.rstrip("f")))
+            kind = "f" if tok[-1] in "fF" else ("i" if re.fullmatch(r"\d+", tok) else "d")
+            return ("num", float(tok.rstrip("fF")), kind)
         if not re.match(r"\$?[A-Za-z_]", tok):
             raise CError("unexpected %r" % tok)
         if self.peek() == "(":
@@ -152,9 +184,27 @@ class _Parser:
         return ("ref", tok, subs) if subs else ("var", tok)
 
     # statements: ('for', v, lo, hi, [body]) ('assign', ref, op, e)
-    # ('local', type, name, e) ('break',)
+    # ('local', type, name, e) ('break',) ('if', cond, [then], [else])
     def stmt(self):
+        start = self.span[self.i][0] if self.i < len(self.span) else 0
+        out = self._stmt()
+        if len(out) == 1 and out[0][0] == "for":
+            self.text_at[id(out[0])] = (start, self.span[self.i - 1][1])
+        return out
+
+    def _stmt(self):
         tok = self.peek()
+        if tok == "if":
+            self.take("if")
+            self.take("(")
+            c = self.cond()
+            self.take(")")
+            then = self.stmt()
+            other = []
+            if self.peek() == "else":
+                self.take("else")
+                other = self.stmt()
+            return [("if", c, then, other)]
         if tok == "{":
             self.take("{")
             body = []
@@ -177,7 +227,7 @@ class _Parser:
             cmp = self.take()
             hi = self.expr()
             if cmp == "<=":
-                hi = ("bin", "+", hi, ("num", 1.0))
+                hi = ("bin", "+", hi, ("num", 1.0, "i"))
             elif cmp != "<":
                 raise CError("loop condition must be < or <=")
             self.take(";")
@@ -291,13 +341,15 @@ TEMPLATES = [
 ]
 
 
-def _parse_stmts(src, where=None):
+def _parse_stmts(src, where=None, spans=None):
     p = _Parser(_lex(src))
     out = []
     while p.peek() is not None:
         out.extend(p.stmt())
     if where is not None:
         where.update(p.for_at)
+    if spans is not None:
+        spans.update(p.text_at)
     return out
 
 
@@ -313,7 +365,7 @@ def _inline(stmts, env=None):
             return ("ref", e[1], [sub(x) for x in e[2]])
         if e[0] == "bin":
             return ("bin", e[1], sub(e[2]), sub(e[3]))
-        if e[0] in ("neg", "addr"):
+        if e[0] in ("neg", "addr", "not"):
             return (e[0], sub(e[1]))
         if e[0] == "cast":
             return ("cast", e[1], sub(e[2]))
@@ -325,6 +377,8 @@ def _inline(stmts, env=None):
     for s in stmts:
         if s[0] == "local":
             env[s[2]] = sub(s[3])
+        elif s[0] == "assign" and s[1][0] == "var":
+            out.append(s)      # a local assigned again: no template has one
         elif s[0] == "assign":
             lhs, rhs = sub(s[1]), sub(s[3])
             if s[2] != "=":
@@ -332,12 +386,19 @@ def _inline(stmts, env=None):
             out.append(("assign", lhs, "=", rhs))
         elif s[0] == "for":
             out.append(("for", s[1], sub(s[2]), sub(s[3]), _inline(s[4], env)))
+        elif s[0] == "if":
+            out.append(("if", sub(s[1]), _inline(s[2], env), _inline(s[3], env)))
         else:
             out.append(s)
     return out
 
 
 _TPL = [(op, _inline(_parse_stmts(src))[0]) for op, src in TEMPLATES]
+
+# pattern variables of each template that stand for arrays
+_BUFFER_OPERANDS = {"gemm": "ABC", "add_scaled": "CA", "avg2": "DXY", "scale": "D", "transpose": "TX",
+                    "copy": "DX", "sumsq": "Xs", "rec_prefix": "vS", "rec_decay": "wp", "lcg_fill": "L",
+                    "copy_interior": "pq", "stencil19": ["p", "q", "res"]}
 
 
 def _match(t, s, env):
@@ -353,6 +414,13 @@ def _match(t, s, env):
         else:
             return False
     kind = t[0]
+    if kind == "num":
+        # a float literal of the template matches the same value written as a
+        # float or an integer literal (C converts the integer exactly); a
+        # double literal makes the expression double arithmetic: no match
+        if s[1] != t[1]:
+            return False
+        return s[2] == t[2] or (t[2] == "f" and s[2] == "i" and abs(s[1]) < 2 ** 24)
     if kind == "var":
         if t[1].startswith("$"):
             if t[1] in env:
@@ -379,19 +447,34 @@ def _match(t, s, env):
     return all(_match(a, b, env) for a, b in zip(t[1:], s[1:]))
 
 
+class _NoMatch(Exception):
+    pass
+
+
 def _literal(e, what):
-    if e[0] == "num":
-        return e[1]
-    if e[0] == "neg" and e[1][0] == "num":
-        return -e[1][1]
-    raise CError("%s must be a literal number" % what)
+    """Value of a float (or integer) literal operand; a double literal, or
+    anything but a literal, is not the library's float operation."""
+    neg = e[0] == "neg"
+    if neg:
+        e = e[1]
+    if e[0] != "num" or e[2] == "d" or (e[2] == "i" and abs(e[1]) >= 2 ** 24):
+        raise _NoMatch(what)
+    return -e[1] if neg else e[1]
 
 
 def _bind(nest, dtypes):
-    """(op, args) of a nest, by template; CError if none matches."""
+    """(op, args) of a nest by template, or None when no operation of the
+    library has its body (the nest then keeps its source text and runs on
+    the CPU)."""
     if _has_break(nest):
-        raise CError("the nest over %s leaves its loop early (break): no operation has such a body"
-                     % ", ".join(_loop_vars(nest)))
+        return None
+    try:
+        return _bind_template(nest, dtypes)
+    except _NoMatch:
+        return None
+
+
+def _bind_template(nest, dtypes):
     src = _inline([nest])[0]
     for op, tpl in _TPL:
         env = {}
@@ -399,12 +482,15 @@ def _bind(nest, dtypes):
             continue
         v = {k[1:]: e for k, e in env.items() if isinstance(k, str)}
         buf = {k: e[1] for k, e in v.items() if e[0] == "var"}
+        for name in _BUFFER_OPERANDS[op]:
+            if v[name][0] != "var" or v[name][1] not in dtypes:
+                raise _NoMatch(name)
         if op == "gemm":
             kinds = {dtypes.get(buf[x]) for x in "AB"}
             if kinds == {"bf16"}:
                 op = "gemm_bf16"
             elif kinds != {"f32"}:
-                raise CError("product operands are both float or both bf16")
+                raise _NoMatch("product operand types")
             return op, {"A": buf["A"], "B": buf["B"], "C": buf["C"]}
         if op == "add_scaled":
             return op, {"C": buf["C"], "A": buf["A"], "alpha": _literal(v["alpha"], "alpha")}
@@ -427,12 +513,14 @@ def _bind(nest, dtypes):
         if op == "copy_interior":
             return op, {"dst": buf["p"], "src": buf["q"]}
         if op == "stencil19":
-            return op, {"p": buf["p"], "q": buf["q"], "res": buf["res"], "slot": buf["n"]}
+            if v["n"][0] != "var":
+                raise _NoMatch("the residual slot must be the repeat variable")
+            return op, {"p": buf["p"], "q": buf["q"], "res": buf["res"], "slot": v["n"][1]}
     for bind in (_bind_init, _bind_cast):
         got = bind(src)
         if got:
             return got
-    raise CError("no operation matches the body of the nest over %s" % ", ".join(_loop_vars(nest)))
+    return None
 
 
 def _rows(src):
@@ -482,7 +570,13 @@ def _bind_cast(src):
 
 
 def _has_break(stmt):
-    return stmt[0] == "break" or (stmt[0] == "for" and any(_has_break(b) for b in stmt[4]))
+    if stmt[0] == "break":
+        return True
+    if stmt[0] == "for":
+        return any(_has_break(b) for b in stmt[4])
+    if stmt[0] == "if":
+        return any(_has_break(b) for b in stmt[2] + stmt[3])
+    return False
 
 
 def _loop_vars(stmt):
@@ -529,7 +623,7 @@ def _accesses(stmt, loop_vars):
         elif e[0] == "bin":
             exprs(e[2])
             exprs(e[3])
-        elif e[0] in ("neg", "addr"):
+        elif e[0] in ("neg", "addr", "not"):
             exprs(e[1])
         elif e[0] == "cast":
             exprs(e[2])
@@ -539,22 +633,41 @@ def _accesses(stmt, loop_vars):
             for x in e[2]:
                 exprs(x)
 
-    def walk(s):
+    locals_ = set()
+    leaves = _has_break(stmt)
+
+    def walk(s, cond):
+        # cond: the statement may not run in every iteration (under an if,
+        # or in a loop that can be left early), so its writes may leave the
+        # old values in place: they count as reads of the element too
         if s[0] == "for":
             for b in s[4]:
-                walk(b)
+                walk(b, cond)
+        elif s[0] == "if":
+            exprs(s[1])
+            for b in s[2] + s[3]:
+                walk(b, True)
         elif s[0] == "local":
+            locals_.add(s[2])
             exprs(s[3])
         elif s[0] == "assign":
+            if s[1][0] == "var":
+                if s[1][1] not in locals_:
+                    raise CError("assignment to %s: assignments go to array elements or declared locals" % s[1][1])
+                exprs(s[3])
+                return
             if s[1][0] != "ref":
                 raise CError("assignments go to array elements (a local is declared with its type)")
             exprs(s[3])
             for x in s[1][2]:
                 exprs(x)
-            events.append(("w" if s[2] == "=" else "u", s[1]))
+            if s[2] == "=":
+                events.append(("cw" if cond else "w", s[1]))
+            else:
+                events.append(("u+" if s[2] == "+=" and not cond else "u", s[1]))
         elif s[0] == "break":
             flags.add("early_exit")
-    walk(stmt)
+    walk(stmt, leaves)
 
     def key(ref):
         return ref[1], tuple(_affine(e) for e in ref[2])
@@ -562,7 +675,7 @@ def _accesses(stmt, loop_vars):
     sums = set()
     for buf in {ref[1] for _, ref in events}:
         mine = [(m, ref) for m, ref in events if ref[1] == buf]
-        if all(m == "u" for m, _ in mine) and not any(
+        if all(m == "u+" for m, _ in mine) and not any(
                 _names_in(x) & set(loop_vars) for _, ref in mine for x in ref[2]):
             sums.add(buf)
     order, state = [], {}
@@ -572,9 +685,9 @@ def _accesses(stmt, loop_vars):
             order.append(k)
             state[k] = {"w": False, "exposed": False}
         st = state[k]
-        if m in ("r", "u") and not st["w"]:
+        if m in ("r", "u", "u+", "cw") and not st["w"]:
             st["exposed"] = True
-        if m in ("w", "u"):
+        if m in ("w", "u", "u+", "cw"):
             st["w"] = True
     writes = [k for k in order if state[k]["w"]]
     reads = [k for k in order if not state[k]["w"]]
@@ -620,6 +733,213 @@ _NEST_NAMES = {
     "copy_interior": lambda a: "copy_interior",
     "stencil19": lambda a: "stencil19",
 }
+
+def _walk_nodes(x, fn):
+    """Call fn on every expression and statement node of a parsed tree."""
+    if isinstance(x, list):
+        for y in x:
+            _walk_nodes(y, fn)
+    elif isinstance(x, tuple) and x and isinstance(x[0], str):
+        fn(x)
+        for y in x[1:]:
+            if isinstance(y, (list, tuple)):
+                _walk_nodes(y, fn)
+
+
+def _calls_in(stmt):
+    out = set()
+    _walk_nodes(stmt, lambda n: out.add(n[1]) if n[0] in ("call", "callstmt") else None)
+    return out
+
+
+def _names_used(stmt):
+    out = set()
+
+    def add(n):
+        if n[0] in ("var", "ref"):
+            out.add(n[1])
+    _walk_nodes(stmt, add)
+    return out
+
+
+def _const_int(text, params):
+    """Value of a bound written as in the IR ('N-1', '0', 'K')."""
+    total, sign, pos = 0, 1, 0
+    for m in re.finditer(r"\s*([+-]?)\s*([A-Za-z_]\w*|\d+)", text):
+        if m.start() != pos:
+            raise CError("bound %r is not a constant" % text)
+        pos = m.end()
+        sign = -1 if m.group(1) == "-" else 1
+        tok = m.group(2)
+        if tok.isdigit():
+            total += sign * int(tok)
+        elif tok in params:
+            total += sign * params[tok]
+        else:
+            return None
+    return total if pos == len(text) else None
+
+
+def _fits(op, args, loops, buffers, params, rvars):
+    """Whether a nest bound to `op` is exactly that operation of the library:
+    operand types and shapes as the operation takes them and loops over the
+    whole index space it covers (the interior of the grid for the sweep and
+    the interior copy); otherwise the nest keeps its own source text."""
+    info = {}
+    for b in buffers:
+        dims = [_const_int(d, params) for d in b["dims"]]
+        info[b["name"]] = (b["dtype"], dims)
+    L = [(_const_int(lo, params), _const_int(hi, params)) for _, lo, hi in loops]
+    if any(lo is None or hi is None for lo, hi in L):
+        return False
+
+    def dt(n):
+        return info[n][0]
+
+    def dims(n):
+        return info[n][1]
+
+    def full(n):
+        return L == [(0, d) for d in dims(n)]
+
+    def interior(n):
+        return L == [(1, d - 1) for d in dims(n)]
+
+    def nbytes(n):
+        c = 1
+        for d in dims(n):
+            c *= d
+        return c * {"f32": 4, "f64": 8, "bf16": 2}[dt(n)]
+
+    a = args
+    if op == "init_uniform":
+        return all(dt(x) == "f32" and full(x) for x in a["out"])
+    if op in ("gemm", "gemm_bf16"):
+        A, B, C = dims(a["A"]), dims(a["B"]), dims(a["C"])
+        return (dt(a["C"]) == "f32" and len(A) == len(B) == len(C) == 2 and A[1] == B[0] and C == [A[0], B[1]]
+                and L == [(0, A[0]), (0, B[1]), (0, A[1])])
+    if op == "add_scaled":
+        return dt(a["C"]) == dt(a["A"]) == "f32" and dims(a["C"]) == dims(a["A"]) and full(a["C"])
+    if op == "avg2":
+        return (all(dt(a[k]) == "f32" for k in "SXY") and dims(a["S"]) == dims(a["X"]) == dims(a["Y"])
+                and full(a["S"]))
+    if op == "scale":
+        return dt(a["D"]) == "f32" and full(a["D"])
+    if op == "copy":
+        return dt(a["dst"]) == dt(a["src"]) and dims(a["dst"]) == dims(a["src"]) and full(a["dst"])
+    if op == "cast_bf16":
+        return all(dt(d) == "bf16" and dt(x) == "f32" and dims(d) == dims(x) and full(d)
+                   for d, x in zip(a["dst"], a["src"]))
+    if op == "transpose":
+        S, T = dims(a["src"]), dims(a["dst"])
+        return (dt(a["src"]) == dt(a["dst"]) == "f32" and len(S) == 2 and T == S[::-1] and a["src"] != a["dst"]
+                and full(a["src"]))
+    if op == "sumsq":
+        return dt(a["x"]) == "f32" and dt(a["s"]) == "f64" and full(a["x"])
+    if op == "stencil19":
+        slot = dict(rvars)
+        return (dt(a["p"]) == dt(a["q"]) == "f32" and dt(a["res"]) == "f64" and len(dims(a["p"])) == 3
+                and dims(a["p"]) == dims(a["q"]) and a["p"] != a["q"] and interior(a["p"])
+                and nbytes(a["p"]) < 2 ** 31 and a["slot"] in slot)
+    if op == "copy_interior":
+        return (dt(a["dst"]) == dt(a["src"]) == "f32" and len(dims(a["dst"])) == 3
+                and dims(a["dst"]) == dims(a["src"]) and interior(a["dst"]) and nbytes(a["dst"]) < 2 ** 31)
+    if op == "rec_prefix":
+        return dt(a["v"]) == dt(a["S"]) == "f32" and len(dims(a["v"])) == 1 and L == [(1, dims(a["v"])[0])]
+    if op == "rec_decay":
+        return dt(a["w"]) == dt(a["p"]) == "f32" and len(dims(a["w"])) == 1 and L == [(1, dims(a["w"])[0])]
+    if op == "lcg_fill":
+        return dt(a["L"]) == "f32" and full(a["L"])
+    return True
+
+
+# The C++ the host object is compiled from: the program's parameters, the
+# bf16 storage type and one entry point per host_code nest, whose body is the
+# nest's own text.
+_HOST_PRELUDE = """// Host forms of loop nests that no operation of the library implements,
+// each the nest's own source text (written by the C front end).
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <math.h>
+#include <stdlib.h>
+
+namespace {
+// bf16 storage: bf16(x) rounds a float to the nearest bfloat16 (ties to
+// even, NaN kept quiet); reading one gives its exact float value
+struct bf16 {
+    uint16_t bits;
+    bf16() = default;
+    bf16(float f) {
+        uint32_t u;
+        std::memcpy(&u, &f, 4);
+        if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) bits = (uint16_t)((u >> 16) | 0x40u);
+        else bits = (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+    }
+    operator float() const {
+        const uint32_t u = (uint32_t)bits << 16;
+        float f;
+        std::memcpy(&f, &u, 4);
+        return f;
+    }
+};
+static_assert(sizeof(bf16) == 2, "bf16 storage");
+}  // namespace
+"""
+
+_CTYPE = {"f32": "float", "f64": "double", "bf16": "bf16"}
+
+
+def host_unit(params, buffers, host_code):
+    """Translation unit of an application's host_code nests.  Each entry
+    point takes the host copy of every buffer (declaration order) and the
+    repeat variables' values (by repeat id)."""
+    out = [_HOST_PRELUDE]
+    for k, v in params.items():
+        out.append("#define %s %d" % (k, v))
+    index = {b["name"]: i for i, b in enumerate(buffers)}
+    for h in host_code:
+        out.append('extern "C" void %s(void *const *ofl_buf, const int64_t *ofl_rep) {' % h["symbol"])
+        for name in h["buffers"]:
+            b = buffers[index[name]]
+            ty, dims = _CTYPE[b["dtype"]], b["dims"]
+            if len(dims) == 1:
+                out.append("    %s *%s = static_cast<%s *>(ofl_buf[%d]);" % (ty, name, ty, index[name]))
+            else:
+                inner = "".join("[%s]" % d for d in dims[1:])
+                out.append("    %s (*%s)%s = reinterpret_cast<%s (*)%s>(ofl_buf[%d]);"
+                           % (ty, name, inner, ty, inner, index[name]))
+        for var, rid in h["repeats"]:
+            out.append("    const int %s = (int)ofl_rep[%d];" % (var, rid))
+        out.append("#line %d" % h["line"])
+        out.append(h["text"])
+        out.append("}")
+    return "\n".join(out) + "\n"
+
+
+HOST_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "_hostobj")
+HOST_CXXFLAGS = ["-O2", "-std=c++17", "-ffp-contract=off", "-fno-fast-math", "-fPIC", "-shared", "-w"]
+
+
+def build_host_object(unit):
+    """Compile a host translation unit (once per distinct text) into a shared
+    object under _hostobj/; returns its path."""
+    key = hashlib.sha256(unit.encode()).hexdigest()[:16]
+    so = os.path.join(HOST_CACHE, "host_%s.so" % key)
+    if os.path.exists(so):
+        return so
+    os.makedirs(HOST_CACHE, exist_ok=True)
+    src = os.path.join(HOST_CACHE, "host_%s.cpp" % key)
+    tmp = so + ".tmp%d" % os.getpid()
+    with open(src, "w") as f:
+        f.write(unit)
+    cxx = os.environ.get("OFL_HOST_CXX", "g++")
+    r = subprocess.run([cxx] + HOST_CXXFLAGS + [src, "-o", tmp, "-lm"], capture_output=True, text=True)
+    if r.returncode != 0:
+        raise CError("the host form of a nest does not compile:\n" + r.stderr[-2000:])
+    os.replace(tmp, so)
+    return so
+
 
 _DEFINE = re.compile(r"\s*#define\s+([A-Za-z_]\w*)\s+(-?\d+)\s*$")
 _ARRAY = re.compile(r"\s*(float|double|bf16)\s+([A-Za-z_]\w*)((?:\s*\[[^\]]+\])+)\s*;\s*(?://\s*ofl:(.*))?$")
@@ -715,11 +1035,18 @@ def _parse(src, name):
                 "loops": [["i", "0", A["dims"][0]], ["j", "0", B["dims"][1]], ["k", "0", A["dims"][1]]],
                 "access": [[Cm["name"], "w", "i", "j"], [A["name"], "r", "i", "k"], [B["name"], "r", "k", "j"]]}
 
-    def nest_ir(stmt, prec):
+    def nest_ir(stmt, prec, rvars=()):
         at.append(where[id(stmt)] + ("loop",))
         loops = _loops(stmt)
         acc, flags = _accesses(stmt, [l[0] for l in loops])
-        op, args = _bind(stmt, dtypes)
+        got = _bind(stmt, dtypes)
+        if got is not None and not _fits(got[0], got[1], loops, buffers, params, rvars):
+            got = None
+        if got is None:
+            if prec is not None:
+                raise CError("prec applies to float products only")
+            return host_nest_ir(stmt, loops, acc, flags, rvars)
+        op, args = got
         if prec is not None:
             if op != "gemm":
                 raise CError("prec applies to float products only")
@@ -732,8 +1059,34 @@ def _parse(src, name):
             n["flags"] = flags
         return n
 
-    prec, where = None, {}
-    for stmt in _parse_stmts("\n".join(body_lines), where):
+    def host_nest_ir(stmt, loops, acc, flags, rvars):
+        # no operation of the library has this body: the nest keeps its own
+        # source text, compiled for the CPU into the application's host
+        # object; it never runs on the GPU
+        line = where[id(stmt)][0]
+        calls = _calls_in(stmt)
+        for c in ("u01", "lcg01"):
+            if c in calls:
+                raise CError("line %d: %s() is available only in the nest forms the library implements" % (line, c))
+        name = "host_L%d" % line
+        names_used[name] = names_used.get(name, 0) + 1
+        if names_used[name] > 1:
+            name = "%s_%d" % (name, names_used[name])
+        a, b = spans[id(stmt)]
+        used = _names_used(stmt)
+        host_code.append({"symbol": "ofl_" + name, "text": body_text[a:b], "line": line,
+                          "buffers": [bf["name"] for bf in buffers if bf["name"] in used],
+                          "repeats": [(v, rid) for v, rid in rvars if v in used]})
+        n = {"nest": name, "op": "host_code", "args": {"symbol": "ofl_" + name},
+             "loops": loops, "access": acc, "source": body_text[a:b]}
+        if flags:
+            n["flags"] = flags
+        return n
+
+    prec, where, spans, host_code = None, {}, {}, []
+    n_repeats = 0
+    body_text = "\n".join(body_lines)
+    for stmt in _parse_stmts(body_text, where, spans):
         if stmt[0] == "pragma":
             prec = stmt[2]
             continue
@@ -752,16 +1105,21 @@ def _parse(src, name):
         if len(inner) >= 2 and all(s[0] == "for" for s in inner):
             if _affine(stmt[2]) != "0":
                 raise CError("a repeat loop counts from 0")
+            rvars = [(stmt[1], n_repeats)]
+            n_repeats += 1
             program.append({"repeat": _affine(stmt[3]), "var": stmt[1],
-                            "body": [nest_ir(s, None) for s in inner]})
+                            "body": [nest_ir(s, None, rvars) for s in inner]})
         else:
             program.append(nest_ir(stmt, prec))
         prec = None
-    return {"name": name, "params": params, "buffers": buffers, "program": program}, at
+    doc = {"name": name, "params": params, "buffers": buffers, "program": program}
+    if host_code:
+        doc["host_object"] = build_host_object(host_unit(params, buffers, host_code))
+    return doc, at
 
 
 _REASONS = {1: "a data dependence between iterations", 2: "a call of an external routine",
-            3: "a break out of the loop"}
+            3: "a break out of the loop", 4: "no GPU form of its body"}
 
 
 def offloaded_source(src, verdicts, gene):

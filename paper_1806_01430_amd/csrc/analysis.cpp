@@ -181,6 +181,12 @@ void analyse(AppIR &app) {
                 n.verdict = reduction ? V_PARALLEL_REDUCTION : V_PARALLEL;
             }
         }
+        // a nest that only has a host form (compiled from its own source)
+        // stays on the CPU even when its loop could run in parallel
+        if (n.verdict != V_REJECT && n.op == OP_HOST_CODE) {
+            n.verdict = V_REJECT;
+            n.reason = RS_NO_KERNEL;
+        }
         n.gene_pos = (n.verdict == V_REJECT) ? -1 : pos++;
     }
     app.gene_len = pos;

@@ -245,6 +245,13 @@ bool run_host_nest(const AppIR &app, const Nest &n, const std::vector<void *> &h
         for (int64_t k = 1; k < g.dims[2]; ++k) w[k] = 0.5f * w[k - 1] + row[k];
         return !dl.expired();
     }
+    case OP_HOST_CODE: {
+        // compiled from the nest's own source text: it runs to completion
+        // (the deadline is checked at the nest's boundary)
+        if (!n.host_fn) return false;
+        n.host_fn(host.data(), env);
+        return !dl.expired();
+    }
     case OP_LCG_FILL: {
         float *L = F(0);
         uint32_t x = n.seed32;

@@ -11,7 +11,7 @@ namespace ofl {
 static const char *kOpNames[OP_COUNT] = {
     "none",       "init_uniform", "gemm",       "gemm_bf16",     "add_scaled", "avg2",
     "scale",      "copy",         "cast_bf16",  "transpose",     "sumsq",      "stencil19",
-    "copy_interior", "rec_prefix", "rec_decay", "lcg_fill", "fft_rows"};
+    "copy_interior", "rec_prefix", "rec_decay", "lcg_fill", "fft_rows", "host_code"};
 
 const char *op_name(Op op) { return (op >= 0 && op < OP_COUNT) ? kOpNames[op] : "?"; }
 
@@ -256,7 +256,8 @@ bool resolve_op(Ctx &cx, Nest &n, const Json *args, const std::vector<int64_t> &
                               B(0).dims == B(1).dims && n.b[0] != n.b[1], "needs distinct f32 grids and an f64 residual"))
             return false;
         if (!need(cx, n, B(0).dims[0] >= 1 && B(0).dims[1] >= 1 && B(0).dims[2] >= 1 &&
-                              B(0).dims[1] * B(0).dims[2] < (1ll << 31), "bad grid extents")) return false;
+                              B(0).nbytes < (1ull << 31), "grid extents (a grid must hold under 2 GiB: the sweep "
+                                                          "addresses it with 32-bit byte offsets)")) return false;
         const Json *sl = args->get("slot");
         if (!sl || sl->kind != Json::Str) return need(cx, n, false, "missing residual slot");
         for (size_t r = 0; r < n.repeats.size(); ++r)
@@ -269,8 +270,10 @@ bool resolve_op(Ctx &cx, Nest &n, const Json *args, const std::vector<int64_t> &
         n.b.push_back(x);
         if (!arg_buf(cx, n, args, "src", x)) return false;
         n.b.push_back(x);
-        return need(cx, n, is(0, DT_F32) && is(1, DT_F32) && B(0).dims.size() == 3 && B(0).dims == B(1).dims,
-                    "needs equal f32 grids");
+        if (!need(cx, n, is(0, DT_F32) && is(1, DT_F32) && B(0).dims.size() == 3 && B(0).dims == B(1).dims,
+                  "needs equal f32 grids")) return false;
+        return need(cx, n, B(0).nbytes < (1ull << 31),
+                    "a grid must hold under 2 GiB (the copy addresses it with 32-bit byte offsets)");
     case OP_REC_PREFIX:
         if (!arg_buf(cx, n, args, "v", x)) return false;
         n.b.push_back(x);
@@ -297,6 +300,14 @@ bool resolve_op(Ctx &cx, Nest &n, const Json *args, const std::vector<int64_t> &
                                B(0).dims[0] < (1ll << 31),
                     "row length must be 2 n floats, n a power of two up to " + std::to_string(kFftMaxPoints));
     }
+    case OP_HOST_CODE: {
+        // a nest no library operation matches, compiled from its own source
+        // text into the application's host object; it runs on the CPU only
+        const Json *sy = args->get("symbol");
+        if (!sy || sy->kind != Json::Str || sy->str.empty()) return need(cx, n, false, "missing symbol");
+        n.symbol = sy->str;
+        return true;
+    }
     case OP_LCG_FILL: {
         if (!arg_buf(cx, n, args, "L", x)) return false;
         n.b.push_back(x);
@@ -308,6 +319,55 @@ bool resolve_op(Ctx &cx, Nest &n, const Json *args, const std::vector<int64_t> &
     default:
         return cx.fail(OFL_E_IR, "unknown op");
     }
+}
+
+// The loops of a nest must run over exactly the index space its operation
+// covers: the library's kernel and host code of an op process that whole
+// space, so a nest over part of it (a partial update, a smaller product) is
+// a different program and must not bind to the op.
+bool check_span(Ctx &cx, const Nest &n) {
+    const AppIR &app = cx.app;
+    auto full = [&](const std::vector<int64_t> &dims) {
+        if (n.loops.size() != dims.size()) return false;
+        for (size_t l = 0; l < dims.size(); ++l)
+            if (n.loops[l].lo != 0 || n.loops[l].hi != dims[l]) return false;
+        return true;
+    };
+    auto interior = [&](const std::vector<int64_t> &dims) {
+        if (n.loops.size() != dims.size()) return false;
+        for (size_t l = 0; l < dims.size(); ++l)
+            if (n.loops[l].lo != 1 || n.loops[l].hi != dims[l] - 1) return false;
+        return true;
+    };
+    auto D = [&](int i) -> const std::vector<int64_t> & { return app.bufs[n.b[i]].dims; };
+    bool ok = true;
+    switch (n.op) {
+    case OP_INIT_UNIFORM:
+        for (size_t i = 0; i < n.b.size(); ++i) ok = ok && full(D((int)i));
+        break;
+    case OP_GEMM:
+    case OP_GEMM_BF16:
+        ok = n.loops.size() == 3 && n.loops[0].lo == 0 && n.loops[0].hi == D(0)[0] && n.loops[1].lo == 0 &&
+             n.loops[1].hi == D(1)[1] && n.loops[2].lo == 0 && n.loops[2].hi == D(0)[1];
+        break;
+    case OP_ADD_SCALED: case OP_AVG2: case OP_SCALE: case OP_COPY: case OP_CAST_BF16: case OP_TRANSPOSE:
+    case OP_SUMSQ: case OP_LCG_FILL: case OP_FFT_ROWS:
+        ok = full(D(0));
+        break;
+    case OP_STENCIL19:
+    case OP_COPY_INTERIOR:
+        ok = interior(D(0));
+        break;
+    case OP_REC_PREFIX:
+    case OP_REC_DECAY: {
+        const int64_t len = D(0)[0];
+        ok = n.loops.size() == 1 && n.loops[0].lo == 1 && n.loops[0].hi == len;
+        break;
+    }
+    default:
+        break;
+    }
+    return ok ? true : need(cx, n, false, "its loops do not span the index space of the operation");
 }
 
 bool parse_nest(Ctx &cx, const Json &j, const std::vector<std::pair<int, int64_t>> &repeats,
@@ -415,6 +475,7 @@ bool parse_nest(Ctx &cx, const Json &j, const std::vector<std::pair<int, int64_t
     if (n.op != OP_NONE && (!args || args->kind != Json::Obj))
         return cx.fail(OFL_E_IR, "nest " + n.name + ": missing args");
     if (!resolve_op(cx, n, args, rep_counts)) return false;
+    if (!check_span(cx, n)) return false;
     // each operand of the body must be declared among the accesses
     for (int b : n.b) {
         bool found = false;
@@ -546,11 +607,21 @@ int parse_app(const std::string &text, AppIR &app, std::string &err,
         b.output = o && o->kind == Json::Bool && o->b;
         app.bufs.push_back(b);
     }
+    const Json *ho = doc.get("host_object");
+    if (ho) {
+        if (ho->kind != Json::Str || ho->str.empty()) { cx.fail(OFL_E_PARSE, "host_object must be a path"); return cx.status; }
+        app.host_object = ho->str;
+    }
     const Json *prog = doc.get("program");
     if (!prog) { cx.fail(OFL_E_PARSE, "missing program"); return cx.status; }
     std::vector<int64_t> rep_counts;
     if (!parse_program(cx, *prog, {}, rep_counts, app.program)) return cx.status;
     if (app.nests.empty()) { cx.fail(OFL_E_IR, "program has no nests"); return cx.status; }
+    for (const auto &n : app.nests)
+        if (n.op == OP_HOST_CODE && app.host_object.empty()) {
+            cx.fail(OFL_E_IR, "nest " + n.name + " is host code but the application names no host_object");
+            return cx.status;
+        }
     analyse(app);
     for (const auto &n : app.nests)
         if (n.verdict != V_REJECT && n.op != OP_NONE && !op_has_device_kernel(n.op)) {

@@ -23,7 +23,7 @@ enum DType { DT_F32 = 0, DT_F64 = 1, DT_BF16 = 2 };
 enum Mode { M_R = 0, M_W = 1, M_RW = 2, M_SUM = 3 };
 enum SubKind { S_CONST = 0, S_LOOP = 1, S_REPEAT = 2 };
 enum Verdict { V_PARALLEL = 0, V_PARALLEL_REDUCTION = 1, V_REJECT = 2 };
-enum Reason { RS_NONE = 0, RS_DATA_DEP = 1, RS_EXTERNAL_CALL = 2, RS_BREAK = 3 };
+enum Reason { RS_NONE = 0, RS_DATA_DEP = 1, RS_EXTERNAL_CALL = 2, RS_BREAK = 3, RS_NO_KERNEL = 4 };
 
 enum Op {
     OP_NONE = 0,        // analysis-only nest (no body)
@@ -43,6 +43,7 @@ enum Op {
     OP_REC_DECAY,
     OP_LCG_FILL,
     OP_FFT_ROWS,        // function block: forward complex DFT of each row
+    OP_HOST_CODE,       // a nest compiled from its own source text, CPU only
     OP_COUNT
 };
 
@@ -94,6 +95,8 @@ struct Nest {
     uint32_t seed32 = 0;         // lcg_fill
     int slot_repeat = -1;        // stencil residual slot: repeat id
     GemmPrec prec = PREC_F32;
+    std::string symbol;          // host_code: entry point in the application's host object
+    void (*host_fn)(void *const *bufs, const int64_t *repeat_env) = nullptr;
 
     // analysis results
     Verdict verdict = V_PARALLEL;
@@ -118,6 +121,7 @@ struct AppIR {
     std::vector<ProgItem> program;
     std::vector<std::string> repeat_names;
     int gene_len = 0;
+    std::string host_object;     // shared object holding the host_code nests (empty: none)
 };
 
 // Parse + validate; returns an OFL_* status and fills `err` on failure.

@@ -1,6 +1,7 @@
 // C ABI, application object and pattern executor.
 #include "../../include/ofl.h"
 
+#include <dlfcn.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -137,6 +138,8 @@ struct ofl_app {
     std::map<std::vector<uint64_t>, std::unique_ptr<GraphEntry>> graphs;
     hipStream_t capture_stream = nullptr;
 
+    void *host_lib = nullptr;                // dlopen handle of the host object, if any
+
     ~ofl_app() {
         graphs.clear();
         if (capture_stream) (void)hipStreamDestroy(capture_stream);
@@ -149,6 +152,7 @@ struct ofl_app {
         if (d_twiddles) (void)hipFree(d_twiddles);
         for (auto e : events) (void)hipEventDestroy(e);
         for (auto e : chain_events) (void)hipEventDestroy(e);
+        if (host_lib) dlclose(host_lib);
     }
 };
 
@@ -1038,6 +1042,25 @@ int load_common(const std::string &text, uint64_t seed, ofl_app **out) {
     if (rc != OFL_OK) {
         delete app;
         return fail(rc, err);
+    }
+    if (!app->ir.host_object.empty()) {
+        // the host object holds one entry point per host_code nest
+        app->host_lib = dlopen(app->ir.host_object.c_str(), RTLD_NOW | RTLD_LOCAL);
+        if (!app->host_lib) {
+            const char *why = dlerror();
+            delete app;
+            return fail(OFL_E_IO, std::string("cannot load host object: ") + (why ? why : "?"));
+        }
+        for (auto &n : app->ir.nests) {
+            if (n.op != OP_HOST_CODE) continue;
+            void *sym = dlsym(app->host_lib, n.symbol.c_str());
+            if (!sym) {
+                const std::string name = n.name, symbol = n.symbol;
+                delete app;
+                return fail(OFL_E_IR, "nest " + name + ": host object has no entry point " + symbol);
+            }
+            n.host_fn = reinterpret_cast<void (*)(void *const *, const int64_t *)>(sym);
+        }
     }
     app->seed = seed;
     *out = app;

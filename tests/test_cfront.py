@@ -103,15 +103,88 @@ def test_sum_reduction_through_temporary():
     # element-wise with a shifted operand: no operation reads a neighbour
     "Y[i][j] = X[i][j];\n X[i][j] = Y[i][j];",
 ])
-def test_unmatched_bodies_are_errors(body):
-    with pytest.raises(cfront.CError):
-        _one("for (int i = 0; i < R; i++) for (int j = 0; j < CC; j++) { " + body + " }")
+def test_unmatched_bodies_keep_their_source(body):
+    # no operation of the library has these bodies: the nest keeps its text,
+    # compiled for the CPU, and gets no gene bit (Sec. 4: a loop whose
+    # directive does not compile stays on the CPU)
+    n = _one("for (int i = 0; i < R; i++) for (int j = 0; j < CC; j++) { " + body + " }")
+    assert n["op"] == "host_code" and body.split(";")[0].strip() in n["source"]
+    _check_host_only(DECLS + "for (int i = 0; i < R; i++) for (int j = 0; j < CC; j++) { " + body + " }",
+                     D.R_NO_KERNEL)
+
+
+def _check_host_only(src, reason):
+    doc = cfront.parse(src, "t")
+    app = ofl.App(doc)
+    want = [tuple(x) for x in D.check_app(ir.load(doc))]
+    assert app.verdicts() == want
+    assert want[-1] == (D.REJECT, reason, -1)
+
+
+@pytest.mark.parametrize("body,reason", [
+    # over part of the array: the library's add would cover all of it
+    ("for (int i = 0; i < 2; i++) for (int j = 0; j < CC; j++) X[i][j] = X[i][j] + 0.5f * Y[i][j];",
+     "no_kernel"),
+    # a double literal makes the update double arithmetic
+    ("for (int i = 0; i < R; i++) for (int j = 0; j < CC; j++) X[i][j] = X[i][j] + 0.1 * Y[i][j];",
+     "no_kernel"),
+    # a product over part of the inner dimension
+    ("for (int i = 0; i < R; i++) for (int j = 0; j < R; j++) { Z[i][j] = 0.0f;"
+     " for (int k = 0; k < 3; k++) Z[i][j] += Y[i][k] * X[k][j]; }", "bounds"),
+    # a math routine, a branch, an early exit
+    ("for (int i = 0; i < R; i++) for (int j = 0; j < CC; j++) Y[i][j] = sqrtf(X[i][j]);", "call"),
+    ("for (int i = 0; i < R; i++) for (int j = 0; j < CC; j++) { float u = X[i][j];"
+     " if (u < 0.5f) u = 0.5f - u; Y[i][j] = u; }", "no_kernel"),
+    ("for (int i = 0; i < R; i++) { if (X[i][0] > 0.5f) break; Y[i][0] = X[i][0]; }", "break"),
+])
+def test_nests_the_library_does_not_implement_stay_on_the_cpu(body, reason):
+    n = _one(body)
+    assert n["op"] == "host_code"
+    want = {"no_kernel": D.R_NO_KERNEL, "call": D.R_EXTERNAL_CALL, "break": D.R_BREAK}.get(reason)
+    if reason == "bounds":
+        # Z is 7 x 5 here, not the 5 x 5 the loops cover: no product binds
+        want = D.R_NO_KERNEL
+    _check_host_only(DECLS + body, want)
+    if reason == "break":
+        # a write in a loop that can be left early may not happen: read-write
+        assert ["Y", "rw", "i", "0"] in n["access"]
+
+
+def test_residual_slot_must_be_the_repeat_variable():
+    src = """#define I 5
+#define J 6
+#define K 7
+float p[I][J][K];
+float q[I][J][K];
+double res[3];
+for (int n = 0; n < 3; n++) {
+    for (int i = 1; i < I - 1; i++) for (int j = 1; j < J - 1; j++) for (int k = 1; k < K - 1; k++) {
+        float xm = (p[i - 1][j - 1][k] + p[i - 1][j + 1][k]) + (p[i - 1][j][k - 1] + p[i - 1][j][k + 1]);
+        float x0 = (p[i][j - 1][k] + p[i][j + 1][k]) + (p[i][j][k - 1] + p[i][j][k + 1]);
+        float xp = (p[i + 1][j - 1][k] + p[i + 1][j + 1][k]) + (p[i + 1][j][k - 1] + p[i + 1][j][k + 1]);
+        float y0 = (p[i][j - 1][k - 1] + p[i][j - 1][k + 1]) + (p[i][j + 1][k - 1] + p[i][j + 1][k + 1]);
+        float faces = (p[i - 1][j][k] + p[i + 1][j][k]) + x0;
+        float edges = (xm + xp) + y0;
+        float r = (0.25f * p[i][j][k] + 0.0625f * faces) + 0.03125f * edges;
+        q[i][j][k] = r;
+        double d = (double)r - (double)p[i][j][k];
+        res[SLOT] += d * d; }
+    for (int i = 1; i < I - 1; i++) for (int j = 1; j < J - 1; j++) for (int k = 1; k < K - 1; k++)
+        p[i][j][k] = q[i][j][k];
+}
+"""
+    doc = cfront.parse(src.replace("SLOT", "n"), "t")
+    assert doc["program"][0]["body"][0]["op"] == "stencil19"
+    doc = cfront.parse(src.replace("SLOT", "0"), "t")
+    assert doc["program"][0]["body"][0]["op"] == "host_code"
+    app = ofl.App(doc)
+    assert app.verdicts() == [tuple(x) for x in D.check_app(ir.load(doc))]
 
 
 def test_source_errors():
     loop = "for (int i = 0; i < R; i++) for (int j = 0; j < CC; j++) "
-    with pytest.raises(cfront.CError, match="break"):
-        _one(loop + "{ Y[i][j] = X[i][j]; break; }")
+    with pytest.raises(cfront.CError, match="u01"):
+        _one(loop + "{ Y[i][j] = u01(0, i, j) * X[i][j]; }")
     with pytest.raises(cfront.CError, match="name \\+ constant"):
         _one(loop + "Y[i][j] = X[2 * i][j];")
     with pytest.raises(cfront.CError, match="step by one"):

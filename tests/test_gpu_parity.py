@@ -750,3 +750,48 @@ def test_precision_workload_error_report():
         # the sweep does not depend on the product: the same field in every form
         assert report[prec]["p"] == report["f32"]["p"] and report[prec]["p"] < S * 8 * 2.0 ** -24
         assert report[prec]["r_S"] < 1e-2   # FP32 field: ~2^-24 / |mu - 1| relative (reported, not tight)
+
+
+# ---------------------------------------------------------------- general C programs
+def test_irregular_program_all_genes():
+    # a C program with loops the library does not implement (index
+    # arithmetic, a partial update, a math routine, double arithmetic, a
+    # branch, an early exit): they run on the CPU from their own compiled
+    # text, and every one of the 32 patterns of the other five nests must
+    # give the serial run of the unmodified program (compiled by the oracle)
+    import os
+    from oracle import cprog
+    from paper_1806_01430_amd import cfront
+    path = os.path.join(workloads.ROOT, "paper_1806_01430_amd", "apps", "irregular.c")
+    with open(path) as f:
+        want = cprog.run_program(f.read())
+    app = ofl.App(cfront.load(path))
+    assert app.gene_len == 5
+    bufs = app.alloc_device_buffers()
+    Cw, Ew = want["C"].astype(np.float64), want["E"].astype(np.float64)
+    # values downstream of the product: the GPU product is within 1e-5 of the
+    # exact one and the serial FP32 product within N u = 1.2e-5 (positive
+    # terms), so C, and what depends on it smoothly (E, G, T), differ by
+    # < 3e-5 relative; F = |C - 8 E| by < 3e-5 (C + 8 E) absolute
+    tol_f = 3e-5 * (Cw + 8.0 * Ew) + 1e-6
+    for idx in range(32):
+        g = [(idx >> k) & 1 for k in range(5)]
+        for pol in (ofl.RESIDENT, ofl.SECTIONS):
+            say("case irregular gene", g, "policy", pol)
+            st = app.run_pattern(g, bufs, policy=pol)
+            assert st["status"] == ofl.ST_OK
+            assert (st["bytes_h2d"], st["bytes_d2h"], st["n_copies"]) == app.plan_transfers(g, pol, 0)
+            got = app.read_all()
+            for name in ("A", "r", "p", "q"):
+                assert np.array_equal(got[name], want[name]), (g, name)
+            assert np.max(np.abs(got["res"] - want["res"]) / want["res"]) <= 1e-12 + 17 * 19 * 65 * 2.0 ** -52
+            for name in ("C", "E", "G", "T"):
+                w = want[name].astype(np.float64)
+                assert np.max(np.abs(got[name].astype(np.float64) - w) / w) < 3e-5, (g, name)
+            if g[0] == 0:
+                # the product on the CPU: the same serial code as the program
+                for name in ("C", "E", "G", "T", "F", "B", "s"):
+                    assert np.array_equal(got[name], want[name]), (g, name)
+            assert np.all(np.abs(got["F"].astype(np.float64) - want["F"]) <= tol_f), g
+            assert np.all(np.abs(got["B"].astype(np.float64) - want["B"]) <= tol_f.T), g
+            assert abs(got["s"][0] - want["s"][0]) / want["s"][0] < 1e-4, g

@@ -402,3 +402,24 @@ def test_fft_call_shapes(R, n, ok):
     else:
         with pytest.raises(ofl.OflError):
             ofl.App(json.dumps(doc))
+
+
+def test_irregular_program_verdicts_and_plans_match_oracle():
+    # a C program with loops the library does not implement: those nests run
+    # on the CPU from their own compiled text; verdicts (with the reason of
+    # each rejection) and every gene's transfers agree with the oracle
+    from paper_1806_01430_amd import cfront
+    doc = cfront.load(os.path.join(ROOT, "paper_1806_01430_amd", "apps", "irregular.c"))
+    app = ofl.App(doc)
+    o = ir.load(doc)
+    v = D.check_app(o)
+    assert app.verdicts() == [tuple(x) for x in v]
+    reasons = {app.nest_name(i): v[i][1] for i in range(app.n_nests) if v[i][0] == D.REJECT}
+    assert sorted(reasons.values()) == [D.R_EXTERNAL_CALL, D.R_BREAK] + [D.R_NO_KERNEL] * 5
+    assert app.gene_len == 5
+    for idx in range(1 << app.gene_len):
+        g = tuple((idx >> k) & 1 for k in range(app.gene_len))
+        pl = xfer.placement_of_gene(o, v, g)
+        for pol in (xfer.RESIDENT, xfer.PER_REGION, xfer.SECTIONS):
+            for flags in (0, 3):
+                assert app.plan_transfers(g, pol, flags) == xfer.totals(o, pl, pol, flags), (g, pol, flags)

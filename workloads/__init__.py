@@ -26,10 +26,6 @@ def app_doc(name, **params):
     return doc
 
 
-def app_json(name, **params):
-    return json.dumps(app_doc(name, **params))
-
-
 # Reduced sizes that keep every structural feature (several GEMM / transpose
 # tiles plus a ragged tail, grids whose extents are not multiples of any tile)
 # while the serial oracle finishes in about a second.
@@ -91,15 +87,3 @@ def time_table(a, seed, lo=0.001, hi=1.0):
     """A seeded table of 2^a positive 'run times' (log-uniform in [lo, hi])."""
     rng = random.Random(seed)
     return [math.exp(rng.uniform(math.log(lo), math.log(hi))) for _ in range(1 << a)]
-
-
-def batch_sizes(n_inst, seed, n_lo=32, n_hi=512, g_lo=17, g_hi=65):
-    """Uneven instance sizes: GEMM N log-uniform in [n_lo, n_hi] (not rounded
-    to any tile), grid I = J uniform in [g_lo, g_hi], K = 2I - 1."""
-    rng = random.Random(seed)
-    out = []
-    for _ in range(n_inst):
-        n = int(math.floor(math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))))
-        g = rng.randint(g_lo, g_hi)
-        out.append({"N": n, "I": g, "J": g, "K": 2 * g - 1})
-    return out
