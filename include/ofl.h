@@ -157,6 +157,20 @@ typedef struct {
                                 TIMEOUT with fitness 0, like a trial cut off
                                 by a timeout (Sec. 5.2); 0 = none.  With
                                 deadline_factor the limit is the smaller one */
+    const char *cache_path;  /* NULL or "": the measurements live only in this
+                                call.  Otherwise a log file of the search (the
+                                same-pattern skip of Sec. 4 kept across calls,
+                                for resuming): created if missing, else read
+                                first -- its measurements are taken in order
+                                instead of measuring again, which retraces the
+                                logged search exactly -- and every fresh
+                                measurement (gene, time, status) and every
+                                generation's end (the random stream's state)
+                                is appended and flushed as one JSON line.  The
+                                log's first line names the search (every
+                                parameter above except T, and the application
+                                or table); a log of another search, or one that
+                                disagrees on the way, gives OFL_E_STATE. */
 } ofl_ga_params;
 
 typedef struct {

@@ -65,7 +65,8 @@ class GaParams(ctypes.Structure):
     _fields_ = [("M", ctypes.c_int32), ("T", ctypes.c_int32), ("Pc", ctypes.c_double), ("Pm", ctypes.c_double),
                 ("p", ctypes.c_double), ("seed", ctypes.c_uint64), ("reps", ctypes.c_int32),
                 ("warmup", ctypes.c_int32), ("policy", ctypes.c_int32), ("flags", ctypes.c_int32),
-                ("deadline_factor", ctypes.c_double), ("timeout_s", ctypes.c_double)]
+                ("deadline_factor", ctypes.c_double), ("timeout_s", ctypes.c_double),
+                ("cache_path", ctypes.c_char_p)]
 
 
 class GaResult(ctypes.Structure):
@@ -203,8 +204,9 @@ def app_doc(app, sets=()):
 
 
 def ga_params(M=12, T=12, Pc=0.9, Pm=0.05, p=0.5, seed=1, reps=3, warmup=1, policy=RESIDENT, flags=0,
-              deadline_factor=0.0, timeout_s=0.0):
-    return GaParams(M, T, Pc, Pm, p, seed, reps, warmup, policy, flags, deadline_factor, timeout_s)
+              deadline_factor=0.0, timeout_s=0.0, cache_path=None):
+    return GaParams(M, T, Pc, Pm, p, seed, reps, warmup, policy, flags, deadline_factor, timeout_s,
+                    cache_path.encode() if cache_path else None)
 
 
 def _ga_result_arrays(a, M, T):

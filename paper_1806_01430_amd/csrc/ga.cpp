@@ -40,6 +40,7 @@ class SplitMix64 {
         return z ^ (z >> 31);
     }
     double uniform() { return (double)(next() >> 11) * 0x1.0p-53; }
+    uint64_t state() const { return state_; }
 
   private:
     uint64_t state_;
@@ -124,6 +125,7 @@ void run_ga(int a, const GaConfig &cfg, const Evaluator &evaluate, GaTrace &out,
         }
         out.pops.push_back(pop);
         out.meas.push_back(meas);
+        out.rng_state = rng.state();
         if (progress) (*progress)(gen, out, elapsed());
         if (gen == cfg.T) break;
 

@@ -2,7 +2,9 @@
 #pragma once
 
 #include <cstdint>
+#include <cstdio>
 #include <functional>
+#include <string>
 #include <vector>
 
 namespace ofl {
@@ -39,6 +41,41 @@ struct GaTrace {
     double best_t = -1.0, best_f = -1.0, t_all0 = -1.0;
     int n_measured = 0;
     double wall_s = 0.0, time_to_best_s = 0.0;
+    uint64_t rng_state = 0;      // state of the GA's random stream after the
+                                 // draws of the generations so far
+};
+
+// Persistent log of a search (resume after a crash or an interrupted run):
+// a first line naming the search (its parameters), then one line per fresh
+// measurement in the order taken and one per generation with the random
+// stream's state.  Opening an existing log queues its measurements: a
+// search with the same parameters takes them from the queue, in order,
+// instead of measuring again, which reproduces the interrupted search
+// exactly (its trajectory depends only on the seed and the measurements),
+// then measures on and appends.  JSON lines; doubles with 17 digits.
+class GaLog {
+  public:
+    ~GaLog();
+    // header: the search's identity (a JSON object's members); returns an
+    // OFL status (OFL_E_IO when the file cannot be read or written,
+    // OFL_E_STATE when it belongs to another search)
+    int open(const std::string &path, const std::string &header, std::string &err);
+    bool active() const { return f_ != nullptr; }
+    // the next queued measurement if it is of gene g: 1 (m filled), 0 (the
+    // queue is empty), -1 (the queue holds another gene: not this search)
+    int take(const std::vector<uint8_t> &g, Measurement &m);
+    void add(const std::vector<uint8_t> &g, const Measurement &m);
+    // generation record; during replay it must equal the logged one (false
+    // when it does not)
+    bool generation(int gen, uint64_t rng_state);
+    int replayed() const { return replayed_; }
+
+  private:
+    std::FILE *f_ = nullptr;
+    std::vector<std::pair<std::vector<uint8_t>, Measurement>> queue_;
+    size_t next_ = 0;
+    std::vector<uint64_t> gens_;   // logged rng state per generation (index gen - 1)
+    int replayed_ = 0;
 };
 
 // With `batch`, every generation's uncached genes are measured by one call of

@@ -1032,6 +1032,81 @@ GaConfig ga_config(const ofl_ga_params *p) {
     return c;
 }
 
+// Identity of a search for its log: every parameter the trajectory depends
+// on (not T: a longer search continues a shorter one) and what is searched.
+std::string search_identity(const ofl_ga_params *p, int a, const std::string &what) {
+    char buf[512];
+    std::snprintf(buf, sizeof buf,
+                  "a=%d;M=%d;Pc=%.17g;Pm=%.17g;p=%.17g;seed=%llu;deadline_factor=%.17g;timeout=%.17g;"
+                  "reps=%d;warmup=%d;policy=%d;flags=%d;",
+                  a, p->M, p->Pc, p->Pm, p->p, (unsigned long long)p->seed, p->deadline_factor, p->timeout_s,
+                  p->reps, p->warmup, p->policy, p->flags & ~OFL_RUN_PROGRESS);
+    return std::string(buf) + what;
+}
+
+// run_ga with the measurement log of params->cache_path (if set): logged
+// measurements are replayed in order, fresh ones appended.  A log that
+// disagrees with this search (another gene where its next measurement is,
+// another random state at a generation's end) stops the measuring and
+// returns OFL_E_STATE.
+int run_logged_ga(int a, const ofl_ga_params *params, const std::string &what, const Evaluator &ev,
+                  const BatchEvaluator &bev, bool print, GaTrace &tr) {
+    GaLog log;
+    if (params->cache_path && params->cache_path[0]) {
+        std::string err;
+        const int rc = log.open(params->cache_path, search_identity(params, a, what), err);
+        if (rc != OFL_OK) return fail(rc, err);
+    }
+    bool bad = false;
+    Evaluator lev = [&](const std::vector<uint8_t> &g, double limit) -> Measurement {
+        if (bad) return Measurement{0.0, OFL_ST_FAILED};
+        Measurement m;
+        const int r = log.take(g, m);
+        if (r == 1) return m;
+        if (r < 0) {
+            bad = true;
+            return Measurement{0.0, OFL_ST_FAILED};
+        }
+        m = ev(g, limit);
+        log.add(g, m);
+        return m;
+    };
+    BatchEvaluator lbev = [&](const std::vector<std::vector<uint8_t>> &gs, double limit) {
+        std::vector<Measurement> out(gs.size(), Measurement{0.0, OFL_ST_FAILED});
+        if (bad) return out;
+        size_t i = 0;
+        for (; i < gs.size(); ++i) {
+            const int r = log.take(gs[i], out[i]);
+            if (r == 0) break;
+            if (r < 0) {
+                bad = true;
+                return out;
+            }
+        }
+        if (i < gs.size()) {
+            const std::vector<std::vector<uint8_t>> rest(gs.begin() + i, gs.end());
+            const std::vector<Measurement> got = bev(rest, limit);
+            for (size_t k = 0; k < rest.size(); ++k) {
+                out[i + k] = k < got.size() ? got[k] : Measurement{0.0, OFL_ST_FAILED};
+                log.add(rest[k], out[i + k]);
+            }
+        }
+        return out;
+    };
+    GaProgress prog = [&](int gen, const GaTrace &t, double wall) {
+        if (!log.generation(gen, t.rng_state)) bad = true;
+        if (print) {
+            std::fprintf(stderr, "ga generation %d/%d: best %.6f s, %d genes measured (%d from the log), %.1f s\n",
+                         gen, params->T, t.best_t, t.n_measured, log.replayed(), wall);
+            std::fflush(stderr);
+        }
+    };
+    run_ga(a, ga_config(params), lev, tr, (params->flags & OFL_RUN_BATCHED) ? &lbev : nullptr, &prog);
+    if (bad) return fail(OFL_E_STATE, std::string("GA log ") + params->cache_path +
+                                          " disagrees with this search (another gene or random state)");
+    return OFL_OK;
+}
+
 int load_common(const std::string &text, uint64_t seed, ofl_app **out) {
     if (!out) return fail(OFL_E_ARG, "null output pointer");
     *out = nullptr;
@@ -1291,15 +1366,12 @@ int ofl_ga_run(ofl_app *app, const ofl_ga_params *params, void *const *dev_bufs,
         if (rc2 != OFL_OK) hard = rc2;
         return out;
     };
-    GaProgress prog = [&](int gen, const GaTrace &t, double wall) {
-        std::fprintf(stderr, "ga generation %d/%d: best %.6f s, %d genes measured, %.1f s\n", gen, params->T,
-                     t.best_t, t.n_measured, wall);
-        std::fflush(stderr);
-    };
     GaTrace tr;
-    run_ga(a, ga_config(params), ev, tr, (params->flags & OFL_RUN_BATCHED) ? &bev : nullptr,
-           (params->flags & OFL_RUN_PROGRESS) ? &prog : nullptr);
+    std::string what = "app=" + app->ir.name + ":" + std::to_string(app->ir.nests.size());
+    for (const auto &n : app->ir.nests) what += ":" + n.name;
+    rc = run_logged_ga(a, params, what, ev, bev, (params->flags & OFL_RUN_PROGRESS) != 0, tr);
     if (hard != OFL_OK) return hard;
+    if (rc != OFL_OK) return rc;
     fill_ga_result(tr, a, params->M, result);
     return OFL_OK;
 }
@@ -1325,8 +1397,18 @@ int ofl_ga_run_table(int32_t gene_len, const ofl_ga_params *params, const double
         for (const auto &g : gs) out.push_back(ev(g, limit));
         return out;
     };
+    // what is searched: the table (FNV-1a over its bytes)
+    uint64_t h = 1469598103934665603ull;
+    auto mixin = [&](const void *p, size_t n) {
+        for (size_t i = 0; i < n; ++i) h = (h ^ static_cast<const unsigned char *>(p)[i]) * 1099511628211ull;
+    };
+    mixin(t_table, sizeof(double) << gene_len);
+    if (status_table) mixin(status_table, sizeof(int32_t) << gene_len);
+    char what[64];
+    std::snprintf(what, sizeof what, "table=%016llx", (unsigned long long)h);
     GaTrace tr;
-    run_ga(gene_len, ga_config(params), ev, tr, (params->flags & OFL_RUN_BATCHED) ? &bev : nullptr);
+    rc = run_logged_ga(gene_len, params, what, ev, bev, false, tr);
+    if (rc != OFL_OK) return rc;
     fill_ga_result(tr, gene_len, params->M, result);
     return OFL_OK;
 }

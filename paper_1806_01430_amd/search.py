@@ -42,6 +42,8 @@ def main(argv=None):
     ap.add_argument("--deadline-factor", type=float, default=0.0)
     ap.add_argument("--timeout", type=float, default=0.0, help="seconds; cut off any run longer than this (0 = none)")
     ap.add_argument("--progress", action="store_true", help="one line per generation on stderr")
+    ap.add_argument("--log", metavar="PATH", default=None,
+                    help="measurement log of the search: resume from it, append to it (JSON lines)")
     ap.add_argument("--baseline", action="store_true", help="also measure the all-CPU gene")
     ap.add_argument("--emit", metavar="PATH", default=None,
                     help="with a C source as --app: write the program with the best gene's directives to PATH")
@@ -60,7 +62,7 @@ def main(argv=None):
     flags = (GRAPH if args.graph else 0) | (BATCHED if args.batched else 0) | (PROGRESS if args.progress else 0)
     params = ga_params(M=args.M, T=args.T, Pc=args.Pc, Pm=args.Pm, p=args.p, seed=args.ga_seed, reps=args.reps,
                        warmup=args.warmup, policy=policy, flags=flags, deadline_factor=args.deadline_factor,
-                       timeout_s=args.timeout)
+                       timeout_s=args.timeout, cache_path=args.log)
     t0 = time.perf_counter()
     res = app.ga_run(params, bufs)
     wall = time.perf_counter() - t0

@@ -423,3 +423,78 @@ def test_irregular_program_verdicts_and_plans_match_oracle():
         for pol in (xfer.RESIDENT, xfer.PER_REGION, xfer.SECTIONS):
             for flags in (0, 3):
                 assert app.plan_transfers(g, pol, flags) == xfer.totals(o, pl, pol, flags), (g, pol, flags)
+
+
+def test_grids_of_2_gib_or_more_are_rejected():
+    # the sweep and the interior copy address a grid with 32-bit byte
+    # offsets: a grid of 2^31 bytes or more is an invalid application
+    from workloads import appgen
+    ok = appgen.stencil_app(1024, 1024, 511, 1)          # 2.14e9 bytes < 2^31
+    ofl.App(json.dumps(ok))
+    big = appgen.stencil_app(1024, 1024, 513, 1)         # 2.15e9 bytes
+    with pytest.raises(ofl.OflError) as e:
+        ofl.App(json.dumps(big))
+    assert e.value.code == -4 and "2 GiB" in str(e.value)
+    only_copy = {"name": "c", "params": {"I": 1024, "J": 1024, "K": 513},
+                 "buffers": [{"name": "p", "dims": ["I", "J", "K"]}, {"name": "q", "dims": ["I", "J", "K"]}],
+                 "program": [appgen.copy_interior_nest("p", "q")]}
+    with pytest.raises(ofl.OflError) as e:
+        ofl.App(json.dumps(only_copy))
+    assert e.value.code == -4
+
+
+@pytest.mark.parametrize("batched", [False, True])
+def test_ga_log_resume_retraces_the_search(tmp_path, batched):
+    # a search interrupted after generation g (or in the middle of one) and
+    # resumed from its log has the trajectory of an uninterrupted one, and
+    # measures none of the logged genes again
+    a, M, T = 10, 12, 12
+    table = workloads.time_table(a, 21, lo=0.01, hi=5.0)
+    kw = dict(M=M, Pc=0.9, Pm=0.05, p=0.5, seed=7, deadline_factor=3.0, flags=ofl.BATCHED if batched else 0)
+    full = ofl.ga_run_table(a, ofl.ga_params(T=T, **kw), table)
+    log = str(tmp_path / "ga.jsonl")
+    part = ofl.ga_run_table(a, ofl.ga_params(T=5, cache_path=log, **kw), table)
+    assert part["n_generations"] == 5
+    lines = open(log).read().splitlines()
+    assert json.loads(lines[0])["search"].startswith("a=10;M=12;")
+    recs = [json.loads(x) for x in lines[1:]]
+    assert sum(1 for r in recs if "gene" in r) == part["n_measured"]
+    assert [r["gen"] for r in recs if "gen" in r] == [1, 2, 3, 4, 5]
+    for cut in (len(lines), len(lines) - 4, 9):
+        with open(log, "w") as f:
+            f.write("\n".join(lines[:cut]) + "\n")
+        got = ofl.ga_run_table(a, ofl.ga_params(T=T, cache_path=log, **kw), table)
+        for gi in range(T):
+            assert np.array_equal(got["pops"][gi], full["pops"][gi]), (cut, gi)
+            assert np.array_equal(got["times"][gi], full["times"][gi])
+        assert got["best_gene"] == full["best_gene"] and got["n_measured"] == full["n_measured"]
+        # every measurement is in the log once, in the order taken
+        genes = [json.loads(x)["gene"] for x in open(log).read().splitlines()[1:] if '"gene"' in x]
+        assert len(genes) == len(set(genes)) == full["n_measured"]
+    # a line cut short by an interrupted write ends the log there
+    with open(log, "w") as f:
+        f.write("\n".join(lines[:6]) + "\n" + lines[6][:12])
+    got = ofl.ga_run_table(a, ofl.ga_params(T=T, cache_path=log, **kw), table)
+    assert got["best_gene"] == full["best_gene"]
+
+
+def test_ga_log_of_another_search_is_refused(tmp_path):
+    a = 8
+    table = workloads.time_table(a, 2, lo=0.01, hi=5.0)
+    log = str(tmp_path / "ga.jsonl")
+    ofl.ga_run_table(a, ofl.ga_params(M=8, T=3, seed=1, cache_path=log), table)
+    with pytest.raises(ofl.OflError) as e:
+        ofl.ga_run_table(a, ofl.ga_params(M=8, T=3, seed=2, cache_path=log), table)
+    assert e.value.code == -12
+    other = list(table)
+    other[5] *= 2.0
+    with pytest.raises(ofl.OflError):
+        ofl.ga_run_table(a, ofl.ga_params(M=8, T=3, seed=1, cache_path=log), other)
+    # a log whose measurements are out of order disagrees with the search
+    lines = open(log).read().splitlines()
+    body = [x for x in lines[1:] if '"gene"' in x]
+    with open(log, "w") as f:
+        f.write("\n".join([lines[0]] + body[1:2] + body[0:1]) + "\n")
+    with pytest.raises(ofl.OflError) as e:
+        ofl.ga_run_table(a, ofl.ga_params(M=8, T=3, seed=1, cache_path=log), table)
+    assert e.value.code == -12
