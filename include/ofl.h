@@ -115,7 +115,9 @@ enum {
 enum { OFL_F32 = 0, OFL_F64 = 1, OFL_BF16 = 2 };
 
 /* Run status inside evaluation / GA traces. */
-enum { OFL_ST_OK = 0, OFL_ST_TIMEOUT = 1, OFL_ST_FAILED = 2 };
+enum { OFL_ST_OK = 0, OFL_ST_TIMEOUT = 1, OFL_ST_FAILED = 2,
+       OFL_ST_MISMATCH = 3   /* outputs differ from the all-CPU run's (see
+                                verify_rtol); fitness 0 */ };
 
 typedef struct ofl_app ofl_app;
 
@@ -123,6 +125,18 @@ typedef struct {
     int32_t policy;          /* OFL_POLICY_* */
     int32_t flags;           /* OFL_RUN_* bits */
     double deadline_s;       /* wall-time limit of the run, 0 = none */
+    double verify_rtol;      /* > 0: check the run's outputs against those of
+                                the all-zero gene (the program as written, all
+                                on the CPU; that run is made once, untimed and
+                                without a deadline, and kept until the inputs
+                                change): at up to 4096 probe elements of every
+                                output buffer (every element of a smaller
+                                one; the same positions each time),
+                                |x - ref| <= verify_rtol * max |ref over the
+                                buffer's probes|, NaN only where the reference
+                                has NaN.  A failed check returns
+                                OFL_E_MISMATCH with status OFL_ST_MISMATCH.
+                                0 = no check */
 } ofl_run_opts;
 
 typedef struct {
@@ -140,6 +154,12 @@ typedef struct {
     int32_t warmup;          /* untimed runs before them (>= 0) */
     int32_t policy, flags;   /* as ofl_run_opts */
     double deadline_s;       /* per run, 0 = none */
+    double verify_rtol;      /* > 0: each distinct gene's outputs are checked
+                                once, as ofl_run_opts.verify_rtol describes,
+                                on its first run (with OFL_RUN_BATCHED, on one
+                                run of its graphs before the submission); a
+                                gene that fails gets OFL_ST_MISMATCH and no
+                                timed runs */
 } ofl_eval_opts;
 
 typedef struct {
@@ -157,6 +177,8 @@ typedef struct {
                                 TIMEOUT with fitness 0, like a trial cut off
                                 by a timeout (Sec. 5.2); 0 = none.  With
                                 deadline_factor the limit is the smaller one */
+    double verify_rtol;      /* > 0: output check of every measured gene, as in
+                                ofl_eval_opts; a gene that fails has fitness 0 */
     const char *cache_path;  /* NULL or "": the measurements live only in this
                                 call.  Otherwise a log file of the search (the
                                 same-pattern skip of Sec. 4 kept across calls,
@@ -207,8 +229,9 @@ typedef struct {
  * (verdict OFL_REJECT, its own reason or OFL_R_NO_KERNEL) and its transfers
  * follow from its declared accesses.  Every nest's loops must span exactly
  * the index space of its operation (the whole arrays; the interior of the
- * grid for the sweep and the interior copy).  A grid of the sweep or the
- * interior copy must hold under 2 GiB.  Errors: OFL_E_IO (file or host
+ * grid for the sweep and the interior copy).  A grid of the interior copy
+ * must hold under 2 GiB, one of the sweep under 2 GiB with six planes added
+ * (both address their grids with 32-bit byte offsets).  Errors: OFL_E_IO (file or host
  * object cannot be read), OFL_E_PARSE, OFL_E_IR, OFL_E_ARG, OFL_E_NOMEM. */
 int ofl_app_load(const char *path, uint64_t seed, ofl_app **out);
 int ofl_app_load_json(const char *json_text, uint64_t seed, ofl_app **out);

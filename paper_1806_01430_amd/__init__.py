@@ -22,7 +22,7 @@ PARALLEL, PARALLEL_REDUCTION, REJECT = 0, 1, 2
 R_NONE, R_DATA_DEP, R_EXTERNAL_CALL, R_BREAK = 0, 1, 2, 3
 RESIDENT, PER_REGION, SECTIONS = 0, 1, 2
 PRESTAGED, KEEP_OUTPUTS, GRAPH, BATCHED, PROGRESS = 1, 2, 4, 8, 16
-ST_OK, ST_TIMEOUT, ST_FAILED = 0, 1, 2
+ST_OK, ST_TIMEOUT, ST_FAILED, ST_MISMATCH = 0, 1, 2, 3
 BATCH_LOOP, BATCH_GROUPED, BATCH_GROUPED_GRAPH = 0, 1, 2
 _NP_DTYPE = {0: np.float32, 1: np.float64, 2: np.uint16}
 
@@ -44,7 +44,8 @@ class OflError(RuntimeError):
 
 
 class RunOpts(ctypes.Structure):
-    _fields_ = [("policy", ctypes.c_int32), ("flags", ctypes.c_int32), ("deadline_s", ctypes.c_double)]
+    _fields_ = [("policy", ctypes.c_int32), ("flags", ctypes.c_int32), ("deadline_s", ctypes.c_double),
+                ("verify_rtol", ctypes.c_double)]
 
 
 class RunStats(ctypes.Structure):
@@ -58,7 +59,7 @@ class RunStats(ctypes.Structure):
 
 class EvalOpts(ctypes.Structure):
     _fields_ = [("reps", ctypes.c_int32), ("warmup", ctypes.c_int32), ("policy", ctypes.c_int32),
-                ("flags", ctypes.c_int32), ("deadline_s", ctypes.c_double)]
+                ("flags", ctypes.c_int32), ("deadline_s", ctypes.c_double), ("verify_rtol", ctypes.c_double)]
 
 
 class GaParams(ctypes.Structure):
@@ -66,7 +67,7 @@ class GaParams(ctypes.Structure):
                 ("p", ctypes.c_double), ("seed", ctypes.c_uint64), ("reps", ctypes.c_int32),
                 ("warmup", ctypes.c_int32), ("policy", ctypes.c_int32), ("flags", ctypes.c_int32),
                 ("deadline_factor", ctypes.c_double), ("timeout_s", ctypes.c_double),
-                ("cache_path", ctypes.c_char_p)]
+                ("verify_rtol", ctypes.c_double), ("cache_path", ctypes.c_char_p)]
 
 
 class GaResult(ctypes.Structure):
@@ -204,8 +205,8 @@ def app_doc(app, sets=()):
 
 
 def ga_params(M=12, T=12, Pc=0.9, Pm=0.05, p=0.5, seed=1, reps=3, warmup=1, policy=RESIDENT, flags=0,
-              deadline_factor=0.0, timeout_s=0.0, cache_path=None):
-    return GaParams(M, T, Pc, Pm, p, seed, reps, warmup, policy, flags, deadline_factor, timeout_s,
+              deadline_factor=0.0, timeout_s=0.0, cache_path=None, verify_rtol=0.0):
+    return GaParams(M, T, Pc, Pm, p, seed, reps, warmup, policy, flags, deadline_factor, timeout_s, verify_rtol,
                     cache_path.encode() if cache_path else None)
 
 
@@ -350,10 +351,11 @@ class App:
             stream = torch.cuda.current_stream()
         return ctypes.c_void_p(stream.cuda_stream)
 
-    def run_pattern(self, gene, bufs, stream=None, policy=RESIDENT, flags=0, deadline_s=0.0, check=True):
+    def run_pattern(self, gene, bufs, stream=None, policy=RESIDENT, flags=0, deadline_s=0.0, check=True,
+                    verify_rtol=0.0):
         g, gp = _u8(gene)
         st = RunStats()
-        opts = RunOpts(policy, flags, deadline_s)
+        opts = RunOpts(policy, flags, deadline_s, verify_rtol)
         rc = lib().ofl_run_pattern(self._h, gp, len(g), self._ptrs(bufs), len(bufs), self._stream(stream),
                                    ctypes.byref(opts), ctypes.byref(st))
         if check:
@@ -363,11 +365,11 @@ class App:
         return d
 
     def eval_population(self, genes, bufs, stream=None, reps=3, warmup=1, policy=RESIDENT, flags=0,
-                        deadline_s=0.0):
+                        deadline_s=0.0, verify_rtol=0.0):
         G = np.ascontiguousarray(np.asarray(genes, np.uint8).reshape(-1, self.gene_len))
         t = np.zeros(G.shape[0], np.float64)
         s = np.zeros(G.shape[0], np.int32)
-        opts = EvalOpts(reps, warmup, policy, flags, deadline_s)
+        opts = EvalOpts(reps, warmup, policy, flags, deadline_s, verify_rtol)
         _check(lib().ofl_eval_population(self._h, G.ctypes.data_as(_U8P), G.shape[0], self.gene_len,
                                          self._ptrs(bufs), len(bufs), self._stream(stream), ctypes.byref(opts),
                                          t.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),

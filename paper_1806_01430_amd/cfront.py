@@ -840,7 +840,7 @@ def _fits(op, args, loops, buffers, params, rvars):
         slot = dict(rvars)
         return (dt(a["p"]) == dt(a["q"]) == "f32" and dt(a["res"]) == "f64" and len(dims(a["p"])) == 3
                 and dims(a["p"]) == dims(a["q"]) and a["p"] != a["q"] and interior(a["p"])
-                and nbytes(a["p"]) < 2 ** 31 and a["slot"] in slot)
+                and (dims(a["p"])[0] + 6) * dims(a["p"])[1] * dims(a["p"])[2] * 4 < 2 ** 31 and a["slot"] in slot)
     if op == "copy_interior":
         return (dt(a["dst"]) == dt(a["src"]) == "f32" and len(dims(a["dst"])) == 3
                 and dims(a["dst"]) == dims(a["src"]) and interior(a["dst"]) and nbytes(a["dst"]) < 2 ** 31)

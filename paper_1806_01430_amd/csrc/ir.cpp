@@ -255,9 +255,11 @@ bool resolve_op(Ctx &cx, Nest &n, const Json *args, const std::vector<int64_t> &
         if (!need(cx, n, is(0, DT_F32) && is(1, DT_F32) && is(2, DT_F64) && B(0).dims.size() == 3 &&
                               B(0).dims == B(1).dims && n.b[0] != n.b[1], "needs distinct f32 grids and an f64 residual"))
             return false;
+        // the sweep forms 32-bit byte offsets up to five planes past the grid
         if (!need(cx, n, B(0).dims[0] >= 1 && B(0).dims[1] >= 1 && B(0).dims[2] >= 1 &&
-                              B(0).nbytes < (1ull << 31), "grid extents (a grid must hold under 2 GiB: the sweep "
-                                                          "addresses it with 32-bit byte offsets)")) return false;
+                              (B(0).dims[0] + 6) * B(0).dims[1] * B(0).dims[2] * 4 < (1ll << 31),
+                  "grid extents (the grid plus six planes must hold under 2 GiB: the sweep addresses it with "
+                  "32-bit byte offsets)")) return false;
         const Json *sl = args->get("slot");
         if (!sl || sl->kind != Json::Str) return need(cx, n, false, "missing residual slot");
         for (size_t r = 0; r < n.repeats.size(); ++r)

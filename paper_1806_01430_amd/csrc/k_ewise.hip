@@ -236,7 +236,32 @@ __global__ __launch_bounds__(kOrderedSumThreads) void k_sumsq_finish(const doubl
     ordered_sum_into(partials, n, s_out);
 }
 
+// out[i] = element idx[i] of src, widened to double (dtype 0 f32, 1 f64,
+// 2 bf16): the probes of an output check.
+__global__ __launch_bounds__(kThreads) void k_gather_probes(const void *__restrict__ src, int dtype,
+                                                            const int64_t *__restrict__ idx, int n,
+                                                            double *__restrict__ out) {
+    const int i = blockIdx.x * kThreads + threadIdx.x;
+    if (i >= n) return;
+    const int64_t e = idx[i];
+    double v;
+    if (dtype == 1) {
+        v = static_cast<const double *>(src)[e];
+    } else if (dtype == 2) {
+        v = (double)__uint_as_float((unsigned)static_cast<const unsigned short *>(src)[e] << 16);
+    } else {
+        v = (double)static_cast<const float *>(src)[e];
+    }
+    out[i] = v;
+}
+
 }  // namespace
+
+hipError_t gather_probes(const void *src, int dtype, const int64_t *idx, int n, double *out, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    return launch(k_gather_probes, dim3((unsigned)((n + kThreads - 1) / kThreads)), dim3(kThreads), 0, s, src,
+                  dtype, idx, n, out);
+}
 
 hipError_t fill_zero(void *dst, uint64_t bytes, hipStream_t s) {
     if (bytes == 0) return hipSuccess;

@@ -17,6 +17,8 @@ struct ReduceScratch {
 };
 
 hipError_t fill_zero(void *dst, uint64_t bytes, hipStream_t s);
+// out[i] = (double) element idx[i] of src (dtype 0 f32, 1 f64, 2 bf16), i < n.
+hipError_t gather_probes(const void *src, int dtype, const int64_t *idx, int n, double *out, hipStream_t s);
 hipError_t init_uniform(float *x, int64_t n, uint64_t key, hipStream_t s);
 hipError_t add_scaled(float *C, const float *A, float alpha, int64_t n, hipStream_t s);
 hipError_t avg2(float *S, const float *X, const float *Y, int64_t n, hipStream_t s);

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <atomic>
 #include <chrono>
+#include <cmath>
 #include <cstdio>
 #include <cstring>
 #include <fstream>
@@ -140,6 +141,15 @@ struct ofl_app {
 
     void *host_lib = nullptr;                // dlopen handle of the host object, if any
 
+    // output check: probe positions per output buffer and the all-zero
+    // gene's values there (valid until the inputs change)
+    bool ref_valid = false, ref_bufs_done = false;
+    std::vector<int> ref_bufs;
+    std::vector<std::vector<int64_t>> ref_pos;
+    std::vector<std::vector<double>> ref_val;
+    int64_t *d_probe_idx = nullptr;
+    double *d_probe_val = nullptr;
+
     ~ofl_app() {
         graphs.clear();
         if (capture_stream) (void)hipStreamDestroy(capture_stream);
@@ -153,6 +163,8 @@ struct ofl_app {
         for (auto e : events) (void)hipEventDestroy(e);
         for (auto e : chain_events) (void)hipEventDestroy(e);
         if (host_lib) dlclose(host_lib);
+        if (d_probe_idx) (void)hipFree(d_probe_idx);
+        if (d_probe_val) (void)hipFree(d_probe_val);
     }
 };
 
@@ -889,6 +901,131 @@ RunResult run_any(ofl_app *app, const std::vector<uint8_t> &placement, void *con
     return run_once(app, placement, dev, stream, policy, flags, deadline_s);
 }
 
+// ------------------------------------------------------------ output check
+// The outputs of a pattern against those of the all-zero gene (the program
+// as written, every nest on the CPU): at up to kProbes fixed positions per
+// output buffer, read from the host copy or, when the device holds the
+// newest values, gathered there by one small kernel.
+constexpr int kProbes = 4096;
+
+void probe_positions(ofl_app *app) {
+    if (!app->ref_pos.empty() || app->ref_bufs_done) return;
+    const AppIR &ir = app->ir;
+    for (size_t b = 0; b < ir.bufs.size(); ++b) {
+        if (!ir.bufs[b].output) continue;
+        const int64_t cnt = ir.bufs[b].count;
+        std::vector<int64_t> pos;
+        if (cnt <= kProbes) {
+            for (int64_t e = 0; e < cnt; ++e) pos.push_back(e);
+        } else {
+            // a fixed pseudo-random sample (the SplitMix64 mix of buffer and
+            // probe number), sorted
+            for (int i = 0; i < kProbes; ++i) {
+                uint64_t z = ((uint64_t)b << 32) + (uint64_t)i + 1;
+                z *= 0x9E3779B97F4A7C15ull;
+                z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+                z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+                z ^= z >> 31;
+                pos.push_back((int64_t)(z % (uint64_t)cnt));
+            }
+            std::sort(pos.begin(), pos.end());
+        }
+        app->ref_bufs.push_back((int)b);
+        app->ref_pos.push_back(pos);
+    }
+    app->ref_bufs_done = true;
+}
+
+double host_value(const Buffer &buf, const void *p, int64_t e) {
+    if (buf.dtype == DT_F64) return static_cast<const double *>(p)[e];
+    if (buf.dtype == DT_BF16) {
+        const uint32_t u = (uint32_t) static_cast<const uint16_t *>(p)[e] << 16;
+        float f;
+        std::memcpy(&f, &u, 4);
+        return f;
+    }
+    return static_cast<const float *>(p)[e];
+}
+
+// Probe values of every output buffer after the last completed run.
+int read_probes(ofl_app *app, std::vector<std::vector<double>> &vals) {
+    probe_positions(app);
+    vals.assign(app->ref_bufs.size(), {});
+    for (size_t k = 0; k < app->ref_bufs.size(); ++k) {
+        const int b = app->ref_bufs[k];
+        const Buffer &buf = app->ir.bufs[b];
+        const std::vector<int64_t> &pos = app->ref_pos[k];
+        vals[k].resize(pos.size());
+        if (app->host_valid[b]) {
+            if (!app->host_written[b] && app->host_dirty[b]) restore_host(app, b);
+            for (size_t i = 0; i < pos.size(); ++i) vals[k][i] = host_value(buf, app->host[b], pos[i]);
+            continue;
+        }
+        hipError_t e = hipSuccess;
+        if (!app->d_probe_idx) {
+            e = hipMalloc(&app->d_probe_idx, kProbes * sizeof(int64_t));
+            if (e == hipSuccess) e = hipMalloc(&app->d_probe_val, kProbes * sizeof(double));
+            if (e != hipSuccess) return hip_fail(e, "probe buffers");
+        }
+        const hipStream_t s = app->last_stream;
+        const int dt = buf.dtype == DT_F64 ? 1 : (buf.dtype == DT_BF16 ? 2 : 0);
+        e = hipMemcpyAsync(app->d_probe_idx, pos.data(), pos.size() * sizeof(int64_t), hipMemcpyHostToDevice, s);
+        if (e == hipSuccess)
+            e = k::gather_probes(app->last_dev[b], dt, app->d_probe_idx, (int)pos.size(), app->d_probe_val, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(vals[k].data(), app->d_probe_val, pos.size() * sizeof(double), hipMemcpyDeviceToHost,
+                               s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "output probes");
+    }
+    return OFL_OK;
+}
+
+// The reference probes: one run of the all-zero gene, untimed, no deadline;
+// kept until the inputs change.
+int ensure_reference(ofl_app *app, void *const *dev, hipStream_t s, int policy) {
+    if (app->ref_valid) return OFL_OK;
+    const std::vector<uint8_t> zero(app->ir.nests.size(), 0);
+    RunResult rr = run_once(app, zero, dev, s, policy, 0, 0.0);
+    if (rr.code != OFL_OK) return rr.code;
+    const int rc = read_probes(app, app->ref_val);
+    if (rc != OFL_OK) return rc;
+    app->ref_valid = true;
+    return OFL_OK;
+}
+
+// Whether the last run's outputs agree with the reference within rtol of
+// each buffer's largest reference probe (NaN only where the reference has
+// NaN).
+int outputs_agree(ofl_app *app, double rtol, bool *agree) {
+    std::vector<std::vector<double>> got;
+    const int rc = read_probes(app, got);
+    if (rc != OFL_OK) return rc;
+    *agree = true;
+    for (size_t k = 0; k < got.size() && *agree; ++k) {
+        const std::vector<double> &ref = app->ref_val[k];
+        double scale = 0.0;
+        for (double r : ref)
+            if (std::isfinite(r)) scale = std::max(scale, std::fabs(r));
+        for (size_t i = 0; i < ref.size(); ++i) {
+            const double x = got[k][i], r = ref[i];
+            if (std::isnan(r) || std::isnan(x)) {
+                if (!(std::isnan(r) && std::isnan(x))) *agree = false;
+            } else if (std::isinf(r) || std::isinf(x)) {
+                if (x != r) *agree = false;
+            } else if (std::fabs(x - r) > rtol * scale) {
+                *agree = false;
+            }
+            if (!*agree) {
+                (void)fail(OFL_E_MISMATCH, "output '" + app->ir.bufs[app->ref_bufs[k]].name + "' differs from the all-CPU run at "
+                               "element " + std::to_string(app->ref_pos[k][i]));
+                break;
+            }
+        }
+    }
+    return OFL_OK;
+}
+
 double median_of(std::vector<double> v) {
     std::sort(v.begin(), v.end());
     const size_t n = v.size();
@@ -897,11 +1034,28 @@ double median_of(std::vector<double> v) {
 
 // warmup + reps runs of one gene; median time
 Measurement measure(ofl_app *app, const std::vector<uint8_t> &placement, void *const *dev, hipStream_t s,
-                    int reps, int warmup, int policy, int flags, double deadline_s, int *hard_error) {
+                    int reps, int warmup, int policy, int flags, double deadline_s, int *hard_error,
+                    double verify_rtol = 0.0) {
     Measurement m;
     std::vector<double> ts;
+    if (verify_rtol > 0) {
+        const int rc = ensure_reference(app, dev, s, policy);
+        if (rc != OFL_OK) {
+            *hard_error = rc;
+            return Measurement{0.0, OFL_ST_FAILED};
+        }
+    }
     for (int r = 0; r < warmup + reps; ++r) {
         RunResult rr = run_any(app, placement, dev, s, policy, flags, deadline_s);
+        if (r == 0 && verify_rtol > 0 && rr.code == OFL_OK) {
+            bool agree = false;
+            const int rc = outputs_agree(app, verify_rtol, &agree);
+            if (rc != OFL_OK) {
+                *hard_error = rc;
+                return Measurement{0.0, OFL_ST_FAILED};
+            }
+            if (!agree) return Measurement{0.0, OFL_ST_MISMATCH};
+        }
         if (rr.code == OFL_E_TIMEOUT) {
             m.status = OFL_ST_TIMEOUT;
             m.t = rr.st.t_total_s;
@@ -924,9 +1078,9 @@ Measurement measure(ofl_app *app, const std::vector<uint8_t> &placement, void *c
 // run graph back to back on the stream, an event pair around every run
 // graph; one synchronisation; per gene the median of its timed intervals.
 // limit > 0: a time over it becomes OFL_ST_TIMEOUT at the limit.
-int measure_batched(ofl_app *app, const std::vector<std::vector<uint8_t>> &placements, void *const *dev,
-                    hipStream_t s, int reps, int warmup, int policy, int flags, double limit,
-                    std::vector<Measurement> &out) {
+int measure_batched_all(ofl_app *app, const std::vector<std::vector<uint8_t>> &placements, void *const *dev,
+                        hipStream_t s, int reps, int warmup, int policy, int flags, double limit,
+                        std::vector<Measurement> &out) {
     const size_t n = placements.size();
     out.assign(n, Measurement{0.0, OFL_ST_FAILED});
     if (n == 0) return OFL_OK;
@@ -983,6 +1137,46 @@ int measure_batched(ofl_app *app, const std::vector<std::vector<uint8_t>> &place
         out[g] = m;
         note_graph_run(app, *ge[g], dev, s);
     }
+    return OFL_OK;
+}
+
+// Batched measurement with the optional output check: each gene runs once
+// eagerly first (with the limit) and is checked; genes that fail the check
+// or time out there are left out of the submission.
+int measure_batched(ofl_app *app, const std::vector<std::vector<uint8_t>> &placements, void *const *dev,
+                    hipStream_t s, int reps, int warmup, int policy, int flags, double limit,
+                    std::vector<Measurement> &out, double verify_rtol = 0.0) {
+    if (!(verify_rtol > 0)) return measure_batched_all(app, placements, dev, s, reps, warmup, policy, flags, limit, out);
+    const size_t n = placements.size();
+    out.assign(n, Measurement{0.0, OFL_ST_FAILED});
+    int rc = ensure_reference(app, dev, s, policy);
+    if (rc != OFL_OK) return rc;
+    std::vector<size_t> keep;
+    std::vector<std::vector<uint8_t>> kept;
+    const int eager = flags & ~(OFL_RUN_GRAPH | OFL_RUN_BATCHED);
+    for (size_t g = 0; g < n; ++g) {
+        RunResult rr = run_once(app, placements[g], dev, s, policy, eager, limit > 0 ? limit : 0.0);
+        if (rr.code == OFL_E_TIMEOUT) {
+            out[g] = Measurement{limit > 0 ? limit : rr.st.t_total_s, OFL_ST_TIMEOUT};
+            continue;
+        }
+        if (rr.code != OFL_OK) {
+            if (rr.code == OFL_E_HIP || rr.code == OFL_E_NOMEM || rr.code == OFL_E_STATE) return rr.code;
+            continue;
+        }
+        bool agree = false;
+        if ((rc = outputs_agree(app, verify_rtol, &agree)) != OFL_OK) return rc;
+        if (!agree) {
+            out[g] = Measurement{0.0, OFL_ST_MISMATCH};
+            continue;
+        }
+        keep.push_back(g);
+        kept.push_back(placements[g]);
+    }
+    std::vector<Measurement> got;
+    rc = measure_batched_all(app, kept, dev, s, reps, warmup, policy, flags, limit, got);
+    if (rc != OFL_OK) return rc;
+    for (size_t i = 0; i < keep.size(); ++i) out[keep[i]] = got[i];
     return OFL_OK;
 }
 
@@ -1227,6 +1421,7 @@ int ofl_set_input(ofl_app *app, int32_t buf, const void *src, uint64_t bytes) {
     }
     if (!app->host.empty()) app->host_dirty[buf] = 1;   // host copy must be refreshed
     app->graphs.clear();   // captured reset graphs refer to the old device copy
+    app->ref_valid = false;   // the reference outputs belong to the old inputs
     if (!app->dev_setup.empty() && app->dev_setup[buf]) {
         (void)hipFree(app->dev_setup[buf]);
         app->dev_setup[buf] = nullptr;
@@ -1279,7 +1474,18 @@ int ofl_run_pattern(ofl_app *app, const uint8_t *gene, int32_t gene_len, void *c
     const double deadline = opts ? opts->deadline_s : 0.0;
     if (policy < OFL_POLICY_RESIDENT || policy > OFL_POLICY_SECTIONS) return fail(OFL_E_ARG, "bad policy");
     if (flags & ~(OFL_RUN_PRESTAGED | OFL_RUN_KEEP_OUTPUTS | OFL_RUN_GRAPH)) return fail(OFL_E_ARG, "bad flags");
+    const double rtol = opts ? opts->verify_rtol : 0.0;
+    if (rtol > 0 && (rc = ensure_reference(app, dev_bufs, static_cast<hipStream_t>(stream), policy)) != OFL_OK)
+        return rc;
     RunResult rr = run_any(app, placement, dev_bufs, static_cast<hipStream_t>(stream), policy, flags, deadline);
+    if (rr.code == OFL_OK && rtol > 0) {
+        bool agree = false;
+        if ((rc = outputs_agree(app, rtol, &agree)) != OFL_OK) return rc;
+        if (!agree) {
+            rr.st.status = OFL_ST_MISMATCH;
+            rr.code = OFL_E_MISMATCH;   // the message names the buffer and element
+        }
+    }
     if (stats) *stats = rr.st;
     return rr.code;
 }
@@ -1310,7 +1516,7 @@ int ofl_eval_population(ofl_app *app, const uint8_t *genes, int32_t pop, int32_t
         }
         std::vector<Measurement> got;
         rc = measure_batched(app, places, dev_bufs, static_cast<hipStream_t>(stream), opts->reps, opts->warmup,
-                             opts->policy, opts->flags, opts->deadline_s, got);
+                             opts->policy, opts->flags, opts->deadline_s, got, opts->verify_rtol);
         if (rc != OFL_OK) return rc;
         for (int32_t m = 0; m < pop; ++m) {
             std::vector<uint8_t> g(genes + (size_t)m * gene_len, genes + (size_t)(m + 1) * gene_len);
@@ -1330,7 +1536,7 @@ int ofl_eval_population(ofl_app *app, const uint8_t *genes, int32_t pop, int32_t
             check_gene(app, g.data(), gene_len, placement);
             int hard = OFL_OK;
             meas = measure(app, placement, dev_bufs, static_cast<hipStream_t>(stream), opts->reps, opts->warmup,
-                           opts->policy, opts->flags, opts->deadline_s, &hard);
+                           opts->policy, opts->flags, opts->deadline_s, &hard, opts->verify_rtol);
             if (hard != OFL_OK) return hard;
             seen[g] = meas;
         }
@@ -1354,7 +1560,7 @@ int ofl_ga_run(ofl_app *app, const ofl_ga_params *params, void *const *dev_bufs,
         std::vector<uint8_t> placement;
         check_gene(app, g.data(), a, placement);
         return measure(app, placement, dev_bufs, static_cast<hipStream_t>(stream), params->reps, params->warmup,
-                       params->policy, params->flags, limit > 0 ? limit : 0.0, &hard);
+                       params->policy, params->flags, limit > 0 ? limit : 0.0, &hard, params->verify_rtol);
     };
     BatchEvaluator bev = [&](const std::vector<std::vector<uint8_t>> &gs, double limit) {
         std::vector<Measurement> out(gs.size(), Measurement{0.0, OFL_ST_FAILED});
@@ -1362,7 +1568,8 @@ int ofl_ga_run(ofl_app *app, const ofl_ga_params *params, void *const *dev_bufs,
         std::vector<std::vector<uint8_t>> places(gs.size());
         for (size_t i = 0; i < gs.size(); ++i) check_gene(app, gs[i].data(), a, places[i]);
         const int rc2 = measure_batched(app, places, dev_bufs, static_cast<hipStream_t>(stream), params->reps,
-                                        params->warmup, params->policy, params->flags, limit, out);
+                                        params->warmup, params->policy, params->flags, limit, out,
+                                        params->verify_rtol);
         if (rc2 != OFL_OK) hard = rc2;
         return out;
     };

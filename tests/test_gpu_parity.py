@@ -797,3 +797,51 @@ def test_irregular_program_all_genes():
             assert np.all(np.abs(got["F"].astype(np.float64) - want["F"]) <= tol_f), g
             assert np.all(np.abs(got["B"].astype(np.float64) - want["B"]) <= tol_f.T), g
             assert abs(got["s"][0] - want["s"][0]) / want["s"][0] < 1e-4, g
+
+
+# ---------------------------------------------------------------- output check
+def test_output_check_against_the_all_cpu_run():
+    # every pattern of the tiny application reproduces the all-CPU run's
+    # outputs at the probes (the product within 1e-4 of each output's scale)
+    doc = workloads.app_doc("tiny")
+    app = ofl.App(json.dumps(doc))
+    bufs = app.alloc_device_buffers()
+    genes = [[(idx >> i) & 1 for i in range(6)] for idx in range(64)]
+    say("case output check, 64 genes eagerly")
+    t, s = app.eval_population(genes, bufs, reps=1, warmup=1, verify_rtol=1e-4)
+    assert np.all(s == ofl.ST_OK) and np.all(t > 0)
+    say("case output check, 64 genes in one submission")
+    t, s = app.eval_population(genes, bufs, reps=1, warmup=0, flags=ofl.BATCHED, verify_rtol=1e-4)
+    assert np.all(s == ofl.ST_OK)
+    say("case output check in the GA")
+    res = app.ga_run(ofl.ga_params(M=6, T=3, seed=3, reps=1, warmup=0, verify_rtol=1e-4), bufs)
+    assert np.all(res["status"] == ofl.ST_OK)
+    # new inputs: the reference is taken again from them
+    p0 = app.read_buffer("p")
+    app.set_input("p", np.zeros_like(p0) + np.float32(0.5))
+    st = app.run_pattern([1] * 6, bufs, verify_rtol=1e-4)
+    assert st["status"] == ofl.ST_OK
+    assert np.all(app.read_buffer("p") == np.float32(0.5))
+
+
+def test_output_check_flags_a_less_accurate_product():
+    # the FP8x2 product differs from the FP32 loop run on the CPU by ~1e-4 of
+    # its scale: within a tolerance of 1e-3, beyond one of 1e-6 (a MISMATCH,
+    # fitness 0); the all-CPU pattern always agrees with itself
+    doc = workloads.app_doc("precision", N=160, I=13, J=17, K=67, SWEEPS=3)
+    doc["program"][1]["args"]["prec"] = "fp8x2"
+    app = ofl.App(json.dumps(doc))
+    bufs = app.alloc_device_buffers()
+    say("case output check fp8x2")
+    assert app.run_pattern([1] * 4, bufs, verify_rtol=1e-3)["status"] == ofl.ST_OK
+    st = app.run_pattern([1] * 4, bufs, verify_rtol=1e-6, check=False)
+    assert st["rc"] == -11 and st["status"] == ofl.ST_MISMATCH
+    assert "differs from the all-CPU run" in ofl.last_error()
+    assert app.run_pattern([0] * 4, bufs, verify_rtol=1e-12)["status"] == ofl.ST_OK
+    assert app.run_pattern([0, 1, 1, 1], bufs, verify_rtol=1e-9)["status"] == ofl.ST_OK
+    t, s = app.eval_population([[1] * 4, [0] * 4, [0, 1, 1, 1]], bufs, reps=1, warmup=0, verify_rtol=1e-6)
+    assert list(s) == [ofl.ST_MISMATCH, ofl.ST_OK, ofl.ST_OK]
+    res = app.ga_run(ofl.ga_params(M=4, T=2, seed=5, reps=1, warmup=0, verify_rtol=1e-6), bufs)
+    for gen_pop, gen_st in zip(res["pops"], res["status"]):
+        for g, st_ in zip(gen_pop, gen_st):
+            assert st_ == (ofl.ST_MISMATCH if g[0] == 1 else ofl.ST_OK), (list(g), st_)

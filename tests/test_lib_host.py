@@ -429,9 +429,10 @@ def test_grids_of_2_gib_or_more_are_rejected():
     # the sweep and the interior copy address a grid with 32-bit byte
     # offsets: a grid of 2^31 bytes or more is an invalid application
     from workloads import appgen
-    ok = appgen.stencil_app(1024, 1024, 511, 1)          # 2.14e9 bytes < 2^31
+    # (the sweep's offsets reach up to five planes past the grid: I + 6 planes)
+    ok = appgen.stencil_app(1000, 1024, 511, 1)          # 1006 planes: 2.106e9 bytes < 2^31
     ofl.App(json.dumps(ok))
-    big = appgen.stencil_app(1024, 1024, 513, 1)         # 2.15e9 bytes
+    big = appgen.stencil_app(1024, 1024, 511, 1)         # 1030 planes: 2.156e9 bytes
     with pytest.raises(ofl.OflError) as e:
         ofl.App(json.dumps(big))
     assert e.value.code == -4 and "2 GiB" in str(e.value)
