@@ -369,6 +369,31 @@ int ofl_set_kernel_timing_sample(ofl_app *app, int32_t stride, int32_t phase);
  * run's launches, timed with neither nest). */
 int ofl_kernel_stats(const ofl_app *app, const char *op, int64_t *executions, double *total_ms);
 
+/* ---------------------------------------------------------------- nest calls */
+
+/* One sweep of the 19-point nest on caller-owned device grids, the offloaded
+ * form of the iterated stencil nest as a call of its own (Sec. 3.2: a call
+ * the offloader can substitute, like a library call's GPU implementation).
+ * p, q: distinct I x J x K f32 grids, p[i][j][k] with k contiguous, 16-byte
+ * aligned; res_slot: one double in device memory, 8-byte aligned.  Writes
+ * q on the interior (1 <= i < I-1, 1 <= j < J-1, 1 <= k < K-1):
+ *   q = (p/4 + F/16) + E/32, F = (a_{i-1} + a_{i+1}) + x_i,
+ *   E = (x_{i-1} + x_{i+1}) + y_i, with the plane partial sums
+ *   a = p, x = (p[j-1] + p[j+1]) + (p[k-1] + p[k+1]),
+ *   y = (p[j-1][k-1] + p[j-1][k+1]) + (p[j+1][k-1] + p[j+1][k+1])
+ * (weights 1/4, 1/16, 1/32 on the centre, the 6 face and the 12 edge
+ * neighbours; FP32, no contraction); the boundary of q is not touched; and
+ * adds sum over the interior of ((double)q - (double)p)^2 to res_slot[0] in
+ * a fixed order (reproducible bits).  Launches on `stream` (a hipStream_t;
+ * NULL = the null stream) and does not synchronise.  Scratch: the sweep's
+ * per-wave residual partials, in device memory the library allocates on the
+ * first call on each device (grown when needed, kept until the process
+ * ends); calls that overlap on one device race on it.  Errors: OFL_E_ARG
+ * (null or misaligned pointer, p == q), OFL_E_RANGE (an extent < 1, or the
+ * grid plus six planes 2 GiB or more: 32-bit byte offsets), OFL_E_NOMEM,
+ * OFL_E_HIP. */
+int ofl_sweep19(const float *p, float *q, int64_t I, int64_t J, int64_t K, double *res_slot, void *stream);
+
 /* ---------------------------------------------------------------- instance batches */
 
 /* Many instances of one application description that differ only in their

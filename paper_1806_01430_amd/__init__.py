@@ -34,7 +34,7 @@ EXPORTS = ["ofl_app_load", "ofl_app_load_json", "ofl_app_free", "ofl_app_info", 
            "ofl_set_kernel_timing_sample", "ofl_kernel_stats",
            "ofl_batch_create", "ofl_batch_free", "ofl_batch_info", "ofl_batch_buf_info", "ofl_batch_buf_dims",
            "ofl_batch_buf_name", "ofl_batch_setup", "ofl_batch_run", "ofl_batch_get_config",
-           "ofl_batch_set_config", "ofl_batch_tune", "ofl_status_str", "ofl_last_error"]
+           "ofl_batch_set_config", "ofl_batch_tune", "ofl_sweep19", "ofl_status_str", "ofl_last_error"]
 
 
 class OflError(RuntimeError):
@@ -159,6 +159,7 @@ def lib():
             "ofl_batch_set_config": (_I, [_P, ctypes.POINTER(BatchConfig)]),
             "ofl_batch_tune": (_I, [_P, ctypes.POINTER(_P), _I, _P, _I, ctypes.POINTER(TuneEntry), _I,
                                     ctypes.POINTER(_I)]),
+            "ofl_sweep19": (_I, [_P, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _P, _P]),
             "ofl_status_str": (ctypes.c_char_p, [_I]),
             "ofl_last_error": (ctypes.c_char_p, []),
         }
@@ -410,6 +411,22 @@ class App:
         n, ms = ctypes.c_int64(), ctypes.c_double()
         _check(lib().ofl_kernel_stats(self._h, op.encode(), ctypes.byref(n), ctypes.byref(ms)), "ofl_kernel_stats")
         return n.value, ms.value
+
+
+def sweep19(p, q, res, slot=0, stream=None):
+    """One sweep of the 19-point nest on torch tensors p, q (float32, I x J x
+    K, on the GPU) adding its FP64 residual into res[slot] (float64 tensor on
+    the GPU); launches on the stream, returns without synchronising."""
+    import torch
+    I, J, K = p.shape
+    if tuple(q.shape) != (I, J, K):
+        raise ValueError("p and q differ in shape")
+    if p.dtype != torch.float32 or q.dtype != torch.float32 or res.dtype != torch.float64:
+        raise ValueError("p, q must be float32 and res float64")
+    if not (p.is_contiguous() and q.is_contiguous()) or not 0 <= slot < res.numel():
+        raise ValueError("p, q must be contiguous and slot inside res")
+    _check(lib().ofl_sweep19(_P(p.data_ptr()), _P(q.data_ptr()), I, J, K, _P(res.data_ptr() + 8 * slot),
+                             App._stream(stream)), "ofl_sweep19")
 
 
 class Batch:

@@ -291,6 +291,64 @@ __global__ __launch_bounds__(kThreads) void k_copy_interior(float *__restrict__ 
     for (int row0 = gwave * ROWS; row0 < rows; row0 += nwaves * ROWS) copy_rows<ROWS, POL>(rp, rq, J, K, rows, row0, lane);
 }
 
+// p = q on the interior, plane-range form: in every interior plane i the
+// elements p[i][1][1] .. p[i][J-2][K-2] lie in one contiguous range of
+// (J-2) K - 2 floats, which is copied in 16-byte pieces aligned to the
+// buffer, U pieces per lane in flight (loads first); the only elements of
+// that range outside the interior are the boundary columns between
+// consecutive rows (k = K-1, then k = 0 of the next row), and a piece that
+// holds one of them (or straddles an end of the range) is written dword by
+// dword without them.  Grid: x covers a plane's pieces, y the interior
+// planes, plus one more row of blocks whose first block runs the residual
+// finish of the sweep launched before (fin_n > 0).
+template <int U, int POL>
+__global__ __launch_bounds__(kThreads) void k_copy_interior_flat(float *__restrict__ p, const float *__restrict__ q,
+                                                                 int I, int J, int K, float invK,
+                                                                 const double *fin_partials, int fin_n,
+                                                                 double *fin_slot) {
+    const int plane = blockIdx.y;
+    if (plane >= I - 2) {
+        if (blockIdx.x == 0) ordered_sum_into(fin_partials, fin_n, fin_slot);
+        return;
+    }
+    const int i = plane + 1;
+    const int pbase = i * J * K;                      // first element of plane i
+    const int s = pbase + K + 1;                      // p[i][1][1]
+    const int e = pbase + (J - 2) * K + K - 1;        // one past p[i][J-2][K-2]
+    const int bytes = I * J * K * 4;
+    const __amdgpu_buffer_rsrc_t rq = __builtin_amdgcn_make_buffer_rsrc((void *)q, (short)0, bytes, kBufferConfig);
+    const __amdgpu_buffer_rsrc_t rp = __builtin_amdgcn_make_buffer_rsrc((void *)p, (short)0, bytes, kBufferConfig);
+    const int g0 = (s >> 2) + blockIdx.x * (kThreads * U) + (int)threadIdx.x;   // first piece of this lane
+    __attribute__((ext_vector_type(4))) unsigned v[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int f = 4 * (g0 + u * kThreads);
+        v[u] = __builtin_amdgcn_raw_buffer_load_b128(rq, f < e ? f * 4 : kOutOfRange, 0, POL);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int f = 4 * (g0 + u * kThreads);
+        // column of the piece's first element (r < 2^24: exact in float, the
+        // quotient off by at most one)
+        const int r = f - pbase;
+        int kq = (int)((float)r * invK);
+        int k = r - kq * K;
+        if (k < 0) k += K;
+        if (k >= K) k -= K;
+        const bool whole = f >= s && f + 4 <= e && k >= 1 && k + 3 <= K - 2;
+        __builtin_amdgcn_raw_buffer_store_b128(v[u], rp, whole ? f * 4 : kOutOfRange, 0, POL);
+        if (!whole && f < e) {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                int kt = k + t;
+                if (kt >= K) kt -= K;
+                const bool ok = f + t >= s && f + t < e && kt != 0 && kt != K - 1;
+                __builtin_amdgcn_raw_buffer_store_b32(v[u][t], rp, ok ? (f + t) * 4 : kOutOfRange, 0, POL);
+            }
+        }
+    }
+}
+
 // Sweep forms: one column per lane (62 outputs per wave), two columns per
 // lane (126 outputs), two columns per lane with scalar-loaded halo columns
 // (128 outputs, 8-byte stores on interior tiles).
@@ -585,6 +643,23 @@ hipError_t launch_copy(float *p, const float *q, int64_t I, int64_t J, int64_t K
                   (int)K, f.partials, f.n, f.target);
 }
 
+constexpr int kFlatPieces = 4;   // 16-byte pieces per lane of the plane-range copy
+
+hipError_t launch_copy_flat(float *p, const float *q, int64_t I, int64_t J, int64_t K, int nt,
+                            const ResidualFinish &f, hipStream_t s) {
+    // pieces a plane's range may touch: its floats / 4, plus one for a
+    // misaligned start and one for the end
+    const int64_t pieces = ((J - 2) * K - 2) / 4 + 2;
+    const int64_t bx = (pieces + kThreads * kFlatPieces - 1) / (kThreads * kFlatPieces);
+    const dim3 grid((unsigned)bx, (unsigned)(I - 2 + (f.n > 0 ? 1 : 0)));
+    const float invK = 1.0f / (float)K;
+    if (nt)
+        return launch((k_copy_interior_flat<kFlatPieces, kNonTemporal>), grid, dim3(kThreads), 0, s, p, q, (int)I,
+                      (int)J, (int)K, invK, f.partials, f.n, f.target);
+    return launch((k_copy_interior_flat<kFlatPieces, 0>), grid, dim3(kThreads), 0, s, p, q, (int)I, (int)J, (int)K,
+                  invK, f.partials, f.n, f.target);
+}
+
 hipError_t copy_interior(float *p, const float *q, int64_t I, int64_t J, int64_t K, hipStream_t s,
                          ResidualFinish *fin) {
     const ResidualFinish f = fin ? *fin : ResidualFinish{};
@@ -599,6 +674,9 @@ hipError_t copy_interior(float *p, const float *q, int64_t I, int64_t J, int64_t
     const bool small = (I - 2) * (J - 2) <= 65536;
     int rows_per_wave = small ? 8 : 2, bpc = small ? 16 : 32, nt = 0;
     copy_env_override(rows_per_wave, bpc, nt);
+    // OFL_COPY_FORM=flat: the plane-range form (tuning knob)
+    const char *form = std::getenv("OFL_COPY_FORM");
+    if (form && form[0] == 'f' && K >= 3 && (I - 2) <= 65535) return launch_copy_flat(p, q, I, J, K, nt, f, s);
     if (rows_per_wave == 2) return launch_copy<2>(p, q, I, J, K, bpc, nt, f, s);
     if (rows_per_wave == 8) return launch_copy<8>(p, q, I, J, K, bpc, nt, f, s);
     return launch_copy<4>(p, q, I, J, K, bpc, nt, f, s);

@@ -299,6 +299,19 @@ def test_stencil_kernel_forms(cfg, form, nt, monkeypatch):
         _run_and_compare(appgen.stencil_app(I, J, K, 2), [[1, 1]])
 
 
+@pytest.mark.parametrize("nt", ["0", "1"])
+def test_copy_interior_plane_range_form(nt, monkeypatch):
+    # the interior copy in its plane-range form (16-byte pieces of each
+    # plane's contiguous interior range, the row-boundary columns left alone):
+    # rows of every alignment, ranges shorter than one piece, one-row planes
+    monkeypatch.setenv("OFL_COPY_FORM", "flat")
+    monkeypatch.setenv("OFL_COPY_CFG", "2,32,%s" % nt)
+    for I, J, K in [(3, 3, 3), (4, 5, 6), (3, 4, 7), (19, 23, 71), (5, 130, 300), (10, 11, 129), (6, 9, 254),
+                    (7, 6, 128), (4, 20, 1025), (33, 33, 65), (5, 3, 1030)]:
+        say("case copy plane-range nt=%s grid %dx%dx%d" % (nt, I, J, K))
+        _run_and_compare(appgen.stencil_app(I, J, K, 2), [[1, 1], [0, 1]])
+
+
 def _two_sweep_app(I, J, K, S):
     # two sweeps back to back (the second reads the first one's output), then
     # the interior copy; a single sweep as the program's last nest
@@ -845,3 +858,32 @@ def test_output_check_flags_a_less_accurate_product():
     for gen_pop, gen_st in zip(res["pops"], res["status"]):
         for g, st_ in zip(gen_pop, gen_st):
             assert st_ == (ofl.ST_MISMATCH if g[0] == 1 else ofl.ST_OK), (list(g), st_)
+
+
+# ---------------------------------------------------------------- the sweep as a call
+@pytest.mark.parametrize("I,J,K", [(3, 3, 3), (5, 7, 9), (33, 33, 65), (19, 23, 71), (130, 40, 260)])
+def test_sweep19_call_matches_oracle(I, J, K):
+    import torch
+    say("case sweep19 call", I, J, K)
+    rng = np.random.default_rng(I * 1000 + K)
+    p0 = rng.random((I, J, K), dtype=np.float32)
+    q0 = rng.random((I, J, K), dtype=np.float32)
+    p = torch.from_numpy(p0).cuda()
+    q = torch.from_numpy(q0).cuda()
+    res = torch.zeros(3, dtype=torch.float64, device="cuda")
+    res[1] = 0.25
+    for _ in range(2):
+        ofl.sweep19(p, q, res, slot=1)
+    torch.cuda.synchronize()
+    want_q = q0.copy()
+    cell = np.array([0.25])
+    for _ in range(2):
+        OC.stencil19(p0, want_q, cell)
+    assert np.array_equal(q.cpu().numpy(), want_q)
+    assert np.array_equal(p.cpu().numpy(), p0)
+    got = res.cpu().numpy()
+    assert got[0] == 0.0 and got[2] == 0.0
+    n = max(1, (I - 2) * (J - 2) * (K - 2))
+    assert abs(got[1] - cell[0]) <= (1e-12 + 2 * n * 2.0 ** -52) * cell[0]
+    with pytest.raises(ofl.OflError):
+        ofl.sweep19(p, p, res)
