@@ -308,8 +308,22 @@ def run_batch(args):
            "grouped_ms": round(1e3 * timed(ofl.BATCH_GROUPED), 3),
            "graph_ms": round(1e3 * timed(ofl.BATCH_GROUPED_GRAPH), 3)}
     t0 = time.perf_counter()
-    b.tune(bufs, reps=3)
+    ents = b.tune(bufs, reps=3)
     out["tune_s"] = round(time.perf_counter() - t0, 3)
+    # rooflines of the grouped launches: the tuner's fastest candidate of each
+    # phase (median of 3 event-timed launches) against the work of all 256
+    # instances (2 N^3 flops per product; read p once, write q's interior
+    # once per sweep)
+    flops = sum(2.0 * pp["N"] ** 3 for pp in params)
+    sweep_b = sum(stencil_bytes(pp["I"], pp["J"], pp["K"]) for pp in params)
+    best = {ph: min(e["ms"] for e in ents if e["phase"] == ph) for ph in ("gemm", "stencil")}
+    tf = flops / (best["gemm"] * 1e-3) / 1e12
+    gbs = sweep_b / (best["stencil"] * 1e-3) / 1e9
+    out["roofline_grouped"] = {
+        "gemm": {"bound": "mfma", "achieved": round(tf, 1), "peak": MFMA_PEAK_TFLOPS["f32"], "unit": "TFLOP/s",
+                 "frac": round(tf / MFMA_PEAK_TFLOPS["f32"], 4), "ms": round(best["gemm"], 4), "flops": flops},
+        "sweep": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                  "frac": round(gbs / HBM_PEAK_GBS, 4), "ms": round(best["stencil"], 4), "bytes": sweep_b}}
     out["tuned_config"] = b.config
     b.setup(bufs)
     out["graph_tuned_ms"] = round(1e3 * timed(ofl.BATCH_GROUPED_GRAPH), 3)

@@ -89,23 +89,25 @@ enum {
     OFL_RUN_BATCHED = 8,     /* population evaluation (ofl_eval_population,
                                 ofl_ga_run, ofl_ga_run_table) only: all
                                 uncached genes of a population / generation are
-                                measured in ONE submission -- per repetition
-                                the reset and run graphs of every gene queued
-                                back to back with an event pair around each run
-                                graph, one synchronisation at the end; a gene's
-                                time is the median of its event intervals (GPU
-                                timeline, host nodes included).  Implies
-                                OFL_RUN_GRAPH.  A deadline applies to the
-                                measured times (a median over the limit gets
-                                OFL_ST_TIMEOUT at the limit) and to the host
+                                measured together, ONE submission per round of
+                                runs (each warm-up round, then each timed
+                                round) -- the reset and run graphs of every
+                                gene queued back to back with an event pair
+                                around each run graph, one synchronisation per
+                                round; a gene's time is the median of its
+                                timed event intervals (GPU timeline, host nodes
+                                included).  Implies OFL_RUN_GRAPH.  A deadline
+                                applies to every run's interval and to the host
                                 nests: each run's graph stamps its start, and a
                                 host nest still running at start + limit stops
                                 (checked between its rows or planes, as in an
-                                eager run), which also makes that gene
-                                OFL_ST_TIMEOUT and skips the host nests of its
-                                remaining runs; GPU work is not cut.  In the GA
-                                every gene of a generation gets the limit taken
-                                at the start of that generation. */
+                                eager run); a run over the limit or cut there
+                                makes the gene OFL_ST_TIMEOUT at the limit and
+                                leaves it out of the later rounds, as an eager
+                                measurement ends at its first run over the
+                                limit; GPU work is not cut.  In the GA every
+                                gene of a generation gets the limit taken at
+                                the start of that generation. */
     OFL_RUN_PROGRESS = 16    /* ofl_ga_run only: one line per generation on
                                 stderr (generation, best time so far, genes
                                 measured, wall time), for long searches */
@@ -416,8 +418,10 @@ enum {
 };
 
 typedef struct {
-    int32_t gemm_cfg;               /* tile shape index: 0..5 = (64,16) (64,32) (64,64)
-                                       (128,16) (128,32) (128,64) as (BM = BN, BK) */
+    int32_t gemm_cfg;               /* tile shape index: 0..7 = (64,16) (64,32) (64,64)
+                                       (128,16) (128,32) (128,64) (256,16) (256,32) as
+                                       (BM = BN, BK); (256,64) is not offered: its double-
+                                       buffered slabs need 272 KB of LDS (160 KB per CU) */
     int32_t gemm_blocks_per_cu;     /* persistent blocks per CU (1..8, <= occupancy) */
     int32_t stencil_rows;           /* rows per sweep item: 2, 4 or 8 */
     int32_t stencil_planes;         /* planes per sweep item (>= 1) */

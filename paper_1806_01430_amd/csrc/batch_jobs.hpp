@@ -49,7 +49,7 @@ struct CopyJob {
 };
 
 // FP32 tile shapes of the grouped product: index -> (BM = BN, BK).
-constexpr int kGemmCfgs = 6;
+constexpr int kGemmCfgs = 8;
 void gemm_cfg_shape(int cfg, int *bm, int *bk);
 
 Geo make_geo(int64_t I, int64_t J, int64_t K, int JR, int IC, int kout = kOut);

@@ -137,8 +137,8 @@ int occupancy_of(F kernel) {
     return n;
 }
 
-constexpr int kCfgBM[kGemmCfgs] = {64, 64, 64, 128, 128, 128};
-constexpr int kCfgBK[kGemmCfgs] = {16, 32, 64, 16, 32, 64};
+constexpr int kCfgBM[kGemmCfgs] = {64, 64, 64, 128, 128, 128, 256, 256};
+constexpr int kCfgBK[kGemmCfgs] = {16, 32, 64, 16, 32, 64, 16, 32};
 
 }  // namespace
 
@@ -158,6 +158,8 @@ int grouped_gemm_occupancy(int cfg) {
         table[3] = occupancy_of(k_gemm_grouped<128, 16>);
         table[4] = occupancy_of(k_gemm_grouped<128, 32>);
         table[5] = occupancy_of(k_gemm_grouped<128, 64>);
+        table[6] = occupancy_of(k_gemm_grouped<256, 16>);
+        table[7] = occupancy_of(k_gemm_grouped<256, 32>);
     });
     return table[(cfg < 0 || cfg >= kGemmCfgs) ? 1 : cfg];
 }
@@ -194,6 +196,8 @@ hipError_t gemm_grouped(int cfg, const GemmJob *jobs, int njobs, int ntiles, uns
     case 3: return launch((k_gemm_grouped<128, 16>), dim3(blocks), dim3(kThreads), 0, s, jobs, njobs, ntiles);
     case 4: return launch((k_gemm_grouped<128, 32>), dim3(blocks), dim3(kThreads), 0, s, jobs, njobs, ntiles);
     case 5: return launch((k_gemm_grouped<128, 64>), dim3(blocks), dim3(kThreads), 0, s, jobs, njobs, ntiles);
+    case 6: return launch((k_gemm_grouped<256, 16>), dim3(blocks), dim3(kThreads), 0, s, jobs, njobs, ntiles);
+    case 7: return launch((k_gemm_grouped<256, 32>), dim3(blocks), dim3(kThreads), 0, s, jobs, njobs, ntiles);
     default: return hipErrorInvalidValue;
     }
 }

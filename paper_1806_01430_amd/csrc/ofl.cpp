@@ -1074,10 +1074,12 @@ Measurement measure(ofl_app *app, const std::vector<uint8_t> &placement, void *c
     return m;
 }
 
-// All genes in one submission: per repetition, each gene's reset graph and
-// run graph back to back on the stream, an event pair around every run
-// graph; one synchronisation; per gene the median of its timed intervals.
-// limit > 0: a time over it becomes OFL_ST_TIMEOUT at the limit.
+// All genes together, one submission per round of runs (the warm-up
+// rounds, then the timed ones): each gene's reset graph and run graph back
+// to back on the stream, an event pair around every run graph, one
+// synchronisation per round; per gene the median of its timed intervals.
+// limit > 0: a run over it (or a host nest cut at it) makes the gene
+// OFL_ST_TIMEOUT at the limit and drops it from the later rounds.
 int measure_batched_all(ofl_app *app, const std::vector<std::vector<uint8_t>> &placements, void *const *dev,
                         hipStream_t s, int reps, int warmup, int policy, int flags, double limit,
                         std::vector<Measurement> &out) {
@@ -1090,8 +1092,7 @@ int measure_batched_all(ofl_app *app, const std::vector<std::vector<uint8_t>> &p
     std::vector<GraphEntry *> ge(n);
     for (size_t g = 0; g < n; ++g)
         if ((rc = get_graph(app, placements[g], dev, policy, flags, &ge[g])) != OFL_OK) return rc;
-    const size_t need = 2 * n * (size_t)reps;
-    while (app->chain_events.size() < need) {
+    while (app->chain_events.size() < 2 * n) {
         hipEvent_t e = nullptr;
         hipError_t he = hipEventCreate(&e);
         if (he != hipSuccess) return hip_fail(he, "hipEventCreate");
@@ -1103,40 +1104,56 @@ int measure_batched_all(ofl_app *app, const std::vector<std::vector<uint8_t>> &p
         ge[g]->clock->limit_s = limit > 0 ? limit : 0.0;
         ge[g]->clock->cut = false;
     }
+    // one submission per round (the warm-up runs, then each timed run): the
+    // reset and run graphs of every gene still measured, back to back, an
+    // event pair around each run graph.  A gene whose run went over the
+    // limit, or whose host nests were cut, is a TIMEOUT and leaves the later
+    // rounds (as an eager measurement stops at its first run over the limit)
+    std::vector<char> dead(n, 0), ran(n, 0);
+    std::vector<std::vector<double>> ts(n);
+    std::vector<size_t> last_round;
     hipError_t e = hipSuccess;
-    for (int r = 0; r < warmup + reps && e == hipSuccess; ++r)
-        for (size_t g = 0; g < n && e == hipSuccess; ++g) {
-            const bool timed = r >= warmup;
-            const size_t ev = 2 * ((size_t)(r - warmup) * n + g);
+    for (int r = 0; r < warmup + reps && e == hipSuccess; ++r) {
+        std::vector<size_t> round;
+        for (size_t g = 0; g < n; ++g)
+            if (!dead[g]) round.push_back(g);
+        if (round.empty()) break;
+        for (size_t k = 0; k < round.size() && e == hipSuccess; ++k) {
+            const size_t g = round[k];
             e = hipGraphLaunch(ge[g]->reset, s);
-            if (e == hipSuccess && timed) e = hipEventRecord(app->chain_events[ev], s);
+            if (e == hipSuccess) e = hipEventRecord(app->chain_events[2 * k], s);
             if (e == hipSuccess) e = hipGraphLaunch(ge[g]->run, s);
-            if (e == hipSuccess && timed) e = hipEventRecord(app->chain_events[ev + 1], s);
+            if (e == hipSuccess) e = hipEventRecord(app->chain_events[2 * k + 1], s);
         }
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
-    std::vector<char> cut(n);
-    for (size_t g = 0; g < n; ++g) {
-        cut[g] = ge[g]->clock->cut ? 1 : 0;
-        ge[g]->clock->limit_s = 0.0;   // later graph runs are not limited
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) break;
+        for (size_t k = 0; k < round.size(); ++k) {
+            const size_t g = round[k];
+            ran[g] = 1;
+            float ms = 0.f;
+            e = hipEventElapsedTime(&ms, app->chain_events[2 * k], app->chain_events[2 * k + 1]);
+            if (e != hipSuccess) break;
+            const double t = 1e-3 * ms;
+            if (r >= warmup) ts[g].push_back(t);
+            if (limit > 0 && (t > limit || ge[g]->clock->cut)) dead[g] = 1;
+        }
+        last_round = round;
     }
+    for (size_t g = 0; g < n; ++g) ge[g]->clock->limit_s = 0.0;   // later graph runs are not limited
     if (e != hipSuccess) return hip_fail(e, "batched evaluation");
     for (size_t g = 0; g < n; ++g) {
-        std::vector<double> ts;
-        for (int r = 0; r < reps; ++r) {
-            const size_t ev = 2 * ((size_t)r * n + g);
-            float ms = 0.f;
-            e = hipEventElapsedTime(&ms, app->chain_events[ev], app->chain_events[ev + 1]);
-            if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
-            ts.push_back(1e-3 * ms);
+        if (dead[g]) {
+            out[g] = Measurement{limit, OFL_ST_TIMEOUT};
+            continue;
         }
-        Measurement m{median_of(ts), OFL_ST_OK};
-        if (limit > 0 && (m.t > limit || cut[g])) {   // over the limit, or host work cut short
-            m.t = limit;
-            m.status = OFL_ST_TIMEOUT;
-        }
-        out[g] = m;
-        note_graph_run(app, *ge[g], dev, s);
+        out[g] = Measurement{median_of(ts[g]), OFL_ST_OK};
     }
+    // host / device state: every gene that ran, those of the last round last
+    // and in order, so the state is that of the last run
+    for (size_t g = 0; g < n; ++g)
+        if (ran[g] && std::find(last_round.begin(), last_round.end(), g) == last_round.end())
+            note_graph_run(app, *ge[g], dev, s);
+    for (size_t g : last_round) note_graph_run(app, *ge[g], dev, s);
     return OFL_OK;
 }
 

@@ -78,7 +78,9 @@ def test_batch_small_matches_oracle(mode):
                                  dict(gemm_cfg=2, gemm_blocks_per_cu=1, stencil_rows=8, stencil_planes=5),
                                  dict(gemm_cfg=3, stencil_rows=4, stencil_planes=32, stencil_blocks_per_cu=1),
                                  dict(gemm_cfg=4, gemm_blocks_per_cu=8, stencil_rows=8, stencil_planes=1),
-                                 dict(gemm_cfg=5, gemm_blocks_per_cu=1, stencil_rows=2, stencil_planes=16)])
+                                 dict(gemm_cfg=5, gemm_blocks_per_cu=1, stencil_rows=2, stencil_planes=16),
+                                 dict(gemm_cfg=6, gemm_blocks_per_cu=1, stencil_rows=4, stencil_planes=8),
+                                 dict(gemm_cfg=7, gemm_blocks_per_cu=1, stencil_rows=4, stencil_planes=8)])
 def test_batch_configs_match_oracle(cfg):
     params, seeds = _small_batch()
     b = ofl.Batch(workloads.app_doc("batch"), params, seeds)

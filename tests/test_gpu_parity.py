@@ -461,8 +461,9 @@ def test_fft_rows_shapes(R, n):
         outs[g] = app.read_buffer("X").copy()
         err = np.max(np.linalg.norm(outs[g] - ref, axis=1) / np.maximum(np.linalg.norm(ref, axis=1), 1e-300))
         assert err <= parity.rel_fft(n) + 2.0 ** -23, (g, err)
-    say("fft", R, n, "GPU and CPU forms identical bits:", bool(np.array_equal(outs[0].view(np.uint32),
-                                                                           outs[1].view(np.uint32))))
+    # beyond the bound: the GPU kernel and the CPU form run the same
+    # butterflies on the same twiddle values, so they give the same bits
+    assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32)), (R, n)
 
 
 def test_fft_rows_full_size_sampled():

@@ -340,11 +340,11 @@ def test_batch_errors():
 def test_batch_config_roundtrip_and_range():
     b = ofl.Batch(_batch_doc(), [{"N": 40}, {"N": 50}], [1, 2])
     c = b.config
-    assert c["stencil_rows"] in (2, 4, 8) and 0 <= c["gemm_cfg"] < 6
+    assert c["stencil_rows"] in (2, 4, 8) and 0 <= c["gemm_cfg"] < 8
     b.set_config(gemm_cfg=5, gemm_blocks_per_cu=1, stencil_rows=8, stencil_planes=16, stencil_blocks_per_cu=4)
     assert b.config == {"gemm_cfg": 5, "gemm_blocks_per_cu": 1, "stencil_rows": 8, "stencil_planes": 16,
                         "stencil_blocks_per_cu": 4}
-    for bad in [dict(gemm_cfg=6), dict(gemm_blocks_per_cu=0), dict(stencil_rows=3), dict(stencil_blocks_per_cu=9),
+    for bad in [dict(gemm_cfg=8), dict(gemm_blocks_per_cu=0), dict(stencil_rows=3), dict(stencil_blocks_per_cu=9),
                 dict(stencil_planes=-1)]:
         with pytest.raises(ofl.OflError) as e:
             b.set_config(**bad)
