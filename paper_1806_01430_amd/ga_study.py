@@ -13,6 +13,17 @@ many distinct genes it measures, and the search time those measurements
 would have taken (each measured gene costs warmup + reps runs; with a
 deadline, a gene cut off at the limit costs the limit once).  Prints one JSON
 line and a markdown table.
+
+Large applications (``--cap S --prune``): every run is cut at S seconds (the
+timeout of the paper's trials, Sec. 5.2) and the landscape is measured only
+where it can hold a time under S.  First, for each gene bit i, the gene with
+every parallelisable nest on the GPU except nest i is measured with the cap
+4 S: if it still runs out, nest i's CPU form alone takes more than 4 S minus
+the rest of that run (a few tenths of a second at most here), so every gene
+that keeps nest i on the CPU runs past S and is recorded as a TIMEOUT at S
+without being run.  The other genes are measured with the cap S.
+
+    python -m paper_1806_01430_amd.ga_study --app large --cap 0.5 --prune --seeds 200
 """
 import argparse
 import json
@@ -39,7 +50,7 @@ SETTINGS = [
 ]
 
 
-def study(a, times, status, settings, seeds, runs_per_gene):
+def study(a, times, status, settings, seeds, runs_per_gene, timeout=0.0):
     """GA outcome statistics over a measured table of 2^a times / statuses."""
     times = np.asarray(times, np.float64)
     status = np.asarray(status, np.int32)
@@ -52,7 +63,8 @@ def study(a, times, status, settings, seeds, runs_per_gene):
     for (M, T, Pc, Pm, p, dl) in settings:
         hits, ranks, measured, cost = 0, [], [], []
         for s in range(1, seeds + 1):
-            r = ga_run_table(a, ga_params(M=M, T=T, Pc=Pc, Pm=Pm, p=p, seed=s, deadline_factor=dl), times, status)
+            r = ga_run_table(a, ga_params(M=M, T=T, Pc=Pc, Pm=Pm, p=p, seed=s, deadline_factor=dl,
+                                          timeout_s=timeout), times, status)
             g = sum(int(b) << i for i, b in enumerate(r["best_gene"]))
             hits += int(g == best)
             ranks.append(int(rank_of[g]))
@@ -60,8 +72,11 @@ def study(a, times, status, settings, seeds, runs_per_gene):
             # search time: every distinct measured gene once, at what its
             # measurement cost (a run cut off at the limit ends the gene)
             seen = {}
-            if dl > 0:   # the all-zero baseline, measured first and without a limit
-                seen[0] = (float(times[0]), int(status[0]))
+            if dl > 0:   # the all-zero baseline, measured first (limited by the timeout only)
+                t0_, s0_ = float(times[0]), int(status[0])
+                if timeout > 0 and s0_ == 0 and t0_ > timeout:
+                    t0_, s0_ = timeout, 1
+                seen[0] = (t0_, s0_)
             for gen in range(r["n_generations"]):
                 for gene, t, st in zip(r["pops"][gen], r["times"][gen], r["status"][gen]):
                     key = sum(int(b) << i for i, b in enumerate(gene))
@@ -101,6 +116,11 @@ def main(argv=None):
     ap.add_argument("--policy", choices=["resident", "per_region", "sections"], default="sections")
     ap.add_argument("--seeds", type=int, default=200)
     ap.add_argument("--chunk", type=int, default=64, help="genes per batched submission while measuring")
+    ap.add_argument("--cap", type=float, default=0.0, help="seconds; cut off every run at this time (0 = none)")
+    ap.add_argument("--prune", action="store_true",
+                    help="with --cap: record genes that keep a nest too slow for the cap on the CPU as "
+                         "timeouts without running them")
+    ap.add_argument("--out", default=None, help="also write the measured table (JSON) here")
     args = ap.parse_args(argv)
 
     import torch
@@ -114,19 +134,40 @@ def main(argv=None):
     a = app.gene_len
     genes = [[(idx >> i) & 1 for i in range(a)] for idx in range(1 << a)]
     t0 = time.perf_counter()
-    times = np.zeros(1 << a)
-    status = np.zeros(1 << a, np.int32)
-    for c0 in range(0, 1 << a, args.chunk):
-        t, s = app.eval_population(genes[c0:c0 + args.chunk], bufs, reps=args.reps, warmup=args.warmup,
-                                   policy=policy, flags=BATCHED)
-        times[c0:c0 + len(t)] = t
-        status[c0:c0 + len(t)] = s
-        print("measured %d / %d genes, %.1f s" % (min(c0 + args.chunk, 1 << a), 1 << a, time.perf_counter() - t0),
+    times = np.full(1 << a, args.cap)
+    status = np.ones(1 << a, np.int32)   # TIMEOUT until measured
+    heavy = []
+    if args.prune:
+        if not args.cap > 0:
+            print("--prune needs --cap", file=sys.stderr)
+            return 2
+        probes = [[0 if k == i else 1 for k in range(a)] for i in range(a)]
+        t, s = app.eval_population(probes, bufs, reps=1, warmup=0, policy=policy, flags=BATCHED,
+                                   deadline_s=4 * args.cap)
+        heavy = [i for i in range(a) if s[i] == 1]
+        print("nests too slow on the CPU for the cap (gene bits): %s, %.1f s" % (heavy, time.perf_counter() - t0),
               file=sys.stderr, flush=True)
-    res = study(a, times, status, SETTINGS, args.seeds, args.reps + args.warmup)
+    todo = [idx for idx in range(1 << a) if all((idx >> i) & 1 for i in heavy)]
+    for c0 in range(0, len(todo), args.chunk):
+        part = todo[c0:c0 + args.chunk]
+        t, s = app.eval_population([genes[i] for i in part], bufs, reps=args.reps, warmup=args.warmup,
+                                   policy=policy, flags=BATCHED, deadline_s=args.cap)
+        times[part] = t
+        status[part] = s
+        print("measured %d / %d genes, %.1f s" % (min(c0 + args.chunk, len(todo)), len(todo),
+                                                  time.perf_counter() - t0), file=sys.stderr, flush=True)
+    res = study(a, times, status, SETTINGS, args.seeds, args.reps + args.warmup, timeout=args.cap)
+    res["cap_s"] = args.cap
+    res["heavy_bits"] = heavy
+    res["genes_measured"] = len(todo) + (a if args.prune else 0)
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump({"gene_len": a, "times": times.tolist(), "status": status.tolist(), "cap_s": args.cap,
+                       "heavy_bits": heavy}, f)
     res.update({"app": args.app, "params": src["params"], "gene_len": a, "reps": args.reps,
                 "warmup": args.warmup, "policy": args.policy, "measure_wall_s": time.perf_counter() - t0,
-                "times_quantiles_s": [float(np.quantile(times, q)) for q in (0.0, 0.25, 0.5, 0.75, 1.0)]})
+                "times_quantiles_s": [float(np.quantile(times, q)) for q in (0.0, 0.25, 0.5, 0.75, 1.0)],
+                "n_ok": int(np.sum(status == 0))})
     print(json.dumps(res), flush=True)
     print(table(res), flush=True)
     return 0

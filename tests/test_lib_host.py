@@ -388,6 +388,19 @@ def test_ga_study_statistics_on_a_table():
         assert got["mean_measured"] == float(np.mean(measured))
         assert abs(got["mean_search_s"] - float(np.mean(cost))) < 1e-9
     assert "| 16 | 8 |" in ga_study.table(res)
+    # every run cut at a timeout (the large application's study): the GA and
+    # the cost of its measurements as the oracle GA gives them
+    tmo = float(np.median(table))
+    res = ga_study.study(a, table, status, settings, seeds, runs, timeout=tmo)
+    for (M, T, Pc, Pm, p, dl), got in zip(settings, res["settings"]):
+        measured, cost = [], []
+        for seed in range(1, seeds + 1):
+            o = G.run_ga(a, M, T, G.table_evaluator(table), Pc=Pc, Pm=Pm, p=p, seed=seed, deadline_factor=dl,
+                         timeout=tmo)
+            measured.append(o["n_measured"])
+            cost.append(sum(t if st == G.ST_TIMEOUT else runs * t for _, t, st in o["log"]))
+        assert got["mean_measured"] == float(np.mean(measured))
+        assert abs(got["mean_search_s"] - float(np.mean(cost))) < 1e-9
 
 
 @pytest.mark.parametrize("R,n,ok", [(4, 1, True), (4, 4096, True), (3, 3, False), (2, 8192, False), (2, 12, False)])
