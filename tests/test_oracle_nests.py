@@ -291,3 +291,31 @@ def test_copy_interior():
     assert np.array_equal(p[inner], q[inner])
     p[inner] = p0[inner]
     assert np.array_equal(p, p0)
+
+
+def test_large_grid_golden_against_closed_form():
+    # the stored oracle run of the large grid (make_large_grid.py) pinned to
+    # the sine-mode closed form r_n = (mu - 1)^2 mu^(2n-2) (I-1)(J-1)(K-1) / 8:
+    # the FP32 field perturbs each difference q - p by about u |p| (u = 2^-24)
+    # against (mu - 1) |p|, with signs that do not correlate, so r_n moves by
+    # about (u / |mu - 1|)^2 = 1.4e-5 relative; 1e-4 allows 7x that, while a
+    # wrong weight or a dropped neighbour changes mu - 1, and with it r_n, by
+    # far more (a dropped edge term alone: by a factor of about 2)
+    I, J, K, S = 513, 513, 1025, 50
+    c = [math.cos(math.pi / (n - 1)) for n in (I, J, K)]
+    mu = 0.25 + sum(c) / 8 + (c[0] * c[1] + c[1] * c[2] + c[2] * c[0]) / 8
+    res = {}
+    n_probes = 0
+    for line in read_golden("large_grid_513x513x1025_S50.txt"):
+        f = line.split()
+        if f[0] == "res":
+            res[int(f[1])] = float(f[2])
+        elif f[0] == "probe":
+            i, j, k = int(f[1]), int(f[2]), int(f[3])
+            assert 0 <= i < I and 0 <= j < J and 0 <= k < K
+            n_probes += 1
+    assert sorted(res) == list(range(1, S + 1)) and n_probes == 4096
+    base = (I - 1) * (J - 1) * (K - 1) / 8.0
+    for n, r in res.items():
+        cf = (mu - 1) ** 2 * mu ** (2 * n - 2) * base
+        assert abs(r - cf) <= 1e-4 * cf, (n, r, cf)
