@@ -281,16 +281,19 @@ def test_stencil_shapes(I, J, K, S):
 # ragged shapes: k-tiles with a partial last tile, j-runs past the last row,
 # i-runs shorter than the item; the band form (a block per band of rows
 # across the whole row, planes staged in LDS) with every row length it takes,
-# whole and partial bands, and its automatic plane runs (IC = 0)
+# whole and partial bands, and its automatic plane runs (IC = 0); the band
+# form with its planes loaded straight into LDS (d), runs of 1 to 32 planes
 @pytest.mark.parametrize("cfg,form,nt", [("2,1", "1", "0"), ("4,3", "1", "1"), ("8,5", "1", "0"), ("2,2", "w", "1"),
                                          ("4,6", "w", "0"), ("8,4", "w", "1"), ("8,16", "w", "0"),
-                                         ("8,2", "b", "0"), ("8,7", "b", "1"), ("8,32", "b", "0"), ("8,0", "b", "0")])
+                                         ("8,2", "b", "0"), ("8,7", "b", "1"), ("8,32", "b", "0"), ("8,0", "b", "0"),
+                                         ("8,1", "d", "0"), ("8,2", "d", "1"), ("8,4", "d", "0"), ("8,7", "d", "1"),
+                                         ("8,32", "d", "0"), ("8,0", "d", "0")])
 def test_stencil_kernel_forms(cfg, form, nt, monkeypatch):
     monkeypatch.setenv("OFL_STENCIL_CFG", cfg)
     monkeypatch.setenv("OFL_STENCIL_FORM", form)
     monkeypatch.setenv("OFL_STENCIL_NT", nt)
     shapes = [(4, 5, 6), (19, 23, 71), (5, 130, 300), (10, 11, 129), (6, 9, 254), (7, 6, 128)]
-    if form == "b":   # band form: 1, 2, 4 and 8 waves across a row, whole and partial bands;
+    if form in ("b", "d"):   # band form: 1, 2, 4 and 8 waves across a row, whole and partial bands;
         # rows longer than 8 tiles fall back to the two-columns form
         shapes += [(9, 26, 258), (6, 70, 131), (5, 40, 520), (4, 20, 1025), (9, 150, 130), (12, 66, 514),
                    (5, 9, 1100)]
@@ -372,8 +375,11 @@ def test_stencil_eigenmode_decay():
     assert err < 100 * 2.0 ** -24
 
 
-@pytest.mark.parametrize("I,J,K", [(257, 257, 513), (513, 513, 1025)])
-def test_stencil_full_size_one_sweep(I, J, K):
+@pytest.mark.parametrize("I,J,K,form", [(257, 257, 513, None), (513, 513, 1025, None), (257, 257, 513, "d"),
+                                         (513, 513, 1025, "d")])
+def test_stencil_full_size_one_sweep(I, J, K, form, monkeypatch):
+    if form:
+        monkeypatch.setenv("OFL_STENCIL_FORM", form)
     _run_and_compare(appgen.stencil_app(I, J, K, 1), [[1, 1]], flags_list=(ofl.PRESTAGED | ofl.KEEP_OUTPUTS,))
 
 
@@ -841,7 +847,8 @@ def test_output_check_against_the_all_cpu_run():
 def test_output_check_flags_a_less_accurate_product():
     # the FP8x2 product differs from the FP32 loop run on the CPU by ~1e-4 of
     # its scale: within a tolerance of 1e-3, beyond one of 1e-6 (a MISMATCH,
-    # fitness 0); the all-CPU pattern always agrees with itself
+    # fitness 0); the all-CPU pattern always agrees with itself, and so does
+    # every pattern that keeps the product (gene bit 1) on the CPU
     doc = workloads.app_doc("precision", N=160, I=13, J=17, K=67, SWEEPS=3)
     doc["program"][1]["args"]["prec"] = "fp8x2"
     app = ofl.App(json.dumps(doc))
@@ -852,13 +859,13 @@ def test_output_check_flags_a_less_accurate_product():
     assert st["rc"] == -11 and st["status"] == ofl.ST_MISMATCH
     assert "differs from the all-CPU run" in ofl.last_error()
     assert app.run_pattern([0] * 4, bufs, verify_rtol=1e-12)["status"] == ofl.ST_OK
-    assert app.run_pattern([0, 1, 1, 1], bufs, verify_rtol=1e-9)["status"] == ofl.ST_OK
-    t, s = app.eval_population([[1] * 4, [0] * 4, [0, 1, 1, 1]], bufs, reps=1, warmup=0, verify_rtol=1e-6)
+    assert app.run_pattern([1, 0, 1, 1], bufs, verify_rtol=1e-9)["status"] == ofl.ST_OK
+    t, s = app.eval_population([[1] * 4, [0] * 4, [1, 0, 1, 1]], bufs, reps=1, warmup=0, verify_rtol=1e-6)
     assert list(s) == [ofl.ST_MISMATCH, ofl.ST_OK, ofl.ST_OK]
     res = app.ga_run(ofl.ga_params(M=4, T=2, seed=5, reps=1, warmup=0, verify_rtol=1e-6), bufs)
     for gen_pop, gen_st in zip(res["pops"], res["status"]):
         for g, st_ in zip(gen_pop, gen_st):
-            assert st_ == (ofl.ST_MISMATCH if g[0] == 1 else ofl.ST_OK), (list(g), st_)
+            assert st_ == (ofl.ST_MISMATCH if g[1] == 1 else ofl.ST_OK), (list(g), st_)
 
 
 # ---------------------------------------------------------------- the sweep as a call
