@@ -93,9 +93,22 @@ __global__ __launch_bounds__(kThreads) void k_stencil19w(const float *__restrict
 // of stencil_item, in the same order.  One barrier per plane: a plane's staging
 // buffer (two buffers, alternating) is written only after every wave has
 // passed the barrier of the step after the one that last read it.
+//
+// DMA variant (DMA = true): the plane loads go straight from memory into LDS
+// (buffer loads with the LDS bit: each lane's 16 bytes land at the wave's LDS
+// base + 16 lane), three staging buffers, and planes i+2 and i+3 in flight
+// while plane i is produced -- a lead of two steps at no register cost.  A
+// wave waits for its own loads of the plane it derives next by counting its
+// outstanding memory operations (s_waitcnt vmcnt: loads and stores of a wave
+// complete in order of issue for this count), then the block barrier makes
+// every wave's loads of that plane visible.
 constexpr int kBandThreads = 1024;
 constexpr int kBandChunks = 3;                               // 16-byte pieces per thread per plane
 constexpr int kBandCap = kBandChunks * kBandThreads * 4;     // floats per staging buffer
+
+// s_waitcnt immediate (gfx9 encoding) that waits until at most n vector
+// memory operations of the wave are outstanding, and nothing else
+constexpr int vmcnt_imm(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
 
 struct GeoB {
     int I, J, K;
@@ -108,12 +121,13 @@ struct GeoB {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-template <int NKT, int SP>
+template <int NKT, int SP, bool DMA>
 __global__ __launch_bounds__(kBandThreads) void k_stencil19b(const float *__restrict__ p, float *__restrict__ q, GeoB g,
                                                              double *partials) {
     constexpr int RG = 16 / NKT;
     static_assert(RG * NKT == 16, "16 waves per block");
-    __shared__ __attribute__((aligned(16))) float lds[2][kBandCap];
+    constexpr int NBUF = DMA ? 3 : 2;
+    __shared__ __attribute__((aligned(16))) float lds[NBUF][kBandCap];
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);
@@ -158,6 +172,28 @@ __global__ __launch_bounds__(kBandThreads) void k_stencil19b(const float *__rest
 #pragma unroll
             for (int u = 0; u < kBandChunks; ++u) *(f32x4 *)(buf + 4 * (u * kBandThreads + tid)) = v[u];
         };
+        // DMA form: plane i's staged range straight into buf (kBandChunks
+        // memory operations per wave, issued whether or not they are masked)
+        auto issue_lds = [&](int i, float *buf) {
+            const int ii = min(i, I - 1);
+            const int f0 = (ii * J + jb - 1) * K, f1 = (ii * J + rend) * K;
+            const int a0 = f0 & ~3;
+#pragma unroll
+            for (int u = 0; u < kBandChunks; ++u) {
+                const int e = a0 + 4 * (u * kBandThreads + tid);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rp, (__attribute__((address_space(3))) void *)(buf + 4 * (u * kBandThreads + wv * kWave)), 16,
+                    (i <= ie && e < f1) ? e * 4 : kOutOfRange, 0, 0, 0);
+            }
+            asm volatile("" ::: "memory");
+        };
+        // wait until this wave has at most N memory operations outstanding,
+        // then the block barrier (after the wave's LDS reads have completed)
+        auto wait_barrier = [&](auto NC) {
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_s_waitcnt(vmcnt_imm(decltype(NC)::value));
+            asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory");
+        };
         // a, x, y of this wave's 4 rows of plane i from the staged plane
         auto derive = [&](const float *buf, int i, f32x2 (&a)[4], f32x2 (&x)[4], f32x2 (&y)[4]) {
             const int sh = ((min(i, I - 1) * J + jb - 1) * K) & 3;   // staged range starts sh floats early
@@ -193,15 +229,27 @@ __global__ __launch_bounds__(kBandThreads) void k_stencil19b(const float *__rest
         };
         // step k of the run (output plane i = ib + k): stage plane i+1 (its
         // loads went out one step earlier), load plane i+2, derive plane i+1,
-        // produce plane i
-        auto step = [&](auto S, auto FULLC, int i) {
+        // produce plane i.  DMA form: wait for plane i+1 (loaded two steps
+        // earlier), load plane i+3 into the buffer plane i left, derive plane
+        // i+1, produce plane i; WAIT is the wave's memory operations issued
+        // after plane i+1's loads (2 S + 3 from the third step on, S stores
+        // per step).
+        auto step = [&](auto S, auto FULLC, int i, auto WAIT) {
             constexpr bool FULL = decltype(FULLC)::value;
             constexpr int k3 = decltype(S)::value;
             constexpr int m = k3, c = (k3 + 1) % 3, n = (k3 + 2) % 3;
-            float *buf = lds[(i + 1 - ib) & 1];             // plane t is staged in buffer (t - ib) mod 2
-            stage(st, buf);
-            __syncthreads();
-            issue(i + 2, st);
+            float *buf;
+            if constexpr (DMA) {
+                // plane t is staged in buffer (t - ib + 1) mod 3
+                buf = lds[(k3 + 2) % 3];
+                wait_barrier(WAIT);
+                issue_lds(i + 3, lds[(k3 + 1) % 3]);
+            } else {
+                buf = lds[(i + 1 - ib) & 1];               // plane t is staged in buffer (t - ib) mod 2
+                stage(st, buf);
+                __syncthreads();
+                issue(i + 2, st);
+            }
             derive(buf, i + 1, Pa[n], Px[n], Py[n]);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -229,22 +277,54 @@ __global__ __launch_bounds__(kBandThreads) void k_stencil19b(const float *__rest
 
         // every wave passes the same barriers whichever store path it takes
         auto run = [&](auto FULLC) {
-            // the previous item's last reads of the staging buffers are done
-            __syncthreads();
-            issue(ib - 1, st);
-            stage(st, lds[1]);
-            issue(ib, st);
-            __syncthreads();
-            derive(lds[1], ib - 1, Pa[0], Px[0], Py[0]);
-            stage(st, lds[0]);
-            issue(ib + 1, st);
-            __syncthreads();
-            derive(lds[0], ib, Pa[1], Px[1], Py[1]);
-            for (int i0 = ib; i0 < ie; i0 += 3) {
-                step(std::integral_constant<int, 0>(), FULLC, i0);
-                if (i0 + 1 < ie) {
-                    step(std::integral_constant<int, 1>(), FULLC, i0 + 1);
-                    if (i0 + 2 < ie) step(std::integral_constant<int, 2>(), FULLC, i0 + 2);
+            constexpr int SPS = decltype(FULLC)::value ? 4 : 8;   // stores per step and wave
+            using W0 = std::integral_constant<int, 0>;
+            if constexpr (DMA) {
+                // the previous item's last reads of the staging buffers are
+                // done, and all of its loads (masked ones write zeros) landed
+                wait_barrier(W0());
+                issue_lds(ib - 1, lds[0]);
+                issue_lds(ib, lds[1]);
+                issue_lds(ib + 1, lds[2]);
+                wait_barrier(std::integral_constant<int, 2 * kBandChunks>());
+                derive(lds[0], ib - 1, Pa[0], Px[0], Py[0]);
+                wait_barrier(std::integral_constant<int, kBandChunks>());
+                issue_lds(ib + 2, lds[0]);
+                derive(lds[1], ib, Pa[1], Px[1], Py[1]);
+                using WA = std::integral_constant<int, kBandChunks>;
+                using WB = std::integral_constant<int, SPS + kBandChunks>;
+                using WC = std::integral_constant<int, 2 * SPS + kBandChunks>;
+                // the first two steps have fewer operations behind their plane
+                step(std::integral_constant<int, 0>(), FULLC, ib, WA());
+                if (ib + 1 < ie) {
+                    step(std::integral_constant<int, 1>(), FULLC, ib + 1, WB());
+                    if (ib + 2 < ie) step(std::integral_constant<int, 2>(), FULLC, ib + 2, WC());
+                }
+                for (int i0 = ib + 3; i0 < ie; i0 += 3) {
+                    step(std::integral_constant<int, 0>(), FULLC, i0, WC());
+                    if (i0 + 1 < ie) {
+                        step(std::integral_constant<int, 1>(), FULLC, i0 + 1, WC());
+                        if (i0 + 2 < ie) step(std::integral_constant<int, 2>(), FULLC, i0 + 2, WC());
+                    }
+                }
+            } else {
+                // the previous item's last reads of the staging buffers are done
+                __syncthreads();
+                issue(ib - 1, st);
+                stage(st, lds[1]);
+                issue(ib, st);
+                __syncthreads();
+                derive(lds[1], ib - 1, Pa[0], Px[0], Py[0]);
+                stage(st, lds[0]);
+                issue(ib + 1, st);
+                __syncthreads();
+                derive(lds[0], ib, Pa[1], Px[1], Py[1]);
+                for (int i0 = ib; i0 < ie; i0 += 3) {
+                    step(std::integral_constant<int, 0>(), FULLC, i0, W0());
+                    if (i0 + 1 < ie) {
+                        step(std::integral_constant<int, 1>(), FULLC, i0 + 1, W0());
+                        if (i0 + 2 < ie) step(std::integral_constant<int, 2>(), FULLC, i0 + 2, W0());
+                    }
                 }
             }
         };
@@ -253,6 +333,8 @@ __global__ __launch_bounds__(kBandThreads) void k_stencil19b(const float *__rest
         else
             run(std::false_type());
     }
+    // DMA form: no load into this block's LDS may still be in flight when it ends
+    if constexpr (DMA) __builtin_amdgcn_s_waitcnt(vmcnt_imm(0));
     acc = wave_sum(acc);
     if (lane == 0) partials[lb * (kBandThreads / kWave) + wv] = acc;
 }
@@ -361,6 +443,7 @@ struct Config {
     Geo g;
     GeoB gb;                 // band form
     int nkt = 0;             // band form: waves across a row (1, 2, 4, 8)
+    bool dma = false;        // band form: planes loaded straight into LDS
     unsigned blocks;
     int waves_per_block = kWavesPerBlock;
 };
@@ -390,7 +473,7 @@ GeoB make_geo_band(int64_t I, int64_t J, int64_t K, int nkt, int IC) {
 }
 
 int resident_blocks_per_cu(int JR, int form);
-int band_blocks_per_cu(int nkt);
+int band_blocks_per_cu(int nkt, bool dma);
 
 bool valid_jr(int JR) { return JR == 2 || JR == 4 || JR == 8; }
 
@@ -441,13 +524,15 @@ Config choose(int64_t I, int64_t J, int64_t K) {
     c.store_nt = grid_bytes >= ((int64_t)4 << 20) && grid_bytes <= ((int64_t)512 << 20);
     if (const char *nt = std::getenv("OFL_STENCIL_NT")) c.store_nt = nt[0] == '1';
     if (const char *wd = std::getenv("OFL_STENCIL_WIDE")) c.form = wd[0] == '1' ? kFormWide : kFormOne;
-    if (const char *fm = std::getenv("OFL_STENCIL_FORM"))
-        c.form = fm[0] == 'b' ? kFormBand : fm[0] == 'w' ? kFormWide : kFormOne;
+    if (const char *fm = std::getenv("OFL_STENCIL_FORM")) {
+        c.form = fm[0] == 'b' || fm[0] == 'd' ? kFormBand : fm[0] == 'w' ? kFormWide : kFormOne;
+        c.dma = fm[0] == 'd';
+    }
     if (c.form == kFormBand) {
         c.nkt = band_nkt(K);
         if (c.nkt > 0) {
             c.JR = JR;
-            const int64_t slots = (int64_t)cu_count() * band_blocks_per_cu(c.nkt);
+            const int64_t slots = (int64_t)cu_count() * band_blocks_per_cu(c.nkt, c.dma);
             if (ic_asked <= 0) {
                 // about one item per resident block: the fewest halo planes
                 const int64_t nbands = (J - 2 + 64 / c.nkt - 1) / (64 / c.nkt);
@@ -475,10 +560,13 @@ Config choose(int64_t I, int64_t J, int64_t K) {
 
 hipError_t launch_band(const Config &c, const float *p, float *q, double *partials, hipStream_t s) {
     const dim3 grid(c.blocks), block(kBandThreads);
-#define OFL_BAND(N)                                                                                         \
-    case N:                                                                                                 \
-        return c.store_nt ? launch((k_stencil19b<N, kNonTemporal>), grid, block, 0, s, p, q, c.gb, partials) \
-                          : launch((k_stencil19b<N, 0>), grid, block, 0, s, p, q, c.gb, partials);
+#define OFL_BAND(N)                                                                                               \
+    case N:                                                                                                       \
+        if (c.dma)                                                                                                \
+            return c.store_nt ? launch((k_stencil19b<N, kNonTemporal, true>), grid, block, 0, s, p, q, c.gb, partials) \
+                              : launch((k_stencil19b<N, 0, true>), grid, block, 0, s, p, q, c.gb, partials);          \
+        return c.store_nt ? launch((k_stencil19b<N, kNonTemporal, false>), grid, block, 0, s, p, q, c.gb, partials)    \
+                          : launch((k_stencil19b<N, 0, false>), grid, block, 0, s, p, q, c.gb, partials);
     switch (c.nkt) {
         OFL_BAND(1)
         OFL_BAND(2)
@@ -522,21 +610,25 @@ int resident_blocks_per_cu(int JR, int form) {
     return table[form == kFormWide ? 1 : 0][JR == 2 ? 0 : JR == 4 ? 1 : 2];
 }
 
-int band_blocks_per_cu(int nkt) {
+int band_blocks_per_cu(int nkt, bool dma) {
     static std::once_flag once;
-    static int table[4];
+    static int table[2][4];
     std::call_once(once, [] {
         auto occ = [](auto kern) {
             int n = 0;
             if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, kBandThreads, 0) != hipSuccess || n < 1) n = 1;
             return n;
         };
-        table[0] = occ(k_stencil19b<1, 0>);
-        table[1] = occ(k_stencil19b<2, 0>);
-        table[2] = occ(k_stencil19b<4, 0>);
-        table[3] = occ(k_stencil19b<8, 0>);
+        table[0][0] = occ(k_stencil19b<1, 0, false>);
+        table[0][1] = occ(k_stencil19b<2, 0, false>);
+        table[0][2] = occ(k_stencil19b<4, 0, false>);
+        table[0][3] = occ(k_stencil19b<8, 0, false>);
+        table[1][0] = occ(k_stencil19b<1, 0, true>);
+        table[1][1] = occ(k_stencil19b<2, 0, true>);
+        table[1][2] = occ(k_stencil19b<4, 0, true>);
+        table[1][3] = occ(k_stencil19b<8, 0, true>);
     });
-    return table[nkt == 1 ? 0 : nkt == 2 ? 1 : nkt == 4 ? 2 : 3];
+    return table[dma ? 1 : 0][nkt == 1 ? 0 : nkt == 2 ? 1 : nkt == 4 ? 2 : 3];
 }
 
 }  // namespace
