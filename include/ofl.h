@@ -396,6 +396,19 @@ int ofl_kernel_stats(const ofl_app *app, const char *op, int64_t *executions, do
  * OFL_E_HIP. */
 int ofl_sweep19(const float *p, float *q, int64_t I, int64_t J, int64_t K, double *res_slot, void *stream);
 
+/* ofl_sweep19 for callers that cannot allocate device memory (code under
+ * stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, result bits, launches and errors, but it allocates nothing.
+ * The residual partials live in a fixed array of the library, 16384 doubles
+ * (128 KiB) on every device it runs on, held until the process ends; a grid
+ * whose sweep needs more partials than that (more than about 2000 CUs) is
+ * rejected with OFL_E_RANGE.  Every call on one device shares that device's
+ * array and leaves its partials there; calls that overlap on one device (on
+ * different streams or threads, or overlapping ofl_sweep19_noalloc launches
+ * of several callers) race on it and must be serialised by the caller. */
+int ofl_sweep19_noalloc(const float *p, float *q, int64_t I, int64_t J, int64_t K, double *res_slot,
+                        void *stream);
+
 /* ---------------------------------------------------------------- instance batches */
 
 /* Many instances of one application description that differ only in their

@@ -34,7 +34,8 @@ EXPORTS = ["ofl_app_load", "ofl_app_load_json", "ofl_app_free", "ofl_app_info", 
            "ofl_set_kernel_timing_sample", "ofl_kernel_stats",
            "ofl_batch_create", "ofl_batch_free", "ofl_batch_info", "ofl_batch_buf_info", "ofl_batch_buf_dims",
            "ofl_batch_buf_name", "ofl_batch_setup", "ofl_batch_run", "ofl_batch_get_config",
-           "ofl_batch_set_config", "ofl_batch_tune", "ofl_sweep19", "ofl_status_str", "ofl_last_error"]
+           "ofl_batch_set_config", "ofl_batch_tune", "ofl_sweep19", "ofl_sweep19_noalloc", "ofl_status_str",
+           "ofl_last_error"]
 
 
 class OflError(RuntimeError):
@@ -160,6 +161,7 @@ def lib():
             "ofl_batch_tune": (_I, [_P, ctypes.POINTER(_P), _I, _P, _I, ctypes.POINTER(TuneEntry), _I,
                                     ctypes.POINTER(_I)]),
             "ofl_sweep19": (_I, [_P, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _P, _P]),
+            "ofl_sweep19_noalloc": (_I, [_P, _P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, _P, _P]),
             "ofl_status_str": (ctypes.c_char_p, [_I]),
             "ofl_last_error": (ctypes.c_char_p, []),
         }
@@ -413,10 +415,11 @@ class App:
         return n.value, ms.value
 
 
-def sweep19(p, q, res, slot=0, stream=None):
+def sweep19(p, q, res, slot=0, stream=None, noalloc=False):
     """One sweep of the 19-point nest on torch tensors p, q (float32, I x J x
     K, on the GPU) adding its FP64 residual into res[slot] (float64 tensor on
-    the GPU); launches on the stream, returns without synchronising."""
+    the GPU); launches on the stream, returns without synchronising.
+    noalloc=True calls ofl_sweep19_noalloc (the library's fixed scratch)."""
     import torch
     I, J, K = p.shape
     if tuple(q.shape) != (I, J, K):
@@ -425,8 +428,9 @@ def sweep19(p, q, res, slot=0, stream=None):
         raise ValueError("p, q must be float32 and res float64")
     if not (p.is_contiguous() and q.is_contiguous()) or not 0 <= slot < res.numel():
         raise ValueError("p, q must be contiguous and slot inside res")
-    _check(lib().ofl_sweep19(_P(p.data_ptr()), _P(q.data_ptr()), I, J, K, _P(res.data_ptr() + 8 * slot),
-                             App._stream(stream)), "ofl_sweep19")
+    name = "ofl_sweep19_noalloc" if noalloc else "ofl_sweep19"
+    _check(getattr(lib(), name)(_P(p.data_ptr()), _P(q.data_ptr()), I, J, K, _P(res.data_ptr() + 8 * slot),
+                                App._stream(stream)), name)
 
 
 class Batch:
