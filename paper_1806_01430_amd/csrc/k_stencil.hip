@@ -121,7 +121,7 @@ struct GeoB {
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
-template <int NKT, int SP, bool DMA>
+template <int NKT, int SP, bool DMA, int LP = 0>
 __global__ __launch_bounds__(kBandThreads) void k_stencil19b(const float *__restrict__ p, float *__restrict__ q, GeoB g,
                                                              double *partials) {
     constexpr int RG = 16 / NKT;
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(kBandThreads) void k_stencil19b(const float *__rest
             for (int u = 0; u < kBandChunks; ++u) {
                 const int e = a0 + 4 * (u * kBandThreads + tid);
                 v[u] = __builtin_bit_cast(
-                    f32x4, __builtin_amdgcn_raw_buffer_load_b128(rp, (i <= ie && e < f1) ? e * 4 : kOutOfRange, 0, 0));
+                    f32x4, __builtin_amdgcn_raw_buffer_load_b128(rp, (i <= ie && e < f1) ? e * 4 : kOutOfRange, 0, LP));
             }
         };
         auto stage = [&](const f32x4 (&v)[kBandChunks], float *buf) {
@@ -183,7 +183,7 @@ __global__ __launch_bounds__(kBandThreads) void k_stencil19b(const float *__rest
                 const int e = a0 + 4 * (u * kBandThreads + tid);
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(
                     rp, (__attribute__((address_space(3))) void *)(buf + 4 * (u * kBandThreads + wv * kWave)), 16,
-                    (i <= ie && e < f1) ? e * 4 : kOutOfRange, 0, 0, 0);
+                    (i <= ie && e < f1) ? e * 4 : kOutOfRange, 0, 0, LP);
             }
             asm volatile("" ::: "memory");
         };
@@ -383,7 +383,7 @@ __global__ __launch_bounds__(kThreads) void k_copy_interior(float *__restrict__ 
 // dword without them.  Grid: x covers a plane's pieces, y the interior
 // planes, plus one more row of blocks whose first block runs the residual
 // finish of the sweep launched before (fin_n > 0).
-template <int U, int POL>
+template <int U, int LPOL, int SPOL>
 __global__ __launch_bounds__(kThreads) void k_copy_interior_flat(float *__restrict__ p, const float *__restrict__ q,
                                                                  int I, int J, int K, float invK,
                                                                  const double *fin_partials, int fin_n,
@@ -405,7 +405,7 @@ __global__ __launch_bounds__(kThreads) void k_copy_interior_flat(float *__restri
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int f = 4 * (g0 + u * kThreads);
-        v[u] = __builtin_amdgcn_raw_buffer_load_b128(rq, f < e ? f * 4 : kOutOfRange, 0, POL);
+        v[u] = __builtin_amdgcn_raw_buffer_load_b128(rq, f < e ? f * 4 : kOutOfRange, 0, LPOL);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -418,14 +418,14 @@ __global__ __launch_bounds__(kThreads) void k_copy_interior_flat(float *__restri
         if (k < 0) k += K;
         if (k >= K) k -= K;
         const bool whole = f >= s && f + 4 <= e && k >= 1 && k + 3 <= K - 2;
-        __builtin_amdgcn_raw_buffer_store_b128(v[u], rp, whole ? f * 4 : kOutOfRange, 0, POL);
+        __builtin_amdgcn_raw_buffer_store_b128(v[u], rp, whole ? f * 4 : kOutOfRange, 0, SPOL);
         if (!whole && f < e) {
 #pragma unroll
             for (int t = 0; t < 4; ++t) {
                 int kt = k + t;
                 if (kt >= K) kt -= K;
                 const bool ok = f + t >= s && f + t < e && kt != 0 && kt != K - 1;
-                __builtin_amdgcn_raw_buffer_store_b32(v[u][t], rp, ok ? (f + t) * 4 : kOutOfRange, 0, POL);
+                __builtin_amdgcn_raw_buffer_store_b32(v[u][t], rp, ok ? (f + t) * 4 : kOutOfRange, 0, SPOL);
             }
         }
     }
@@ -444,6 +444,7 @@ struct Config {
     GeoB gb;                 // band form
     int nkt = 0;             // band form: waves across a row (1, 2, 4, 8)
     bool dma = false;        // band form: planes loaded straight into LDS
+    bool load_nt = false;    // band form, 8 waves across: planes read with the streaming policy
     unsigned blocks;
     int waves_per_block = kWavesPerBlock;
 };
@@ -523,6 +524,7 @@ Config choose(int64_t I, int64_t J, int64_t K) {
     const int64_t grid_bytes = I * J * K * 4;
     c.store_nt = grid_bytes >= ((int64_t)4 << 20) && grid_bytes <= ((int64_t)512 << 20);
     if (const char *nt = std::getenv("OFL_STENCIL_NT")) c.store_nt = nt[0] == '1';
+    if (const char *lnt = std::getenv("OFL_STENCIL_LNT")) c.load_nt = lnt[0] == '1';
     if (const char *wd = std::getenv("OFL_STENCIL_WIDE")) c.form = wd[0] == '1' ? kFormWide : kFormOne;
     if (const char *fm = std::getenv("OFL_STENCIL_FORM")) {
         c.form = fm[0] == 'b' || fm[0] == 'd' ? kFormBand : fm[0] == 'w' ? kFormWide : kFormOne;
@@ -567,6 +569,10 @@ hipError_t launch_band(const Config &c, const float *p, float *q, double *partia
                               : launch((k_stencil19b<N, 0, true>), grid, block, 0, s, p, q, c.gb, partials);          \
         return c.store_nt ? launch((k_stencil19b<N, kNonTemporal, false>), grid, block, 0, s, p, q, c.gb, partials)    \
                           : launch((k_stencil19b<N, 0, false>), grid, block, 0, s, p, q, c.gb, partials);
+    if (c.load_nt && c.nkt == 8 && !c.dma)   // tuning knob: planes read with the streaming policy
+        return c.store_nt ? launch((k_stencil19b<8, kNonTemporal, false, kNonTemporal>), grid, block, 0, s, p, q,
+                                   c.gb, partials)
+                          : launch((k_stencil19b<8, 0, false, kNonTemporal>), grid, block, 0, s, p, q, c.gb, partials);
     switch (c.nkt) {
         OFL_BAND(1)
         OFL_BAND(2)
@@ -735,21 +741,46 @@ hipError_t launch_copy(float *p, const float *q, int64_t I, int64_t J, int64_t K
                   (int)K, f.partials, f.n, f.target);
 }
 
-constexpr int kFlatPieces = 4;   // 16-byte pieces per lane of the plane-range copy
-
-hipError_t launch_copy_flat(float *p, const float *q, int64_t I, int64_t J, int64_t K, int nt,
-                            const ResidualFinish &f, hipStream_t s) {
+// Plane-range copy, U 16-byte pieces per lane, load / store policies
+template <int U, int LPOL, int SPOL>
+hipError_t launch_copy_flat_u(float *p, const float *q, int64_t I, int64_t J, int64_t K, const ResidualFinish &f,
+                              hipStream_t s) {
     // pieces a plane's range may touch: its floats / 4, plus one for a
     // misaligned start and one for the end
     const int64_t pieces = ((J - 2) * K - 2) / 4 + 2;
-    const int64_t bx = (pieces + kThreads * kFlatPieces - 1) / (kThreads * kFlatPieces);
+    const int64_t bx = (pieces + kThreads * U - 1) / (kThreads * U);
     const dim3 grid((unsigned)bx, (unsigned)(I - 2 + (f.n > 0 ? 1 : 0)));
     const float invK = 1.0f / (float)K;
-    if (nt)
-        return launch((k_copy_interior_flat<kFlatPieces, kNonTemporal>), grid, dim3(kThreads), 0, s, p, q, (int)I,
-                      (int)J, (int)K, invK, f.partials, f.n, f.target);
-    return launch((k_copy_interior_flat<kFlatPieces, 0>), grid, dim3(kThreads), 0, s, p, q, (int)I, (int)J, (int)K,
+    return launch((k_copy_interior_flat<U, LPOL, SPOL>), grid, dim3(kThreads), 0, s, p, q, (int)I, (int)J, (int)K,
                   invK, f.partials, f.n, f.target);
+}
+
+// Tuning knob OFL_COPY_FLAT="U,LNT,SNT": pieces per lane (1, 2 or 4) and the
+// streaming policy for the loads / stores (0 or 1); default "4,nt,nt" with nt
+// from OFL_COPY_CFG.
+template <int U>
+hipError_t launch_copy_flat_p(float *p, const float *q, int64_t I, int64_t J, int64_t K, int lnt, int snt,
+                              const ResidualFinish &f, hipStream_t s) {
+    if (lnt && snt) return launch_copy_flat_u<U, kNonTemporal, kNonTemporal>(p, q, I, J, K, f, s);
+    if (lnt) return launch_copy_flat_u<U, kNonTemporal, 0>(p, q, I, J, K, f, s);
+    if (snt) return launch_copy_flat_u<U, 0, kNonTemporal>(p, q, I, J, K, f, s);
+    return launch_copy_flat_u<U, 0, 0>(p, q, I, J, K, f, s);
+}
+
+hipError_t launch_copy_flat(float *p, const float *q, int64_t I, int64_t J, int64_t K, int nt,
+                            const ResidualFinish &f, hipStream_t s) {
+    int u = 4, lnt = nt, snt = nt;
+    if (const char *e = std::getenv("OFL_COPY_FLAT")) {
+        int a = 0, b = 0, c = 0;
+        if (std::sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && (a == 1 || a == 2 || a == 4)) {
+            u = a;
+            lnt = b == 1;
+            snt = c == 1;
+        }
+    }
+    if (u == 1) return launch_copy_flat_p<1>(p, q, I, J, K, lnt, snt, f, s);
+    if (u == 2) return launch_copy_flat_p<2>(p, q, I, J, K, lnt, snt, f, s);
+    return launch_copy_flat_p<4>(p, q, I, J, K, lnt, snt, f, s);
 }
 
 hipError_t copy_interior(float *p, const float *q, int64_t I, int64_t J, int64_t K, hipStream_t s,

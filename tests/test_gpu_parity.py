@@ -287,9 +287,13 @@ def test_stencil_shapes(I, J, K, S):
                                          ("4,6", "w", "0"), ("8,4", "w", "1"), ("8,16", "w", "0"),
                                          ("8,2", "b", "0"), ("8,7", "b", "1"), ("8,32", "b", "0"), ("8,0", "b", "0"),
                                          ("8,1", "d", "0"), ("8,2", "d", "1"), ("8,4", "d", "0"), ("8,7", "d", "1"),
-                                         ("8,32", "d", "0"), ("8,0", "d", "0")])
+                                         ("8,32", "d", "0"), ("8,0", "d", "0"), ("8,0", "bl", "0"),
+                                         ("8,5", "bl", "1")])
 def test_stencil_kernel_forms(cfg, form, nt, monkeypatch):
     monkeypatch.setenv("OFL_STENCIL_CFG", cfg)
+    if form == "bl":   # band form, planes read with the streaming policy
+        form = "b"
+        monkeypatch.setenv("OFL_STENCIL_LNT", "1")
     monkeypatch.setenv("OFL_STENCIL_FORM", form)
     monkeypatch.setenv("OFL_STENCIL_NT", nt)
     shapes = [(4, 5, 6), (19, 23, 71), (5, 130, 300), (10, 11, 129), (6, 9, 254), (7, 6, 128)]
@@ -302,13 +306,17 @@ def test_stencil_kernel_forms(cfg, form, nt, monkeypatch):
         _run_and_compare(appgen.stencil_app(I, J, K, 2), [[1, 1]])
 
 
-@pytest.mark.parametrize("nt", ["0", "1"])
-def test_copy_interior_plane_range_form(nt, monkeypatch):
+@pytest.mark.parametrize("nt,flat", [("0", None), ("1", None), ("0", "1,0,0"), ("0", "1,1,1"), ("0", "2,1,0"),
+                                     ("0", "4,0,1")])
+def test_copy_interior_plane_range_form(nt, flat, monkeypatch):
     # the interior copy in its plane-range form (16-byte pieces of each
     # plane's contiguous interior range, the row-boundary columns left alone):
-    # rows of every alignment, ranges shorter than one piece, one-row planes
+    # rows of every alignment, ranges shorter than one piece, one-row planes;
+    # 1, 2 or 4 pieces per lane, streaming loads and / or stores
     monkeypatch.setenv("OFL_COPY_FORM", "flat")
     monkeypatch.setenv("OFL_COPY_CFG", "2,32,%s" % nt)
+    if flat:
+        monkeypatch.setenv("OFL_COPY_FLAT", flat)
     for I, J, K in [(3, 3, 3), (4, 5, 6), (3, 4, 7), (19, 23, 71), (5, 130, 300), (10, 11, 129), (6, 9, 254),
                     (7, 6, 128), (4, 20, 1025), (33, 33, 65), (5, 3, 1030)]:
         say("case copy plane-range nt=%s grid %dx%dx%d" % (nt, I, J, K))
