@@ -716,15 +716,29 @@ hipError_t stencil19(const float *p, float *q, int64_t I, int64_t J, int64_t K, 
     return residual_finish(fin, s);
 }
 
-// Tuning knob: OFL_COPY_CFG="ROWS,BLOCKS_PER_CU,NT" (ROWS in {2,4,8}, NT 0/1).
-void copy_env_override(int &rows_per_wave, int &bpc, int &nt) {
+// Tuning knob: OFL_COPY_CFG="ROWS,BLOCKS_PER_CU,NT" (ROWS in {2,4,8}, NT 0/1);
+// true when it is set.
+bool copy_env_override(int &rows_per_wave, int &bpc, int &nt) {
     const char *s = std::getenv("OFL_COPY_CFG");
-    if (!s) return;
+    if (!s) return false;
     int a = 0, b = 0, c = 0;
-    if (std::sscanf(s, "%d,%d,%d", &a, &b, &c) < 2) return;
+    if (std::sscanf(s, "%d,%d,%d", &a, &b, &c) < 2) return false;
     if (a == 2 || a == 4 || a == 8) rows_per_wave = a;
     if (b >= 1 && b <= 64) bpc = b;
     nt = c == 1 ? 1 : 0;
+    return true;
+}
+
+// Tuning knob: OFL_COPY_FLAT="U,LNT,SNT" for the plane-range form.
+void flat_env_override(int &u, int &lnt, int &snt) {
+    const char *e = std::getenv("OFL_COPY_FLAT");
+    if (!e) return;
+    int a = 0, b = 0, c = 0;
+    if (std::sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && (a == 1 || a == 2 || a == 4)) {
+        u = a;
+        lnt = b == 1;
+        snt = c == 1;
+    }
 }
 
 template <int ROWS>
@@ -756,8 +770,7 @@ hipError_t launch_copy_flat_u(float *p, const float *q, int64_t I, int64_t J, in
 }
 
 // Tuning knob OFL_COPY_FLAT="U,LNT,SNT": pieces per lane (1, 2 or 4) and the
-// streaming policy for the loads / stores (0 or 1); default "4,nt,nt" with nt
-// from OFL_COPY_CFG.
+// streaming policy for the loads / stores (0 or 1), overriding the choice.
 template <int U>
 hipError_t launch_copy_flat_p(float *p, const float *q, int64_t I, int64_t J, int64_t K, int lnt, int snt,
                               const ResidualFinish &f, hipStream_t s) {
@@ -767,17 +780,8 @@ hipError_t launch_copy_flat_p(float *p, const float *q, int64_t I, int64_t J, in
     return launch_copy_flat_u<U, 0, 0>(p, q, I, J, K, f, s);
 }
 
-hipError_t launch_copy_flat(float *p, const float *q, int64_t I, int64_t J, int64_t K, int nt,
+hipError_t launch_copy_flat(float *p, const float *q, int64_t I, int64_t J, int64_t K, int u, int lnt, int snt,
                             const ResidualFinish &f, hipStream_t s) {
-    int u = 4, lnt = nt, snt = nt;
-    if (const char *e = std::getenv("OFL_COPY_FLAT")) {
-        int a = 0, b = 0, c = 0;
-        if (std::sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && (a == 1 || a == 2 || a == 4)) {
-            u = a;
-            lnt = b == 1;
-            snt = c == 1;
-        }
-    }
     if (u == 1) return launch_copy_flat_p<1>(p, q, I, J, K, lnt, snt, f, s);
     if (u == 2) return launch_copy_flat_p<2>(p, q, I, J, K, lnt, snt, f, s);
     return launch_copy_flat_p<4>(p, q, I, J, K, lnt, snt, f, s);
@@ -792,14 +796,36 @@ hipError_t copy_interior(float *p, const float *q, int64_t I, int64_t J, int64_t
         return residual_finish(g, s);
     }
     if (I * J * K * 4 >= (1ll << 31)) return hipErrorInvalidValue;   // 32-bit buffer offsets
-    // measured on gfx950: 8 rows per wave and 16 blocks per CU up to 64 K
-    // interior rows (129^2-class planes), 2 rows and 32 blocks per CU beyond
+    // Forms measured on gfx950 (sweep + copy pair, the sweep's time depends
+    // on what the copy leaves in the caches):
+    //   grids of 512 MB and more: plane-range form, one 16-byte piece per
+    //     lane, streaming loads and stores -- 513x513x1025 pair 746 us
+    //     (copy 360 + sweep 386) against 833 (431 + 402) in the row form;
+    //     the copy's streaming stores leave no dirty lines of p for the
+    //     sweep to write back
+    //   64 MB to 512 MB: plane-range form, two pieces per lane, cached --
+    //     257x257x513 pair 90.8 us against 96.5 (streaming: 106.5; the
+    //     grids partly stay in the 256 MB last-level cache)
+    //   smaller: row form, 8 rows per wave and 16 blocks per CU up to 64 K
+    //     interior rows, 2 rows and 32 blocks per CU beyond -- 129x129x257
+    //     pair 19.2 us (plane-range forms 19.6-27.7)
+    // Knobs: OFL_COPY_FORM=flat / rows forces a form, OFL_COPY_CFG and
+    // OFL_COPY_FLAT its parameters.
+    const int64_t grid_bytes = I * J * K * 4;
     const bool small = (I - 2) * (J - 2) <= 65536;
     int rows_per_wave = small ? 8 : 2, bpc = small ? 16 : 32, nt = 0;
-    copy_env_override(rows_per_wave, bpc, nt);
-    // OFL_COPY_FORM=flat: the plane-range form (tuning knob)
+    const bool cfg_set = copy_env_override(rows_per_wave, bpc, nt);
     const char *form = std::getenv("OFL_COPY_FORM");
-    if (form && form[0] == 'f' && K >= 3 && (I - 2) <= 65535) return launch_copy_flat(p, q, I, J, K, nt, f, s);
+    const bool flat_ok = (I - 2) <= 65535;
+    bool flat = flat_ok && grid_bytes >= ((int64_t)64 << 20);
+    if (form) flat = flat_ok && form[0] == 'f';
+    if (flat) {
+        const bool huge = grid_bytes >= ((int64_t)512 << 20);
+        int u = huge ? 1 : 2, lnt = huge ? 1 : 0, snt = lnt;
+        if (cfg_set) lnt = snt = nt;
+        flat_env_override(u, lnt, snt);
+        return launch_copy_flat(p, q, I, J, K, u, lnt, snt, f, s);
+    }
     if (rows_per_wave == 2) return launch_copy<2>(p, q, I, J, K, bpc, nt, f, s);
     if (rows_per_wave == 8) return launch_copy<8>(p, q, I, J, K, bpc, nt, f, s);
     return launch_copy<4>(p, q, I, J, K, bpc, nt, f, s);

@@ -383,10 +383,15 @@ def test_stencil_eigenmode_decay():
     assert err < 100 * 2.0 ** -24
 
 
+# the default forms at full size (a grid of 512 MB or more copies in the
+# plane-range form with streaming accesses, 64-512 MB cached with two pieces
+# per lane), the band sweep loading straight into LDS, the row-form copy
 @pytest.mark.parametrize("I,J,K,form", [(257, 257, 513, None), (513, 513, 1025, None), (257, 257, 513, "d"),
-                                         (513, 513, 1025, "d")])
+                                         (513, 513, 1025, "d"), (257, 257, 513, "rows"), (513, 513, 1025, "rows")])
 def test_stencil_full_size_one_sweep(I, J, K, form, monkeypatch):
-    if form:
+    if form == "rows":
+        monkeypatch.setenv("OFL_COPY_FORM", "rows")
+    elif form:
         monkeypatch.setenv("OFL_STENCIL_FORM", form)
     _run_and_compare(appgen.stencil_app(I, J, K, 1), [[1, 1]], flags_list=(ofl.PRESTAGED | ofl.KEEP_OUTPUTS,))
 
