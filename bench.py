@@ -467,6 +467,8 @@ def main():
     ap.add_argument("--large-only", action="store_true",
                     help="only the large application's timed steps (for profiling)")
     ap.add_argument("--extras-only", action="store_true", help="only the extra lines (for profiling)")
+    ap.add_argument("--only", choices=["medium", "kernels", "precision", "batch", "population"], default=None,
+                    help="only one extra line (for profiling)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="first run a plain 1 GiB copy kernel (reference for hardware byte counters)")
     args = ap.parse_args()
@@ -483,6 +485,11 @@ def main():
         log("bench: calibration copy (1 GiB)")
         calibration_copy()
         torch.cuda.empty_cache()
+    if args.only:
+        fn = {"medium": run_medium, "kernels": run_kernels_large, "precision": run_precision, "batch": run_batch,
+              "population": run_population}[args.only]
+        print(json.dumps({args.only: fn(args)}), flush=True)
+        return
     if args.extras_only:
         out = {"medium": run_medium(args), "kernels_large": run_kernels_large(args)}
         torch.cuda.empty_cache()
