@@ -5,6 +5,7 @@
 // (k_gemm_nt) after preparation passes (k_split.hip).
 #include <hip/hip_runtime.h>
 
+#include <cstdlib>
 #include <type_traits>
 
 #include "gemm_tile.hpp"
@@ -61,22 +62,33 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(const float *__restrict__
 // lane takes a contiguous 32-byte run of the slab for its lane group.
 typedef long fp8x8;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-template <typename T, int BM, int BN, bool SCALED>
-__global__ __launch_bounds__(kThreads, 2) void k_gemm_nt(const T *__restrict__ A, const T *__restrict__ B,
-                                                      float *__restrict__ C, int M, int N, int Kp,
-                                                      const float *__restrict__ sa, const float *__restrict__ sb) {
+// Block shape BM x BN, WGM x WGN waves (each a (BM/WGM) x (BN/WGN) tile of
+// 16 x 16 MFMA tiles), MINB blocks per CU, NSET register sets of staged
+// slabs: with two, the slab two ahead is in flight from global memory while
+// the current one is computed (two compute periods to arrive); with one, the
+// next slab's loads go out before the current slab is computed (one period),
+// and the fragments of each half-slab are read just before its MFMAs -- the
+// register budget of the 256 x 256 block (128 accumulators per wave at two
+// waves per SIMD).
+template <typename T, int BM, int BN, int WGM, int WGN, int MINB, int NSET, bool SCALED>
+__global__ __launch_bounds__(WGM * WGN * 64, MINB) void k_gemm_nt(const T *__restrict__ A, const T *__restrict__ B,
+                                                               float *__restrict__ C, int M, int N, int Kp,
+                                                               const float *__restrict__ sa,
+                                                               const float *__restrict__ sb) {
+    constexpr int NT = WGM * WGN * 64;              // threads
     constexpr int SLAB = 128;                       // bytes of k per row per slab
     constexpr int LDS_ROW = SLAB + 16;              // padded row: conflict-free 16-byte reads
-    constexpr int WM = BM / 2, WN = BN / 2;
+    constexpr int WM = BM / WGM, WN = BN / WGN;
     constexpr int TM = WM / 16, TN = WN / 16;
-    constexpr int A_PER = BM * SLAB / 16 / kThreads;
-    constexpr int B_PER = BN * SLAB / 16 / kThreads;
-    static_assert(A_PER * 16 * kThreads == BM * SLAB && B_PER * 16 * kThreads == BN * SLAB, "tile mismatch");
+    constexpr int A_PER = BM * SLAB / 16 / NT;
+    constexpr int B_PER = BN * SLAB / 16 / NT;
+    static_assert(A_PER * 16 * NT == BM * SLAB && B_PER * 16 * NT == BN * SLAB, "tile mismatch");
+    static_assert(NSET == 1 || NSET == 2, "one or two staging sets");
     __shared__ __attribute__((aligned(16))) unsigned char As[2][BM * LDS_ROW];
     __shared__ __attribute__((aligned(16))) unsigned char Bs[2][BN * LDS_ROW];
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int wm = wave >> 1, wn = wave & 1;
+    const int wm = wave / WGN, wn = wave % WGN;
     int tm, tn;
     tile_of(blockIdx.x, (M + BM - 1) / BM, (N + BN - 1) / BN, tm, tn);
     const int m0 = tm * BM, n0 = tn * BN;
@@ -90,97 +102,137 @@ __global__ __launch_bounds__(kThreads, 2) void k_gemm_nt(const T *__restrict__ A
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-    // two register sets of staged slabs: the slab two ahead is in flight
-    // from global memory while the current one is computed, so each load has
-    // two compute periods to arrive before it is written to LDS
-    u32x4 ra[2][A_PER], rb[2][B_PER];
+    u32x4 ra[NSET][A_PER], rb[NSET][B_PER];
     auto gload = [&](int slab, int set) {
         const size_t kb = (size_t)slab * SLAB;
 #pragma unroll
         for (int s = 0; s < A_PER; ++s) {
-            const int idx = tid + s * kThreads, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
+            const int idx = tid + s * NT, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
             ra[set][s] = *reinterpret_cast<const u32x4 *>(Ab + (size_t)row * row_bytes + kb + c);
         }
 #pragma unroll
         for (int s = 0; s < B_PER; ++s) {
-            const int idx = tid + s * kThreads, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
+            const int idx = tid + s * NT, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
             rb[set][s] = *reinterpret_cast<const u32x4 *>(Bb + (size_t)row * row_bytes + kb + c);
         }
     };
     auto sstore = [&](int buf, int set) {
 #pragma unroll
         for (int s = 0; s < A_PER; ++s) {
-            const int idx = tid + s * kThreads, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
+            const int idx = tid + s * NT, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
             *reinterpret_cast<u32x4 *>(&As[buf][row * LDS_ROW + c]) = ra[set][s];
         }
 #pragma unroll
         for (int s = 0; s < B_PER; ++s) {
-            const int idx = tid + s * kThreads, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
+            const int idx = tid + s * NT, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
             *reinterpret_cast<u32x4 *>(&Bs[buf][row * LDS_ROW + c]) = rb[set][s];
         }
     };
     const int r = lane & 15, g = lane >> 4;
-    auto compute = [&](int buf) {
-        // lane group g owns bytes [32g, 32g+32) of the slab: two 16-byte
-        // halves h, each feeding one k-step of every accumulator; all reads
-        // of the slab are issued before the first MFMA
-        u32x4 af[TM][2], bfr[TN][2];
-#pragma unroll
-        for (int i = 0; i < TM; ++i)
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-                af[i][h] = *reinterpret_cast<const u32x4 *>(&As[buf][(wm * WM + i * 16 + r) * LDS_ROW + 32 * g + 16 * h]);
-#pragma unroll
-        for (int j = 0; j < TN; ++j)
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-                bfr[j][h] = *reinterpret_cast<const u32x4 *>(&Bs[buf][(wn * WN + j * 16 + r) * LDS_ROW + 32 * g + 16 * h]);
+    // lane group g owns bytes [32g, 32g+32) of the slab: two 16-byte halves
+    // h, each feeding one k-step of every accumulator
+    auto mfma_half = [&](const u32x4 (&af)[TM], const u32x4 (&bfr)[TN]) {
         if constexpr (sizeof(T) == 2) {
             // 8 bf16 per lane and MFMA
 #pragma unroll
-            for (int h = 0; h < 2; ++h)
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[i]),
+                                                                        __builtin_bit_cast(bf16x8, bfr[j]), acc[i][j],
+                                                                        0, 0, 0);
+        } else {
+            // 16 fp8 per lane and half: two MFMA steps of 8
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) {
+                        const fp8x8 a8 = (fp8x8)(((unsigned long)af[i][2 * q + 1] << 32) | af[i][2 * q]);
+                        const fp8x8 b8 = (fp8x8)(((unsigned long)bfr[j][2 * q + 1] << 32) | bfr[j][2 * q]);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a8, b8, acc[i][j], 0, 0, 0);
+                    }
+        }
+    };
+    auto read_half = [&](int buf, int h, u32x4 (&af)[TM], u32x4 (&bfr)[TN]) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+            af[i] = *reinterpret_cast<const u32x4 *>(&As[buf][(wm * WM + i * 16 + r) * LDS_ROW + 32 * g + 16 * h]);
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+            bfr[j] = *reinterpret_cast<const u32x4 *>(&Bs[buf][(wn * WN + j * 16 + r) * LDS_ROW + 32 * g + 16 * h]);
+    };
+    auto compute = [&](int buf) {
+        if constexpr (NSET == 2) {
+            // all reads of the slab issued before the first MFMA
+            u32x4 af[2][TM], bfr[2][TN];
+            read_half(buf, 0, af[0], bfr[0]);
+            read_half(buf, 1, af[1], bfr[1]);
+            mfma_half(af[0], bfr[0]);
+            mfma_half(af[1], bfr[1]);
+        } else if constexpr (sizeof(T) == 2) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                u32x4 af[TM], bfr[TN];
+                read_half(buf, h, af, bfr);
+                mfma_half(af, bfr);
+            }
+        } else {
+            // fp8: four k-steps of 8 bytes per lane, each read just before
+            // its MFMAs (8-byte fragments keep the register count in budget)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                fp8x8 af[TM], bfr[TN];
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+                    af[i] = *reinterpret_cast<const fp8x8 *>(
+                        &As[buf][(wm * WM + i * 16 + r) * LDS_ROW + 32 * g + 8 * q]);
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    bfr[j] = *reinterpret_cast<const fp8x8 *>(
+                        &Bs[buf][(wn * WN + j * 16 + r) * LDS_ROW + 32 * g + 8 * q]);
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
                     for (int j = 0; j < TN; ++j)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[i][h]),
-                                                                            __builtin_bit_cast(bf16x8, bfr[j][h]),
-                                                                            acc[i][j], 0, 0, 0);
-        } else {
-            // 16 fp8 per lane and half: two MFMA steps of 8
-#pragma unroll
-            for (int h = 0; h < 2; ++h)
-#pragma unroll
-                for (int q = 0; q < 2; ++q)
-#pragma unroll
-                    for (int i = 0; i < TM; ++i)
-#pragma unroll
-                        for (int j = 0; j < TN; ++j) {
-                            const fp8x8 a8 = (fp8x8)(((unsigned long)af[i][h][2 * q + 1] << 32) | af[i][h][2 * q]);
-                            const fp8x8 b8 = (fp8x8)(((unsigned long)bfr[j][h][2 * q + 1] << 32) | bfr[j][h][2 * q]);
-                            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a8, b8, acc[i][j], 0, 0, 0);
-                        }
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(af[i], bfr[j], acc[i][j], 0, 0, 0);
+            }
         }
     };
 
-    // slab kt lives in LDS buffer kt & 1 and, before that, in register set
-    // kt & 1; iteration kt loads slab kt + 2 into the set slab kt left,
-    // computes slab kt and writes slab kt + 1 to the other LDS buffer
     const int nslab = (int)(row_bytes / SLAB);
-    gload(0, 0);
-    sstore(0, 0);
-    if (nslab > 1) gload(1, 1);
-    __syncthreads();
-    auto iteration = [&](int kt, auto SET) {
-        constexpr int set = decltype(SET)::value;      // = kt & 1
-        if (kt + 2 < nslab) gload(kt + 2, set);
-        compute(set);
-        if (kt + 1 < nslab) sstore(set ^ 1, set ^ 1);
+    if constexpr (NSET == 2) {
+        // slab kt lives in LDS buffer kt & 1 and, before that, in register
+        // set kt & 1; iteration kt loads slab kt + 2 into the set slab kt
+        // left, computes slab kt and writes slab kt + 1 to the other buffer
+        gload(0, 0);
+        sstore(0, 0);
+        if (nslab > 1) gload(1, 1);
         __syncthreads();
-    };
-    for (int kt = 0; kt < nslab; kt += 2) {
-        iteration(kt, std::integral_constant<int, 0>());
-        if (kt + 1 < nslab) iteration(kt + 1, std::integral_constant<int, 1>());
+        auto iteration = [&](int kt, auto SET) {
+            constexpr int set = decltype(SET)::value;      // = kt & 1
+            if (kt + 2 < nslab) gload(kt + 2, set);
+            compute(set);
+            if (kt + 1 < nslab) sstore(set ^ 1, set ^ 1);
+            __syncthreads();
+        };
+        for (int kt = 0; kt < nslab; kt += 2) {
+            iteration(kt, std::integral_constant<int, 0>());
+            if (kt + 1 < nslab) iteration(kt + 1, std::integral_constant<int, 1>());
+        }
+    } else {
+        // iteration kt loads slab kt + 1 into the one register set, computes
+        // slab kt from LDS buffer kt & 1, then stages slab kt + 1 in the other
+        gload(0, 0);
+        sstore(0, 0);
+        __syncthreads();
+        for (int kt = 0; kt < nslab; ++kt) {
+            if (kt + 1 < nslab) gload(kt + 1, 0);
+            compute(kt & 1);
+            if (kt + 1 < nslab) sstore((kt + 1) & 1, 0);
+            __syncthreads();
+        }
     }
 #pragma unroll
     for (int i = 0; i < TM; ++i)
@@ -220,12 +272,20 @@ hipError_t gemm_f32(const float *A, const float *B, float *C, int64_t M, int64_t
 
 // ---------------------------------------------------------------- split-precision GEMM
 namespace {
-// Tile of the k-contiguous product (rows of A' x rows of B'): 128 x 128.  A
-// 256 x 256 tile (4 waves of 128 x 128, accumulators in AGPRs, one block per
-// CU) halves the LDS traffic per MFMA but measured slower on gfx950 at 4096
-// (521 vs 472 us for the bf16x3 product): with one wave per SIMD the LDS and
-// global latencies stay exposed.
-int nt_tile(int64_t, int64_t) { return 128; }
+// Tile of the k-contiguous product (rows of A' x rows of B'): 128 x 128
+// (4 waves of 64 x 64, two blocks per CU), or 256 x 256 (8 waves of
+// 128 x 64, one block per CU: a third less LDS traffic per MFMA) for
+// products of at least 256 such tiles.  An earlier 256 x 256 form with 4
+// waves of 128 x 128 (one wave per SIMD) measured slower than 128 x 128 at
+// 4096 (521 vs 472 us, bf16x3): its LDS and global latencies stayed exposed.
+// Knob OFL_GEMM_NT_TILE=128/256 forces a tile.
+int nt_tile(int64_t M, int64_t N) {
+    if (const char *e = std::getenv("OFL_GEMM_NT_TILE")) {
+        if (std::atoi(e) == 256) return 256;
+        if (std::atoi(e) == 128) return 128;
+    }
+    return ((M + 255) / 256) * ((N + 255) / 256) >= 256 ? 256 : 128;
+}
 
 int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
 
@@ -263,8 +323,11 @@ template <typename T, bool SCALED>
 hipError_t launch_nt(const NtLayout &L, const void *A, const void *B, float *C, int64_t M, int64_t N,
                      const float *sa, const float *sb, hipStream_t s) {
     const unsigned tiles = (unsigned)((L.Mp / L.tile) * (L.Np / L.tile));
-    return launch((k_gemm_nt<T, 128, 128, SCALED>), dim3(tiles), dim3(kThreads), 0, s, static_cast<const T *>(A),
-                  static_cast<const T *>(B), C, (int)M, (int)N, (int)L.Kp, sa, sb);
+    if (L.tile == 256)
+        return launch((k_gemm_nt<T, 256, 256, 2, 4, 1, 1, SCALED>), dim3(tiles), dim3(512), 0, s,
+                      static_cast<const T *>(A), static_cast<const T *>(B), C, (int)M, (int)N, (int)L.Kp, sa, sb);
+    return launch((k_gemm_nt<T, 128, 128, 2, 2, 2, 2, SCALED>), dim3(tiles), dim3(kThreads), 0, s,
+                  static_cast<const T *>(A), static_cast<const T *>(B), C, (int)M, (int)N, (int)L.Kp, sa, sb);
 }
 
 bool nt_sizes_ok(int64_t M, int64_t N, int64_t K) {

@@ -74,7 +74,8 @@ struct HostTask {
 };
 struct HostRestore {
     ofl_app *app = nullptr;
-    std::vector<int> bufs;
+    std::vector<int> bufs;    // set-up content the run consumes on the host
+    std::vector<int> marks;   // host copies the run writes
 };
 
 // Captured graphs of one (placement, policy, flags, device buffers).
@@ -639,13 +640,20 @@ void host_task_cb(void *p) {
 
 void clock_start_cb(void *p) { static_cast<GraphClock *>(p)->start = std::chrono::steady_clock::now(); }
 
+// Reset node of a run graph: restore the consumed host copies that differ
+// from their set-up content (as an eager run does), then mark the ones the
+// run after it writes -- the run follows this node on the stream, and the
+// flags are read by the submitting thread only after it synchronised.
 void host_restore_cb(void *p) {
     const HostRestore *r = static_cast<const HostRestore *>(p);
     for (int b : r->bufs) {
+        if (!r->app->host_dirty[b]) continue;
         const Buffer &buf = r->app->ir.bufs[b];
         if (!r->app->setup[b].empty()) std::memcpy(r->app->host[b], r->app->setup[b].data(), buf.nbytes);
         else std::memset(r->app->host[b], 0, buf.nbytes);
+        r->app->host_dirty[b] = 0;
     }
+    for (int b : r->marks) r->app->host_dirty[b] = 1;
 }
 
 // Whether this execution of nest n is timed; exec_count[op] counts the
@@ -720,8 +728,10 @@ int build_graphs(ofl_app *app, const std::vector<uint8_t> &placement, void *cons
             }
     ge.restore.reset(new HostRestore());
     ge.restore->app = app;
-    for (size_t b = 0; b < nb; ++b)
+    for (size_t b = 0; b < nb; ++b) {
         if (plan.host_init_used[b]) ge.restore->bufs.push_back((int)b);
+        if (ge.host_written[b]) ge.restore->marks.push_back((int)b);
+    }
 
     hipStream_t cs;
     int rc = capture_begin(app);

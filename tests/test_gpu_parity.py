@@ -148,8 +148,12 @@ def test_gemm_identity_and_rank1_exact():
         assert np.array_equal(app.read_buffer("C"), (N * np.outer(u, v)).astype(np.float32))
 
 
-@pytest.mark.parametrize("M,N,K", [(16, 16, 32), (100, 70, 45), (512, 512, 512)])
-def test_gemm_bf16_shapes(M, N, K):
+# tile "256": the 8-wave 256 x 256 form forced (chosen by size from 256 tiles up)
+@pytest.mark.parametrize("M,N,K,tile", [(16, 16, 32, None), (100, 70, 45, None), (512, 512, 512, None),
+                                        (100, 70, 45, "256"), (512, 512, 512, "256"), (300, 600, 130, "256")])
+def test_gemm_bf16_shapes(M, N, K, tile, monkeypatch):
+    if tile:
+        monkeypatch.setenv("OFL_GEMM_NT_TILE", tile)
     doc = appgen.gemm_app(M, N, K, op="gemm_bf16")
     A = OC.cast_bf16(OC.init_uniform(M * K, 4, 0).reshape(M, K))
     B = OC.cast_bf16(OC.init_uniform(K * N, 4, 1).reshape(K, N))
@@ -167,10 +171,14 @@ def _wide(shape, seed):
 
 
 @pytest.mark.parametrize("prec", SPLIT)
-@pytest.mark.parametrize("M,N,K", [(1, 1, 1), (17, 33, 5), (130, 70, 37), (257, 129, 300), (384, 256, 200)])
-def test_gemm_split_shapes(prec, M, N, K):
+@pytest.mark.parametrize("M,N,K,tile", [(1, 1, 1, None), (17, 33, 5, None), (130, 70, 37, None),
+                                        (257, 129, 300, None), (384, 256, 200, None), (1, 1, 1, "256"),
+                                        (257, 129, 300, "256"), (520, 300, 70, "256")])
+def test_gemm_split_shapes(prec, M, N, K, tile, monkeypatch):
     # gene 1: the split product (oracle: its definition summed in FP64);
     # gene 0: the nest as written, plain FP32 on the CPU
+    if tile:
+        monkeypatch.setenv("OFL_GEMM_NT_TILE", tile)
     doc = appgen.gemm_app(M, N, K, prec=prec)
     A = OC.init_uniform(M * K, 21, 0).reshape(M, K)
     B = OC.init_uniform(K * N, 21, 1).reshape(K, N)
@@ -196,10 +204,13 @@ def test_gemm_split_signed_wide_range(prec):
 
 
 @pytest.mark.parametrize("prec", SPLIT)
-def test_gemm_split_identity_and_rank1_exact(prec):
+@pytest.mark.parametrize("tile", [None, "256"])
+def test_gemm_split_identity_and_rank1_exact(prec, tile, monkeypatch):
     # A = I: every output is hi + lo of one element of B, exact in FP32, so the
     # GPU must equal the oracle's split bit for bit -- including e4m3
     # subnormals, as B spans many decades within each column
+    if tile:
+        monkeypatch.setenv("OFL_GEMM_NT_TILE", tile)
     for N in (64, 200):
         app = ofl.App(json.dumps(appgen.gemm_app(N, N, N, prec=prec)))
         B = _wide((N, N), N)
@@ -710,10 +721,11 @@ def test_sections_policy_random_genes(name, params):
 
 
 @pytest.mark.parametrize("op,prec", [("gemm", "bf16x3"), ("gemm", "fp8x2"), ("gemm_bf16", None)])
-def test_gemm_nt_256_tiles_ragged_sampled(op, prec):
-    # sizes past 2048 on both sides take the 256 x 256 tiles; ragged edges
-    # exercise the zero padding; sampled rows (and the ragged last rows)
-    # against the oracle
+def test_gemm_nt_256_tiles_ragged_sampled(op, prec, monkeypatch):
+    # the 256 x 256 tiles (8 waves; chosen by size from 256 tiles up, forced
+    # here); ragged edges exercise the zero padding; sampled rows (and the
+    # ragged last rows) against the oracle
+    monkeypatch.setenv("OFL_GEMM_NT_TILE", "256")
     M, N, K = 2100, 2060, 300
     app = ofl.App(json.dumps(appgen.gemm_app(M, N, K, op=op, prec=prec)))
     A = OC.init_uniform(M * K, 31, 0).reshape(M, K)
