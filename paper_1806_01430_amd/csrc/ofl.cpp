@@ -1114,20 +1114,47 @@ int measure_batched_all(ofl_app *app, const std::vector<std::vector<uint8_t>> &p
         ge[g]->clock->limit_s = limit > 0 ? limit : 0.0;
         ge[g]->clock->cut = false;
     }
+    std::vector<char> dead(n, 0), ran(n, 0), eager_warm(n, 0);
+    // A cut inside a captured run stops its host nests, but every later copy
+    // and kernel of the run still executes.  A host nest inside a repeated
+    // block (an iterated sweep left on the CPU) interleaves host work with
+    // copies in every repetition, so after a cut such a run still moves the
+    // buffers across PCIe once per repetition.  With a limit, these genes
+    // take their warm-up runs eagerly, where the limit ends the whole run, and
+    // join the submitted rounds only if they stay within it.
+    if (limit > 0 && warmup > 0) {
+        const size_t nn = app->ir.nests.size();
+        for (size_t g = 0; g < n; ++g) {
+            std::vector<int> cpu_runs(nn, 0);
+            for (const Step &st : ge[g]->plan.steps)
+                if (st.kind == ST_CPU && ++cpu_runs[st.idx] > 1) eager_warm[g] = 1;
+        }
+        for (size_t g = 0; g < n; ++g) {
+            if (!eager_warm[g]) continue;
+            for (int r = 0; r < warmup && !dead[g]; ++r) {
+                RunResult rr = run_once(app, placements[g], dev, s, policy, flags & ~(OFL_RUN_GRAPH | OFL_RUN_BATCHED),
+                                        limit);
+                if (rr.code == OFL_E_TIMEOUT || (rr.code == OFL_OK && rr.st.t_total_s > limit)) dead[g] = 1;
+                else if (rr.code != OFL_OK) return rr.code;
+            }
+        }
+    }
     // one submission per round (the warm-up runs, then each timed run): the
     // reset and run graphs of every gene still measured, back to back, an
     // event pair around each run graph.  A gene whose run went over the
     // limit, or whose host nests were cut, is a TIMEOUT and leaves the later
     // rounds (as an eager measurement stops at its first run over the limit)
-    std::vector<char> dead(n, 0), ran(n, 0);
     std::vector<std::vector<double>> ts(n);
     std::vector<size_t> last_round;
     hipError_t e = hipSuccess;
     for (int r = 0; r < warmup + reps && e == hipSuccess; ++r) {
         std::vector<size_t> round;
         for (size_t g = 0; g < n; ++g)
-            if (!dead[g]) round.push_back(g);
-        if (round.empty()) break;
+            if (!dead[g] && !(r < warmup && eager_warm[g])) round.push_back(g);
+        if (round.empty()) {
+            if (r < warmup) continue;   // every gene left took its warm-up eagerly
+            break;
+        }
         for (size_t k = 0; k < round.size() && e == hipSuccess; ++k) {
             const size_t g = round[k];
             e = hipGraphLaunch(ge[g]->reset, s);
