@@ -26,9 +26,16 @@ typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kGemmThreads = 256;
 
+// A slab of A is staged chunk-major: the 16-byte chunk c (k = 4c .. 4c+3) of
+// row m at float offset c*BM*4 + 4m, loaded with rows fastest (a wave takes
+// chunks 4h .. 4h+3 of 16 consecutive rows), so that an operand read (16
+// consecutive rows, one chunk) and a staging write each cover 256 contiguous
+// bytes per 16 lanes; rows padded to BK+4 floats left the operand reads
+// two-way bank conflicted on gfx950.  B stays row-major Bs[k][n] (its reads
+// walk n).
 template <int BM, int BN, int BK>
 struct GemmLds {
-    float As[2][BM * (BK + 4)];   // As[m][k], 16-byte aligned rows, conflict-free b128 reads
+    float As[2][BM * BK];
     float Bs[2][BK * (BN + 4)];   // Bs[k][n]
 };
 
@@ -37,8 +44,15 @@ __device__ inline void gemm_f32_tile(const float *__restrict__ A, const float *_
                                      int M, int N, int K, int m0, int n0, GemmLds<BM, BN, BK> &sm) {
     constexpr int WM = BM / 2, WN = BN / 2;
     constexpr int TM = WM / 16, TN = WN / 16;
-    constexpr int LDA = BK + 4;          // As[m][k], 16-byte aligned rows, conflict-free b128 reads
     constexpr int LDB = BN + 4;          // Bs[k][n]
+    static_assert((BK == 16 || BK == 32 || BK == 64) && BM % 16 == 0, "4, 8 or 16 chunks per row, 16-row groups");
+    // row and chunk of staged A piece p (0 .. BM BK/4 - 1): p = r16 + 16 (c_lo
+    // + 4 (group + BM/16 c_hi)) is chunk c_lo + 4 c_hi of row 16 group + r16
+    auto piece = [](int p, int &row, int &c) {
+        const int rest = p / 64;
+        row = (rest % (BM / 16)) * 16 + (p % 16);
+        c = (p / 16) % 4 + 4 * (rest / (BM / 16));
+    };
     constexpr int A_PER = BM * BK / 4 / kGemmThreads;
     constexpr int B_PER = BK * BN / 4 / kGemmThreads;
     static_assert(A_PER * 4 * kGemmThreads == BM * BK && B_PER * 4 * kGemmThreads == BK * BN, "tile / thread mismatch");
@@ -58,8 +72,9 @@ __device__ inline void gemm_f32_tile(const float *__restrict__ A, const float *_
     auto gload = [&](int k0) {
 #pragma unroll
         for (int s = 0; s < A_PER; ++s) {
-            const int idx = tid + s * kGemmThreads, row = idx / (BK / 4), c4 = (idx % (BK / 4)) * 4;
-            const int gm = m0 + row, gk = k0 + c4;
+            int row, c;
+            piece(tid + s * kGemmThreads, row, c);
+            const int gm = m0 + row, gk = k0 + 4 * c;
             if (VEC) {
                 ra[s] = (gm < M && gk < K) ? *reinterpret_cast<const float4 *>(A + (size_t)gm * K + gk)
                                            : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -92,8 +107,9 @@ __device__ inline void gemm_f32_tile(const float *__restrict__ A, const float *_
     auto sstore = [&](int buf) {
 #pragma unroll
         for (int s = 0; s < A_PER; ++s) {
-            const int idx = tid + s * kGemmThreads, row = idx / (BK / 4), c4 = (idx % (BK / 4)) * 4;
-            *reinterpret_cast<float4 *>(&As[buf][row * LDA + c4]) = ra[s];
+            int row, c;
+            piece(tid + s * kGemmThreads, row, c);
+            *reinterpret_cast<float4 *>(&As[buf][c * BM * 4 + 4 * row]) = ra[s];
         }
 #pragma unroll
         for (int s = 0; s < B_PER; ++s) {
@@ -106,9 +122,11 @@ __device__ inline void gemm_f32_tile(const float *__restrict__ A, const float *_
 #pragma unroll
         for (int ks = 0; ks < BK; ks += 16) {
             float4 af[TM];
+            const int c = ks / 4 + g;                       // this lane group's chunk
+            const int off = c * BM * 4 + 4 * r;               // + 4 * (16-row group base)
 #pragma unroll
             for (int i = 0; i < TM; ++i)
-                af[i] = *reinterpret_cast<const float4 *>(&As[buf][(wm * WM + i * 16 + r) * LDA + ks + 4 * g]);
+                af[i] = *reinterpret_cast<const float4 *>(&As[buf][off + 4 * (wm * WM + i * 16)]);
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 float bf[TN];

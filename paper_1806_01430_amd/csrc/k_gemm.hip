@@ -70,22 +70,43 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 // and the fragments of each half-slab are read just before its MFMAs -- the
 // register budget of the 256 x 256 block (128 accumulators per wave at two
 // waves per SIMD).
-template <typename T, int BM, int BN, int WGM, int WGN, int MINB, int NSET, bool SCALED>
+//
+// LDS layout of a staged slab (LAY), both staged row by row (8 lanes per
+// 128-byte row, the coalesced order of the global loads): 0 = row-major rows
+// padded to 144 bytes; 1 = chunk-major: the 16-byte chunk c of row R at
+// c * rows * 16 + 16 (R ^ 2c) (the XOR keeps a row's eight chunks in
+// distinct slots of one 256-byte span).  Measured on gfx950: layout 1 is
+// 4-5% faster (BF16x3 at 4096); both leave half of the LDS cycles bank
+// conflicted.  A chunk-major layout without the XOR, staged with rows
+// fastest, had no conflicts at all but ran 16% slower: the loads of a wave
+// then touch 16 rows at 64 bytes each instead of 8 rows at 128 bytes, and
+// the global side, not LDS, is what limits these kernels.
+template <typename T, int BM, int BN, int WGM, int WGN, int MINB, int NSET, int LAY, bool SCALED>
 __global__ __launch_bounds__(WGM * WGN * 64, MINB) void k_gemm_nt(const T *__restrict__ A, const T *__restrict__ B,
                                                                float *__restrict__ C, int M, int N, int Kp,
                                                                const float *__restrict__ sa,
                                                                const float *__restrict__ sb) {
     constexpr int NT = WGM * WGN * 64;              // threads
     constexpr int SLAB = 128;                       // bytes of k per row per slab
-    constexpr int LDS_ROW = SLAB + 16;              // padded row: conflict-free 16-byte reads
+    constexpr int LDS_ROW = LAY == 0 ? SLAB + 16 : SLAB;   // padded row (layout 0)
     constexpr int WM = BM / WGM, WN = BN / WGN;
     constexpr int TM = WM / 16, TN = WN / 16;
     constexpr int A_PER = BM * SLAB / 16 / NT;
     constexpr int B_PER = BN * SLAB / 16 / NT;
     static_assert(A_PER * 16 * NT == BM * SLAB && B_PER * 16 * NT == BN * SLAB, "tile mismatch");
     static_assert(NSET == 1 || NSET == 2, "one or two staging sets");
+    static_assert(BM % 16 == 0 && BN % 16 == 0, "whole 16-row groups");
     __shared__ __attribute__((aligned(16))) unsigned char As[2][BM * LDS_ROW];
     __shared__ __attribute__((aligned(16))) unsigned char Bs[2][BN * LDS_ROW];
+    // byte offset of chunk c (16 bytes) of row R in a staged slab of ROWS rows
+    auto at = [](int ROWS, int R, int c) {
+        return LAY == 0 ? R * LDS_ROW + 16 * c : c * ROWS * 16 + 16 * (R ^ (2 * c));
+    };
+    // the row and chunk of staged piece p (0 .. 8 ROWS - 1): row by row
+    auto piece = [](int, int p, int &row, int &c) {
+        row = p / (SLAB / 16);
+        c = p % (SLAB / 16);
+    };
 
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave / WGN, wn = wave % WGN;
@@ -107,25 +128,29 @@ __global__ __launch_bounds__(WGM * WGN * 64, MINB) void k_gemm_nt(const T *__res
         const size_t kb = (size_t)slab * SLAB;
 #pragma unroll
         for (int s = 0; s < A_PER; ++s) {
-            const int idx = tid + s * NT, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
-            ra[set][s] = *reinterpret_cast<const u32x4 *>(Ab + (size_t)row * row_bytes + kb + c);
+            int row, c;
+            piece(BM, tid + s * NT, row, c);
+            ra[set][s] = *reinterpret_cast<const u32x4 *>(Ab + (size_t)row * row_bytes + kb + 16 * c);
         }
 #pragma unroll
         for (int s = 0; s < B_PER; ++s) {
-            const int idx = tid + s * NT, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
-            rb[set][s] = *reinterpret_cast<const u32x4 *>(Bb + (size_t)row * row_bytes + kb + c);
+            int row, c;
+            piece(BN, tid + s * NT, row, c);
+            rb[set][s] = *reinterpret_cast<const u32x4 *>(Bb + (size_t)row * row_bytes + kb + 16 * c);
         }
     };
     auto sstore = [&](int buf, int set) {
 #pragma unroll
         for (int s = 0; s < A_PER; ++s) {
-            const int idx = tid + s * NT, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
-            *reinterpret_cast<u32x4 *>(&As[buf][row * LDS_ROW + c]) = ra[set][s];
+            int row, c;
+            piece(BM, tid + s * NT, row, c);
+            *reinterpret_cast<u32x4 *>(&As[buf][at(BM, row, c)]) = ra[set][s];
         }
 #pragma unroll
         for (int s = 0; s < B_PER; ++s) {
-            const int idx = tid + s * NT, row = idx / (SLAB / 16), c = (idx % (SLAB / 16)) * 16;
-            *reinterpret_cast<u32x4 *>(&Bs[buf][row * LDS_ROW + c]) = rb[set][s];
+            int row, c;
+            piece(BN, tid + s * NT, row, c);
+            *reinterpret_cast<u32x4 *>(&Bs[buf][at(BN, row, c)]) = rb[set][s];
         }
     };
     const int r = lane & 15, g = lane >> 4;
@@ -155,13 +180,18 @@ __global__ __launch_bounds__(WGM * WGN * 64, MINB) void k_gemm_nt(const T *__res
                     }
         }
     };
+    // a lane's byte offset of chunk c in the 16-row group that starts at row
+    // R0 (a multiple of 16): the group's base plus a per-lane part, so the
+    // group bases fold into instruction offsets
+    auto lane_off = [&](int ROWS, int c) { return at(ROWS, r, c); };
     auto read_half = [&](int buf, int h, u32x4 (&af)[TM], u32x4 (&bfr)[TN]) {
+        const int oa = lane_off(BM, 2 * g + h), ob = lane_off(BN, 2 * g + h);
 #pragma unroll
         for (int i = 0; i < TM; ++i)
-            af[i] = *reinterpret_cast<const u32x4 *>(&As[buf][(wm * WM + i * 16 + r) * LDS_ROW + 32 * g + 16 * h]);
+            af[i] = *reinterpret_cast<const u32x4 *>(&As[buf][oa + (wm * WM + i * 16) * (LAY == 0 ? LDS_ROW : 16)]);
 #pragma unroll
         for (int j = 0; j < TN; ++j)
-            bfr[j] = *reinterpret_cast<const u32x4 *>(&Bs[buf][(wn * WN + j * 16 + r) * LDS_ROW + 32 * g + 16 * h]);
+            bfr[j] = *reinterpret_cast<const u32x4 *>(&Bs[buf][ob + (wn * WN + j * 16) * (LAY == 0 ? LDS_ROW : 16)]);
     };
     auto compute = [&](int buf) {
         if constexpr (NSET == 2) {
@@ -184,14 +214,16 @@ __global__ __launch_bounds__(WGM * WGN * 64, MINB) void k_gemm_nt(const T *__res
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
                 fp8x8 af[TM], bfr[TN];
+                const int oa = lane_off(BM, 2 * g + (q >> 1)) + 8 * (q & 1);
+                const int ob = lane_off(BN, 2 * g + (q >> 1)) + 8 * (q & 1);
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
                     af[i] = *reinterpret_cast<const fp8x8 *>(
-                        &As[buf][(wm * WM + i * 16 + r) * LDS_ROW + 32 * g + 8 * q]);
+                        &As[buf][oa + (wm * WM + i * 16) * (LAY == 0 ? LDS_ROW : 16)]);
 #pragma unroll
                 for (int j = 0; j < TN; ++j)
                     bfr[j] = *reinterpret_cast<const fp8x8 *>(
-                        &Bs[buf][(wn * WN + j * 16 + r) * LDS_ROW + 32 * g + 8 * q]);
+                        &Bs[buf][ob + (wn * WN + j * 16) * (LAY == 0 ? LDS_ROW : 16)]);
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -323,11 +355,20 @@ template <typename T, bool SCALED>
 hipError_t launch_nt(const NtLayout &L, const void *A, const void *B, float *C, int64_t M, int64_t N,
                      const float *sa, const float *sb, hipStream_t s) {
     const unsigned tiles = (unsigned)((L.Mp / L.tile) * (L.Np / L.tile));
+    // knob OFL_GEMM_NT_LAYOUT=0/1: the LDS layout of the staged slabs
+    const char *lay = std::getenv("OFL_GEMM_NT_LAYOUT");
+    const bool cm = !(lay && lay[0] == '0');
+    const T *a = static_cast<const T *>(A), *b = static_cast<const T *>(B);
+    const int m = (int)M, n = (int)N, kp = (int)L.Kp;
     if (L.tile == 256)
-        return launch((k_gemm_nt<T, 256, 256, 2, 4, 1, 1, SCALED>), dim3(tiles), dim3(512), 0, s,
-                      static_cast<const T *>(A), static_cast<const T *>(B), C, (int)M, (int)N, (int)L.Kp, sa, sb);
-    return launch((k_gemm_nt<T, 128, 128, 2, 2, 2, 2, SCALED>), dim3(tiles), dim3(kThreads), 0, s,
-                  static_cast<const T *>(A), static_cast<const T *>(B), C, (int)M, (int)N, (int)L.Kp, sa, sb);
+        return cm ? launch((k_gemm_nt<T, 256, 256, 2, 4, 1, 1, 1, SCALED>), dim3(tiles), dim3(512), 0, s, a, b, C, m,
+                           n, kp, sa, sb)
+                  : launch((k_gemm_nt<T, 256, 256, 2, 4, 1, 1, 0, SCALED>), dim3(tiles), dim3(512), 0, s, a, b, C, m,
+                           n, kp, sa, sb);
+    return cm ? launch((k_gemm_nt<T, 128, 128, 2, 2, 2, 2, 1, SCALED>), dim3(tiles), dim3(kThreads), 0, s, a, b, C, m,
+                       n, kp, sa, sb)
+              : launch((k_gemm_nt<T, 128, 128, 2, 2, 2, 2, 0, SCALED>), dim3(tiles), dim3(kThreads), 0, s, a, b, C, m,
+                       n, kp, sa, sb);
 }
 
 bool nt_sizes_ok(int64_t M, int64_t N, int64_t K) {
