@@ -108,9 +108,23 @@ enum {
                                 limit; GPU work is not cut.  In the GA every
                                 gene of a generation gets the limit taken at
                                 the start of that generation. */
-    OFL_RUN_PROGRESS = 16    /* ofl_ga_run only: one line per generation on
+    OFL_RUN_PROGRESS = 16,   /* ofl_ga_run only: one line per generation on
                                 stderr (generation, best time so far, genes
                                 measured, wall time), for long searches */
+    OFL_RUN_CONCURRENT = 32  /* eager runs: the application's components --
+                                groups of nests that share no buffer (nor the
+                                product workspace) -- run at the same time,
+                                each on a stream of its own (default priority,
+                                created by the library; the caller's stream
+                                carries the first) and from a host thread of
+                                its own, each in program order, so that a
+                                memory-bound part overlaps a compute-bound one
+                                and a host nest holds up only its own part.
+                                Results are those of the sequential run (no
+                                data is shared between components); plans,
+                                copies and byte counts are the same.  Graph
+                                runs (OFL_RUN_GRAPH / OFL_RUN_BATCHED) stay
+                                sequential. */
 };
 
 /* Buffer element types. */

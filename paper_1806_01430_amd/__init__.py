@@ -21,7 +21,7 @@ E = {-1: "E_ARG", -2: "E_IO", -3: "E_PARSE", -4: "E_IR", -5: "E_GENE_LEN", -6: "
 PARALLEL, PARALLEL_REDUCTION, REJECT = 0, 1, 2
 R_NONE, R_DATA_DEP, R_EXTERNAL_CALL, R_BREAK = 0, 1, 2, 3
 RESIDENT, PER_REGION, SECTIONS = 0, 1, 2
-PRESTAGED, KEEP_OUTPUTS, GRAPH, BATCHED, PROGRESS = 1, 2, 4, 8, 16
+PRESTAGED, KEEP_OUTPUTS, GRAPH, BATCHED, PROGRESS, CONCURRENT = 1, 2, 4, 8, 16, 32
 ST_OK, ST_TIMEOUT, ST_FAILED, ST_MISMATCH = 0, 1, 2, 3
 BATCH_LOOP, BATCH_GROUPED, BATCH_GROUPED_GRAPH = 0, 1, 2
 _NP_DTYPE = {0: np.float32, 1: np.float64, 2: np.uint16}

@@ -16,6 +16,7 @@
 #include <new>
 #include <sstream>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "ga.hpp"
@@ -136,6 +137,16 @@ struct ofl_app {
     // event pairs of batched population evaluation
     std::vector<hipEvent_t> chain_events;
 
+    // concurrent runs (OFL_RUN_CONCURRENT): component of every buffer and
+    // nest (nests that share no buffer, nor the product workspace, are in
+    // different components), and per component beyond the first a stream and
+    // reduction scratch of its own
+    bool comps_done = false;
+    int n_comps = 1;
+    std::vector<int> buf_comp, nest_comp;
+    std::vector<hipStream_t> side_streams;
+    std::vector<double *> side_partials;
+
     // captured graphs and the stream they are captured on
     std::map<std::vector<uint64_t>, std::unique_ptr<GraphEntry>> graphs;
     hipStream_t capture_stream = nullptr;
@@ -163,6 +174,10 @@ struct ofl_app {
         if (d_twiddles) (void)hipFree(d_twiddles);
         for (auto e : events) (void)hipEventDestroy(e);
         for (auto e : chain_events) (void)hipEventDestroy(e);
+        for (auto st : side_streams)
+            if (st) (void)hipStreamDestroy(st);
+        for (double *p : side_partials)
+            if (p) (void)hipFree(p);
         if (host_lib) dlclose(host_lib);
         if (d_probe_idx) (void)hipFree(d_probe_idx);
         if (d_probe_val) (void)hipFree(d_probe_val);
@@ -318,11 +333,10 @@ int check_bufs(const ofl_app *app, void *const *dev_bufs, int32_t n_bufs) {
 // sets it, an interior copy runs it as its extra block.  The callers run it
 // by itself (k::residual_finish) before any other step.
 hipError_t launch_nest(ofl_app *app, const Nest &n, void *const *dev, const int64_t *env, hipStream_t s,
-                       k::ResidualFinish &fin) {
+                       k::ResidualFinish &fin, const k::ReduceScratch &rs) {
     const AppIR &ir = app->ir;
     auto F = [&](int i) { return static_cast<float *>(dev[n.b[i]]); };
     auto cnt = [&](int i) { return ir.bufs[n.b[i]].count; };
-    k::ReduceScratch rs{app->d_partials, app->partial_cap};
     hipError_t e = hipSuccess;
     switch (n.op) {
     case OP_INIT_UNIFORM:
@@ -396,6 +410,187 @@ struct RunResult {
     ofl_run_stats st{};
 };
 
+// Components of the application: buffers joined by every nest that touches
+// them (and every product nest that uses the shared operand workspace), so
+// that nests of different components share no data and may run at once.
+void ensure_components(ofl_app *app) {
+    if (app->comps_done) return;
+    const AppIR &ir = app->ir;
+    const size_t nb = ir.bufs.size();
+    std::vector<int> parent(nb + 1);   // + 1: the product workspace
+    for (size_t i = 0; i <= nb; ++i) parent[i] = (int)i;
+    auto find = [&](int x) {
+        while (parent[x] != x) x = parent[x] = parent[parent[x]];
+        return x;
+    };
+    auto unite = [&](int x, int y) { parent[find(x)] = find(y); };
+    for (const Nest &n : ir.nests) {
+        std::vector<int> bs = n.b;
+        bs.insert(bs.end(), n.reads.begin(), n.reads.end());
+        bs.insert(bs.end(), n.writes.begin(), n.writes.end());
+        if ((n.op == OP_GEMM || n.op == OP_GEMM_BF16) && gemm_variant(n) != 0) bs.push_back((int)nb);
+        for (size_t i = 1; i < bs.size(); ++i) unite(bs[0], bs[i]);
+    }
+    // number the components of buffers some nest touches, in program order
+    std::map<int, int> id;
+    app->nest_comp.assign(ir.nests.size(), 0);
+    for (size_t k = 0; k < ir.nests.size(); ++k) {
+        const Nest &n = ir.nests[k];
+        const int b0 = !n.b.empty() ? n.b[0] : !n.writes.empty() ? n.writes[0] : !n.reads.empty() ? n.reads[0] : -1;
+        if (b0 < 0) continue;
+        const int root = find(b0);
+        if (!id.count(root)) id[root] = (int)id.size();
+        app->nest_comp[k] = id[root];
+    }
+    app->buf_comp.assign(nb, 0);
+    for (size_t b = 0; b < nb; ++b) {
+        const auto it = id.find(find((int)b));
+        app->buf_comp[b] = it == id.end() ? 0 : it->second;
+    }
+    app->n_comps = std::max<int>(1, (int)id.size());
+    app->comps_done = true;
+}
+
+int step_comp(const ofl_app *app, const Step &step) {
+    return (step.kind == ST_H2D || step.kind == ST_D2H) ? app->buf_comp[step.idx] : app->nest_comp[step.idx];
+}
+
+// A stream (default priority) and reduction scratch for every component
+// beyond the first.
+int ensure_side_streams(ofl_app *app) {
+    while ((int)app->side_streams.size() < app->n_comps - 1) {
+        hipStream_t st = nullptr;
+        hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamCreateWithFlags");
+        app->side_streams.push_back(st);
+        void *mem = nullptr;
+        e = hipMalloc(&mem, (size_t)app->partial_cap * sizeof(double) + 256);
+        if (e != hipSuccess) {
+            app->side_partials.push_back(nullptr);
+            return e == hipErrorOutOfMemory ? fail(OFL_E_NOMEM, "device scratch") : hip_fail(e, "hipMalloc");
+        }
+        app->side_partials.push_back(static_cast<double *>(mem));
+    }
+    for (double *p : app->side_partials)
+        if (!p) return fail(OFL_E_NOMEM, "device scratch");
+    return OFL_OK;
+}
+
+// What one component's part of a run did.
+struct StepsOut {
+    int code = OFL_OK;
+    std::string msg;
+    bool timed_out = false;
+    uint64_t h2d = 0, d2h = 0;
+    int32_t copies = 0, launches = 0, host_nests = 0;
+    std::vector<char> host_written;
+    std::vector<std::pair<int, int>> timed;   // (nest, event index)
+};
+
+hipError_t copy_box_d2h(const Buffer &buf, void *host, const void *dev, const Box &bx, hipStream_t s);
+
+// The timed part of an eager run for the steps `idx` (indices into
+// plan.steps, in program order) on `stream`: copies and kernels issued
+// asynchronously, the stream synchronised before each host nest, the
+// deadline checked before each step and inside host nests.  step_ev[i] is
+// the event pair of step i (-1: not timed).
+void run_steps(ofl_app *app, const Plan &plan, const std::vector<int> &idx, const std::vector<int> &step_ev,
+               void *const *dev, hipStream_t stream, const k::ReduceScratch &rs, const Deadline &dl, StepsOut &out) {
+    const AppIR &ir = app->ir;
+    bool pending = false;
+    hipError_t e = hipSuccess;
+    k::ResidualFinish fin;
+    auto failed = [&](int code) {
+        out.code = code;
+        out.msg = ofl_last_error();
+    };
+    for (int i : idx) {
+        const Step &step = plan.steps[i];
+        if (dl.expired()) {
+            out.timed_out = true;
+            break;
+        }
+        if (fin.n > 0 && !takes_finish(step, ir)) {
+            e = k::residual_finish(fin, stream);
+            if (e != hipSuccess) {
+                failed(hip_fail(e, "launch of a residual finish"));
+                break;
+            }
+            out.launches++;
+        }
+        switch (step.kind) {
+        case ST_H2D:
+            e = hipMemcpyAsync(dev[step.idx], app->host[step.idx], ir.bufs[step.idx].nbytes, hipMemcpyHostToDevice,
+                               stream);
+            if (e != hipSuccess) {
+                failed(hip_fail(e, "H2D copy"));
+                break;
+            }
+            out.h2d += ir.bufs[step.idx].nbytes;
+            out.copies++;
+            pending = true;
+            break;
+        case ST_D2H:
+            e = step.box < 0 ? hipMemcpyAsync(app->host[step.idx], dev[step.idx], ir.bufs[step.idx].nbytes,
+                                              hipMemcpyDeviceToHost, stream)
+                             : copy_box_d2h(ir.bufs[step.idx], app->host[step.idx], dev[step.idx],
+                                            plan.boxes[step.box], stream);
+            if (e != hipSuccess) {
+                failed(hip_fail(e, "D2H copy"));
+                break;
+            }
+            out.d2h += step.box < 0 ? ir.bufs[step.idx].nbytes : box_bytes(ir.bufs[step.idx], plan.boxes[step.box]);
+            out.copies++;
+            out.host_written[step.idx] = 1;
+            pending = true;
+            break;
+        case ST_GPU: {
+            const Nest &n = ir.nests[step.idx];
+            const int ev = step_ev[i];
+            // a single-launch nest gets its events in the dispatch packet itself
+            // (kernel-only interval); a multi-launch nest is bracketed by events
+            const bool single = kernel_launch_count(ir, n) == 1;
+            if (ev >= 0 && single) k::arm_launch_events(app->events[ev], app->events[ev + 1]);
+            if (ev >= 0 && !single) (void)hipEventRecord(app->events[ev], stream);
+            e = launch_nest(app, n, dev, plan.env.data() + step.env, stream, fin, rs);
+            k::arm_launch_events(nullptr, nullptr);
+            if (e != hipSuccess) {
+                failed(hip_fail(e, (std::string("launch of nest ") + n.name).c_str()));
+                break;
+            }
+            if (ev >= 0) {
+                if (!single) (void)hipEventRecord(app->events[ev + 1], stream);
+                out.timed.emplace_back(step.idx, ev);
+            }
+            out.launches += kernel_launch_count(ir, n);
+            pending = true;
+            break;
+        }
+        case ST_CPU: {
+            if (pending) {
+                e = hipStreamSynchronize(stream);
+                if (e != hipSuccess) {
+                    failed(hip_fail(e, "hipStreamSynchronize"));
+                    break;
+                }
+                pending = false;
+            }
+            const Nest &n = ir.nests[step.idx];
+            if (!run_host_nest(ir, n, app->host, plan.env.data() + step.env, app->seed, dl)) out.timed_out = true;
+            for (int b : n.writes) out.host_written[b] = 1;
+            out.host_nests++;
+            break;
+        }
+        }
+        if (out.code != OFL_OK || out.timed_out) break;
+    }
+    if (out.code == OFL_OK && !out.timed_out && fin.n > 0) {
+        e = k::residual_finish(fin, stream);
+        if (e != hipSuccess) failed(hip_fail(e, "launch of a residual finish"));
+        else out.launches++;
+    }
+}
+
 // Copy box `bx` of buffer b from the device to the same place in its host
 // copy: the trailing dimensions the box covers whole and the first partial
 // one form contiguous runs; the next dimension out becomes the rows of one
@@ -449,6 +644,7 @@ RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *co
     Plan plan;
     build_plan(ir, placement, policy, flags, plan);
     app->ran = false;
+    ensure_components(app);
 
     // ---- untimed reset: restore only set-up content that this run consumes
     for (size_t b = 0; b < nb; ++b)
@@ -482,7 +678,6 @@ RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *co
     }
 
     // per-kernel timing events: two per GPU nest step
-    std::vector<std::pair<int, int>> timed;   // (nest, event index)
     if (app->timing) {
         const size_t need = 2 * (size_t)plan.launches;
         while (app->events.size() < need) {
@@ -492,105 +687,78 @@ RunResult run_once(ofl_app *app, const std::vector<uint8_t> &placement, void *co
         }
     }
 
-    std::vector<char> host_written(nb, 0);
+    // which GPU steps carry timing events (program order, as a sequential
+    // run samples them) and their event pairs
+    std::vector<int> step_ev(plan.steps.size(), -1);
+    {
+        size_t ev_next = 0;
+        int32_t exec_count[OP_COUNT] = {};
+        for (size_t i = 0; i < plan.steps.size(); ++i) {
+            const Step &step = plan.steps[i];
+            if (step.kind != ST_GPU) continue;
+            if (timed_nest(app, ir.nests[step.idx], exec_count) && ev_next + 2 <= app->events.size()) {
+                step_ev[i] = (int)ev_next;
+                ev_next += 2;
+            }
+        }
+    }
+    // the steps of each component, in program order
+    const bool concurrent = (flags & OFL_RUN_CONCURRENT) && app->n_comps > 1;
+    if (concurrent && (rc = ensure_side_streams(app)) != OFL_OK) {
+        rr.code = rc;
+        st.status = OFL_ST_FAILED;
+        return rr;
+    }
+    const int nc = concurrent ? app->n_comps : 1;
+    std::vector<std::vector<int>> comp_steps(nc);
+    for (size_t i = 0; i < plan.steps.size(); ++i)
+        comp_steps[concurrent ? step_comp(app, plan.steps[i]) : 0].push_back((int)i);
+
     Deadline dl;
     const auto t0 = clk::now();
     if (deadline_s > 0) {
         dl.active = true;
         dl.until = t0 + std::chrono::duration_cast<clk::duration>(std::chrono::duration<double>(deadline_s));
     }
-    bool pending = false, timed_out = false;
-    size_t ev_next = 0;
-    k::ResidualFinish fin;
-    int32_t exec_count[OP_COUNT] = {};
-    for (const Step &step : plan.steps) {
-        if (dl.expired()) {
-            timed_out = true;
-            break;
-        }
-        if (fin.n > 0 && !takes_finish(step, ir)) {
-            e = k::residual_finish(fin, stream);
-            if (e != hipSuccess) {
-                rr.code = hip_fail(e, "launch of a residual finish");
-                break;
-            }
-            st.n_launches++;
-        }
-        switch (step.kind) {
-        case ST_H2D:
-            e = hipMemcpyAsync(dev[step.idx], app->host[step.idx], ir.bufs[step.idx].nbytes, hipMemcpyHostToDevice,
-                               stream);
-            if (e != hipSuccess) {
-                rr.code = hip_fail(e, "H2D copy");
-                break;
-            }
-            st.bytes_h2d += ir.bufs[step.idx].nbytes;
-            st.n_copies++;
-            pending = true;
-            break;
-        case ST_D2H:
-            e = step.box < 0 ? hipMemcpyAsync(app->host[step.idx], dev[step.idx], ir.bufs[step.idx].nbytes,
-                                              hipMemcpyDeviceToHost, stream)
-                             : copy_box_d2h(ir.bufs[step.idx], app->host[step.idx], dev[step.idx],
-                                            plan.boxes[step.box], stream);
-            if (e != hipSuccess) {
-                rr.code = hip_fail(e, "D2H copy");
-                break;
-            }
-            st.bytes_d2h += step.box < 0 ? ir.bufs[step.idx].nbytes : box_bytes(ir.bufs[step.idx], plan.boxes[step.box]);
-            st.n_copies++;
-            host_written[step.idx] = 1;
-            pending = true;
-            break;
-        case ST_GPU: {
-            const Nest &n = ir.nests[step.idx];
-            const bool tm = timed_nest(app, n, exec_count) && ev_next + 2 <= app->events.size();
-            // a single-launch nest gets its events in the dispatch packet itself
-            // (kernel-only interval); a multi-launch nest is bracketed by events
-            const bool single = kernel_launch_count(ir, n) == 1;
-            if (tm && single) k::arm_launch_events(app->events[ev_next], app->events[ev_next + 1]);
-            if (tm && !single) (void)hipEventRecord(app->events[ev_next], stream);
-            e = launch_nest(app, n, dev, plan.env.data() + step.env, stream, fin);
-            k::arm_launch_events(nullptr, nullptr);
-            if (e != hipSuccess) {
-                rr.code = hip_fail(e, (std::string("launch of nest ") + n.name).c_str());
-                break;
-            }
-            if (tm) {
-                if (!single) (void)hipEventRecord(app->events[ev_next + 1], stream);
-                timed.emplace_back(step.idx, (int)ev_next);
-                ev_next += 2;
-            }
-            st.n_launches += kernel_launch_count(ir, n);
-            pending = true;
-            break;
-        }
-        case ST_CPU: {
-            if (pending) {
-                e = hipStreamSynchronize(stream);
-                if (e != hipSuccess) {
-                    rr.code = hip_fail(e, "hipStreamSynchronize");
-                    break;
-                }
-                pending = false;
-            }
-            const Nest &n = ir.nests[step.idx];
-            if (!run_host_nest(ir, n, app->host, plan.env.data() + step.env, app->seed, dl)) timed_out = true;
-            for (int b : n.writes) host_written[b] = 1;
-            st.n_host_nests++;
-            break;
-        }
-        }
-        if (rr.code != OFL_OK || timed_out) break;
+    std::vector<StepsOut> outs(nc);
+    for (auto &o : outs) o.host_written.assign(nb, 0);
+    auto exec = [&](int c) {
+        const hipStream_t cs = c == 0 ? stream : app->side_streams[c - 1];
+        const k::ReduceScratch rs{c == 0 ? app->d_partials : app->side_partials[c - 1], app->partial_cap};
+        run_steps(app, plan, comp_steps[c], step_ev, dev, cs, rs, dl, outs[c]);
+    };
+    if (nc == 1) {
+        exec(0);
+    } else {
+        // every component from a host thread of its own (a host nest blocks
+        // only its own component), on its own stream
+        std::vector<std::thread> th;
+        for (int c = 1; c < nc; ++c)
+            if (!comp_steps[c].empty()) th.emplace_back(exec, c);
+        exec(0);
+        for (auto &t : th) t.join();
     }
-    if (rr.code == OFL_OK && !timed_out && fin.n > 0) {
-        e = k::residual_finish(fin, stream);
-        if (e != hipSuccess) rr.code = hip_fail(e, "launch of a residual finish");
-        else st.n_launches++;
+    e = hipSuccess;
+    for (int c = 0; c < nc; ++c) {
+        const hipError_t ec = hipStreamSynchronize(c == 0 ? stream : app->side_streams[c - 1]);
+        if (e == hipSuccess) e = ec;
     }
-    e = hipStreamSynchronize(stream);
     const auto t1 = clk::now();
     st.t_total_s = std::chrono::duration<double>(t1 - t0).count();
+    std::vector<char> host_written(nb, 0);
+    bool timed_out = false;
+    std::vector<std::pair<int, int>> timed;   // (nest, event index)
+    for (const StepsOut &o : outs) {
+        if (rr.code == OFL_OK && o.code != OFL_OK) rr.code = fail(o.code, o.msg);
+        timed_out = timed_out || o.timed_out;
+        st.bytes_h2d += o.h2d;
+        st.bytes_d2h += o.d2h;
+        st.n_copies += o.copies;
+        st.n_launches += o.launches;
+        st.n_host_nests += o.host_nests;
+        for (size_t b = 0; b < nb; ++b) host_written[b] = host_written[b] || o.host_written[b];
+        timed.insert(timed.end(), o.timed.begin(), o.timed.end());
+    }
     for (size_t b = 0; b < nb; ++b)
         if (host_written[b]) app->host_dirty[b] = 1;
     if (rr.code == OFL_OK && e != hipSuccess) rr.code = hip_fail(e, "hipStreamSynchronize");
@@ -783,7 +951,9 @@ int build_graphs(ofl_app *app, const std::vector<uint8_t> &placement, void *cons
                 }
                 e = capture_event_node(cs, ev0);
             }
-            if (e == hipSuccess) e = launch_nest(app, ir.nests[st.idx], dev, plan.env.data() + st.env, cs, fin);
+            if (e == hipSuccess)
+                e = launch_nest(app, ir.nests[st.idx], dev, plan.env.data() + st.env, cs, fin,
+                                k::ReduceScratch{app->d_partials, app->partial_cap});
             if (e == hipSuccess && tm) e = capture_event_node(cs, ev1);
             ge.launches += kernel_launch_count(ir, ir.nests[st.idx]);
             break;
@@ -812,7 +982,7 @@ int build_graphs(ofl_app *app, const std::vector<uint8_t> &placement, void *cons
 int get_graph(ofl_app *app, const std::vector<uint8_t> &placement, void *const *dev, int policy, int flags,
               GraphEntry **out) {
     const size_t nb = app->ir.bufs.size();
-    const int gflags = flags & ~(OFL_RUN_GRAPH | OFL_RUN_BATCHED);
+    const int gflags = flags & ~(OFL_RUN_GRAPH | OFL_RUN_BATCHED | OFL_RUN_CONCURRENT);
     std::vector<uint64_t> key(placement.begin(), placement.end());
     key.push_back((uint64_t)policy);
     key.push_back((uint64_t)gflags);
@@ -1502,7 +1672,8 @@ int ofl_plan_transfers(const ofl_app *app, const uint8_t *gene, int32_t gene_len
                        uint64_t *bytes_h2d, uint64_t *bytes_d2h, int32_t *n_copies) {
     if (!app) return fail(OFL_E_ARG, "null app");
     if (policy < OFL_POLICY_RESIDENT || policy > OFL_POLICY_SECTIONS) return fail(OFL_E_ARG, "bad policy");
-    if (flags & ~(OFL_RUN_PRESTAGED | OFL_RUN_KEEP_OUTPUTS | OFL_RUN_GRAPH)) return fail(OFL_E_ARG, "bad flags");
+    if (flags & ~(OFL_RUN_PRESTAGED | OFL_RUN_KEEP_OUTPUTS | OFL_RUN_GRAPH | OFL_RUN_CONCURRENT))
+        return fail(OFL_E_ARG, "bad flags");
     std::vector<uint8_t> placement;
     int rc = check_gene(app, gene, gene_len, placement);
     if (rc != OFL_OK) return rc;
@@ -1527,7 +1698,8 @@ int ofl_run_pattern(ofl_app *app, const uint8_t *gene, int32_t gene_len, void *c
     const int flags = opts ? opts->flags : 0;
     const double deadline = opts ? opts->deadline_s : 0.0;
     if (policy < OFL_POLICY_RESIDENT || policy > OFL_POLICY_SECTIONS) return fail(OFL_E_ARG, "bad policy");
-    if (flags & ~(OFL_RUN_PRESTAGED | OFL_RUN_KEEP_OUTPUTS | OFL_RUN_GRAPH)) return fail(OFL_E_ARG, "bad flags");
+    if (flags & ~(OFL_RUN_PRESTAGED | OFL_RUN_KEEP_OUTPUTS | OFL_RUN_GRAPH | OFL_RUN_CONCURRENT))
+        return fail(OFL_E_ARG, "bad flags");
     const double rtol = opts ? opts->verify_rtol : 0.0;
     if (rtol > 0 && (rc = ensure_reference(app, dev_bufs, static_cast<hipStream_t>(stream), policy)) != OFL_OK)
         return rc;
@@ -1551,7 +1723,7 @@ int ofl_eval_population(ofl_app *app, const uint8_t *genes, int32_t pop, int32_t
     if (opts->reps < 1 || opts->warmup < 0) return fail(OFL_E_ARG, "need reps >= 1 and warmup >= 0");
     int rc = check_bufs(app, dev_bufs, n_bufs);
     if (rc != OFL_OK) return rc;
-    if (opts->flags & ~(OFL_RUN_PRESTAGED | OFL_RUN_KEEP_OUTPUTS | OFL_RUN_GRAPH | OFL_RUN_BATCHED))
+    if (opts->flags & ~(OFL_RUN_PRESTAGED | OFL_RUN_KEEP_OUTPUTS | OFL_RUN_GRAPH | OFL_RUN_BATCHED | OFL_RUN_CONCURRENT))
         return fail(OFL_E_ARG, "bad flags");
     std::map<std::vector<uint8_t>, Measurement> seen;
     std::vector<uint8_t> placement;

@@ -18,7 +18,8 @@ import time
 
 import numpy as np
 
-from . import App, app_doc, ga_params, RESIDENT, PER_REGION, SECTIONS, PRESTAGED, KEEP_OUTPUTS, GRAPH, BATCHED, PROGRESS
+from . import App, app_doc, ga_params, RESIDENT, PER_REGION, SECTIONS, PRESTAGED, KEEP_OUTPUTS, GRAPH, BATCHED, PROGRESS, \
+    CONCURRENT
 
 
 def main(argv=None):
@@ -39,6 +40,8 @@ def main(argv=None):
     ap.add_argument("--graph", action="store_true", help="measure graph replays")
     ap.add_argument("--batched", action="store_true",
                     help="measure each generation's new genes in one submission (graph chain)")
+    ap.add_argument("--concurrent", action="store_true",
+                    help="run the application's independent parts at once (eager runs, OFL_RUN_CONCURRENT)")
     ap.add_argument("--deadline-factor", type=float, default=0.0)
     ap.add_argument("--timeout", type=float, default=0.0, help="seconds; cut off any run longer than this (0 = none)")
     ap.add_argument("--progress", action="store_true", help="one line per generation on stderr")
@@ -59,7 +62,8 @@ def main(argv=None):
     app = App(src, seed=args.seed)
     bufs = app.alloc_device_buffers("cuda:0")
     policy = {"resident": RESIDENT, "per_region": PER_REGION, "sections": SECTIONS}[args.policy]
-    flags = (GRAPH if args.graph else 0) | (BATCHED if args.batched else 0) | (PROGRESS if args.progress else 0)
+    flags = (GRAPH if args.graph else 0) | (BATCHED if args.batched else 0) | (PROGRESS if args.progress else 0) | \
+        (CONCURRENT if args.concurrent else 0)
     params = ga_params(M=args.M, T=args.T, Pc=args.Pc, Pm=args.Pm, p=args.p, seed=args.ga_seed, reps=args.reps,
                        warmup=args.warmup, policy=policy, flags=flags, deadline_factor=args.deadline_factor,
                        timeout_s=args.timeout, cache_path=args.log)

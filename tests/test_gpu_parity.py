@@ -185,6 +185,23 @@ def test_gemm_split_shapes(prec, M, N, K, tile, monkeypatch):
     _run_and_compare(doc, [[1], [0]], inputs={"A": A, "B": B})
 
 
+@pytest.mark.parametrize("tile", ["128", "256"])
+def test_gemm_nt_padded_row_layout(tile, monkeypatch):
+    # the products with their slabs staged in padded rows (the alternative LDS
+    # layout, a knob) on ragged shapes, each form against the oracle
+    monkeypatch.setenv("OFL_GEMM_NT_LAYOUT", "0")
+    monkeypatch.setenv("OFL_GEMM_NT_TILE", tile)
+    M, N, K = 300, 270, 140
+    A = OC.init_uniform(M * K, 23, 0).reshape(M, K)
+    B = OC.init_uniform(K * N, 23, 1).reshape(K, N)
+    for prec in SPLIT:
+        say("case nt padded layout", tile, prec)
+        _run_and_compare(appgen.gemm_app(M, N, K, prec=prec), [[1]], inputs={"A": A, "B": B})
+    say("case nt padded layout", tile, "bf16")
+    _run_and_compare(appgen.gemm_app(M, N, K, op="gemm_bf16"), [[1]],
+                     inputs={"A": OC.cast_bf16(A), "B": OC.cast_bf16(B)})
+
+
 @pytest.mark.parametrize("prec", SPLIT)
 def test_gemm_split_signed_wide_range(prec):
     M, N, K = 200, 150, 333
@@ -561,21 +578,26 @@ def test_search_from_c_source(tmp_path, capsys):
 
 
 def test_batched_deadline_cuts_host_nests():
-    # in one batched submission the limit stops host nests at the limit: the
-    # all-CPU gene of the medium application (seconds of serial work) ends as
-    # a TIMEOUT after about the limit per run, not after its full run time
+    # with a limit, batched measurement stops host work at the limit: the
+    # product left on the CPU (gene bit 1; ~1 s of serial work) is cut inside
+    # the submitted graph; the all-CPU gene of the medium application, whose
+    # sweeps sit in the repeated block, takes its warm-up eagerly and ends
+    # there -- both TIMEOUTs after about the limit, not after their full run
     import time
     doc = workloads.app_doc("medium")
     app = ofl.App(json.dumps(doc))
     bufs = app.alloc_device_buffers()
-    say("case batched deadline, medium all-CPU and all-GPU genes")
+    say("case batched deadline, medium all-CPU, all-GPU and CPU-product genes")
+    cpu_gemm = [1] * 10
+    cpu_gemm[1] = 0
     app.eval_population([[1] * 10], bufs, reps=1, warmup=0, flags=ofl.BATCHED)   # capture, warm
     t0 = time.perf_counter()
-    t, s = app.eval_population([[0] * 10, [1] * 10], bufs, reps=3, warmup=1, flags=ofl.BATCHED, deadline_s=0.05)
+    t, s = app.eval_population([[0] * 10, [1] * 10, cpu_gemm], bufs, reps=3, warmup=1, flags=ofl.BATCHED,
+                               deadline_s=0.05)
     wall = time.perf_counter() - t0
-    assert list(s) == [ofl.ST_TIMEOUT, ofl.ST_OK]
-    assert t[0] == 0.05 and 0 < t[1] < 0.05
-    assert wall < 2.0, wall   # four runs of ~1.5 s each without the cut
+    assert list(s) == [ofl.ST_TIMEOUT, ofl.ST_OK, ofl.ST_TIMEOUT]
+    assert t[0] == 0.05 and 0 < t[1] < 0.05 and t[2] == 0.05
+    assert wall < 2.0, wall   # eight runs of ~1-1.5 s each without the cut
     # later runs are not limited: the all-CPU gene completes and matches the oracle
     o = ir.load(doc)
     o32, o64 = parity.oracle_outputs(o, 1)
@@ -891,6 +913,41 @@ def test_output_check_flags_a_less_accurate_product():
     for gen_pop, gen_st in zip(res["pops"], res["status"]):
         for g, st_ in zip(gen_pop, gen_st):
             assert st_ == (ofl.ST_MISMATCH if g[1] == 1 else ofl.ST_OK), (list(g), st_)
+
+
+# ---------------------------------------------------------------- concurrent components
+@pytest.mark.parametrize("name,params", [("large", workloads.SMALL_LARGE), ("medium", workloads.SMALL_MEDIUM)])
+def test_components_concurrent_match_oracle(name, params):
+    # OFL_RUN_CONCURRENT: the matrix nests and the grid nests share no buffer
+    # and run at once, each part on its own stream and host thread; results,
+    # copies and byte counts are those of the sequential run, for genes that
+    # leave nests of either part (and both parts' host nests) on the CPU
+    doc = workloads.app_doc(name, **params)
+    app = ofl.App(json.dumps(doc), seed=1)
+    a = app.gene_len
+    rng = random.Random(11)
+    genes = [[1] * a, [0] * a] + [[rng.randint(0, 1) for _ in range(a)] for _ in range(4)]
+    o = ir.load(doc)
+    o32, o64 = parity.oracle_outputs(o, 1)
+    bufs = app.alloc_device_buffers()
+    for pol in (ofl.SECTIONS, ofl.RESIDENT):
+        for fl in (ofl.CONCURRENT, ofl.CONCURRENT | ofl.PRESTAGED | ofl.KEEP_OUTPUTS):
+            for g in genes:
+                say("case concurrent", name, "gene", g, "policy", pol, "flags", fl)
+                st = app.run_pattern(g, bufs, policy=pol, flags=fl)
+                assert st["status"] == ofl.ST_OK
+                assert (st["bytes_h2d"], st["bytes_d2h"], st["n_copies"]) == app.plan_transfers(g, pol, fl)
+                bad = parity.compare(o, app.read_all(), o32, o64)
+                assert not bad, (g, pol, fl, bad)
+    # kernel timing across both streams: every sweep and product timed
+    app.set_kernel_timing(True)
+    app.run_pattern([1] * a, bufs, policy=ofl.SECTIONS, flags=ofl.CONCURRENT)
+    app.set_kernel_timing(False)
+    assert app.kernel_stats("stencil19")[0] == doc["params"]["SWEEPS"]
+    assert app.kernel_stats("gemm")[0] >= 1
+    # a deadline cuts the concurrent run (the all-CPU gene takes far longer)
+    st = app.run_pattern([0] * a, bufs, flags=ofl.CONCURRENT, deadline_s=1e-6, check=False)
+    assert st["status"] == ofl.ST_TIMEOUT
 
 
 # ---------------------------------------------------------------- the sweep as a call
