@@ -281,6 +281,154 @@ __global__ __launch_bounds__(WGM * WGN * 64, MINB) void k_gemm_nt(const T *__res
             }
 }
 
+// The k-contiguous product with the operand slabs loaded straight into LDS
+// (buffer loads with the LDS bit: each lane's 16 bytes land at the
+// instruction's LDS base + 16 lane), for 256 x 256 blocks of 8 waves (2 x 4,
+// each 128 x 64).  128-byte slabs (whole 128-byte lines per row, one request
+// to L2 per line) in two LDS stages of 64 KB; the loads hold no registers.
+// A slab holds two half-slabs of 64 bytes, each one MFMA k-step for bf16
+// (lane group g supplies chunk 4h + g of half h) and two for fp8 (the low
+// and the high 8 bytes of that chunk).  The loads of slab kt + 1 go out after
+// the barrier inside step kt - 1 (once every wave has read slab kt - 1) and
+// are waited for at the barrier inside step kt, a lead of one slab.  Step kt:
+// read half 1 of slab kt, MFMAs of half 0, barrier, read half 0 of slab
+// kt + 1, MFMAs of half 1, so that LDS reads always overlap MFMAs of the
+// other register set.  A wave waits for its own loads by counting its
+// outstanding memory operations; the barrier then makes every wave's part
+// visible.  Stage layout: row R at R * 128, chunk c in slot c ^ (R & 7); one
+// load instruction fills 8 rows (8 lanes per row).
+//
+// Measured on gfx950 against the register-staged form (bf16 8192^3 product
+// 1.02 -> 0.79 ms): a form with 64-byte slabs in four stages (a lead of three
+// half-slabs) came between the two; it sends 64-byte requests to L2, twice as
+// many as here.
+constexpr int kRawBuffer = 0x00020000;   // raw buffer resource, gfx9 family
+constexpr int kDmaThreads = 512;
+
+// s_waitcnt immediates (gfx9 encoding): no vector memory operation of the
+// wave outstanding; no LDS read outstanding
+constexpr int kVm0 = (7 << 4) | (15 << 8);
+constexpr int kLgkm0 = 15 | (3 << 14) | (7 << 4);
+
+template <typename T, bool SCALED>
+__global__ __launch_bounds__(kDmaThreads, 1) void k_gemm_nt_dma(const T *__restrict__ A, const T *__restrict__ B,
+                                                                float *__restrict__ C, int M, int N, int Kp,
+                                                                const float *__restrict__ sa,
+                                                                const float *__restrict__ sb) {
+    constexpr int BM = 256, BN = 256, WGM = 2, WGN = 4, WM = BM / WGM, WN = BN / WGN, TM = WM / 16, TN = WN / 16;
+    constexpr int SL = 128;
+    constexpr int STAGE = (BM + BN) * SL;
+    constexpr int PER_WAVE = BM / 8 / (kDmaThreads / 64);   // load instructions per wave per operand
+    __shared__ __attribute__((aligned(1024))) unsigned char lds[2 * STAGE];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave / WGN, wn = wave % WGN;
+    int tm, tn;
+    tile_of(blockIdx.x, (M + BM - 1) / BM, (N + BN - 1) / BN, tm, tn);
+    const int row_bytes = Kp * (int)sizeof(T);
+    const int nslab = row_bytes / SL;
+    const unsigned char *Ab = reinterpret_cast<const unsigned char *>(A) + (size_t)tm * BM * row_bytes;
+    const unsigned char *Bb = reinterpret_cast<const unsigned char *>(B) + (size_t)tn * BN * row_bytes;
+    const __amdgpu_buffer_rsrc_t ra = __builtin_amdgcn_make_buffer_rsrc((void *)Ab, (short)0, BM * row_bytes, kRawBuffer);
+    const __amdgpu_buffer_rsrc_t rb = __builtin_amdgcn_make_buffer_rsrc((void *)Bb, (short)0, BN * row_bytes, kRawBuffer);
+    // row lane / 8 of the instruction's 8, the chunk that belongs in slot lane % 8
+    const int vo = (lane >> 3) * row_bytes + 16 * ((lane & 7) ^ ((lane >> 3) & 7));
+    auto issue = [&](int slab) {
+        unsigned char *st = lds + (slab & 1) * STAGE;
+#pragma unroll
+        for (int h = 0; h < PER_WAVE; ++h) {
+            const int u = PER_WAVE * wave + h;   // rows [8u, 8u + 8) of A and of B
+            const int off = vo + u * 8 * row_bytes + slab * SL;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (__attribute__((address_space(3))) void *)(st + u * 1024), 16,
+                                                     off, 0, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rb, (__attribute__((address_space(3))) void *)(st + BM * SL + u * 1024), 16, off, 0, 0, 0);
+        }
+        asm volatile("" ::: "memory");
+    };
+    // this wave's loads complete and its LDS reads done (waits as builtins,
+    // so the compiler knows that nothing issued before them is pending), then
+    // the block barrier
+    auto wait_barrier = [&]() {
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_waitcnt(kVm0);
+        __builtin_amdgcn_s_waitcnt(kLgkm0);
+        asm volatile("s_barrier" ::: "memory");
+    };
+    const int r = lane & 15, g = lane >> 4;
+    auto read = [&](int slab, int h, u32x4(&af)[TM], u32x4(&bf)[TN]) {
+        const unsigned char *st = lds + (slab & 1) * STAGE;
+        const int lo = r * SL + 16 * ((4 * h + g) ^ (r & 7));
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+            af[i] = *reinterpret_cast<const u32x4 *>(st + (wm * WM + i * 16) * SL + lo);
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+            bf[j] = *reinterpret_cast<const u32x4 *>(st + BM * SL + (wn * WN + j * 16) * SL + lo);
+    };
+
+    floatx4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    auto mfma = [&](const u32x4(&af)[TM], const u32x4(&bf)[TN]) {
+        if constexpr (sizeof(T) == 2) {
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[i]),
+                                                                        __builtin_bit_cast(bf16x8, bf[j]), acc[i][j],
+                                                                        0, 0, 0);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) {
+                        const fp8x8 a8 = (fp8x8)(((unsigned long)af[i][2 * q + 1] << 32) | af[i][2 * q]);
+                        const fp8x8 b8 = (fp8x8)(((unsigned long)bf[j][2 * q + 1] << 32) | bf[j][2 * q]);
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a8, b8, acc[i][j], 0, 0, 0);
+                    }
+        }
+    };
+
+    u32x4 fa[2][TM], fb[2][TN];
+    issue(0);
+    wait_barrier();
+    if (nslab > 1) issue(1);
+    read(0, 0, fa[0], fb[0]);
+    for (int kt = 0; kt + 1 < nslab; ++kt) {
+        read(kt, 1, fa[1], fb[1]);
+        mfma(fa[0], fb[0]);
+        // slab kt + 1 has landed and every wave has read slab kt: slab kt + 2
+        // takes its stage
+        wait_barrier();
+        if (kt + 2 < nslab) issue(kt + 2);
+        read(kt + 1, 0, fa[0], fb[0]);
+        mfma(fa[1], fb[1]);
+    }
+    read(nslab - 1, 1, fa[1], fb[1]);
+    mfma(fa[0], fb[0]);
+    __builtin_amdgcn_s_waitcnt(kLgkm0);
+    mfma(fa[1], fb[1]);
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = tm * BM + wm * WM + i * 16 + 4 * g + e, col = tn * BN + wn * WN + j * 16 + r;
+                if (row < M && col < N) {
+                    float v = acc[i][j][e];
+                    if (SCALED) v = v * (sa[row] * sb[col]);
+                    C[(size_t)row * N + col] = v;
+                }
+            }
+}
+
 template <int BM, int BN, int BK>
 hipError_t launch_f32(const float *A, const float *B, float *C, int M, int N, int K, hipStream_t s) {
     const unsigned tiles = (unsigned)(((M + BM - 1) / BM) * ((N + BN - 1) / BN));
@@ -360,6 +508,13 @@ hipError_t launch_nt(const NtLayout &L, const void *A, const void *B, float *C, 
     const bool cm = !(lay && lay[0] == '0');
     const T *a = static_cast<const T *>(A), *b = static_cast<const T *>(B);
     const int m = (int)M, n = (int)N, kp = (int)L.Kp;
+    // 256 x 256 tiles: the form with LDS-direct loads, unless knob
+    // OFL_GEMM_NT_FORM=reg asks for the register-staged one or a tile's panel
+    // (256 rows) exceeds the 31-bit offsets of a buffer load
+    const char *form = std::getenv("OFL_GEMM_NT_FORM");
+    const bool dma = !(form && form[0] == 'r') && 256 * L.Kp * (int64_t)sizeof(T) < ((int64_t)1 << 31);
+    if (L.tile == 256 && dma)
+        return launch((k_gemm_nt_dma<T, SCALED>), dim3(tiles), dim3(kDmaThreads), 0, s, a, b, C, m, n, kp, sa, sb);
     if (L.tile == 256)
         return cm ? launch((k_gemm_nt<T, 256, 256, 2, 4, 1, 1, 1, SCALED>), dim3(tiles), dim3(512), 0, s, a, b, C, m,
                            n, kp, sa, sb)

@@ -148,12 +148,18 @@ def test_gemm_identity_and_rank1_exact():
         assert np.array_equal(app.read_buffer("C"), (N * np.outer(u, v)).astype(np.float32))
 
 
-# tile "256": the 8-wave 256 x 256 form forced (chosen by size from 256 tiles up)
+# tile "256": the 8-wave 256 x 256 form forced (chosen by size from 256 tiles
+# up; operands loaded straight into LDS), "256reg": that tile with
+# register-staged loads
 @pytest.mark.parametrize("M,N,K,tile", [(16, 16, 32, None), (100, 70, 45, None), (512, 512, 512, None),
-                                        (100, 70, 45, "256"), (512, 512, 512, "256"), (300, 600, 130, "256")])
+                                        (100, 70, 45, "256"), (512, 512, 512, "256"), (300, 600, 130, "256"),
+                                        (300, 600, 130, "256reg"), (520, 260, 700, "256"),
+                                        (256, 256, 64, "256")])
 def test_gemm_bf16_shapes(M, N, K, tile, monkeypatch):
     if tile:
-        monkeypatch.setenv("OFL_GEMM_NT_TILE", tile)
+        monkeypatch.setenv("OFL_GEMM_NT_TILE", "256")
+        if tile.endswith("reg"):
+            monkeypatch.setenv("OFL_GEMM_NT_FORM", "reg")
     doc = appgen.gemm_app(M, N, K, op="gemm_bf16")
     A = OC.cast_bf16(OC.init_uniform(M * K, 4, 0).reshape(M, K))
     B = OC.cast_bf16(OC.init_uniform(K * N, 4, 1).reshape(K, N))
@@ -191,6 +197,7 @@ def test_gemm_nt_padded_row_layout(tile, monkeypatch):
     # layout, a knob) on ragged shapes, each form against the oracle
     monkeypatch.setenv("OFL_GEMM_NT_LAYOUT", "0")
     monkeypatch.setenv("OFL_GEMM_NT_TILE", tile)
+    monkeypatch.setenv("OFL_GEMM_NT_FORM", "reg")
     M, N, K = 300, 270, 140
     A = OC.init_uniform(M * K, 23, 0).reshape(M, K)
     B = OC.init_uniform(K * N, 23, 1).reshape(K, N)
@@ -742,12 +749,17 @@ def test_sections_policy_random_genes(name, params):
                      flags_list=(0, ofl.PRESTAGED | ofl.KEEP_OUTPUTS, ofl.GRAPH | ofl.PRESTAGED))
 
 
-@pytest.mark.parametrize("op,prec", [("gemm", "bf16x3"), ("gemm", "fp8x2"), ("gemm_bf16", None)])
-def test_gemm_nt_256_tiles_ragged_sampled(op, prec, monkeypatch):
+@pytest.mark.parametrize("op,prec,form", [("gemm", "bf16x3", None), ("gemm", "bf16x3", "reg"), ("gemm", "fp8x2", None),
+                                          ("gemm", "fp8x2", "reg"), ("gemm_bf16", None, None),
+                                          ("gemm_bf16", None, "reg")])
+def test_gemm_nt_256_tiles_ragged_sampled(op, prec, form, monkeypatch):
     # the 256 x 256 tiles (8 waves; chosen by size from 256 tiles up, forced
-    # here); ragged edges exercise the zero padding; sampled rows (and the
-    # ragged last rows) against the oracle
+    # here; operands loaded straight into LDS unless form "reg");
+    # ragged edges exercise the zero padding; sampled rows (and the ragged
+    # last rows) against the oracle
     monkeypatch.setenv("OFL_GEMM_NT_TILE", "256")
+    if form:
+        monkeypatch.setenv("OFL_GEMM_NT_FORM", form)
     M, N, K = 2100, 2060, 300
     app = ofl.App(json.dumps(appgen.gemm_app(M, N, K, op=op, prec=prec)))
     A = OC.init_uniform(M * K, 31, 0).reshape(M, K)
