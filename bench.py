@@ -52,6 +52,10 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def nan_none(x, nd=3):
+    return None if x != x else round(x, nd)
+
+
 def stencil_bytes(I, J, K):
     # read every element of p once, write every interior element of q once
     return 4 * I * J * K + 4 * (I - 2) * (J - 2) * (K - 2)
@@ -165,14 +169,17 @@ def run_large(args):
     app.set_kernel_timing(False)
     live = kernel_table(app, list(work))
     # the paper's protocol (context): set-up content copied in over PCIe and
-    # outputs copied out, inside the timed region
-    pcie = sorted(app.run_pattern(gene, bufs, policy=policy, flags=0)["t_total_s"] for _ in range(3))
-    # the same runs with the application's independent parts (the matrix
-    # nests, the grid nests, the generator) on streams of their own
-    conc = sorted(app.run_pattern(gene, bufs, policy=policy, flags=flags | ofl.CONCURRENT)["t_total_s"]
-                  for _ in range(3))
-    pcie_conc = sorted(app.run_pattern(gene, bufs, policy=policy, flags=ofl.CONCURRENT)["t_total_s"]
-                       for _ in range(3))
+    # outputs copied out, inside the timed region; then both protocols with
+    # the application's independent parts (the matrix nests, the grid nests,
+    # the generator) on streams of their own.  Left out under --large-only,
+    # so that a profile of it holds the resident steps alone.
+    pcie = conc = pcie_conc = [float("nan")] * 3
+    if not args.large_only:
+        pcie = sorted(app.run_pattern(gene, bufs, policy=policy, flags=0)["t_total_s"] for _ in range(3))
+        conc = sorted(app.run_pattern(gene, bufs, policy=policy, flags=flags | ofl.CONCURRENT)["t_total_s"]
+                      for _ in range(3))
+        pcie_conc = sorted(app.run_pattern(gene, bufs, policy=policy, flags=ofl.CONCURRENT)["t_total_s"]
+                           for _ in range(3))
     internal.sort()
     return {"params": P, "wall": wall, "internal_median_s": internal[len(internal) // 2], "pcie_median_s": pcie[1],
             "concurrent_median_s": conc[1], "pcie_concurrent_median_s": pcie_conc[1],
@@ -472,7 +479,8 @@ def main():
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the medium, element-wise, precision, batching and population lines")
     ap.add_argument("--large-only", action="store_true",
-                    help="only the large application's timed steps (for profiling)")
+                    help="only the large application's resident steps (for profiling): no PCIe or "
+                         "concurrent runs, no extra lines, no CPU baseline")
     ap.add_argument("--extras-only", action="store_true", help="only the extra lines (for profiling)")
     ap.add_argument("--only", choices=["medium", "kernels", "precision", "batch", "population"], default=None,
                     help="only one extra line (for profiling)")
@@ -530,10 +538,10 @@ def main():
                                     "copy and of each product" % LIVE_STRIDE,
                        "inputs": "resident in HBM at the start of the timed region; outputs left in HBM"},
             "app_time_ms": round(1e3 * r["internal_median_s"], 3),
-            "app_time_pcie_ms": round(1e3 * r["pcie_median_s"], 3),
-            "pcie_runs_per_s": round(1.0 / r["pcie_median_s"], 3),
-            "app_time_concurrent_ms": round(1e3 * r["concurrent_median_s"], 3),
-            "app_time_pcie_concurrent_ms": round(1e3 * r["pcie_concurrent_median_s"], 3),
+            "app_time_pcie_ms": nan_none(1e3 * r["pcie_median_s"]),
+            "pcie_runs_per_s": nan_none(1.0 / r["pcie_median_s"]),
+            "app_time_concurrent_ms": nan_none(1e3 * r["concurrent_median_s"]),
+            "app_time_pcie_concurrent_ms": nan_none(1e3 * r["pcie_concurrent_median_s"]),
             "plan_bytes": {"pcie_h2d_d2h_copies": r["plan_pcie"], "resident_h2d_d2h_copies": r["plan_resident"]},
             "roofline": roofline,
             "roofline_kernels": roofs,

@@ -62,6 +62,7 @@ __global__ __launch_bounds__(kThreads) void k_gemm_f32(const float *__restrict__
 // lane takes a contiguous 32-byte run of the slab for its lane group.
 typedef long fp8x8;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 // Block shape BM x BN, WGM x WGN waves (each a (BM/WGM) x (BN/WGN) tile of
 // 16 x 16 MFMA tiles), MINB blocks per CU, NSET register sets of staged
 // slabs: with two, the slab two ahead is in flight from global memory while
@@ -287,12 +288,12 @@ __global__ __launch_bounds__(WGM * WGN * 64, MINB) void k_gemm_nt(const T *__res
 // each 128 x 64).  128-byte slabs (whole 128-byte lines per row, one request
 // to L2 per line) in two LDS stages of 64 KB; the loads hold no registers.
 // A slab holds two half-slabs of 64 bytes, each one MFMA k-step for bf16
-// (lane group g supplies chunk 4h + g of half h) and two for fp8 (the low
-// and the high 8 bytes of that chunk).  The loads of slab kt + 1 go out after
+// (lane group g supplies chunk 4h + g of half h); for fp8 the whole slab is
+// one k-step of the 128-deep MFMA.  The loads of slab kt + 1 go out after
 // the barrier inside step kt - 1 (once every wave has read slab kt - 1) and
-// are waited for at the barrier inside step kt, a lead of one slab.  Step kt:
-// read half 1 of slab kt, MFMAs of half 0, barrier, read half 0 of slab
-// kt + 1, MFMAs of half 1, so that LDS reads always overlap MFMAs of the
+// are waited for at the barrier inside step kt, a lead of one slab.  bf16
+// step kt: read half 1 of slab kt, MFMAs of half 0, barrier, read half 0 of
+// slab kt + 1, MFMAs of half 1, so that LDS reads always overlap MFMAs of the
 // other register set.  A wave waits for its own loads by counting its
 // outstanding memory operations; the barrier then makes every wave's part
 // visible.  Stage layout: row R at R * 128, chunk c in slot c ^ (R & 7); one
@@ -372,48 +373,66 @@ __global__ __launch_bounds__(kDmaThreads, 1) void k_gemm_nt_dma(const T *__restr
     for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    // bf16: one half-slab per MFMA k-step
     auto mfma = [&](const u32x4(&af)[TM], const u32x4(&bf)[TN]) {
-        if constexpr (sizeof(T) == 2) {
 #pragma unroll
-            for (int i = 0; i < TM; ++i)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int j = 0; j < TN; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[i]),
-                                                                        __builtin_bit_cast(bf16x8, bf[j]), acc[i][j],
-                                                                        0, 0, 0);
-        } else {
+            for (int j = 0; j < TN; ++j)
+                acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, af[i]),
+                                                                    __builtin_bit_cast(bf16x8, bf[j]), acc[i][j], 0, 0,
+                                                                    0);
+    };
+    // fp8: the whole slab in one MFMA k-step of 128 (v_mfma_f32_16x16x128_f8f6f4,
+    // e4m3 x e4m3, no block scales): lane group g supplies chunk g of each
+    // half, 32 bytes
+    auto mfma8 = [&](const u32x4(&a0)[TM], const u32x4(&a1)[TM], const u32x4(&b0)[TN], const u32x4(&b1)[TN]) {
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
+        for (int i = 0; i < TM; ++i)
 #pragma unroll
-                for (int i = 0; i < TM; ++i)
-#pragma unroll
-                    for (int j = 0; j < TN; ++j) {
-                        const fp8x8 a8 = (fp8x8)(((unsigned long)af[i][2 * q + 1] << 32) | af[i][2 * q]);
-                        const fp8x8 b8 = (fp8x8)(((unsigned long)bf[j][2 * q + 1] << 32) | bf[j][2 * q]);
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a8, b8, acc[i][j], 0, 0, 0);
-                    }
-        }
+            for (int j = 0; j < TN; ++j) {
+                const i32x8 a = {(int)a0[i][0], (int)a0[i][1], (int)a0[i][2], (int)a0[i][3],
+                                 (int)a1[i][0], (int)a1[i][1], (int)a1[i][2], (int)a1[i][3]};
+                const i32x8 b = {(int)b0[j][0], (int)b0[j][1], (int)b0[j][2], (int)b0[j][3],
+                                 (int)b1[j][0], (int)b1[j][1], (int)b1[j][2], (int)b1[j][3]};
+                acc[i][j] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc[i][j], 0, 0, 0, 0, 0, 0);
+            }
     };
 
     u32x4 fa[2][TM], fb[2][TN];
-    issue(0);
-    wait_barrier();
-    if (nslab > 1) issue(1);
-    read(0, 0, fa[0], fb[0]);
-    for (int kt = 0; kt + 1 < nslab; ++kt) {
-        read(kt, 1, fa[1], fb[1]);
-        mfma(fa[0], fb[0]);
-        // slab kt + 1 has landed and every wave has read slab kt: slab kt + 2
-        // takes its stage
+    if constexpr (sizeof(T) == 2) {
+        issue(0);
         wait_barrier();
-        if (kt + 2 < nslab) issue(kt + 2);
-        read(kt + 1, 0, fa[0], fb[0]);
+        if (nslab > 1) issue(1);
+        read(0, 0, fa[0], fb[0]);
+        for (int kt = 0; kt + 1 < nslab; ++kt) {
+            read(kt, 1, fa[1], fb[1]);
+            mfma(fa[0], fb[0]);
+            // slab kt + 1 has landed and every wave has read slab kt: slab
+            // kt + 2 takes its stage
+            wait_barrier();
+            if (kt + 2 < nslab) issue(kt + 2);
+            read(kt + 1, 0, fa[0], fb[0]);
+            mfma(fa[1], fb[1]);
+        }
+        read(nslab - 1, 1, fa[1], fb[1]);
+        mfma(fa[0], fb[0]);
+        __builtin_amdgcn_s_waitcnt(kLgkm0);
         mfma(fa[1], fb[1]);
+    } else {
+        // fp8: one MFMA step needs both halves of a slab, so a step reads the
+        // whole slab and then multiplies it (the LDS reads of one wave overlap
+        // the MFMAs of the other wave on its SIMD); slab kt + 1 goes out once
+        // every wave has read slab kt - 1
+        issue(0);
+        for (int kt = 0; kt < nslab; ++kt) {
+            wait_barrier();
+            if (kt + 1 < nslab) issue(kt + 1);
+            read(kt, 0, fa[0], fb[0]);
+            read(kt, 1, fa[1], fb[1]);
+            mfma8(fa[0], fa[1], fb[0], fb[1]);
+        }
     }
-    read(nslab - 1, 1, fa[1], fb[1]);
-    mfma(fa[0], fb[0]);
-    __builtin_amdgcn_s_waitcnt(kLgkm0);
-    mfma(fa[1], fb[1]);
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
