@@ -107,11 +107,13 @@ def large_work(P):
     return {"stencil19": (stencil_bytes(I, J, K), "GB/s", "hbm", HBM_PEAK_GBS),
             "copy_interior": (copy_interior_bytes(I, J, K), "GB/s", "hbm", HBM_PEAK_GBS),
             "gemm": (2.0 * N ** 3, "TFLOP/s", "mfma", MFMA_PEAK_TFLOPS["f32"]),
-            "gemm_bf16": (2.0 * N ** 3, "TFLOP/s", "mfma", MFMA_PEAK_TFLOPS["bf16"])}
+            # the nest's span: B transposed to k-contiguous bf16, then the product
+            "gemm_bf16": (2.0 * N ** 3, "TFLOP/s", "mfma", MFMA_PEAK_TFLOPS["bf16"],
+                          "nest: B transpose pass + product kernel")}
 
 
 def roof_entry(kind, work, live, workload):
-    amount, unit, bound, peak = work
+    amount, unit, bound, peak = work[:4]
     secs = live["avg_us"] * 1e-6
     achieved = amount / secs / (1e9 if unit == "GB/s" else 1e12)
     traffic = measured_traffic(kind, workload) if unit == "GB/s" else None
@@ -120,6 +122,8 @@ def roof_entry(kind, work, live, workload):
            ("bytes_per_launch" if unit == "GB/s" else "flops_per_launch"): amount,
            "avg_launch_us": round(live["avg_us"], 3), "launches_timed": live["launches"],
            "total_ms_timed": round(live["total_ms"], 3)}
+    if len(work) > 4:
+        out["span"] = work[4]
     return out
 
 
