@@ -448,6 +448,119 @@ __global__ __launch_bounds__(kDmaThreads, 1) void k_gemm_nt_dma(const T *__restr
             }
 }
 
+// FP32 product with the slabs of A and B loaded straight into LDS, for
+// shapes of whole 128 x 128 tiles and whole 32-deep k slabs: 128 x 128 blocks
+// of 4 waves (64 x 64 each, v_mfma_f32_16x16x4f32), two LDS stages of 32 KB
+// (two blocks per CU), the loads of slab kt + 1 issued after the barrier of
+// step kt, once every wave has read slab kt - 1.  A slab of A: row R (128
+// bytes of k) at R * 128, its 16-byte chunk c in slot c ^ (R & 7); a slab of
+// B: k-row r (512 bytes of n) at r * 512, its chunk c in slot
+// c ^ (4 ((r >> 2) & 3)), so that the four lane groups of an operand read
+// (k-rows 4 apart, 64 bytes each) fall on four different 64-byte spans.
+// Lane group g of a k-step of 16 takes k = 4 g .. 4 g + 3 (as the
+// register-staged tile does).
+constexpr int kF32DmaThreads = 256;
+
+__global__ __launch_bounds__(kF32DmaThreads, 2) void k_gemm_f32_dma(const float *__restrict__ A,
+                                                                    const float *__restrict__ B,
+                                                                    float *__restrict__ C, int M, int N, int K) {
+    constexpr int BM = 128, BN = 128, BK = 32, WM = 64, WN = 64, TM = WM / 16, TN = WN / 16;
+    constexpr int A_STAGE = BM * BK * 4, STAGE = A_STAGE + BK * BN * 4;   // 16 KB + 16 KB
+    constexpr int PER_WAVE = A_STAGE / 1024 / (kF32DmaThreads / 64);     // load instructions per wave per operand
+    __shared__ __attribute__((aligned(1024))) unsigned char lds[2 * STAGE];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int wm = wave >> 1, wn = wave & 1;
+    int tm, tn;
+    tile_of(blockIdx.x, M / BM, N / BN, tm, tn);
+    const int nslab = K / BK;
+    const unsigned char *Ab = reinterpret_cast<const unsigned char *>(A + (size_t)tm * BM * K);
+    const unsigned char *Bb = reinterpret_cast<const unsigned char *>(B + (size_t)tn * BN);
+    const __amdgpu_buffer_rsrc_t ra =
+        __builtin_amdgcn_make_buffer_rsrc((void *)Ab, (short)0, BM * K * 4, kRawBuffer);
+    const __amdgpu_buffer_rsrc_t rb =
+        __builtin_amdgcn_make_buffer_rsrc((void *)Bb, (short)0, (K - 1) * N * 4 + BN * 4, kRawBuffer);
+    // A: instruction u fills rows 8u .. 8u + 7 (8 lanes per row); B: k-rows
+    // 2u, 2u + 1 (32 lanes per row)
+    const int ra_row = lane >> 3, ra_ch = (lane & 7) ^ ((lane >> 3) & 7);
+    const int va = ra_row * K * 4 + 16 * ra_ch;
+    const int rb_row = lane >> 5;
+    auto issue = [&](int slab) {
+        unsigned char *st = lds + (slab & 1) * STAGE;
+#pragma unroll
+        for (int h = 0; h < PER_WAVE; ++h) {
+            const int u = PER_WAVE * wave + h;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(ra, (__attribute__((address_space(3))) void *)(st + u * 1024), 16,
+                                                     va + u * 8 * K * 4 + slab * BK * 4, 0, 0, 0);
+            const int kr = 2 * u + rb_row;                               // k-row of the slab
+            const int ch = (lane & 31) ^ (4 * ((kr >> 2) & 3));
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rb, (__attribute__((address_space(3))) void *)(st + A_STAGE + u * 1024), 16,
+                (slab * BK + kr) * N * 4 + 16 * ch, 0, 0, 0);
+        }
+        asm volatile("" ::: "memory");
+    };
+    auto wait_barrier = [&]() {
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_s_waitcnt(kVm0);
+        __builtin_amdgcn_s_waitcnt(kLgkm0);
+        asm volatile("s_barrier" ::: "memory");
+    };
+    const int r = lane & 15, g = lane >> 4;
+    floatx4 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+    auto compute = [&](int slab) {
+        const unsigned char *st = lds + (slab & 1) * STAGE;
+#pragma unroll
+        for (int ks = 0; ks < BK; ks += 16) {
+            const int c = ks / 4 + g;                                    // this lane group's chunk of A
+            floatx4 af[TM];
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+                af[i] = *reinterpret_cast<const floatx4 *>(st + (wm * WM + i * 16 + r) * 128 + 16 * (c ^ (r & 7)));
+            const int x = 4 * ((ks / 4 + g) & 3);                        // B swizzle of k-rows ks + 4g + s
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int kr = ks + 4 * g + s4;
+                float bf[TN];
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const int n = wn * WN + j * 16 + r;
+                    bf[j] = *reinterpret_cast<const float *>(st + A_STAGE + kr * 512 + 16 * ((n >> 2) ^ x) +
+                                                             4 * (n & 3));
+                }
+#pragma unroll
+                for (int i = 0; i < TM; ++i) {
+                    const float a = af[i][s4];
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bf[j], acc[i][j], 0, 0, 0);
+                }
+            }
+        }
+    };
+    issue(0);
+    for (int kt = 0; kt < nslab; ++kt) {
+        // slab kt has landed and every wave has read slab kt - 1, so slab
+        // kt + 1 takes its stage
+        wait_barrier();
+        if (kt + 1 < nslab) issue(kt + 1);
+        compute(kt);
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int row = tm * BM + wm * WM + i * 16 + 4 * g + e, col = tn * BN + wn * WN + j * 16 + r;
+                C[(size_t)row * N + col] = acc[i][j][e];
+            }
+}
+
 template <int BM, int BN, int BK>
 hipError_t launch_f32(const float *A, const float *B, float *C, int M, int N, int K, hipStream_t s) {
     const unsigned tiles = (unsigned)(((M + BM - 1) / BM) * ((N + BN - 1) / BN));
@@ -464,8 +577,19 @@ hipError_t gemm_f32(const float *A, const float *B, float *C, int64_t M, int64_t
     if (M <= 0 || N <= 0) return hipSuccess;
     if (K <= 0) return fill_zero(C, (uint64_t)M * N * sizeof(float), s);
     if (M > (1 << 30) || N > (1 << 30) || K > (1 << 30)) return hipErrorInvalidValue;
-    // large products: 128 x 128 tiles; smaller ones: 64 x 64 so the grid still covers the CUs
-    if ((M / 128) * (N / 128) >= 512) return launch_f32<128, 128, 32>(A, B, C, (int)M, (int)N, (int)K, s);
+    // large products: 128 x 128 tiles (with LDS-direct loads when the shape
+    // is whole tiles and slabs and the operands fit the 31-bit offsets of a
+    // buffer load, unless knob OFL_GEMM_F32_FORM=reg); smaller ones: 64 x 64
+    // so that the grid still covers the CUs
+    if ((M / 128) * (N / 128) >= 512) {
+        const char *form = std::getenv("OFL_GEMM_F32_FORM");
+        const bool dma = !(form && form[0] == 'r') && M % 128 == 0 && N % 128 == 0 && K % 32 == 0 &&
+                         128 * K * 4 < ((int64_t)1 << 31) && K * N * 4 < ((int64_t)1 << 31);
+        if (dma)
+            return launch(k_gemm_f32_dma, dim3((unsigned)((M / 128) * (N / 128))), dim3(kF32DmaThreads), 0, s, A, B,
+                          C, (int)M, (int)N, (int)K);
+        return launch_f32<128, 128, 32>(A, B, C, (int)M, (int)N, (int)K, s);
+    }
     return launch_f32<64, 64, 32>(A, B, C, (int)M, (int)N, (int)K, s);
 }
 

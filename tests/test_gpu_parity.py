@@ -128,6 +128,34 @@ def test_gemm_f32_large_sampled():
     del torch
 
 
+@pytest.mark.parametrize("M,N,K", [(2048, 4096, 160), (2049, 4096, 160), (2048, 4100, 96)])
+def test_gemm_f32_lds_direct_form(M, N, K, monkeypatch):
+    # products of 512 tiles of 128 x 128 and more take the LDS-direct form
+    # when the shape is whole tiles and 32-deep slabs (the first case), else
+    # the register-staged one; both sum each output in the same order, so
+    # the forms must agree bit for bit; sampled rows (and the ragged last
+    # rows) against the FP64 twin
+    A = OC.init_uniform(M * K, 13, 0).reshape(M, K)
+    B = OC.init_uniform(K * N, 13, 1).reshape(K, N)
+    out = {}
+    for form in (None, "reg"):
+        if form:
+            monkeypatch.setenv("OFL_GEMM_F32_FORM", form)
+        app = ofl.App(json.dumps(appgen.gemm_app(M, N, K)))
+        app.set_input("A", A)
+        app.set_input("B", B)
+        bufs = app.alloc_device_buffers()
+        say("case gemm f32 form", form, M, N, K)
+        app.run_pattern([1], bufs, flags=ofl.KEEP_OUTPUTS)
+        out[form] = app.read_buffer("C")
+        del app, bufs
+    assert np.array_equal(out[None].view(np.uint32), out["reg"].view(np.uint32))
+    rows = np.array(sorted(set(list(np.random.default_rng(3).choice(M, 8, replace=False)) + [0, M - 1])))
+    ref = OC.gemm_f64(np.ascontiguousarray(A[rows]), B)
+    err = np.max(np.abs(out[None][rows] - ref) / ref)
+    assert err < parity.REL_GEMM, err
+
+
 def test_gemm_identity_and_rank1_exact():
     for N in (64, 200, 1024):
         doc = appgen.gemm_app(N, N, N)
