@@ -128,7 +128,7 @@ def test_gemm_f32_large_sampled():
     del torch
 
 
-@pytest.mark.parametrize("M,N,K", [(2048, 4096, 160), (2049, 4096, 160), (2048, 4100, 96)])
+@pytest.mark.parametrize("M,N,K", [(2048, 4096, 160), (2048, 4096, 32), (2049, 4096, 160), (2048, 4100, 96)])
 def test_gemm_f32_lds_direct_form(M, N, K, monkeypatch):
     # products of 512 tiles of 128 x 128 and more take the LDS-direct form
     # when the shape is whole tiles and 32-deep slabs (the first case), else
