@@ -162,6 +162,33 @@ __global__ __launch_bounds__(kThreads) void k_split_bt(const void *__restrict__ 
     }
 }
 
+// The plain bf16 transpose of B (MODE 2) when K and N are whole 64-element
+// tiles: 16-byte loads of 8 columns and 16-byte stores of 8 k values (the
+// form above moves 2 bytes per lane); other shapes take the form above.
+__global__ __launch_bounds__(kThreads) void k_transpose_bf16(const unsigned short *__restrict__ B,
+                                                             unsigned short *__restrict__ Bt, int K, int N, int Kp) {
+    constexpr int P = kT + 8;   // row pitch in elements (16-byte aligned rows)
+    __shared__ __attribute__((aligned(16))) unsigned short tile[kT][P];
+    const int k0 = blockIdx.x * kT, j0 = blockIdx.y * kT;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int c = tid + u * kThreads, r = c >> 3, q = c & 7;   // k-row r, columns 8q .. 8q + 7
+        *reinterpret_cast<uint4 *>(&tile[r][8 * q]) =
+            *reinterpret_cast<const uint4 *>(B + (size_t)(k0 + r) * N + j0 + 8 * q);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int c = tid + u * kThreads, j = c >> 3, q = c & 7;   // output row j, k values 8q .. 8q + 7
+        unsigned w[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+            w[t] = (unsigned)tile[8 * q + 2 * t][j] | ((unsigned)tile[8 * q + 2 * t + 1][j] << 16);
+        *reinterpret_cast<uint4 *>(Bt + (size_t)(j0 + j) * Kp + k0 + 8 * q) = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+}
+
 // Row scales of A: one wave per row, max |A[i][k]| -> s_i; inv_s_i.
 __global__ __launch_bounds__(kThreads) void k_row_scale(const float *__restrict__ A, float *__restrict__ s,
                                                         float *__restrict__ inv, int M, int K) {
@@ -225,6 +252,9 @@ hipError_t split_bt(const void *B, void *Bt, const float *sb, int K, int N, int 
     if (grid.y > 65535) return hipErrorInvalidValue;
     if (mode == 0) return launch((k_split_bt<0>), grid, dim3(kThreads), 0, s, B, Bt, sb, K, N, Kp);
     if (mode == 1) return launch((k_split_bt<1>), grid, dim3(kThreads), 0, s, B, Bt, sb, K, N, Kp);
+    if (K % kT == 0 && N % kT == 0 && Kp % 8 == 0)
+        return launch(k_transpose_bf16, grid, dim3(kThreads), 0, s, static_cast<const unsigned short *>(B),
+                      static_cast<unsigned short *>(Bt), K, N, Kp);
     return launch((k_split_bt<2>), grid, dim3(kThreads), 0, s, B, Bt, sb, K, N, Kp);
 }
 
