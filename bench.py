@@ -34,7 +34,7 @@ sys.path.insert(0, ROOT)
 METRIC = "app time & speedup vs 1-core oracle; stencil GB/s, GEMM MFMA % of peak"
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}
-LIVE_STRIDE = 5
+LIVE_STRIDE = 10
 CSRC = os.path.join(ROOT, "paper_1806_01430_amd", "csrc")
 # sources each kernel kind is compiled from: a profile's byte counts hold only
 # while these are unchanged

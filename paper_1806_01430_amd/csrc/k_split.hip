@@ -119,6 +119,53 @@ __global__ __launch_bounds__(kThreads) void k_prep_a(const void *__restrict__ Av
     }
 }
 
+// The same rows with 4 consecutive k per lane (16-byte loads, 8-byte bf16
+// or 4-byte e4m3 stores per segment) when K is a multiple of 4: same parts,
+// same bits.
+template <int MODE>   // 0: bf16 hi/lo split, 1: e4m3 split of A * sa[i]
+__global__ __launch_bounds__(kThreads) void k_prep_a4(const float *__restrict__ A, void *__restrict__ Apv,
+                                                      const float *__restrict__ sa, int M, int K, int Kp, int kx) {
+    const int i = blockIdx.x;
+    const int kk = (blockIdx.y * kThreads + (int)threadIdx.x) * 4;
+    const float scale = (MODE == 1 && i < M) ? sa[i] : 1.0f;
+    if (kk < K) {
+        float4 a = make_float4(0.f, 0.f, 0.f, 0.f);
+        if (i < M) a = *reinterpret_cast<const float4 *>(A + (size_t)i * K + kk);
+        const float v[4] = {a.x, a.y, a.z, a.w};
+        if (MODE == 0) {
+            unsigned hi[2] = {0, 0}, lo[2] = {0, 0};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const Bf16Parts q = split_bf16(v[t]);
+                hi[t >> 1] |= (unsigned)q.hi << (16 * (t & 1));
+                lo[t >> 1] |= (unsigned)q.lo << (16 * (t & 1));
+            }
+            unsigned short *row = static_cast<unsigned short *>(Apv) + (size_t)i * Kp;
+            *reinterpret_cast<uint2 *>(row + kk) = make_uint2(hi[0], hi[1]);
+            *reinterpret_cast<uint2 *>(row + K + kk) = make_uint2(hi[0], hi[1]);
+            *reinterpret_cast<uint2 *>(row + 2 * K + kk) = make_uint2(lo[0], lo[1]);
+        } else {
+            unsigned hi = 0, lo = 0;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const Fp8Parts q = split_fp8(v[t] * scale);
+                hi |= (unsigned)q.hi << (8 * t);
+                lo |= (unsigned)q.lo << (8 * t);
+            }
+            unsigned char *row = static_cast<unsigned char *>(Apv) + (size_t)i * Kp;
+            *reinterpret_cast<unsigned *>(row + kk) = hi;
+            *reinterpret_cast<unsigned *>(row + K + kk) = hi;
+            *reinterpret_cast<unsigned *>(row + 2 * K + kk) = lo;
+        }
+    }
+    if (kk < Kp - kx) {   // the row's zero tail, 4 elements at a time
+        if (MODE == 0)
+            *reinterpret_cast<uint2 *>(static_cast<unsigned short *>(Apv) + (size_t)i * Kp + kx + kk) = make_uint2(0, 0);
+        else
+            *reinterpret_cast<unsigned *>(static_cast<unsigned char *>(Apv) + (size_t)i * Kp + kx + kk) = 0u;
+    }
+}
+
 // B'^T: row j (< N) of the output holds column j of B: [hi | lo | hi | 0 ...]
 // (or the plain bf16 column for the bf16-input product).  64 x 64 tiles of B
 // through LDS, so both the read of B and the write of B'^T are coalesced.
@@ -158,6 +205,55 @@ __global__ __launch_bounds__(kThreads) void k_split_bt(const void *__restrict__ 
         } else {
             unsigned short *Bt = static_cast<unsigned short *>(Btv) + (size_t)j * Kp;
             Bt[kk] = bf16_rne_bits(x);
+        }
+    }
+}
+
+// The split of B (MODE 0 / 1) when K and N are whole 64-element tiles:
+// 16-byte loads of 4 columns, and per output row 8 k values at a time
+// (16-byte bf16 / 8-byte e4m3 stores per segment); same parts, same bits.
+template <int MODE>
+__global__ __launch_bounds__(kThreads) void k_split_bt8(const float *__restrict__ B, void *__restrict__ Btv,
+                                                        const float *__restrict__ sb, int K, int N, int Kp) {
+    constexpr int P = kT + 4;   // row pitch in floats (16-byte aligned rows)
+    __shared__ __attribute__((aligned(16))) float tile[kT][P];
+    const int k0 = blockIdx.x * kT, j0 = blockIdx.y * kT;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int c = tid + u * kThreads, r = c >> 4, q = c & 15;   // k-row r, columns 4q .. 4q + 3
+        *reinterpret_cast<float4 *>(&tile[r][4 * q]) =
+            *reinterpret_cast<const float4 *>(B + (size_t)(k0 + r) * N + j0 + 4 * q);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int c = tid + u * kThreads, j = c >> 3, q = c & 7;   // output row j, k values 8q .. 8q + 7
+        const float scale = MODE == 1 ? sb[j0 + j] : 1.0f;
+        if (MODE == 0) {
+            unsigned hi[4] = {0, 0, 0, 0}, lo[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const Bf16Parts p = split_bf16(tile[8 * q + t][j]);
+                hi[t >> 1] |= (unsigned)p.hi << (16 * (t & 1));
+                lo[t >> 1] |= (unsigned)p.lo << (16 * (t & 1));
+            }
+            unsigned short *row = static_cast<unsigned short *>(Btv) + (size_t)(j0 + j) * Kp + k0 + 8 * q;
+            *reinterpret_cast<uint4 *>(row) = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+            *reinterpret_cast<uint4 *>(row + K) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+            *reinterpret_cast<uint4 *>(row + 2 * K) = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+        } else {
+            unsigned hi[2] = {0, 0}, lo[2] = {0, 0};
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const Fp8Parts p = split_fp8(tile[8 * q + t][j] * scale);
+                hi[t >> 2] |= (unsigned)p.hi << (8 * (t & 3));
+                lo[t >> 2] |= (unsigned)p.lo << (8 * (t & 3));
+            }
+            unsigned char *row = static_cast<unsigned char *>(Btv) + (size_t)(j0 + j) * Kp + k0 + 8 * q;
+            *reinterpret_cast<uint2 *>(row) = make_uint2(hi[0], hi[1]);
+            *reinterpret_cast<uint2 *>(row + K) = make_uint2(lo[0], lo[1]);
+            *reinterpret_cast<uint2 *>(row + 2 * K) = make_uint2(hi[0], hi[1]);
         }
     }
 }
@@ -242,6 +338,13 @@ hipError_t prep_a(const void *A, void *Ap, const float *sa, int M, int K, int Mp
     const int span = K > Kp - kx ? K : Kp - kx;   // k range the threads of one row cover
     const dim3 grid((unsigned)Mp, (unsigned)((span + kThreads * kPrepV - 1) / (kThreads * kPrepV)));
     if (grid.y > 65535 || K <= 0) return hipErrorInvalidValue;
+    if (mode != 2 && K % 4 == 0) {
+        const dim3 g4((unsigned)Mp, (unsigned)((span + kThreads * 4 - 1) / (kThreads * 4)));
+        if (mode == 0)
+            return launch((k_prep_a4<0>), g4, dim3(kThreads), 0, s, static_cast<const float *>(A), Ap, sa, M, K, Kp,
+                          kx);
+        return launch((k_prep_a4<1>), g4, dim3(kThreads), 0, s, static_cast<const float *>(A), Ap, sa, M, K, Kp, kx);
+    }
     if (mode == 0) return launch((k_prep_a<0>), grid, dim3(kThreads), 0, s, A, Ap, sa, M, K, Kp, kx);
     if (mode == 1) return launch((k_prep_a<1>), grid, dim3(kThreads), 0, s, A, Ap, sa, M, K, Kp, kx);
     return launch((k_prep_a<2>), grid, dim3(kThreads), 0, s, A, Ap, sa, M, K, Kp, kx);
@@ -250,6 +353,11 @@ hipError_t prep_a(const void *A, void *Ap, const float *sa, int M, int K, int Mp
 hipError_t split_bt(const void *B, void *Bt, const float *sb, int K, int N, int Kp, int mode, hipStream_t s) {
     dim3 grid((unsigned)((K + kT - 1) / kT), (unsigned)((N + kT - 1) / kT));
     if (grid.y > 65535) return hipErrorInvalidValue;
+    if (mode != 2 && K % kT == 0 && N % kT == 0) {
+        const float *Bf = static_cast<const float *>(B);
+        if (mode == 0) return launch((k_split_bt8<0>), grid, dim3(kThreads), 0, s, Bf, Bt, sb, K, N, Kp);
+        return launch((k_split_bt8<1>), grid, dim3(kThreads), 0, s, Bf, Bt, sb, K, N, Kp);
+    }
     if (mode == 0) return launch((k_split_bt<0>), grid, dim3(kThreads), 0, s, B, Bt, sb, K, N, Kp);
     if (mode == 1) return launch((k_split_bt<1>), grid, dim3(kThreads), 0, s, B, Bt, sb, K, N, Kp);
     if (K % kT == 0 && N % kT == 0 && Kp % 8 == 0)

@@ -205,9 +205,12 @@ def _wide(shape, seed):
 
 
 @pytest.mark.parametrize("prec", SPLIT)
+# K a multiple of 4: A split 4 elements per lane; K and N whole 64-element
+# tiles: B split through 16-byte accesses
 @pytest.mark.parametrize("M,N,K,tile", [(1, 1, 1, None), (17, 33, 5, None), (130, 70, 37, None),
-                                        (257, 129, 300, None), (384, 256, 200, None), (1, 1, 1, "256"),
-                                        (257, 129, 300, "256"), (520, 300, 70, "256")])
+                                        (257, 129, 300, None), (384, 256, 200, None), (128, 192, 64, None),
+                                        (1, 1, 1, "256"), (257, 129, 300, "256"), (520, 300, 70, "256"),
+                                        (300, 320, 128, "256")])
 def test_gemm_split_shapes(prec, M, N, K, tile, monkeypatch):
     # gene 1: the split product (oracle: its definition summed in FP64);
     # gene 0: the nest as written, plain FP32 on the CPU
