@@ -258,20 +258,21 @@ def run_kernels_large(args):
             gbs = b * R * C * runs / (ms * 1e-3) / 1e9
             out["ewise_8192_" + op] = {"launches_per_run": n // runs, "ms_per_run": round(ms / runs, 4),
                                        "GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
-    del bufs, app
     Rf, n = 8192, 1024
-    app = ofl.App(json.dumps(appgen.fft_app(Rf, n)), seed=1)
-    app.set_input("X", np.random.default_rng(5).standard_normal((Rf, 2 * n)).astype(np.float32))
-    bufs = app.alloc_device_buffers("cuda:0")
-    app.run_pattern([1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
-    app.set_kernel_timing(True)
-    for _ in range(5):
+    for inverse in (False, True):
+        del bufs, app
+        app = ofl.App(json.dumps(appgen.fft_app(Rf, n, inverse=inverse)), seed=1)
+        app.set_input("X", np.random.default_rng(5).standard_normal((Rf, 2 * n)).astype(np.float32))
+        bufs = app.alloc_device_buffers("cuda:0")
         app.run_pattern([1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
-    nl, ms = app.kernel_stats("fft_rows")
-    avg = ms / nl * 1e-3
-    gbs = 16.0 * Rf * n / avg / 1e9
-    out["fft_rows_8192x1024"] = {"avg_us": round(avg * 1e6, 3), "GBps": round(gbs, 1),
-                                 "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+        app.set_kernel_timing(True)
+        for _ in range(5):
+            app.run_pattern([1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
+        nl, ms = app.kernel_stats("fft_rows")
+        avg = ms / nl * 1e-3
+        gbs = 16.0 * Rf * n / avg / 1e9
+        out[("ifft" if inverse else "fft") + "_rows_8192x1024"] = {
+            "avg_us": round(avg * 1e6, 3), "GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
     return out
 
 

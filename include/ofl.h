@@ -233,7 +233,8 @@ typedef struct {
  * also be a function block, a library call given one gene bit (Sec. 3.2,
  * steps 1-2 and 1-3, name FFT library calls beside loops): op "fft_rows",
  * the forward DFT of every row of an f32 buffer [R][2n] (n complex values per
- * row, interleaved; n a power of two up to 4096).  `seed` drives the
+ * row, interleaved; n a power of two up to 4096), or with args "inverse":
+ * true / 1 the inverse DFT scaled by 1/n.  `seed` drives the
  * application's random-initialisation nests.  Allocates nothing on the GPU
  * (the device scratch, and for an FFT call its twiddle tables, come with the
  * first run).  A nest of op "host_code" (args {"symbol": name}) is a loop

@@ -1,5 +1,5 @@
 """Oracle of the FFT function block (test infrastructure only; parity
-pinned by tests/test_oracle_nests.py against closed forms and numpy.fft).
+pinned by tests/test_oracle_dft.py against closed forms and numpy.fft).
 
 The analysis of Sec. 3.2 (steps 1-2, 1-3) names FFT library calls beside
 loop statements as offloadable parts.  The call computes, for each row of n
@@ -8,9 +8,16 @@ row of length 2n), the forward discrete Fourier transform by its definition
 
     X[k] = sum_{j=0}^{n-1} x[j] * exp(-2 pi i j k / n),   k = 0..n-1.
 
-Evaluated here as that sum in complex double precision (one matrix product
-of the row with the n x n matrix of exp(-2 pi i ((j k) mod n) / n); the
-exponent index is reduced exactly in integers first).
+The inverse call computes, per row, the inverse transform scaled by 1/n,
+
+    x[j] = (1/n) sum_{k=0}^{n-1} X[k] * exp(+2 pi i j k / n),   j = 0..n-1,
+
+so that the inverse of the forward transform gives the row back.
+
+Evaluated here as those sums in complex double precision (one matrix
+product of the row with the n x n matrix of exp(-2 pi i ((j k) mod n) / n),
+or its complex conjugate for the inverse; the exponent index is reduced
+exactly in integers first).
 """
 import numpy as np
 
@@ -30,6 +37,22 @@ def dft_rows(x):
     n = m // 2
     z = x[:, 0::2] + 1j * x[:, 1::2]
     Z = z @ dft_matrix(n) if n else z
+    out = np.empty((R, m), np.float64)
+    out[:, 0::2] = Z.real
+    out[:, 1::2] = Z.imag
+    return out
+
+
+def idft_rows(x):
+    """Inverse DFT (scaled by 1/n) of each row of x[R][2n] (interleaved);
+    float64 result of the same layout."""
+    x = np.asarray(x, np.float64)
+    R, m = x.shape
+    if m % 2:
+        raise ValueError("rows hold interleaved complex values")
+    n = m // 2
+    z = x[:, 0::2] + 1j * x[:, 1::2]
+    Z = (z @ np.conj(dft_matrix(n))) / n if n else z
     out = np.empty((R, m), np.float64)
     out[:, 0::2] = Z.real
     out[:, 1::2] = Z.imag

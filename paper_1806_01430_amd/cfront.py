@@ -15,8 +15,8 @@ as source instead of the JSON IR:
   array references, locals, ``+ - * /``, parentheses, casts ``(double)x``
   and calls ``f(...)``.
 
-A call statement of its own outside any loop, ``fft_rows(X);`` or
-``sgemm(A, B, C);``, is a function block (the FFT library calls Sec. 3.2 names beside loop statements
+A call statement of its own outside any loop, ``fft_rows(X);``,
+``ifft_rows(X);`` or ``sgemm(A, B, C);``, is a function block (the FFT library calls Sec. 3.2 names beside loop statements
 as offloadable parts): one nest with one gene bit, whose GPU and CPU forms
 are the library's own.
 
@@ -298,9 +298,10 @@ PURE_CALLS = ("u01", "bf16")
 # the library implements on the CPU and on the GPU: each call becomes a
 # function block (one nest, one gene bit).  fft_rows(X): the forward DFT of
 # every row of X[R][2n] (n complex values per row, interleaved);
+# ifft_rows(X): the inverse DFT of every row, scaled by 1/n;
 # sgemm(A, B, C): C = A B (FP32 or bf16 operands by their declarations),
 # the same nest as the loop form of the product.
-FUNCTION_BLOCKS = {"fft_rows": "fft_rows", "sgemm": "gemm"}
+FUNCTION_BLOCKS = {"fft_rows": "fft_rows", "ifft_rows": "fft_rows", "sgemm": "gemm"}
 
 # One C snippet per operation, each the nest's definition in the evaluation
 # order the library follows; names beginning with $ are pattern variables
@@ -1008,10 +1009,11 @@ def _parse(src, name):
         if b["dtype"] != "f32" or len(b["dims"]) != 2:
             raise CError("%s needs a 2-D float array (rows of interleaved complex values)" % name)
         at.append(where[id(stmt)] + ("call",))
-        base = "fft_" + x
+        inverse = name == "ifft_rows"
+        base = ("ifft_" if inverse else "fft_") + x
         names_used[base] = names_used.get(base, 0) + 1
         return {"nest": base if names_used[base] == 1 else "%s_%d" % (base, names_used[base]),
-                "op": FUNCTION_BLOCKS[name], "args": {"x": x},
+                "op": FUNCTION_BLOCKS[name], "args": {"x": x, "inverse": 1} if inverse else {"x": x},
                 "loops": [["r", "0", b["dims"][0]], ["e", "0", b["dims"][1]]], "access": [[x, "rw", "r", "e"]]}
 
     def gemm_block_ir(stmt):

@@ -263,7 +263,8 @@ bool run_host_nest(const AppIR &app, const Nest &n, const std::vector<void *> &h
     }
     case OP_FFT_ROWS: {
         // the CPU form of the FFT call: the same radix-2 self-sorting
-        // (Stockham) passes as the GPU kernel, per row
+        // (Stockham) passes as the GPU kernel, per row; the inverse conjugates
+        // the row, transforms it forward, and conjugates and scales by 1/n
         const Buffer &x = app.bufs[n.b[0]];
         const int64_t rows = x.dims[0], pts = x.dims[1] / 2, half = pts / 2, ws = kFftMaxPoints / std::max<int64_t>(pts, 1);
         std::vector<float> w(kFftMaxPoints), a(2 * pts), b(2 * pts);
@@ -273,6 +274,8 @@ bool run_host_nest(const AppIR &app, const Nest &n, const std::vector<void *> &h
             if ((r & 15) == 0 && dl.expired()) return false;
             float *xr = X + r * 2 * pts;
             std::memcpy(a.data(), xr, 2 * pts * sizeof(float));
+            if (n.inverse)
+                for (int64_t j = 0; j < pts; ++j) a[2 * j + 1] = -a[2 * j + 1];
             for (int64_t ns = 1, st = half; ns < pts; ns <<= 1, st >>= 1) {
                 for (int64_t j = 0; j < half; ++j) {
                     const int64_t k = j & (ns - 1), o = ((j - k) << 1) + k;
@@ -287,6 +290,13 @@ bool run_host_nest(const AppIR &app, const Nest &n, const std::vector<void *> &h
                     b[2 * (o + ns) + 1] = ui - vi;
                 }
                 a.swap(b);
+            }
+            if (n.inverse) {
+                const float sc = 1.0f / (float)pts;
+                for (int64_t j = 0; j < pts; ++j) {
+                    a[2 * j] = a[2 * j] * sc;
+                    a[2 * j + 1] = -a[2 * j + 1] * sc;
+                }
             }
             std::memcpy(xr, a.data(), 2 * pts * sizeof(float));
         }

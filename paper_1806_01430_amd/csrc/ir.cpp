@@ -297,6 +297,13 @@ bool resolve_op(Ctx &cx, Nest &n, const Json *args, const std::vector<int64_t> &
         if (!arg_buf(cx, n, args, "x", x)) return false;
         n.b.push_back(x);
         if (!need(cx, n, is(0, DT_F32) && B(0).dims.size() == 2, "needs a 2-D f32 buffer")) return false;
+        // optional "inverse": true / 1 for the inverse transform
+        if (const Json *inv = args->get("inverse")) {
+            const bool ok = (inv->kind == Json::Bool) || (inv->kind == Json::Num && inv->is_int &&
+                                                          (inv->inum == 0 || inv->inum == 1));
+            if (!need(cx, n, ok, "inverse must be true / false or 0 / 1")) return false;
+            n.inverse = inv->kind == Json::Bool ? inv->b : inv->inum == 1;
+        }
         const int64_t pts = B(0).dims[1] / 2;
         return need(cx, n, B(0).dims[1] % 2 == 0 && pts >= 1 && pts <= kFftMaxPoints && (pts & (pts - 1)) == 0 &&
                                B(0).dims[0] < (1ll << 31),

@@ -42,7 +42,7 @@ enum Op {
     OP_REC_PREFIX,
     OP_REC_DECAY,
     OP_LCG_FILL,
-    OP_FFT_ROWS,        // function block: forward complex DFT of each row
+    OP_FFT_ROWS,        // function block: complex DFT of each row (forward, or inverse / n)
     OP_HOST_CODE,       // a nest compiled from its own source text, CPU only
     OP_COUNT
 };
@@ -93,6 +93,7 @@ struct Nest {
     std::vector<uint32_t> streams;
     double alpha = 0.0;          // add_scaled alpha / scale beta
     uint32_t seed32 = 0;         // lcg_fill
+    bool inverse = false;        // fft_rows: the inverse transform (scaled by 1/n)
     int slot_repeat = -1;        // stencil residual slot: repeat id
     GemmPrec prec = PREC_F32;
     std::string symbol;          // host_code: entry point in the application's host object

@@ -20,6 +20,13 @@
 // first pair reads the row from HBM, the last writes it back; odd log2 n
 // begins with one plain pass.  Short rows share a block (below); rows of
 // 256 to 4096 points take the register form further down.
+//
+// The inverse transform, x[j] = (1/n) sum_k X[k] exp(+2 pi i j k / n), is
+// the forward one applied to the conjugated row, conjugated again and
+// scaled by 1/n (exact: a power of two): the kernels conjugate as they read
+// the row and conjugate and scale as they write it, so the passes, twiddles
+// and bits are those of the forward transform (and of the CPU form, which
+// does the same).
 #include "fft_limits.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
@@ -34,39 +41,45 @@ constexpr int kFftThreads = 256;
 __device__ inline float2 cmul(float2 v, float2 t) {
     return make_float2(v.x * t.x - v.y * t.y, v.x * t.y + v.y * t.x);
 }
+// a value read from the row (conjugated for the inverse) and one written to
+// it (conjugated and scaled by 1/n for the inverse)
+__device__ inline float2 rd(float2 v, bool inv) { return inv ? make_float2(v.x, -v.y) : v; }
+__device__ inline float2 wr(float2 v, bool inv, float sc) { return inv ? make_float2(v.x * sc, -v.y * sc) : v; }
 
 // One plain radix-2 pass (half-size ns): src -> dst, by threads t of T.
-// `put` = false skips the stores (a row past the end of the array).
+// `put` = false skips the stores (a row past the end of the array); ci / co:
+// src / dst is the row of an inverse transform (sc = 1/n).
 __device__ inline void pass1(const float2 *__restrict__ src, float2 *__restrict__ dst, const float2 *w, int n,
-                             int ns, int st, int t, int T, bool put) {
+                             int ns, int st, int t, int T, bool put, bool ci, bool co, float sc) {
     const int half = n >> 1;
     for (int j = t; j < half; j += T) {
         const int k = j & (ns - 1), o = ((j - k) << 1) + k;
-        const float2 u = src[j], v = cmul(src[j + half], w[k * st]);
+        const float2 u = rd(src[j], ci), v = cmul(rd(src[j + half], ci), w[k * st]);
         if (put) {
-            dst[o] = make_float2(u.x + v.x, u.y + v.y);
-            dst[o + ns] = make_float2(u.x - v.x, u.y - v.y);
+            dst[o] = wr(make_float2(u.x + v.x, u.y + v.y), co, sc);
+            dst[o + ns] = wr(make_float2(u.x - v.x, u.y - v.y), co, sc);
         }
     }
 }
 
 // Passes s and s + 1 (half-sizes ns and 2 ns): src -> dst, by threads t of T.
 __device__ inline void pass2(const float2 *__restrict__ src, float2 *__restrict__ dst, const float2 *w, int n,
-                             int ns, int t, int T, bool put) {
+                             int ns, int t, int T, bool put, bool ci, bool co, float sc) {
     const int q4 = n >> 2, st = n / (2 * ns), st2 = st >> 1;
     for (int g = t; g < q4; g += T) {
         const int k = g & (ns - 1), base = ((g - k) << 2) + k;
-        const float2 x0 = src[g], x1 = src[g + q4], x2 = src[g + 2 * q4], x3 = src[g + 3 * q4];
+        const float2 x0 = rd(src[g], ci), x1 = rd(src[g + q4], ci), x2 = rd(src[g + 2 * q4], ci),
+                     x3 = rd(src[g + 3 * q4], ci);
         const float2 tw1 = w[k * st];
         const float2 m2 = cmul(x2, tw1), m3 = cmul(x3, tw1);
         const float2 u0 = make_float2(x0.x + m2.x, x0.y + m2.y), v0 = make_float2(x0.x - m2.x, x0.y - m2.y);
         const float2 u1 = make_float2(x1.x + m3.x, x1.y + m3.y), v1 = make_float2(x1.x - m3.x, x1.y - m3.y);
         const float2 p = cmul(u1, w[k * st2]), r = cmul(v1, w[(k + ns) * st2]);
         if (put) {
-            dst[base] = make_float2(u0.x + p.x, u0.y + p.y);
-            dst[base + 2 * ns] = make_float2(u0.x - p.x, u0.y - p.y);
-            dst[base + ns] = make_float2(v0.x + r.x, v0.y + r.y);
-            dst[base + 3 * ns] = make_float2(v0.x - r.x, v0.y - r.y);
+            dst[base] = wr(make_float2(u0.x + p.x, u0.y + p.y), co, sc);
+            dst[base + 2 * ns] = wr(make_float2(u0.x - p.x, u0.y - p.y), co, sc);
+            dst[base + ns] = wr(make_float2(v0.x + r.x, v0.y + r.y), co, sc);
+            dst[base + 3 * ns] = wr(make_float2(v0.x - r.x, v0.y - r.y), co, sc);
         }
     }
 }
@@ -77,7 +90,7 @@ __device__ inline void pass2(const float2 *__restrict__ src, float2 *__restrict_
 // past the end read row 0 and store nothing; every thread reaches every
 // barrier.
 __global__ __launch_bounds__(kFftThreads) void k_fft_rows(float2 *__restrict__ x, const float2 *__restrict__ tw,
-                                                          int64_t rows, int n, int logn) {
+                                                          int64_t rows, int n, int logn, bool inv) {
     extern __shared__ float2 lds[];
     const int T = n >= 4 ? n >> 2 : 1, rb = kFftThreads / T;
     const int sub = threadIdx.x / T, t = threadIdx.x - sub * T;
@@ -88,11 +101,12 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows(float2 *__restrict__ x
     const int half = n >> 1;
     for (int m = threadIdx.x; m < half; m += blockDim.x) w[m] = tw[m];
     __syncthreads();
+    const float sc = 1.0f / (float)n;
     int s = 0;
     const float2 *src = xr;
     if (logn & 1) {
         // one plain pass first; with n = 2 it is the whole transform
-        pass1(xr, logn == 1 ? xr : a, w, n, 1, half, t, T, logn != 1 || valid);
+        pass1(xr, logn == 1 ? xr : a, w, n, 1, half, t, T, logn != 1 || valid, inv, inv && logn == 1, sc);
         if (logn == 1) return;
         __syncthreads();
         src = a;
@@ -102,7 +116,7 @@ __global__ __launch_bounds__(kFftThreads) void k_fft_rows(float2 *__restrict__ x
     for (; s < logn; s += 2) {
         const bool last = s + 2 >= logn;
         float2 *dst = last ? xr : spare;
-        pass2(src, dst, w, n, 1 << s, t, T, !last || valid);
+        pass2(src, dst, w, n, 1 << s, t, T, !last || valid, inv && src == xr, inv && last, sc);
         if (last) break;
         __syncthreads();
         spare = const_cast<float2 *>(src == xr ? b : src);
@@ -146,7 +160,7 @@ __device__ inline void fft_stage(float2 (&v)[1 << R], const float2 *__restrict__
 
 // The transform of one row whose sixteen first-stage points per thread are
 // already in registers; ends with the row written back.
-template <int LOGN>
+template <int LOGN, bool INV>
 __device__ inline void fft_row16(float2 (&v)[16], float2 *__restrict__ xr, float2 *lds,
                                  const float2 *__restrict__ tw) {
     constexpr int N = 1 << LOGN, G16 = N / 16, R3 = LOGN - 8, G3 = N >> R3;
@@ -169,7 +183,7 @@ __device__ inline void fft_row16(float2 (&v)[16], float2 *__restrict__ xr, float
         for (int m = 0; m < (1 << R3); ++m) w[m] = lds[fft_pad(g + m * G3)];
         fft_stage<R3, 8, LOGN>(w, tw, g);
 #pragma unroll
-        for (int d = 0; d < (1 << R3); ++d) xr[g + (d << 8)] = w[d];
+        for (int d = 0; d < (1 << R3); ++d) xr[g + (d << 8)] = wr(w[d], INV, 1.0f / N);
     }
 }
 
@@ -177,7 +191,7 @@ __device__ inline void fft_row16(float2 (&v)[16], float2 *__restrict__ xr, float
 // streams in from HBM while the first is transformed.
 constexpr int kFftRowsPerBlock = 2;
 
-template <int LOGN>
+template <int LOGN, bool INV>
 __global__ __launch_bounds__((1 << LOGN) / 16) void k_fft_rows16(float2 *__restrict__ x,
                                                                    const float2 *__restrict__ tw, int64_t rows) {
     constexpr int N = 1 << LOGN, G16 = N / 16;
@@ -188,15 +202,15 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void k_fft_rows16(float2 *__restr
     const int tid = threadIdx.x;
     float2 v0[16], v1[16];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) v0[m] = x0[tid + m * G16];
+    for (int m = 0; m < 16; ++m) v0[m] = rd(x0[tid + m * G16], INV);
     if (two) {
 #pragma unroll
-        for (int m = 0; m < 16; ++m) v1[m] = x1[tid + m * G16];
+        for (int m = 0; m < 16; ++m) v1[m] = rd(x1[tid + m * G16], INV);
     }
-    fft_row16<LOGN>(v0, x0, lds, tw);
+    fft_row16<LOGN, INV>(v0, x0, lds, tw);
     if (two) {
         __syncthreads();   // the first row's last LDS reads before the second row's stores
-        fft_row16<LOGN>(v1, x1, lds, tw);
+        fft_row16<LOGN, INV>(v1, x1, lds, tw);
     }
 }
 
@@ -204,7 +218,7 @@ __global__ __launch_bounds__((1 << LOGN) / 16) void k_fft_rows16(float2 *__restr
 // per row and 64 / T rows per one-wave block, each row in its own LDS area;
 // at 256 points the second stage is the last and writes the row back.
 // Threads of a row past the end read row 0 and store nothing.
-template <int LOGN>
+template <int LOGN, bool INV>
 __global__ __launch_bounds__(64) void k_fft_rows16s(float2 *__restrict__ x, const float2 *__restrict__ tw,
                                                      int64_t rows) {
     constexpr int N = 1 << LOGN, T = N / 16, RW = 64 / T, R3 = LOGN - 8, P = N + N / 16;
@@ -216,7 +230,7 @@ __global__ __launch_bounds__(64) void k_fft_rows16s(float2 *__restrict__ x, cons
     float2 *lds = lds_all + sub * P;
     float2 v[16];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) v[m] = xr[tid + m * T];
+    for (int m = 0; m < 16; ++m) v[m] = rd(xr[tid + m * T], INV);
     fft_stage<4, 0, LOGN>(v, tw, 0);
 #pragma unroll
     for (int d = 0; d < 16; ++d) lds[fft_pad((tid << 4) + d)] = v[d];
@@ -228,7 +242,7 @@ __global__ __launch_bounds__(64) void k_fft_rows16s(float2 *__restrict__ x, cons
     if constexpr (R3 == 0) {
         if (valid) {
 #pragma unroll
-            for (int d = 0; d < 16; ++d) xr[((tid - k) << 4) + k + (d << 4)] = v[d];
+            for (int d = 0; d < 16; ++d) xr[((tid - k) << 4) + k + (d << 4)] = wr(v[d], INV, 1.0f / N);
         }
     } else {
         __syncthreads();   // every read of this stage before its stores
@@ -243,32 +257,39 @@ __global__ __launch_bounds__(64) void k_fft_rows16s(float2 *__restrict__ x, cons
             fft_stage<R3, 8, LOGN>(w, tw, g);
             if (valid) {
 #pragma unroll
-                for (int d = 0; d < (1 << R3); ++d) xr[g + (d << 8)] = w[d];
+                for (int d = 0; d < (1 << R3); ++d) xr[g + (d << 8)] = wr(w[d], INV, 1.0f / N);
             }
         }
     }
 }
 
-}  // namespace
-
-hipError_t fft_rows(float *x, int64_t rows, int64_t n, const float *tw, hipStream_t s) {
-    if (rows <= 0 || n <= 1) return hipSuccess;   // a 1-point transform is the identity
-    if (n > kFftMaxPoints || (n & (n - 1)) != 0 || rows > 0x7FFFFFFF || tw == nullptr) return hipErrorInvalidValue;
-    const float2 *t2 = reinterpret_cast<const float2 *>(tw) + (n / 2 - 1);   // this length's table
-    float2 *x2 = reinterpret_cast<float2 *>(x);
+template <bool INV>
+hipError_t fft_rows_t(float2 *x2, const float2 *t2, int64_t rows, int64_t n, hipStream_t s) {
     const dim3 pairs((unsigned)((rows + kFftRowsPerBlock - 1) / kFftRowsPerBlock));
-    if (n == 1024) return launch(k_fft_rows16<10>, pairs, dim3(64), 0, s, x2, t2, rows);
-    if (n == 2048) return launch(k_fft_rows16<11>, pairs, dim3(128), 0, s, x2, t2, rows);
-    if (n == 4096) return launch(k_fft_rows16<12>, pairs, dim3(256), 0, s, x2, t2, rows);
-    if (n == 256) return launch(k_fft_rows16s<8>, dim3((unsigned)((rows + 3) / 4)), dim3(64), 0, s, x2, t2, rows);
-    if (n == 512) return launch(k_fft_rows16s<9>, dim3((unsigned)((rows + 1) / 2)), dim3(64), 0, s, x2, t2, rows);
+    if (n == 1024) return launch(k_fft_rows16<10, INV>, pairs, dim3(64), 0, s, x2, t2, rows);
+    if (n == 2048) return launch(k_fft_rows16<11, INV>, pairs, dim3(128), 0, s, x2, t2, rows);
+    if (n == 4096) return launch(k_fft_rows16<12, INV>, pairs, dim3(256), 0, s, x2, t2, rows);
+    if (n == 256)
+        return launch(k_fft_rows16s<8, INV>, dim3((unsigned)((rows + 3) / 4)), dim3(64), 0, s, x2, t2, rows);
+    if (n == 512)
+        return launch(k_fft_rows16s<9, INV>, dim3((unsigned)((rows + 1) / 2)), dim3(64), 0, s, x2, t2, rows);
     if (n > 128) return hipErrorInvalidValue;
     int logn = 0;
     while ((1ll << logn) < n) ++logn;
     const int64_t rb = kFftThreads / (n >= 4 ? n / 4 : 1);
     const uint32_t lds_bytes = (uint32_t)((rb * 2 * n + n / 2) * sizeof(float2));
     return launch(k_fft_rows, dim3((unsigned)((rows + rb - 1) / rb)), dim3(kFftThreads), lds_bytes, s, x2, t2, rows,
-                  (int)n, logn);
+                  (int)n, logn, INV);
+}
+
+}  // namespace
+
+hipError_t fft_rows(float *x, int64_t rows, int64_t n, const float *tw, bool inverse, hipStream_t s) {
+    if (rows <= 0 || n <= 1) return hipSuccess;   // a 1-point transform (either way) is the identity
+    if (n > kFftMaxPoints || (n & (n - 1)) != 0 || rows > 0x7FFFFFFF || tw == nullptr) return hipErrorInvalidValue;
+    const float2 *t2 = reinterpret_cast<const float2 *>(tw) + (n / 2 - 1);   // this length's table
+    float2 *x2 = reinterpret_cast<float2 *>(x);
+    return inverse ? fft_rows_t<true>(x2, t2, rows, n, s) : fft_rows_t<false>(x2, t2, rows, n, s);
 }
 
 }  // namespace k

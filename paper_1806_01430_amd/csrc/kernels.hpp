@@ -27,11 +27,12 @@ hipError_t copy_bytes(void *dst, const void *src, uint64_t bytes, hipStream_t s)
 hipError_t cast_bf16(uint16_t *dst, const float *src, int64_t n, hipStream_t s);
 hipError_t transpose(const float *X, float *T, int64_t R, int64_t Cc, hipStream_t s);
 hipError_t sumsq(const float *x, int64_t n, double *s_out, const ReduceScratch &rs, hipStream_t s);
-// In-place forward DFT of each of `rows` rows of n complex values (real and
-// imaginary parts interleaved), n a power of two up to kFftMaxPoints (4096);
+// In-place DFT of each of `rows` rows of n complex values (real and
+// imaginary parts interleaved), n a power of two up to kFftMaxPoints (4096):
+// forward, or with `inverse` the inverse transform scaled by 1/n;
 // `tw` is the device copy of fft_twiddle_packed (the contiguous table of
 // each row length, 4095 complex values).
-hipError_t fft_rows(float *x, int64_t rows, int64_t n, const float *tw, hipStream_t s);
+hipError_t fft_rows(float *x, int64_t rows, int64_t n, const float *tw, bool inverse, hipStream_t s);
 // The sweep writes q and one residual partial per wave; adding the partials
 // to the sweep's residual slot is a separate step (ResidualFinish) that runs
 // as a one-block kernel or as the extra block of an interior copy launched

@@ -380,7 +380,7 @@ hipError_t launch_nest(ofl_app *app, const Nest &n, void *const *dev, const int6
     }
     case OP_FFT_ROWS: {
         const auto &d = ir.bufs[n.b[0]].dims;
-        return k::fft_rows(F(0), d[0], d[1] / 2, app->d_twiddles, s);
+        return k::fft_rows(F(0), d[0], d[1] / 2, app->d_twiddles, n.inverse, s);
     }
     default:
         return hipErrorInvalidValue;

@@ -282,6 +282,21 @@ def test_library_call_is_a_function_block():
         cfront.parse(DECLS + "fft_rows(t);", "t")
 
 
+def test_inverse_fft_call_is_a_function_block():
+    # ifft_rows(X): the same op with the inverse flag, one more gene bit; a
+    # forward call then an inverse one parse to the round-trip application
+    from workloads import appgen
+    src = ("#define R 37\n#define M 512\nfloat X[R][M]; // ofl: output\n"
+           "fft_rows(X);\nifft_rows(X);\n")
+    doc = cfront.parse(src, "fft_roundtrip")
+    want = appgen.fft_roundtrip_app(37, 256)
+    assert [(n["nest"], n["op"], n["args"]) for n in doc["program"]] == \
+        [(n["nest"], n["op"], n["args"]) for n in want["program"]]
+    app = ofl.App(json.dumps(doc))
+    assert app.gene_len == 2
+    assert app.verdicts() == [tuple(x) for x in D.check_app(ir.load(doc))]
+
+
 def test_matrix_product_call_is_the_product_nest():
     # sgemm(A, B, C) as a function block gives the same nest as the loop form
     loop = cfront.load(os.path.join(APPS, "tiny.c"))

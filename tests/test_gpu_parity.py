@@ -530,16 +530,18 @@ def test_eval_population_and_ga_tiny():
 
 
 # ---------------------------------------------------------------- FFT call
+@pytest.mark.parametrize("inverse", [False, True])
 @pytest.mark.parametrize("R,n", [(1, 1), (3, 2), (5, 4), (7, 8), (37, 64), (16, 128), (9, 256), (33, 512),
                                  (64, 1024), (7, 1024), (1, 1024), (20, 2048), (3, 2048), (6, 4096), (3, 4096)])
-def test_fft_rows_shapes(R, n):
-    # the function block on the GPU (gene 1) and its CPU form (gene 0),
-    # each row within the FFT error bound of the exact transform
-    from oracle.dft import dft_rows
+def test_fft_rows_shapes(R, n, inverse):
+    # the function block (forward or inverse) on the GPU (gene 1) and its CPU
+    # form (gene 0), each row within the FFT error bound of the exact
+    # transform (the inverse's conjugations and 1/n scale are exact)
+    from oracle.dft import dft_rows, idft_rows
     X = np.random.default_rng(R * 4099 + n).standard_normal((R, 2 * n)).astype(np.float32)
-    doc = appgen.fft_app(R, n)
+    doc = appgen.fft_app(R, n, inverse=inverse)
     app, bufs = _run_and_compare(doc, [[0], [1]], inputs={"X": X})
-    ref = dft_rows(X)
+    ref = idft_rows(X) if inverse else dft_rows(X)
     outs = {}
     for g in (0, 1):
         app.run_pattern([g], bufs, flags=ofl.KEEP_OUTPUTS)
@@ -567,6 +569,26 @@ def test_fft_rows_full_size_sampled():
     ref = dft_rows(X[rows])
     err = np.max(np.linalg.norm(Y[rows] - ref, axis=1) / np.linalg.norm(ref, axis=1))
     assert err <= parity.rel_fft(n) + 2.0 ** -23, err
+
+
+@pytest.mark.parametrize("R,n", [(5, 64), (9, 256), (6, 1024), (3, 4096)])
+def test_fft_round_trip(R, n):
+    # the forward call then the inverse one: every gene gives the row back
+    # within twice the FFT bound, and the genes that place both calls alike
+    # agree bit for bit (the GPU and CPU forms run the same butterflies)
+    X = np.random.default_rng(R + n).standard_normal((R, 2 * n)).astype(np.float32)
+    app = ofl.App(json.dumps(appgen.fft_roundtrip_app(R, n)))
+    app.set_input("X", X)
+    bufs = app.alloc_device_buffers()
+    outs = {}
+    for g in ([0, 0], [1, 1], [1, 0], [0, 1]):
+        say("case fft round trip", R, n, g)
+        assert app.run_pattern(g, bufs)["status"] == ofl.ST_OK
+        outs[tuple(g)] = app.read_buffer("X").copy()
+        err = np.max(np.linalg.norm(outs[tuple(g)] - X, axis=1) / np.linalg.norm(X, axis=1))
+        assert err <= 2 * (parity.rel_fft(n) + 2.0 ** -23), (g, err)
+    for g in ((1, 1), (1, 0), (0, 1)):
+        assert np.array_equal(outs[g].view(np.uint32), outs[(0, 0)].view(np.uint32)), g
 
 
 def test_spectral_all_genes():

@@ -417,6 +417,20 @@ def test_fft_call_shapes(R, n, ok):
             ofl.App(json.dumps(doc))
 
 
+@pytest.mark.parametrize("flag,ok", [(1, True), (0, True), (True, True), (2, False), ("yes", False)])
+def test_inverse_fft_flag(flag, ok):
+    # the inverse call is the FFT op with "inverse": true / 1 (0 / false is
+    # the forward one); any other value is an invalid application
+    from workloads import appgen
+    doc = appgen.fft_app(4, 64)
+    doc["program"][0]["args"]["inverse"] = flag
+    if ok:
+        assert ofl.App(json.dumps(doc)).verdicts() == [(D.PARALLEL, D.R_NONE, 0)]
+    else:
+        with pytest.raises(ofl.OflError):
+            ofl.App(json.dumps(doc))
+
+
 def test_irregular_program_verdicts_and_plans_match_oracle():
     # a C program with loops the library does not implement: those nests run
     # on the CPU from their own compiled text; verdicts (with the reason of

@@ -1,11 +1,12 @@
 """Pins of the FFT function block's oracle (the DFT by its definition):
 closed forms that catch a wrong sign of the exponent, swapped real and
 imaginary parts or a transposed index, Parseval's identity, the shift
-theorem, and the library FFT (numpy.fft) as an independent special case."""
+theorem, and the library FFT (numpy.fft) as an independent special case;
+for the inverse call also its 1/n scale and the round trip."""
 import numpy as np
 import pytest
 
-from oracle.dft import dft_rows
+from oracle.dft import dft_rows, idft_rows
 
 import parity
 
@@ -95,3 +96,37 @@ def test_fft_bound_values():
         ref = _complex(dft_rows(_interleave(z.astype(complex))))
         err = np.max(np.linalg.norm(y - ref, axis=1) / np.linalg.norm(ref, axis=1))
         assert err < parity.rel_fft(n), (n, err)
+
+
+@pytest.mark.parametrize("n", [1, 2, 4, 8, 64, 1024])
+def test_inverse_of_delta_is_the_scaled_constant(n):
+    # x = delta_0: every output 1/n exactly (a power of two); a missing or
+    # doubled scale, or the forward transform, would give 1 or n
+    z = np.zeros(n, complex)
+    z[0] = 1
+    assert np.array_equal(_complex(idft_rows(_interleave(z))), np.full((1, n), 1.0 / n, complex))
+
+
+@pytest.mark.parametrize("n", [4, 16, 256])
+def test_inverse_tone_lands_in_the_mirrored_bin(n):
+    j = np.arange(n)
+    for m in (1, 3 % n, n // 2, n - 1):
+        z = np.exp(2j * np.pi * m * j / n)        # exp(+2 pi i m j / n)
+        x = _complex(idft_rows(_interleave(z)))[0]
+        want = np.zeros(n, complex)
+        want[(n - m) % n] = 1                     # inverse: exp(+...) pairs with bin -m, value 1 (scaled by 1/n)
+        assert np.max(np.abs(x - want)) < 1e-12, (n, m)
+
+
+def test_inverse_round_trip_and_library_ifft():
+    rng = np.random.default_rng(6)
+    for n in (1, 2, 8, 128, 512):
+        z = rng.standard_normal((5, n)) + 1j * rng.standard_normal((5, n))
+        back = _complex(idft_rows(dft_rows(_interleave(z))))
+        assert np.max(np.abs(back - z)) < 1e-12 * max(1, n)
+        x = _complex(idft_rows(_interleave(z)))
+        ref = np.fft.ifft(z, axis=1)
+        assert np.max(np.linalg.norm(x - ref, axis=1) / np.linalg.norm(ref, axis=1)) < 1e-12
+    # n = 2 by hand: ((a + b) / 2, (a - b) / 2)
+    x = _complex(idft_rows(_interleave(np.array([2 + 1j, -3 + 0.5j]))))[0]
+    assert np.allclose(x, [-0.5 + 0.75j, 2.5 + 0.25j], rtol=0, atol=1e-15)

@@ -116,12 +116,13 @@ def lcg_nest(L, seed32):
             "loops": [["e", "0", "N"]], "access": [[L, "w", "e"]], "flags": ["opaque_call"]}
 
 
-def fft_nest(x, rows="R", width="M"):
+def fft_nest(x, rows="R", width="M", inverse=False):
     """The FFT library call on x[rows][width] (width = 2n floats per row: n
     complex values, interleaved) as a function block: one gene bit; its
     iteration space is the rows and the floats of a row, all read and written
-    in place."""
-    return {"nest": "fft_" + x, "op": "fft_rows", "args": {"x": x},
+    in place.  inverse: the inverse transform scaled by 1/n."""
+    args = {"x": x, "inverse": 1} if inverse else {"x": x}
+    return {"nest": ("ifft_" if inverse else "fft_") + x, "op": "fft_rows", "args": args,
             "loops": [["r", "0", rows], ["e", "0", width]], "access": [[x, "rw", "r", "e"]]}
 
 
@@ -253,11 +254,20 @@ def stencil_app(I, J, K, sweeps, mode=1):
             "program": [sweep_block()]}
 
 
-def fft_app(R, n):
-    """The FFT call alone on R rows of n complex values (caller-supplied)."""
+def fft_app(R, n, inverse=False):
+    """The FFT call alone (forward or inverse) on R rows of n complex values
+    (caller-supplied)."""
     return {"name": "fft", "params": {"R": R, "M": 2 * n},
             "buffers": [{"name": "X", "dtype": "f32", "dims": ["R", "M"], "output": True}],
-            "program": [fft_nest("X")]}
+            "program": [fft_nest("X", inverse=inverse)]}
+
+
+def fft_roundtrip_app(R, n):
+    """The forward FFT call, then the inverse one, on the same rows: two
+    function blocks, two gene bits."""
+    return {"name": "fft_roundtrip", "params": {"R": R, "M": 2 * n},
+            "buffers": [{"name": "X", "dtype": "f32", "dims": ["R", "M"], "output": True}],
+            "program": [fft_nest("X"), fft_nest("X", inverse=True)]}
 
 
 def ewise_app(R, Cc):
