@@ -16,7 +16,9 @@ as source instead of the JSON IR:
   and calls ``f(...)``.
 
 A call statement of its own outside any loop, ``fft_rows(X);``,
-``ifft_rows(X);`` or ``sgemm(A, B, C);``, is a function block (the FFT library calls Sec. 3.2 names beside loop statements
+``ifft_rows(X);``, ``sgemm(A, B, C);`` or one of the level-1 BLAS calls
+``saxpy(alpha, X, Y);``, ``scopy(X, Y);``, ``sscal(alpha, X);``, is a
+function block (the FFT library calls Sec. 3.2 names beside loop statements
 as offloadable parts): one nest with one gene bit, whose GPU and CPU forms
 are the library's own.
 
@@ -46,6 +48,8 @@ import json
 import os
 import re
 import subprocess
+
+import numpy as np
 
 # ------------------------------------------------------------------ lexing
 _TOKEN = re.compile(r"""
@@ -300,8 +304,12 @@ PURE_CALLS = ("u01", "bf16")
 # every row of X[R][2n] (n complex values per row, interleaved);
 # ifft_rows(X): the inverse DFT of every row, scaled by 1/n;
 # sgemm(A, B, C): C = A B (FP32 or bf16 operands by their declarations),
-# the same nest as the loop form of the product.
-FUNCTION_BLOCKS = {"fft_rows": "fft_rows", "ifft_rows": "fft_rows", "sgemm": "gemm"}
+# the same nest as the loop form of the product; the level-1 BLAS routines
+# on whole float arrays of one shape: saxpy(alpha, X, Y): Y = Y + alpha X,
+# scopy(X, Y): Y = X, sscal(alpha, X): X = alpha X, the same nests as the
+# loop forms (alpha a number, passed as the routine's float parameter).
+FUNCTION_BLOCKS = {"fft_rows": "fft_rows", "ifft_rows": "fft_rows", "sgemm": "gemm",
+                   "saxpy": "add_scaled", "scopy": "copy", "sscal": "scale"}
 
 # One C snippet per operation, each the nest's definition in the evaluation
 # order the library follows; names beginning with $ are pattern variables
@@ -1002,6 +1010,8 @@ def _parse(src, name):
             raise CError("call of %s: not a known library routine (only %s)" % (name, ", ".join(FUNCTION_BLOCKS)))
         if name == "sgemm":
             return gemm_block_ir(stmt)
+        if name in ("saxpy", "scopy", "sscal"):
+            return blas1_block_ir(stmt)
         if len(args) != 1 or args[0][0] != "var" or args[0][1] not in dtypes:
             raise CError("%s takes one declared array" % name)
         x = args[0][1]
@@ -1015,6 +1025,45 @@ def _parse(src, name):
         return {"nest": base if names_used[base] == 1 else "%s_%d" % (base, names_used[base]),
                 "op": FUNCTION_BLOCKS[name], "args": {"x": x, "inverse": 1} if inverse else {"x": x},
                 "loops": [["r", "0", b["dims"][0]], ["e", "0", b["dims"][1]]], "access": [[x, "rw", "r", "e"]]}
+
+    def blas1_block_ir(stmt):
+        name, args = stmt[1], stmt[2]
+        nscal = 0 if name == "scopy" else 1
+        narr = 1 if name == "sscal" else 2
+        if len(args) != nscal + narr:
+            raise CError("%s takes %s" % (name, {"saxpy": "alpha, X, Y", "scopy": "X, Y", "sscal": "alpha, X"}[name]))
+        alpha = None
+        if nscal:
+            a = args[0]
+            sign = 1.0
+            if a[0] == "neg":
+                sign, a = -1.0, a[1]
+            if a[0] != "num":
+                raise CError("%s: alpha must be a number" % name)
+            # the routine's float parameter: the literal converted to float
+            alpha = float(np.float32(sign * a[1]))
+        arrs = args[nscal:]
+        if any(a[0] != "var" or a[1] not in dtypes for a in arrs):
+            raise CError("%s takes declared arrays" % name)
+        bufs = [next(b for b in buffers if b["name"] == a[1]) for a in arrs]
+        if any(b["dtype"] != "f32" for b in bufs) or any(b["dims"] != bufs[0]["dims"] for b in bufs):
+            raise CError("%s: float arrays of one shape" % name)
+        loops = [[v, "0", d] for v, d in zip("ijklmn", bufs[0]["dims"])]
+        sub = [l[0] for l in loops]
+        if name == "saxpy":
+            op, a = "add_scaled", {"C": bufs[1]["name"], "A": bufs[0]["name"], "alpha": alpha}
+            acc = [[bufs[1]["name"], "rw"] + sub, [bufs[0]["name"], "r"] + sub]
+        elif name == "scopy":
+            op, a = "copy", {"dst": bufs[1]["name"], "src": bufs[0]["name"]}
+            acc = [[bufs[1]["name"], "w"] + sub, [bufs[0]["name"], "r"] + sub]
+        else:
+            op, a = "scale", {"D": bufs[0]["name"], "beta": alpha}
+            acc = [[bufs[0]["name"], "rw"] + sub]
+        at.append(where[id(stmt)] + ("call",))
+        base = _NEST_NAMES[op](a)
+        names_used[base] = names_used.get(base, 0) + 1
+        return {"nest": base if names_used[base] == 1 else "%s_%d" % (base, names_used[base]), "op": op, "args": a,
+                "loops": loops, "access": acc}
 
     def gemm_block_ir(stmt):
         args = stmt[2]

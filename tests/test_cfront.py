@@ -297,6 +297,32 @@ def test_inverse_fft_call_is_a_function_block():
     assert app.verdicts() == [tuple(x) for x in D.check_app(ir.load(doc))]
 
 
+BLAS1_SRC = open(os.path.join(APPS, "blas1.c")).read()
+
+
+def test_level1_blas_calls_are_the_loop_nests():
+    # saxpy / scopy / sscal on whole arrays become the nests of their loop
+    # forms (alpha as the routine's float parameter: a double literal is
+    # converted to float); one gene bit each
+    import numpy as np
+    doc = cfront.parse(BLAS1_SRC, "blas1")
+    prog = doc["program"]
+    assert [(n["op"], n["args"]) for n in prog[1:]] == [
+        ("add_scaled", {"C": "Y", "A": "X", "alpha": float(np.float32(0.1))}),
+        ("copy", {"dst": "Z", "src": "Y"}),
+        ("scale", {"D": "Z", "beta": -2.5}),
+        ("add_scaled", {"C": "Z", "A": "X", "alpha": 0.5})]
+    assert prog[1]["loops"] == prog[4]["loops"] and prog[1]["access"][1] == prog[4]["access"][1]
+    app = ofl.App(json.dumps(doc))
+    assert app.gene_len == 5
+    assert app.verdicts() == [tuple(x) for x in D.check_app(ir.load(doc))]
+    for bad, msg in (("saxpy(X, Y);", "takes"), ("saxpy(a, X, Y);", "alpha must be a number"),
+                     ("scopy(X, W);", "one shape"), ("sscal(2.0f, t);", "declared arrays")):
+        with pytest.raises(cfront.CError, match=msg):
+            cfront.parse(BLAS1_SRC.replace("sscal(-2.5f, Z);", bad).replace(
+                "float Z[N][M];", "float Z[N][M];\nfloat W[N][N];"), "t")
+
+
 def test_matrix_product_call_is_the_product_nest():
     # sgemm(A, B, C) as a function block gives the same nest as the loop form
     loop = cfront.load(os.path.join(APPS, "tiny.c"))

@@ -613,6 +613,16 @@ def test_spectral_population_batched():
     assert not parity.compare(o, app.read_all(), o32, o64)
 
 
+def test_level1_blas_calls_every_gene():
+    # saxpy / scopy / sscal function blocks from C source: every gene of the
+    # program (init, three calls, one loop-form axpy) against the oracle
+    import os
+    from paper_1806_01430_amd import cfront
+    doc = cfront.load(os.path.join(os.path.dirname(ofl.__file__), "apps", "blas1.c"))
+    genes = [[(idx >> i) & 1 for i in range(5)] for idx in range(32)]
+    _run_and_compare(doc, genes, policies=(ofl.RESIDENT, ofl.SECTIONS))
+
+
 def test_search_from_c_source(tmp_path, capsys):
     # the whole flow from C source: parse, check, GA over measured runs,
     # the program written back with the best gene's directives; the parsed
