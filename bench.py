@@ -273,6 +273,19 @@ def run_kernels_large(args):
         gbs = 16.0 * Rf * n / avg / 1e9
         out[("ifft" if inverse else "fft") + "_rows_8192x1024"] = {
             "avg_us": round(avg * 1e6, 3), "GBps": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)}
+    # the real call on 8192 rows of 2048 values (the same 64 MB): the
+    # 1024-point complex kernel and the unpacking pass, each reading and
+    # writing the array once
+    del bufs, app
+    app = ofl.App(json.dumps(appgen.fft_app(Rf, 2 * n, real=True)), seed=1)
+    app.set_input("X", np.random.default_rng(5).standard_normal((Rf, 2 * n)).astype(np.float32))
+    bufs = app.alloc_device_buffers("cuda:0")
+    app.run_pattern([1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
+    app.set_kernel_timing(True)
+    for _ in range(5):
+        app.run_pattern([1], bufs, flags=ofl.PRESTAGED | ofl.KEEP_OUTPUTS)
+    nl, ms = app.kernel_stats("fft_rows")
+    out["rfft_rows_8192x2048"] = {"avg_us_per_call": round(ms / nl * 1e3, 3), "calls": nl}
     return out
 
 

@@ -14,6 +14,11 @@ The inverse call computes, per row, the inverse transform scaled by 1/n,
 
 so that the inverse of the forward transform gives the row back.
 
+The real call takes rows of n real values and writes each row's spectrum
+X[0..n/2] (X[n-k] = conj X[k] for real input) packed into the same n floats:
+[X[0], X[n/2], Re X[1], Im X[1], ..., Re X[n/2-1], Im X[n/2-1]] (X[0] and
+X[n/2] are real).
+
 Evaluated here as those sums in complex double precision (one matrix
 product of the row with the n x n matrix of exp(-2 pi i ((j k) mod n) / n),
 or its complex conjugate for the inverse; the exponent index is reduced
@@ -56,4 +61,20 @@ def idft_rows(x):
     out = np.empty((R, m), np.float64)
     out[:, 0::2] = Z.real
     out[:, 1::2] = Z.imag
+    return out
+
+
+def rdft_packed_rows(x):
+    """DFT of each row of n real values, packed as described above; float64
+    result of the same shape."""
+    x = np.asarray(x, np.float64)
+    R, n = x.shape
+    if n < 2 or n % 2:
+        raise ValueError("real rows hold an even number of values")
+    X = x @ dft_matrix(n)[:, : n // 2 + 1]
+    out = np.empty((R, n), np.float64)
+    out[:, 0] = X[:, 0].real
+    out[:, 1] = X[:, n // 2].real
+    out[:, 2::2] = X[:, 1 : n // 2].real
+    out[:, 3::2] = X[:, 1 : n // 2].imag
     return out

@@ -14,7 +14,7 @@ ops), as the accuracy reference for GPU results whose rounding order differs.
 import numpy as np
 
 from . import cnests as C
-from .dft import dft_rows, idft_rows
+from .dft import dft_rows, idft_rows, rdft_packed_rows
 from .ir import load  # noqa: F401  (re-exported for callers)
 
 _NP = {"f32": np.float32, "f64": np.float64, "bf16": np.uint16}
@@ -126,10 +126,13 @@ def run_nest(app, nest, bufs, seed, repeat_env, twin=False, offloaded=False):
         else:
             C.rec_decay(w, p)
     elif op == "fft_rows":
-        # the FFT call: the exact transform (forward, or inverse scaled by
-        # 1/n), rounded to the buffer's precision
+        # the FFT call: the exact transform (forward, inverse scaled by 1/n,
+        # or of real rows, packed), rounded to the buffer's precision
         X = bufs[a["x"]]
-        X[...] = (idft_rows(X) if a.get("inverse") else dft_rows(X)).astype(X.dtype)
+        if a.get("real"):
+            X[...] = rdft_packed_rows(X).astype(X.dtype)
+        else:
+            X[...] = (idft_rows(X) if a.get("inverse") else dft_rows(X)).astype(X.dtype)
     elif op == "lcg_fill":
         L = bufs[a["L"]]
         if twin:

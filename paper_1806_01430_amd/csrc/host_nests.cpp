@@ -264,7 +264,8 @@ bool run_host_nest(const AppIR &app, const Nest &n, const std::vector<void *> &h
     case OP_FFT_ROWS: {
         // the CPU form of the FFT call: the same radix-2 self-sorting
         // (Stockham) passes as the GPU kernel, per row; the inverse conjugates
-        // the row, transforms it forward, and conjugates and scales by 1/n
+        // the row, transforms it forward, and conjugates and scales by 1/n; a
+        // real row is transformed as half as many complex values and unpacked
         const Buffer &x = app.bufs[n.b[0]];
         const int64_t rows = x.dims[0], pts = x.dims[1] / 2, half = pts / 2, ws = kFftMaxPoints / std::max<int64_t>(pts, 1);
         std::vector<float> w(kFftMaxPoints), a(2 * pts), b(2 * pts);
@@ -290,6 +291,35 @@ bool run_host_nest(const AppIR &app, const Nest &n, const std::vector<void *> &h
                     b[2 * (o + ns) + 1] = ui - vi;
                 }
                 a.swap(b);
+            }
+            if (n.real) {
+                // the row held 2 pts real values: unpack the spectrum of the
+                // half-length transform, bin pairs (k, pts - k), as the kernel does
+                const int64_t wr = ws / 2;   // twiddle stride of length 2 pts
+                auto bin = [&](int64_t ka, int64_t kb, int64_t kt, float &yr, float &yi) {
+                    const float ar = a[2 * ka], ai = a[2 * ka + 1], br = a[2 * kb], bi = a[2 * kb + 1];
+                    const float er = (ar + br) * 0.5f, ei = (ai - bi) * 0.5f;
+                    const float dr = (ar - br) * 0.5f, di = (ai + bi) * 0.5f;
+                    const float orr = di, oi = -dr;
+                    const float tr = w[2 * kt * wr], ti = w[2 * kt * wr + 1];
+                    const float pr = orr * tr - oi * ti, pi = orr * ti + oi * tr;
+                    yr = er + pr;
+                    yi = ei + pi;
+                };
+                for (int64_t k = 1; 2 * k <= pts; ++k) {
+                    float yr, yi, zr = 0.f, zi = 0.f;
+                    bin(k, pts - k, k, yr, yi);
+                    if (2 * k != pts) bin(pts - k, k, pts - k, zr, zi);
+                    a[2 * k] = yr;
+                    a[2 * k + 1] = yi;
+                    if (2 * k != pts) {
+                        a[2 * (pts - k)] = zr;
+                        a[2 * (pts - k) + 1] = zi;
+                    }
+                }
+                const float z0r = a[0], z0i = a[1];
+                a[0] = z0r + z0i;
+                a[1] = z0r - z0i;
             }
             if (n.inverse) {
                 const float sc = 1.0f / (float)pts;

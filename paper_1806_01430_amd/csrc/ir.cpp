@@ -297,12 +297,24 @@ bool resolve_op(Ctx &cx, Nest &n, const Json *args, const std::vector<int64_t> &
         if (!arg_buf(cx, n, args, "x", x)) return false;
         n.b.push_back(x);
         if (!need(cx, n, is(0, DT_F32) && B(0).dims.size() == 2, "needs a 2-D f32 buffer")) return false;
-        // optional "inverse": true / 1 for the inverse transform
-        if (const Json *inv = args->get("inverse")) {
-            const bool ok = (inv->kind == Json::Bool) || (inv->kind == Json::Num && inv->is_int &&
-                                                          (inv->inum == 0 || inv->inum == 1));
-            if (!need(cx, n, ok, "inverse must be true / false or 0 / 1")) return false;
-            n.inverse = inv->kind == Json::Bool ? inv->b : inv->inum == 1;
+        // optional flags "inverse" (the inverse transform) and "real" (rows
+        // of real values), each true / false or 0 / 1
+        for (const char *key : {"inverse", "real"}) {
+            if (const Json *f = args->get(key)) {
+                const bool ok = (f->kind == Json::Bool) ||
+                                (f->kind == Json::Num && f->is_int && (f->inum == 0 || f->inum == 1));
+                if (!need(cx, n, ok, std::string(key) + " must be true / false or 0 / 1")) return false;
+                (key[0] == 'i' ? n.inverse : n.real) = f->kind == Json::Bool ? f->b : f->inum == 1;
+            }
+        }
+        if (n.real) {
+            // x[R][n]: R rows of n real values, n a power of two from 2 to
+            // kFftMaxPoints, replaced by their packed spectrum
+            if (!need(cx, n, !n.inverse, "the real transform is forward only")) return false;
+            const int64_t nr = B(0).dims[1];
+            return need(cx, n, nr >= 2 && nr <= kFftMaxPoints && (nr & (nr - 1)) == 0 && B(0).dims[0] < (1ll << 31),
+                        "real rows must hold n values, n a power of two from 2 to " +
+                            std::to_string(kFftMaxPoints));
         }
         const int64_t pts = B(0).dims[1] / 2;
         return need(cx, n, B(0).dims[1] % 2 == 0 && pts >= 1 && pts <= kFftMaxPoints && (pts & (pts - 1)) == 0 &&

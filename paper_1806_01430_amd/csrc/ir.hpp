@@ -94,6 +94,7 @@ struct Nest {
     double alpha = 0.0;          // add_scaled alpha / scale beta
     uint32_t seed32 = 0;         // lcg_fill
     bool inverse = false;        // fft_rows: the inverse transform (scaled by 1/n)
+    bool real = false;           // fft_rows: rows of n real values, packed spectrum
     int slot_repeat = -1;        // stencil residual slot: repeat id
     GemmPrec prec = PREC_F32;
     std::string symbol;          // host_code: entry point in the application's host object

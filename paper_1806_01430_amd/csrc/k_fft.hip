@@ -27,6 +27,8 @@
 // the row and conjugate and scale as they write it, so the passes, twiddles
 // and bits are those of the forward transform (and of the CPU form, which
 // does the same).
+#include <algorithm>
+
 #include "fft_limits.hpp"
 #include "kernels.hpp"
 #include "launch.hpp"
@@ -263,6 +265,41 @@ __global__ __launch_bounds__(64) void k_fft_rows16s(float2 *__restrict__ x, cons
     }
 }
 
+// Real rows: the n real values of a row read as m = n/2 complex values z
+// (z[j] = x[2j] + i x[2j+1]) have the transform Z (the complex kernels
+// above); the spectrum of the real row follows from pairs of Z,
+//   X[k] = E[k] + w^k O[k],  E[k] = (Z[k] + conj Z[m-k]) / 2,
+//   O[k] = (Z[k] - conj Z[m-k]) / 2i,  w = exp(-2 pi i / n),
+// with X[0] = Z0.x + Z0.y and X[m] = Z0.x - Z0.y real.  One thread per pair
+// (k, m - k), k = 0 .. m/2, writes both bins in place (packed: X[0] and X[m]
+// in the row's first two floats).  The CPU form does the same operations.
+__device__ inline float2 rfft_bin(float2 a, float2 b, float2 t) {
+    const float2 e = make_float2((a.x + b.x) * 0.5f, (a.y - b.y) * 0.5f);
+    const float2 d = make_float2((a.x - b.x) * 0.5f, (a.y + b.y) * 0.5f);
+    const float2 p = cmul(make_float2(d.y, -d.x), t);
+    return make_float2(e.x + p.x, e.y + p.y);
+}
+
+__global__ __launch_bounds__(kFftThreads) void k_rfft_unpack(float2 *__restrict__ x, const float2 *__restrict__ tw,
+                                                             int64_t rows, int m) {
+    const int64_t pairs = m / 2 + 1, total = rows * pairs;
+    for (int64_t u = blockIdx.x * (int64_t)kFftThreads + threadIdx.x; u < total;
+         u += (int64_t)gridDim.x * kFftThreads) {
+        const int64_t r = u / pairs;
+        const int k = (int)(u - r * pairs);
+        float2 *z = x + r * m;
+        if (k == 0) {
+            const float2 z0 = z[0];
+            z[0] = make_float2(z0.x + z0.y, z0.x - z0.y);
+        } else {
+            const float2 a = z[k], b = z[m - k];
+            const float2 yk = rfft_bin(a, b, tw[k]);
+            if (2 * k != m) z[m - k] = rfft_bin(b, a, tw[m - k]);
+            z[k] = yk;
+        }
+    }
+}
+
 template <bool INV>
 hipError_t fft_rows_t(float2 *x2, const float2 *t2, int64_t rows, int64_t n, hipStream_t s) {
     const dim3 pairs((unsigned)((rows + kFftRowsPerBlock - 1) / kFftRowsPerBlock));
@@ -283,6 +320,18 @@ hipError_t fft_rows_t(float2 *x2, const float2 *t2, int64_t rows, int64_t n, hip
 }
 
 }  // namespace
+
+hipError_t rfft_rows(float *x, int64_t rows, int64_t n, const float *tw, hipStream_t s) {
+    if (rows <= 0) return hipSuccess;
+    if (n < 2 || n > kFftMaxPoints || (n & (n - 1)) != 0 || rows > 0x7FFFFFFF || tw == nullptr)
+        return hipErrorInvalidValue;
+    hipError_t e = fft_rows(x, rows, n / 2, tw, false, s);
+    if (e != hipSuccess) return e;
+    const int64_t total = rows * (n / 4 + 1);
+    const int64_t blocks = std::min<int64_t>((total + kFftThreads - 1) / kFftThreads, 65536);
+    return launch(k_rfft_unpack, dim3((unsigned)blocks), dim3(kFftThreads), 0, s, reinterpret_cast<float2 *>(x),
+                  reinterpret_cast<const float2 *>(tw) + (n / 2 - 1), rows, (int)(n / 2));
+}
 
 hipError_t fft_rows(float *x, int64_t rows, int64_t n, const float *tw, bool inverse, hipStream_t s) {
     if (rows <= 0 || n <= 1) return hipSuccess;   // a 1-point transform (either way) is the identity

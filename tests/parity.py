@@ -50,10 +50,30 @@ def rel_fft(n):
     return L * eta / (1 - L * eta)
 
 
-def fft_points(app_o):
-    """Largest row length (complex points) of the FFT calls, 0 if none."""
-    return max([app_o.buffers[app_o.buf_index[n.args["x"]]].dims[1] // 2 for n in app_o.nests
-                if n.op == "fft_rows"] or [0])
+def rel_rfft(n):
+    """Norm-wise bound for the real call on n values: the complex transform
+    of the n/2 values z[j] = x[2j] + i x[2j+1] (rel_fft(n/2) of ||Z||), then
+    per bin pair E = (Z[k] + conj Z[m-k]) / 2 and O = (Z[k] - conj Z[m-k]) / 2i
+    (one rounding each, the halving exact) and X[k] = E + w^k O (a rounded
+    twiddle within mu, a complex product within gamma_2 sqrt 2, one addition):
+    at most 6u of ||Z|| per output on top.  The map Z -> packed X has norm at
+    most sqrt 2 (each Z[k] enters two bins, with coefficients of modulus 1/2
+    and |w^k|/2), and ||Z|| <= ||packed X|| (Parseval: ||Z||^2 = m ||x||^2,
+    ||X_full||^2 = 2m ||x||^2, and the packed bins hold more than half of
+    it).  Hence ||got - exact|| <= (sqrt 2 rel_fft(n/2) + 6u) ||exact||."""
+    u = 2.0 ** -24
+    return np.sqrt(2.0) * rel_fft(max(1, n // 2)) + 6 * u
+
+
+def fft_bound(app_o):
+    """Largest norm-wise bound of the FFT calls (0 if none)."""
+    out = [0.0]
+    for n in app_o.nests:
+        if n.op != "fft_rows":
+            continue
+        width = app_o.buffers[app_o.buf_index[n.args["x"]]].dims[1]
+        out.append(rel_rfft(width) if n.args.get("real") else rel_fft(width // 2))
+    return max(out)
 
 
 def fft_tainted(app_o):
@@ -132,7 +152,7 @@ def compare(app_o, got, o32, o64, names=None, rel_gemm=REL_GEMM):
     bad = []
     tainted = gemm_tainted(app_o)
     spectral = fft_tainted(app_o)
-    rf = rel_fft(fft_points(app_o))
+    rf = fft_bound(app_o)
     terms = sum_terms(app_o)
     for b, buf in enumerate(app_o.buffers):
         if names is not None and buf.name not in names:

@@ -571,6 +571,26 @@ def test_fft_rows_full_size_sampled():
     assert err <= parity.rel_fft(n) + 2.0 ** -23, err
 
 
+@pytest.mark.parametrize("R,n", [(1, 2), (3, 4), (5, 8), (7, 16), (37, 128), (16, 256), (9, 512), (33, 1024),
+                                 (64, 2048), (7, 2048), (6, 4096), (3, 4096)])
+def test_fft_real_rows_shapes(R, n):
+    # the real call on the GPU (gene 1; the half-length complex kernels and
+    # the unpacking pass) and its CPU form (gene 0): the oracle's packed
+    # spectrum within the real-call bound, and the same bits on both sides
+    from oracle.dft import rdft_packed_rows
+    X = np.random.default_rng(R * 31 + n).standard_normal((R, n)).astype(np.float32)
+    doc = appgen.fft_app(R, n, real=True)
+    app, bufs = _run_and_compare(doc, [[0], [1]], inputs={"X": X})
+    ref = rdft_packed_rows(X)
+    outs = {}
+    for g in (0, 1):
+        app.run_pattern([g], bufs, flags=ofl.KEEP_OUTPUTS)
+        outs[g] = app.read_buffer("X").copy()
+        err = np.max(np.linalg.norm(outs[g] - ref, axis=1) / np.linalg.norm(ref, axis=1))
+        assert err <= parity.rel_rfft(n) + 2.0 ** -23, (g, err)
+    assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32)), (R, n)
+
+
 @pytest.mark.parametrize("R,n", [(5, 64), (9, 256), (6, 1024), (3, 4096)])
 def test_fft_round_trip(R, n):
     # the forward call then the inverse one: every gene gives the row back

@@ -431,6 +431,21 @@ def test_inverse_fft_flag(flag, ok):
             ofl.App(json.dumps(doc))
 
 
+@pytest.mark.parametrize("n,extra,ok", [(2, {}, True), (4096, {}, True), (6, {}, False), (8192, {}, False),
+                                         (64, {"inverse": 1}, False), (64, {"real": 0}, True)])
+def test_real_fft_call_shapes(n, extra, ok):
+    # the real call: rows of n real values, n a power of two from 2 to 4096;
+    # forward only
+    from workloads import appgen
+    doc = appgen.fft_app(3, n, real=True)
+    doc["program"][0]["args"].update(extra)
+    if ok:
+        assert ofl.App(json.dumps(doc)).verdicts() == [(D.PARALLEL, D.R_NONE, 0)]
+    else:
+        with pytest.raises(ofl.OflError):
+            ofl.App(json.dumps(doc))
+
+
 def test_irregular_program_verdicts_and_plans_match_oracle():
     # a C program with loops the library does not implement: those nests run
     # on the CPU from their own compiled text; verdicts (with the reason of

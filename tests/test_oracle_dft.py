@@ -2,11 +2,12 @@
 closed forms that catch a wrong sign of the exponent, swapped real and
 imaginary parts or a transposed index, Parseval's identity, the shift
 theorem, and the library FFT (numpy.fft) as an independent special case;
-for the inverse call also its 1/n scale and the round trip."""
+for the inverse call also its 1/n scale and the round trip; for the real
+call the packing of bins 0 and n/2 and the library's numpy.fft.rfft."""
 import numpy as np
 import pytest
 
-from oracle.dft import dft_rows, idft_rows
+from oracle.dft import dft_rows, idft_rows, rdft_packed_rows
 
 import parity
 
@@ -130,3 +131,53 @@ def test_inverse_round_trip_and_library_ifft():
     # n = 2 by hand: ((a + b) / 2, (a - b) / 2)
     x = _complex(idft_rows(_interleave(np.array([2 + 1j, -3 + 0.5j]))))[0]
     assert np.allclose(x, [-0.5 + 0.75j, 2.5 + 0.25j], rtol=0, atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [2, 4, 8, 64, 1024])
+def test_real_delta_and_constant(n):
+    # delta_0: every bin 1 (packed: X0, X(n/2), then (1, 0) pairs); a
+    # constant c: only X0 = n c
+    x = np.zeros((1, n))
+    x[0, 0] = 1
+    want = np.zeros(n)
+    want[0] = want[1] = 1
+    want[2::2] = 1
+    assert np.array_equal(rdft_packed_rows(x)[0], want)
+    y = rdft_packed_rows(np.full((1, n), -0.75))[0]
+    assert y[0] == -0.75 * n and np.max(np.abs(y[1:])) < 1e-12 * n
+
+
+@pytest.mark.parametrize("n", [4, 16, 256])
+def test_real_tones_land_in_their_packed_slots(n):
+    j = np.arange(n)
+    for m in range(1, n // 2):
+        for f, slot in ((np.cos, 2 * m), (np.sin, 2 * m + 1)):
+            y = rdft_packed_rows(f(2 * np.pi * m * j / n)[None, :])[0]
+            want = np.zeros(n)
+            want[slot] = n / 2 if f is np.cos else -n / 2   # sin: X[m] = -i n/2
+            assert np.max(np.abs(y - want)) < 1e-9 * n, (n, m, f.__name__)
+    alt = rdft_packed_rows(((-1.0) ** j)[None, :])[0]      # X[n/2] = n, packed second
+    want = np.zeros(n)
+    want[1] = n
+    assert np.max(np.abs(alt - want)) < 1e-9 * n
+
+
+def test_real_matches_complex_and_library():
+    rng = np.random.default_rng(8)
+    for n in (2, 8, 128, 2048):
+        x = rng.standard_normal((4, n))
+        y = rdft_packed_rows(x)
+        full = _complex(dft_rows(_interleave(x.astype(complex))))
+        ref = np.fft.rfft(x, axis=1)
+        for Z in (full[:, : n // 2 + 1], ref):
+            assert np.allclose(y[:, 0], Z[:, 0].real, atol=1e-9 * n)
+            assert np.allclose(y[:, 1], Z[:, n // 2].real, atol=1e-9 * n)
+            assert np.allclose(y[:, 2::2] + 1j * y[:, 3::2], Z[:, 1: n // 2], atol=1e-9 * n)
+
+
+def test_real_bound_values():
+    # sqrt 2 times the half-length complex bound plus 6u; n = 2 is one
+    # addition per output (no complex pass)
+    u = 2.0 ** -24
+    assert parity.rel_rfft(2) == 6 * u
+    assert abs(parity.rel_rfft(1024) - (np.sqrt(2) * parity.rel_fft(512) + 6 * u)) < 1e-20

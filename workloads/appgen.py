@@ -116,13 +116,18 @@ def lcg_nest(L, seed32):
             "loops": [["e", "0", "N"]], "access": [[L, "w", "e"]], "flags": ["opaque_call"]}
 
 
-def fft_nest(x, rows="R", width="M", inverse=False):
+def fft_nest(x, rows="R", width="M", inverse=False, real=False):
     """The FFT library call on x[rows][width] (width = 2n floats per row: n
     complex values, interleaved) as a function block: one gene bit; its
     iteration space is the rows and the floats of a row, all read and written
-    in place.  inverse: the inverse transform scaled by 1/n."""
-    args = {"x": x, "inverse": 1} if inverse else {"x": x}
-    return {"nest": ("ifft_" if inverse else "fft_") + x, "op": "fft_rows", "args": args,
+    in place.  inverse: the inverse transform scaled by 1/n; real: rows of
+    `width` real values, replaced by their packed spectrum."""
+    args = {"x": x}
+    if inverse:
+        args["inverse"] = 1
+    if real:
+        args["real"] = 1
+    return {"nest": ("ifft_" if inverse else "rfft_" if real else "fft_") + x, "op": "fft_rows", "args": args,
             "loops": [["r", "0", rows], ["e", "0", width]], "access": [[x, "rw", "r", "e"]]}
 
 
@@ -254,12 +259,12 @@ def stencil_app(I, J, K, sweeps, mode=1):
             "program": [sweep_block()]}
 
 
-def fft_app(R, n, inverse=False):
-    """The FFT call alone (forward or inverse) on R rows of n complex values
-    (caller-supplied)."""
-    return {"name": "fft", "params": {"R": R, "M": 2 * n},
+def fft_app(R, n, inverse=False, real=False):
+    """The FFT call alone (forward or inverse) on R rows of n complex values,
+    or (real) on R rows of n real values (caller-supplied)."""
+    return {"name": "fft", "params": {"R": R, "M": n if real else 2 * n},
             "buffers": [{"name": "X", "dtype": "f32", "dims": ["R", "M"], "output": True}],
-            "program": [fft_nest("X", inverse=inverse)]}
+            "program": [fft_nest("X", inverse=inverse, real=real)]}
 
 
 def fft_roundtrip_app(R, n):
