@@ -236,7 +236,8 @@ typedef struct {
  * row, interleaved; n a power of two up to 4096), or with args "inverse":
  * true / 1 the inverse DFT scaled by 1/n, or with "real": true / 1 the DFT
  * of rows of n real values [R][n] (2 <= n <= 4096), written in place packed
- * as [X0, X(n/2), Re X1, Im X1, ..., Re X(n/2-1), Im X(n/2-1)].  `seed` drives the
+ * as [X0, X(n/2), Re X1, Im X1, ..., Re X(n/2-1), Im X(n/2-1)]; both flags:
+ * such packed spectra replaced by their real rows (scaled by 1/n).  `seed` drives the
  * application's random-initialisation nests.  Allocates nothing on the GPU
  * (the device scratch, and for an FFT call its twiddle tables, come with the
  * first run).  A nest of op "host_code" (args {"symbol": name}) is a loop

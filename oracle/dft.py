@@ -17,7 +17,9 @@ so that the inverse of the forward transform gives the row back.
 The real call takes rows of n real values and writes each row's spectrum
 X[0..n/2] (X[n-k] = conj X[k] for real input) packed into the same n floats:
 [X[0], X[n/2], Re X[1], Im X[1], ..., Re X[n/2-1], Im X[n/2-1]] (X[0] and
-X[n/2] are real).
+X[n/2] are real); its inverse call takes such packed rows back to the real
+rows, x[j] = (1/n) sum_k X[k] exp(+2 pi i j k / n) over the full
+(Hermitian) spectrum.
 
 Evaluated here as those sums in complex double precision (one matrix
 product of the row with the n x n matrix of exp(-2 pi i ((j k) mod n) / n),
@@ -78,3 +80,19 @@ def rdft_packed_rows(x):
     out[:, 2::2] = X[:, 1 : n // 2].real
     out[:, 3::2] = X[:, 1 : n // 2].imag
     return out
+
+
+def irdft_packed_rows(p):
+    """Real rows of the packed spectra p[R][n] (the inverse of
+    rdft_packed_rows); float64 result of the same shape."""
+    p = np.asarray(p, np.float64)
+    R, n = p.shape
+    if n < 2 or n % 2:
+        raise ValueError("packed rows hold an even number of values")
+    m = n // 2
+    X = np.zeros((R, n), complex)
+    X[:, 0] = p[:, 0]
+    X[:, m] = p[:, 1]
+    X[:, 1:m] = p[:, 2::2] + 1j * p[:, 3::2]
+    X[:, m + 1:] = np.conj(X[:, 1:m][:, ::-1])
+    return ((X @ np.conj(dft_matrix(n))) / n).real

@@ -14,7 +14,7 @@ ops), as the accuracy reference for GPU results whose rounding order differs.
 import numpy as np
 
 from . import cnests as C
-from .dft import dft_rows, idft_rows, rdft_packed_rows
+from .dft import dft_rows, idft_rows, irdft_packed_rows, rdft_packed_rows
 from .ir import load  # noqa: F401  (re-exported for callers)
 
 _NP = {"f32": np.float32, "f64": np.float64, "bf16": np.uint16}
@@ -130,7 +130,7 @@ def run_nest(app, nest, bufs, seed, repeat_env, twin=False, offloaded=False):
         # or of real rows, packed), rounded to the buffer's precision
         X = bufs[a["x"]]
         if a.get("real"):
-            X[...] = rdft_packed_rows(X).astype(X.dtype)
+            X[...] = (irdft_packed_rows(X) if a.get("inverse") else rdft_packed_rows(X)).astype(X.dtype)
         else:
             X[...] = (idft_rows(X) if a.get("inverse") else dft_rows(X)).astype(X.dtype)
     elif op == "lcg_fill":

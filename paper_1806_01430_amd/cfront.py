@@ -16,7 +16,7 @@ as source instead of the JSON IR:
   and calls ``f(...)``.
 
 A call statement of its own outside any loop, ``fft_rows(X);``,
-``ifft_rows(X);``, ``rfft_rows(X);``, ``sgemm(A, B, C);`` or one of the level-1 BLAS calls
+``ifft_rows(X);``, ``rfft_rows(X);``, ``irfft_rows(X);``, ``sgemm(A, B, C);`` or one of the level-1 BLAS calls
 ``saxpy(alpha, X, Y);``, ``scopy(X, Y);``, ``sscal(alpha, X);``, is a
 function block (the FFT library calls Sec. 3.2 names beside loop statements
 as offloadable parts): one nest with one gene bit, whose GPU and CPU forms
@@ -304,13 +304,15 @@ PURE_CALLS = ("u01", "bf16")
 # every row of X[R][2n] (n complex values per row, interleaved);
 # ifft_rows(X): the inverse DFT of every row, scaled by 1/n; rfft_rows(X):
 # the DFT of every row of X[R][n] (n real values), written packed in place
-# ([X0, X(n/2), Re X1, Im X1, ...]);
+# ([X0, X(n/2), Re X1, Im X1, ...]); irfft_rows(X): packed spectra back to
+# their real rows;
 # sgemm(A, B, C): C = A B (FP32 or bf16 operands by their declarations),
 # the same nest as the loop form of the product; the level-1 BLAS routines
 # on whole float arrays of one shape: saxpy(alpha, X, Y): Y = Y + alpha X,
 # scopy(X, Y): Y = X, sscal(alpha, X): X = alpha X, the same nests as the
 # loop forms (alpha a number, passed as the routine's float parameter).
-FUNCTION_BLOCKS = {"fft_rows": "fft_rows", "ifft_rows": "fft_rows", "rfft_rows": "fft_rows", "sgemm": "gemm",
+FUNCTION_BLOCKS = {"fft_rows": "fft_rows", "ifft_rows": "fft_rows", "rfft_rows": "fft_rows",
+                   "irfft_rows": "fft_rows", "sgemm": "gemm",
                    "saxpy": "add_scaled", "scopy": "copy", "sscal": "scale"}
 
 # One C snippet per operation, each the nest's definition in the evaluation
@@ -1020,14 +1022,14 @@ def _parse(src, name):
         b = next(b for b in buffers if b["name"] == x)
         if b["dtype"] != "f32" or len(b["dims"]) != 2:
             raise CError("%s needs a 2-D float array (rows of interleaved complex values, or of real values "
-                         "for rfft_rows)" % name)
+                         "for rfft_rows / irfft_rows)" % name)
         at.append(where[id(stmt)] + ("call",))
-        base = {"fft_rows": "fft_", "ifft_rows": "ifft_", "rfft_rows": "rfft_"}[name] + x
+        base = {"fft_rows": "fft_", "ifft_rows": "ifft_", "rfft_rows": "rfft_", "irfft_rows": "irfft_"}[name] + x
         names_used[base] = names_used.get(base, 0) + 1
         fa = {"x": x}
-        if name == "ifft_rows":
+        if name in ("ifft_rows", "irfft_rows"):
             fa["inverse"] = 1
-        elif name == "rfft_rows":
+        if name in ("rfft_rows", "irfft_rows"):
             fa["real"] = 1
         return {"nest": base if names_used[base] == 1 else "%s_%d" % (base, names_used[base]),
                 "op": FUNCTION_BLOCKS[name], "args": fa,

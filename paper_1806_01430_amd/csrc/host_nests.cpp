@@ -275,6 +275,34 @@ bool run_host_nest(const AppIR &app, const Nest &n, const std::vector<void *> &h
             if ((r & 15) == 0 && dl.expired()) return false;
             float *xr = X + r * 2 * pts;
             std::memcpy(a.data(), xr, 2 * pts * sizeof(float));
+            if (n.real && n.inverse) {
+                // a packed spectrum of 2 pts real values: back to the
+                // half-length transform Z, bin pairs (k, pts - k), as the kernel does
+                const int64_t wr = ws / 2;
+                auto zbin = [&](int64_t ka, int64_t kb, int64_t kt, float &zr, float &zi) {
+                    const float ar = a[2 * ka], ai = a[2 * ka + 1], br = a[2 * kb], bi = a[2 * kb + 1];
+                    const float er = (ar + br) * 0.5f, ei = (ai - bi) * 0.5f;
+                    const float dr = (ar - br) * 0.5f, di = (ai + bi) * 0.5f;
+                    const float tr = w[2 * kt * wr], ti = -w[2 * kt * wr + 1];
+                    const float orr = dr * tr - di * ti, oi = dr * ti + di * tr;
+                    zr = er - oi;
+                    zi = ei + orr;
+                };
+                for (int64_t k = 1; 2 * k <= pts; ++k) {
+                    float yr, yi, qr = 0.f, qi = 0.f;
+                    zbin(k, pts - k, k, yr, yi);
+                    if (2 * k != pts) zbin(pts - k, k, pts - k, qr, qi);
+                    a[2 * k] = yr;
+                    a[2 * k + 1] = yi;
+                    if (2 * k != pts) {
+                        a[2 * (pts - k)] = qr;
+                        a[2 * (pts - k) + 1] = qi;
+                    }
+                }
+                const float p0 = a[0], p1 = a[1];
+                a[0] = (p0 + p1) * 0.5f;
+                a[1] = (p0 - p1) * 0.5f;
+            }
             if (n.inverse)
                 for (int64_t j = 0; j < pts; ++j) a[2 * j + 1] = -a[2 * j + 1];
             for (int64_t ns = 1, st = half; ns < pts; ns <<= 1, st >>= 1) {
@@ -292,7 +320,7 @@ bool run_host_nest(const AppIR &app, const Nest &n, const std::vector<void *> &h
                 }
                 a.swap(b);
             }
-            if (n.real) {
+            if (n.real && !n.inverse) {
                 // the row held 2 pts real values: unpack the spectrum of the
                 // half-length transform, bin pairs (k, pts - k), as the kernel does
                 const int64_t wr = ws / 2;   // twiddle stride of length 2 pts

@@ -309,8 +309,8 @@ bool resolve_op(Ctx &cx, Nest &n, const Json *args, const std::vector<int64_t> &
         }
         if (n.real) {
             // x[R][n]: R rows of n real values, n a power of two from 2 to
-            // kFftMaxPoints, replaced by their packed spectrum
-            if (!need(cx, n, !n.inverse, "the real transform is forward only")) return false;
+            // kFftMaxPoints, replaced by their packed spectrum (inverse: a
+            // packed spectrum replaced by its real row)
             const int64_t nr = B(0).dims[1];
             return need(cx, n, nr >= 2 && nr <= kFftMaxPoints && (nr & (nr - 1)) == 0 && B(0).dims[0] < (1ll << 31),
                         "real rows must hold n values, n a power of two from 2 to " +

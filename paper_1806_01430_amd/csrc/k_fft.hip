@@ -300,6 +300,38 @@ __global__ __launch_bounds__(kFftThreads) void k_rfft_unpack(float2 *__restrict_
     }
 }
 
+// The inverse: from the packed spectrum back to Z of the half-length
+// transform, per bin pair: E = (X[k] + conj X[m-k]) / 2 and
+// O = (X[k] - conj X[m-k]) / 2 conj(w^k), Z[k] = E + i O (k = 0: E and O
+// are the half-sum and half-difference of X0 and X(m)); then the inverse
+// complex transform of m values, scaled by 1/m, gives z, i.e. the real row.
+__device__ inline float2 irfft_bin(float2 a, float2 b, float2 t) {
+    const float2 e = make_float2((a.x + b.x) * 0.5f, (a.y - b.y) * 0.5f);
+    const float2 d = make_float2((a.x - b.x) * 0.5f, (a.y + b.y) * 0.5f);
+    const float2 o = cmul(d, make_float2(t.x, -t.y));
+    return make_float2(e.x - o.y, e.y + o.x);
+}
+
+__global__ __launch_bounds__(kFftThreads) void k_irfft_pack(float2 *__restrict__ x, const float2 *__restrict__ tw,
+                                                            int64_t rows, int m) {
+    const int64_t pairs = m / 2 + 1, total = rows * pairs;
+    for (int64_t u = blockIdx.x * (int64_t)kFftThreads + threadIdx.x; u < total;
+         u += (int64_t)gridDim.x * kFftThreads) {
+        const int64_t r = u / pairs;
+        const int k = (int)(u - r * pairs);
+        float2 *z = x + r * m;
+        if (k == 0) {
+            const float2 p = z[0];   // (X0, X(m))
+            z[0] = make_float2((p.x + p.y) * 0.5f, (p.x - p.y) * 0.5f);
+        } else {
+            const float2 a = z[k], b = z[m - k];
+            const float2 zk = irfft_bin(a, b, tw[k]);
+            if (2 * k != m) z[m - k] = irfft_bin(b, a, tw[m - k]);
+            z[k] = zk;
+        }
+    }
+}
+
 template <bool INV>
 hipError_t fft_rows_t(float2 *x2, const float2 *t2, int64_t rows, int64_t n, hipStream_t s) {
     const dim3 pairs((unsigned)((rows + kFftRowsPerBlock - 1) / kFftRowsPerBlock));
@@ -321,16 +353,22 @@ hipError_t fft_rows_t(float2 *x2, const float2 *t2, int64_t rows, int64_t n, hip
 
 }  // namespace
 
-hipError_t rfft_rows(float *x, int64_t rows, int64_t n, const float *tw, hipStream_t s) {
+hipError_t rfft_rows(float *x, int64_t rows, int64_t n, const float *tw, bool inverse, hipStream_t s) {
     if (rows <= 0) return hipSuccess;
     if (n < 2 || n > kFftMaxPoints || (n & (n - 1)) != 0 || rows > 0x7FFFFFFF || tw == nullptr)
         return hipErrorInvalidValue;
-    hipError_t e = fft_rows(x, rows, n / 2, tw, false, s);
-    if (e != hipSuccess) return e;
     const int64_t total = rows * (n / 4 + 1);
     const int64_t blocks = std::min<int64_t>((total + kFftThreads - 1) / kFftThreads, 65536);
-    return launch(k_rfft_unpack, dim3((unsigned)blocks), dim3(kFftThreads), 0, s, reinterpret_cast<float2 *>(x),
-                  reinterpret_cast<const float2 *>(tw) + (n / 2 - 1), rows, (int)(n / 2));
+    float2 *x2 = reinterpret_cast<float2 *>(x);
+    const float2 *t2 = reinterpret_cast<const float2 *>(tw) + (n / 2 - 1);   // exp(-2 pi i k / n), k < n/2
+    if (inverse) {
+        hipError_t e = launch(k_irfft_pack, dim3((unsigned)blocks), dim3(kFftThreads), 0, s, x2, t2, rows, (int)(n / 2));
+        if (e != hipSuccess) return e;
+        return fft_rows(x, rows, n / 2, tw, true, s);
+    }
+    hipError_t e = fft_rows(x, rows, n / 2, tw, false, s);
+    if (e != hipSuccess) return e;
+    return launch(k_rfft_unpack, dim3((unsigned)blocks), dim3(kFftThreads), 0, s, x2, t2, rows, (int)(n / 2));
 }
 
 hipError_t fft_rows(float *x, int64_t rows, int64_t n, const float *tw, bool inverse, hipStream_t s) {

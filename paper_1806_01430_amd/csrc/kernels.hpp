@@ -36,8 +36,10 @@ hipError_t fft_rows(float *x, int64_t rows, int64_t n, const float *tw, bool inv
 // In-place DFT of each of `rows` rows of n real values (n a power of two,
 // 2 <= n <= kFftMaxPoints), written as the packed spectrum [Re X0, Re X(n/2),
 // Re X1, Im X1, ..., Re X(n/2-1), Im X(n/2-1)]: the complex transform of the
-// row read as n/2 complex values, then one unpacking pass.
-hipError_t rfft_rows(float *x, int64_t rows, int64_t n, const float *tw, hipStream_t s);
+// row read as n/2 complex values, then one unpacking pass; `inverse`: a
+// packed spectrum replaced by its real row (one packing pass, then the
+// inverse complex transform of n/2 values).
+hipError_t rfft_rows(float *x, int64_t rows, int64_t n, const float *tw, bool inverse, hipStream_t s);
 // The sweep writes q and one residual partial per wave; adding the partials
 // to the sweep's residual slot is a separate step (ResidualFinish) that runs
 // as a one-block kernel or as the extra block of an interior copy launched

@@ -380,7 +380,7 @@ hipError_t launch_nest(ofl_app *app, const Nest &n, void *const *dev, const int6
     }
     case OP_FFT_ROWS: {
         const auto &d = ir.bufs[n.b[0]].dims;
-        if (n.real) return k::rfft_rows(F(0), d[0], d[1], app->d_twiddles, s);
+        if (n.real) return k::rfft_rows(F(0), d[0], d[1], app->d_twiddles, n.inverse, s);
         return k::fft_rows(F(0), d[0], d[1] / 2, app->d_twiddles, n.inverse, s);
     }
     default:
@@ -392,7 +392,7 @@ int32_t kernel_launch_count(const AppIR &ir, const Nest &n) {
     if (n.op == OP_INIT_UNIFORM) return (int32_t)n.b.size();
     if (n.op == OP_CAST_BF16) return (int32_t)(n.b.size() / 2);
     if (n.op == OP_SUMSQ) return 2;   // block partials + ordered finish
-    if (n.op == OP_FFT_ROWS && n.real)  // the half-length complex transform (none for 2 values) + the unpacking
+    if (n.op == OP_FFT_ROWS && n.real)  // the half-length complex transform (none for 2 values) + the (un)packing
         return ir.bufs[n.b[0]].dims[1] > 2 ? 2 : 1;
     if (n.op == OP_GEMM || n.op == OP_GEMM_BF16) {
         const auto &a = ir.bufs[n.b[0]].dims, &bb = ir.bufs[n.b[1]].dims;

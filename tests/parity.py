@@ -65,6 +65,19 @@ def rel_rfft(n):
     return np.sqrt(2.0) * rel_fft(max(1, n // 2)) + 6 * u
 
 
+def rel_irfft(n):
+    """Norm-wise bound for the inverse real call on n values: per bin pair
+    Z[k] = E + i O with E = (X[k] + conj X[m-k]) / 2 and O = (X[k] - conj
+    X[m-k]) / 2 conj(w^k) (one rounding each for E and d, a complex product
+    with a rounded twiddle, one addition): within 6u of ||packed X|| per
+    output; then the inverse complex transform of m = n/2 values (rel_fft(m)
+    of ||Z||, the 1/m scale exact).  With ||Z||^2 = m ||x||^2 and
+    ||packed X||^2 <= 2m ||x||^2, the result x = IDFT(Z) / m has
+    ||got - exact|| <= (rel_fft(n/2) + 6 sqrt 2 u) ||exact||."""
+    u = 2.0 ** -24
+    return rel_fft(max(1, n // 2)) + 6 * np.sqrt(2.0) * u
+
+
 def fft_bound(app_o):
     """Largest norm-wise bound of the FFT calls (0 if none)."""
     out = [0.0]
@@ -72,7 +85,10 @@ def fft_bound(app_o):
         if n.op != "fft_rows":
             continue
         width = app_o.buffers[app_o.buf_index[n.args["x"]]].dims[1]
-        out.append(rel_rfft(width) if n.args.get("real") else rel_fft(width // 2))
+        if n.args.get("real"):
+            out.append(rel_irfft(width) if n.args.get("inverse") else rel_rfft(width))
+        else:
+            out.append(rel_fft(width // 2))
     return max(out)
 
 

@@ -296,9 +296,10 @@ def test_inverse_fft_call_is_a_function_block():
     assert app.gene_len == 2
     assert app.verdicts() == [tuple(x) for x in D.check_app(ir.load(doc))]
     # rfft_rows(X): rows of real values, the same op with the real flag
-    real = cfront.parse("#define R 5\n#define M 64\nfloat X[R][M]; // ofl: output\nrfft_rows(X);\n", "r")
+    real = cfront.parse("#define R 5\n#define M 64\nfloat X[R][M]; // ofl: output\n"
+                        "rfft_rows(X);\nirfft_rows(X);\n", "r")
     assert [(n["nest"], n["op"], n["args"]) for n in real["program"]] == \
-        [(n["nest"], n["op"], n["args"]) for n in appgen.fft_app(5, 64, real=True)["program"]]
+        [(n["nest"], n["op"], n["args"]) for n in appgen.rfft_roundtrip_app(5, 64)["program"]]
 
 
 BLAS1_SRC = open(os.path.join(APPS, "blas1.c")).read()

@@ -571,24 +571,47 @@ def test_fft_rows_full_size_sampled():
     assert err <= parity.rel_fft(n) + 2.0 ** -23, err
 
 
+@pytest.mark.parametrize("inverse", [False, True])
 @pytest.mark.parametrize("R,n", [(1, 2), (3, 4), (5, 8), (7, 16), (37, 128), (16, 256), (9, 512), (33, 1024),
                                  (64, 2048), (7, 2048), (6, 4096), (3, 4096)])
-def test_fft_real_rows_shapes(R, n):
-    # the real call on the GPU (gene 1; the half-length complex kernels and
-    # the unpacking pass) and its CPU form (gene 0): the oracle's packed
-    # spectrum within the real-call bound, and the same bits on both sides
-    from oracle.dft import rdft_packed_rows
+def test_fft_real_rows_shapes(R, n, inverse):
+    # the real call or its inverse on the GPU (gene 1; the half-length
+    # complex kernels and the (un)packing pass) and its CPU form (gene 0):
+    # the oracle within the call's bound, and the same bits on both sides
+    from oracle.dft import irdft_packed_rows, rdft_packed_rows
     X = np.random.default_rng(R * 31 + n).standard_normal((R, n)).astype(np.float32)
-    doc = appgen.fft_app(R, n, real=True)
+    doc = appgen.fft_app(R, n, inverse=inverse, real=True)
     app, bufs = _run_and_compare(doc, [[0], [1]], inputs={"X": X})
-    ref = rdft_packed_rows(X)
+    ref = irdft_packed_rows(X) if inverse else rdft_packed_rows(X)
+    bound = parity.rel_irfft(n) if inverse else parity.rel_rfft(n)
     outs = {}
     for g in (0, 1):
         app.run_pattern([g], bufs, flags=ofl.KEEP_OUTPUTS)
         outs[g] = app.read_buffer("X").copy()
         err = np.max(np.linalg.norm(outs[g] - ref, axis=1) / np.linalg.norm(ref, axis=1))
-        assert err <= parity.rel_rfft(n) + 2.0 ** -23, (g, err)
+        assert err <= bound + 2.0 ** -23, (g, err)
     assert np.array_equal(outs[0].view(np.uint32), outs[1].view(np.uint32)), (R, n)
+
+
+@pytest.mark.parametrize("R,n", [(5, 64), (9, 512), (3, 4096)])
+def test_fft_real_round_trip(R, n):
+    # the real call then its inverse under every gene: the rows come back
+    # within sqrt 2 rel_rfft + rel_irfft, the same bits whichever side runs
+    # each call
+    X = np.random.default_rng(R * 7 + n).standard_normal((R, n)).astype(np.float32)
+    app = ofl.App(json.dumps(appgen.rfft_roundtrip_app(R, n)))
+    app.set_input("X", X)
+    bufs = app.alloc_device_buffers()
+    outs = {}
+    bound = np.sqrt(2.0) * parity.rel_rfft(n) + parity.rel_irfft(n) + 2.0 ** -22
+    for g in ([0, 0], [1, 1], [1, 0], [0, 1]):
+        say("case rfft round trip", R, n, g)
+        assert app.run_pattern(g, bufs)["status"] == ofl.ST_OK
+        outs[tuple(g)] = app.read_buffer("X").copy()
+        err = np.max(np.linalg.norm(outs[tuple(g)] - X, axis=1) / np.linalg.norm(X, axis=1))
+        assert err <= bound, (g, err)
+    for g in ((1, 1), (1, 0), (0, 1)):
+        assert np.array_equal(outs[g].view(np.uint32), outs[(0, 0)].view(np.uint32)), g
 
 
 @pytest.mark.parametrize("R,n", [(5, 64), (9, 256), (6, 1024), (3, 4096)])

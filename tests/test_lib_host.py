@@ -432,10 +432,12 @@ def test_inverse_fft_flag(flag, ok):
 
 
 @pytest.mark.parametrize("n,extra,ok", [(2, {}, True), (4096, {}, True), (6, {}, False), (8192, {}, False),
-                                         (64, {"inverse": 1}, False), (64, {"real": 0}, True)])
+                                         (64, {"inverse": 1}, True), (4096, {"inverse": 1}, True),
+                                         (12, {"inverse": 1}, False), (64, {"real": 0}, True),
+                                         (64, {"real": 3}, False)])
 def test_real_fft_call_shapes(n, extra, ok):
-    # the real call: rows of n real values, n a power of two from 2 to 4096;
-    # forward only
+    # the real call and its inverse: rows of n real values (or packed
+    # spectra), n a power of two from 2 to 4096
     from workloads import appgen
     doc = appgen.fft_app(3, n, real=True)
     doc["program"][0]["args"].update(extra)

@@ -7,7 +7,7 @@ call the packing of bins 0 and n/2 and the library's numpy.fft.rfft."""
 import numpy as np
 import pytest
 
-from oracle.dft import dft_rows, idft_rows, rdft_packed_rows
+from oracle.dft import dft_rows, idft_rows, irdft_packed_rows, rdft_packed_rows
 
 import parity
 
@@ -181,3 +181,25 @@ def test_real_bound_values():
     u = 2.0 ** -24
     assert parity.rel_rfft(2) == 6 * u
     assert abs(parity.rel_rfft(1024) - (np.sqrt(2) * parity.rel_fft(512) + 6 * u)) < 1e-20
+
+
+def test_real_inverse_round_trip_and_library():
+    # irdft_packed_rows undoes rdft_packed_rows; a packed flat spectrum
+    # (all bins 1) is the delta; numpy.fft.irfft of the unpacked bins agrees
+    rng = np.random.default_rng(10)
+    for n in (2, 4, 64, 1024):
+        x = rng.standard_normal((3, n))
+        assert np.max(np.abs(irdft_packed_rows(rdft_packed_rows(x)) - x)) < 1e-12 * n
+        flat = np.zeros((1, n))
+        flat[0, 0] = flat[0, 1] = 1
+        flat[0, 2::2] = 1
+        want = np.zeros(n)
+        want[0] = 1
+        assert np.max(np.abs(irdft_packed_rows(flat)[0] - want)) < 1e-12
+        p = rdft_packed_rows(x)
+        bins = np.zeros((3, n // 2 + 1), complex)
+        bins[:, 0], bins[:, n // 2] = p[:, 0], p[:, 1]
+        bins[:, 1: n // 2] = p[:, 2::2] + 1j * p[:, 3::2]
+        assert np.allclose(irdft_packed_rows(p), np.fft.irfft(bins, n, axis=1), atol=1e-12 * n)
+    # n = 2 by hand: [a, b] packed as (X0, X1) = (a + b, a - b)
+    assert np.allclose(irdft_packed_rows(np.array([[5.0, -1.0]])), [[2.0, 3.0]], rtol=0, atol=1e-15)

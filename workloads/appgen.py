@@ -121,13 +121,15 @@ def fft_nest(x, rows="R", width="M", inverse=False, real=False):
     complex values, interleaved) as a function block: one gene bit; its
     iteration space is the rows and the floats of a row, all read and written
     in place.  inverse: the inverse transform scaled by 1/n; real: rows of
-    `width` real values, replaced by their packed spectrum."""
+    `width` real values, replaced by their packed spectrum (with inverse:
+    packed spectra replaced by their real rows)."""
     args = {"x": x}
     if inverse:
         args["inverse"] = 1
     if real:
         args["real"] = 1
-    return {"nest": ("ifft_" if inverse else "rfft_" if real else "fft_") + x, "op": "fft_rows", "args": args,
+    prefix = {(False, False): "fft_", (True, False): "ifft_", (False, True): "rfft_", (True, True): "irfft_"}
+    return {"nest": prefix[(bool(inverse), bool(real))] + x, "op": "fft_rows", "args": args,
             "loops": [["r", "0", rows], ["e", "0", width]], "access": [[x, "rw", "r", "e"]]}
 
 
@@ -265,6 +267,13 @@ def fft_app(R, n, inverse=False, real=False):
     return {"name": "fft", "params": {"R": R, "M": n if real else 2 * n},
             "buffers": [{"name": "X", "dtype": "f32", "dims": ["R", "M"], "output": True}],
             "program": [fft_nest("X", inverse=inverse, real=real)]}
+
+
+def rfft_roundtrip_app(R, n):
+    """The real FFT call, then its inverse, on rows of n real values."""
+    return {"name": "rfft_roundtrip", "params": {"R": R, "M": n},
+            "buffers": [{"name": "X", "dtype": "f32", "dims": ["R", "M"], "output": True}],
+            "program": [fft_nest("X", real=True), fft_nest("X", inverse=True, real=True)]}
 
 
 def fft_roundtrip_app(R, n):
