@@ -48,8 +48,11 @@ LARGE_OPS = ["init_uniform", "gemm", "add_scaled", "transpose", "avg2", "sumsq",
              "copy", "scale", "cast_bf16", "gemm_bf16"]
 
 
+_T_START = time.perf_counter()
+
+
 def log(*a):
-    print(*a, file=sys.stderr, flush=True)
+    print("[%6.1f s]" % (time.perf_counter() - _T_START), *a, file=sys.stderr, flush=True)
 
 
 def nan_none(x, nd=3):
@@ -599,6 +602,7 @@ def main():
             "per_nest_s": cb["per_nest_s"]}
         line["speedup_vs_1core_oracle"] = round(cb["total_s"] / r["internal_median_s"], 1)
         line["speedup_vs_1core_oracle_pcie"] = round(cb["total_s"] / r["pcie_median_s"], 1)
+    log("bench: done")
     print(json.dumps(line), flush=True)
 
 
