@@ -14,10 +14,19 @@ namespace {
 
 constexpr int kThreads = 256;
 
-inline unsigned grid_for(int64_t work_items, int per_thread = 1) {
+// Blocks for work_items units of per_thread items, at most cap (256 CUs x 32
+// blocks by default: grid-stride beyond that).  The element-wise updates and
+// the cast (one 16-byte piece of each operand per thread and iteration) take
+// the larger cap kStreamCap, so that on large arrays more blocks keep more
+// loads in flight: at 8192 x 8192 (16384 blocks of 4 pieces per thread
+// instead of 8192 of 8) on gfx950 add_scaled 148 vs 175 us, avg2 158 vs 178,
+// cast_bf16 74 vs 83, scale 79 vs 84; init_uniform and the sum of squares
+// gained nothing.
+constexpr int64_t kStreamCap = 65536;
+inline unsigned grid_for(int64_t work_items, int per_thread = 1, int64_t cap = 8192) {
     int64_t blocks = (work_items + (int64_t)kThreads * per_thread - 1) / ((int64_t)kThreads * per_thread);
     if (blocks < 1) blocks = 1;
-    if (blocks > 8192) blocks = 8192;   // 256 CUs x 32 blocks: grid-stride beyond that
+    if (blocks > cap) blocks = cap;
     return (unsigned)blocks;
 }
 
@@ -303,17 +312,17 @@ hipError_t init_uniform(float *x, int64_t n, uint64_t key, hipStream_t s) {
 
 hipError_t add_scaled(float *C, const float *A, float alpha, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    return launch(k_add_scaled, dim3(grid_for(n / 4 + 1, 4)), dim3(kThreads), 0, s, C, A, alpha, n);
+    return launch(k_add_scaled, dim3(grid_for(n / 4 + 1, 4, kStreamCap)), dim3(kThreads), 0, s, C, A, alpha, n);
 }
 
 hipError_t avg2(float *S, const float *X, const float *Y, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    return launch(k_avg2, dim3(grid_for(n / 4 + 1, 4)), dim3(kThreads), 0, s, S, X, Y, n);
+    return launch(k_avg2, dim3(grid_for(n / 4 + 1, 4, kStreamCap)), dim3(kThreads), 0, s, S, X, Y, n);
 }
 
 hipError_t scale(float *D, float beta, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    return launch(k_scale, dim3(grid_for(n / 4 + 1, 4)), dim3(kThreads), 0, s, D, beta, n);
+    return launch(k_scale, dim3(grid_for(n / 4 + 1, 4, kStreamCap)), dim3(kThreads), 0, s, D, beta, n);
 }
 
 hipError_t copy_bytes(void *dst, const void *src, uint64_t bytes, hipStream_t s) {
@@ -333,7 +342,7 @@ hipError_t copy_bytes(void *dst, const void *src, uint64_t bytes, hipStream_t s)
 
 hipError_t cast_bf16(uint16_t *dst, const float *src, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
-    return launch(k_cast_bf16, dim3(grid_for(n / 4 + 1, 4)), dim3(kThreads), 0, s,
+    return launch(k_cast_bf16, dim3(grid_for(n / 4 + 1, 4, kStreamCap)), dim3(kThreads), 0, s,
                        reinterpret_cast<unsigned short *>(dst), src, n);
 }
 
