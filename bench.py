@@ -35,6 +35,9 @@ METRIC = "app time & speedup vs 1-core oracle; stencil GB/s, GEMM MFMA % of peak
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}
 LIVE_STRIDE = 10
+# product sizes the CPU baseline times (leading blocks of the real operands);
+# the largest is extrapolated to the full size as n^3
+SAMPLE_N = (1024, 2048, 2896)
 CSRC = os.path.join(ROOT, "paper_1806_01430_amd", "csrc")
 # sources each kernel kind is compiled from: a profile's byte counts hold only
 # while these are unchanged
@@ -421,9 +424,9 @@ def cpu_baseline_large():
     """The oracle's serial run of the large application (all 16 nests on the
     CPU: the all-zero gene), on one pinned host core, from a bounded sample:
     every nest once at full size in program order (the sweep and the interior
-    copy once each, counted SWEEPS times); the two products at N = 1024 and
-    2048 on leading blocks of their real operands, extrapolated as
-    t(2048) (N / 2048)^3."""
+    copy once each, counted SWEEPS times); the two products at n = 1024, 2048
+    and 2896 (about N / 2.83) on leading blocks of their real operands,
+    extrapolated as t(2896) (N / 2896)^3."""
     import numpy as np
 
     import workloads
@@ -458,14 +461,18 @@ def cpu_baseline_large():
         A, B = bufs[a["A"]], bufs[a["B"]]
         fn = C.gemm_f32 if nest.op == "gemm" else C.gemm_bf16
         ts = {}
-        for n in (1024, 2048):
+        for n in SAMPLE_N:
             As, Bs = np.ascontiguousarray(A[:n, :n]), np.ascontiguousarray(B[:n, :n])
             t0 = time.perf_counter()
             fn(As, Bs)
             ts[n] = time.perf_counter() - t0
-        est = ts[2048] * (A.shape[0] / 2048.0) ** 3
-        gemm_fit[nest.name] = {"t1024_s": round(ts[1024], 3), "t2048_s": round(ts[2048], 3),
-                               "ratio_2048_1024": round(ts[2048] / ts[1024], 2), "extrapolated_s": round(est, 1)}
+        big = SAMPLE_N[-1]
+        est = ts[big] * (A.shape[0] / float(big)) ** 3
+        gemm_fit[nest.name] = {"t_s": {str(n): round(ts[n], 3) for n in SAMPLE_N},
+                               # t(n) / n^3 relative to the largest sample: 1.0 where the cost is cubic
+                               "per_n3": {str(n): round((ts[n] / n ** 3) / (ts[big] / big ** 3), 3)
+                                          for n in SAMPLE_N},
+                               "extrapolated_s": round(est, 1)}
         return est
 
     def walk(items, env, mult):
@@ -589,17 +596,18 @@ def main():
     if not args.no_cpu_baseline:
         log("bench: oracle on one pinned host core (large application, bounded sample)")
         cb = cpu_baseline_large()
-        fit = "; ".join("%s %.2f s at 1024, %.2f s at 2048 (ratio %.2f) -> %.0f s at %d" % (
-            n, f["t1024_s"], f["t2048_s"], f["ratio_2048_1024"], f["extrapolated_s"], P["N"])
+        fit = "; ".join("%s %s -> %.0f s at %d" % (
+            n, ", ".join("%.2f s at %s" % (t, k) for k, t in f["t_s"].items()), f["extrapolated_s"], P["N"])
             for n, f in cb["gemm_fit"].items())
         line["cpu_baseline"] = {
             "value": round(1.0 / cb["total_s"], 6), "unit": "large-app runs/s", "cores": 1, "kind": "oracle",
             "sample": "serial oracle of the large application on host core %d: every non-product nest once at "
-                      "full size (the sweep and interior copy once each, x%d), the two 8192 products "
-                      "extrapolated as t(2048) (N/2048)^3 [%s]; estimated all-CPU run %.1f s from %.1f s of "
-                      "CPU work" % (cb["core"], P["SWEEPS"], fit, cb["total_s"], cb["sample_s"]),
+                      "full size (the sweep and interior copy once each, x%d), the two %d products "
+                      "extrapolated as t(n) (N/n)^3 from n = %d [%s]; estimated all-CPU run %.1f s from %.1f s "
+                      "of CPU work" % (cb["core"], P["SWEEPS"], P["N"], SAMPLE_N[-1], fit, cb["total_s"],
+                                       cb["sample_s"]),
             "host_cpu": cb["model"], "host_logical_cpus": cb["n_cpu"], "cpus_available": cb["n_affinity"],
-            "per_nest_s": cb["per_nest_s"]}
+            "per_nest_s": cb["per_nest_s"], "product_fit": cb["gemm_fit"]}
         line["speedup_vs_1core_oracle"] = round(cb["total_s"] / r["internal_median_s"], 1)
         line["speedup_vs_1core_oracle_pcie"] = round(cb["total_s"] / r["pcie_median_s"], 1)
     log("bench: done")
