@@ -10,7 +10,9 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <fstream>
+#include <limits>
 #include <map>
 #include <memory>
 #include <new>
@@ -1367,6 +1369,21 @@ int measure_batched_all(ofl_app *app, const std::vector<std::vector<uint8_t>> &p
     return OFL_OK;
 }
 
+// Runs of this length (seconds) or longer gain nothing from a batched GA
+// generation: at the large application (130 ms to 0.5 s per run) the search
+// took 195 s batched against 177 s gene by gene in one session, the difference
+// being the capture and instantiation of every gene's graphs.  The GA's
+// batched evaluator measures gene by gene while no run measured so far was
+// faster than this; OFL_BATCH_EAGER_S overrides it (0: always gene by gene).
+double batch_eager_threshold() {
+    if (const char *e = std::getenv("OFL_BATCH_EAGER_S")) {
+        char *end = nullptr;
+        const double v = std::strtod(e, &end);
+        if (end != e && v >= 0) return v;
+    }
+    return 0.02;
+}
+
 // Batched measurement with the optional output check: each gene runs once
 // eagerly first (with the limit) and is checked; genes that fail the check
 // or time out there are left out of the submission.
@@ -1784,22 +1801,46 @@ int ofl_ga_run(ofl_app *app, const ofl_ga_params *params, void *const *dev_bufs,
     if (params->reps < 1 || params->warmup < 0) return fail(OFL_E_ARG, "need reps >= 1 and warmup >= 0");
     int hard = OFL_OK;
     const int a = app->ir.gene_len;
+    // fastest successful run measured so far (the batched evaluator's switch)
+    double fastest = std::numeric_limits<double>::infinity();
+    auto note = [&](const Measurement &m) {
+        if (m.status == OFL_ST_OK && m.t < fastest) fastest = m.t;
+    };
     Evaluator ev = [&](const std::vector<uint8_t> &g, double limit) -> Measurement {
         if (hard != OFL_OK) return Measurement{0.0, OFL_ST_FAILED};
         std::vector<uint8_t> placement;
         check_gene(app, g.data(), a, placement);
-        return measure(app, placement, dev_bufs, static_cast<hipStream_t>(stream), params->reps, params->warmup,
-                       params->policy, params->flags, limit > 0 ? limit : 0.0, &hard, params->verify_rtol);
+        const Measurement m = measure(app, placement, dev_bufs, static_cast<hipStream_t>(stream), params->reps,
+                                      params->warmup, params->policy, params->flags, limit > 0 ? limit : 0.0, &hard,
+                                      params->verify_rtol);
+        note(m);
+        return m;
     };
+    // A generation's fresh genes in one submission once some run measured
+    // so far was faster than batch_eager_threshold(); until then (the first
+    // generation included) they are measured one after the other (eager
+    // runs, each under the generation's limit, as in the submission), since
+    // for long runs capturing each gene's graphs costs more than the launch
+    // overhead a submission saves
+    const double eager_from = batch_eager_threshold();
     BatchEvaluator bev = [&](const std::vector<std::vector<uint8_t>> &gs, double limit) {
         std::vector<Measurement> out(gs.size(), Measurement{0.0, OFL_ST_FAILED});
         if (hard != OFL_OK) return out;
         std::vector<std::vector<uint8_t>> places(gs.size());
         for (size_t i = 0; i < gs.size(); ++i) check_gene(app, gs[i].data(), a, places[i]);
-        const int rc2 = measure_batched(app, places, dev_bufs, static_cast<hipStream_t>(stream), params->reps,
-                                        params->warmup, params->policy, params->flags, limit, out,
-                                        params->verify_rtol);
-        if (rc2 != OFL_OK) hard = rc2;
+        if (fastest >= eager_from) {
+            const int eager = params->flags & ~(OFL_RUN_GRAPH | OFL_RUN_BATCHED);
+            for (size_t i = 0; i < gs.size() && hard == OFL_OK; ++i)
+                out[i] = measure(app, places[i], dev_bufs, static_cast<hipStream_t>(stream), params->reps,
+                                 params->warmup, params->policy, eager, limit > 0 ? limit : 0.0, &hard,
+                                 params->verify_rtol);
+        } else {
+            const int rc2 = measure_batched(app, places, dev_bufs, static_cast<hipStream_t>(stream), params->reps,
+                                            params->warmup, params->policy, params->flags, limit, out,
+                                            params->verify_rtol);
+            if (rc2 != OFL_OK) hard = rc2;
+        }
+        for (const Measurement &m : out) note(m);
         return out;
     };
     GaTrace tr;

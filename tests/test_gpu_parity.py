@@ -820,6 +820,32 @@ def test_ga_batched_generations_medium_reduced():
     assert res["best_time"] == float(np.min(res["times"]))
 
 
+def test_ga_batched_generations_gene_by_gene_for_long_runs(monkeypatch):
+    # the batched GA measures a generation gene by gene while no run measured
+    # so far was faster than the threshold (here forced to 0 s: every
+    # generation); the search keeps its batched semantics (one limit per
+    # generation) and its results stay consistent
+    monkeypatch.setenv("OFL_BATCH_EAGER_S", "0")
+    doc = workloads.app_doc("medium", **workloads.SMALL_MEDIUM)
+    app = ofl.App(json.dumps(doc))
+    bufs = app.alloc_device_buffers()
+    params = ofl.ga_params(M=8, T=4, p=1.0, seed=5, reps=2, warmup=1, flags=ofl.BATCHED, deadline_factor=3.0)
+    say("case GA batched medium reduced, gene by gene")
+    res = app.ga_run(params, bufs)
+    assert res["n_generations"] == 4
+    # with a deadline the all-CPU gene is measured first, as the reference
+    uniq = {tuple(int(x) for x in g) for gen in res["pops"] for g in gen} | {(0,) * app.gene_len}
+    assert res["n_measured"] == len(uniq) and res["t_all0"] > 0
+    ok = res["status"] == ofl.ST_OK
+    assert np.any(ok) and np.all((res["status"] == ofl.ST_OK) | (res["status"] == ofl.ST_TIMEOUT))
+    assert res["best_time"] == float(np.min(res["times"][ok]))
+    o = ir.load(doc)
+    o32, o64 = parity.oracle_outputs(o, 1)
+    st = app.run_pattern([int(x) for x in res["best_gene"]], bufs)
+    assert st["status"] == ofl.ST_OK
+    assert not parity.compare(o, app.read_all(), o32, o64)
+
+
 def test_kernel_timing_in_graph_replays():
     doc = workloads.app_doc("medium", **workloads.SMALL_MEDIUM)
     app = ofl.App(json.dumps(doc))
