@@ -107,12 +107,14 @@ enum {
                                 measurement ends at its first run over the
                                 limit; GPU work is not cut.  In the GA every
                                 gene of a generation gets the limit taken at
-                                the start of that generation, and ofl_ga_run
-                                measures a generation's genes one after the
-                                other (eager runs under that same limit) while
-                                no run measured so far took less than 20 ms
+                                the start of that generation.  ofl_ga_run
+                                submits a generation only once the best run
+                                so far is shorter than 20 ms
                                 (OFL_BATCH_EAGER_S in the environment sets
-                                the threshold in seconds): for longer runs
+                                the threshold in seconds); before that (the
+                                first generation included) it measures the
+                                genes one after the other with eager runs,
+                                exactly as without this flag: for longer runs
                                 capturing each gene's graphs costs more than
                                 the launch overhead a submission saves. */
     OFL_RUN_PROGRESS = 16,   /* ofl_ga_run only: one line per generation on

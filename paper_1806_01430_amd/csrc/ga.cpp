@@ -54,7 +54,7 @@ double ga_fitness(const Measurement &m, double p) {
 }
 
 void run_ga(int a, const GaConfig &cfg, const Evaluator &evaluate, GaTrace &out, const BatchEvaluator *batch,
-            const GaProgress *progress) {
+            const GaProgress *progress, const BatchGate *gate) {
     using clk = std::chrono::steady_clock;
     const auto t_start = clk::now();
     out = GaTrace();
@@ -96,7 +96,7 @@ void run_ga(int a, const GaConfig &cfg, const Evaluator &evaluate, GaTrace &out,
     };
 
     for (int gen = 1; gen <= cfg.T; ++gen) {
-        if (batch) {
+        if (batch && (!gate || (*gate)(out))) {
             std::vector<std::vector<uint8_t>> todo;
             for (int m = 0; m < cfg.M; ++m)
                 if (!cache.count(pop[m]) && std::find(todo.begin(), todo.end(), pop[m]) == todo.end())

@@ -78,10 +78,17 @@ class GaLog {
     int replayed_ = 0;
 };
 
+// gate(trace so far) -> whether this generation goes to the batch evaluator
+using BatchGate = std::function<bool(const GaTrace &)>;
+
 // With `batch`, every generation's uncached genes are measured by one call of
-// it (the baseline all-zero gene still by `evaluate`).
+// it (the baseline all-zero gene still by `evaluate`), except the
+// generations for which `gate` (if given) says no: their uncached genes are
+// measured one after the other by `evaluate`, each under the limit of that
+// moment, as in the search without `batch`.
 void run_ga(int a, const GaConfig &cfg, const Evaluator &evaluate, GaTrace &out,
-            const BatchEvaluator *batch = nullptr, const GaProgress *progress = nullptr);
+            const BatchEvaluator *batch = nullptr, const GaProgress *progress = nullptr,
+            const BatchGate *gate = nullptr);
 
 double ga_fitness(const Measurement &m, double p);
 

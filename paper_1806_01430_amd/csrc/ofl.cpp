@@ -1372,9 +1372,9 @@ int measure_batched_all(ofl_app *app, const std::vector<std::vector<uint8_t>> &p
 // Runs of this length (seconds) or longer gain nothing from a batched GA
 // generation: at the large application (130 ms to 0.5 s per run) the search
 // took 195 s batched against 177 s gene by gene in one session, the difference
-// being the capture and instantiation of every gene's graphs.  The GA's
-// batched evaluator measures gene by gene while no run measured so far was
-// faster than this; OFL_BATCH_EAGER_S overrides it (0: always gene by gene).
+// being the capture and instantiation of every gene's graphs.  A batched GA
+// measures its generations gene by gene until the best run so far is shorter
+// than this; OFL_BATCH_EAGER_S overrides it (0: always gene by gene).
 double batch_eager_threshold() {
     if (const char *e = std::getenv("OFL_BATCH_EAGER_S")) {
         char *end = nullptr;
@@ -1488,7 +1488,7 @@ std::string search_identity(const ofl_ga_params *p, int a, const std::string &wh
 // another random state at a generation's end) stops the measuring and
 // returns OFL_E_STATE.
 int run_logged_ga(int a, const ofl_ga_params *params, const std::string &what, const Evaluator &ev,
-                  const BatchEvaluator &bev, bool print, GaTrace &tr) {
+                  const BatchEvaluator &bev, bool print, GaTrace &tr, const BatchGate *gate = nullptr) {
     GaLog log;
     if (params->cache_path && params->cache_path[0]) {
         std::string err;
@@ -1539,7 +1539,7 @@ int run_logged_ga(int a, const ofl_ga_params *params, const std::string &what, c
             std::fflush(stderr);
         }
     };
-    run_ga(a, ga_config(params), lev, tr, (params->flags & OFL_RUN_BATCHED) ? &lbev : nullptr, &prog);
+    run_ga(a, ga_config(params), lev, tr, (params->flags & OFL_RUN_BATCHED) ? &lbev : nullptr, &prog, gate);
     if (bad) return fail(OFL_E_STATE, std::string("GA log ") + params->cache_path +
                                           " disagrees with this search (another gene or random state)");
     return OFL_OK;
@@ -1801,52 +1801,40 @@ int ofl_ga_run(ofl_app *app, const ofl_ga_params *params, void *const *dev_bufs,
     if (params->reps < 1 || params->warmup < 0) return fail(OFL_E_ARG, "need reps >= 1 and warmup >= 0");
     int hard = OFL_OK;
     const int a = app->ir.gene_len;
-    // fastest successful run measured so far (the batched evaluator's switch)
-    double fastest = std::numeric_limits<double>::infinity();
-    auto note = [&](const Measurement &m) {
-        if (m.status == OFL_ST_OK && m.t < fastest) fastest = m.t;
-    };
+    // the gene-by-gene evaluator; in a batched search (the generations that
+    // do not go to a submission, and the all-CPU reference gene) it runs
+    // eagerly, so that no gene's graphs are captured for a handful of runs
+    const int eager = (params->flags & OFL_RUN_BATCHED) ? params->flags & ~(OFL_RUN_GRAPH | OFL_RUN_BATCHED)
+                                                         : params->flags;
     Evaluator ev = [&](const std::vector<uint8_t> &g, double limit) -> Measurement {
         if (hard != OFL_OK) return Measurement{0.0, OFL_ST_FAILED};
         std::vector<uint8_t> placement;
         check_gene(app, g.data(), a, placement);
-        const Measurement m = measure(app, placement, dev_bufs, static_cast<hipStream_t>(stream), params->reps,
-                                      params->warmup, params->policy, params->flags, limit > 0 ? limit : 0.0, &hard,
-                                      params->verify_rtol);
-        note(m);
-        return m;
+        return measure(app, placement, dev_bufs, static_cast<hipStream_t>(stream), params->reps, params->warmup,
+                       params->policy, eager, limit > 0 ? limit : 0.0, &hard, params->verify_rtol);
     };
-    // A generation's fresh genes in one submission once some run measured
-    // so far was faster than batch_eager_threshold(); until then (the first
-    // generation included) they are measured one after the other (eager
-    // runs, each under the generation's limit, as in the submission), since
-    // for long runs capturing each gene's graphs costs more than the launch
-    // overhead a submission saves
-    const double eager_from = batch_eager_threshold();
     BatchEvaluator bev = [&](const std::vector<std::vector<uint8_t>> &gs, double limit) {
         std::vector<Measurement> out(gs.size(), Measurement{0.0, OFL_ST_FAILED});
         if (hard != OFL_OK) return out;
         std::vector<std::vector<uint8_t>> places(gs.size());
         for (size_t i = 0; i < gs.size(); ++i) check_gene(app, gs[i].data(), a, places[i]);
-        if (fastest >= eager_from) {
-            const int eager = params->flags & ~(OFL_RUN_GRAPH | OFL_RUN_BATCHED);
-            for (size_t i = 0; i < gs.size() && hard == OFL_OK; ++i)
-                out[i] = measure(app, places[i], dev_bufs, static_cast<hipStream_t>(stream), params->reps,
-                                 params->warmup, params->policy, eager, limit > 0 ? limit : 0.0, &hard,
-                                 params->verify_rtol);
-        } else {
-            const int rc2 = measure_batched(app, places, dev_bufs, static_cast<hipStream_t>(stream), params->reps,
-                                            params->warmup, params->policy, params->flags, limit, out,
-                                            params->verify_rtol);
-            if (rc2 != OFL_OK) hard = rc2;
-        }
-        for (const Measurement &m : out) note(m);
+        const int rc2 = measure_batched(app, places, dev_bufs, static_cast<hipStream_t>(stream), params->reps,
+                                        params->warmup, params->policy, params->flags, limit, out,
+                                        params->verify_rtol);
+        if (rc2 != OFL_OK) hard = rc2;
         return out;
     };
+    // A generation's fresh genes go to one submission once the best run
+    // measured so far is shorter than batch_eager_threshold(); until then
+    // (the first generation included) the search measures them gene by gene,
+    // exactly as without OFL_RUN_BATCHED: for long runs, capturing each
+    // gene's graphs costs more than the launch overhead a submission saves
+    const double eager_from = batch_eager_threshold();
+    const BatchGate gate = [eager_from](const GaTrace &t) { return t.best_f > 0.0 && t.best_t < eager_from; };
     GaTrace tr;
     std::string what = "app=" + app->ir.name + ":" + std::to_string(app->ir.nests.size());
     for (const auto &n : app->ir.nests) what += ":" + n.name;
-    rc = run_logged_ga(a, params, what, ev, bev, (params->flags & OFL_RUN_PROGRESS) != 0, tr);
+    rc = run_logged_ga(a, params, what, ev, bev, (params->flags & OFL_RUN_PROGRESS) != 0, tr, &gate);
     if (hard != OFL_OK) return hard;
     if (rc != OFL_OK) return rc;
     fill_ga_result(tr, a, params->M, result);
